@@ -1,0 +1,115 @@
+"""ctypes binding of the C oracle O2 (oracle/matfree.c).  Test infrastructure only.
+
+All arrays are numpy complex128 in canonical layout (see oracle/matfree.c).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        i32p = np.ctypeslib.ndpointer(np.int32, flags="C")
+        cdp = np.ctypeslib.ndpointer(np.complex128, flags="C")
+        f64p = np.ctypeslib.ndpointer(np.float64, flags="C")
+        L.orc_num_threads.restype = C.c_int
+        L.orc_dirac_apply.argtypes = [i32p, i32p, cdp, C.c_double, cdp, cdp, C.c_int]
+        L.orc_block_apply.argtypes = [i32p, i32p, cdp, C.c_double, i32p, C.c_int32, C.c_int,
+                                      C.c_int, cdp, cdp, C.c_int]
+        L.orc_drr_solve.argtypes = [i32p, i32p, cdp, C.c_double, i32p, C.c_int32, cdp, cdp,
+                                    C.c_int, C.c_int, C.c_double, C.c_int, i32p, f64p]
+        L.orc_drr_residual.argtypes = [i32p, i32p, cdp, C.c_double, i32p, C.c_int32, cdp, cdp,
+                                       C.c_int, f64p]
+        L.orc_schur_apply.argtypes = [i32p, i32p, cdp, C.c_double, i32p, C.c_int32, cdp, cdp,
+                                      C.c_int, C.c_int, C.c_double, C.c_int, i32p, f64p]
+        _lib = L
+    return _lib
+
+
+def _geom(dims, bc):
+    return (np.ascontiguousarray(dims, dtype=np.int32), np.ascontiguousarray(bc, dtype=np.int32))
+
+
+def _fields(a, per):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    if a.ndim == 1:
+        a = a[None, :]
+    assert a.shape[1] == per, (a.shape, per)
+    return a
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def dirac_apply(links, dims, m0, x, bc=(1, 1, 1, -1)):
+    """D x for x of shape (nrhs, 12V)."""
+    d, b = _geom(dims, bc)
+    v = int(np.prod(dims))
+    x = _fields(x, 12 * v)
+    out = np.empty_like(x)
+    lib().orc_dirac_apply(d, b, np.ascontiguousarray(links), float(m0), x, out, x.shape[0])
+    return out
+
+
+def block_apply(links, dims, m0, q, nb, osel, isel, x, bc=(1, 1, 1, -1)):
+    """mask_osel D mask_isel x with sel = 1 for coarse sites q[:nb], 0 for the rest."""
+    d, b = _geom(dims, bc)
+    v = int(np.prod(dims))
+    x = _fields(x, 12 * v)
+    out = np.empty_like(x)
+    lib().orc_block_apply(d, b, np.ascontiguousarray(links), float(m0),
+                          np.ascontiguousarray(q, dtype=np.int32), int(nb), int(osel), int(isel),
+                          x, out, x.shape[0])
+    return out
+
+
+def drr_solve(links, dims, m0, q, nb, rhs, restart=8, tol=1e-13, maxit=10000, bc=(1, 1, 1, -1)):
+    """GCR solve of D_rr x = rhs; returns (x, iters, relres)."""
+    d, b = _geom(dims, bc)
+    v = int(np.prod(dims))
+    rhs = _fields(rhs, 12 * v)
+    x = np.empty_like(rhs)
+    it = np.zeros(rhs.shape[0], np.int32)
+    rr = np.zeros(rhs.shape[0], np.float64)
+    lib().orc_drr_solve(d, b, np.ascontiguousarray(links), float(m0),
+                        np.ascontiguousarray(q, dtype=np.int32), int(nb), rhs, x, rhs.shape[0],
+                        int(restart), float(tol), int(maxit), it, rr)
+    return x, it, rr
+
+
+def drr_residual(links, dims, m0, q, nb, rhs, x, bc=(1, 1, 1, -1)):
+    """||rhs - D_rr x|| / ||rhs|| per RHS, recomputed in FP64 by the oracle."""
+    d, b = _geom(dims, bc)
+    v = int(np.prod(dims))
+    rhs = _fields(rhs, 12 * v)
+    x = _fields(x, 12 * v)
+    rr = np.zeros(rhs.shape[0], np.float64)
+    lib().orc_drr_residual(d, b, np.ascontiguousarray(links), float(m0),
+                           np.ascontiguousarray(q, dtype=np.int32), int(nb), rhs, x,
+                           rhs.shape[0], rr)
+    return rr
+
+
+def schur_apply(links, dims, m0, q, nb, xb, restart=8, tol=1e-13, maxit=10000, bc=(1, 1, 1, -1)):
+    """S_bb x_b for x_b of shape (nrhs, 12 nb); returns (y_b, iters, relres)."""
+    d, b = _geom(dims, bc)
+    xb = _fields(xb, 12 * int(nb))
+    yb = np.empty_like(xb)
+    it = np.zeros(xb.shape[0], np.int32)
+    rr = np.zeros(xb.shape[0], np.float64)
+    lib().orc_schur_apply(d, b, np.ascontiguousarray(links), float(m0),
+                          np.ascontiguousarray(q, dtype=np.int32), int(nb), xb, yb, xb.shape[0],
+                          int(restart), float(tol), int(maxit), it, rr)
+    return yb, it, rr

@@ -1,0 +1,85 @@
+"""The matrix-free C oracle (O2) against the dense oracle (O1), which is pinned
+in test_oracle_pins.py: full D, the four sub-blocks, the D_rr solve and the
+Schur-complement apply, on 4^4 and 4^3 x 8 lattices."""
+import numpy as np
+import pytest
+
+from grg_inputs import gaussian_vectors, su3_links
+from oracle import dense, matfree
+
+PERMS = [("I", False), ("II", False), ("I", True), ("II", True)]
+
+
+@pytest.fixture(scope="module")
+def setup4():
+    dims = (4, 4, 4, 4)
+    u = su3_links(dims, 0.4, 1)
+    return dims, u, dense.wilson_dense(u, dims, 0.1)
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (4, 4, 4, 8), (4, 2, 6, 4)])
+def test_dirac_apply_vs_dense(dims):
+    u = su3_links(dims, 0.5, 11)
+    d = dense.wilson_dense(u, dims, -0.2)
+    v = int(np.prod(dims))
+    x = gaussian_vectors(12 * v, 3, 11)
+    y = matfree.dirac_apply(u, dims, -0.2, x)
+    assert np.abs(y - (d @ x.T).T).max() < 1e-13 * np.abs(y).max()
+
+
+@pytest.mark.parametrize("kind,inv", PERMS)
+def test_block_apply_vs_dense(setup4, kind, inv):
+    dims, u, d = setup4
+    q, nb = dense.permutation_block(dims, kind, inv)
+    x = gaussian_vectors(12 * 256, 2, 3)
+    mask = np.zeros(256, bool)
+    mask[q[:nb]] = True
+    dmask = np.repeat(mask, 12)
+    for osel in (0, 1):
+        for isel in (0, 1):
+            want = d.copy()
+            want[dmask != bool(osel), :] = 0
+            want[:, dmask != bool(isel)] = 0
+            got = matfree.block_apply(u, dims, 0.1, q, nb, osel, isel, x)
+            assert np.abs(got - (want @ x.T).T).max() < 1e-13 * max(1.0, np.abs(got).max())
+
+
+@pytest.mark.parametrize("kind,inv", PERMS)
+def test_drr_solve_vs_dense(setup4, kind, inv):
+    dims, u, d = setup4
+    q, nb = dense.permutation_block(dims, kind, inv)
+    _, _, _, drr = dense.blocks(d, q, nb)
+    o = dense.dof_order(q)[12 * nb:]
+    b = np.zeros((2, 12 * 256), np.complex128)
+    b[:, o] = gaussian_vectors(len(o), 2, 4)
+    x, it, rr = matfree.drr_solve(u, dims, 0.1, q, nb, b, restart=8, tol=1e-13)
+    assert (rr <= 1e-13).all() and (it > 0).all()
+    xd = np.linalg.solve(drr, b[:, o].T).T
+    assert np.abs(x[:, o] - xd).max() < 1e-11 * np.abs(xd).max()
+    # nothing leaks onto coarse sites
+    ob = dense.dof_order(q)[: 12 * nb]
+    assert np.abs(x[:, ob]).max() == 0.0
+    rr2 = matfree.drr_residual(u, dims, 0.1, q, nb, b, x)
+    assert np.allclose(rr, rr2, rtol=1e-6, atol=1e-16)
+
+
+@pytest.mark.parametrize("kind,inv", PERMS)
+@pytest.mark.parametrize("restart", [1, 8])
+def test_schur_apply_vs_dense(setup4, kind, inv, restart):
+    dims, u, d = setup4
+    q, nb = dense.permutation_block(dims, kind, inv)
+    s = dense.schur_dense(d, q, nb)
+    xb = gaussian_vectors(12 * nb, 2, 1)
+    yb, it, rr = matfree.schur_apply(u, dims, 0.1, q, nb, xb, restart=restart, tol=1e-13)
+    want = (s @ xb.T).T
+    err = np.linalg.norm(yb - want, axis=1) / np.linalg.norm(want, axis=1)
+    assert err.max() < 1e-11, err
+
+
+def test_restart_does_not_change_the_answer(setup4):
+    dims, u, d = setup4
+    q, nb = dense.permutation_block(dims, "I")
+    xb = gaussian_vectors(12 * nb, 1, 9)
+    y1, _, _ = matfree.schur_apply(u, dims, 0.1, q, nb, xb, restart=1, tol=1e-13)
+    y2, _, _ = matfree.schur_apply(u, dims, 0.1, q, nb, xb, restart=16, tol=1e-13)
+    assert np.linalg.norm(y1 - y2) < 1e-11 * np.linalg.norm(y1)
