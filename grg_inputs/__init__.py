@@ -22,6 +22,8 @@ for them, since no ensemble is available.
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 
 __all__ = [
@@ -70,7 +72,7 @@ def _reunitarise(u: np.ndarray) -> np.ndarray:
     return np.stack([r0, r1, r2], axis=-2)
 
 
-def su3_links(dims, eps: float, seed: int, chunk: int = 1 << 18) -> np.ndarray:
+def su3_links(dims, eps: float, seed: int, chunk: int = 1 << 16) -> np.ndarray:
     """Random SU(3) links, shape (V, 4, 3, 3) complex128.
 
     a[t][z][y][x][mu][k] ~ N(0,1) is drawn from numpy.random.default_rng(seed)
@@ -83,13 +85,24 @@ def su3_links(dims, eps: float, seed: int, chunk: int = 1 << 18) -> np.ndarray:
     a = rng.standard_normal((lt, lz, ly, lx, 4, 8)).reshape(v * 4, 8)
     lam = gell_mann()
     out = np.empty((v * 4, 3, 3), dtype=np.complex128)
-    for s in range(0, v * 4, chunk):
+
+    def one(s):
         e = min(s + chunk, v * 4)
         h = np.einsum("nk,kij->nij", a[s:e], lam)
         w, vec = np.linalg.eigh(h)
         ph = np.exp(1j * eps * w)
         u0 = np.einsum("nij,nj,nkj->nik", vec, ph, np.conj(vec))
         out[s:e] = _reunitarise(u0)
+
+    starts = range(0, v * 4, chunk)
+    if v * 4 <= chunk:
+        one(0)
+    else:
+        # chunks are independent and deterministic, so threads do not change the result
+        from concurrent.futures import ThreadPoolExecutor
+
+        with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+            list(ex.map(one, starts))
     return out.reshape(v, 4, 3, 3)
 
 

@@ -1,0 +1,163 @@
+/*
+ * grg.h -- C ABI of the MI355X (gfx950) library for the coarse Dirac operator
+ * of a one-step gauged renormalisation-group blocking of Wilson fermions
+ * (A. Borici, "On Gauged Renormalisation Group Transformations of Lattice
+ * Fermions", arXiv:0704.2341).
+ *
+ * The operator.  After a site permutation that labels the coarse sites first,
+ * the Wilson-Dirac matrix is partitioned as D = [[D_bb, D_br], [D_rb, D_rr]]
+ * (section 1, step 1) and the coarse operator is the Schur complement
+ *     S_bb = D_bb - D_br D_rr^{-1} D_rb                 (section 1)
+ * of the block-UL factorisation.  Applying S_bb needs a solve with D_rr
+ * (section 2, closing remark on cost), which dominates the run time.
+ *
+ * The Wilson operator (the paper names it without writing it out; the
+ * standard r = 1 form in the DeGrand-Rossi basis):
+ *     D psi(x) = (4 + m0) psi(x)
+ *       - 1/2 sum_mu [ (1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^+ psi(x-mu) ]
+ * with a sign bc[mu] (+1 periodic, -1 antiperiodic) on hops that wrap.
+ *
+ * Layout at the boundary (canonical; the internal layout is private):
+ *   - dims = {Lx, Ly, Lz, Lt}; site s = x + Lx (y + Ly (z + Lz t)), x fastest;
+ *   - a lattice field is 12 complex128 per site, dof = 12 s + 3 spin + colour,
+ *     interleaved (re, im) doubles; a batch of nrhs fields is [nrhs][12 V];
+ *   - links are [V][4][3][3] complex128, U[s][mu][row][col], mu = x, y, z, t;
+ *   - a coarse-space field is [nrhs][12 N_b] complex128; coarse index k is
+ *     lattice site q[k] of the ordering vector (see grg_permutation_block).
+ *
+ * Ownership and memory: field and link pointers passed to the compute calls
+ * are DEVICE pointers owned by the caller (e.g. torch tensors); the library
+ * never frees them.  Handles and every workspace are owned by the library:
+ * workspaces are allocated by *_create for a stated maximum nrhs, so the
+ * apply/solve calls do not allocate.  Work is enqueued on the stream given at
+ * lattice creation; every call returns after that stream has drained.
+ * Handles must not be used from two threads at once.
+ *
+ * Errors: every call returns a grg_status and never aborts or throws across
+ * the boundary.  Arguments are validated before anything is enqueued.  The
+ * message of the last failure in the calling thread is grg_last_error().
+ */
+#ifndef GRG_H
+#define GRG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GRG_OK = 0,
+    GRG_EINVAL = -1,       /* invalid argument (null pointer, bad size, ...) */
+    GRG_EODD_EXTENT = -2,  /* Type I/II blocking needs even extents */
+    GRG_ENOMEM = -3,       /* device or host allocation failed */
+    GRG_EHIP = -4,         /* HIP runtime error; text in grg_last_error() */
+    GRG_ENOCONV = -5,      /* solver hit its iteration cap; best iterate kept */
+    GRG_ENONFINITE = -6,   /* NaN or Inf met in a residual */
+    GRG_ETOO_LARGE = -7,   /* output would exceed the caller's capacity */
+    GRG_EUNSUPPORTED = -8  /* valid request this build does not support */
+} grg_status;
+
+typedef enum { GRG_PERM_I = 1, GRG_PERM_II = 2 } grg_perm_type;
+
+/* Storage/arithmetic of a dslash or of the inner solve.  GRG_BF16 stores
+ * fields and links in bfloat16 and computes in FP32. */
+typedef enum { GRG_FP64 = 0, GRG_FP32 = 1, GRG_BF16 = 2 } grg_precision;
+
+typedef struct grg_lattice_s *grg_lattice;
+typedef struct grg_schur_s *grg_schur;
+
+/* Parameters of the D_rr solve.  Restarted GCR(restart) with the residual
+ * carried through restarts (restart = 1 is minimal residual).  With
+ * inner = GRG_FP64 the whole solve is FP64; otherwise an FP64 defect
+ * correction wraps inner solves in the given precision, each reducing its
+ * residual by inner_tol. */
+typedef struct {
+    double tol;        /* target: ||b - D_rr x|| <= tol ||b|| in FP64, per RHS */
+    int max_iter;      /* cap on inner iterations per solve (summed over outer) */
+    int restart;       /* GCR restart length m >= 1 */
+    int inner;         /* grg_precision of the inner iterations */
+    double inner_tol;  /* relative reduction per inner solve (mixed only) */
+    int max_outer;     /* cap on defect-correction steps (mixed only) */
+    int max_rhs;       /* largest nrhs per call; sizes the workspaces (<= 16) */
+    int check_every;   /* iterations between host-side convergence checks */
+} grg_solver_params;
+
+typedef struct {
+    int iters;             /* inner iterations taken (all outer steps) */
+    int outer;             /* defect-correction steps (0 for plain FP64) */
+    int converged;         /* 1 if every RHS met tol */
+    int n_dslash;          /* dslash launches in the call */
+    double true_rel_resid; /* max over RHS of the FP64 ||b - D_rr x|| / ||b|| */
+    double t_total_ms;     /* wall time of the call on the stream */
+    double t_dslash_ms;    /* summed dslash time (only with profiling on) */
+} grg_solver_stats;
+
+/* Thread-local message of the last failure; never NULL. */
+const char *grg_last_error(void);
+const char *grg_version(void);
+
+/* Fill p with the defaults (tol 1e-10, restart 1, FP64, max_rhs 12, ...). */
+grg_status grg_solver_params_default(grg_solver_params *p);
+
+/* Lattice geometry and the stream all work of this lattice runs on.
+ * dims: four positive extents; bc: +1 / -1 per direction; stream: a
+ * hipStream_t (NULL = default stream).  The current HIP device is recorded. */
+grg_status grg_lattice_create(const int32_t dims[4], const int32_t bc[4], void *stream,
+                              grg_lattice *out);
+grg_status grg_lattice_destroy(grg_lattice lat);
+grg_status grg_lattice_volume(grg_lattice lat, int64_t *volume);
+
+/* Set the gauge field from canonical links (host pointer if on_device == 0,
+ * device pointer otherwise).  Copies are made in every precision. */
+grg_status grg_gauge_set(grg_lattice lat, const double *links, int on_device);
+
+/* The site permutation of section 2 (Permutation_block): q[k] is the site
+ * placed at row k, coarse sites first.  Type I blocks in all directions at
+ * once (coarse = all-even sites); Type II blocks one direction at a time
+ * (nested red-black, x first).  inverse != 0 returns the inverse ordering
+ * (operator P^T).  q: host array of V int32, caller-owned.  *n_coarse = V/16.
+ * Odd extents give GRG_EODD_EXTENT.  Host-only: no device work. */
+grg_status grg_permutation_block(const int32_t dims[4], int type, int inverse, int32_t *q,
+                                 int32_t *n_coarse);
+
+/* out = D in for nrhs canonical lattice fields (device pointers), computed
+ * in the given precision (inputs rounded to it, result widened to FP64). */
+grg_status grg_dirac_apply(grg_lattice lat, double m0, int precision, const double *in,
+                           double *out, int nrhs);
+
+/* A coarse operator for ordering q (host, V entries, a permutation of the
+ * sites) with the first n_coarse entries coarse.  Allocates every workspace
+ * for params->max_rhs right-hand sides.  params NULL = defaults. */
+grg_status grg_schur_create(grg_lattice lat, double m0, const int32_t *q, int32_t n_coarse,
+                            const grg_solver_params *params, grg_schur *out);
+grg_status grg_schur_destroy(grg_schur s);
+grg_status grg_schur_set_params(grg_schur s, const grg_solver_params *params);
+
+/* x = D_rr^{-1} rhs for nrhs canonical lattice fields (device).  Entries of
+ * rhs on coarse sites are ignored; x is zero there.  GRG_ENOCONV keeps the
+ * best iterate.  stats may be NULL. */
+grg_status grg_drr_solve(grg_schur s, const double *rhs, double *x, int nrhs,
+                         grg_solver_stats *stats);
+
+/* y_b = S_bb x_b for nrhs coarse fields [nrhs][12 N_b] (device), computed as
+ * S x = [ D (u - D_rr^{-1} (D u)_r) ]_b with u = x on the coarse sites. */
+grg_status grg_schur_apply(grg_schur s, const double *x_b, double *y_b, int nrhs,
+                           grg_solver_stats *stats);
+
+/* The dense S_bb, column-major (12 N_b)^2 complex128 in HOST memory, by
+ * applying S_bb to unit vectors.  GRG_ETOO_LARGE if it exceeds cap_bytes. */
+grg_status grg_schur_assemble(grg_schur s, double *S, size_t cap_bytes);
+
+/* Kernel timing: with profiling on, every dslash launch is bracketed by HIP
+ * events on the lattice stream; grg_profile_read returns the count and the
+ * summed milliseconds since the last reset, per dslash precision. */
+grg_status grg_profile_enable(grg_schur s, int on);
+grg_status grg_profile_read(grg_schur s, int precision, int64_t *count, double *total_ms);
+grg_status grg_profile_reset(grg_schur s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GRG_H */

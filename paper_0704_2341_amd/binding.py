@@ -1,0 +1,260 @@
+"""ctypes binding of libgrg.so (include/grg.h), names as in the C ABI.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device buffers are torch tensors (complex128 on a ROCm device),
+passed by ``data_ptr()``; the stream is torch's current stream unless given.
+There is no CPU fallback: if the library is missing or fails to load, every
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgrg.so")
+
+GRG_OK = 0
+GRG_EINVAL = -1
+GRG_EODD_EXTENT = -2
+GRG_ENOMEM = -3
+GRG_EHIP = -4
+GRG_ENOCONV = -5
+GRG_ENONFINITE = -6
+GRG_ETOO_LARGE = -7
+GRG_EUNSUPPORTED = -8
+STATUS_NAMES = {
+    0: "GRG_OK", -1: "GRG_EINVAL", -2: "GRG_EODD_EXTENT", -3: "GRG_ENOMEM", -4: "GRG_EHIP",
+    -5: "GRG_ENOCONV", -6: "GRG_ENONFINITE", -7: "GRG_ETOO_LARGE", -8: "GRG_EUNSUPPORTED",
+}
+GRG_PERM_I, GRG_PERM_II = 1, 2
+GRG_FP64, GRG_FP32, GRG_BF16 = 0, 1, 2
+PRECISIONS = {"fp64": GRG_FP64, "fp32": GRG_FP32, "bf16": GRG_BF16}
+
+# Every symbol include/grg.h declares.
+EXPORTS = (
+    "grg_last_error", "grg_version", "grg_solver_params_default", "grg_lattice_create",
+    "grg_lattice_destroy", "grg_lattice_volume", "grg_gauge_set", "grg_permutation_block",
+    "grg_dirac_apply", "grg_schur_create", "grg_schur_destroy", "grg_schur_set_params",
+    "grg_drr_solve", "grg_schur_apply", "grg_schur_assemble", "grg_profile_enable",
+    "grg_profile_read", "grg_profile_reset",
+)
+
+
+class GrgError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class grg_solver_params(C.Structure):
+    _fields_ = [
+        ("tol", C.c_double), ("max_iter", C.c_int), ("restart", C.c_int), ("inner", C.c_int),
+        ("inner_tol", C.c_double), ("max_outer", C.c_int), ("max_rhs", C.c_int),
+        ("check_every", C.c_int),
+    ]
+
+
+class grg_solver_stats(C.Structure):
+    _fields_ = [
+        ("iters", C.c_int), ("outer", C.c_int), ("converged", C.c_int), ("n_dslash", C.c_int),
+        ("true_rel_resid", C.c_double), ("t_total_ms", C.c_double), ("t_dslash_ms", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load libgrg.so; raise if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_0704_2341_amd.build` "
+                          "(there is no CPU fallback)")
+    # torch bundles its own HIP runtime (same soname as /opt/rocm's).  Loading
+    # torch first makes libgrg.so bind to that one runtime; loading libgrg.so
+    # first would map a second HIP/HSA runtime into the process, and the two
+    # cannot share the device.
+    import torch  # noqa: F401
+
+    L = C.CDLL(LIB_PATH)
+    vp, i32p, i64p, dp = C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_double)
+    sig = {
+        "grg_last_error": (C.c_char_p, []),
+        "grg_version": (C.c_char_p, []),
+        "grg_solver_params_default": (C.c_int, [C.POINTER(grg_solver_params)]),
+        "grg_lattice_create": (C.c_int, [i32p, i32p, vp, C.POINTER(vp)]),
+        "grg_lattice_destroy": (C.c_int, [vp]),
+        "grg_lattice_volume": (C.c_int, [vp, i64p]),
+        "grg_gauge_set": (C.c_int, [vp, vp, C.c_int]),
+        "grg_permutation_block": (C.c_int, [i32p, C.c_int, C.c_int, i32p, i32p]),
+        "grg_dirac_apply": (C.c_int, [vp, C.c_double, C.c_int, vp, vp, C.c_int]),
+        "grg_schur_create": (C.c_int, [vp, C.c_double, i32p, C.c_int32,
+                                       C.POINTER(grg_solver_params), C.POINTER(vp)]),
+        "grg_schur_destroy": (C.c_int, [vp]),
+        "grg_schur_set_params": (C.c_int, [vp, C.POINTER(grg_solver_params)]),
+        "grg_drr_solve": (C.c_int, [vp, vp, vp, C.c_int, C.POINTER(grg_solver_stats)]),
+        "grg_schur_apply": (C.c_int, [vp, vp, vp, C.c_int, C.POINTER(grg_solver_stats)]),
+        "grg_schur_assemble": (C.c_int, [vp, vp, C.c_size_t]),
+        "grg_profile_enable": (C.c_int, [vp, C.c_int]),
+        "grg_profile_read": (C.c_int, [vp, C.c_int, i64p, dp]),
+        "grg_profile_reset": (C.c_int, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int, allow=()):
+    if status != GRG_OK and status not in allow:
+        raise GrgError(status, load().grg_last_error().decode())
+    return status
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _ptr(t):
+    return C.c_void_p(int(t.data_ptr()))
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    import torch
+
+    return C.c_void_p(int(torch.cuda.current_stream().cuda_stream))
+
+
+def _prec(p):
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+# ------------------------------------------------------------------ the ABI
+def grg_last_error() -> str:
+    return load().grg_last_error().decode()
+
+
+def grg_version() -> str:
+    return load().grg_version().decode()
+
+
+def grg_solver_params_default(**overrides) -> grg_solver_params:
+    p = grg_solver_params()
+    _check(load().grg_solver_params_default(C.byref(p)))
+    for k, v in overrides.items():
+        if k == "inner":
+            v = _prec(v)
+        setattr(p, k, v)
+    return p
+
+
+def grg_lattice_create(dims, bc=(1, 1, 1, -1), stream=None):
+    d, dp = _i32(dims)
+    b, bp = _i32(bc)
+    h = C.c_void_p()
+    _check(load().grg_lattice_create(dp, bp, _stream(stream), C.byref(h)))
+    return h
+
+
+def grg_lattice_destroy(lat):
+    _check(load().grg_lattice_destroy(lat))
+
+
+def grg_lattice_volume(lat) -> int:
+    v = C.c_int64()
+    _check(load().grg_lattice_volume(lat, C.byref(v)))
+    return v.value
+
+
+def grg_gauge_set(lat, links):
+    """links: complex128 (V, 4, 3, 3) numpy array (host) or torch tensor (host or device)."""
+    if isinstance(links, np.ndarray):
+        a = np.ascontiguousarray(links, dtype=np.complex128)
+        _check(load().grg_gauge_set(lat, C.c_void_p(a.ctypes.data), 0))
+        return
+    t = links.contiguous()
+    _check(load().grg_gauge_set(lat, _ptr(t), 1 if t.is_cuda else 0))
+
+
+def grg_permutation_block(dims, type, inverse=False):
+    """Returns (q int32[V], n_coarse)."""
+    d, dp = _i32(dims)
+    v = int(np.prod(d, dtype=np.int64))
+    q = np.zeros(v, dtype=np.int32)
+    nb = C.c_int32()
+    _check(load().grg_permutation_block(dp, int(type), int(bool(inverse)),
+                                        q.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(nb)))
+    return q, nb.value
+
+
+def grg_dirac_apply(lat, m0, precision, x, out, nrhs):
+    _check(load().grg_dirac_apply(lat, float(m0), _prec(precision), _ptr(x), _ptr(out), int(nrhs)))
+
+
+def grg_schur_create(lat, m0, q, n_coarse, params=None):
+    qa, qp = _i32(q)
+    h = C.c_void_p()
+    pp = C.byref(params) if params is not None else None
+    _check(load().grg_schur_create(lat, float(m0), qp, int(n_coarse), pp, C.byref(h)))
+    return h
+
+
+def grg_schur_destroy(s):
+    _check(load().grg_schur_destroy(s))
+
+
+def grg_schur_set_params(s, params):
+    _check(load().grg_schur_set_params(s, C.byref(params)))
+
+
+def grg_drr_solve(s, rhs, x, nrhs, allow_noconv=False):
+    st = grg_solver_stats()
+    status = _check(load().grg_drr_solve(s, _ptr(rhs), _ptr(x), int(nrhs), C.byref(st)),
+                    allow=(GRG_ENOCONV,) if allow_noconv else ())
+    d = st.as_dict()
+    d["status"] = status
+    return d
+
+
+def grg_schur_apply(s, x_b, y_b, nrhs, allow_noconv=False):
+    st = grg_solver_stats()
+    status = _check(load().grg_schur_apply(s, _ptr(x_b), _ptr(y_b), int(nrhs), C.byref(st)),
+                    allow=(GRG_ENOCONV,) if allow_noconv else ())
+    d = st.as_dict()
+    d["status"] = status
+    return d
+
+
+def grg_schur_assemble(s, n_coarse):
+    """Dense S_bb as a numpy complex128 (12 N_b, 12 N_b) array."""
+    n = 12 * int(n_coarse)
+    buf = np.zeros(n * n, dtype=np.complex128)
+    _check(load().grg_schur_assemble(s, C.c_void_p(buf.ctypes.data), buf.nbytes))
+    return buf.reshape(n, n).T  # column-major storage
+
+
+def grg_profile_enable(s, on=True):
+    _check(load().grg_profile_enable(s, int(bool(on))))
+
+
+def grg_profile_read(s, precision):
+    n, ms = C.c_int64(), C.c_double()
+    _check(load().grg_profile_read(s, _prec(precision), C.byref(n), C.byref(ms)))
+    return n.value, ms.value
+
+
+def grg_profile_reset(s):
+    _check(load().grg_profile_reset(s))

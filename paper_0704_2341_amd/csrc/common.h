@@ -1,0 +1,138 @@
+// Internal definitions shared by the kernels and the host engine.
+//
+// Internal field layout (private; the boundary is canonical):
+//   spinor field, nrhs right-hand sides:  elem(rhs, c, s) at  (rhs*12 + c)*Vs + s
+//     c = 3*spin + colour, s = lexicographic site (x fastest), Vs = V padded;
+//   gauge field:                          elem(mu, e, s)  at  (mu*9 + e)*Vs + s
+//     e = 3*row + col, the boundary sign bc[mu] folded into U_mu(x) on the
+//     last slice x_mu = L_mu - 1.
+// One complex number per element: double2 (FP64), float2 (FP32) or a 32-bit
+// word holding two bfloat16 (re in the low half, im in the high half).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "grg.h"
+
+namespace grg {
+
+typedef uint32_t bf16x2;
+
+// ------------------------------------------------------------------ geometry
+struct Geom {
+    int L[4];
+    int V;   // number of sites
+    int Vs;  // component stride (V rounded up to a multiple of 256)
+};
+
+// Work decomposition of the site-parallel kernels: blocks of SB sites
+// (a power of two), right-hand sides handled in groups of RG by one thread
+// (looped), items ordered so that each of the 8 XCDs owns one contiguous
+// eighth of the lattice.
+struct Launch {
+    int SB;       // sites per work item
+    int RG;       // right-hand sides per work item (looped inside a thread)
+    int grid;     // workgroups (multiple of 8)
+};
+
+static inline size_t spinor_elems(const Geom &g, int nrhs) { return (size_t)nrhs * 12 * g.Vs; }
+static inline size_t gauge_elems(const Geom &g) { return (size_t)4 * 9 * g.Vs; }
+static inline size_t prec_bytes(int prec) { return prec == GRG_FP64 ? 16 : prec == GRG_FP32 ? 8 : 4; }
+
+// ------------------------------------------------------------------ complex
+template <class R>
+struct cpx {
+    R re, im;
+};
+
+template <class R>
+__device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// conj(a) * b
+template <class R>
+__device__ __forceinline__ cpx<R> cmulc(cpx<R> a, cpx<R> b)
+{
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+
+// ------------------------------------------------------------------ storage
+template <int P>
+struct Store;
+template <>
+struct Store<GRG_FP64> {
+    typedef double2 S;
+    typedef double R;
+};
+template <>
+struct Store<GRG_FP32> {
+    typedef float2 S;
+    typedef float R;
+};
+template <>
+struct Store<GRG_BF16> {
+    typedef bf16x2 S;
+    typedef float R;
+};
+
+__device__ __forceinline__ cpx<double> ldc(const double2 *p, size_t i)
+{
+    double2 v = p[i];
+    return {v.x, v.y};
+}
+__device__ __forceinline__ cpx<float> ldc(const float2 *p, size_t i)
+{
+    float2 v = p[i];
+    return {v.x, v.y};
+}
+__device__ __forceinline__ cpx<float> ldc(const bf16x2 *p, size_t i)
+{
+    uint32_t u = p[i];
+    return {__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u)};
+}
+
+// float -> bfloat16 bits, round to nearest even; NaN stays NaN.
+__device__ __forceinline__ uint32_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+__device__ __forceinline__ void stc(double2 *p, size_t i, cpx<double> v) { p[i] = make_double2(v.re, v.im); }
+__device__ __forceinline__ void stc(float2 *p, size_t i, cpx<float> v) { p[i] = make_float2(v.re, v.im); }
+__device__ __forceinline__ void stc(bf16x2 *p, size_t i, cpx<float> v)
+{
+    p[i] = f2bf(v.re) | (f2bf(v.im) << 16);
+}
+
+// ------------------------------------------------------------------ work items
+// Work item w in [0, nitems) of a grid-stride loop, XCD-aware: workgroup b
+// runs on XCD b % 8 and walks the b-th eighth of the items.
+struct ItemRange {
+    int begin, end, step;
+};
+__device__ __forceinline__ ItemRange xcd_items(int nitems)
+{
+    const int xcd = blockIdx.x & 7;
+    const int per_xcd_wg = gridDim.x >> 3;
+    const int nper = (nitems + 7) >> 3;
+    ItemRange r;
+    r.begin = xcd * nper + (blockIdx.x >> 3);
+    r.end = min((xcd + 1) * nper, nitems);
+    r.step = per_xcd_wg;
+    return r;
+}
+
+// wave64 sum
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+}  // namespace grg

@@ -1,0 +1,121 @@
+// Host-side engine: kernel launchers and handle structures.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace grg {
+
+constexpr int kMaxRhs = 16;
+
+void set_error(const char *fmt, ...);
+
+#define GRG_TRY_HIP(expr)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            ::grg::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                             __LINE__);                                                      \
+            return GRG_EHIP;                                                                 \
+        }                                                                                    \
+    } while (0)
+
+#define GRG_TRY(expr)                        \
+    do {                                     \
+        grg_status s_ = (expr);              \
+        if (s_ != GRG_OK) return s_;         \
+    } while (0)
+
+// ------------------------------------------------------------------ kernels
+struct DslashArgs {
+    const void *in;
+    void *out;
+    const void *U;
+    const uint8_t *mask;  // output-site mask, nullptr = every site
+    int sel;              // rows kept: mask[s] == sel
+    double diag;          // 4 + m0
+    Geom g;
+    int nrhs;
+    int SB;               // sites per work item == workgroup size
+    int RG;               // right-hand sides per work item
+    double *partials;     // [grid][nrhs][3] or nullptr
+};
+
+struct CoarseArgs {
+    const void *in;       // internal FP64 lattice field
+    void *out;            // canonical coarse [nrhs][nb][12] complex128
+    const void *U;        // internal FP64 links
+    const int32_t *q;     // coarse index -> site
+    int nb;
+    double diag;
+    Geom g;
+    int nrhs;
+};
+
+hipError_t launch_dslash(int prec, const DslashArgs &a, int grid, hipStream_t st);
+hipError_t launch_dslash_coarse(const CoarseArgs &a, hipStream_t st);
+hipError_t launch_pack_gauge(const double *src, const Geom &g, const int bc[4], void *u64,
+                             void *u32, void *u16, hipStream_t st);
+hipError_t launch_pack_spinor(int prec, const double *src, void *dst, const Geom &g, int nrhs,
+                              hipStream_t st);
+hipError_t launch_unpack_spinor(int prec, const void *src, double *dst, const Geom &g, int nrhs,
+                                hipStream_t st);
+hipError_t launch_pack_masked(const double *src, void *dst, const uint8_t *mask, int keep,
+                              const Geom &g, int nrhs, hipStream_t st);
+hipError_t launch_scatter_coarse(const double *xb, void *dst, const int32_t *bidx, int nb,
+                                 const Geom &g, int nrhs, hipStream_t st);
+
+// BLAS-1 on internal fields.  Every kernel walks sites in work items of
+// SB sites x all RHS (looped); partial sums go to [grid][nrhs][k] doubles.
+struct BlasShape {
+    Geom g;
+    int nrhs;
+    int grid;   // workgroups, multiple of 8
+};
+
+// partials -> per-RHS reductions (fixed-order tree, deterministic)
+//  mode kAlpha: in k = 3 (re<q,r>, im<q,r>, |q|^2); alpha[r] = <q,r>/|q|^2 if
+//               active[r], else 0.  Also stores |q|^2 in aux[r].
+//  mode kNorm : in k = 1; out2[r] = sum; active[r] = sum > thr2[r].
+enum { kAlpha = 0, kNorm = 1 };
+hipError_t launch_reduce(int mode, const double *partials, int nparts, int nrhs, double2 *alpha,
+                         double *out2, const double *thr2, int *active, hipStream_t st);
+
+// x += alpha r ; r -= alpha q ; partial |r|^2     (one MR/GCR step)
+hipError_t launch_mr_update(int prec, const BlasShape &sh, void *x, void *r, const void *q,
+                            const void *p, const double2 *alpha, double *partials,
+                            hipStream_t st);
+// partial |v|^2
+hipError_t launch_norm2(int prec, const BlasShape &sh, const void *v, double *partials,
+                        hipStream_t st);
+// r = b - ax (FP64), partial |r|^2
+hipError_t launch_sub_norm(const BlasShape &sh, const void *b, const void *ax, void *r,
+                           double *partials, hipStream_t st);
+// y (prec_out) = beta*y + scale[r] * x (prec_in); scale from a device array
+// of per-RHS reals, multiplied by 1/sqrt(scale) when inv_sqrt != 0.
+hipError_t launch_axpy_convert(int prec_in, int prec_out, const BlasShape &sh, const void *x,
+                               void *y, const double *scale, int inv_sqrt, int beta,
+                               const int *active, hipStream_t st);
+// y = x - y (FP64), used for u - z
+hipError_t launch_xmy(const BlasShape &sh, const void *x, void *y, hipStream_t st);
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
+hipError_t launch_copy(int prec, const BlasShape &sh, const void *x, void *y, hipStream_t st);
+
+// GCR(m > 1): <q_j, q> for j < k, then q -= sum beta_j q_j, p -= sum beta_j p_j
+// with beta_j = <q_j, q>/|q_j|^2, fused with the partials of
+// (re<q,r>, im<q,r>, |q|^2) for the step length.
+hipError_t launch_multidot(int prec, const BlasShape &sh, const void *Q, int k, const void *q,
+                           double *partials, hipStream_t st);
+hipError_t launch_reduce_multi(const double *partials, int nparts, int nrhs, int k,
+                               const double *qnorm2, const int *active, double2 *beta,
+                               hipStream_t st);
+hipError_t launch_orthogonalise(int prec, const BlasShape &sh, const void *Q, const void *P,
+                                int k, const double2 *beta, void *q, void *p, const void *r,
+                                double *partials, hipStream_t st);
+
+}  // namespace grg

@@ -1,0 +1,64 @@
+// Handle structures behind the opaque grg_lattice / grg_schur pointers.
+#pragma once
+
+#include <vector>
+
+#include "engine.h"
+
+struct grg_lattice_s {
+    grg::Geom g;
+    int bc[4];
+    int device;
+    hipStream_t stream;
+    void *U[3] = {nullptr, nullptr, nullptr};  // internal links per grg_precision
+    bool gauge_set = false;
+    // grow-only scratch of grg_dirac_apply
+    void *tmp_in = nullptr, *tmp_out = nullptr;
+    size_t tmp_bytes = 0;
+    double *tmp_links = nullptr;  // staging of host links
+};
+
+namespace grg {
+
+struct ProfilePool {
+    bool on = false;
+    std::vector<hipEvent_t> start, stop;
+    std::vector<int> prec;
+    int used = 0;
+    long long count[3] = {0, 0, 0};
+    double total_ms[3] = {0, 0, 0};
+};
+
+}  // namespace grg
+
+struct grg_schur_s {
+    grg_lattice lat;
+    double m0;
+    int nb;
+    grg_solver_params prm;
+    std::vector<int32_t> q_host;
+    uint8_t *d_mask = nullptr;    // 1 on coarse sites
+    int32_t *d_q = nullptr;       // coarse index -> site
+    int32_t *d_bidx = nullptr;    // site -> coarse index or -1
+    // FP64 outer fields, [max_rhs][12][Vs] each
+    void *b64 = nullptr, *x64 = nullptr, *r64 = nullptr, *t64 = nullptr, *u64 = nullptr;
+    // inner fields (one set per precision, allocated on first use)
+    void *in_b[3] = {nullptr, nullptr, nullptr};
+    void *in_x[3] = {nullptr, nullptr, nullptr};
+    void *in_r[3] = {nullptr, nullptr, nullptr};
+    void *in_q[3] = {nullptr, nullptr, nullptr};
+    void *in_P[3] = {nullptr, nullptr, nullptr};  // GCR(m) search directions, m fields
+    void *in_Q[3] = {nullptr, nullptr, nullptr};  // their images A p_j
+    int in_m[3] = {0, 0, 0};
+    // coarse-space staging for assembly
+    double *cb_in = nullptr, *cb_out = nullptr;
+    // reduction scratch
+    double *partials = nullptr;
+    size_t partials_elems = 0;
+    double2 *alpha = nullptr, *beta = nullptr;
+    double *rn2 = nullptr, *thr2 = nullptr, *qn2 = nullptr, *bn2 = nullptr;
+    int *active = nullptr;
+    double *h_buf = nullptr;  // pinned host staging (4 * kMaxRhs doubles)
+    grg::ProfilePool prof;
+    int n_dslash = 0;
+};

@@ -1,0 +1,519 @@
+// Krylov vector operations on internal fields, with deterministic reductions.
+//
+// Every kernel is a grid-stride walk over blocks of 256 sites (XCD-aware, as
+// the stencil) with all right-hand sides looped inside the thread.  Sums are
+// formed per thread in FP64, reduced over the wavefront by shuffles, over the
+// workgroup through LDS, and written as one partial per workgroup and RHS;
+// launch_reduce then adds the partials in a fixed tree order.  No floating
+// point atomics anywhere, so every reduction is bitwise reproducible.
+#include "common.h"
+#include "engine.h"
+
+namespace grg {
+
+constexpr int kBlasSB = 256;
+
+#define SITE_LOOP_BEGIN(sh)                                            \
+    const int nsb_ = ((sh).g.V + kBlasSB - 1) / kBlasSB;               \
+    const ItemRange it_ = xcd_items(nsb_);                             \
+    for (int w_ = it_.begin; w_ < it_.end; w_ += it_.step) {           \
+        const int s = w_ * kBlasSB + (int)threadIdx.x;                 \
+        const bool valid = s < (sh).g.V;
+
+#define SITE_LOOP_END }
+
+// per-wave LDS accumulators, summed and written at the end of the kernel
+template <int K>
+struct Partial {
+    double (*red)[K];  // [4 * nrhs] rows of K, row = wave * nrhs + rhs
+    int nrhs;
+    __device__ void init(double *smem, int nrhs_)
+    {
+        red = (double (*)[K])smem;
+        nrhs = nrhs_;
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        for (int i = lane; i < nrhs * K; i += 64) red[wave * nrhs + i / K][i % K] = 0.0;
+        __syncthreads();
+    }
+    __device__ void add(int r, const double (&v)[K])
+    {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double t = wave_sum(v[k]);
+            if (lane == 0) red[wave * nrhs + r][k] += t;
+        }
+    }
+    __device__ void flush(double *partials)
+    {
+        __syncthreads();
+        const int nw = blockDim.x >> 6;
+        for (int i = threadIdx.x; i < nrhs * K; i += blockDim.x) {
+            double t = 0;
+            for (int w = 0; w < nw; ++w) t += red[w * nrhs + i / K][i % K];
+            partials[(size_t)blockIdx.x * nrhs * K + i] = t;
+        }
+    }
+};
+
+// ------------------------------------------------------------------ MR / GCR step
+template <int P>
+__global__ void __launch_bounds__(256) mr_update_kernel(BlasShape sh, void *x_, void *r_,
+                                                        const void *q_, const void *p_,
+                                                        const double2 *alpha, double *partials)
+{
+    typedef typename Store<P>::S S;
+    typedef typename Store<P>::R R;
+    __shared__ double smem[4 * kMaxRhs];
+    Partial<1> part;
+    part.init(smem, sh.nrhs);
+    S *x = (S *)x_, *r = (S *)r_;
+    const S *q = (const S *)q_, *p = p_ ? (const S *)p_ : (const S *)r_;
+    const size_t Vs = sh.g.Vs;
+    SITE_LOOP_BEGIN(sh)
+    for (int k = 0; k < sh.nrhs; ++k) {
+        const double2 a2 = alpha[k];
+        const cpx<R> a = {(R)a2.x, (R)a2.y};
+        double rr = 0;
+        if (valid) {
+            const size_t base = (size_t)k * 12 * Vs + s;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const size_t i = base + c * Vs;
+                cpx<R> xv = ldc(x, i), rv = ldc(r, i);
+                const cpx<R> pv = ldc(p, i), qv = ldc(q, i);
+                const cpx<R> ap = cmul(a, pv), aq = cmul(a, qv);
+                xv.re += ap.re; xv.im += ap.im;
+                rv.re -= aq.re; rv.im -= aq.im;
+                stc(x, i, xv);
+                stc(r, i, rv);
+                // the norm of the value actually stored
+                const cpx<R> rs = ldc(r, i);
+                rr += (double)rs.re * rs.re + (double)rs.im * rs.im;
+            }
+        }
+        const double v[1] = {rr};
+        part.add(k, v);
+    }
+    SITE_LOOP_END
+    part.flush(partials);
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) norm2_kernel(BlasShape sh, const void *v_, double *partials)
+{
+    typedef typename Store<P>::S S;
+    typedef typename Store<P>::R R;
+    __shared__ double smem[4 * kMaxRhs];
+    Partial<1> part;
+    part.init(smem, sh.nrhs);
+    const S *v = (const S *)v_;
+    const size_t Vs = sh.g.Vs;
+    SITE_LOOP_BEGIN(sh)
+    for (int k = 0; k < sh.nrhs; ++k) {
+        double t = 0;
+        if (valid) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const cpx<R> a = ldc(v, (size_t)(k * 12 + c) * Vs + s);
+                t += (double)a.re * a.re + (double)a.im * a.im;
+            }
+        }
+        const double vv[1] = {t};
+        part.add(k, vv);
+    }
+    SITE_LOOP_END
+    part.flush(partials);
+}
+
+__global__ void __launch_bounds__(256) sub_norm_kernel(BlasShape sh, const double2 *b,
+                                                       const double2 *ax, double2 *r,
+                                                       double *partials)
+{
+    __shared__ double smem[4 * kMaxRhs];
+    Partial<1> part;
+    part.init(smem, sh.nrhs);
+    const size_t Vs = sh.g.Vs;
+    SITE_LOOP_BEGIN(sh)
+    for (int k = 0; k < sh.nrhs; ++k) {
+        double t = 0;
+        if (valid) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const size_t i = (size_t)(k * 12 + c) * Vs + s;
+                const double2 bv = b[i], av = ax[i];
+                const double2 d = make_double2(bv.x - av.x, bv.y - av.y);
+                r[i] = d;
+                t += d.x * d.x + d.y * d.y;
+            }
+        }
+        const double vv[1] = {t};
+        part.add(k, vv);
+    }
+    SITE_LOOP_END
+    part.flush(partials);
+}
+
+// y = beta*y + f(scale[k]) * x, f = identity / 1/sqrt / sqrt
+template <int PI, int PO>
+__global__ void __launch_bounds__(256) axpy_convert_kernel(BlasShape sh, const void *x_, void *y_,
+                                                           const double *scale, int mode,
+                                                           int beta, const int *active)
+{
+    typedef typename Store<PI>::S SI;
+    typedef typename Store<PI>::R RI;
+    typedef typename Store<PO>::S SO;
+    typedef typename Store<PO>::R RO;
+    const SI *x = (const SI *)x_;
+    SO *y = (SO *)y_;
+    const size_t Vs = sh.g.Vs;
+    SITE_LOOP_BEGIN(sh)
+    if (valid) {
+        for (int k = 0; k < sh.nrhs; ++k) {
+            double f = scale ? scale[k] : 1.0;
+            if (mode == 1) f = f > 0 ? 1.0 / sqrt(f) : 0.0;
+            if (mode == 2) f = sqrt(f);
+            if (active && !active[k]) f = 0.0;
+            const RO fo = (RO)f;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const size_t i = (size_t)(k * 12 + c) * Vs + s;
+                const cpx<RI> a = ldc(x, i);
+                cpx<RO> o = {fo * (RO)a.re, fo * (RO)a.im};
+                if (beta) {
+                    const cpx<RO> yo = ldc(y, i);
+                    o.re += yo.re;
+                    o.im += yo.im;
+                }
+                stc(y, i, o);
+            }
+        }
+    }
+    SITE_LOOP_END
+}
+
+__global__ void __launch_bounds__(256) xmy_kernel(BlasShape sh, const double2 *x, double2 *y)
+{
+    const size_t Vs = sh.g.Vs;
+    SITE_LOOP_BEGIN(sh)
+    if (valid) {
+        for (int k = 0; k < sh.nrhs; ++k) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const size_t i = (size_t)(k * 12 + c) * Vs + s;
+                const double2 a = x[i], b = y[i];
+                y[i] = make_double2(a.x - b.x, a.y - b.y);
+            }
+        }
+    }
+    SITE_LOOP_END
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) copy_kernel(BlasShape sh, const void *x_, void *y_)
+{
+    typedef typename Store<P>::S S;
+    const S *x = (const S *)x_;
+    S *y = (S *)y_;
+    const size_t Vs = sh.g.Vs;
+    SITE_LOOP_BEGIN(sh)
+    if (valid) {
+        for (int k = 0; k < sh.nrhs; ++k) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const size_t i = (size_t)(k * 12 + c) * Vs + s;
+                y[i] = x[i];
+            }
+        }
+    }
+    SITE_LOOP_END
+}
+
+__global__ void fill_zero_kernel(uint4 *p, size_t n16, uint8_t *tail, size_t ntail)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+        p[i] = make_uint4(0, 0, 0, 0);
+    if (blockIdx.x == 0 && threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+// ------------------------------------------------------------------ GCR(m > 1)
+template <int P>
+__global__ void __launch_bounds__(256) multidot_kernel(BlasShape sh, const void *Q_, int k,
+                                                       const void *q_, double *partials)
+{
+    typedef typename Store<P>::S S;
+    typedef typename Store<P>::R R;
+    extern __shared__ double dsm[];
+    const S *Q = (const S *)Q_, *q = (const S *)q_;
+    const size_t Vs = sh.g.Vs;
+    const size_t vstride = (size_t)sh.nrhs * 12 * Vs;
+    const int nr = sh.nrhs * k;  // rows (rhs, j)
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double (*red)[2] = (double (*)[2])dsm;  // [4 waves][nr][2]
+    for (int i = lane; i < nr * 2; i += 64) red[wave * nr + i / 2][i % 2] = 0.0;
+    __syncthreads();
+    SITE_LOOP_BEGIN(sh)
+    for (int r = 0; r < sh.nrhs; ++r) {
+        cpx<R> qv[12];
+        if (valid) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) qv[c] = ldc(q, (size_t)(r * 12 + c) * Vs + s);
+        }
+        for (int j = 0; j < k; ++j) {
+            double re = 0, im = 0;
+            if (valid) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    const cpx<R> a = ldc(Q, j * vstride + (size_t)(r * 12 + c) * Vs + s);
+                    re += (double)a.re * qv[c].re + (double)a.im * qv[c].im;
+                    im += (double)a.re * qv[c].im - (double)a.im * qv[c].re;
+                }
+            }
+            re = wave_sum(re);
+            im = wave_sum(im);
+            if (lane == 0) {
+                red[wave * nr + r * k + j][0] += re;
+                red[wave * nr + r * k + j][1] += im;
+            }
+        }
+    }
+    SITE_LOOP_END
+    __syncthreads();
+    const int nw = blockDim.x >> 6;
+    for (int i = threadIdx.x; i < nr * 2; i += blockDim.x) {
+        double t = 0;
+        for (int w = 0; w < nw; ++w) t += red[w * nr + i / 2][i % 2];
+        partials[(size_t)blockIdx.x * nr * 2 + i] = t;
+    }
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) orthogonalise_kernel(BlasShape sh, const void *Q_,
+                                                            const void *P_, int k,
+                                                            const double2 *beta, void *q_,
+                                                            void *p_, const void *r_,
+                                                            double *partials)
+{
+    typedef typename Store<P>::S S;
+    typedef typename Store<P>::R R;
+    __shared__ double smem[4 * kMaxRhs * 3];
+    Partial<3> part;
+    part.init(smem, sh.nrhs);
+    const S *Q = (const S *)Q_, *Pm = (const S *)P_, *rr = (const S *)r_;
+    S *q = (S *)q_, *p = (S *)p_;
+    const size_t Vs = sh.g.Vs;
+    const size_t vstride = (size_t)sh.nrhs * 12 * Vs;
+    SITE_LOOP_BEGIN(sh)
+    for (int r = 0; r < sh.nrhs; ++r) {
+        double d[3] = {0, 0, 0};
+        if (valid) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const size_t i = (size_t)(r * 12 + c) * Vs + s;
+                cpx<R> qv = ldc(q, i), pv = ldc(p, i);
+                for (int j = 0; j < k; ++j) {
+                    const double2 b2 = beta[r * kMaxRhs + j];
+                    const cpx<R> b = {(R)b2.x, (R)b2.y};
+                    const cpx<R> tq = cmul(b, ldc(Q, j * vstride + i));
+                    const cpx<R> tp = cmul(b, ldc(Pm, j * vstride + i));
+                    qv.re -= tq.re; qv.im -= tq.im;
+                    pv.re -= tp.re; pv.im -= tp.im;
+                }
+                stc(q, i, qv);
+                stc(p, i, pv);
+                const cpx<R> qs = ldc(q, i), rv = ldc(rr, i);
+                d[0] += (double)qs.re * rv.re + (double)qs.im * rv.im;
+                d[1] += (double)qs.re * rv.im - (double)qs.im * rv.re;
+                d[2] += (double)qs.re * qs.re + (double)qs.im * qs.im;
+            }
+        }
+        part.add(r, d);
+    }
+    SITE_LOOP_END
+    part.flush(partials);
+}
+
+// ------------------------------------------------------------------ reductions
+__global__ void __launch_bounds__(256) reduce_kernel(int mode, const double *partials, int nparts,
+                                                     int nrhs, double2 *alpha, double *out2,
+                                                     const double *thr2, int *active)
+{
+    __shared__ double sm[3][256];
+    const int r = blockIdx.x;
+    const int K = mode == kAlpha ? 3 : 1;
+    double acc[3] = {0, 0, 0};
+    for (int i = threadIdx.x; i < nparts; i += 256)
+        for (int k = 0; k < K; ++k) acc[k] += partials[((size_t)i * nrhs + r) * K + k];
+    for (int k = 0; k < K; ++k) sm[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int k = 0; k < K; ++k) sm[k][threadIdx.x] += sm[k][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (mode == kAlpha) {
+            const double qq = sm[2][0];
+            const bool on = (active == nullptr || active[r]) && qq > 0;
+            alpha[r] = on ? make_double2(sm[0][0] / qq, sm[1][0] / qq) : make_double2(0.0, 0.0);
+            if (out2) out2[r] = qq;
+        } else {
+            out2[r] = sm[0][0];
+            if (active) active[r] = sm[0][0] > thr2[r] ? 1 : 0;
+        }
+    }
+}
+
+// beta[r][j] = <q_j, q> / |q_j|^2 ; qnorm2 laid out [j][kMaxRhs]
+__global__ void __launch_bounds__(256) reduce_multi_kernel(const double *partials, int nparts,
+                                                           int nrhs, int k, const double *qnorm2,
+                                                           const int *active, double2 *beta)
+{
+    __shared__ double sm[2][256];
+    const int r = blockIdx.x / k, j = blockIdx.x % k;
+    const int nr = nrhs * k;
+    double a0 = 0, a1 = 0;
+    for (int i = threadIdx.x; i < nparts; i += 256) {
+        a0 += partials[((size_t)i * nr + r * k + j) * 2];
+        a1 += partials[((size_t)i * nr + r * k + j) * 2 + 1];
+    }
+    sm[0][threadIdx.x] = a0;
+    sm[1][threadIdx.x] = a1;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            sm[0][threadIdx.x] += sm[0][threadIdx.x + o];
+            sm[1][threadIdx.x] += sm[1][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double n2 = qnorm2[j * kMaxRhs + r];
+        const bool on = (active == nullptr || active[r]) && n2 > 0;
+        beta[r * kMaxRhs + j] = on ? make_double2(sm[0][0] / n2, sm[1][0] / n2) : make_double2(0.0, 0.0);
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+#define DISPATCH_P(prec, KERNEL, ...)                                                           \
+    switch (prec) {                                                                             \
+    case GRG_FP64: hipLaunchKernelGGL(KERNEL<GRG_FP64>, __VA_ARGS__); break;                    \
+    case GRG_FP32: hipLaunchKernelGGL(KERNEL<GRG_FP32>, __VA_ARGS__); break;                    \
+    case GRG_BF16: hipLaunchKernelGGL(KERNEL<GRG_BF16>, __VA_ARGS__); break;                    \
+    default: return hipErrorInvalidValue;                                                       \
+    }
+
+static bool shape_ok(const BlasShape &sh)
+{
+    return sh.nrhs >= 1 && sh.nrhs <= kMaxRhs && sh.grid >= 8 && sh.grid % 8 == 0;
+}
+
+hipError_t launch_reduce(int mode, const double *partials, int nparts, int nrhs, double2 *alpha,
+                         double *out2, const double *thr2, int *active, hipStream_t st)
+{
+    hipLaunchKernelGGL(reduce_kernel, dim3(nrhs), dim3(256), 0, st, mode, partials, nparts, nrhs,
+                       alpha, out2, thr2, active);
+    return hipGetLastError();
+}
+
+hipError_t launch_mr_update(int prec, const BlasShape &sh, void *x, void *r, const void *q,
+                            const void *p, const double2 *alpha, double *partials,
+                            hipStream_t st)
+{
+    if (!shape_ok(sh)) return hipErrorInvalidValue;
+    DISPATCH_P(prec, mr_update_kernel, dim3(sh.grid), dim3(kBlasSB), 0, st, sh, x, r, q, p, alpha,
+               partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm2(int prec, const BlasShape &sh, const void *v, double *partials,
+                        hipStream_t st)
+{
+    if (!shape_ok(sh)) return hipErrorInvalidValue;
+    DISPATCH_P(prec, norm2_kernel, dim3(sh.grid), dim3(kBlasSB), 0, st, sh, v, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_sub_norm(const BlasShape &sh, const void *b, const void *ax, void *r,
+                           double *partials, hipStream_t st)
+{
+    if (!shape_ok(sh)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(sub_norm_kernel, dim3(sh.grid), dim3(kBlasSB), 0, st, sh,
+                       (const double2 *)b, (const double2 *)ax, (double2 *)r, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_convert(int prec_in, int prec_out, const BlasShape &sh, const void *x,
+                               void *y, const double *scale, int mode, int beta,
+                               const int *active, hipStream_t st)
+{
+    if (!shape_ok(sh)) return hipErrorInvalidValue;
+    dim3 g(sh.grid), b(kBlasSB);
+#define AXC(PI, PO)                                                                                \
+    if (prec_in == PI && prec_out == PO) {                                                         \
+        hipLaunchKernelGGL((axpy_convert_kernel<PI, PO>), g, b, 0, st, sh, x, y, scale, mode, beta, \
+                           active);                                                                \
+        return hipGetLastError();                                                                  \
+    }
+    AXC(GRG_FP64, GRG_FP64) AXC(GRG_FP64, GRG_FP32) AXC(GRG_FP64, GRG_BF16)
+    AXC(GRG_FP32, GRG_FP64) AXC(GRG_FP32, GRG_FP32) AXC(GRG_FP32, GRG_BF16)
+    AXC(GRG_BF16, GRG_FP64) AXC(GRG_BF16, GRG_FP32) AXC(GRG_BF16, GRG_BF16)
+#undef AXC
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_xmy(const BlasShape &sh, const void *x, void *y, hipStream_t st)
+{
+    if (!shape_ok(sh)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(xmy_kernel, dim3(sh.grid), dim3(kBlasSB), 0, st, sh, (const double2 *)x,
+                       (double2 *)y);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(int prec, const BlasShape &sh, const void *x, void *y, hipStream_t st)
+{
+    if (!shape_ok(sh)) return hipErrorInvalidValue;
+    DISPATCH_P(prec, copy_kernel, dim3(sh.grid), dim3(kBlasSB), 0, st, sh, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st)
+{
+    if (bytes == 0) return hipSuccess;
+    const size_t n16 = bytes / 16, ntail = bytes % 16;
+    int grid = (int)std::min<size_t>((n16 + 255) / 256 + 1, 8192);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(grid), dim3(256), 0, st, (uint4 *)p, n16,
+                       (uint8_t *)p + n16 * 16, ntail);
+    return hipGetLastError();
+}
+
+hipError_t launch_multidot(int prec, const BlasShape &sh, const void *Q, int k, const void *q,
+                           double *partials, hipStream_t st)
+{
+    if (!shape_ok(sh) || k < 1 || k > kMaxRhs) return hipErrorInvalidValue;
+    const size_t lds = (size_t)4 * sh.nrhs * k * 2 * sizeof(double);
+    DISPATCH_P(prec, multidot_kernel, dim3(sh.grid), dim3(kBlasSB), lds, st, sh, Q, k, q, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_multi(const double *partials, int nparts, int nrhs, int k,
+                               const double *qnorm2, const int *active, double2 *beta,
+                               hipStream_t st)
+{
+    hipLaunchKernelGGL(reduce_multi_kernel, dim3(nrhs * k), dim3(256), 0, st, partials, nparts,
+                       nrhs, k, qnorm2, active, beta);
+    return hipGetLastError();
+}
+
+hipError_t launch_orthogonalise(int prec, const BlasShape &sh, const void *Q, const void *P,
+                                int k, const double2 *beta, void *q, void *p, const void *r,
+                                double *partials, hipStream_t st)
+{
+    if (!shape_ok(sh) || k < 1 || k > kMaxRhs) return hipErrorInvalidValue;
+    DISPATCH_P(prec, orthogonalise_kernel, dim3(sh.grid), dim3(kBlasSB), 0, st, sh, Q, P, k, beta,
+               q, p, r, partials);
+    return hipGetLastError();
+}
+
+}  // namespace grg

@@ -1,0 +1,319 @@
+// D_rr solves and the Schur-complement apply.
+//
+// The coarse operator S_bb = D_bb - D_br D_rr^{-1} D_rb (section 1) is applied
+// matrix-free:
+//     u = x on the coarse sites, 0 elsewhere
+//     y = (D u)_r                         (= D_rb x)
+//     z = D_rr^{-1} y                     (the cost of the method: section 2)
+//     S x = [ D (u - z) ]_b               (= D_bb x - D_br z)
+//
+// D_rr^{-1} is an FP64 defect correction (iterative refinement) around an
+// inner restarted GCR(m) in FP64, FP32 or BF16 storage:
+//     x = 0, r = b
+//     repeat: e ~= A_low^{-1} (r / |r|) to a relative residual eps_in
+//             x += |r| e ;  r = b - A x   (FP64)
+//     until |r| <= tol |b| for every right-hand side.
+// With FP64 inner iterations the loop is a plain FP64 GCR whose result is
+// confirmed by the recomputed FP64 residual.  The inner GCR keeps its residual
+// recursively across restarts (no extra matvec per restart); restart length 1
+// is minimal residual.  Every right-hand side has its own step lengths and a
+// device-side "active" flag that freezes it once it has converged, so the
+// host only reads the residual norms every check_every iterations.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "handles.h"
+
+namespace grg {
+
+static inline int round8(long v) { return (int)std::max<long>(8, ((v + 7) / 8) * 8); }
+
+int dslash_grid(const Geom &g, int nrhs, int SB, int RG)
+{
+    const long items = (long)((g.V + SB - 1) / SB) * ((nrhs + RG - 1) / RG);
+    return round8(std::min<long>(items, 2048));
+}
+
+BlasShape blas_shape(const Geom &g, int nrhs)
+{
+    BlasShape sh;
+    sh.g = g;
+    sh.nrhs = nrhs;
+    sh.grid = round8(std::min<long>((g.V + 255) / 256, 2048));
+    return sh;
+}
+
+static int dslash_sb(const Geom &g) { return g.V >= (1 << 16) ? 128 : 64; }
+
+// One stencil launch, bracketed by profiling events when enabled.
+grg_status run_dslash(grg_schur S, int prec, const void *in, void *out, int sel, int nrhs,
+                      double *partials)
+{
+    grg_lattice L = S->lat;
+    DslashArgs a;
+    a.in = in;
+    a.out = out;
+    a.U = L->U[prec];
+    a.mask = sel < 0 ? nullptr : S->d_mask;
+    a.sel = sel < 0 ? 0 : sel;
+    a.diag = 4.0 + S->m0;
+    a.g = L->g;
+    a.nrhs = nrhs;
+    a.SB = dslash_sb(L->g);
+    a.RG = nrhs;
+    a.partials = partials;
+    const int grid = dslash_grid(L->g, nrhs, a.SB, a.RG);
+    ProfilePool &P = S->prof;
+    const bool ev = P.on && P.used < (int)P.start.size();
+    if (ev) GRG_TRY_HIP(hipEventRecord(P.start[P.used], L->stream));
+    GRG_TRY_HIP(launch_dslash(prec, a, grid, L->stream));
+    if (ev) {
+        GRG_TRY_HIP(hipEventRecord(P.stop[P.used], L->stream));
+        P.prec[P.used] = prec;
+        ++P.used;
+    }
+    ++S->n_dslash;
+    return GRG_OK;
+}
+
+int partial_rows(const Geom &g, int nrhs)
+{
+    return std::max(dslash_grid(g, nrhs, dslash_sb(g), nrhs), blas_shape(g, nrhs).grid);
+}
+
+static grg_status read_norms(grg_schur S, int nrhs, double *host)
+{
+    GRG_TRY_HIP(hipMemcpyAsync(S->h_buf, S->rn2, sizeof(double) * nrhs, hipMemcpyDeviceToHost,
+                               S->lat->stream));
+    GRG_TRY_HIP(hipStreamSynchronize(S->lat->stream));
+    memcpy(host, S->h_buf, sizeof(double) * nrhs);
+    return GRG_OK;
+}
+
+grg_status ensure_inner(grg_schur S, int prec)
+{
+    const Geom &g = S->lat->g;
+    const int m = std::max(1, S->prm.restart);
+    const size_t bytes = spinor_elems(g, S->prm.max_rhs) * prec_bytes(prec);
+    void **bufs[4] = {&S->in_b[prec], &S->in_x[prec], &S->in_r[prec], &S->in_q[prec]};
+    for (void **b : bufs) {
+        if (*b) continue;
+        if (hipMalloc(b, bytes) != hipSuccess) {
+            *b = nullptr;
+            set_error("inner workspace: hipMalloc of %zu bytes failed", bytes);
+            return GRG_ENOMEM;
+        }
+        GRG_TRY_HIP(launch_fill_zero(*b, bytes, S->lat->stream));
+    }
+    if (m > 1 && S->in_m[prec] < m) {
+        if (S->in_P[prec]) hipFree(S->in_P[prec]);
+        if (S->in_Q[prec]) hipFree(S->in_Q[prec]);
+        S->in_P[prec] = S->in_Q[prec] = nullptr;
+        if (hipMalloc(&S->in_P[prec], bytes * m) != hipSuccess ||
+            hipMalloc(&S->in_Q[prec], bytes * m) != hipSuccess) {
+            set_error("GCR(%d) basis: hipMalloc of 2 x %zu bytes failed", m, bytes * m);
+            return GRG_ENOMEM;
+        }
+        GRG_TRY_HIP(launch_fill_zero(S->in_P[prec], bytes * m, S->lat->stream));
+        GRG_TRY_HIP(launch_fill_zero(S->in_Q[prec], bytes * m, S->lat->stream));
+        S->in_m[prec] = m;
+    }
+    return GRG_OK;
+}
+
+// Inner GCR(m) on D_rr in precision prec: solves A x = b (in_b -> in_x) until
+// |r|^2 <= thr[k] per RHS (thr: host copy of the device array thr2) or maxit
+// iterations.
+// Returns the iterations taken in *iters.
+static grg_status inner_gcr(grg_schur S, int prec, int nrhs, const double *thr, int maxit,
+                            int *iters)
+{
+    grg_lattice L = S->lat;
+    hipStream_t st = L->stream;
+    const Geom &g = L->g;
+    const BlasShape sh = blas_shape(g, nrhs);
+    const size_t vbytes = spinor_elems(g, nrhs) * prec_bytes(prec);
+    const size_t vstride = spinor_elems(g, nrhs) * prec_bytes(prec);
+    const int m = std::max(1, S->prm.restart);
+    const int check = std::max(1, S->prm.check_every);
+    const int dgrid = dslash_grid(g, nrhs, dslash_sb(g), nrhs);
+    void *b = S->in_b[prec], *x = S->in_x[prec], *r = S->in_r[prec], *q = S->in_q[prec];
+    char *Pm = (char *)S->in_P[prec], *Qm = (char *)S->in_Q[prec];
+
+    GRG_TRY_HIP(launch_fill_zero(x, vbytes, st));
+    GRG_TRY_HIP(launch_copy(prec, sh, b, r, st));
+    GRG_TRY_HIP(launch_norm2(prec, sh, r, S->partials, st));
+    GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, S->thr2,
+                              S->active, st));
+    double h[kMaxRhs];
+    GRG_TRY(read_norms(S, nrhs, h));
+    auto all_done = [&](const double *n2) {
+        for (int k = 0; k < nrhs; ++k) {
+            if (!isfinite(n2[k])) return -1;
+            if (n2[k] > thr[k]) return 0;
+        }
+        return 1;
+    };
+    int it = 0;
+    int done = all_done(h);
+    while (done == 0 && it < maxit) {
+        const int k = it % m;
+        if (m == 1) {
+            GRG_TRY(run_dslash(S, prec, r, q, 0, nrhs, S->partials));
+            GRG_TRY_HIP(launch_reduce(kAlpha, S->partials, dgrid, nrhs, S->alpha, nullptr, nullptr,
+                                      S->active, st));
+            GRG_TRY_HIP(launch_mr_update(prec, sh, x, r, q, nullptr, S->alpha, S->partials, st));
+        } else {
+            void *pk = Pm + (size_t)k * vstride, *qk = Qm + (size_t)k * vstride;
+            GRG_TRY_HIP(launch_copy(prec, sh, r, pk, st));
+            if (k == 0) {
+                GRG_TRY(run_dslash(S, prec, pk, qk, 0, nrhs, S->partials));
+                GRG_TRY_HIP(launch_reduce(kAlpha, S->partials, dgrid, nrhs, S->alpha, S->qn2,
+                                          nullptr, S->active, st));
+            } else {
+                GRG_TRY(run_dslash(S, prec, pk, qk, 0, nrhs, nullptr));
+                GRG_TRY_HIP(launch_multidot(prec, sh, Qm, k, qk, S->partials, st));
+                GRG_TRY_HIP(launch_reduce_multi(S->partials, sh.grid, nrhs, k, S->qn2, S->active,
+                                                S->beta, st));
+                GRG_TRY_HIP(launch_orthogonalise(prec, sh, Qm, Pm, k, S->beta, qk, pk, r,
+                                                 S->partials, st));
+                GRG_TRY_HIP(launch_reduce(kAlpha, S->partials, sh.grid, nrhs, S->alpha,
+                                          S->qn2 + (size_t)k * kMaxRhs, nullptr, S->active, st));
+            }
+            GRG_TRY_HIP(launch_mr_update(prec, sh, x, r, qk, pk, S->alpha, S->partials, st));
+        }
+        GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, S->thr2,
+                                  S->active, st));
+        ++it;
+        if (it % check == 0 || it == maxit) {
+            GRG_TRY(read_norms(S, nrhs, h));
+            done = all_done(h);
+        }
+    }
+    *iters = it;
+    if (done < 0) {
+        set_error("non-finite residual in the inner solve");
+        return GRG_ENONFINITE;
+    }
+    return GRG_OK;
+}
+
+// b64 (internal FP64, zero on coarse sites) -> x64 = D_rr^{-1} b64.
+grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
+{
+    grg_lattice L = S->lat;
+    hipStream_t st = L->stream;
+    const Geom &g = L->g;
+    const grg_solver_params &p = S->prm;
+    const int prec = p.inner;
+    const BlasShape sh = blas_shape(g, nrhs);
+    const size_t vb64 = spinor_elems(g, nrhs) * 16;
+    GRG_TRY(ensure_inner(S, prec));
+
+    // x = 0, r = b, |b|^2
+    GRG_TRY_HIP(launch_fill_zero(S->x64, vb64, st));
+    GRG_TRY_HIP(launch_copy(GRG_FP64, sh, S->b64, S->r64, st));
+    GRG_TRY_HIP(launch_norm2(GRG_FP64, sh, S->b64, S->partials, st));
+    GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->bn2, nullptr, nullptr,
+                              st));
+    double bn2[kMaxRhs], rn2[kMaxRhs];
+    GRG_TRY_HIP(hipMemcpyAsync(S->h_buf, S->bn2, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+    GRG_TRY_HIP(hipStreamSynchronize(st));
+    memcpy(bn2, S->h_buf, sizeof(double) * nrhs);
+    memcpy(rn2, bn2, sizeof(double) * nrhs);
+
+    int total = 0, outer = 0;
+    grg_status status = GRG_OK;
+    double worst = 0;
+    for (;;) {
+        bool conv = true;
+        worst = 0;
+        for (int k = 0; k < nrhs; ++k) {
+            if (!isfinite(rn2[k])) {
+                set_error("non-finite FP64 residual");
+                return GRG_ENONFINITE;
+            }
+            const double rel = bn2[k] > 0 ? sqrt(rn2[k] / bn2[k]) : 0.0;
+            worst = std::max(worst, rel);
+            if (rel > p.tol) conv = false;
+        }
+        if (conv) break;
+        if (outer >= p.max_outer || total >= p.max_iter) {
+            status = GRG_ENOCONV;
+            set_error("D_rr solve: no convergence after %d outer / %d inner iterations "
+                      "(residual %.3e > %.3e)", outer, total, worst, p.tol);
+            break;
+        }
+        // inner thresholds on the normalised residual r / |r|
+        double thr[kMaxRhs];
+        for (int k = 0; k < nrhs; ++k) {
+            const double need = bn2[k] > 0 && rn2[k] > 0 ? p.tol * sqrt(bn2[k] / rn2[k]) : 1.0;
+            const double rel = prec == GRG_FP64 ? need : std::max(p.inner_tol, 0.5 * need);
+            const bool on = bn2[k] > 0 && sqrt(rn2[k] / bn2[k]) > p.tol;
+            thr[k] = on ? rel * rel : 2.0;  // 2 > |r/|r||^2 = 1: inactive
+        }
+        memcpy(S->h_buf + 2 * kMaxRhs, thr, sizeof(double) * nrhs);
+        GRG_TRY_HIP(hipMemcpyAsync(S->thr2, S->h_buf + 2 * kMaxRhs, sizeof(double) * nrhs,
+                                   hipMemcpyHostToDevice, st));
+        // r_in = r / |r|  (rn2 on the device holds |r|^2)
+        GRG_TRY_HIP(launch_axpy_convert(GRG_FP64, prec, sh, S->r64, S->in_b[prec], S->rn2, 1, 0,
+                                        nullptr, st));
+        int it = 0;
+        GRG_TRY(inner_gcr(S, prec, nrhs, thr, p.max_iter - total, &it));
+        total += it;
+        ++outer;
+        // x += |r| e   (rn2 still holds the outer |r|^2: restore it first)
+        memcpy(S->h_buf + 3 * kMaxRhs, rn2, sizeof(double) * nrhs);
+        GRG_TRY_HIP(hipMemcpyAsync(S->rn2, S->h_buf + 3 * kMaxRhs, sizeof(double) * nrhs,
+                                   hipMemcpyHostToDevice, st));
+        GRG_TRY_HIP(launch_axpy_convert(prec, GRG_FP64, sh, S->in_x[prec], S->x64, S->rn2, 2, 1,
+                                        nullptr, st));
+        // r = b - D_rr x in FP64
+        GRG_TRY(run_dslash(S, GRG_FP64, S->x64, S->t64, 0, nrhs, nullptr));
+        GRG_TRY_HIP(launch_sub_norm(sh, S->b64, S->t64, S->r64, S->partials, st));
+        GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, nullptr,
+                                  nullptr, st));
+        GRG_TRY(read_norms(S, nrhs, rn2));
+    }
+    if (stats) {
+        stats->iters = total;
+        stats->outer = outer;
+        stats->converged = status == GRG_OK;
+        stats->true_rel_resid = worst;
+    }
+    return status;
+}
+
+// x_b (canonical coarse, device) -> y_b
+grg_status schur_apply_internal(grg_schur S, const double *xb, double *yb, int nrhs,
+                                grg_solver_stats *stats)
+{
+    grg_lattice L = S->lat;
+    hipStream_t st = L->stream;
+    const Geom &g = L->g;
+    const BlasShape sh = blas_shape(g, nrhs);
+    // u = x on coarse sites
+    GRG_TRY_HIP(launch_scatter_coarse(xb, S->u64, S->d_bidx, S->nb, g, nrhs, st));
+    // b = (D u)_r
+    GRG_TRY(run_dslash(S, GRG_FP64, S->u64, S->b64, 0, nrhs, nullptr));
+    // z = D_rr^{-1} b   (into x64)
+    grg_status s = drr_solve_internal(S, nrhs, stats);
+    if (s != GRG_OK && s != GRG_ENOCONV) return s;
+    // x64 = u - z ; y_b = [D (u - z)]_b
+    GRG_TRY_HIP(launch_xmy(sh, S->u64, S->x64, st));
+    CoarseArgs c;
+    c.in = S->x64;
+    c.out = yb;
+    c.U = L->U[GRG_FP64];
+    c.q = S->d_q;
+    c.nb = S->nb;
+    c.diag = 4.0 + S->m0;
+    c.g = g;
+    c.nrhs = nrhs;
+    GRG_TRY_HIP(launch_dslash_coarse(c, st));
+    return s;
+}
+
+}  // namespace grg

@@ -1,0 +1,80 @@
+"""GPU Wilson stencil (grg_dirac_apply) against the CPU oracle, element by
+element, in FP64, FP32 and BF16 storage; ragged volumes; many RHS; run-to-run
+determinism."""
+import numpy as np
+import pytest
+
+from grg_inputs import gaussian_vectors, su3_links
+from oracle import matfree
+
+from gpu_support import Lattice, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+# FP32: inputs, links and the 1320-flop stencil in single precision; BF16
+# stores 8 significand bits (unit roundoff 2^-9) for inputs, links and output.
+TOL = {"fp64": 1e-14, "fp32": 2e-6, "bf16": 1.5e-2}
+
+
+def gpu_apply(lat, m0, prec, x):
+    import torch
+
+    xd = to_dev(x)
+    out = torch.empty_like(xd)
+    lat.grg.grg_dirac_apply(lat.h, m0, prec, xd, out, x.shape[0])
+    return to_host(out)
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (4, 4, 4, 8), (6, 2, 10, 4), (3, 5, 7, 2), (8, 8, 8, 16)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_dirac_apply_vs_oracle(dims, prec):
+    lat = Lattice(dims, 0.5, 21)
+    x = gaussian_vectors(12 * lat.V, 3, 21)
+    want = matfree.dirac_apply(lat.links, dims, -0.2, x)
+    got = gpu_apply(lat, -0.2, prec, x)
+    assert rel_err(got, want) < TOL[prec]
+    lat.close()
+
+
+@pytest.mark.parametrize("nrhs", [1, 2, 5, 12, 16])
+def test_dirac_apply_many_rhs(nrhs):
+    dims = (4, 6, 4, 8)
+    lat = Lattice(dims, 0.4, 3)
+    x = gaussian_vectors(12 * lat.V, nrhs, 3)
+    want = matfree.dirac_apply(lat.links, dims, 0.1, x)
+    assert rel_err(gpu_apply(lat, 0.1, "fp64", x), want) < TOL["fp64"]
+    lat.close()
+
+
+def test_dirac_apply_16_4_and_periodic_t():
+    dims = (16, 16, 16, 16)
+    lat = Lattice(dims, 0.5, 2, bc=(1, 1, 1, 1))
+    x = gaussian_vectors(12 * lat.V, 2, 2)
+    want = matfree.dirac_apply(lat.links, dims, -0.2, x, bc=(1, 1, 1, 1))
+    assert rel_err(gpu_apply(lat, -0.2, "fp64", x), want) < TOL["fp64"]
+    lat.close()
+
+
+def test_dirac_apply_deterministic():
+    dims = (8, 8, 8, 8)
+    lat = Lattice(dims, 0.5, 5)
+    x = gaussian_vectors(12 * lat.V, 4, 5)
+    for prec in ("fp64", "fp32", "bf16"):
+        a = gpu_apply(lat, -0.3, prec, x)
+        b = gpu_apply(lat, -0.3, prec, x)
+        assert np.array_equal(a, b)
+    lat.close()
+
+
+def test_dirac_apply_rejects_bad_arguments():
+    import paper_0704_2341_amd as grg
+
+    lat = Lattice((4, 4, 4, 4), 0.4, 1)
+    x = to_dev(np.zeros((1, 12 * 256)))
+    for nrhs in (0, 17):
+        with pytest.raises(grg.GrgError) as e:
+            grg.grg_dirac_apply(lat.h, 0.1, "fp64", x, x, nrhs)
+        assert e.value.status == grg.GRG_EINVAL
+    with pytest.raises(grg.GrgError):
+        grg.grg_dirac_apply(lat.h, 0.1, 7, x, x, 1)
+    lat.close()
