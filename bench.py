@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Throughput of the coarse Dirac operator S_bb = D_bb - D_br D_rr^{-1} D_rb on one GPU.
+
+Workload (one "step" = one S_bb apply of the whole batch, every stage of the
+method on the GPU: scatter to the lattice, D_rb, the D_rr solve, the final
+D_bb/D_br combine and the gather):
+
+  32^4 lattice, periodic in x, y, z and antiperiodic in t; synthetic SU(3)
+  links U = reunitarised exp(i 0.5 sum_k a_k lambda_k), a_k ~ N(0,1), seed 3;
+  Wilson mass m0 = -0.3; Type I permutation (coarse = all-even sites,
+  N_b = 65536); 12 right-hand sides = unit point sources on coarse site 0, one
+  per spin-colour; D_rr solved to a 1e-10 relative FP64 residual.
+
+The product path (--inner, default bf16) stores the inner Krylov vectors and
+links in bfloat16 with FP32 arithmetic inside an FP64 defect correction; the
+plain-FP64 GCR path on the same workload is timed beside it.  value is
+S_bb applies/s (right-hand sides x steps / seconds) with all inputs resident
+in HBM.  The CPU oracle is timed on a bounded sample on the host cores.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "S_bb applies/s + dslash HBM GB/s at 32^4; mixed+learned vs FP64 at 1e-10"
+PEAK_HBM_GBS = 8000.0
+REAL_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dslash_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_0704_2341_amd", "csrc", f)
+                  for f in ("kernels_dslash.hip", "common.h")]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def dslash_bytes_per_launch(prec: str, volume: int, nrhs: int) -> int:
+    """Compulsory bytes of one stencil launch: every site reads 12 complex of
+    input and writes 12 complex of output per RHS, and reads its 4 links
+    (4 x 9 complex) once; neighbour spinors and backward links are re-reads."""
+    b = REAL_BYTES[prec]
+    return volume * (nrhs * 2 * 24 * b + 72 * b)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(prec: str, nrhs: int, dims):
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None if
+    the kernel source changed since they were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    key = f"{prec}_nrhs{nrhs}_{'x'.join(map(str, dims))}"
+    e = t.get("kernels", {}).get(key)
+    return None if e is None else e.get("hbm_bytes_per_launch")
+
+
+def time_applies(grg, s, xb, yb, nrhs, steps, warmup, profile):
+    import torch
+
+    for _ in range(warmup):
+        grg.grg_schur_apply(s, xb, yb, nrhs)
+    grg.grg_profile_enable(s, profile)
+    grg.grg_profile_reset(s)
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        stats.append(grg.grg_schur_apply(s, xb, yb, nrhs))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = {p: grg.grg_profile_read(s, p) for p in ("fp64", "fp32", "bf16")}
+    grg.grg_profile_enable(s, False)
+    return t1 - t0, stats, prof
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--inner", default="bf16", choices=["bf16", "fp32", "fp64"])
+    ap.add_argument("--inner-tol", type=float, default=None)
+    ap.add_argument("--restart", type=int, default=1)
+    ap.add_argument("--fp64-restart", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--dims", default="32,32,32,32")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the stencil autotuner")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the multi-GPU path is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_0704_2341_amd as grg
+    from grg_inputs import point_sources, su3_links
+
+    dims = tuple(int(d) for d in args.dims.split(","))
+    volume = int(np.prod(dims))
+    m0, eps, seed, nrhs, tol = -0.3, 0.5, 3, 12, 1e-10
+    inner_tol = args.inner_tol or {"bf16": 1e-2, "fp32": 1e-5, "fp64": tol}[args.inner]
+
+    log(f"links {dims} eps={eps} seed={seed}")
+    t = time.perf_counter()
+    links = su3_links(dims, eps, seed)
+    log(f"links ready in {time.perf_counter() - t:.1f} s")
+    torch.cuda.init()
+    lat = grg.grg_lattice_create(dims, (1, 1, 1, -1))
+    grg.grg_gauge_set(lat, links)
+    q, nb = grg.grg_permutation_block(dims, grg.GRG_PERM_I, False)
+    xb_host = point_sources(nb, nrhs)
+    xb = torch.from_numpy(xb_host).to("cuda")
+    yb = torch.empty_like(xb)
+
+    prm = grg.grg_solver_params_default(tol=tol, inner=args.inner, inner_tol=inner_tol,
+                                        restart=args.restart, max_rhs=nrhs, max_iter=4000)
+    s = grg.grg_schur_create(lat, m0, q, nb, prm)
+    if not args.no_tune:
+        t = time.perf_counter()
+        grg.grg_schur_tune(s, nrhs)
+        log(f"tuned in {time.perf_counter() - t:.1f} s: "
+            f"{args.inner} {grg.grg_schur_tune_info(s, args.inner, nrhs)}, "
+            f"fp64 {grg.grg_schur_tune_info(s, 'fp64', nrhs)}")
+    log(f"timing {args.inner} path: warmup {args.warmup}, steps {args.steps}")
+    dt, stats, prof = time_applies(grg, s, xb, yb, nrhs, args.steps, args.warmup, True)
+    y_mixed = yb.cpu().numpy()
+    value = nrhs * args.steps / dt
+    st = stats[-1]
+    log(f"{args.inner}: {dt / args.steps * 1e3:.2f} ms/step, {value:.1f} applies/s, "
+        f"iters {st['iters']} outer {st['outer']} resid {st['true_rel_resid']:.2e}")
+
+    kernels = {}
+    for p, (cnt, ms) in prof.items():
+        if cnt:
+            avg = ms / cnt
+            gbs = dslash_bytes_per_launch(p, volume, nrhs) / (avg * 1e-3) / 1e9
+            kernels[f"dslash_{p}"] = {"launches": cnt, "avg_ms": avg, "alg_GBps": gbs,
+                                      "alg_bytes_per_launch": dslash_bytes_per_launch(p, volume, nrhs)}
+    dom = f"dslash_{args.inner}"
+    dk = kernels[dom]
+    traffic = measured_traffic(args.inner, nrhs, dims)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBps"], "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": dk["alg_GBps"] / PEAK_HBM_GBS,
+                "traffic": traffic, "alg_bytes_per_launch": dk["alg_bytes_per_launch"],
+                "avg_launch_ms": dk["avg_ms"]}
+
+    fp64 = None
+    if not args.no_fp64 and args.inner != "fp64":
+        prm64 = grg.grg_solver_params_default(tol=tol, inner="fp64", restart=args.fp64_restart,
+                                              max_rhs=nrhs, max_iter=4000)
+        s64 = grg.grg_schur_create(lat, m0, q, nb, prm64)
+        if not args.no_tune:
+            grg.grg_schur_tune(s64, nrhs)
+        k64 = args.fp64_steps or max(1, args.steps // 2)
+        log(f"timing fp64 path: steps {k64}")
+        dt64, st64, prof64 = time_applies(grg, s64, xb, yb, nrhs, k64, 1, True)
+        y64 = yb.cpu().numpy()
+        diff = np.linalg.norm(y_mixed - y64, axis=1) / np.linalg.norm(y64, axis=1)
+        cnt, ms = prof64["fp64"]
+        fp64 = {"value": nrhs * k64 / dt64, "ms_per_step": dt64 / k64 * 1e3,
+                "iters": st64[-1]["iters"], "restart": args.fp64_restart,
+                "true_rel_resid": st64[-1]["true_rel_resid"],
+                "dslash_fp64_avg_ms": ms / cnt,
+                "dslash_fp64_alg_GBps": dslash_bytes_per_launch("fp64", volume, nrhs) / (ms / cnt * 1e-3) / 1e9,
+                "max_rel_diff_mixed_vs_fp64": float(diff.max())}
+        log(f"fp64: {fp64['ms_per_step']:.2f} ms/step, {fp64['value']:.1f} applies/s, "
+            f"diff vs mixed {diff.max():.2e}")
+        grg.grg_schur_destroy(s64)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import matfree
+
+        log("timing the CPU oracle on one right-hand side")
+        t = time.perf_counter()
+        y_or, it_or, rr_or = matfree.schur_apply(links, dims, m0, q, nb, xb_host[:1], restart=8, tol=tol)
+        dt_cpu = time.perf_counter() - t
+        agree = float(np.linalg.norm(y_mixed[0] - y_or[0]) / np.linalg.norm(y_or[0]))
+        cpu = {"value": 1.0 / dt_cpu, "unit": "S_bb applies/s", "cores": matfree.num_threads(),
+               "kind": "oracle",
+               "sample": f"one of the 12 point sources, full S_bb apply at {args.dims.replace(',', 'x')} "
+                         f"(C oracle, GCR(8) to {tol:g}, {int(it_or[0])} iterations) in {dt_cpu:.1f} s",
+               "gpu_vs_oracle_rel_diff": agree}
+        log(f"oracle: {dt_cpu:.1f} s per apply, GPU agreement {agree:.2e}")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "S_bb applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"bf16": "bf16-store/f32-arith inner + f64 outer",
+                  "fp32": "f32 inner + f64 outer", "fp64": "f64"}[args.inner],
+        "data": "synthetic",
+        "config": {"workload": f"S_bb apply, {args.dims.replace(',', 'x')} Wilson, Type I, m0={m0}, "
+                               f"eps={eps}, {nrhs} point sources, tol={tol:g}",
+                   "lattice": list(dims), "nrhs": nrhs, "inner": args.inner,
+                   "inner_tol": inner_tol, "restart": args.restart, "tol": tol,
+                   "dslash_launch": grg.grg_schur_tune_info(s, args.inner, nrhs),
+                   "parallelism": "1 GPU"},
+        "solver": {"iters": st["iters"], "outer": st["outer"],
+                   "true_rel_resid": st["true_rel_resid"], "n_dslash": st["n_dslash"]},
+        "kernels": kernels,
+        "roofline": roofline,
+        "fp64_gcr": fp64,
+        "speedup_vs_fp64": (value / fp64["value"]) if fp64 else None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    grg.grg_schur_destroy(s)
+    grg.grg_lattice_destroy(lat)
+
+
+if __name__ == "__main__":
+    main()

@@ -88,10 +88,9 @@ def su3_links(dims, eps: float, seed: int, chunk: int = 1 << 16) -> np.ndarray:
 
     def one(s):
         e = min(s + chunk, v * 4)
-        h = np.einsum("nk,kij->nij", a[s:e], lam)
+        h = (a[s:e] @ lam.reshape(8, 9)).reshape(-1, 3, 3)
         w, vec = np.linalg.eigh(h)
-        ph = np.exp(1j * eps * w)
-        u0 = np.einsum("nij,nj,nkj->nik", vec, ph, np.conj(vec))
+        u0 = (vec * np.exp(1j * eps * w)[:, None, :]) @ np.conj(vec).transpose(0, 2, 1)
         out[s:e] = _reunitarise(u0)
 
     starts = range(0, v * 4, chunk)

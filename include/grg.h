@@ -150,6 +150,18 @@ grg_status grg_schur_apply(grg_schur s, const double *x_b, double *y_b, int nrhs
  * applying S_bb to unit vectors.  GRG_ETOO_LARGE if it exceeds cap_bytes. */
 grg_status grg_schur_assemble(grg_schur s, double *S, size_t cap_bytes);
 
+/* Autotuner: time every candidate launch shape of the stencil (sites per
+ * workgroup, right-hand sides per thread, hop grouping, grid size) for nrhs
+ * right-hand sides, in FP64 and in the inner precision, on this handle's
+ * workspaces, and keep the fastest for later calls with that nrhs.  Every
+ * candidate evaluates each site in the same order, so tuning changes speed,
+ * not results.  Takes a few hundred stencil launches. */
+grg_status grg_schur_tune(grg_schur s, int nrhs);
+/* The launch used for (precision, nrhs): info = {sites per workgroup, RHS per
+ * thread, one-hop-per-iteration flag, workgroups}; *ms = its tuned time per
+ * launch, or -1 if untuned (defaults in use). */
+grg_status grg_schur_tune_info(grg_schur s, int precision, int nrhs, int32_t info[4], float *ms);
+
 /* Kernel timing: with profiling on, every dslash launch is bracketed by HIP
  * events on the lattice stream; grg_profile_read returns the count and the
  * summed milliseconds since the last reset, per dslash precision. */

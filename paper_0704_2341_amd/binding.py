@@ -38,7 +38,8 @@ EXPORTS = (
     "grg_last_error", "grg_version", "grg_solver_params_default", "grg_lattice_create",
     "grg_lattice_destroy", "grg_lattice_volume", "grg_gauge_set", "grg_permutation_block",
     "grg_dirac_apply", "grg_schur_create", "grg_schur_destroy", "grg_schur_set_params",
-    "grg_drr_solve", "grg_schur_apply", "grg_schur_assemble", "grg_profile_enable",
+    "grg_drr_solve", "grg_schur_apply", "grg_schur_assemble", "grg_schur_tune",
+    "grg_schur_tune_info", "grg_profile_enable",
     "grg_profile_read", "grg_profile_reset",
 )
 
@@ -103,6 +104,8 @@ def load():
         "grg_drr_solve": (C.c_int, [vp, vp, vp, C.c_int, C.POINTER(grg_solver_stats)]),
         "grg_schur_apply": (C.c_int, [vp, vp, vp, C.c_int, C.POINTER(grg_solver_stats)]),
         "grg_schur_assemble": (C.c_int, [vp, vp, C.c_size_t]),
+        "grg_schur_tune": (C.c_int, [vp, C.c_int]),
+        "grg_schur_tune_info": (C.c_int, [vp, C.c_int, C.c_int, i32p, C.POINTER(C.c_float)]),
         "grg_profile_enable": (C.c_int, [vp, C.c_int]),
         "grg_profile_read": (C.c_int, [vp, C.c_int, i64p, dp]),
         "grg_profile_reset": (C.c_int, [vp]),
@@ -244,6 +247,18 @@ def grg_schur_assemble(s, n_coarse):
     buf = np.zeros(n * n, dtype=np.complex128)
     _check(load().grg_schur_assemble(s, C.c_void_p(buf.ctypes.data), buf.nbytes))
     return buf.reshape(n, n).T  # column-major storage
+
+
+def grg_schur_tune(s, nrhs):
+    _check(load().grg_schur_tune(s, int(nrhs)))
+
+
+def grg_schur_tune_info(s, precision, nrhs):
+    """{'SB', 'RG', 'split', 'grid', 'ms'} of the stencil launch in use."""
+    info = (C.c_int32 * 4)()
+    ms = C.c_float()
+    _check(load().grg_schur_tune_info(s, _prec(precision), int(nrhs), info, C.byref(ms)))
+    return {"SB": info[0], "RG": info[1], "split": info[2], "grid": info[3], "ms": ms.value}
 
 
 def grg_profile_enable(s, on=True):

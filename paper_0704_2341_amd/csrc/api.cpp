@@ -32,6 +32,8 @@ grg_status run_dslash(grg_schur S, int prec, const void *in, void *out, int sel,
                       double *partials);
 int partial_rows(const Geom &g, int nrhs);
 int dslash_grid(const Geom &g, int nrhs, int SB, int RG);
+DslashTune default_tune(const Geom &g, int prec, int nrhs);
+grg_status tune_dslash(grg_schur S, int prec, int nrhs, int reps);
 
 static grg_status dmalloc(void **p, size_t bytes, const char *what)
 {
@@ -272,10 +274,12 @@ grg_status grg_dirac_apply(grg_lattice L, double m0, int precision, const double
     a.diag = 4.0 + m0;
     a.g = L->g;
     a.nrhs = nrhs;
-    a.SB = L->g.V >= (1 << 16) ? 128 : 64;
-    a.RG = nrhs;
+    const DslashTune t = default_tune(L->g, precision, nrhs);
+    a.SB = t.SB;
+    a.RG = t.RG;
+    a.split = t.split;
     a.partials = nullptr;
-    GRG_TRY_HIP(launch_dslash(precision, a, dslash_grid(L->g, nrhs, a.SB, a.RG), L->stream));
+    GRG_TRY_HIP(launch_dslash(precision, a, t.grid, L->stream));
     GRG_TRY_HIP(launch_unpack_spinor(precision, L->tmp_out, out, L->g, nrhs, L->stream));
     GRG_TRY_HIP(hipStreamSynchronize(L->stream));
     return GRG_OK;
@@ -367,7 +371,7 @@ grg_status grg_schur_create(grg_lattice L, double m0, const int32_t *q, int32_t 
     ALLOC(S->rn2, sizeof(double) * kMaxRhs);
     ALLOC(S->thr2, sizeof(double) * kMaxRhs);
     ALLOC(S->qn2, sizeof(double) * kMaxRhs * kMaxRhs);
-    ALLOC(S->bn2, sizeof(double) * kMaxRhs);
+    ALLOC(S->bn2, sizeof(double) * 2 * kMaxRhs);  // |b|^2, then the outer |r|^2
     ALLOC(S->active, sizeof(int) * kMaxRhs);
 #undef ALLOC
     if (s == GRG_OK && hipHostMalloc((void **)&S->h_buf, sizeof(double) * 4 * kMaxRhs) != hipSuccess) {
@@ -516,6 +520,33 @@ grg_status grg_schur_assemble(grg_schur S, double *out, size_t cap_bytes)
         GRG_TRY_HIP(hipMemcpy(out + j0 * n * 2, S->cb_out, n * 16 * cnt, hipMemcpyDeviceToHost));
     }
     return worst;
+}
+
+grg_status grg_schur_tune(grg_schur S, int nrhs)
+{
+    if (!S) return set_error("null argument"), GRG_EINVAL;
+    if (nrhs < 1 || nrhs > S->prm.max_rhs)
+        return set_error("nrhs = %d outside 1..max_rhs = %d", nrhs, S->prm.max_rhs), GRG_EINVAL;
+    DeviceGuard dg(S->lat->device);
+    GRG_TRY(tune_dslash(S, GRG_FP64, nrhs, 3));
+    if (S->prm.inner != GRG_FP64) GRG_TRY(tune_dslash(S, S->prm.inner, nrhs, 3));
+    GRG_TRY_HIP(hipStreamSynchronize(S->lat->stream));
+    return GRG_OK;
+}
+
+grg_status grg_schur_tune_info(grg_schur S, int precision, int nrhs, int32_t info[4], float *ms)
+{
+    if (!S || !info || !ms) return set_error("null argument"), GRG_EINVAL;
+    if (precision < 0 || precision > 2 || nrhs < 1 || nrhs > kMaxRhs)
+        return set_error("bad precision or nrhs"), GRG_EINVAL;
+    const DslashTune &t = S->tune[precision][nrhs];
+    const DslashTune d = t.valid ? t : default_tune(S->lat->g, precision, nrhs);
+    info[0] = d.SB;
+    info[1] = d.RG;
+    info[2] = d.split;
+    info[3] = d.grid;
+    *ms = t.valid ? t.ms : -1.0f;
+    return GRG_OK;
 }
 
 grg_status grg_profile_enable(grg_schur S, int on)

@@ -1,11 +1,18 @@
 // Internal definitions shared by the kernels and the host engine.
 //
-// Internal field layout (private; the boundary is canonical):
-//   spinor field, nrhs right-hand sides:  elem(rhs, c, s) at  (rhs*12 + c)*Vs + s
-//     c = 3*spin + colour, s = lexicographic site (x fastest), Vs = V padded;
-//   gauge field:                          elem(mu, e, s)  at  (mu*9 + e)*Vs + s
-//     e = 3*row + col, the boundary sign bc[mu] folded into U_mu(x) on the
-//     last slice x_mu = L_mu - 1.
+// Internal field layout (private; the boundary is canonical): sites are
+// grouped in tiles of 64 consecutive lexicographic sites (one wavefront), and
+// inside a tile every component is a contiguous run of 64 values.
+//   spinor field with nrhs right-hand sides, site s, RHS r, c = 3*spin + colour:
+//     fidx = ((tile(s) * nrhs + r) * 12 + c) * 64 + lane(s)
+//   gauge field, direction mu, entry e = 3*row + col:
+//     lidx = ((tile(s) * 4 + mu) * 9 + e) * 64 + lane(s)
+//   with the boundary sign bc[mu] folded into U_mu(x) on the last slice
+//   x_mu = L_mu - 1.
+// A wavefront's loads for one component are one coalesced 64-wide run, and all
+// the data of a tile (every RHS) sits in one contiguous block, so the pages a
+// wavefront touches are few (a component-major layout would put each of the
+// 12 x 9 neighbour components and 72 link entries a field's length apart).
 // One complex number per element: double2 (FP64), float2 (FP32) or a 32-bit
 // word holding two bfloat16 (re in the low half, im in the high half).
 #pragma once
@@ -23,7 +30,7 @@ typedef uint32_t bf16x2;
 struct Geom {
     int L[4];
     int V;   // number of sites
-    int Vs;  // component stride (V rounded up to a multiple of 256)
+    int Vs;  // V rounded up to a whole number of 64-site tiles (a multiple of 256)
 };
 
 // Work decomposition of the site-parallel kernels: blocks of SB sites
@@ -35,6 +42,15 @@ struct Launch {
     int RG;       // right-hand sides per work item (looped inside a thread)
     int grid;     // workgroups (multiple of 8)
 };
+
+__host__ __device__ __forceinline__ size_t fidx(int s, int r, int c, int nrhs)
+{
+    return ((((size_t)(s >> 6) * nrhs + r) * 12 + c) << 6) + (s & 63);
+}
+__host__ __device__ __forceinline__ size_t lidx(int s, int mu, int e)
+{
+    return ((((size_t)(s >> 6) * 4 + mu) * 9 + e) << 6) + (s & 63);
+}
 
 static inline size_t spinor_elems(const Geom &g, int nrhs) { return (size_t)nrhs * 12 * g.Vs; }
 static inline size_t gauge_elems(const Geom &g) { return (size_t)4 * 9 * g.Vs; }

@@ -43,7 +43,15 @@ struct DslashArgs {
     int nrhs;
     int SB;               // sites per work item == workgroup size
     int RG;               // right-hand sides per work item
+    int split;            // 1: one hop per loop iteration, 0: one direction (two hops)
     double *partials;     // [grid][nrhs][3] or nullptr
+};
+
+// A tuned launch of the stencil for one precision and RHS count.
+struct DslashTune {
+    int valid = 0;
+    int SB = 128, RG = 1, split = 0, grid = 0;
+    float ms = 0;
 };
 
 struct CoarseArgs {

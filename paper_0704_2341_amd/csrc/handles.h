@@ -56,9 +56,12 @@ struct grg_schur_s {
     double *partials = nullptr;
     size_t partials_elems = 0;
     double2 *alpha = nullptr, *beta = nullptr;
+    // per-RHS scalars: residual norms, thresholds, GCR |q_j|^2, |b|^2 and the
+    // outer |r|^2 (bn2[kMaxRhs..])
     double *rn2 = nullptr, *thr2 = nullptr, *qn2 = nullptr, *bn2 = nullptr;
     int *active = nullptr;
     double *h_buf = nullptr;  // pinned host staging (4 * kMaxRhs doubles)
     grg::ProfilePool prof;
     int n_dslash = 0;
+    grg::DslashTune tune[3][grg::kMaxRhs + 1];  // per precision and nrhs
 };

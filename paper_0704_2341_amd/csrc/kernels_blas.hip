@@ -69,17 +69,15 @@ __global__ void __launch_bounds__(256) mr_update_kernel(BlasShape sh, void *x_, 
     part.init(smem, sh.nrhs);
     S *x = (S *)x_, *r = (S *)r_;
     const S *q = (const S *)q_, *p = p_ ? (const S *)p_ : (const S *)r_;
-    const size_t Vs = sh.g.Vs;
     SITE_LOOP_BEGIN(sh)
     for (int k = 0; k < sh.nrhs; ++k) {
         const double2 a2 = alpha[k];
         const cpx<R> a = {(R)a2.x, (R)a2.y};
         double rr = 0;
         if (valid) {
-            const size_t base = (size_t)k * 12 * Vs + s;
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                const size_t i = base + c * Vs;
+                const size_t i = fidx(s, k, c, sh.nrhs);
                 cpx<R> xv = ldc(x, i), rv = ldc(r, i);
                 const cpx<R> pv = ldc(p, i), qv = ldc(q, i);
                 const cpx<R> ap = cmul(a, pv), aq = cmul(a, qv);
@@ -108,14 +106,13 @@ __global__ void __launch_bounds__(256) norm2_kernel(BlasShape sh, const void *v_
     Partial<1> part;
     part.init(smem, sh.nrhs);
     const S *v = (const S *)v_;
-    const size_t Vs = sh.g.Vs;
     SITE_LOOP_BEGIN(sh)
     for (int k = 0; k < sh.nrhs; ++k) {
         double t = 0;
         if (valid) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                const cpx<R> a = ldc(v, (size_t)(k * 12 + c) * Vs + s);
+                const cpx<R> a = ldc(v, fidx(s, k, c, sh.nrhs));
                 t += (double)a.re * a.re + (double)a.im * a.im;
             }
         }
@@ -133,14 +130,13 @@ __global__ void __launch_bounds__(256) sub_norm_kernel(BlasShape sh, const doubl
     __shared__ double smem[4 * kMaxRhs];
     Partial<1> part;
     part.init(smem, sh.nrhs);
-    const size_t Vs = sh.g.Vs;
     SITE_LOOP_BEGIN(sh)
     for (int k = 0; k < sh.nrhs; ++k) {
         double t = 0;
         if (valid) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                const size_t i = (size_t)(k * 12 + c) * Vs + s;
+                const size_t i = fidx(s, k, c, sh.nrhs);
                 const double2 bv = b[i], av = ax[i];
                 const double2 d = make_double2(bv.x - av.x, bv.y - av.y);
                 r[i] = d;
@@ -166,7 +162,6 @@ __global__ void __launch_bounds__(256) axpy_convert_kernel(BlasShape sh, const v
     typedef typename Store<PO>::R RO;
     const SI *x = (const SI *)x_;
     SO *y = (SO *)y_;
-    const size_t Vs = sh.g.Vs;
     SITE_LOOP_BEGIN(sh)
     if (valid) {
         for (int k = 0; k < sh.nrhs; ++k) {
@@ -177,7 +172,7 @@ __global__ void __launch_bounds__(256) axpy_convert_kernel(BlasShape sh, const v
             const RO fo = (RO)f;
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                const size_t i = (size_t)(k * 12 + c) * Vs + s;
+                const size_t i = fidx(s, k, c, sh.nrhs);
                 const cpx<RI> a = ldc(x, i);
                 cpx<RO> o = {fo * (RO)a.re, fo * (RO)a.im};
                 if (beta) {
@@ -194,13 +189,12 @@ __global__ void __launch_bounds__(256) axpy_convert_kernel(BlasShape sh, const v
 
 __global__ void __launch_bounds__(256) xmy_kernel(BlasShape sh, const double2 *x, double2 *y)
 {
-    const size_t Vs = sh.g.Vs;
     SITE_LOOP_BEGIN(sh)
     if (valid) {
         for (int k = 0; k < sh.nrhs; ++k) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                const size_t i = (size_t)(k * 12 + c) * Vs + s;
+                const size_t i = fidx(s, k, c, sh.nrhs);
                 const double2 a = x[i], b = y[i];
                 y[i] = make_double2(a.x - b.x, a.y - b.y);
             }
@@ -215,13 +209,12 @@ __global__ void __launch_bounds__(256) copy_kernel(BlasShape sh, const void *x_,
     typedef typename Store<P>::S S;
     const S *x = (const S *)x_;
     S *y = (S *)y_;
-    const size_t Vs = sh.g.Vs;
     SITE_LOOP_BEGIN(sh)
     if (valid) {
         for (int k = 0; k < sh.nrhs; ++k) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                const size_t i = (size_t)(k * 12 + c) * Vs + s;
+                const size_t i = fidx(s, k, c, sh.nrhs);
                 y[i] = x[i];
             }
         }
@@ -246,8 +239,7 @@ __global__ void __launch_bounds__(256) multidot_kernel(BlasShape sh, const void 
     typedef typename Store<P>::R R;
     extern __shared__ double dsm[];
     const S *Q = (const S *)Q_, *q = (const S *)q_;
-    const size_t Vs = sh.g.Vs;
-    const size_t vstride = (size_t)sh.nrhs * 12 * Vs;
+    const size_t vstride = (size_t)sh.nrhs * 12 * sh.g.Vs;
     const int nr = sh.nrhs * k;  // rows (rhs, j)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double (*red)[2] = (double (*)[2])dsm;  // [4 waves][nr][2]
@@ -258,14 +250,14 @@ __global__ void __launch_bounds__(256) multidot_kernel(BlasShape sh, const void 
         cpx<R> qv[12];
         if (valid) {
 #pragma unroll
-            for (int c = 0; c < 12; ++c) qv[c] = ldc(q, (size_t)(r * 12 + c) * Vs + s);
+            for (int c = 0; c < 12; ++c) qv[c] = ldc(q, fidx(s, r, c, sh.nrhs));
         }
         for (int j = 0; j < k; ++j) {
             double re = 0, im = 0;
             if (valid) {
 #pragma unroll
                 for (int c = 0; c < 12; ++c) {
-                    const cpx<R> a = ldc(Q, j * vstride + (size_t)(r * 12 + c) * Vs + s);
+                    const cpx<R> a = ldc(Q, j * vstride + fidx(s, r, c, sh.nrhs));
                     re += (double)a.re * qv[c].re + (double)a.im * qv[c].im;
                     im += (double)a.re * qv[c].im - (double)a.im * qv[c].re;
                 }
@@ -302,15 +294,14 @@ __global__ void __launch_bounds__(256) orthogonalise_kernel(BlasShape sh, const 
     part.init(smem, sh.nrhs);
     const S *Q = (const S *)Q_, *Pm = (const S *)P_, *rr = (const S *)r_;
     S *q = (S *)q_, *p = (S *)p_;
-    const size_t Vs = sh.g.Vs;
-    const size_t vstride = (size_t)sh.nrhs * 12 * Vs;
+    const size_t vstride = (size_t)sh.nrhs * 12 * sh.g.Vs;
     SITE_LOOP_BEGIN(sh)
     for (int r = 0; r < sh.nrhs; ++r) {
         double d[3] = {0, 0, 0};
         if (valid) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                const size_t i = (size_t)(r * 12 + c) * Vs + s;
+                const size_t i = fidx(s, r, c, sh.nrhs);
                 cpx<R> qv = ldc(q, i), pv = ldc(p, i);
                 for (int j = 0; j < k; ++j) {
                     const double2 b2 = beta[r * kMaxRhs + j];

@@ -26,17 +26,11 @@
 namespace grg {
 
 // ------------------------------------------------------------------ stencil
-template <int MU, bool FWD, class S, class R>
-__device__ __forceinline__ void hop(cpx<R> (&acc)[12], const S *__restrict__ in,
-                                    const S *__restrict__ U, int Vs, int n, int ls)
+// One hop's arithmetic on loaded data: p = psi at the neighbour, u = link.
+template <int MU, bool FWD, class R>
+__device__ __forceinline__ void hop_math(cpx<R> (&acc)[12], const cpx<R> (&p)[12],
+                                         const cpx<R> (&u)[9])
 {
-    cpx<R> p[12];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) p[c] = ldc(in, (size_t)c * Vs + n);
-    cpx<R> u[9];
-#pragma unroll
-    for (int e = 0; e < 9; ++e) u[e] = ldc(U, (size_t)(MU * 9 + e) * Vs + ls);
-
     // h = psi_up -/+ B_mu psi_lo   (- for the forward hop, + for the backward)
     const R sg = FWD ? R(-1) : R(1);
     cpx<R> h0[3], h1[3];
@@ -106,52 +100,102 @@ __device__ __forceinline__ void hop(cpx<R> (&acc)[12], const S *__restrict__ in,
     }
 }
 
-struct Nbr {
-    int p[4], m[4];
+// Site coordinates and the four lattice strides.
+struct SiteGeo {
+    int c[4];
 };
 
-__device__ __forceinline__ Nbr neighbours(int s, const Geom &g)
+__device__ __forceinline__ SiteGeo site_geo(int s, const Geom &g)
 {
-    const int L0 = g.L[0], L1 = g.L[1], L2 = g.L[2], L3 = g.L[3];
-    const int x = s % L0, t1 = s / L0;
-    const int y = t1 % L1, t2 = t1 / L1;
-    const int z = t2 % L2, t = t2 / L2;
-    const int s1 = L0, s2 = L0 * L1, s3 = L0 * L1 * L2;
-    Nbr nb;
-    nb.p[0] = x == L0 - 1 ? s - (L0 - 1) : s + 1;
-    nb.m[0] = x == 0 ? s + (L0 - 1) : s - 1;
-    nb.p[1] = y == L1 - 1 ? s - (L1 - 1) * s1 : s + s1;
-    nb.m[1] = y == 0 ? s + (L1 - 1) * s1 : s - s1;
-    nb.p[2] = z == L2 - 1 ? s - (L2 - 1) * s2 : s + s2;
-    nb.m[2] = z == 0 ? s + (L2 - 1) * s2 : s - s2;
-    nb.p[3] = t == L3 - 1 ? s - (L3 - 1) * s3 : s + s3;
-    nb.m[3] = t == 0 ? s + (L3 - 1) * s3 : s - s3;
-    return nb;
+    SiteGeo q;
+    const int t1 = s / g.L[0];
+    q.c[0] = s - t1 * g.L[0];
+    const int t2 = t1 / g.L[1];
+    q.c[1] = t1 - t2 * g.L[1];
+    const int t3 = t2 / g.L[2];
+    q.c[2] = t2 - t3 * g.L[2];
+    q.c[3] = t3;
+    return q;
 }
 
-template <class S, class R>
+// Neighbours of s along mu (mu is wave-uniform; selects, not array indexing,
+// so that nothing lands in scratch).
+__device__ __forceinline__ void nbr(int s, int mu, const SiteGeo &q, const Geom &g, int &sp, int &sm)
+{
+    const int L = mu == 0 ? g.L[0] : mu == 1 ? g.L[1] : mu == 2 ? g.L[2] : g.L[3];
+    const int x = mu == 0 ? q.c[0] : mu == 1 ? q.c[1] : mu == 2 ? q.c[2] : q.c[3];
+    const int st = mu == 0 ? 1 : mu == 1 ? g.L[0] : mu == 2 ? g.L[0] * g.L[1]
+                                                             : g.L[0] * g.L[1] * g.L[2];
+    sp = x == L - 1 ? s - (L - 1) * st : s + st;
+    sm = x == 0 ? s + (L - 1) * st : s - st;
+}
+
+// acc = (D in)(s) for RHS r of a field with nrhs RHS.  The hop loop is not
+// unrolled: each iteration loads one direction's two neighbours and links
+// (24 + 18 complex; SPLIT: one hop, 12 + 9 complex) and consumes them, which
+// bounds the live registers and keeps several wavefronts per SIMD in flight.
+template <class S, class R, bool SPLIT>
 __device__ __forceinline__ void dslash_site(cpx<R> (&acc)[12], const S *__restrict__ in,
-                                            const S *__restrict__ U, int Vs, int s,
-                                            const Nbr &nb, R diag)
+                                            const S *__restrict__ U, int s, const SiteGeo &q,
+                                            const Geom &g, int r, int nrhs, R diag)
 {
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-        const cpx<R> v = ldc(in, (size_t)c * Vs + s);
+        const cpx<R> v = ldc(in, fidx(s, r, c, nrhs));
         acc[c] = {diag * v.re, diag * v.im};
     }
-    hop<0, true>(acc, in, U, Vs, nb.p[0], s);
-    hop<0, false>(acc, in, U, Vs, nb.m[0], nb.m[0]);
-    hop<1, true>(acc, in, U, Vs, nb.p[1], s);
-    hop<1, false>(acc, in, U, Vs, nb.m[1], nb.m[1]);
-    hop<2, true>(acc, in, U, Vs, nb.p[2], s);
-    hop<2, false>(acc, in, U, Vs, nb.m[2], nb.m[2]);
-    hop<3, true>(acc, in, U, Vs, nb.p[3], s);
-    hop<3, false>(acc, in, U, Vs, nb.m[3], nb.m[3]);
+    if (SPLIT) {
+#pragma unroll 1
+        for (int h = 0; h < 8; ++h) {
+            const int mu = h >> 1;
+            int sp, sm;
+            nbr(s, mu, q, g, sp, sm);
+            const int n = (h & 1) ? sm : sp;
+            cpx<R> p[12], u[9];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) p[c] = ldc(in, fidx(n, r, c, nrhs));
+#pragma unroll
+            for (int e = 0; e < 9; ++e) u[e] = ldc(U, lidx((h & 1) ? sm : s, mu, e));
+            switch (h) {
+            case 0: hop_math<0, true>(acc, p, u); break;
+            case 1: hop_math<0, false>(acc, p, u); break;
+            case 2: hop_math<1, true>(acc, p, u); break;
+            case 3: hop_math<1, false>(acc, p, u); break;
+            case 4: hop_math<2, true>(acc, p, u); break;
+            case 5: hop_math<2, false>(acc, p, u); break;
+            case 6: hop_math<3, true>(acc, p, u); break;
+            default: hop_math<3, false>(acc, p, u); break;
+            }
+        }
+        return;
+    }
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+        int sp, sm;
+        nbr(s, mu, q, g, sp, sm);
+        cpx<R> pf[12], pb[12], uf[9], ub[9];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            pf[c] = ldc(in, fidx(sp, r, c, nrhs));
+            pb[c] = ldc(in, fidx(sm, r, c, nrhs));
+        }
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            uf[e] = ldc(U, lidx(s, mu, e));
+            ub[e] = ldc(U, lidx(sm, mu, e));
+        }
+        switch (mu) {
+        case 0: hop_math<0, true>(acc, pf, uf); hop_math<0, false>(acc, pb, ub); break;
+        case 1: hop_math<1, true>(acc, pf, uf); hop_math<1, false>(acc, pb, ub); break;
+        case 2: hop_math<2, true>(acc, pf, uf); hop_math<2, false>(acc, pb, ub); break;
+        default: hop_math<3, true>(acc, pf, uf); hop_math<3, false>(acc, pb, ub); break;
+        }
+    }
 }
 
 // out = mask_sel D in, for nrhs fields.  With a.partials set, also the
 // per-workgroup partial sums of conj(out).in (re, im) and |out|^2 per RHS.
-template <int P>
+template <int P, bool SPLIT>
 __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
 {
     typedef typename Store<P>::S S;
@@ -160,7 +204,6 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
     const S *__restrict__ in = (const S *)a.in;
     S *__restrict__ out = (S *)a.out;
     const S *__restrict__ U = (const S *)a.U;
-    const int Vs = a.g.Vs;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const bool dots = a.partials != nullptr;
     if (dots) {
@@ -175,29 +218,27 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
         const int s = sb * a.SB + (int)threadIdx.x;
         const bool valid = s < a.g.V;
         const bool on = valid && (a.mask == nullptr || a.mask[s] == a.sel);
-        Nbr nb;
-        if (on) nb = neighbours(s, a.g);
+        SiteGeo q;
+        if (on) q = site_geo(s, a.g);
         const int r0 = grp * a.RG, r1 = min(r0 + a.RG, a.nrhs);
         for (int r = r0; r < r1; ++r) {
-            const S *inr = in + (size_t)r * 12 * Vs;
-            S *outr = out + (size_t)r * 12 * Vs;
             cpx<R> acc[12];
             if (on) {
-                dslash_site<S, R>(acc, inr, U, Vs, s, nb, (R)a.diag);
+                dslash_site<S, R, SPLIT>(acc, in, U, s, q, a.g, r, a.nrhs, (R)a.diag);
             } else {
 #pragma unroll
                 for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
             }
             if (valid) {
 #pragma unroll
-                for (int c = 0; c < 12; ++c) stc(outr, (size_t)c * Vs + s, acc[c]);
+                for (int c = 0; c < 12; ++c) stc(out, fidx(s, r, c, a.nrhs), acc[c]);
             }
             if (dots) {
                 double dre = 0, dim = 0, dqq = 0;
                 if (on) {
 #pragma unroll
                     for (int c = 0; c < 12; ++c) {
-                        const cpx<R> v = ldc(inr, (size_t)c * Vs + s);
+                        const cpx<R> v = ldc(in, fidx(s, r, c, a.nrhs));
                         dre += (double)acc[c].re * v.re + (double)acc[c].im * v.im;
                         dim += (double)acc[c].re * v.im - (double)acc[c].im * v.re;
                         dqq += (double)acc[c].re * acc[c].re + (double)acc[c].im * acc[c].im;
@@ -231,12 +272,12 @@ __global__ void __launch_bounds__(256) dslash_coarse_kernel(CoarseArgs a)
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.nb) return;
     const int s = a.q[k];
-    const Nbr nb = neighbours(s, a.g);
+    const SiteGeo q = site_geo(s, a.g);
     const double2 *in = (const double2 *)a.in;
     const double2 *U = (const double2 *)a.U;
     for (int r = 0; r < a.nrhs; ++r) {
         cpx<double> acc[12];
-        dslash_site<double2, double>(acc, in + (size_t)r * 12 * a.g.Vs, U, a.g.Vs, s, nb, a.diag);
+        dslash_site<double2, double, true>(acc, in, U, s, q, a.g, r, a.nrhs, a.diag);
         double2 *o = (double2 *)a.out + ((size_t)r * a.nb + k) * 12;
 #pragma unroll
         for (int c = 0; c < 12; ++c) o[c] = make_double2(acc[c].re, acc[c].im);
@@ -244,7 +285,7 @@ __global__ void __launch_bounds__(256) dslash_coarse_kernel(CoarseArgs a)
 }
 
 // ------------------------------------------------------------------ layouts
-// canonical links [V][4][3][3] complex128 -> internal [mu][9][Vs] in three
+// canonical links [V][4][3][3] complex128 -> internal tiles in three
 // precisions, boundary sign folded into the last slice of each direction.
 __global__ void pack_gauge_kernel(const double2 *__restrict__ src, Geom g, int4 bc,
                                   double2 *u64, float2 *u32, bf16x2 *u16)
@@ -252,25 +293,22 @@ __global__ void pack_gauge_kernel(const double2 *__restrict__ src, Geom g, int4 
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= g.V * 4) return;
     const int s = idx >> 2, mu = idx & 3;
-    int c[4];
-    int r = s;
-    for (int nu = 0; nu < 4; ++nu) {
-        c[nu] = r % g.L[nu];
-        r /= g.L[nu];
-    }
+    const SiteGeo q = site_geo(s, g);
     const int b = mu == 0 ? bc.x : mu == 1 ? bc.y : mu == 2 ? bc.z : bc.w;
-    const double sign = (c[mu] == g.L[mu] - 1) ? (double)b : 1.0;
+    const int x = mu == 0 ? q.c[0] : mu == 1 ? q.c[1] : mu == 2 ? q.c[2] : q.c[3];
+    const int L = mu == 0 ? g.L[0] : mu == 1 ? g.L[1] : mu == 2 ? g.L[2] : g.L[3];
+    const double sign = (x == L - 1) ? (double)b : 1.0;
     for (int e = 0; e < 9; ++e) {
         const double2 v = src[(size_t)idx * 9 + e];
         const cpx<double> d = {sign * v.x, sign * v.y};
-        const size_t o = (size_t)(mu * 9 + e) * g.Vs + s;
+        const size_t o = lidx(s, mu, e);
         stc(u64, o, d);
         stc(u32, o, cpx<float>{(float)d.re, (float)d.im});
         stc(u16, o, cpx<float>{(float)d.re, (float)d.im});
     }
 }
 
-// canonical [nrhs][V][12] complex128  <->  internal [nrhs][12][Vs]
+// canonical [nrhs][V][12] complex128  <->  internal tiles
 template <int P>
 __global__ void pack_spinor_kernel(const double2 *__restrict__ src, void *dst, Geom g, int nrhs)
 {
@@ -280,11 +318,11 @@ __global__ void pack_spinor_kernel(const double2 *__restrict__ src, void *dst, G
     const int r = blockIdx.y;
     if (s >= g.V || r >= nrhs) return;
     const double2 *p = src + ((size_t)r * g.V + s) * 12;
-    S *o = (S *)dst + (size_t)r * 12 * g.Vs;
+    S *o = (S *)dst;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
         const double2 v = p[c];
-        stc(o, (size_t)c * g.Vs + s, cpx<R>{(R)v.x, (R)v.y});
+        stc(o, fidx(s, r, c, nrhs), cpx<R>{(R)v.x, (R)v.y});
     }
 }
 
@@ -296,11 +334,11 @@ __global__ void unpack_spinor_kernel(const void *src, double2 *__restrict__ dst,
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
     if (s >= g.V || r >= nrhs) return;
-    const S *p = (const S *)src + (size_t)r * 12 * g.Vs;
+    const S *p = (const S *)src;
     double2 *o = dst + ((size_t)r * g.V + s) * 12;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-        const cpx<R> v = ldc(p, (size_t)c * g.Vs + s);
+        const cpx<R> v = ldc(p, fidx(s, r, c, nrhs));
         o[c] = make_double2((double)v.re, (double)v.im);
     }
 }
@@ -315,9 +353,8 @@ __global__ void pack_masked_kernel(const double2 *__restrict__ src, double2 *__r
     if (s >= g.V || r >= nrhs) return;
     const bool k = mask[s] == keep;
     const double2 *p = src + ((size_t)r * g.V + s) * 12;
-    double2 *o = dst + (size_t)r * 12 * g.Vs;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) o[(size_t)c * g.Vs + s] = k ? p[c] : make_double2(0.0, 0.0);
+    for (int c = 0; c < 12; ++c) dst[fidx(s, r, c, nrhs)] = k ? p[c] : make_double2(0.0, 0.0);
 }
 
 // coarse canonical [nrhs][nb][12] -> internal FP64 lattice field, zero on
@@ -329,10 +366,9 @@ __global__ void scatter_coarse_kernel(const double2 *__restrict__ xb, double2 *_
     const int r = blockIdx.y;
     if (s >= g.V || r >= nrhs) return;
     const int k = bidx[s];
-    double2 *o = dst + (size_t)r * 12 * g.Vs;
     const double2 *p = xb + ((size_t)r * nb + (k < 0 ? 0 : k)) * 12;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) o[(size_t)c * g.Vs + s] = k >= 0 ? p[c] : make_double2(0.0, 0.0);
+    for (int c = 0; c < 12; ++c) dst[fidx(s, r, c, nrhs)] = k >= 0 ? p[c] : make_double2(0.0, 0.0);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -344,12 +380,16 @@ hipError_t launch_dslash(int prec, const DslashArgs &a, int grid, hipStream_t st
     if (a.nrhs < 1 || a.nrhs > kMaxRhs || a.RG < 1) return hipErrorInvalidValue;
     if (grid < 8 || grid % 8) return hipErrorInvalidValue;
     dim3 blk(a.SB), grd(grid);
+#define DSL(PP)                                                                                 \
+    if (a.split) hipLaunchKernelGGL((dslash_kernel<PP, true>), grd, blk, 0, st, a);             \
+    else hipLaunchKernelGGL((dslash_kernel<PP, false>), grd, blk, 0, st, a);
     switch (prec) {
-    case GRG_FP64: hipLaunchKernelGGL(dslash_kernel<GRG_FP64>, grd, blk, 0, st, a); break;
-    case GRG_FP32: hipLaunchKernelGGL(dslash_kernel<GRG_FP32>, grd, blk, 0, st, a); break;
-    case GRG_BF16: hipLaunchKernelGGL(dslash_kernel<GRG_BF16>, grd, blk, 0, st, a); break;
+    case GRG_FP64: DSL(GRG_FP64) break;
+    case GRG_FP32: DSL(GRG_FP32) break;
+    case GRG_BF16: DSL(GRG_BF16) break;
     default: return hipErrorInvalidValue;
     }
+#undef DSL
     return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@
 
 namespace grg {
 
-static inline int round8(long v) { return (int)std::max<long>(8, ((v + 7) / 8) * 8); }
+int round8(long v) { return (int)std::max<long>(8, ((v + 7) / 8) * 8); }
 
 int dslash_grid(const Geom &g, int nrhs, int SB, int RG)
 {
@@ -47,28 +47,49 @@ BlasShape blas_shape(const Geom &g, int nrhs)
 
 static int dslash_sb(const Geom &g) { return g.V >= (1 << 16) ? 128 : 64; }
 
+// Default stencil launch (before or without tuning).
+DslashTune default_tune(const Geom &g, int prec, int nrhs)
+{
+    DslashTune t;
+    t.SB = dslash_sb(g);
+    t.RG = nrhs;
+    t.split = prec == GRG_FP64 ? 1 : 0;
+    t.grid = dslash_grid(g, nrhs, t.SB, t.RG);
+    return t;
+}
+
+static grg_status launch_tuned(grg_lattice L, int prec, const DslashTune &t, const void *in,
+                               void *out, const uint8_t *mask, int sel, double m0, int nrhs,
+                               double *partials)
+{
+    DslashArgs a;
+    a.in = in;
+    a.out = out;
+    a.U = L->U[prec];
+    a.mask = mask;
+    a.sel = sel;
+    a.diag = 4.0 + m0;
+    a.g = L->g;
+    a.nrhs = nrhs;
+    a.SB = t.SB;
+    a.RG = t.RG;
+    a.split = t.split;
+    a.partials = partials;
+    GRG_TRY_HIP(launch_dslash(prec, a, t.grid, L->stream));
+    return GRG_OK;
+}
+
 // One stencil launch, bracketed by profiling events when enabled.
 grg_status run_dslash(grg_schur S, int prec, const void *in, void *out, int sel, int nrhs,
                       double *partials)
 {
     grg_lattice L = S->lat;
-    DslashArgs a;
-    a.in = in;
-    a.out = out;
-    a.U = L->U[prec];
-    a.mask = sel < 0 ? nullptr : S->d_mask;
-    a.sel = sel < 0 ? 0 : sel;
-    a.diag = 4.0 + S->m0;
-    a.g = L->g;
-    a.nrhs = nrhs;
-    a.SB = dslash_sb(L->g);
-    a.RG = nrhs;
-    a.partials = partials;
-    const int grid = dslash_grid(L->g, nrhs, a.SB, a.RG);
+    const DslashTune t = S->tune[prec][nrhs].valid ? S->tune[prec][nrhs] : default_tune(L->g, prec, nrhs);
     ProfilePool &P = S->prof;
     const bool ev = P.on && P.used < (int)P.start.size();
     if (ev) GRG_TRY_HIP(hipEventRecord(P.start[P.used], L->stream));
-    GRG_TRY_HIP(launch_dslash(prec, a, grid, L->stream));
+    GRG_TRY(launch_tuned(L, prec, t, in, out, sel < 0 ? nullptr : S->d_mask, sel < 0 ? 0 : sel,
+                         S->m0, nrhs, partials));
     if (ev) {
         GRG_TRY_HIP(hipEventRecord(P.stop[P.used], L->stream));
         P.prec[P.used] = prec;
@@ -78,9 +99,76 @@ grg_status run_dslash(grg_schur S, int prec, const void *in, void *out, int sel,
     return GRG_OK;
 }
 
-int partial_rows(const Geom &g, int nrhs)
+grg_status ensure_inner(grg_schur S, int prec);
+
+// Largest grid any stencil or BLAS launch may use (sizes the partial sums).
+constexpr int kMaxGrid = 4096;
+int partial_rows(const Geom &, int) { return kMaxGrid; }
+
+// Autotuner: time every candidate launch of the D_rr stencil (with its fused
+// dot products, as the solver runs it) on the handle's own workspaces and keep
+// the fastest.  Every candidate computes each site in the same operation
+// order, so the choice changes speed only, never the stencil's output.
+grg_status tune_dslash(grg_schur S, int prec, int nrhs, int reps)
 {
-    return std::max(dslash_grid(g, nrhs, dslash_sb(g), nrhs), blas_shape(g, nrhs).grid);
+    grg_lattice L = S->lat;
+    hipStream_t st = L->stream;
+    const Geom &g = L->g;
+    GRG_TRY(ensure_inner(S, prec));
+    const void *in = prec == GRG_FP64 ? S->b64 : S->in_b[prec];
+    void *out = prec == GRG_FP64 ? S->t64 : S->in_q[prec];
+    std::vector<DslashTune> cands;
+    const int sbs[3] = {64, 128, 256};
+    for (int sb : sbs) {
+        if (sb > 64 && g.V < 4 * sb) continue;
+        for (int rg = 1; rg <= nrhs; ++rg) {
+            if (nrhs % rg && rg != nrhs) continue;
+            if (rg > 4 && rg != nrhs) continue;
+            for (int split = 0; split < 2; ++split) {
+                const long items = (long)((g.V + sb - 1) / sb) * ((nrhs + rg - 1) / rg);
+                const int caps[3] = {1024, 2048, kMaxGrid};
+                int last = -1;
+                for (int cap : caps) {
+                    DslashTune t;
+                    t.SB = sb;
+                    t.RG = rg;
+                    t.split = split;
+                    t.grid = round8(std::min<long>(items, cap));
+                    if (t.grid == last) continue;
+                    last = t.grid;
+                    t.valid = 1;
+                    cands.push_back(t);
+                }
+            }
+        }
+    }
+    hipEvent_t e0, e1;
+    GRG_TRY_HIP(hipEventCreate(&e0));
+    GRG_TRY_HIP(hipEventCreate(&e1));
+    DslashTune best;
+    best.ms = 1e30f;
+    grg_status status = GRG_OK;
+    for (DslashTune &t : cands) {
+        status = launch_tuned(L, prec, t, in, out, S->d_mask, 0, S->m0, nrhs, S->partials);
+        if (status != GRG_OK) break;
+        if (hipEventRecord(e0, st) != hipSuccess) { status = GRG_EHIP; break; }
+        for (int k = 0; k < reps && status == GRG_OK; ++k)
+            status = launch_tuned(L, prec, t, in, out, S->d_mask, 0, S->m0, nrhs, S->partials);
+        if (status != GRG_OK) break;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            status = GRG_EHIP;
+            break;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        t.ms = ms / reps;
+        if (t.ms < best.ms) best = t;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status != GRG_OK) return status;
+    S->tune[prec][nrhs] = best;
+    return GRG_OK;
 }
 
 static grg_status read_norms(grg_schur S, int nrhs, double *host)
@@ -108,8 +196,8 @@ grg_status ensure_inner(grg_schur S, int prec)
         GRG_TRY_HIP(launch_fill_zero(*b, bytes, S->lat->stream));
     }
     if (m > 1 && S->in_m[prec] < m) {
-        if (S->in_P[prec]) hipFree(S->in_P[prec]);
-        if (S->in_Q[prec]) hipFree(S->in_Q[prec]);
+        if (S->in_P[prec]) (void)hipFree(S->in_P[prec]);
+        if (S->in_Q[prec]) (void)hipFree(S->in_Q[prec]);
         S->in_P[prec] = S->in_Q[prec] = nullptr;
         if (hipMalloc(&S->in_P[prec], bytes * m) != hipSuccess ||
             hipMalloc(&S->in_Q[prec], bytes * m) != hipSuccess) {
@@ -138,7 +226,8 @@ static grg_status inner_gcr(grg_schur S, int prec, int nrhs, const double *thr, 
     const size_t vstride = spinor_elems(g, nrhs) * prec_bytes(prec);
     const int m = std::max(1, S->prm.restart);
     const int check = std::max(1, S->prm.check_every);
-    const int dgrid = dslash_grid(g, nrhs, dslash_sb(g), nrhs);
+    const int dgrid = S->tune[prec][nrhs].valid ? S->tune[prec][nrhs].grid
+                                                : default_tune(g, prec, nrhs).grid;
     void *b = S->in_b[prec], *x = S->in_x[prec], *r = S->in_r[prec], *q = S->in_q[prec];
     char *Pm = (char *)S->in_P[prec], *Qm = (char *)S->in_Q[prec];
 
@@ -257,19 +346,20 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
         memcpy(S->h_buf + 2 * kMaxRhs, thr, sizeof(double) * nrhs);
         GRG_TRY_HIP(hipMemcpyAsync(S->thr2, S->h_buf + 2 * kMaxRhs, sizeof(double) * nrhs,
                                    hipMemcpyHostToDevice, st));
-        // r_in = r / |r|  (rn2 on the device holds |r|^2)
-        GRG_TRY_HIP(launch_axpy_convert(GRG_FP64, prec, sh, S->r64, S->in_b[prec], S->rn2, 1, 0,
-                                        nullptr, st));
+        // the outer |r|^2 on the device (the inner solve reuses rn2 for its own norms)
+        memcpy(S->h_buf + 3 * kMaxRhs, rn2, sizeof(double) * nrhs);
+        GRG_TRY_HIP(hipMemcpyAsync(S->bn2 + kMaxRhs, S->h_buf + 3 * kMaxRhs,
+                                   sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+        // r_in = r / |r|
+        GRG_TRY_HIP(launch_axpy_convert(GRG_FP64, prec, sh, S->r64, S->in_b[prec],
+                                        S->bn2 + kMaxRhs, 1, 0, nullptr, st));
         int it = 0;
         GRG_TRY(inner_gcr(S, prec, nrhs, thr, p.max_iter - total, &it));
         total += it;
         ++outer;
-        // x += |r| e   (rn2 still holds the outer |r|^2: restore it first)
-        memcpy(S->h_buf + 3 * kMaxRhs, rn2, sizeof(double) * nrhs);
-        GRG_TRY_HIP(hipMemcpyAsync(S->rn2, S->h_buf + 3 * kMaxRhs, sizeof(double) * nrhs,
-                                   hipMemcpyHostToDevice, st));
-        GRG_TRY_HIP(launch_axpy_convert(prec, GRG_FP64, sh, S->in_x[prec], S->x64, S->rn2, 2, 1,
-                                        nullptr, st));
+        // x += |r| e
+        GRG_TRY_HIP(launch_axpy_convert(prec, GRG_FP64, sh, S->in_x[prec], S->x64,
+                                        S->bn2 + kMaxRhs, 2, 1, nullptr, st));
         // r = b - D_rr x in FP64
         GRG_TRY(run_dslash(S, GRG_FP64, S->x64, S->t64, 0, nrhs, nullptr));
         GRG_TRY_HIP(launch_sub_norm(sh, S->b64, S->t64, S->r64, S->partials, st));

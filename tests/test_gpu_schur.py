@@ -176,3 +176,39 @@ def test_16_4_mixed_matches_fp64(c2, inner):
     assert rel_err(ymx, y64) < 1e-10
     s64.close()
     smx.close()
+
+
+def test_iteration_count_matches_oracle():
+    """Minimal residual on D_rr takes as many iterations on the GPU as the
+    oracle's GCR (37 on this field), also for a handle created after another
+    was destroyed (the defect correction must never see stale norms)."""
+    lat = Lattice((8, 8, 8, 8), 0.5, 3)
+    xb = point_sources(lat.V // 16, 12)
+    _, it_or, _ = matfree.schur_apply(lat.links, lat.dims, -0.3, *lat.grg.grg_permutation_block(lat.dims, 1),
+                                      xb[:1], restart=1, tol=1e-10)
+    for _ in range(2):
+        s = lat.schur(-0.3, "I", False, tol=1e-10, restart=1)
+        _, st = s.apply(xb)
+        assert st["outer"] == 1 and st["iters"] <= it_or[0] + 2, (st, it_or)
+        s.close()
+    for inner, tol_in in (("fp32", 1e-5), ("bf16", 1e-2)):
+        s = lat.schur(-0.3, "I", False, tol=1e-10, inner=inner, inner_tol=tol_in)
+        _, st = s.apply(xb)
+        assert st["converged"] and st["iters"] <= 2 * it_or[0], (inner, st)
+        s.close()
+    lat.close()
+
+
+@pytest.mark.parametrize("inner", ["fp64", "bf16"])
+def test_tuned_launch_same_result(inner):
+    lat = Lattice((8, 8, 8, 16), 0.5, 6)
+    s = lat.schur(-0.1, "II", False, tol=1e-12, inner=inner, inner_tol=1e-2)
+    xb = gaussian_vectors(12 * s.nb, 4, 6)
+    y0, _ = s.apply(xb)
+    lat.grg.grg_schur_tune(s.h, 4)
+    info = lat.grg.grg_schur_tune_info(s.h, inner, 4)
+    assert info["ms"] > 0 and info["SB"] in (64, 128, 256) and info["grid"] % 8 == 0
+    y1, st = s.apply(xb)
+    assert st["converged"] and rel_err(y1, y0) < 1e-11
+    s.close()
+    lat.close()
