@@ -158,9 +158,29 @@ grg_status grg_schur_assemble(grg_schur s, double *S, size_t cap_bytes);
  * not results.  Takes a few hundred stencil launches. */
 grg_status grg_schur_tune(grg_schur s, int nrhs);
 /* The launch used for (precision, nrhs): info = {sites per workgroup, RHS per
- * thread, one-hop-per-iteration flag, workgroups}; *ms = its tuned time per
+ * thread (site-parallel kernel) or per workgroup (t-marching kernel),
+ * one-hop-per-iteration flag, workgroups, items per XCD chunk (0 = one
+ * contiguous eighth of the lattice per XCD), time-chunk length of the
+ * t-marching kernel (0 = site-parallel kernel)}; *ms = its tuned time per
  * launch, or -1 if untuned (defaults in use). */
-grg_status grg_schur_tune_info(grg_schur s, int precision, int nrhs, int32_t info[4], float *ms);
+grg_status grg_schur_tune_info(grg_schur s, int precision, int nrhs, int32_t info[6], float *ms);
+
+/* Pin the stencil launch for (precision, nrhs), e.g. from a saved tuning
+ * result: info as returned by grg_schur_tune_info.  GRG_EINVAL if the shape
+ * is not valid for this lattice (a t-marching workgroup holds 64 * RHS
+ * threads, at most 512 in FP64 and 768 otherwise).  Solver launches with
+ * fused dot products fall back to the default shape when a t-marching shape
+ * does not hold every RHS. */
+grg_status grg_schur_set_launch(grg_schur s, int precision, int nrhs, const int32_t info[6]);
+
+/* The sub-blocks of the partition (section 1, step 1): out = D_{rows,cols} in
+ * for nrhs canonical lattice fields (device), with rows / cols = 1 for the
+ * coarse sites, 0 for the rest, -1 for every site; in is read only on the
+ * cols sites and out is zero off the rows sites.  Computed in the given
+ * precision with the handle's stencil launch.  D_rr is the operator the solve
+ * inverts; D_rb, D_br and D_bb enter S_bb. */
+grg_status grg_block_apply(grg_schur s, int precision, int rows, int cols, const double *in,
+                           double *out, int nrhs);
 
 /* Kernel timing: with profiling on, every dslash launch is bracketed by HIP
  * events on the lattice stream; grg_profile_read returns the count and the

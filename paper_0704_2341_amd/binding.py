@@ -39,7 +39,7 @@ EXPORTS = (
     "grg_lattice_destroy", "grg_lattice_volume", "grg_gauge_set", "grg_permutation_block",
     "grg_dirac_apply", "grg_schur_create", "grg_schur_destroy", "grg_schur_set_params",
     "grg_drr_solve", "grg_schur_apply", "grg_schur_assemble", "grg_schur_tune",
-    "grg_schur_tune_info", "grg_profile_enable",
+    "grg_schur_tune_info", "grg_schur_set_launch", "grg_block_apply", "grg_profile_enable",
     "grg_profile_read", "grg_profile_reset",
 )
 
@@ -106,6 +106,8 @@ def load():
         "grg_schur_assemble": (C.c_int, [vp, vp, C.c_size_t]),
         "grg_schur_tune": (C.c_int, [vp, C.c_int]),
         "grg_schur_tune_info": (C.c_int, [vp, C.c_int, C.c_int, i32p, C.POINTER(C.c_float)]),
+        "grg_schur_set_launch": (C.c_int, [vp, C.c_int, C.c_int, i32p]),
+        "grg_block_apply": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, vp, C.c_int]),
         "grg_profile_enable": (C.c_int, [vp, C.c_int]),
         "grg_profile_read": (C.c_int, [vp, C.c_int, i64p, dp]),
         "grg_profile_reset": (C.c_int, [vp]),
@@ -254,11 +256,26 @@ def grg_schur_tune(s, nrhs):
 
 
 def grg_schur_tune_info(s, precision, nrhs):
-    """{'SB', 'RG', 'split', 'grid', 'ms'} of the stencil launch in use."""
-    info = (C.c_int32 * 4)()
+    """{'SB', 'RG', 'split', 'grid', 'chunk', 'ms'} of the stencil launch in use."""
+    info = (C.c_int32 * 6)()
     ms = C.c_float()
     _check(load().grg_schur_tune_info(s, _prec(precision), int(nrhs), info, C.byref(ms)))
-    return {"SB": info[0], "RG": info[1], "split": info[2], "grid": info[3], "ms": ms.value}
+    return {"SB": info[0], "RG": info[1], "split": info[2], "grid": info[3], "chunk": info[4],
+            "march": info[5], "ms": ms.value}
+
+
+def grg_schur_set_launch(s, precision, nrhs, info):
+    """info: dict as returned by grg_schur_tune_info (or a 6-sequence)."""
+    if isinstance(info, dict):
+        info = [info.get(k, 0) for k in ("SB", "RG", "split", "grid", "chunk", "march")]
+    arr, ptr = _i32(info)
+    _check(load().grg_schur_set_launch(s, _prec(precision), int(nrhs), ptr))
+
+
+def grg_block_apply(s, precision, rows, cols, x, out, nrhs):
+    """out = D_{rows, cols} x; rows / cols: 1 coarse, 0 rest, -1 all."""
+    _check(load().grg_block_apply(s, _prec(precision), int(rows), int(cols), _ptr(x), _ptr(out),
+                                  int(nrhs)))
 
 
 def grg_profile_enable(s, on=True):

@@ -33,6 +33,9 @@ grg_status run_dslash(grg_schur S, int prec, const void *in, void *out, int sel,
 int partial_rows(const Geom &g, int nrhs);
 int dslash_grid(const Geom &g, int nrhs, int SB, int RG);
 DslashTune default_tune(const Geom &g, int prec, int nrhs);
+bool launch_ok(const Geom &g, int prec, int nrhs, const DslashTune &t, bool dots);
+grg_status block_apply_internal(grg_schur S, int prec, int rows, int cols, const double *in,
+                                double *out, int nrhs);
 grg_status tune_dslash(grg_schur S, int prec, int nrhs, int reps);
 
 static grg_status dmalloc(void **p, size_t bytes, const char *what)
@@ -278,6 +281,8 @@ grg_status grg_dirac_apply(grg_lattice L, double m0, int precision, const double
     a.SB = t.SB;
     a.RG = t.RG;
     a.split = t.split;
+    a.chunk = t.chunk;
+    a.march = t.march;
     a.partials = nullptr;
     GRG_TRY_HIP(launch_dslash(precision, a, t.grid, L->stream));
     GRG_TRY_HIP(launch_unpack_spinor(precision, L->tmp_out, out, L->g, nrhs, L->stream));
@@ -534,7 +539,7 @@ grg_status grg_schur_tune(grg_schur S, int nrhs)
     return GRG_OK;
 }
 
-grg_status grg_schur_tune_info(grg_schur S, int precision, int nrhs, int32_t info[4], float *ms)
+grg_status grg_schur_tune_info(grg_schur S, int precision, int nrhs, int32_t info[6], float *ms)
 {
     if (!S || !info || !ms) return set_error("null argument"), GRG_EINVAL;
     if (precision < 0 || precision > 2 || nrhs < 1 || nrhs > kMaxRhs)
@@ -545,8 +550,50 @@ grg_status grg_schur_tune_info(grg_schur S, int precision, int nrhs, int32_t inf
     info[1] = d.RG;
     info[2] = d.split;
     info[3] = d.grid;
+    info[4] = d.chunk;
+    info[5] = d.march;
     *ms = t.valid ? t.ms : -1.0f;
     return GRG_OK;
+}
+
+grg_status grg_schur_set_launch(grg_schur S, int precision, int nrhs, const int32_t info[6])
+{
+    if (!S || !info) return set_error("null argument"), GRG_EINVAL;
+    if (precision < 0 || precision > 2 || nrhs < 1 || nrhs > S->prm.max_rhs)
+        return set_error("bad precision or nrhs"), GRG_EINVAL;
+    DslashTune t;
+    t.SB = info[0];
+    t.RG = info[1];
+    t.split = info[2];
+    t.grid = info[3];
+    t.chunk = info[4];
+    t.march = info[5];
+    t.valid = 1;
+    t.ms = 0;
+    if (!launch_ok(S->lat->g, precision, nrhs, t, false))
+        return set_error("launch {%d, %d, %d, %d, %d, %d} not valid for precision %d, nrhs %d",
+                         info[0], info[1], info[2], info[3], info[4], info[5], precision, nrhs),
+               GRG_EINVAL;
+    S->tune[precision][nrhs] = t;
+    return GRG_OK;
+}
+
+grg_status grg_block_apply(grg_schur S, int precision, int rows, int cols, const double *in,
+                           double *out, int nrhs)
+{
+    GRG_TRY(check_call(S, in, out, nrhs));
+    if (precision < 0 || precision > 2) return set_error("bad precision"), GRG_EINVAL;
+    if (rows < -1 || rows > 1 || cols < -1 || cols > 1)
+        return set_error("rows / cols must be -1, 0 or 1"), GRG_EINVAL;
+    DeviceGuard dg(S->lat->device);
+    grg_status st = block_apply_internal(S, precision, rows, cols, in, out, nrhs);
+    hipError_t e = hipStreamSynchronize(S->lat->stream);
+    if (st == GRG_OK && e != hipSuccess) {
+        set_error("stream synchronise failed: %s", hipGetErrorString(e));
+        st = GRG_EHIP;
+    }
+    collect_profile(S);
+    return st;
 }
 
 grg_status grg_profile_enable(grg_schur S, int on)

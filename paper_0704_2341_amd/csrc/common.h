@@ -74,6 +74,24 @@ __device__ __forceinline__ cpx<R> cmulc(cpx<R> a, cpx<R> b)
     return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
 }
 
+// acc += m * h and acc += conj(m) * h as four fused multiply-adds
+template <class R>
+__device__ __forceinline__ void cmac(cpx<R> &acc, cpx<R> m, cpx<R> h)
+{
+    acc.re = fma(m.re, h.re, acc.re);
+    acc.re = fma(-m.im, h.im, acc.re);
+    acc.im = fma(m.re, h.im, acc.im);
+    acc.im = fma(m.im, h.re, acc.im);
+}
+template <class R>
+__device__ __forceinline__ void cmacc(cpx<R> &acc, cpx<R> m, cpx<R> h)
+{
+    acc.re = fma(m.re, h.re, acc.re);
+    acc.re = fma(m.im, h.im, acc.re);
+    acc.im = fma(m.re, h.im, acc.im);
+    acc.im = fma(-m.im, h.re, acc.im);
+}
+
 // ------------------------------------------------------------------ storage
 template <int P>
 struct Store;
@@ -109,6 +127,14 @@ __device__ __forceinline__ cpx<float> ldc(const bf16x2 *p, size_t i)
     return {__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u)};
 }
 
+// load converted to the compute type R
+template <class R, class S>
+__device__ __forceinline__ cpx<R> ldr(const S *p, size_t i)
+{
+    const auto v = ldc(p, i);
+    return {(R)v.re, (R)v.im};
+}
+
 // float -> bfloat16 bits, round to nearest even; NaN stays NaN.
 __device__ __forceinline__ uint32_t f2bf(float f)
 {
@@ -120,10 +146,16 @@ __device__ __forceinline__ uint32_t f2bf(float f)
 
 __device__ __forceinline__ void stc(double2 *p, size_t i, cpx<double> v) { p[i] = make_double2(v.re, v.im); }
 __device__ __forceinline__ void stc(float2 *p, size_t i, cpx<float> v) { p[i] = make_float2(v.re, v.im); }
-__device__ __forceinline__ void stc(bf16x2 *p, size_t i, cpx<float> v)
+// Both halves at once with the gfx950 packed conversion (round to nearest
+// even, the rounding of f2bf above).
+typedef float f32x2_v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16(float re, float im)
 {
-    p[i] = f2bf(v.re) | (f2bf(v.im) << 16);
+    const f32x2_v v = {re, im};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_v));
 }
+__device__ __forceinline__ void stc(bf16x2 *p, size_t i, cpx<float> v) { p[i] = pack_bf16(v.re, v.im); }
 
 // ------------------------------------------------------------------ work items
 // Work item w in [0, nitems) of a grid-stride loop, XCD-aware: workgroup b
@@ -141,6 +173,20 @@ __device__ __forceinline__ ItemRange xcd_items(int nitems)
     r.end = min((xcd + 1) * nper, nitems);
     r.step = per_xcd_wg;
     return r;
+}
+
+// Chunked XCD mapping: items are cut into chunks of C consecutive items and
+// chunk k belongs to XCD k % 8.  Workgroups of one XCD share its L2 and walk
+// its chunks in order, so neighbouring sites of a chunk meet in that L2,
+// while the eight XCDs stay in the same region of the lattice, so that data
+// evicted from one L2 is still in the shared last-level cache when a
+// neighbouring chunk needs it.  C = ceil(nitems / 8) gives each XCD one
+// contiguous eighth; C = 1 is plain round-robin.  Returns -1 past the end.
+__device__ __forceinline__ int xcd_chunk_item(int j, int C, int nitems)
+{
+    const int ch = (int)(blockIdx.x & 7) + 8 * (j / C);
+    const int item = ch * C + (j - (j / C) * C);
+    return item < nitems ? item : -1;
 }
 
 // wave64 sum

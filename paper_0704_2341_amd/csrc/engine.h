@@ -12,6 +12,7 @@
 namespace grg {
 
 constexpr int kMaxRhs = 16;
+constexpr int kMaxGridValue = 4096;  // largest stencil/BLAS grid (sizes partial sums)
 
 void set_error(const char *fmt, ...);
 
@@ -44,13 +45,16 @@ struct DslashArgs {
     int SB;               // sites per work item == workgroup size
     int RG;               // right-hand sides per work item
     int split;            // 1: one hop per loop iteration, 0: one direction (two hops)
+    int chunk;            // items per XCD chunk (0 = one contiguous eighth per XCD)
+    int march;            // > 0: t-marching kernel with time chunks of this length
+                          //      (64 sites x RG RHS wavefronts per workgroup)
     double *partials;     // [grid][nrhs][3] or nullptr
 };
 
 // A tuned launch of the stencil for one precision and RHS count.
 struct DslashTune {
     int valid = 0;
-    int SB = 128, RG = 1, split = 0, grid = 0;
+    int SB = 128, RG = 1, split = 0, grid = 0, chunk = 0, march = 0;
     float ms = 0;
 };
 
@@ -65,12 +69,28 @@ struct CoarseArgs {
     int nrhs;
 };
 
+// Fused FP64 defect-correction step (see dc_update_kernel).
+struct DcArgs {
+    const void *e;        // inner solution, internal tiles in the inner precision
+    const void *U;        // FP64 links
+    const void *r_in;     // FP64 residual before the step
+    const void *x_in;     // FP64 iterate before the step, or nullptr for zero
+    void *r_out, *x_out;  // FP64 results (may alias the inputs)
+    const double *fr2;    // per-RHS |r|^2 the inner right-hand side was scaled by
+    const uint8_t *mask;  // 1 on coarse sites
+    double diag;          // 4 + m0
+    Geom g;
+    int nrhs;
+    double *partials;     // [grid][nrhs]: |r_out|^2
+};
+
 hipError_t launch_dslash(int prec, const DslashArgs &a, int grid, hipStream_t st);
+hipError_t launch_dc_update(int prec, const DcArgs &a, int grid, int SB, hipStream_t st);
 hipError_t launch_dslash_coarse(const CoarseArgs &a, hipStream_t st);
 hipError_t launch_pack_gauge(const double *src, const Geom &g, const int bc[4], void *u64,
                              void *u32, void *u16, hipStream_t st);
 hipError_t launch_pack_spinor(int prec, const double *src, void *dst, const Geom &g, int nrhs,
-                              hipStream_t st);
+                              hipStream_t st, const uint8_t *mask = nullptr, int keep = 0);
 hipError_t launch_unpack_spinor(int prec, const void *src, double *dst, const Geom &g, int nrhs,
                                 hipStream_t st);
 hipError_t launch_pack_masked(const double *src, void *dst, const uint8_t *mask, int keep,

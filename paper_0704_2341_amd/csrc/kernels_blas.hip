@@ -57,7 +57,8 @@ struct Partial {
 };
 
 // ------------------------------------------------------------------ MR / GCR step
-template <int P>
+// HAS_P = false: p is r itself (minimal residual), read once
+template <int P, bool HAS_P>
 __global__ void __launch_bounds__(256) mr_update_kernel(BlasShape sh, void *x_, void *r_,
                                                         const void *q_, const void *p_,
                                                         const double2 *alpha, double *partials)
@@ -68,29 +69,29 @@ __global__ void __launch_bounds__(256) mr_update_kernel(BlasShape sh, void *x_, 
     Partial<1> part;
     part.init(smem, sh.nrhs);
     S *x = (S *)x_, *r = (S *)r_;
-    const S *q = (const S *)q_, *p = p_ ? (const S *)p_ : (const S *)r_;
+    const S *q = (const S *)q_, *p = (const S *)p_;
     SITE_LOOP_BEGIN(sh)
     for (int k = 0; k < sh.nrhs; ++k) {
         const double2 a2 = alpha[k];
         const cpx<R> a = {(R)a2.x, (R)a2.y};
-        double rr = 0;
+        R rr = 0;
         if (valid) {
+            const cpx<R> na = {-a.re, -a.im};
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 const size_t i = fidx(s, k, c, sh.nrhs);
                 cpx<R> xv = ldc(x, i), rv = ldc(r, i);
-                const cpx<R> pv = ldc(p, i), qv = ldc(q, i);
-                const cpx<R> ap = cmul(a, pv), aq = cmul(a, qv);
-                xv.re += ap.re; xv.im += ap.im;
-                rv.re -= aq.re; rv.im -= aq.im;
+                const cpx<R> pv = HAS_P ? ldc(p, i) : rv, qv = ldc(q, i);
+                cmac(xv, a, pv);
+                cmac(rv, na, qv);
                 stc(x, i, xv);
                 stc(r, i, rv);
                 // the norm of the value actually stored
                 const cpx<R> rs = ldc(r, i);
-                rr += (double)rs.re * rs.re + (double)rs.im * rs.im;
+                rr = fma(rs.re, rs.re, fma(rs.im, rs.im, rr));
             }
         }
-        const double v[1] = {rr};
+        const double v[1] = {(double)rr};
         part.add(k, v);
     }
     SITE_LOOP_END
@@ -413,8 +414,17 @@ hipError_t launch_mr_update(int prec, const BlasShape &sh, void *x, void *r, con
                             hipStream_t st)
 {
     if (!shape_ok(sh)) return hipErrorInvalidValue;
-    DISPATCH_P(prec, mr_update_kernel, dim3(sh.grid), dim3(kBlasSB), 0, st, sh, x, r, q, p, alpha,
-               partials);
+    dim3 g(sh.grid), b(kBlasSB);
+#define MRU(PP)                                                                                    \
+    if (p) hipLaunchKernelGGL((mr_update_kernel<PP, true>), g, b, 0, st, sh, x, r, q, p, alpha, partials); \
+    else hipLaunchKernelGGL((mr_update_kernel<PP, false>), g, b, 0, st, sh, x, r, q, p, alpha, partials);
+    switch (prec) {
+    case GRG_FP64: MRU(GRG_FP64) break;
+    case GRG_FP32: MRU(GRG_FP32) break;
+    case GRG_BF16: MRU(GRG_BF16) break;
+    default: return hipErrorInvalidValue;
+    }
+#undef MRU
     return hipGetLastError();
 }
 

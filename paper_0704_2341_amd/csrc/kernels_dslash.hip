@@ -54,18 +54,21 @@ __device__ __forceinline__ void hop_math(cpx<R> (&acc)[12], const cpx<R> (&p)[12
         h0[a] = {p[a].re + sg * b0.re, p[a].im + sg * b0.im};
         h1[a] = {p[3 + a].re + sg * b1.re, p[3 + a].im + sg * b1.im};
     }
-    // w = U h (forward) or U^+ h (backward), one colour vector per spin
+    // w = U h (forward) or U^+ h (backward), one colour vector per spin;
+    // each complex multiply-add is four fused multiply-adds
     cpx<R> w0[3], w1[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
         cpx<R> s0 = {0, 0}, s1 = {0, 0};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const cpx<R> m = FWD ? u[3 * r + c] : u[3 * c + r];
-            const cpx<R> t0 = FWD ? cmul(m, h0[c]) : cmulc(m, h0[c]);
-            const cpx<R> t1 = FWD ? cmul(m, h1[c]) : cmulc(m, h1[c]);
-            s0.re += t0.re; s0.im += t0.im;
-            s1.re += t1.re; s1.im += t1.im;
+            if (FWD) {
+                cmac(s0, u[3 * r + c], h0[c]);
+                cmac(s1, u[3 * r + c], h1[c]);
+            } else {
+                cmacc(s0, u[3 * c + r], h0[c]);
+                cmacc(s1, u[3 * c + r], h1[c]);
+            }
         }
         w0[r] = s0;
         w1[r] = s1;
@@ -75,10 +78,10 @@ __device__ __forceinline__ void hop_math(cpx<R> (&acc)[12], const cpx<R> (&p)[12
     const R hl = FWD ? R(0.5) : R(-0.5);
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-        acc[r].re += hu * w0[r].re;
-        acc[r].im += hu * w0[r].im;
-        acc[3 + r].re += hu * w1[r].re;
-        acc[3 + r].im += hu * w1[r].im;
+        acc[r].re = fma(hu, w0[r].re, acc[r].re);
+        acc[r].im = fma(hu, w0[r].im, acc[r].im);
+        acc[3 + r].re = fma(hu, w1[r].re, acc[3 + r].re);
+        acc[3 + r].im = fma(hu, w1[r].im, acc[3 + r].im);
         cpx<R> d0, d1;  // B^+ w
         if (MU == 0) {        // (-i w1, -i w0)
             d0 = {w1[r].im, -w1[r].re};
@@ -93,10 +96,10 @@ __device__ __forceinline__ void hop_math(cpx<R> (&acc)[12], const cpx<R> (&p)[12
             d0 = w0[r];
             d1 = w1[r];
         }
-        acc[6 + r].re += hl * d0.re;
-        acc[6 + r].im += hl * d0.im;
-        acc[9 + r].re += hl * d1.re;
-        acc[9 + r].im += hl * d1.im;
+        acc[6 + r].re = fma(hl, d0.re, acc[6 + r].re);
+        acc[6 + r].im = fma(hl, d0.im, acc[6 + r].im);
+        acc[9 + r].re = fma(hl, d1.re, acc[9 + r].re);
+        acc[9 + r].im = fma(hl, d1.im, acc[9 + r].im);
     }
 }
 
@@ -134,14 +137,14 @@ __device__ __forceinline__ void nbr(int s, int mu, const SiteGeo &q, const Geom 
 // unrolled: each iteration loads one direction's two neighbours and links
 // (24 + 18 complex; SPLIT: one hop, 12 + 9 complex) and consumes them, which
 // bounds the live registers and keeps several wavefronts per SIMD in flight.
-template <class S, class R, bool SPLIT>
+template <class S, class R, bool SPLIT, class SU = S>
 __device__ __forceinline__ void dslash_site(cpx<R> (&acc)[12], const S *__restrict__ in,
-                                            const S *__restrict__ U, int s, const SiteGeo &q,
+                                            const SU *__restrict__ U, int s, const SiteGeo &q,
                                             const Geom &g, int r, int nrhs, R diag)
 {
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-        const cpx<R> v = ldc(in, fidx(s, r, c, nrhs));
+        const cpx<R> v = ldr<R>(in, fidx(s, r, c, nrhs));
         acc[c] = {diag * v.re, diag * v.im};
     }
     if (SPLIT) {
@@ -153,9 +156,9 @@ __device__ __forceinline__ void dslash_site(cpx<R> (&acc)[12], const S *__restri
             const int n = (h & 1) ? sm : sp;
             cpx<R> p[12], u[9];
 #pragma unroll
-            for (int c = 0; c < 12; ++c) p[c] = ldc(in, fidx(n, r, c, nrhs));
+            for (int c = 0; c < 12; ++c) p[c] = ldr<R>(in, fidx(n, r, c, nrhs));
 #pragma unroll
-            for (int e = 0; e < 9; ++e) u[e] = ldc(U, lidx((h & 1) ? sm : s, mu, e));
+            for (int e = 0; e < 9; ++e) u[e] = ldr<R>(U, lidx((h & 1) ? sm : s, mu, e));
             switch (h) {
             case 0: hop_math<0, true>(acc, p, u); break;
             case 1: hop_math<0, false>(acc, p, u); break;
@@ -176,13 +179,13 @@ __device__ __forceinline__ void dslash_site(cpx<R> (&acc)[12], const S *__restri
         cpx<R> pf[12], pb[12], uf[9], ub[9];
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            pf[c] = ldc(in, fidx(sp, r, c, nrhs));
-            pb[c] = ldc(in, fidx(sm, r, c, nrhs));
+            pf[c] = ldr<R>(in, fidx(sp, r, c, nrhs));
+            pb[c] = ldr<R>(in, fidx(sm, r, c, nrhs));
         }
 #pragma unroll
         for (int e = 0; e < 9; ++e) {
-            uf[e] = ldc(U, lidx(s, mu, e));
-            ub[e] = ldc(U, lidx(sm, mu, e));
+            uf[e] = ldr<R>(U, lidx(s, mu, e));
+            ub[e] = ldr<R>(U, lidx(sm, mu, e));
         }
         switch (mu) {
         case 0: hop_math<0, true>(acc, pf, uf); hop_math<0, false>(acc, pb, ub); break;
@@ -212,8 +215,11 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
     }
     const int ngroups = (a.nrhs + a.RG - 1) / a.RG;
     const int nsb = (a.g.V + a.SB - 1) / a.SB;
-    const ItemRange it = xcd_items(nsb * ngroups);
-    for (int w = it.begin; w < it.end; w += it.step) {
+    const int nitems = nsb * ngroups;
+    const int C = a.chunk > 0 ? a.chunk : (nitems + 7) / 8;
+    for (int j = blockIdx.x >> 3;; j += gridDim.x >> 3) {
+        const int w = xcd_chunk_item(j, C, nitems);
+        if (w < 0) break;
         const int sb = w / ngroups, grp = w - sb * ngroups;
         const int s = sb * a.SB + (int)threadIdx.x;
         const bool valid = s < a.g.V;
@@ -234,19 +240,21 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
                 for (int c = 0; c < 12; ++c) stc(out, fidx(s, r, c, a.nrhs), acc[c]);
             }
             if (dots) {
-                double dre = 0, dim = 0, dqq = 0;
+                // a site's 12 terms in the compute precision, the sums over
+                // sites and workgroups in FP64
+                R sre = 0, sim = 0, sqq = 0;
                 if (on) {
 #pragma unroll
                     for (int c = 0; c < 12; ++c) {
                         const cpx<R> v = ldc(in, fidx(s, r, c, a.nrhs));
-                        dre += (double)acc[c].re * v.re + (double)acc[c].im * v.im;
-                        dim += (double)acc[c].re * v.im - (double)acc[c].im * v.re;
-                        dqq += (double)acc[c].re * acc[c].re + (double)acc[c].im * acc[c].im;
+                        sre = fma(acc[c].re, v.re, fma(acc[c].im, v.im, sre));
+                        sim = fma(acc[c].re, v.im, fma(-acc[c].im, v.re, sim));
+                        sqq = fma(acc[c].re, acc[c].re, fma(acc[c].im, acc[c].im, sqq));
                     }
                 }
-                dre = wave_sum(dre);
-                dim = wave_sum(dim);
-                dqq = wave_sum(dqq);
+                const double dre = wave_sum((double)sre);
+                const double dim = wave_sum((double)sim);
+                const double dqq = wave_sum((double)sqq);
                 if (lane == 0) {
                     red[wave][r][0] += dre;
                     red[wave][r][1] += dim;
@@ -263,6 +271,225 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
             for (int k = 0; k < nw; ++k) t += red[k][i / 3][i % 3];
             a.partials[(size_t)blockIdx.x * a.nrhs * 3 + i] = t;
         }
+    }
+}
+
+// t-marching stencil.  A workgroup owns 64 sites of one x-y-z plane (one
+// wavefront of sites) for RG right-hand sides (one wavefront per RHS), over a
+// chunk of T consecutive time slices, and walks t upwards.  psi(t) is loaded
+// once and used three times from registers: as the diagonal term of site t,
+// in the backward t-hop of site t+1 and in the forward t-hop of site t-1;
+// U_t(t) serves the backward hop of t+1 now and the forward hop of t on the
+// next step.  The t-neighbours, whose reuse distance (a whole 3-d slice) no L2
+// can hold at this footprint, thus cost nothing beyond the slice itself, and
+// the links of a site are read once for all RG right-hand sides (the RG
+// wavefronts of a workgroup request the same lines together).
+template <int P>
+__device__ __forceinline__ void march_store(DslashArgs &a, cpx<typename Store<P>::R> (&acc)[12],
+                                            int s, int r, bool valid, double (&dot)[3])
+{
+    typedef typename Store<P>::S S;
+    typedef typename Store<P>::R R;
+    const bool on = valid && (a.mask == nullptr || a.mask[s] == a.sel);
+    if (!valid) return;
+    S *out = (S *)a.out;
+    const S *in = (const S *)a.in;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const size_t i = fidx(s, r, c, a.nrhs);
+        const cpx<R> o = on ? acc[c] : cpx<R>{0, 0};
+        stc(out, i, o);
+        if (a.partials && on) {
+            const cpx<R> v = ldc(in, i);
+            dot[0] += (double)o.re * v.re + (double)o.im * v.im;
+            dot[1] += (double)o.re * v.im - (double)o.im * v.re;
+            dot[2] += (double)o.re * o.re + (double)o.im * o.im;
+        }
+    }
+}
+
+// Largest workgroup of the t-marching kernel: 12 RHS wavefronts in FP32/BF16
+// (<= 170 VGPRs at 3 waves per SIMD), 8 in FP64.
+__host__ __device__ constexpr int march_max_threads(int prec) { return prec == GRG_FP64 ? 512 : 768; }
+
+template <int P>
+__global__ void __launch_bounds__(march_max_threads(P)) dslash_march_kernel(DslashArgs a)
+{
+    typedef typename Store<P>::S S;
+    typedef typename Store<P>::R R;
+    __shared__ double red[16][3];
+    const S *__restrict__ in = (const S *)a.in;
+    const S *__restrict__ U = (const S *)a.U;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int V3 = a.g.L[0] * a.g.L[1] * a.g.L[2], Lt = a.g.L[3];
+    const int nb3 = (V3 + 63) >> 6;
+    const int T = a.march;
+    const int ntc = (Lt + T - 1) / T;
+    const int ngroups = (a.nrhs + a.RG - 1) / a.RG;
+    const int nitems = nb3 * ntc * ngroups;
+    const R diag = (R)a.diag;
+    double dot[3] = {0, 0, 0};
+    const int C = a.chunk > 0 ? a.chunk : (nitems + 7) / 8;
+    for (int j = blockIdx.x >> 3;; j += gridDim.x >> 3) {
+        const int w = xcd_chunk_item(j, C, nitems);
+        if (w < 0) break;
+        const int b3 = w % nb3, rest = w / nb3;
+        const int grp = rest % ngroups, tc = rest / ngroups;
+        const int s3 = b3 * 64 + lane;
+        const int r = grp * a.RG + wv;
+        if (r >= a.nrhs) continue;  // whole wavefront idles
+        const bool valid = s3 < V3;
+        const int s3c = valid ? s3 : 0;  // keep idle lanes' addresses in range
+        const int t0 = tc * T, t1 = min(t0 + T, Lt);
+        SiteGeo q = site_geo(s3c, a.g);
+        // prologue: backward t-hop of site t0 from psi(t0 - 1)
+        cpx<R> acc_cur[12], acc_prev[12], ut_prev[9];
+        {
+            const int sm = s3c + V3 * (t0 == 0 ? Lt - 1 : t0 - 1);
+            cpx<R> p[12], u[9];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) p[c] = ldc(in, fidx(sm, r, c, a.nrhs));
+#pragma unroll
+            for (int e = 0; e < 9; ++e) u[e] = ldc(U, lidx(sm, 3, e));
+#pragma unroll
+            for (int c = 0; c < 12; ++c) acc_cur[c] = {0, 0};
+            hop_math<3, false>(acc_cur, p, u);
+        }
+#pragma unroll 1
+        for (int t = t0; t < t1; ++t) {
+            const int s = s3c + V3 * t;
+            q.c[3] = t;
+            cpx<R> psi[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) psi[c] = ldc(in, fidx(s, r, c, a.nrhs));
+            if (t > t0) {  // finish site t - 1 with its forward t-hop
+                hop_math<3, true>(acc_prev, psi, ut_prev);
+                march_store<P>(a, acc_prev, s - V3, r, valid, dot);
+            }
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                acc_cur[c].re += diag * psi[c].re;
+                acc_cur[c].im += diag * psi[c].im;
+            }
+#pragma unroll 1
+            for (int h = 0; h < 6; ++h) {  // x, y, z hops, one at a time
+                const int mu = h >> 1;
+                int sp, sm;
+                nbr(s, mu, q, a.g, sp, sm);
+                const int n = (h & 1) ? sm : sp;
+                cpx<R> p[12], u[9];
+#pragma unroll
+                for (int c = 0; c < 12; ++c) p[c] = ldc(in, fidx(n, r, c, a.nrhs));
+#pragma unroll
+                for (int e = 0; e < 9; ++e) u[e] = ldc(U, lidx((h & 1) ? sm : s, mu, e));
+                switch (h) {
+                case 0: hop_math<0, true>(acc_cur, p, u); break;
+                case 1: hop_math<0, false>(acc_cur, p, u); break;
+                case 2: hop_math<1, true>(acc_cur, p, u); break;
+                case 3: hop_math<1, false>(acc_cur, p, u); break;
+                case 4: hop_math<2, true>(acc_cur, p, u); break;
+                default: hop_math<2, false>(acc_cur, p, u); break;
+                }
+            }
+            // backward t-hop of site t + 1, from psi(t) and U_t(t)
+#pragma unroll
+            for (int e = 0; e < 9; ++e) ut_prev[e] = ldc(U, lidx(s, 3, e));
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                acc_prev[c] = acc_cur[c];
+                acc_cur[c] = {0, 0};
+            }
+            hop_math<3, false>(acc_cur, psi, ut_prev);
+        }
+        // epilogue: forward t-hop of site t1 - 1 from psi(t1)
+        {
+            const int sp = s3c + V3 * (t1 == Lt ? 0 : t1);
+            cpx<R> p[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) p[c] = ldc(in, fidx(sp, r, c, a.nrhs));
+            hop_math<3, true>(acc_prev, p, ut_prev);
+            march_store<P>(a, acc_prev, s3c + V3 * (t1 - 1), r, valid, dot);
+        }
+    }
+    if (a.partials) {
+        // one wavefront per RHS slot: reduce over lanes, then over the
+        // workgroup's items; slot wv holds RHS grp * RG + wv of each item
+        // (with RG == nrhs every workgroup covers every RHS)
+        for (int k = 0; k < 3; ++k) dot[k] = wave_sum(dot[k]);
+        if (lane == 0)
+            for (int k = 0; k < 3; ++k) red[wv][k] = dot[k];
+        __syncthreads();
+        for (int i = threadIdx.x; i < a.nrhs * 3; i += blockDim.x) {
+            const int rr = i / 3, k = i % 3;
+            a.partials[(size_t)blockIdx.x * a.nrhs * 3 + i] = (rr < (int)(blockDim.x >> 6)) ? red[rr][k] : 0.0;
+        }
+    }
+}
+
+// One FP64 defect-correction step, fused.  e is the inner solution (stored in
+// precision P, zero on coarse sites), f_k = sqrt(fr2[k]) the outer residual
+// norm it was normalised by:
+//     r_out = r_in - f (D_rr e)        x_out = x_in + f e        (FP64)
+// on the r-sites; coarse sites are written as zero.  x_in == nullptr reads as
+// zero.  Also the per-workgroup partial sums of |r_out|^2 per RHS.  r_out may
+// alias r_in and x_out may alias x_in (each thread touches only its own site).
+template <int P>
+__global__ void __launch_bounds__(256) dc_update_kernel(DcArgs a)
+{
+    typedef typename Store<P>::S S;
+    __shared__ double red[4][kMaxRhs];
+    const S *__restrict__ e = (const S *)a.e;
+    const double2 *__restrict__ U = (const double2 *)a.U;
+    const double2 *r_in = (const double2 *)a.r_in;
+    const double2 *x_in = (const double2 *)a.x_in;
+    double2 *r_out = (double2 *)a.r_out;
+    double2 *x_out = (double2 *)a.x_out;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = lane; i < a.nrhs; i += 64) red[wave][i] = 0.0;
+    __syncthreads();
+    const int nsb = (a.g.V + blockDim.x - 1) / blockDim.x;
+    const ItemRange it = xcd_items(nsb);
+    for (int w = it.begin; w < it.end; w += it.step) {
+        const int s = w * blockDim.x + (int)threadIdx.x;
+        const bool valid = s < a.g.V;
+        const bool on = valid && a.mask[s] == 0;
+        SiteGeo q;
+        if (on) q = site_geo(s, a.g);
+        for (int r = 0; r < a.nrhs; ++r) {
+            double nrm = 0;
+            if (on) {
+                cpx<double> acc[12];
+                dslash_site<S, double, true, double2>(acc, e, U, s, q, a.g, r, a.nrhs, a.diag);
+                const double f = sqrt(a.fr2[r]);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    const size_t i = fidx(s, r, c, a.nrhs);
+                    const double2 rv = r_in[i];
+                    const double2 d = make_double2(rv.x - f * acc[c].re, rv.y - f * acc[c].im);
+                    r_out[i] = d;
+                    nrm += d.x * d.x + d.y * d.y;
+                    const cpx<double> ev = ldr<double>(e, i);
+                    const double2 xv = x_in ? x_in[i] : make_double2(0.0, 0.0);
+                    x_out[i] = make_double2(xv.x + f * ev.re, xv.y + f * ev.im);
+                }
+            } else if (valid) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    const size_t i = fidx(s, r, c, a.nrhs);
+                    r_out[i] = make_double2(0.0, 0.0);
+                    x_out[i] = make_double2(0.0, 0.0);
+                }
+            }
+            nrm = wave_sum(nrm);
+            if (lane == 0) red[wave][r] += nrm;
+        }
+    }
+    __syncthreads();
+    const int nw = blockDim.x >> 6;
+    for (int i = threadIdx.x; i < a.nrhs; i += blockDim.x) {
+        double t = 0;
+        for (int k = 0; k < nw; ++k) t += red[k][i];
+        a.partials[(size_t)blockIdx.x * a.nrhs + i] = t;
     }
 }
 
@@ -309,19 +536,22 @@ __global__ void pack_gauge_kernel(const double2 *__restrict__ src, Geom g, int4 
 }
 
 // canonical [nrhs][V][12] complex128  <->  internal tiles
+// mask != nullptr: sites with mask[s] != keep are written as zero
 template <int P>
-__global__ void pack_spinor_kernel(const double2 *__restrict__ src, void *dst, Geom g, int nrhs)
+__global__ void pack_spinor_kernel(const double2 *__restrict__ src, void *dst, Geom g, int nrhs,
+                                   const uint8_t *__restrict__ mask, int keep)
 {
     typedef typename Store<P>::S S;
     typedef typename Store<P>::R R;
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
     if (s >= g.V || r >= nrhs) return;
+    const bool k = mask == nullptr || mask[s] == keep;
     const double2 *p = src + ((size_t)r * g.V + s) * 12;
     S *o = (S *)dst;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-        const double2 v = p[c];
+        const double2 v = k ? p[c] : make_double2(0.0, 0.0);
         stc(o, fidx(s, r, c, nrhs), cpx<R>{(R)v.x, (R)v.y});
     }
 }
@@ -376,9 +606,22 @@ static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 hipError_t launch_dslash(int prec, const DslashArgs &a, int grid, hipStream_t st)
 {
-    if (a.SB != 256 && a.SB != 128 && a.SB != 64) return hipErrorInvalidValue;
     if (a.nrhs < 1 || a.nrhs > kMaxRhs || a.RG < 1) return hipErrorInvalidValue;
     if (grid < 8 || grid % 8) return hipErrorInvalidValue;
+    if (a.march > 0) {
+        // one wavefront per RHS of a group; fused dots need the whole batch per workgroup
+        if (64 * a.RG > march_max_threads(prec) || (a.partials && a.RG != a.nrhs))
+            return hipErrorInvalidValue;
+        dim3 blk(64 * a.RG), grd(grid);
+        switch (prec) {
+        case GRG_FP64: hipLaunchKernelGGL(dslash_march_kernel<GRG_FP64>, grd, blk, 0, st, a); break;
+        case GRG_FP32: hipLaunchKernelGGL(dslash_march_kernel<GRG_FP32>, grd, blk, 0, st, a); break;
+        case GRG_BF16: hipLaunchKernelGGL(dslash_march_kernel<GRG_BF16>, grd, blk, 0, st, a); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    if (a.SB != 256 && a.SB != 128 && a.SB != 64) return hipErrorInvalidValue;
     dim3 blk(a.SB), grd(grid);
 #define DSL(PP)                                                                                 \
     if (a.split) hipLaunchKernelGGL((dslash_kernel<PP, true>), grd, blk, 0, st, a);             \
@@ -390,6 +633,19 @@ hipError_t launch_dslash(int prec, const DslashArgs &a, int grid, hipStream_t st
     default: return hipErrorInvalidValue;
     }
 #undef DSL
+    return hipGetLastError();
+}
+
+hipError_t launch_dc_update(int prec, const DcArgs &a, int grid, int SB, hipStream_t st)
+{
+    if (a.nrhs < 1 || a.nrhs > kMaxRhs || grid < 8 || grid % 8) return hipErrorInvalidValue;
+    if (SB != 64 && SB != 128 && SB != 256) return hipErrorInvalidValue;
+    switch (prec) {
+    case GRG_FP64: hipLaunchKernelGGL(dc_update_kernel<GRG_FP64>, dim3(grid), dim3(SB), 0, st, a); break;
+    case GRG_FP32: hipLaunchKernelGGL(dc_update_kernel<GRG_FP32>, dim3(grid), dim3(SB), 0, st, a); break;
+    case GRG_BF16: hipLaunchKernelGGL(dc_update_kernel<GRG_BF16>, dim3(grid), dim3(SB), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -410,14 +666,14 @@ hipError_t launch_pack_gauge(const double *src, const Geom &g, const int bc[4], 
 }
 
 hipError_t launch_pack_spinor(int prec, const double *src, void *dst, const Geom &g, int nrhs,
-                              hipStream_t st)
+                              hipStream_t st, const uint8_t *mask, int keep)
 {
     dim3 grd(cdiv(g.V, 256), nrhs), blk(256);
     const double2 *s = (const double2 *)src;
     switch (prec) {
-    case GRG_FP64: hipLaunchKernelGGL(pack_spinor_kernel<GRG_FP64>, grd, blk, 0, st, s, dst, g, nrhs); break;
-    case GRG_FP32: hipLaunchKernelGGL(pack_spinor_kernel<GRG_FP32>, grd, blk, 0, st, s, dst, g, nrhs); break;
-    case GRG_BF16: hipLaunchKernelGGL(pack_spinor_kernel<GRG_BF16>, grd, blk, 0, st, s, dst, g, nrhs); break;
+    case GRG_FP64: hipLaunchKernelGGL(pack_spinor_kernel<GRG_FP64>, grd, blk, 0, st, s, dst, g, nrhs, mask, keep); break;
+    case GRG_FP32: hipLaunchKernelGGL(pack_spinor_kernel<GRG_FP32>, grd, blk, 0, st, s, dst, g, nrhs, mask, keep); break;
+    case GRG_BF16: hipLaunchKernelGGL(pack_spinor_kernel<GRG_BF16>, grd, blk, 0, st, s, dst, g, nrhs, mask, keep); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -74,9 +74,24 @@ static grg_status launch_tuned(grg_lattice L, int prec, const DslashTune &t, con
     a.SB = t.SB;
     a.RG = t.RG;
     a.split = t.split;
+    a.chunk = t.chunk;
+    a.march = t.march;
     a.partials = partials;
     GRG_TRY_HIP(launch_dslash(prec, a, t.grid, L->stream));
     return GRG_OK;
+}
+
+// Validity of a launch shape for (prec, nrhs); the solver's fused dot
+// products additionally need a t-marching workgroup to hold every RHS.
+bool launch_ok(const Geom &g, int prec, int nrhs, const DslashTune &t, bool dots)
+{
+    if (t.grid < 8 || t.grid % 8 || t.grid > kMaxGridValue || t.chunk < 0 || t.march < 0) return false;
+    if (t.march > 0) {
+        if (t.march > g.L[3] || t.RG < 1 || 64 * t.RG > (prec == GRG_FP64 ? 512 : 768)) return false;
+        return !dots || t.RG == nrhs;
+    }
+    return (t.SB == 64 || t.SB == 128 || t.SB == 256) && t.RG >= 1 && t.RG <= nrhs &&
+           (t.split == 0 || t.split == 1);
 }
 
 // One stencil launch, bracketed by profiling events when enabled.
@@ -84,7 +99,9 @@ grg_status run_dslash(grg_schur S, int prec, const void *in, void *out, int sel,
                       double *partials)
 {
     grg_lattice L = S->lat;
-    const DslashTune t = S->tune[prec][nrhs].valid ? S->tune[prec][nrhs] : default_tune(L->g, prec, nrhs);
+    DslashTune t = S->tune[prec][nrhs].valid ? S->tune[prec][nrhs] : default_tune(L->g, prec, nrhs);
+    // fused dot products need every RHS of a t-marching workgroup
+    if (partials && t.march > 0 && t.RG != nrhs) t = default_tune(L->g, prec, nrhs);
     ProfilePool &P = S->prof;
     const bool ev = P.on && P.used < (int)P.start.size();
     if (ev) GRG_TRY_HIP(hipEventRecord(P.start[P.used], L->stream));
@@ -102,7 +119,7 @@ grg_status run_dslash(grg_schur S, int prec, const void *in, void *out, int sel,
 grg_status ensure_inner(grg_schur S, int prec);
 
 // Largest grid any stencil or BLAS launch may use (sizes the partial sums).
-constexpr int kMaxGrid = 4096;
+constexpr int kMaxGrid = kMaxGridValue;
 int partial_rows(const Geom &, int) { return kMaxGrid; }
 
 // Autotuner: time every candidate launch of the D_rr stencil (with its fused
@@ -117,6 +134,27 @@ grg_status tune_dslash(grg_schur S, int prec, int nrhs, int reps)
     GRG_TRY(ensure_inner(S, prec));
     const void *in = prec == GRG_FP64 ? S->b64 : S->in_b[prec];
     void *out = prec == GRG_FP64 ? S->t64 : S->in_q[prec];
+    hipEvent_t e0, e1;
+    GRG_TRY_HIP(hipEventCreate(&e0));
+    GRG_TRY_HIP(hipEventCreate(&e1));
+    grg_status status = GRG_OK;
+    auto timeit = [&](DslashTune &t) {
+        if (status != GRG_OK) return;
+        status = launch_tuned(L, prec, t, in, out, S->d_mask, 0, S->m0, nrhs, S->partials);
+        if (status != GRG_OK) return;
+        if (hipEventRecord(e0, st) != hipSuccess) { status = GRG_EHIP; return; }
+        for (int k = 0; k < reps && status == GRG_OK; ++k)
+            status = launch_tuned(L, prec, t, in, out, S->d_mask, 0, S->m0, nrhs, S->partials);
+        if (status != GRG_OK) return;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            status = GRG_EHIP;
+            return;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        t.ms = ms / reps;
+    };
+    // stage 1: workgroup size, RHS per thread, hop grouping (default grid and mapping)
     std::vector<DslashTune> cands;
     const int sbs[3] = {64, 128, 256};
     for (int sb : sbs) {
@@ -125,48 +163,59 @@ grg_status tune_dslash(grg_schur S, int prec, int nrhs, int reps)
             if (nrhs % rg && rg != nrhs) continue;
             if (rg > 4 && rg != nrhs) continue;
             for (int split = 0; split < 2; ++split) {
-                const long items = (long)((g.V + sb - 1) / sb) * ((nrhs + rg - 1) / rg);
-                const int caps[3] = {1024, 2048, kMaxGrid};
-                int last = -1;
-                for (int cap : caps) {
-                    DslashTune t;
-                    t.SB = sb;
-                    t.RG = rg;
-                    t.split = split;
-                    t.grid = round8(std::min<long>(items, cap));
-                    if (t.grid == last) continue;
-                    last = t.grid;
-                    t.valid = 1;
-                    cands.push_back(t);
-                }
+                DslashTune t;
+                t.SB = sb;
+                t.RG = rg;
+                t.split = split;
+                t.grid = dslash_grid(g, nrhs, sb, rg);
+                t.valid = 1;
+                timeit(t);
+                cands.push_back(t);
             }
         }
     }
-    hipEvent_t e0, e1;
-    GRG_TRY_HIP(hipEventCreate(&e0));
-    GRG_TRY_HIP(hipEventCreate(&e1));
-    DslashTune best;
-    best.ms = 1e30f;
-    grg_status status = GRG_OK;
-    for (DslashTune &t : cands) {
-        status = launch_tuned(L, prec, t, in, out, S->d_mask, 0, S->m0, nrhs, S->partials);
-        if (status != GRG_OK) break;
-        if (hipEventRecord(e0, st) != hipSuccess) { status = GRG_EHIP; break; }
-        for (int k = 0; k < reps && status == GRG_OK; ++k)
-            status = launch_tuned(L, prec, t, in, out, S->d_mask, 0, S->m0, nrhs, S->partials);
-        if (status != GRG_OK) break;
-        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-            status = GRG_EHIP;
-            break;
+    // t-marching kernel: one workgroup = 64 sites x all RHS, time chunks of T
+    if (64 * nrhs <= (prec == GRG_FP64 ? 512 : 768)) {
+        const int V3 = g.L[0] * g.L[1] * g.L[2];
+        const int nb3 = (V3 + 63) / 64;
+        for (int T = 2; T <= g.L[3]; T *= 2) {
+            DslashTune t;
+            t.march = T;
+            t.SB = 64;
+            t.RG = nrhs;
+            t.split = 0;
+            const long items = (long)nb3 * ((g.L[3] + T - 1) / T);
+            t.grid = round8(std::min<long>(items, 2048));
+            t.valid = 1;
+            timeit(t);
+            cands.push_back(t);
         }
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        t.ms = ms / reps;
-        if (t.ms < best.ms) best = t;
+    }
+    std::sort(cands.begin(), cands.end(), [](const DslashTune &a, const DslashTune &b) { return a.ms < b.ms; });
+    // stage 2: grid size and XCD chunking for the three best shapes
+    DslashTune best = cands.empty() ? default_tune(g, prec, nrhs) : cands[0];
+    for (size_t i = 0; i < std::min<size_t>(3, cands.size()); ++i) {
+        const long items =
+            cands[i].march > 0
+                ? (long)((g.L[0] * g.L[1] * g.L[2] + 63) / 64) * ((g.L[3] + cands[i].march - 1) / cands[i].march)
+                : (long)((g.V + cands[i].SB - 1) / cands[i].SB) * ((nrhs + cands[i].RG - 1) / cands[i].RG);
+        const int caps[3] = {1024, 2048, kMaxGrid};
+        const int chunks[4] = {0, 1, 8, 64};
+        for (int cap : caps) {
+            for (int ch : chunks) {
+                DslashTune t = cands[i];
+                t.grid = round8(std::min<long>(items, cap));
+                t.chunk = ch;
+                if (ch > 0 && ch * 8 >= items) continue;
+                timeit(t);
+                if (t.ms < best.ms) best = t;
+            }
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (status != GRG_OK) return status;
+    best.valid = 1;
     S->tune[prec][nrhs] = best;
     return GRG_OK;
 }
@@ -226,8 +275,9 @@ static grg_status inner_gcr(grg_schur S, int prec, int nrhs, const double *thr, 
     const size_t vstride = spinor_elems(g, nrhs) * prec_bytes(prec);
     const int m = std::max(1, S->prm.restart);
     const int check = std::max(1, S->prm.check_every);
-    const int dgrid = S->tune[prec][nrhs].valid ? S->tune[prec][nrhs].grid
-                                                : default_tune(g, prec, nrhs).grid;
+    const DslashTune &tt = S->tune[prec][nrhs];
+    const int dgrid = tt.valid && !(tt.march > 0 && tt.RG != nrhs) ? tt.grid
+                                                                   : default_tune(g, prec, nrhs).grid;
     void *b = S->in_b[prec], *x = S->in_x[prec], *r = S->in_r[prec], *q = S->in_q[prec];
     char *Pm = (char *)S->in_P[prec], *Qm = (char *)S->in_Q[prec];
 
@@ -290,6 +340,12 @@ static grg_status inner_gcr(grg_schur S, int prec, int nrhs, const double *thr, 
 }
 
 // b64 (internal FP64, zero on coarse sites) -> x64 = D_rr^{-1} b64.
+//
+// Outer loop, FP64 (r_0 = b, x_0 = 0):
+//     e   ~= A^{-1} (r / |r|)                      inner GCR, inner precision
+//     r   <- r - |r| A e,   x <- x + |r| e         one fused FP64 kernel
+// until |r| <= tol |b|; then the residual is recomputed from x as b - A x,
+// and the loop resumes from that true residual if it is still above tol.
 grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
 {
     grg_lattice L = S->lat;
@@ -300,10 +356,8 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
     const BlasShape sh = blas_shape(g, nrhs);
     const size_t vb64 = spinor_elems(g, nrhs) * 16;
     GRG_TRY(ensure_inner(S, prec));
+    double *fr2 = S->bn2 + kMaxRhs;  // device copy of the outer |r|^2
 
-    // x = 0, r = b, |b|^2
-    GRG_TRY_HIP(launch_fill_zero(S->x64, vb64, st));
-    GRG_TRY_HIP(launch_copy(GRG_FP64, sh, S->b64, S->r64, st));
     GRG_TRY_HIP(launch_norm2(GRG_FP64, sh, S->b64, S->partials, st));
     GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->bn2, nullptr, nullptr,
                               st));
@@ -313,9 +367,14 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
     memcpy(bn2, S->h_buf, sizeof(double) * nrhs);
     memcpy(rn2, bn2, sizeof(double) * nrhs);
 
+    const void *r_src = S->b64;  // the residual of the current iterate
+    const void *x_src = nullptr; // the iterate (nullptr: zero)
     int total = 0, outer = 0;
+    bool verified = false;
     grg_status status = GRG_OK;
     double worst = 0;
+    const int dc_sb = 128;
+    const int dc_grid = round8(std::min<long>((g.V + dc_sb - 1) / dc_sb, 2048));
     for (;;) {
         bool conv = true;
         worst = 0;
@@ -328,7 +387,19 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
             worst = std::max(worst, rel);
             if (rel > p.tol) conv = false;
         }
-        if (conv) break;
+        if (conv && (verified || x_src == nullptr)) break;
+        if (conv) {
+            // confirm with the residual recomputed from the iterate
+            GRG_TRY(run_dslash(S, GRG_FP64, S->x64, S->t64, 0, nrhs, nullptr));
+            GRG_TRY_HIP(launch_sub_norm(sh, S->b64, S->t64, S->r64, S->partials, st));
+            GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, nullptr,
+                                      nullptr, st));
+            GRG_TRY(read_norms(S, nrhs, rn2));
+            r_src = S->r64;
+            verified = true;
+            continue;
+        }
+        verified = false;
         if (outer >= p.max_outer || total >= p.max_iter) {
             status = GRG_ENOCONV;
             set_error("D_rr solve: no convergence after %d outer / %d inner iterations "
@@ -346,27 +417,38 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
         memcpy(S->h_buf + 2 * kMaxRhs, thr, sizeof(double) * nrhs);
         GRG_TRY_HIP(hipMemcpyAsync(S->thr2, S->h_buf + 2 * kMaxRhs, sizeof(double) * nrhs,
                                    hipMemcpyHostToDevice, st));
-        // the outer |r|^2 on the device (the inner solve reuses rn2 for its own norms)
         memcpy(S->h_buf + 3 * kMaxRhs, rn2, sizeof(double) * nrhs);
-        GRG_TRY_HIP(hipMemcpyAsync(S->bn2 + kMaxRhs, S->h_buf + 3 * kMaxRhs,
-                                   sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
-        // r_in = r / |r|
-        GRG_TRY_HIP(launch_axpy_convert(GRG_FP64, prec, sh, S->r64, S->in_b[prec],
-                                        S->bn2 + kMaxRhs, 1, 0, nullptr, st));
+        GRG_TRY_HIP(hipMemcpyAsync(fr2, S->h_buf + 3 * kMaxRhs, sizeof(double) * nrhs,
+                                   hipMemcpyHostToDevice, st));
+        // inner right-hand side r / |r| in the inner precision
+        GRG_TRY_HIP(launch_axpy_convert(GRG_FP64, prec, sh, r_src, S->in_b[prec], fr2, 1, 0,
+                                        nullptr, st));
         int it = 0;
         GRG_TRY(inner_gcr(S, prec, nrhs, thr, p.max_iter - total, &it));
         total += it;
         ++outer;
-        // x += |r| e
-        GRG_TRY_HIP(launch_axpy_convert(prec, GRG_FP64, sh, S->in_x[prec], S->x64,
-                                        S->bn2 + kMaxRhs, 2, 1, nullptr, st));
-        // r = b - D_rr x in FP64
-        GRG_TRY(run_dslash(S, GRG_FP64, S->x64, S->t64, 0, nrhs, nullptr));
-        GRG_TRY_HIP(launch_sub_norm(sh, S->b64, S->t64, S->r64, S->partials, st));
-        GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, nullptr,
+        // r -= |r| A e ; x += |r| e   (FP64, fused)
+        DcArgs d;
+        d.e = S->in_x[prec];
+        d.U = L->U[GRG_FP64];
+        d.r_in = r_src;
+        d.x_in = x_src;
+        d.r_out = S->r64;
+        d.x_out = S->x64;
+        d.fr2 = fr2;
+        d.mask = S->d_mask;
+        d.diag = 4.0 + S->m0;
+        d.g = g;
+        d.nrhs = nrhs;
+        d.partials = S->partials;
+        GRG_TRY_HIP(launch_dc_update(prec, d, dc_grid, dc_sb, st));
+        GRG_TRY_HIP(launch_reduce(kNorm, S->partials, dc_grid, nrhs, nullptr, S->rn2, nullptr,
                                   nullptr, st));
         GRG_TRY(read_norms(S, nrhs, rn2));
+        r_src = S->r64;
+        x_src = S->x64;
     }
+    if (x_src == nullptr) GRG_TRY_HIP(launch_fill_zero(S->x64, vb64, st));
     if (stats) {
         stats->iters = total;
         stats->outer = outer;
@@ -374,6 +456,22 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
         stats->true_rel_resid = worst;
     }
     return status;
+}
+
+// out = D_{rows, cols} in on canonical lattice fields, in precision prec, with
+// the handle's launch for (prec, nrhs).  rows / cols: 1 coarse sites, 0 the
+// rest, -1 every site.
+grg_status block_apply_internal(grg_schur S, int prec, int rows, int cols, const double *in,
+                                double *out, int nrhs)
+{
+    grg_lattice L = S->lat;
+    GRG_TRY(ensure_inner(S, prec));
+    void *a = S->in_b[prec], *b = S->in_q[prec];
+    GRG_TRY_HIP(launch_pack_spinor(prec, in, a, L->g, nrhs, L->stream, cols < 0 ? nullptr : S->d_mask,
+                                   cols));
+    GRG_TRY(run_dslash(S, prec, a, b, rows, nrhs, nullptr));
+    GRG_TRY_HIP(launch_unpack_spinor(prec, b, out, L->g, nrhs, L->stream));
+    return GRG_OK;
 }
 
 // x_b (canonical coarse, device) -> y_b

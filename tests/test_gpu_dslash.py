@@ -78,3 +78,28 @@ def test_dirac_apply_rejects_bad_arguments():
     with pytest.raises(grg.GrgError):
         grg.grg_dirac_apply(lat.h, 0.1, 7, x, x, 1)
     lat.close()
+
+
+def bf16_rne(v):
+    """float64 -> float32 -> bfloat16 (round to nearest, ties to even) -> float64."""
+    a = np.asarray(v, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    a = (a + 0x7FFF + ((a >> 16) & 1)) >> 16
+    return (a.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def test_bf16_storage_rounds_to_nearest_even():
+    """With m0 = -3 the diagonal is 1; on a site whose neighbours are zero the
+    output is the input rounded to bfloat16 (round to nearest, ties to even)."""
+    dims = (4, 4, 4, 4)
+    lat = Lattice(dims, 0.5, 1)
+    v = np.array([1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -9, -(1 + 2 ** -8), 1.5 + 2 ** -8,
+                  1 + 2 ** -8 + 2 ** -12, 3.0, 1 - 2 ** -9 - 2 ** -10, 0.1, -7.25, 1e30, 2.0 ** -100])
+    want = bf16_rne(v)
+    # spot values fixed by hand: ties go to the even neighbour
+    assert want[0] == 1.0 and want[1] == 1 + 2 ** -6 and want[4] == 1.5 and want[5] == 1 + 2 ** -7
+    x = np.zeros((1, 12 * lat.V), np.complex128)
+    dof = 12 * (5 + 2 * 64)
+    x[0, dof:dof + 12] = v + 1j * v[::-1]
+    got = gpu_apply(lat, -3.0, "bf16", x)
+    assert np.array_equal(got[0, dof:dof + 12], want + 1j * want[::-1])
+    lat.close()
