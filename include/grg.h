@@ -67,6 +67,7 @@ typedef enum { GRG_FP64 = 0, GRG_FP32 = 1, GRG_BF16 = 2 } grg_precision;
 
 typedef struct grg_lattice_s *grg_lattice;
 typedef struct grg_schur_s *grg_schur;
+typedef struct grg_precond_s *grg_precond;
 
 /* Parameters of the D_rr solve.  Restarted GCR(restart) with the residual
  * carried through restarts (restart = 1 is minimal residual).  With
@@ -92,7 +93,26 @@ typedef struct {
     double true_rel_resid; /* max over RHS of the FP64 ||b - D_rr x|| / ||b|| */
     double t_total_ms;     /* wall time of the call on the stream */
     double t_dslash_ms;    /* summed dslash time (only with profiling on) */
+    int fallbacks;         /* inner solves redone without the preconditioner */
 } grg_solver_stats;
+
+/* Training of the learned preconditioner (see grg_precond_train). */
+typedef struct {
+    int steps;          /* optimiser steps */
+    int batch;          /* residual/error pairs per step (<= the schur's max_rhs) */
+    int max_mr_steps;   /* pairs come from 0..max_mr_steps minimal-residual steps */
+    double lr;          /* Adam learning rate (beta1 0.9, beta2 0.999, eps 1e-8) */
+    uint64_t seed;      /* seeds the random errors and the step counts */
+    int log_every;      /* loss read back every log_every steps (0: first/last only) */
+} grg_train_params;
+
+typedef struct {
+    int steps;
+    int pairs;          /* residual/error pairs consumed */
+    double loss_first;  /* loss of the first minibatch */
+    double loss_last;   /* mean loss of the last log_every minibatches */
+    double t_ms;
+} grg_train_stats;
 
 /* Thread-local message of the last failure; never NULL. */
 const char *grg_last_error(void);
@@ -181,6 +201,51 @@ grg_status grg_schur_set_launch(grg_schur s, int precision, int nrhs, const int3
  * inverts; D_rb, D_br and D_bb enter S_bb. */
 grg_status grg_block_apply(grg_schur s, int precision, int rows, int cols, const double *in,
                            double *out, int nrhs);
+
+/* ---------------------------------------------------------------------------
+ * Learned preconditioner.  M is a linear, gauge-covariant network of three
+ * parallel-transport convolutions with 4 -> 8 -> 8 -> 4 colour-vector channels
+ * (12 -> 24 -> 24 -> 12 complex per site; the spin index of a Dirac field is
+ * the channel):  Y_f(x) = sum_h sum_f' W_h[f, f'] (T_h X_f')(x) over the hops
+ * h = 0, +x, -x, +y, -y, +z, -z, +t, -t, with T_0 = 1,
+ * T_{+mu} X(x) = U_mu(x) X(x + mu), T_{-mu} X(x) = U_mu(x - mu)^+ X(x - mu).
+ * No bias, no activation.  Weights are complex, 9 * (32 + 64 + 32) = 1152 of
+ * them, stored layer by layer as [hop][f_out][f_in] (interleaved re, im
+ * doubles).  Activations and weights enter the matrix cores as bfloat16 with
+ * FP32 accumulation.  Inputs are read on the rest sites only and outputs are
+ * zero on the coarse sites, so M approximates D_rr^{-1}.
+ * ------------------------------------------------------------------------- */
+#define GRG_PRECOND_WEIGHTS 1152
+
+/* A network bound to s (its lattice, links and coarse sites), workspaces for
+ * s's max_rhs, weights zero except W_0 of every layer = identity on the
+ * first channels (so M starts as the identity on Dirac fields). */
+grg_status grg_precond_create(grg_schur s, grg_precond *out);
+grg_status grg_precond_destroy(grg_precond p);
+/* Host arrays of GRG_PRECOND_WEIGHTS complex (2 doubles each). */
+grg_status grg_precond_set_weights(grg_precond p, const double *w);
+grg_status grg_precond_get_weights(grg_precond p, double *w);
+/* out = M in for nrhs canonical lattice fields (device). */
+grg_status grg_precond_apply(grg_precond p, const double *in, double *out, int nrhs);
+/* Loss L = (1/B) sum_i |M r_i - e_i|^2 / |e_i|^2 over nrhs = B pairs of
+ * canonical lattice fields (device) and its Wirtinger gradient dL/dconj(W)
+ * (host, GRG_PRECOND_WEIGHTS complex; the gradient of the real and imaginary
+ * parts is twice its real and imaginary parts). */
+grg_status grg_precond_loss_grad(grg_precond p, const double *r, const double *e, int nrhs,
+                                 double *loss, double *grad);
+/* Train on the GPU: each step draws `batch` random errors e_0 on the rest
+ * sites, runs k minimal-residual steps of the solver on D_rr x = D_rr e_0
+ * (k uniform in 0..max_mr_steps), takes the pairs (r_k, e_k = e_0 - x_k) the
+ * solver produced, and applies one Adam step to the loss above. */
+grg_status grg_precond_train(grg_precond p, const grg_train_params *tp, grg_train_stats *st);
+/* Versioned binary weight file (magic, version, channel shape, seed, steps). */
+grg_status grg_precond_save(grg_precond p, const char *path);
+grg_status grg_precond_load(grg_precond p, const char *path);
+/* Use p as the right preconditioner of s's inner GCR (NULL detaches).  An
+ * inner solve that fails to converge or meets a non-finite value with the
+ * preconditioner is redone with plain GCR, which also judges the result
+ * through the FP64 residual of the defect correction. */
+grg_status grg_schur_attach_precond(grg_schur s, grg_precond p);
 
 /* Kernel timing: with profiling on, every dslash launch is bracketed by HIP
  * events on the lattice stream; grg_profile_read returns the count and the

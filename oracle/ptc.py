@@ -104,17 +104,24 @@ def net_forward(x, ws, links, dims, bc=(1, 1, 1, -1)):
     return acts
 
 
-def loss_and_grads(rs, es, ws, links, dims, bc=(1, 1, 1, -1)):
-    """Loss over a batch and dL/d conj(W) per layer.  rs, es: (B, V, 4, 3)."""
+def loss_and_grads(rs, es, ws, links, dims, bc=(1, 1, 1, -1), out_mask=None):
+    """Loss over a batch and dL/d conj(W) per layer.  rs, es: (B, V, 4, 3).
+    out_mask (V,) of 0/1, if given, multiplies the network output (the
+    preconditioner's output lives on the rest sites only)."""
     B = len(rs)
     loss = 0.0
     grads = [np.zeros_like(w) for w in ws]
+    m = None if out_mask is None else np.asarray(out_mask, float)[:, None, None]
     for r, e in zip(rs, es):
         acts = net_forward(r, ws, links, dims, bc)
+        if m is not None:
+            acts[-1] = acts[-1] * m
         en = np.vdot(e, e).real
         d = acts[-1] - e
         loss += np.vdot(d, d).real / en / B
         dy = d / en / B  # dL/d conj(Y)
+        if m is not None:
+            dy = dy * m
         for l in range(len(ws) - 1, -1, -1):
             grads[l] += layer_weight_grad(dy, acts[l], links, dims, bc)
             dy = layer_adjoint(dy, ws[l], links, dims, bc)

@@ -39,7 +39,10 @@ EXPORTS = (
     "grg_lattice_destroy", "grg_lattice_volume", "grg_gauge_set", "grg_permutation_block",
     "grg_dirac_apply", "grg_schur_create", "grg_schur_destroy", "grg_schur_set_params",
     "grg_drr_solve", "grg_schur_apply", "grg_schur_assemble", "grg_schur_tune",
-    "grg_schur_tune_info", "grg_schur_set_launch", "grg_block_apply", "grg_profile_enable",
+    "grg_schur_tune_info", "grg_schur_set_launch", "grg_block_apply", "grg_precond_create",
+    "grg_precond_destroy", "grg_precond_set_weights", "grg_precond_get_weights", "grg_precond_apply",
+    "grg_precond_loss_grad", "grg_precond_train", "grg_precond_save", "grg_precond_load",
+    "grg_schur_attach_precond", "grg_profile_enable",
     "grg_profile_read", "grg_profile_reset",
 )
 
@@ -62,11 +65,27 @@ class grg_solver_stats(C.Structure):
     _fields_ = [
         ("iters", C.c_int), ("outer", C.c_int), ("converged", C.c_int), ("n_dslash", C.c_int),
         ("true_rel_resid", C.c_double), ("t_total_ms", C.c_double), ("t_dslash_ms", C.c_double),
+        ("fallbacks", C.c_int),
     ]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
+
+class grg_train_params(C.Structure):
+    _fields_ = [("steps", C.c_int), ("batch", C.c_int), ("max_mr_steps", C.c_int),
+                ("lr", C.c_double), ("seed", C.c_uint64), ("log_every", C.c_int)]
+
+
+class grg_train_stats(C.Structure):
+    _fields_ = [("steps", C.c_int), ("pairs", C.c_int), ("loss_first", C.c_double),
+                ("loss_last", C.c_double), ("t_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+GRG_PRECOND_WEIGHTS = 1152
 
 _lib = None
 
@@ -108,6 +127,16 @@ def load():
         "grg_schur_tune_info": (C.c_int, [vp, C.c_int, C.c_int, i32p, C.POINTER(C.c_float)]),
         "grg_schur_set_launch": (C.c_int, [vp, C.c_int, C.c_int, i32p]),
         "grg_block_apply": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, vp, C.c_int]),
+        "grg_precond_create": (C.c_int, [vp, C.POINTER(vp)]),
+        "grg_precond_destroy": (C.c_int, [vp]),
+        "grg_precond_set_weights": (C.c_int, [vp, vp]),
+        "grg_precond_get_weights": (C.c_int, [vp, vp]),
+        "grg_precond_apply": (C.c_int, [vp, vp, vp, C.c_int]),
+        "grg_precond_loss_grad": (C.c_int, [vp, vp, vp, C.c_int, C.POINTER(C.c_double), vp]),
+        "grg_precond_train": (C.c_int, [vp, C.POINTER(grg_train_params), C.POINTER(grg_train_stats)]),
+        "grg_precond_save": (C.c_int, [vp, C.c_char_p]),
+        "grg_precond_load": (C.c_int, [vp, C.c_char_p]),
+        "grg_schur_attach_precond": (C.c_int, [vp, vp]),
         "grg_profile_enable": (C.c_int, [vp, C.c_int]),
         "grg_profile_read": (C.c_int, [vp, C.c_int, i64p, dp]),
         "grg_profile_reset": (C.c_int, [vp]),
@@ -276,6 +305,62 @@ def grg_block_apply(s, precision, rows, cols, x, out, nrhs):
     """out = D_{rows, cols} x; rows / cols: 1 coarse, 0 rest, -1 all."""
     _check(load().grg_block_apply(s, _prec(precision), int(rows), int(cols), _ptr(x), _ptr(out),
                                   int(nrhs)))
+
+
+def grg_precond_create(s):
+    h = C.c_void_p()
+    _check(load().grg_precond_create(s, C.byref(h)))
+    return h
+
+
+def grg_precond_destroy(p):
+    _check(load().grg_precond_destroy(p))
+
+
+def grg_precond_set_weights(p, w):
+    """w: complex128 array of GRG_PRECOND_WEIGHTS (layer-major, [hop][f_out][f_in])."""
+    a = np.ascontiguousarray(w, dtype=np.complex128)
+    assert a.size == GRG_PRECOND_WEIGHTS
+    _check(load().grg_precond_set_weights(p, C.c_void_p(a.ctypes.data)))
+
+
+def grg_precond_get_weights(p):
+    a = np.zeros(GRG_PRECOND_WEIGHTS, dtype=np.complex128)
+    _check(load().grg_precond_get_weights(p, C.c_void_p(a.ctypes.data)))
+    return a
+
+
+def grg_precond_apply(p, x, out, nrhs):
+    _check(load().grg_precond_apply(p, _ptr(x), _ptr(out), int(nrhs)))
+
+
+def grg_precond_loss_grad(p, r, e, nrhs):
+    """(loss, dL/dconj(W) as complex128 array)."""
+    loss = C.c_double()
+    g = np.zeros(GRG_PRECOND_WEIGHTS, dtype=np.complex128)
+    _check(load().grg_precond_loss_grad(p, _ptr(r), _ptr(e), int(nrhs), C.byref(loss),
+                                        C.c_void_p(g.ctypes.data)))
+    return loss.value, g
+
+
+def grg_precond_train(p, steps, batch, max_mr_steps=20, lr=1e-3, seed=5, log_every=20):
+    tp = grg_train_params(int(steps), int(batch), int(max_mr_steps), float(lr), int(seed),
+                          int(log_every))
+    st = grg_train_stats()
+    _check(load().grg_precond_train(p, C.byref(tp), C.byref(st)))
+    return st.as_dict()
+
+
+def grg_precond_save(p, path):
+    _check(load().grg_precond_save(p, os.fsencode(path)))
+
+
+def grg_precond_load(p, path):
+    _check(load().grg_precond_load(p, os.fsencode(path)))
+
+
+def grg_schur_attach_precond(s, p):
+    _check(load().grg_schur_attach_precond(s, p))
 
 
 def grg_profile_enable(s, on=True):

@@ -29,7 +29,7 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats);
 grg_status schur_apply_internal(grg_schur S, const double *xb, double *yb, int nrhs,
                                 grg_solver_stats *stats);
 grg_status run_dslash(grg_schur S, int prec, const void *in, void *out, int sel, int nrhs,
-                      double *partials);
+                      double *partials, const void *dot_with = nullptr);
 int partial_rows(const Geom &g, int nrhs);
 int dslash_grid(const Geom &g, int nrhs, int SB, int RG);
 DslashTune default_tune(const Geom &g, int prec, int nrhs);
@@ -284,6 +284,7 @@ grg_status grg_dirac_apply(grg_lattice L, double m0, int precision, const double
     a.chunk = t.chunk;
     a.march = t.march;
     a.partials = nullptr;
+    a.dot_with = nullptr;
     GRG_TRY_HIP(launch_dslash(precision, a, t.grid, L->stream));
     GRG_TRY_HIP(launch_unpack_spinor(precision, L->tmp_out, out, L->g, nrhs, L->stream));
     GRG_TRY_HIP(hipStreamSynchronize(L->stream));
@@ -405,6 +406,7 @@ grg_status grg_schur_destroy(grg_schur S)
     if (!S) return GRG_OK;
     DeviceGuard dg(S->lat->device);
     hipStreamSynchronize(S->lat->stream);
+    if (S->precond) S->precond->schur = nullptr;
     schur_free(S);
     delete S;
     return GRG_OK;
@@ -474,6 +476,7 @@ grg_status grg_drr_solve(grg_schur S, const double *rhs, double *x, int nrhs, gr
     double before = 0;
     for (int p = 0; p < 3; ++p) before += S->prof.total_ms[p];
     S->n_dslash = 0;
+    S->fallbacks = 0;
     grg_lattice L = S->lat;
     GRG_TRY_HIP(launch_pack_masked(rhs, S->b64, S->d_mask, 0, L->g, nrhs, L->stream));
     grg_status st = drr_solve_internal(S, nrhs, stats);
@@ -492,6 +495,7 @@ grg_status grg_schur_apply(grg_schur S, const double *x_b, double *y_b, int nrhs
     double before = 0;
     for (int p = 0; p < 3; ++p) before += S->prof.total_ms[p];
     S->n_dslash = 0;
+    S->fallbacks = 0;
     grg_status st = schur_apply_internal(S, x_b, y_b, nrhs, stats);
     return finish_call(S, st, t0, stats, before);
 }

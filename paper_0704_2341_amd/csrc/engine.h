@@ -49,6 +49,7 @@ struct DslashArgs {
     int march;            // > 0: t-marching kernel with time chunks of this length
                           //      (64 sites x RG RHS wavefronts per workgroup)
     double *partials;     // [grid][nrhs][3] or nullptr
+    const void *dot_with; // the fused dots use this field instead of `in` (or nullptr)
 };
 
 // A tuned launch of the stencil for one precision and RHS count.

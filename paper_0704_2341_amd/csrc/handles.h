@@ -31,6 +31,27 @@ struct ProfilePool {
 
 }  // namespace grg
 
+// Learned preconditioner: three layer network, weights on the device.
+struct grg_precond_s {
+    grg_schur schur = nullptr;      // lattice, links and coarse mask it is bound to
+    int max_rhs = 0;
+    double2 *w = nullptr;           // master weights, kPtcWeights complex (FP64)
+    double2 *grad = nullptr;        // dL/dconj(W)
+    double *adam_m = nullptr, *adam_v = nullptr;
+    int adam_step = 0;
+    __bf16 *A[3] = {nullptr, nullptr, nullptr};     // forward layers, [16][KP]
+    __bf16 *Aadj[3] = {nullptr, nullptr, nullptr};  // adjoint layers
+    void *act[4] = {nullptr, nullptr, nullptr, nullptr};  // bf16 activations
+    void *dact[4] = {nullptr, nullptr, nullptr, nullptr}; // their gradients
+    void *ebuf = nullptr;           // training targets (bf16 Dirac field)
+    void *gen[3] = {nullptr, nullptr, nullptr};  // pair generation: x, r, q (bf16)
+    float *wpart = nullptr;         // weight-gradient partials
+    double *lpart = nullptr, *lsums = nullptr, *loss = nullptr;
+    double *neg_one = nullptr;      // -1 per RHS (e = e_0 - x)
+    double *h_buf = nullptr;        // pinned host staging
+    bool weights_finite = true;
+};
+
 struct grg_schur_s {
     grg_lattice lat;
     double m0;
@@ -64,4 +85,6 @@ struct grg_schur_s {
     grg::ProfilePool prof;
     int n_dslash = 0;
     grg::DslashTune tune[3][grg::kMaxRhs + 1];  // per precision and nrhs
+    grg_precond precond = nullptr;  // right preconditioner of the inner GCR, or none
+    int fallbacks = 0;              // inner solves redone without the preconditioner
 };

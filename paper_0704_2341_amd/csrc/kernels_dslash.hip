@@ -244,9 +244,10 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
                 // sites and workgroups in FP64
                 R sre = 0, sim = 0, sqq = 0;
                 if (on) {
+                    const S *dw = a.dot_with ? (const S *)a.dot_with : in;
 #pragma unroll
                     for (int c = 0; c < 12; ++c) {
-                        const cpx<R> v = ldc(in, fidx(s, r, c, a.nrhs));
+                        const cpx<R> v = ldc(dw, fidx(s, r, c, a.nrhs));
                         sre = fma(acc[c].re, v.re, fma(acc[c].im, v.im, sre));
                         sim = fma(acc[c].re, v.im, fma(-acc[c].im, v.re, sim));
                         sqq = fma(acc[c].re, acc[c].re, fma(acc[c].im, acc[c].im, sqq));
@@ -293,7 +294,7 @@ __device__ __forceinline__ void march_store(DslashArgs &a, cpx<typename Store<P>
     const bool on = valid && (a.mask == nullptr || a.mask[s] == a.sel);
     if (!valid) return;
     S *out = (S *)a.out;
-    const S *in = (const S *)a.in;
+    const S *in = (const S *)(a.dot_with ? a.dot_with : a.in);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
         const size_t i = fidx(s, r, c, a.nrhs);

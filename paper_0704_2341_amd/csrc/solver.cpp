@@ -60,9 +60,10 @@ DslashTune default_tune(const Geom &g, int prec, int nrhs)
 
 static grg_status launch_tuned(grg_lattice L, int prec, const DslashTune &t, const void *in,
                                void *out, const uint8_t *mask, int sel, double m0, int nrhs,
-                               double *partials)
+                               double *partials, const void *dot_with = nullptr)
 {
     DslashArgs a;
+    a.dot_with = dot_with;
     a.in = in;
     a.out = out;
     a.U = L->U[prec];
@@ -96,7 +97,7 @@ bool launch_ok(const Geom &g, int prec, int nrhs, const DslashTune &t, bool dots
 
 // One stencil launch, bracketed by profiling events when enabled.
 grg_status run_dslash(grg_schur S, int prec, const void *in, void *out, int sel, int nrhs,
-                      double *partials)
+                      double *partials, const void *dot_with = nullptr)
 {
     grg_lattice L = S->lat;
     DslashTune t = S->tune[prec][nrhs].valid ? S->tune[prec][nrhs] : default_tune(L->g, prec, nrhs);
@@ -106,7 +107,7 @@ grg_status run_dslash(grg_schur S, int prec, const void *in, void *out, int sel,
     const bool ev = P.on && P.used < (int)P.start.size();
     if (ev) GRG_TRY_HIP(hipEventRecord(P.start[P.used], L->stream));
     GRG_TRY(launch_tuned(L, prec, t, in, out, sel < 0 ? nullptr : S->d_mask, sel < 0 ? 0 : sel,
-                         S->m0, nrhs, partials));
+                         S->m0, nrhs, partials, dot_with));
     if (ev) {
         GRG_TRY_HIP(hipEventRecord(P.stop[P.used], L->stream));
         P.prec[P.used] = prec;
@@ -117,6 +118,7 @@ grg_status run_dslash(grg_schur S, int prec, const void *in, void *out, int sel,
 }
 
 grg_status ensure_inner(grg_schur S, int prec);
+grg_status precond_apply_inner(grg_schur S, int prec, const void *r, void *p, int nrhs);
 
 // Largest grid any stencil or BLAS launch may use (sizes the partial sums).
 constexpr int kMaxGrid = kMaxGridValue;
@@ -244,18 +246,19 @@ grg_status ensure_inner(grg_schur S, int prec)
         }
         GRG_TRY_HIP(launch_fill_zero(*b, bytes, S->lat->stream));
     }
-    if (m > 1 && S->in_m[prec] < m) {
+    const int need_m = (m > 1 || S->precond) ? m : 0;  // search directions kept
+    if (need_m > 0 && S->in_m[prec] < need_m) {
         if (S->in_P[prec]) (void)hipFree(S->in_P[prec]);
         if (S->in_Q[prec]) (void)hipFree(S->in_Q[prec]);
         S->in_P[prec] = S->in_Q[prec] = nullptr;
-        if (hipMalloc(&S->in_P[prec], bytes * m) != hipSuccess ||
-            hipMalloc(&S->in_Q[prec], bytes * m) != hipSuccess) {
-            set_error("GCR(%d) basis: hipMalloc of 2 x %zu bytes failed", m, bytes * m);
+        if (hipMalloc(&S->in_P[prec], bytes * need_m) != hipSuccess ||
+            hipMalloc(&S->in_Q[prec], bytes * need_m) != hipSuccess) {
+            set_error("GCR(%d) basis: hipMalloc of 2 x %zu bytes failed", m, bytes * need_m);
             return GRG_ENOMEM;
         }
-        GRG_TRY_HIP(launch_fill_zero(S->in_P[prec], bytes * m, S->lat->stream));
-        GRG_TRY_HIP(launch_fill_zero(S->in_Q[prec], bytes * m, S->lat->stream));
-        S->in_m[prec] = m;
+        GRG_TRY_HIP(launch_fill_zero(S->in_P[prec], bytes * need_m, S->lat->stream));
+        GRG_TRY_HIP(launch_fill_zero(S->in_Q[prec], bytes * need_m, S->lat->stream));
+        S->in_m[prec] = need_m;
     }
     return GRG_OK;
 }
@@ -299,16 +302,17 @@ static grg_status inner_gcr(grg_schur S, int prec, int nrhs, const double *thr, 
     int done = all_done(h);
     while (done == 0 && it < maxit) {
         const int k = it % m;
-        if (m == 1) {
+        if (m == 1 && !S->precond) {
             GRG_TRY(run_dslash(S, prec, r, q, 0, nrhs, S->partials));
             GRG_TRY_HIP(launch_reduce(kAlpha, S->partials, dgrid, nrhs, S->alpha, nullptr, nullptr,
                                       S->active, st));
             GRG_TRY_HIP(launch_mr_update(prec, sh, x, r, q, nullptr, S->alpha, S->partials, st));
         } else {
             void *pk = Pm + (size_t)k * vstride, *qk = Qm + (size_t)k * vstride;
-            GRG_TRY_HIP(launch_copy(prec, sh, r, pk, st));
+            if (S->precond) GRG_TRY(precond_apply_inner(S, prec, r, pk, nrhs));  // p = M r
+            else GRG_TRY_HIP(launch_copy(prec, sh, r, pk, st));
             if (k == 0) {
-                GRG_TRY(run_dslash(S, prec, pk, qk, 0, nrhs, S->partials));
+                GRG_TRY(run_dslash(S, prec, pk, qk, 0, nrhs, S->partials, r));
                 GRG_TRY_HIP(launch_reduce(kAlpha, S->partials, dgrid, nrhs, S->alpha, S->qn2,
                                           nullptr, S->active, st));
             } else {
@@ -336,6 +340,20 @@ static grg_status inner_gcr(grg_schur S, int prec, int nrhs, const double *thr, 
         set_error("non-finite residual in the inner solve");
         return GRG_ENONFINITE;
     }
+    return done ? GRG_OK : GRG_ENOCONV;
+}
+
+// Inner iterations allowed to a preconditioned inner solve before the plain
+// GCR fallback takes over.
+constexpr int kPrecondInnerCap = 100;
+
+// the inner right-hand side r / |r| again (the failed attempt overwrote nothing
+// of it, but keep the restart explicit)
+static grg_status launch_axpy_convert_guard(grg_schur S, int prec, const BlasShape &sh,
+                                            const void *r_src, const double *fr2)
+{
+    GRG_TRY_HIP(launch_axpy_convert(GRG_FP64, prec, sh, r_src, S->in_b[prec], fr2, 1, 0, nullptr,
+                                    S->lat->stream));
     return GRG_OK;
 }
 
@@ -424,8 +442,25 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
         GRG_TRY_HIP(launch_axpy_convert(GRG_FP64, prec, sh, r_src, S->in_b[prec], fr2, 1, 0,
                                         nullptr, st));
         int it = 0;
-        GRG_TRY(inner_gcr(S, prec, nrhs, thr, p.max_iter - total, &it));
-        total += it;
+        grg_status is;
+        if (S->precond) {
+            // preconditioned inner solve, with plain GCR as the fallback
+            is = inner_gcr(S, prec, nrhs, thr, std::min(p.max_iter - total, kPrecondInnerCap), &it);
+            total += it;
+            if (is != GRG_OK) {
+                grg_precond keep = S->precond;
+                S->precond = nullptr;
+                ++S->fallbacks;
+                GRG_TRY(launch_axpy_convert_guard(S, prec, sh, r_src, fr2));
+                is = inner_gcr(S, prec, nrhs, thr, p.max_iter - total, &it);
+                S->precond = keep;
+                total += it;
+            }
+        } else {
+            is = inner_gcr(S, prec, nrhs, thr, p.max_iter - total, &it);
+            total += it;
+        }
+        if (is != GRG_OK && is != GRG_ENOCONV) return is;
         ++outer;
         // r -= |r| A e ; x += |r| e   (FP64, fused)
         DcArgs d;
@@ -450,6 +485,7 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
     }
     if (x_src == nullptr) GRG_TRY_HIP(launch_fill_zero(S->x64, vb64, st));
     if (stats) {
+        stats->fallbacks = S->fallbacks;
         stats->iters = total;
         stats->outer = outer;
         stats->converged = status == GRG_OK;
