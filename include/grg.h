@@ -247,6 +247,42 @@ grg_status grg_precond_load(grg_precond p, const char *path);
  * through the FP64 residual of the defect correction. */
 grg_status grg_schur_attach_precond(grg_schur s, grg_precond p);
 
+/* ---------------------------------------------------------------------------
+ * Many independent lattices at once.  The members (each with its own extents,
+ * boundary signs, m0, links and ordering) are concatenated in one site index
+ * and every kernel covers all of them in one launch; the inner iterations are
+ * replayed from a HIP graph (captured on the batch's own stream), with
+ * per-(member, RHS) step lengths and convergence flags.  Each member's volume
+ * must be a multiple of 256 sites.
+ * ------------------------------------------------------------------------- */
+typedef struct grg_batch_s *grg_batch;
+
+typedef struct {
+    int32_t dims[4];
+    int32_t bc[4];
+    double m0;
+    const double *links;  /* host, canonical [V][4][3][3] complex128 */
+    const int32_t *q;     /* host ordering (V entries), coarse sites first */
+    int32_t n_coarse;
+} grg_batch_member;
+
+/* params->inner / inner_tol / tol / max_iter / max_outer as for one lattice;
+ * check_every = inner iterations per graph replay.  stream: the caller's
+ * stream, waited on at entry and made to wait for the result at exit. */
+grg_status grg_batch_create(const grg_batch_member *members, int count, int nrhs,
+                            const grg_solver_params *params, void *stream, grg_batch *out);
+grg_status grg_batch_destroy(grg_batch b);
+/* Coarse vectors of the whole batch are one device array: member i's block
+ * [nrhs][12 N_b(i)] complex128 starts at complex offset *offset; member ==
+ * count gives the total length and total N_b. */
+grg_status grg_batch_layout(grg_batch b, int member, int64_t *offset, int32_t *n_coarse);
+/* y_b = S_bb x_b for every member and RHS.  use_graph = 0 launches the same
+ * kernels eagerly (for checking the graph). */
+grg_status grg_batch_apply(grg_batch b, const double *x_b, double *y_b, int use_graph,
+                           grg_solver_stats *stats);
+/* Time the batched stencil launch shapes and keep the fastest. */
+grg_status grg_batch_tune(grg_batch b);
+
 /* Kernel timing: with profiling on, every dslash launch is bracketed by HIP
  * events on the lattice stream; grg_profile_read returns the count and the
  * summed milliseconds since the last reset, per dslash precision. */

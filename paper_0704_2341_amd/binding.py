@@ -42,7 +42,8 @@ EXPORTS = (
     "grg_schur_tune_info", "grg_schur_set_launch", "grg_block_apply", "grg_precond_create",
     "grg_precond_destroy", "grg_precond_set_weights", "grg_precond_get_weights", "grg_precond_apply",
     "grg_precond_loss_grad", "grg_precond_train", "grg_precond_save", "grg_precond_load",
-    "grg_schur_attach_precond", "grg_profile_enable",
+    "grg_schur_attach_precond", "grg_batch_create", "grg_batch_destroy", "grg_batch_layout",
+    "grg_batch_apply", "grg_batch_tune", "grg_profile_enable",
     "grg_profile_read", "grg_profile_reset",
 )
 
@@ -86,6 +87,11 @@ class grg_train_stats(C.Structure):
 
 
 GRG_PRECOND_WEIGHTS = 1152
+
+
+class grg_batch_member(C.Structure):
+    _fields_ = [("dims", C.c_int32 * 4), ("bc", C.c_int32 * 4), ("m0", C.c_double),
+                ("links", C.c_void_p), ("q", C.c_void_p), ("n_coarse", C.c_int32)]
 
 _lib = None
 
@@ -137,6 +143,12 @@ def load():
         "grg_precond_save": (C.c_int, [vp, C.c_char_p]),
         "grg_precond_load": (C.c_int, [vp, C.c_char_p]),
         "grg_schur_attach_precond": (C.c_int, [vp, vp]),
+        "grg_batch_create": (C.c_int, [C.POINTER(grg_batch_member), C.c_int, C.c_int,
+                                       C.POINTER(grg_solver_params), vp, C.POINTER(vp)]),
+        "grg_batch_destroy": (C.c_int, [vp]),
+        "grg_batch_layout": (C.c_int, [vp, C.c_int, i64p, i32p]),
+        "grg_batch_apply": (C.c_int, [vp, vp, vp, C.c_int, C.POINTER(grg_solver_stats)]),
+        "grg_batch_tune": (C.c_int, [vp]),
         "grg_profile_enable": (C.c_int, [vp, C.c_int]),
         "grg_profile_read": (C.c_int, [vp, C.c_int, i64p, dp]),
         "grg_profile_reset": (C.c_int, [vp]),
@@ -361,6 +373,50 @@ def grg_precond_load(p, path):
 
 def grg_schur_attach_precond(s, p):
     _check(load().grg_schur_attach_precond(s, p))
+
+
+def grg_batch_create(members, nrhs, params=None, stream=None):
+    """members: list of dicts with dims, bc, m0, links (complex128 numpy
+    (V, 4, 3, 3)), q (int array), n_coarse.  Returns (handle, keepalive)."""
+    arr = (grg_batch_member * len(members))()
+    keep = []
+    for i, m in enumerate(members):
+        links = np.ascontiguousarray(m["links"], dtype=np.complex128)
+        q = np.ascontiguousarray(m["q"], dtype=np.int32)
+        keep += [links, q]
+        arr[i].dims[:] = [int(d) for d in m["dims"]]
+        arr[i].bc[:] = [int(b) for b in m.get("bc", (1, 1, 1, -1))]
+        arr[i].m0 = float(m["m0"])
+        arr[i].links = links.ctypes.data
+        arr[i].q = q.ctypes.data
+        arr[i].n_coarse = int(m["n_coarse"])
+    h = C.c_void_p()
+    pp = C.byref(params) if params is not None else None
+    _check(load().grg_batch_create(arr, len(members), int(nrhs), pp, _stream(stream), C.byref(h)))
+    return h
+
+
+def grg_batch_destroy(b):
+    _check(load().grg_batch_destroy(b))
+
+
+def grg_batch_layout(b, member):
+    off, nb = C.c_int64(), C.c_int32()
+    _check(load().grg_batch_layout(b, int(member), C.byref(off), C.byref(nb)))
+    return off.value, nb.value
+
+
+def grg_batch_apply(b, x_b, y_b, use_graph=True, allow_noconv=False):
+    st = grg_solver_stats()
+    status = _check(load().grg_batch_apply(b, _ptr(x_b), _ptr(y_b), int(bool(use_graph)), C.byref(st)),
+                    allow=(GRG_ENOCONV,) if allow_noconv else ())
+    d = st.as_dict()
+    d["status"] = status
+    return d
+
+
+def grg_batch_tune(b):
+    _check(load().grg_batch_tune(b))
 
 
 def grg_profile_enable(s, on=True):

@@ -17,8 +17,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgrg.so")
-SOURCES = ["kernels_dslash.hip", "kernels_blas.hip", "kernels_ptc.hip", "solver.cpp", "api.cpp",
-           "precond.cpp"]
+SOURCES = ["kernels_dslash.hip", "kernels_blas.hip", "kernels_ptc.hip", "kernels_batch.hip",
+           "solver.cpp", "api.cpp", "precond.cpp", "batch.cpp"]
 ARCH = "gfx950"
 
 # Packed-FP32 instructions are disabled for every HIP translation unit.
