@@ -94,6 +94,86 @@ def time_applies(grg, s, xb, yb, nrhs, steps, warmup, profile):
     return t1 - t0, stats, prof
 
 
+def learned_leg(grg, torch, args, lat, s, xb, yb, y_plain, nrhs, plain_value, plain_stats):
+    """Train the network on a 16^4 field (m0 -0.3, seed 5) from solver pairs,
+    then use it as the right preconditioner of the same 32^4 solve."""
+    from grg_inputs import su3_links
+
+    dims16 = (16, 16, 16, 16)
+    lat16 = grg.grg_lattice_create(dims16)
+    grg.grg_gauge_set(lat16, su3_links(dims16, 0.5, 5))
+    q16, nb16 = grg.grg_permutation_block(dims16, grg.GRG_PERM_I)
+    s16 = grg.grg_schur_create(lat16, -0.3, q16, nb16,
+                               grg.grg_solver_params_default(inner="bf16", inner_tol=1e-2, max_rhs=12))
+    p16 = grg.grg_precond_create(s16)
+    log(f"training the preconditioner: {args.train_steps} steps x 12 pairs on 16^4")
+    tr = grg.grg_precond_train(p16, steps=args.train_steps, batch=12, max_mr_steps=30, lr=2e-3, seed=5,
+                               log_every=50)
+    w = grg.grg_precond_get_weights(p16)
+    grg.grg_precond_destroy(p16)
+    grg.grg_schur_destroy(s16)
+    grg.grg_lattice_destroy(lat16)
+    p = grg.grg_precond_create(s)
+    grg.grg_precond_set_weights(p, w)
+    grg.grg_schur_attach_precond(s, p)
+    k = max(1, args.steps // 2)
+    dt, stats, _ = time_applies(grg, s, xb, yb, nrhs, k, 1, False)
+    st = stats[-1]
+    y = yb.cpu().numpy()
+    grg.grg_schur_attach_precond(s, None)
+    grg.grg_precond_destroy(p)
+    val = nrhs * k / dt
+    diff = float(np.max(np.linalg.norm(y - y_plain, axis=1) / np.linalg.norm(y_plain, axis=1)))
+    log(f"learned: {dt / k * 1e3:.1f} ms/step, {val:.1f} applies/s, iters {st['iters']} "
+        f"(plain {plain_stats['iters']}), fallbacks {st['fallbacks']}")
+    return {"train": {"pairs": tr["pairs"], "steps": tr["steps"], "loss_first": tr["loss_first"],
+                      "loss_last": tr["loss_last"], "seconds": tr["t_ms"] / 1e3, "lattice": "16^4"},
+            "value": val, "ms_per_step": dt / k * 1e3, "inner_iters": st["iters"],
+            "inner_iters_plain": plain_stats["iters"], "outer": st["outer"], "fallbacks": st["fallbacks"],
+            "true_rel_resid": st["true_rel_resid"], "max_rel_diff_vs_plain": diff,
+            "speedup_vs_plain_mixed": val / plain_value}
+
+
+def batch_leg(grg, torch, args):
+    """48 lattices, sizes uniform over {8^4, 12^4, 16^4, 8^3x16}, own seeds,
+    m0 in [-0.3, 0.1], 4 RHS each, FP32 inner / FP64 outer, one batch."""
+    from grg_inputs import batch_instances, gaussian_vectors, su3_links
+
+    descs = batch_instances(48)
+    ms = []
+    for d in descs:
+        q, nb = grg.grg_permutation_block(d["dims"], grg.GRG_PERM_I)
+        ms.append(dict(dims=d["dims"], m0=d["m0"], links=su3_links(d["dims"], 0.5, d["seed"]), q=q,
+                       n_coarse=nb))
+    nrhs = 4
+    prm = grg.grg_solver_params_default(tol=1e-10, inner="fp32", inner_tol=1e-5, check_every=4)
+    b = grg.grg_batch_create(ms, nrhs, prm)
+    grg.grg_batch_tune(b)
+    total, _ = grg.grg_batch_layout(b, 48)
+    x = np.zeros(total, np.complex128)
+    for i in range(48):
+        off, nb = grg.grg_batch_layout(b, i)
+        x[off:off + 12 * nb * nrhs] = gaussian_vectors(12 * nb, nrhs, 4000 + i).reshape(-1)
+    xd = torch.from_numpy(x).to("cuda")
+    yd = torch.empty_like(xd)
+    out = {"lattices": 48, "rhs_per_lattice": nrhs, "systems": 48 * nrhs,
+           "sites": int(sum(int(np.prod(m["dims"])) for m in ms))}
+    for mode, graph in (("graph", True), ("eager", False)):
+        grg.grg_batch_apply(b, xd, yd, use_graph=graph)
+        torch.cuda.synchronize()
+        k = max(1, args.steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(k):
+            st = grg.grg_batch_apply(b, xd, yd, use_graph=graph)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / k
+        out[mode] = {"ms_per_batch": dt * 1e3, "applies_per_s": 48 * nrhs / dt, "inner_iters": st["iters"],
+                     "outer": st["outer"], "true_rel_resid": st["true_rel_resid"]}
+        log(f"batch ({mode}): {dt * 1e3:.2f} ms per 48 x {nrhs} applies, {48 * nrhs / dt:.1f} applies/s")
+    grg.grg_batch_destroy(b)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +188,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the stencil autotuner")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 48-lattice batch leg")
+    ap.add_argument("--train-steps", type=int, default=1667, help="12-pair Adam steps (1667 = 20k pairs)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -193,6 +276,13 @@ def main():
             f"diff vs mixed {diff.max():.2e}")
         grg.grg_schur_destroy(s64)
 
+    learned = None
+    if not args.no_learned:
+        learned = learned_leg(grg, torch, args, lat, s, xb, yb, y_mixed, nrhs, value, st)
+    batch = None
+    if not args.no_batch:
+        batch = batch_leg(grg, torch, args)
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import matfree
@@ -235,6 +325,8 @@ def main():
         "roofline": roofline,
         "fp64_gcr": fp64,
         "speedup_vs_fp64": (value / fp64["value"]) if fp64 else None,
+        "learned_preconditioner": learned,
+        "batch_48": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
