@@ -22,7 +22,6 @@ in HBM.  The CPU oracle is timed on a bounded sample on the host cores.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -36,11 +35,6 @@ sys.path.insert(0, ROOT)
 METRIC = "S_bb applies/s + dslash HBM GB/s at 32^4; mixed+learned vs FP64 at 1e-10"
 PEAK_HBM_GBS = 8000.0
 REAL_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dslash_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_0704_2341_amd", "csrc", f)
-                  for f in ("kernels_dslash.hip", "common.h")]
-
-
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -53,26 +47,31 @@ def dslash_bytes_per_launch(prec: str, volume: int, nrhs: int) -> int:
     return volume * (nrhs * 2 * 24 * b + 72 * b)
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+PREC_ID = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 
-def measured_traffic(prec: str, nrhs: int, dims):
-    """HBM bytes per launch from committed rocprofv3 counter runs, or None if
-    the kernel source changed since they were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    with open(TRAFFIC_FILE) as f:
-        t = json.load(f)
-    if t.get("kernel_source_sha256") != kernel_source_hash():
-        return None
-    key = f"{prec}_nrhs{nrhs}_{'x'.join(map(str, dims))}"
-    e = t.get("kernels", {}).get(key)
-    return None if e is None else e.get("hbm_bytes_per_launch")
+def launch_descriptor(info: dict, prec: str, launches: int) -> dict:
+    """The stencil kernel a tuned launch runs, as a profiler names it, and its
+    work-items per dispatch."""
+    p = PREC_ID[prec]
+    if info["march"] > 0:
+        sym, gs = f"dslash_march_kernel<{p}>", info["grid"] * 64 * info["RG"]
+    else:
+        sym, gs = f"dslash_kernel<{p}, {'true' if info['split'] else 'false'}>", info["grid"] * info["SB"]
+    shape = {k: info[k] for k in ("SB", "RG", "split", "grid", "chunk", "march")}
+    return {"symbol": sym, "grid_size": gs, "launches": launches, "shape": shape}
+
+
+def copy_calibration(torch, mib: int) -> int:
+    """A plain streaming kernel of known size for the counter runs: torch's
+    negation reads and writes n bytes once each."""
+    n = mib << 20
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    return n
 
 
 def time_applies(grg, s, xb, yb, nrhs, steps, warmup, profile):
@@ -191,6 +190,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the 48-lattice batch leg")
     ap.add_argument("--train-steps", type=int, default=1667, help="12-pair Adam steps (1667 = 20k pairs)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run a plain copy kernel of MIB MiB (for counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -203,6 +204,7 @@ def main():
 
     import paper_0704_2341_amd as grg
     from grg_inputs import point_sources, su3_links
+    from paper_0704_2341_amd.profiling import measured_traffic
 
     dims = tuple(int(d) for d in args.dims.split(","))
     volume = int(np.prod(dims))
@@ -251,7 +253,9 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBps"], "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": dk["alg_GBps"] / PEAK_HBM_GBS,
                 "traffic": traffic, "alg_bytes_per_launch": dk["alg_bytes_per_launch"],
-                "avg_launch_ms": dk["avg_ms"]}
+                "avg_launch_ms": dk["avg_ms"],
+                "launch": launch_descriptor(grg.grg_schur_tune_info(s, args.inner, nrhs), args.inner,
+                                            dk["launches"])}
 
     fp64 = None
     if not args.no_fp64 and args.inner != "fp64":
@@ -282,6 +286,8 @@ def main():
     batch = None
     if not args.no_batch:
         batch = batch_leg(grg, torch, args)
+
+    copy_bytes = copy_calibration(torch, args.calibrate_copy) if args.calibrate_copy else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -329,6 +335,8 @@ def main():
         "batch_48": batch,
         "cpu_baseline": cpu,
     }
+    if copy_bytes:
+        out["calibration_copy_bytes"] = copy_bytes
     print(json.dumps(out), flush=True)
     grg.grg_schur_destroy(s)
     grg.grg_lattice_destroy(lat)
