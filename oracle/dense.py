@@ -16,7 +16,11 @@ Everything here is the plain definition, written out entry by entry:
 * the general Gaussian-integration form of section 1 (D~ = D + Bbar D_bb B,
   S_bb = D_bb - D_bb B D~^{-1} Bbar D_bb) with the blocking kernels B, Bbar of
   section 1 (step 2), used only to check that it reduces to the Schur
-  complement.
+  complement;
+* the second-order Schur complement approximation of section 3,
+  S~_bb = D_bb - D_br (d_rr^{-1} + d~_rr^{-1} - d_rr^{-1} D_rr d~_rr^{-1}) D_rb,
+  with d_rr the diagonal of D_rr and d~_rr the diagonal matrix of the row sums
+  of D_rr (read literally: the sum of each scalar row, dof by dof).
 
 Sizes: 12*V dof; at 4^4 the matrix is 3072 x 3072 complex (151 MB).
 """
@@ -192,3 +196,18 @@ def schur_apply_dense(d, q, n_b, x_b):
     """S_bb x_b for a batch x_b of shape (nrhs, 12 N_b)."""
     s = schur_dense(d, q, n_b)
     return (s @ np.atleast_2d(x_b).T).T
+
+
+# ---------------------------------------------------------------- approximation (section 3)
+def reusken_inverse(drr: np.ndarray) -> np.ndarray:
+    """M = d^{-1} + d~^{-1} - d^{-1} D_rr d~^{-1}, the approximate D_rr^{-1} of
+    the section 3 formula: d = diag(D_rr), d~ = diag(row sums of D_rr)."""
+    d = np.diag(drr)
+    dt = drr.sum(axis=1)
+    return np.diag(1.0 / d) + np.diag(1.0 / dt) - (drr / d[:, None]) / dt[None, :]
+
+
+def reusken_dense(d: np.ndarray, q, n_b: int) -> np.ndarray:
+    """S~_bb = D_bb - D_br M D_rb (section 3)."""
+    dbb, dbr, drb, drr = blocks(d, q, n_b)
+    return dbb - dbr @ reusken_inverse(drr) @ drb

@@ -113,3 +113,32 @@ def schur_apply(links, dims, m0, q, nb, xb, restart=8, tol=1e-13, maxit=10000, b
                           np.ascontiguousarray(q, dtype=np.int32), int(nb), xb, yb, xb.shape[0],
                           int(restart), float(tol), int(maxit), it, rr)
     return yb, it, rr
+
+
+def reusken_apply(links, dims, m0, q, nb, xb, bc=(1, 1, 1, -1)):
+    """S~_bb x_b of section 3, matrix-free from the stencil's blocks:
+        u = x_b on the coarse sites,  y = D_rb u,  d~ = D_rr 1 (row sums),
+        t = y / d~,  M y = y / d + t - (D_rr t) / d   (d = 4 + m0, the
+        diagonal of the Wilson operator),  S~ x_b = D_bb x_b - D_br M y.
+    Returns (nrhs, 12 nb)."""
+    v = int(np.prod(dims))
+    q = np.asarray(q)
+    xb = _fields(xb, 12 * int(nb))
+    nrhs = xb.shape[0]
+    u = np.zeros((nrhs, v, 12), np.complex128)
+    u[:, q[:nb]] = xb.reshape(nrhs, nb, 12)
+    u = u.reshape(nrhs, 12 * v)
+    rest = np.ones(v, bool)
+    rest[q[:nb]] = False
+    ones = np.zeros((1, v, 12), np.complex128)
+    ones[:, rest] = 1.0
+    dt = block_apply(links, dims, m0, q, nb, 0, 0, ones.reshape(1, -1), bc).reshape(v, 12)
+    y = block_apply(links, dims, m0, q, nb, 0, 1, u, bc).reshape(nrhs, v, 12)
+    t = np.zeros_like(y)
+    t[:, rest] = y[:, rest] / dt[rest]
+    z = block_apply(links, dims, m0, q, nb, 0, 0, t.reshape(nrhs, -1), bc).reshape(nrhs, v, 12)
+    my = (y - z) / (4.0 + m0) + t
+    # D_bb x_b - D_br M y = [D (u - M y)]_b   (u is zero on the rest sites, M y on the coarse)
+    w = u - my.reshape(nrhs, -1)
+    out = dirac_apply(links, dims, m0, w, bc).reshape(nrhs, v, 12)
+    return np.ascontiguousarray(out[:, q[:nb]].reshape(nrhs, 12 * int(nb)))
