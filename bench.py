@@ -189,6 +189,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the stencil autotuner")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the 48-lattice batch leg")
+    ap.add_argument("--no-reusken", action="store_true", help="skip the section 3 approximation leg")
     ap.add_argument("--train-steps", type=int, default=1667, help="12-pair Adam steps (1667 = 20k pairs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain copy kernel of MIB MiB (for counter calibration)")
@@ -231,7 +232,8 @@ def main():
         grg.grg_schur_tune(s, nrhs)
         log(f"tuned in {time.perf_counter() - t:.1f} s: "
             f"{args.inner} {grg.grg_schur_tune_info(s, args.inner, nrhs)}, "
-            f"fp64 {grg.grg_schur_tune_info(s, 'fp64', nrhs)}")
+            f"fp64 {grg.grg_schur_tune_info(s, 'fp64', nrhs)}, "
+            f"defect correction {grg.grg_schur_dc_launch_info(s, args.inner, nrhs)}")
     log(f"timing {args.inner} path: warmup {args.warmup}, steps {args.steps}")
     dt, stats, prof = time_applies(grg, s, xb, yb, nrhs, args.steps, args.warmup, True)
     y_mixed = yb.cpu().numpy()
@@ -280,6 +282,24 @@ def main():
             f"diff vs mixed {diff.max():.2e}")
         grg.grg_schur_destroy(s64)
 
+    reusken = None
+    if not args.no_reusken:
+        # the section 3 approximation on the same workload: no solve
+        ya = torch.empty_like(xb)
+        grg.grg_reusken_apply(s, xb, ya, nrhs)
+        torch.cuda.synchronize()
+        kr = max(1, args.steps)
+        t0 = time.perf_counter()
+        for _ in range(kr):
+            grg.grg_reusken_apply(s, xb, ya, nrhs)
+        torch.cuda.synchronize()
+        dtr = (time.perf_counter() - t0) / kr
+        ya_h = ya.cpu().numpy()
+        rd = float(np.max(np.linalg.norm(ya_h - y_mixed, axis=1) / np.linalg.norm(y_mixed, axis=1)))
+        reusken = {"value": nrhs / dtr, "unit": "S~_bb applies/s", "ms_per_step": dtr * 1e3,
+                   "rel_diff_vs_exact": rd}
+        log(f"reusken: {dtr * 1e3:.2f} ms/step, {nrhs / dtr:.1f} applies/s, |S~x - Sx|/|Sx| {rd:.3f}")
+
     learned = None
     if not args.no_learned:
         learned = learned_leg(grg, torch, args, lat, s, xb, yb, y_mixed, nrhs, value, st)
@@ -324,6 +344,7 @@ def main():
                    "lattice": list(dims), "nrhs": nrhs, "inner": args.inner,
                    "inner_tol": inner_tol, "restart": args.restart, "tol": tol,
                    "dslash_launch": grg.grg_schur_tune_info(s, args.inner, nrhs),
+                   "dc_launch": grg.grg_schur_dc_launch_info(s, args.inner, nrhs),
                    "parallelism": "1 GPU"},
         "solver": {"iters": st["iters"], "outer": st["outer"],
                    "true_rel_resid": st["true_rel_resid"], "n_dslash": st["n_dslash"]},
@@ -331,6 +352,7 @@ def main():
         "roofline": roofline,
         "fp64_gcr": fp64,
         "speedup_vs_fp64": (value / fp64["value"]) if fp64 else None,
+        "reusken_approximation": reusken,
         "learned_preconditioner": learned,
         "batch_48": batch,
         "cpu_baseline": cpu,

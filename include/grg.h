@@ -83,6 +83,10 @@ typedef struct {
     int max_outer;     /* cap on defect-correction steps (mixed only) */
     int max_rhs;       /* largest nrhs per call; sizes the workspaces (<= 16) */
     int check_every;   /* iterations between host-side convergence checks */
+    int verify;        /* 1: on convergence, recompute b - D_rr x from x in FP64 and resume
+                          if it misses tol; 0 (default): stop on the defect correction's
+                          FP64 residual, which is updated with the exact FP64 operator
+                          and equals b - D_rr x up to FP64 rounding */
 } grg_solver_params;
 
 typedef struct {
@@ -170,16 +174,31 @@ grg_status grg_schur_apply(grg_schur s, const double *x_b, double *y_b, int nrhs
  * applying S_bb to unit vectors.  GRG_ETOO_LARGE if it exceeds cap_bytes. */
 grg_status grg_schur_assemble(grg_schur s, double *S, size_t cap_bytes);
 
+/* The second-order Schur complement approximation of section 3,
+ *     S~_bb = D_bb - D_br (d^{-1} + d~^{-1} - d^{-1} D_rr d~^{-1}) D_rb,
+ * with d the diagonal of D_rr (4 + m0) and d~ the diagonal matrix of the row
+ * sums of D_rr, each scalar row summed over its dof (d~ = D_rr applied to the
+ * field that is 1 on every rest-site dof).  y_b = S~_bb x_b for nrhs
+ * coarse-space fields (device, layout as grg_schur_apply), in FP64: four
+ * stencil launches and no solve.  GRG_EINVAL if 4 + m0 = 0; a zero row sum
+ * gives non-finite output (no check).  Uses the handle's workspaces. */
+grg_status grg_reusken_apply(grg_schur s, const double *x_b, double *y_b, int nrhs);
+/* Dense S~_bb (host, column-major complex128), as grg_schur_assemble. */
+grg_status grg_reusken_assemble(grg_schur s, double *S, size_t cap_bytes);
+
 /* Autotuner: time every candidate launch shape of the stencil (sites per
  * workgroup, right-hand sides per thread, hop grouping, grid size) for nrhs
- * right-hand sides, in FP64 and in the inner precision, on this handle's
- * workspaces, and keep the fastest for later calls with that nrhs.  Every
- * candidate evaluates each site in the same order, so tuning changes speed,
- * not results.  Takes a few hundred stencil launches. */
+ * right-hand sides, in FP64 and in the inner precision, and of the fused
+ * defect-correction step, on this handle's workspaces, and keep the fastest
+ * for later calls with that nrhs.  Every candidate evaluates each site in the
+ * same order, so tuning changes speed, not results.  Takes a few hundred
+ * stencil launches; overwrites the handle's workspaces (not caller memory). */
 grg_status grg_schur_tune(grg_schur s, int nrhs);
 /* The launch used for (precision, nrhs): info = {sites per workgroup, RHS per
  * thread (site-parallel kernel) or per workgroup (t-marching kernel),
- * one-hop-per-iteration flag, workgroups, items per XCD chunk (0 = one
+ * hop schedule (0: one direction per loop iteration, 1: one hop per
+ * iteration, 2: BF16 only, straight-line with the next hop's loads issued
+ * before the current hop's arithmetic), workgroups, items per XCD chunk (0 = one
  * contiguous eighth of the lattice per XCD), time-chunk length of the
  * t-marching kernel (0 = site-parallel kernel)}; *ms = its tuned time per
  * launch, or -1 if untuned (defaults in use). */
@@ -188,10 +207,19 @@ grg_status grg_schur_tune_info(grg_schur s, int precision, int nrhs, int32_t inf
 /* Pin the stencil launch for (precision, nrhs), e.g. from a saved tuning
  * result: info as returned by grg_schur_tune_info.  GRG_EINVAL if the shape
  * is not valid for this lattice (a t-marching workgroup holds 64 * RHS
- * threads, at most 512 in FP64 and 768 otherwise).  Solver launches with
- * fused dot products fall back to the default shape when a t-marching shape
- * does not hold every RHS. */
+ * threads, at most 512 in FP64 and 768 otherwise). */
 grg_status grg_schur_set_launch(grg_schur s, int precision, int nrhs, const int32_t info[6]);
+
+/* The launch of the fused FP64 defect-correction step r -= D_rr e / s,
+ * x += e / s (inner solution e stored in `precision`), for nrhs RHS: info as
+ * in grg_schur_tune_info, where info[5] = 0 selects the site-parallel kernel
+ * (info[0] threads per workgroup: 64, 128 or 256) and info[5] = T > 0 the
+ * t-marching kernel (64 * info[1] <= 512 threads, time chunks of T);
+ * info[2] is ignored.  *ms = tuned time per step, or -1 if untuned. */
+grg_status grg_schur_dc_launch_info(grg_schur s, int precision, int nrhs, int32_t info[6],
+                                    float *ms);
+/* Pin that launch; GRG_EINVAL if the shape is not valid for this lattice. */
+grg_status grg_schur_set_dc_launch(grg_schur s, int precision, int nrhs, const int32_t info[6]);
 
 /* The sub-blocks of the partition (section 1, step 1): out = D_{rows,cols} in
  * for nrhs canonical lattice fields (device), with rows / cols = 1 for the

@@ -38,8 +38,10 @@ EXPORTS = (
     "grg_last_error", "grg_version", "grg_solver_params_default", "grg_lattice_create",
     "grg_lattice_destroy", "grg_lattice_volume", "grg_gauge_set", "grg_permutation_block",
     "grg_dirac_apply", "grg_schur_create", "grg_schur_destroy", "grg_schur_set_params",
-    "grg_drr_solve", "grg_schur_apply", "grg_schur_assemble", "grg_schur_tune",
-    "grg_schur_tune_info", "grg_schur_set_launch", "grg_block_apply", "grg_precond_create",
+    "grg_drr_solve", "grg_schur_apply", "grg_schur_assemble", "grg_reusken_apply",
+    "grg_reusken_assemble", "grg_schur_tune",
+    "grg_schur_tune_info", "grg_schur_set_launch", "grg_schur_dc_launch_info",
+    "grg_schur_set_dc_launch", "grg_block_apply", "grg_precond_create",
     "grg_precond_destroy", "grg_precond_set_weights", "grg_precond_get_weights", "grg_precond_apply",
     "grg_precond_loss_grad", "grg_precond_train", "grg_precond_save", "grg_precond_load",
     "grg_schur_attach_precond", "grg_batch_create", "grg_batch_destroy", "grg_batch_layout",
@@ -58,7 +60,7 @@ class grg_solver_params(C.Structure):
     _fields_ = [
         ("tol", C.c_double), ("max_iter", C.c_int), ("restart", C.c_int), ("inner", C.c_int),
         ("inner_tol", C.c_double), ("max_outer", C.c_int), ("max_rhs", C.c_int),
-        ("check_every", C.c_int),
+        ("check_every", C.c_int), ("verify", C.c_int),
     ]
 
 
@@ -129,9 +131,13 @@ def load():
         "grg_drr_solve": (C.c_int, [vp, vp, vp, C.c_int, C.POINTER(grg_solver_stats)]),
         "grg_schur_apply": (C.c_int, [vp, vp, vp, C.c_int, C.POINTER(grg_solver_stats)]),
         "grg_schur_assemble": (C.c_int, [vp, vp, C.c_size_t]),
+        "grg_reusken_apply": (C.c_int, [vp, vp, vp, C.c_int]),
+        "grg_reusken_assemble": (C.c_int, [vp, vp, C.c_size_t]),
         "grg_schur_tune": (C.c_int, [vp, C.c_int]),
         "grg_schur_tune_info": (C.c_int, [vp, C.c_int, C.c_int, i32p, C.POINTER(C.c_float)]),
         "grg_schur_set_launch": (C.c_int, [vp, C.c_int, C.c_int, i32p]),
+        "grg_schur_dc_launch_info": (C.c_int, [vp, C.c_int, C.c_int, i32p, C.POINTER(C.c_float)]),
+        "grg_schur_set_dc_launch": (C.c_int, [vp, C.c_int, C.c_int, i32p]),
         "grg_block_apply": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, vp, C.c_int]),
         "grg_precond_create": (C.c_int, [vp, C.POINTER(vp)]),
         "grg_precond_destroy": (C.c_int, [vp]),
@@ -292,6 +298,19 @@ def grg_schur_assemble(s, n_coarse):
     return buf.reshape(n, n).T  # column-major storage
 
 
+def grg_reusken_apply(s, x_b, y_b, nrhs):
+    """y_b = S~_bb x_b, the section 3 approximation (FP64, no solve)."""
+    _check(load().grg_reusken_apply(s, _ptr(x_b), _ptr(y_b), int(nrhs)))
+
+
+def grg_reusken_assemble(s, n_coarse):
+    """Dense S~_bb as a numpy complex128 (12 N_b, 12 N_b) array."""
+    n = 12 * int(n_coarse)
+    buf = np.zeros(n * n, dtype=np.complex128)
+    _check(load().grg_reusken_assemble(s, C.c_void_p(buf.ctypes.data), buf.nbytes))
+    return buf.reshape(n, n).T  # column-major storage
+
+
 def grg_schur_tune(s, nrhs):
     _check(load().grg_schur_tune(s, int(nrhs)))
 
@@ -311,6 +330,23 @@ def grg_schur_set_launch(s, precision, nrhs, info):
         info = [info.get(k, 0) for k in ("SB", "RG", "split", "grid", "chunk", "march")]
     arr, ptr = _i32(info)
     _check(load().grg_schur_set_launch(s, _prec(precision), int(nrhs), ptr))
+
+
+def grg_schur_dc_launch_info(s, precision, nrhs):
+    """The defect-correction step's launch for (inner precision, nrhs), as a dict."""
+    info = (C.c_int32 * 6)()
+    ms = C.c_float()
+    _check(load().grg_schur_dc_launch_info(s, _prec(precision), int(nrhs), info, C.byref(ms)))
+    return {"SB": info[0], "RG": info[1], "split": info[2], "grid": info[3], "chunk": info[4],
+            "march": info[5], "ms": ms.value}
+
+
+def grg_schur_set_dc_launch(s, precision, nrhs, info):
+    """info: dict as returned by grg_schur_dc_launch_info (or a 6-sequence)."""
+    if isinstance(info, dict):
+        info = [info.get(k, 0) for k in ("SB", "RG", "split", "grid", "chunk", "march")]
+    arr, ptr = _i32(info)
+    _check(load().grg_schur_set_dc_launch(s, _prec(precision), int(nrhs), ptr))
 
 
 def grg_block_apply(s, precision, rows, cols, x, out, nrhs):

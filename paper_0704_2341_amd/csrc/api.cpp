@@ -37,6 +37,10 @@ bool launch_ok(const Geom &g, int prec, int nrhs, const DslashTune &t, bool dots
 grg_status block_apply_internal(grg_schur S, int prec, int rows, int cols, const double *in,
                                 double *out, int nrhs);
 grg_status tune_dslash(grg_schur S, int prec, int nrhs, int reps);
+grg_status reusken_apply_internal(grg_schur S, const double *xb, double *yb, int nrhs);
+grg_status tune_dc(grg_schur S, int prec, int nrhs, int reps);
+DslashTune default_dc_tune(const Geom &g);
+bool dc_launch_ok(const Geom &g, int nrhs, const DslashTune &t);
 
 static grg_status dmalloc(void **p, size_t bytes, const char *what)
 {
@@ -70,6 +74,7 @@ static grg_status validate_params(const grg_solver_params &p)
     if (p.max_rhs < 1 || p.max_rhs > kMaxRhs)
         return set_error("max_rhs must be in 1..%d", kMaxRhs), GRG_EINVAL;
     if (p.check_every < 1) return set_error("check_every must be >= 1"), GRG_EINVAL;
+    if (p.verify != 0 && p.verify != 1) return set_error("verify must be 0 or 1"), GRG_EINVAL;
     return GRG_OK;
 }
 
@@ -145,6 +150,7 @@ grg_status grg_solver_params_default(grg_solver_params *p)
     p->max_outer = 30;
     p->max_rhs = 12;
     p->check_every = 1;
+    p->verify = 0;
     return GRG_OK;
 }
 
@@ -308,6 +314,7 @@ static void schur_free(grg_schur S)
     }
     dfree((void *&)S->cb_in);
     dfree((void *&)S->cb_out);
+    dfree(S->dt64);
     dfree((void *&)S->partials);
     dfree((void *&)S->alpha);
     dfree((void *&)S->beta);
@@ -377,10 +384,10 @@ grg_status grg_schur_create(grg_lattice L, double m0, const int32_t *q, int32_t 
     ALLOC(S->rn2, sizeof(double) * kMaxRhs);
     ALLOC(S->thr2, sizeof(double) * kMaxRhs);
     ALLOC(S->qn2, sizeof(double) * kMaxRhs * kMaxRhs);
-    ALLOC(S->bn2, sizeof(double) * 2 * kMaxRhs);  // |b|^2, then the outer |r|^2
+    ALLOC(S->bn2, sizeof(double) * 4 * kMaxRhs);  // |b|^2, then per-RHS scales
     ALLOC(S->active, sizeof(int) * kMaxRhs);
 #undef ALLOC
-    if (s == GRG_OK && hipHostMalloc((void **)&S->h_buf, sizeof(double) * 4 * kMaxRhs) != hipSuccess) {
+    if (s == GRG_OK && hipHostMalloc((void **)&S->h_buf, sizeof(double) * 8 * kMaxRhs) != hipSuccess) {
         S->h_buf = nullptr;
         set_error("hipHostMalloc failed");
         s = GRG_ENOMEM;
@@ -500,7 +507,22 @@ grg_status grg_schur_apply(grg_schur S, const double *x_b, double *y_b, int nrhs
     return finish_call(S, st, t0, stats, before);
 }
 
-grg_status grg_schur_assemble(grg_schur S, double *out, size_t cap_bytes)
+grg_status grg_reusken_apply(grg_schur S, const double *x_b, double *y_b, int nrhs)
+{
+    GRG_TRY(check_call(S, x_b, y_b, nrhs));
+    if (4.0 + S->m0 == 0.0) return set_error("4 + m0 = 0: D_rr has a zero diagonal"), GRG_EINVAL;
+    DeviceGuard dg(S->lat->device);
+    const auto t0 = clk::now();
+    double before = 0;
+    for (int p = 0; p < 3; ++p) before += S->prof.total_ms[p];
+    S->n_dslash = 0;
+    grg_status st = reusken_apply_internal(S, x_b, y_b, nrhs);
+    return finish_call(S, st, t0, nullptr, before);
+}
+
+// Dense coarse operator from its applies to unit vectors, max_rhs columns at
+// a time.  exact: S_bb (solves), else the section 3 approximation.
+static grg_status assemble(grg_schur S, double *out, size_t cap_bytes, bool exact)
 {
     if (!S || !out) return set_error("null argument"), GRG_EINVAL;
     const size_t n = (size_t)12 * S->nb;
@@ -522,13 +544,24 @@ grg_status grg_schur_assemble(grg_schur S, double *out, size_t cap_bytes)
         for (int k = 0; k < cnt; ++k) unit[((size_t)k * n + j0 + k) * 2] = 1.0;
         GRG_TRY_HIP(hipMemcpyAsync(S->cb_in, unit.data(), n * 16 * cnt, hipMemcpyHostToDevice, st));
         grg_solver_stats sst;
-        grg_status s = grg_schur_apply(S, S->cb_in, S->cb_out, cnt, &sst);
+        grg_status s = exact ? grg_schur_apply(S, S->cb_in, S->cb_out, cnt, &sst)
+                             : grg_reusken_apply(S, S->cb_in, S->cb_out, cnt);
         if (s != GRG_OK && s != GRG_ENOCONV) return s;
         if (s == GRG_ENOCONV) worst = s;
         // column j0 + k of the column-major matrix is output vector k
         GRG_TRY_HIP(hipMemcpy(out + j0 * n * 2, S->cb_out, n * 16 * cnt, hipMemcpyDeviceToHost));
     }
     return worst;
+}
+
+grg_status grg_schur_assemble(grg_schur S, double *out, size_t cap_bytes)
+{
+    return assemble(S, out, cap_bytes, true);
+}
+
+grg_status grg_reusken_assemble(grg_schur S, double *out, size_t cap_bytes)
+{
+    return assemble(S, out, cap_bytes, false);
 }
 
 grg_status grg_schur_tune(grg_schur S, int nrhs)
@@ -539,7 +572,43 @@ grg_status grg_schur_tune(grg_schur S, int nrhs)
     DeviceGuard dg(S->lat->device);
     GRG_TRY(tune_dslash(S, GRG_FP64, nrhs, 3));
     if (S->prm.inner != GRG_FP64) GRG_TRY(tune_dslash(S, S->prm.inner, nrhs, 3));
+    GRG_TRY(tune_dc(S, S->prm.inner, nrhs, 3));
     GRG_TRY_HIP(hipStreamSynchronize(S->lat->stream));
+    return GRG_OK;
+}
+
+grg_status grg_schur_dc_launch_info(grg_schur S, int precision, int nrhs, int32_t info[6], float *ms)
+{
+    if (!S || !info || !ms) return set_error("null argument"), GRG_EINVAL;
+    if (precision < 0 || precision > 2 || nrhs < 1 || nrhs > kMaxRhs)
+        return set_error("bad precision or nrhs"), GRG_EINVAL;
+    const DslashTune &t = S->dctune[precision][nrhs];
+    const DslashTune d = t.valid ? t : default_dc_tune(S->lat->g);
+    const int32_t v[6] = {d.SB, d.RG, d.split, d.grid, d.chunk, d.march};
+    memcpy(info, v, sizeof(v));
+    *ms = t.valid ? t.ms : -1.0f;
+    return GRG_OK;
+}
+
+grg_status grg_schur_set_dc_launch(grg_schur S, int precision, int nrhs, const int32_t info[6])
+{
+    if (!S || !info) return set_error("null argument"), GRG_EINVAL;
+    if (precision < 0 || precision > 2 || nrhs < 1 || nrhs > S->prm.max_rhs)
+        return set_error("bad precision or nrhs"), GRG_EINVAL;
+    DslashTune t;
+    t.SB = info[0];
+    t.RG = info[1];
+    t.split = 0;
+    t.grid = info[3];
+    t.chunk = info[4];
+    t.march = info[5];
+    t.valid = 1;
+    t.ms = 0;
+    if (!dc_launch_ok(S->lat->g, nrhs, t))
+        return set_error("defect-correction launch {%d, %d, %d, %d, %d, %d} not valid for nrhs %d",
+                         info[0], info[1], info[2], info[3], info[4], info[5], nrhs),
+               GRG_EINVAL;
+    S->dctune[precision][nrhs] = t;
     return GRG_OK;
 }
 

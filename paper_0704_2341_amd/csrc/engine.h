@@ -77,15 +77,20 @@ struct DcArgs {
     const void *r_in;     // FP64 residual before the step
     const void *x_in;     // FP64 iterate before the step, or nullptr for zero
     void *r_out, *x_out;  // FP64 results (may alias the inputs)
-    const double *fr2;    // per-RHS |r|^2 the inner right-hand side was scaled by
+    const double *f;      // per-RHS factor of e (the inner right-hand side was r / f)
+    void *r_next;         // r_out * s_next in the inner precision (next inner rhs), or nullptr
+    const double *s_next; // per-RHS scale of r_next
     const uint8_t *mask;  // 1 on coarse sites
     double diag;          // 4 + m0
     Geom g;
     int nrhs;
     double *partials;     // [grid][nrhs]: |r_out|^2
+    int RG, chunk, march; // t-marching launch (march > 0), as in DslashArgs
 };
 
 hipError_t launch_dslash(int prec, const DslashArgs &a, int grid, hipStream_t st);
+// SB: workgroup of the site-parallel kernel (a.march == 0); with a.march > 0
+// the t-marching kernel runs with 64 * a.RG threads per workgroup.
 hipError_t launch_dc_update(int prec, const DcArgs &a, int grid, int SB, hipStream_t st);
 hipError_t launch_dslash_coarse(const CoarseArgs &a, hipStream_t st);
 hipError_t launch_pack_gauge(const double *src, const Geom &g, const int bc[4], void *u64,
@@ -132,6 +137,14 @@ hipError_t launch_axpy_convert(int prec_in, int prec_out, const BlasShape &sh, c
                                const int *active, hipStream_t st);
 // y = x - y (FP64), used for u - z
 hipError_t launch_xmy(const BlasShape &sh, const void *x, void *y, hipStream_t st);
+// Second-order Schur complement approximation (kernels_blas.hip): the
+// rest-site ones field, t = y / d~ and w = u - ((y - z) / d + t).
+hipError_t launch_rest_ones(const Geom &g, const uint8_t *mask, void *o, hipStream_t st);
+hipError_t launch_reusken_divide(const BlasShape &sh, const void *y, const void *dt,
+                                 const uint8_t *mask, void *t, hipStream_t st);
+hipError_t launch_reusken_combine(const BlasShape &sh, const void *u, const void *y, const void *z,
+                                  const void *t, const uint8_t *mask, double inv_d, void *w,
+                                  hipStream_t st);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 hipError_t launch_copy(int prec, const BlasShape &sh, const void *x, void *y, hipStream_t st);
 

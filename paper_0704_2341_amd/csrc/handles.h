@@ -73,18 +73,21 @@ struct grg_schur_s {
     int in_m[3] = {0, 0, 0};
     // coarse-space staging for assembly
     double *cb_in = nullptr, *cb_out = nullptr;
+    // row sums of D_rr (one FP64 field) for the section 3 approximation
+    void *dt64 = nullptr;
     // reduction scratch
     double *partials = nullptr;
     size_t partials_elems = 0;
     double2 *alpha = nullptr, *beta = nullptr;
-    // per-RHS scalars: residual norms, thresholds, GCR |q_j|^2, |b|^2 and the
-    // outer |r|^2 (bn2[kMaxRhs..])
+    // per-RHS scalars: residual norms, thresholds, GCR |q_j|^2, and bn2 =
+    // [|b|^2 | 1/s | s | next s] of the defect correction (4 kMaxRhs)
     double *rn2 = nullptr, *thr2 = nullptr, *qn2 = nullptr, *bn2 = nullptr;
     int *active = nullptr;
-    double *h_buf = nullptr;  // pinned host staging (4 * kMaxRhs doubles)
+    double *h_buf = nullptr;  // pinned host staging (8 * kMaxRhs doubles: reads, then uploads)
     grg::ProfilePool prof;
     int n_dslash = 0;
-    grg::DslashTune tune[3][grg::kMaxRhs + 1];  // per precision and nrhs
+    grg::DslashTune tune[3][grg::kMaxRhs + 1];    // per precision and nrhs
+    grg::DslashTune dctune[3][grg::kMaxRhs + 1];  // defect-correction step, per inner precision
     grg_precond precond = nullptr;  // right preconditioner of the inner GCR, or none
     int fallbacks = 0;              // inner solves redone without the preconditioner
 };

@@ -57,45 +57,119 @@ struct Partial {
 };
 
 // ------------------------------------------------------------------ MR / GCR step
-// HAS_P = false: p is r itself (minimal residual), read once
+// 16-byte vectors of a field: 4 complex in BF16, 2 in FP32, 1 in FP64.
+template <int P>
+struct VecIO;
+template <>
+struct VecIO<GRG_BF16> {
+    static constexpr int N = 4;
+    typedef float R;
+    __device__ static void get(const uint4 &v, cpx<float> (&c)[N])
+    {
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < N; ++e) c[e] = {__uint_as_float(w[e] << 16), __uint_as_float(w[e] & 0xffff0000u)};
+    }
+    __device__ static uint4 put(const cpx<float> (&c)[N])
+    {
+        return make_uint4(pack_bf16(c[0].re, c[0].im), pack_bf16(c[1].re, c[1].im),
+                          pack_bf16(c[2].re, c[2].im), pack_bf16(c[3].re, c[3].im));
+    }
+};
+template <>
+struct VecIO<GRG_FP32> {
+    static constexpr int N = 2;
+    typedef float R;
+    __device__ static void get(const uint4 &v, cpx<float> (&c)[N])
+    {
+        c[0] = {__uint_as_float(v.x), __uint_as_float(v.y)};
+        c[1] = {__uint_as_float(v.z), __uint_as_float(v.w)};
+    }
+    __device__ static uint4 put(const cpx<float> (&c)[N])
+    {
+        return make_uint4(__float_as_uint(c[0].re), __float_as_uint(c[0].im), __float_as_uint(c[1].re),
+                          __float_as_uint(c[1].im));
+    }
+};
+template <>
+struct VecIO<GRG_FP64> {
+    static constexpr int N = 1;
+    typedef double R;
+    __device__ static void get(const uint4 &v, cpx<double> (&c)[N])
+    {
+        c[0] = {__hiloint2double((int)v.y, (int)v.x), __hiloint2double((int)v.w, (int)v.z)};
+    }
+    __device__ static uint4 put(const cpx<double> (&c)[N])
+    {
+        const long long a = __double_as_longlong(c[0].re), b = __double_as_longlong(c[0].im);
+        return make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32));
+    }
+};
+
+// x += alpha_k p, r -= alpha_k q, and the partial sums of |r|^2 (of the values
+// as stored) per RHS.  HAS_P = false: p is r itself (minimal residual).
+//
+// All RHS of a 64-site tile are one contiguous block, and one RHS of a tile
+// (12 components x 64 sites) is a contiguous unit; a wavefront streams whole
+// units with 16-byte accesses, so every load and store instruction of the
+// wavefront moves 1 KB of consecutive memory, and alpha and the norm of a
+// unit belong to one RHS.  Units are walked in tile order, XCD-aware.
 template <int P, bool HAS_P>
 __global__ void __launch_bounds__(256) mr_update_kernel(BlasShape sh, void *x_, void *r_,
                                                         const void *q_, const void *p_,
                                                         const double2 *alpha, double *partials)
 {
-    typedef typename Store<P>::S S;
-    typedef typename Store<P>::R R;
-    __shared__ double smem[4 * kMaxRhs];
-    Partial<1> part;
-    part.init(smem, sh.nrhs);
-    S *x = (S *)x_, *r = (S *)r_;
-    const S *q = (const S *)q_, *p = (const S *)p_;
-    SITE_LOOP_BEGIN(sh)
-    for (int k = 0; k < sh.nrhs; ++k) {
+    typedef VecIO<P> IO;
+    typedef typename IO::R R;
+    constexpr int N = IO::N;
+    constexpr int UV = 12 * 64 / N;  // 16-byte vectors per unit
+    constexpr int NV = UV / 64;      // per lane
+    __shared__ double red[4][kMaxRhs];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = lane; i < sh.nrhs; i += 64) red[wave][i] = 0.0;
+    uint4 *x = (uint4 *)x_, *r = (uint4 *)r_;
+    const uint4 *q = (const uint4 *)q_, *p = (const uint4 *)p_;
+    const int ntiles = (sh.g.V + 63) >> 6;
+    const int nunits = ntiles * sh.nrhs;
+    const ItemRange it = xcd_items((nunits + 3) >> 2);
+    for (int w = it.begin; w < it.end; w += it.step) {
+        const int u = w * 4 + wave;
+        if (u >= nunits) continue;  // the whole wavefront
+        const int tile = u / sh.nrhs, k = u - tile * sh.nrhs;
         const double2 a2 = alpha[k];
-        const cpx<R> a = {(R)a2.x, (R)a2.y};
+        const cpx<R> a = {(R)a2.x, (R)a2.y}, na = {-a.re, -a.im};
+        const size_t base = (size_t)u * UV;
         R rr = 0;
-        if (valid) {
-            const cpx<R> na = {-a.re, -a.im};
 #pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                const size_t i = fidx(s, k, c, sh.nrhs);
-                cpx<R> xv = ldc(x, i), rv = ldc(r, i);
-                const cpx<R> pv = HAS_P ? ldc(p, i) : rv, qv = ldc(q, i);
-                cmac(xv, a, pv);
-                cmac(rv, na, qv);
-                stc(x, i, xv);
-                stc(r, i, rv);
-                // the norm of the value actually stored
-                const cpx<R> rs = ldc(r, i);
-                rr = fma(rs.re, rs.re, fma(rs.im, rs.im, rr));
+        for (int v = 0; v < NV; ++v) {
+            const int site = tile * 64 + (((v * 64 + lane) * N) & 63);
+            if (site < sh.g.V) {
+                const size_t i = base + v * 64 + lane;
+                const uint4 xv = x[i], rv = r[i], qv = q[i];
+                cpx<R> xc[N], rc[N], qc[N], pc[N];
+                IO::get(xv, xc);
+                IO::get(rv, rc);
+                IO::get(qv, qc);
+                if (HAS_P) IO::get(p[i], pc);
+#pragma unroll
+                for (int e = 0; e < N; ++e) {
+                    cmac(xc[e], a, HAS_P ? pc[e] : rc[e]);
+                    cmac(rc[e], na, qc[e]);
+                }
+                const uint4 ro = IO::put(rc);
+                x[i] = IO::put(xc);
+                r[i] = ro;
+                IO::get(ro, rc);  // the norm of the values as stored
+#pragma unroll
+                for (int e = 0; e < N; ++e) rr = fma(rc[e].re, rc[e].re, fma(rc[e].im, rc[e].im, rr));
             }
         }
-        const double v[1] = {(double)rr};
-        part.add(k, v);
+        const double t = wave_sum((double)rr);
+        if (lane == 0) red[wave][k] += t;
     }
-    SITE_LOOP_END
-    part.flush(partials);
+    __syncthreads();
+    for (int i = threadIdx.x; i < sh.nrhs; i += blockDim.x)
+        partials[(size_t)blockIdx.x * sh.nrhs + i] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
 }
 
 template <int P>
@@ -202,6 +276,106 @@ __global__ void __launch_bounds__(256) xmy_kernel(BlasShape sh, const double2 *x
         }
     }
     SITE_LOOP_END
+}
+
+static bool shape_ok(const BlasShape &sh);
+
+// ------------------------------------------------------------------ section 3 approximation
+// The pieces of S~_bb x = [D (u - M y)]_b, M = d^{-1} + d~^{-1} - d^{-1} D_rr d~^{-1},
+// y = D_rb u, d = 4 + m0 and d~ = D_rr 1 (row sums):
+//   ones:     1 on every rest-site dof (one field), 0 on the coarse sites
+//   divide:   t = y / d~ on the rest sites, 0 on the coarse sites
+//   combine:  w = u - ((y - D_rr t) / d + t) on the rest sites, u on the coarse sites
+__global__ void __launch_bounds__(256) rest_ones_kernel(BlasShape sh, const uint8_t *mask, double2 *o)
+{
+    SITE_LOOP_BEGIN(sh)
+    if (valid) {
+        const double v = mask[s] == 0 ? 1.0 : 0.0;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) o[fidx(s, 0, c, 1)] = make_double2(v, 0.0);
+    }
+    SITE_LOOP_END
+}
+
+__global__ void __launch_bounds__(256) reusken_divide_kernel(BlasShape sh, const double2 *y,
+                                                             const double2 *dt, const uint8_t *mask,
+                                                             double2 *t)
+{
+    SITE_LOOP_BEGIN(sh)
+    if (valid) {
+        const bool rest = mask[s] == 0;
+        for (int k = 0; k < sh.nrhs; ++k) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const size_t i = fidx(s, k, c, sh.nrhs);
+                double2 o = make_double2(0.0, 0.0);
+                if (rest) {
+                    const double2 a = y[i], b = dt[fidx(s, 0, c, 1)];
+                    const double den = b.x * b.x + b.y * b.y;
+                    o = make_double2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
+                }
+                t[i] = o;
+            }
+        }
+    }
+    SITE_LOOP_END
+}
+
+__global__ void __launch_bounds__(256) reusken_combine_kernel(BlasShape sh, const double2 *u,
+                                                              const double2 *y, const double2 *z,
+                                                              const double2 *t, const uint8_t *mask,
+                                                              double inv_d, double2 *w)
+{
+    SITE_LOOP_BEGIN(sh)
+    if (valid) {
+        const bool rest = mask[s] == 0;
+        for (int k = 0; k < sh.nrhs; ++k) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const size_t i = fidx(s, k, c, sh.nrhs);
+                const double2 uv = u[i];
+                double2 o = uv;
+                if (rest) {
+                    const double2 yv = y[i], zv = z[i], tv = t[i];
+                    o = make_double2(uv.x - ((yv.x - zv.x) * inv_d + tv.x),
+                                     uv.y - ((yv.y - zv.y) * inv_d + tv.y));
+                }
+                w[i] = o;
+            }
+        }
+    }
+    SITE_LOOP_END
+}
+
+hipError_t launch_rest_ones(const Geom &g, const uint8_t *mask, void *o, hipStream_t st)
+{
+    BlasShape sh;
+    sh.g = g;
+    sh.nrhs = 1;
+    const int blocks = (g.V + 255) / 256;
+    sh.grid = blocks < 8 ? 8 : blocks > 2048 ? 2048 : (blocks + 7) / 8 * 8;
+    hipLaunchKernelGGL(rest_ones_kernel, dim3(sh.grid), dim3(kBlasSB), 0, st, sh, mask, (double2 *)o);
+    return hipGetLastError();
+}
+
+hipError_t launch_reusken_divide(const BlasShape &sh, const void *y, const void *dt,
+                                 const uint8_t *mask, void *t, hipStream_t st)
+{
+    if (!shape_ok(sh)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(reusken_divide_kernel, dim3(sh.grid), dim3(kBlasSB), 0, st, sh,
+                       (const double2 *)y, (const double2 *)dt, mask, (double2 *)t);
+    return hipGetLastError();
+}
+
+hipError_t launch_reusken_combine(const BlasShape &sh, const void *u, const void *y, const void *z,
+                                  const void *t, const uint8_t *mask, double inv_d, void *w,
+                                  hipStream_t st)
+{
+    if (!shape_ok(sh)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(reusken_combine_kernel, dim3(sh.grid), dim3(kBlasSB), 0, st, sh,
+                       (const double2 *)u, (const double2 *)y, (const double2 *)z, (const double2 *)t,
+                       mask, inv_d, (double2 *)w);
+    return hipGetLastError();
 }
 
 template <int P>

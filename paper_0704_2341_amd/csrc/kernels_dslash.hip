@@ -28,7 +28,7 @@ namespace grg {
 
 // out = mask_sel D in, for nrhs fields.  With a.partials set, also the
 // per-workgroup partial sums of conj(out).in (re, im) and |out|^2 per RHS.
-template <int P, bool SPLIT>
+template <int P, int SPLIT>
 __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
 {
     typedef typename Store<P>::S S;
@@ -115,43 +115,129 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
 // can hold at this footprint, thus cost nothing beyond the slice itself, and
 // the links of a site are read once for all RG right-hand sides (the RG
 // wavefronts of a workgroup request the same lines together).
+// Epilogues of the t-marching stencil: what happens to the finished sum acc of
+// site s, RHS r.  K partial sums per RHS are accumulated per workgroup.
+//
+// StoreEpi: out = acc on the selected rows (zero elsewhere), with the solver's
+// fused sums conj(out).w (re, im) and |out|^2, w = dot_with or in.
 template <int P>
-__device__ __forceinline__ void march_store(DslashArgs &a, cpx<typename Store<P>::R> (&acc)[12],
-                                            int s, int r, bool valid, double (&dot)[3])
-{
-    typedef typename Store<P>::S S;
+struct StoreEpi {
+    typedef typename Store<P>::S SIN;
+    typedef SIN SU;
     typedef typename Store<P>::R R;
-    const bool on = valid && (a.mask == nullptr || a.mask[s] == a.sel);
-    if (!valid) return;
-    S *out = (S *)a.out;
-    const S *in = (const S *)(a.dot_with ? a.dot_with : a.in);
+    typedef DslashArgs Args;
+    static constexpr int K = 3;
+    static constexpr int kThreads = P == GRG_FP64 ? 512 : 768;
+    __device__ static const SIN *input(const Args &a) { return (const SIN *)a.in; }
+    __device__ static const SU *links(const Args &a) { return (const SU *)a.U; }
+    __device__ static double *partials(const Args &a) { return a.partials; }
+    __device__ static void store(const Args &a, cpx<R> (&acc)[12], int s, int r, bool valid,
+                                 double (&dot)[K])
+    {
+        if (!valid) return;
+        const bool on = a.mask == nullptr || a.mask[s] == a.sel;
+        SIN *out = (SIN *)a.out;
+        const SIN *w = (const SIN *)(a.dot_with ? a.dot_with : a.in);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-        const size_t i = fidx(s, r, c, a.nrhs);
-        const cpx<R> o = on ? acc[c] : cpx<R>{0, 0};
-        stc(out, i, o);
-        if (a.partials && on) {
-            const cpx<R> v = ldc(in, i);
-            dot[0] += (double)o.re * v.re + (double)o.im * v.im;
-            dot[1] += (double)o.re * v.im - (double)o.im * v.re;
-            dot[2] += (double)o.re * o.re + (double)o.im * o.im;
+        for (int c = 0; c < 12; ++c) {
+            const size_t i = fidx(s, r, c, a.nrhs);
+            const cpx<R> o = on ? acc[c] : cpx<R>{0, 0};
+            stc(out, i, o);
+            if (a.partials && on) {
+                const cpx<R> v = ldc(w, i);
+                dot[0] += (double)o.re * v.re + (double)o.im * v.im;
+                dot[1] += (double)o.re * v.im - (double)o.im * v.re;
+                dot[2] += (double)o.re * o.re + (double)o.im * o.im;
+            }
         }
     }
-}
+};
 
-// Largest workgroup of the t-marching kernel: 12 RHS wavefronts in FP32/BF16
-// (<= 170 VGPRs at 3 waves per SIMD), 8 in FP64.
-__host__ __device__ constexpr int march_max_threads(int prec) { return prec == GRG_FP64 ? 512 : 768; }
-
+// DcEpi: one FP64 defect-correction step on the rest sites (see
+// dc_update_kernel): r_out = r_in - f acc, x_out = x_in + f e, r_next =
+// s_next r_out, and |r_out|^2.  The stencil of e runs in FP64 with FP64 links.
 template <int P>
-__global__ void __launch_bounds__(march_max_threads(P)) dslash_march_kernel(DslashArgs a)
+struct DcEpi {
+    typedef typename Store<P>::S SIN;
+    typedef double2 SU;
+    typedef double R;
+    typedef DcArgs Args;
+    static constexpr int K = 1;
+    static constexpr int kThreads = 512;
+    __device__ static const SIN *input(const Args &a) { return (const SIN *)a.e; }
+    __device__ static const SU *links(const Args &a) { return (const SU *)a.U; }
+    __device__ static double *partials(const Args &a) { return a.partials; }
+    __device__ static void store(const Args &a, cpx<double> (&acc)[12], int s, int r, bool valid,
+                                 double (&nrm)[K])
+    {
+        if (!valid) return;
+        typedef typename Store<P>::R RN;
+        const bool on = a.mask[s] == 0;
+        const double2 *r_in = (const double2 *)a.r_in;
+        const double2 *x_in = (const double2 *)a.x_in;
+        double2 *r_out = (double2 *)a.r_out;
+        double2 *x_out = (double2 *)a.x_out;
+        SIN *r_next = (SIN *)a.r_next;
+        const SIN *e = (const SIN *)a.e;
+        const double f = a.f[r];
+        const double sn = r_next ? a.s_next[r] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            // three components at a time: a compiler barrier keeps the
+            // streams' loads from being hoisted all at once (registers)
+            if (c % 3 == 0) asm volatile("" ::: "memory");
+            const size_t i = fidx(s, r, c, a.nrhs);
+            if (on) {
+                const double2 rv = r_in[i];
+                const double2 d = make_double2(rv.x - f * acc[c].re, rv.y - f * acc[c].im);
+                r_out[i] = d;
+                if (r_next) stc(r_next, i, cpx<RN>{(RN)(sn * d.x), (RN)(sn * d.y)});
+                nrm[0] += d.x * d.x + d.y * d.y;
+                const cpx<double> ev = ldr<double>(e, i);
+                const double2 xv = x_in ? x_in[i] : make_double2(0.0, 0.0);
+                x_out[i] = make_double2(xv.x + f * ev.re, xv.y + f * ev.im);
+            } else {
+                r_out[i] = make_double2(0.0, 0.0);
+                x_out[i] = make_double2(0.0, 0.0);
+                if (r_next) stc(r_next, i, cpx<RN>{0, 0});
+            }
+        }
+    }
+};
+
+// t-marching stencil.  A workgroup owns 64 sites of one x-y-z plane (one
+// wavefront of sites) for RG right-hand sides (one wavefront per RHS), over a
+// chunk of T consecutive time slices, and walks t upwards.  psi(t) is loaded
+// once and used three times from registers: as the diagonal term of site t,
+// in the backward t-hop of site t+1 and in the forward t-hop of site t-1;
+// U_t(t) serves the backward hop of t+1 now and the forward hop of t on the
+// next step.  The t-neighbours, whose reuse distance (a whole 3-d slice) no L2
+// can hold at this footprint, thus cost nothing beyond the slice itself, and
+// the links of a site are read once for all RG right-hand sides (the RG
+// wavefronts of a workgroup request the same lines together).  Wavefront wv
+// of an item with RHS group grp holds RHS grp * RG + wv, so it only ever sees
+// RHS with r % RG == wv: the per-RHS sums of the workgroup's items go to LDS
+// rows no other wavefront writes.
+template <class E>
+__global__ void __launch_bounds__(E::kThreads) march_kernel(typename E::Args a)
 {
-    typedef typename Store<P>::S S;
-    typedef typename Store<P>::R R;
-    __shared__ double red[16][3];
-    const S *__restrict__ in = (const S *)a.in;
-    const S *__restrict__ U = (const S *)a.U;
+    typedef typename E::SIN S;
+    typedef typename E::SU SU;
+    typedef typename E::R R;
+    typedef Operand<S, R> OP;
+    typedef Operand<SU, R> OU;
+    typedef typename OP::T PT;
+    typedef typename OU::T UT;
+    constexpr int K = E::K;
+    __shared__ double red[kMaxRhs][K];
+    const S *__restrict__ in = E::input(a);
+    const SU *__restrict__ U = E::links(a);
+    double *partials = E::partials(a);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (partials) {
+        for (int i = threadIdx.x; i < kMaxRhs * K; i += blockDim.x) red[i / K][i % K] = 0.0;
+        __syncthreads();
+    }
     const int V3 = a.g.L[0] * a.g.L[1] * a.g.L[2], Lt = a.g.L[3];
     const int nb3 = (V3 + 63) >> 6;
     const int T = a.march;
@@ -159,7 +245,9 @@ __global__ void __launch_bounds__(march_max_threads(P)) dslash_march_kernel(Dsla
     const int ngroups = (a.nrhs + a.RG - 1) / a.RG;
     const int nitems = nb3 * ntc * ngroups;
     const R diag = (R)a.diag;
-    double dot[3] = {0, 0, 0};
+    double dot[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) dot[k] = 0.0;
     const int C = a.chunk > 0 ? a.chunk : (nitems + 7) / 8;
     for (int j = blockIdx.x >> 3;; j += gridDim.x >> 3) {
         const int w = xcd_chunk_item(j, C, nitems);
@@ -174,33 +262,39 @@ __global__ void __launch_bounds__(march_max_threads(P)) dslash_march_kernel(Dsla
         const int t0 = tc * T, t1 = min(t0 + T, Lt);
         SiteGeo q = site_geo(s3c, a.g);
         // prologue: backward t-hop of site t0 from psi(t0 - 1)
-        cpx<R> acc_cur[12], acc_prev[12], ut_prev[9];
+        cpx<R> acc_cur[12], acc_prev[12];
+        UT ut_prev[9];
         {
             const int sm = s3c + V3 * (t0 == 0 ? Lt - 1 : t0 - 1);
-            cpx<R> p[12], u[9];
+            PT p[12];
+            UT u[9];
 #pragma unroll
-            for (int c = 0; c < 12; ++c) p[c] = ldc(in, fidx(sm, r, c, a.nrhs));
+            for (int c = 0; c < 12; ++c) p[c] = OP::load(in, fidx(sm, r, c, a.nrhs));
 #pragma unroll
-            for (int e = 0; e < 9; ++e) u[e] = ldc(U, lidx(sm, 3, e));
+            for (int e = 0; e < 9; ++e) u[e] = OU::load(U, lidx(sm, 3, e));
 #pragma unroll
             for (int c = 0; c < 12; ++c) acc_cur[c] = {0, 0};
-            hop_math<3, false>(acc_cur, p, u);
+            hop<3, false>(acc_cur, p, u);
         }
 #pragma unroll 1
         for (int t = t0; t < t1; ++t) {
             const int s = s3c + V3 * t;
             q.c[3] = t;
-            cpx<R> psi[12];
+            PT psi[12];
 #pragma unroll
-            for (int c = 0; c < 12; ++c) psi[c] = ldc(in, fidx(s, r, c, a.nrhs));
+            for (int c = 0; c < 12; ++c) psi[c] = OP::load(in, fidx(s, r, c, a.nrhs));
+            // wide (FP64) psi is not kept live across the x, y, z hops: it is
+            // loaded again (from cache) for the backward t-hop below
+            constexpr bool kKeep = sizeof(PT) <= 8;
             if (t > t0) {  // finish site t - 1 with its forward t-hop
-                hop_math<3, true>(acc_prev, psi, ut_prev);
-                march_store<P>(a, acc_prev, s - V3, r, valid, dot);
+                hop<3, true>(acc_prev, psi, ut_prev);
+                E::store(a, acc_prev, s - V3, r, valid, dot);
             }
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                acc_cur[c].re += diag * psi[c].re;
-                acc_cur[c].im += diag * psi[c].im;
+                const auto v = as_cpx(psi[c]);
+                acc_cur[c].re += diag * (R)v.re;
+                acc_cur[c].im += diag * (R)v.im;
             }
 #pragma unroll 1
             for (int h = 0; h < 6; ++h) {  // x, y, z hops, one at a time
@@ -208,66 +302,73 @@ __global__ void __launch_bounds__(march_max_threads(P)) dslash_march_kernel(Dsla
                 int sp, sm;
                 nbr(s, mu, q, a.g, sp, sm);
                 const int n = (h & 1) ? sm : sp;
-                cpx<R> p[12], u[9];
+                PT p[12];
+                UT u[9];
 #pragma unroll
-                for (int c = 0; c < 12; ++c) p[c] = ldc(in, fidx(n, r, c, a.nrhs));
+                for (int c = 0; c < 12; ++c) p[c] = OP::load(in, fidx(n, r, c, a.nrhs));
 #pragma unroll
-                for (int e = 0; e < 9; ++e) u[e] = ldc(U, lidx((h & 1) ? sm : s, mu, e));
+                for (int e = 0; e < 9; ++e) u[e] = OU::load(U, lidx((h & 1) ? sm : s, mu, e));
                 switch (h) {
-                case 0: hop_math<0, true>(acc_cur, p, u); break;
-                case 1: hop_math<0, false>(acc_cur, p, u); break;
-                case 2: hop_math<1, true>(acc_cur, p, u); break;
-                case 3: hop_math<1, false>(acc_cur, p, u); break;
-                case 4: hop_math<2, true>(acc_cur, p, u); break;
-                default: hop_math<2, false>(acc_cur, p, u); break;
+                case 0: hop<0, true>(acc_cur, p, u); break;
+                case 1: hop<0, false>(acc_cur, p, u); break;
+                case 2: hop<1, true>(acc_cur, p, u); break;
+                case 3: hop<1, false>(acc_cur, p, u); break;
+                case 4: hop<2, true>(acc_cur, p, u); break;
+                default: hop<2, false>(acc_cur, p, u); break;
                 }
             }
             // backward t-hop of site t + 1, from psi(t) and U_t(t)
 #pragma unroll
-            for (int e = 0; e < 9; ++e) ut_prev[e] = ldc(U, lidx(s, 3, e));
+            for (int e = 0; e < 9; ++e) ut_prev[e] = OU::load(U, lidx(s, 3, e));
+            if (!kKeep) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) psi[c] = OP::load(in, fidx(s, r, c, a.nrhs));
+            }
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 acc_prev[c] = acc_cur[c];
                 acc_cur[c] = {0, 0};
             }
-            hop_math<3, false>(acc_cur, psi, ut_prev);
+            hop<3, false>(acc_cur, psi, ut_prev);
         }
         // epilogue: forward t-hop of site t1 - 1 from psi(t1)
         {
             const int sp = s3c + V3 * (t1 == Lt ? 0 : t1);
-            cpx<R> p[12];
+            PT p[12];
 #pragma unroll
-            for (int c = 0; c < 12; ++c) p[c] = ldc(in, fidx(sp, r, c, a.nrhs));
-            hop_math<3, true>(acc_prev, p, ut_prev);
-            march_store<P>(a, acc_prev, s3c + V3 * (t1 - 1), r, valid, dot);
+            for (int c = 0; c < 12; ++c) p[c] = OP::load(in, fidx(sp, r, c, a.nrhs));
+            hop<3, true>(acc_prev, p, ut_prev);
+            E::store(a, acc_prev, s3c + V3 * (t1 - 1), r, valid, dot);
+        }
+        if (partials) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const double t = wave_sum(dot[k]);
+                if (lane == 0) red[r][k] += t;
+                dot[k] = 0.0;
+            }
         }
     }
-    if (a.partials) {
-        // one wavefront per RHS slot: reduce over lanes, then over the
-        // workgroup's items; slot wv holds RHS grp * RG + wv of each item
-        // (with RG == nrhs every workgroup covers every RHS)
-        for (int k = 0; k < 3; ++k) dot[k] = wave_sum(dot[k]);
-        if (lane == 0)
-            for (int k = 0; k < 3; ++k) red[wv][k] = dot[k];
+    if (partials) {
         __syncthreads();
-        for (int i = threadIdx.x; i < a.nrhs * 3; i += blockDim.x) {
-            const int rr = i / 3, k = i % 3;
-            a.partials[(size_t)blockIdx.x * a.nrhs * 3 + i] = (rr < (int)(blockDim.x >> 6)) ? red[rr][k] : 0.0;
-        }
+        for (int i = threadIdx.x; i < a.nrhs * K; i += blockDim.x)
+            partials[(size_t)blockIdx.x * a.nrhs * K + i] = red[i / K][i % K];
     }
 }
 
 // One FP64 defect-correction step, fused.  e is the inner solution (stored in
-// precision P, zero on coarse sites), f_k = sqrt(fr2[k]) the outer residual
-// norm it was normalised by:
+// precision P, zero on coarse sites) of A e = r_in / f_k:
 //     r_out = r_in - f (D_rr e)        x_out = x_in + f e        (FP64)
 // on the r-sites; coarse sites are written as zero.  x_in == nullptr reads as
-// zero.  Also the per-workgroup partial sums of |r_out|^2 per RHS.  r_out may
-// alias r_in and x_out may alias x_in (each thread touches only its own site).
+// zero.  With r_next set, also r_next = s_next r_out in precision P (the next
+// inner right-hand side), and always the per-workgroup partial sums of
+// |r_out|^2 per RHS.  r_out may alias r_in and x_out may alias x_in (each
+// thread touches only its own site).
 template <int P>
 __global__ void __launch_bounds__(256) dc_update_kernel(DcArgs a)
 {
     typedef typename Store<P>::S S;
+    typedef typename Store<P>::R R;
     __shared__ double red[4][kMaxRhs];
     const S *__restrict__ e = (const S *)a.e;
     const double2 *__restrict__ U = (const double2 *)a.U;
@@ -275,6 +376,7 @@ __global__ void __launch_bounds__(256) dc_update_kernel(DcArgs a)
     const double2 *x_in = (const double2 *)a.x_in;
     double2 *r_out = (double2 *)a.r_out;
     double2 *x_out = (double2 *)a.x_out;
+    S *r_next = (S *)a.r_next;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int i = lane; i < a.nrhs; i += 64) red[wave][i] = 0.0;
     __syncthreads();
@@ -291,13 +393,15 @@ __global__ void __launch_bounds__(256) dc_update_kernel(DcArgs a)
             if (on) {
                 cpx<double> acc[12];
                 dslash_site<S, double, true, double2>(acc, e, U, s, q, a.g, r, a.nrhs, a.diag);
-                const double f = sqrt(a.fr2[r]);
+                const double f = a.f[r];
+                const double sn = r_next ? a.s_next[r] : 0.0;
 #pragma unroll
                 for (int c = 0; c < 12; ++c) {
                     const size_t i = fidx(s, r, c, a.nrhs);
                     const double2 rv = r_in[i];
                     const double2 d = make_double2(rv.x - f * acc[c].re, rv.y - f * acc[c].im);
                     r_out[i] = d;
+                    if (r_next) stc(r_next, i, cpx<R>{(R)(sn * d.x), (R)(sn * d.y)});
                     nrm += d.x * d.x + d.y * d.y;
                     const cpx<double> ev = ldr<double>(e, i);
                     const double2 xv = x_in ? x_in[i] : make_double2(0.0, 0.0);
@@ -309,6 +413,7 @@ __global__ void __launch_bounds__(256) dc_update_kernel(DcArgs a)
                     const size_t i = fidx(s, r, c, a.nrhs);
                     r_out[i] = make_double2(0.0, 0.0);
                     x_out[i] = make_double2(0.0, 0.0);
+                    if (r_next) stc(r_next, i, cpx<R>{0, 0});
                 }
             }
             nrm = wave_sum(nrm);
@@ -440,14 +545,13 @@ hipError_t launch_dslash(int prec, const DslashArgs &a, int grid, hipStream_t st
     if (a.nrhs < 1 || a.nrhs > kMaxRhs || a.RG < 1) return hipErrorInvalidValue;
     if (grid < 8 || grid % 8) return hipErrorInvalidValue;
     if (a.march > 0) {
-        // one wavefront per RHS of a group; fused dots need the whole batch per workgroup
-        if (64 * a.RG > march_max_threads(prec) || (a.partials && a.RG != a.nrhs))
-            return hipErrorInvalidValue;
+        // one wavefront per RHS of a group
+        if (64 * a.RG > (prec == GRG_FP64 ? 512 : 768)) return hipErrorInvalidValue;
         dim3 blk(64 * a.RG), grd(grid);
         switch (prec) {
-        case GRG_FP64: hipLaunchKernelGGL(dslash_march_kernel<GRG_FP64>, grd, blk, 0, st, a); break;
-        case GRG_FP32: hipLaunchKernelGGL(dslash_march_kernel<GRG_FP32>, grd, blk, 0, st, a); break;
-        case GRG_BF16: hipLaunchKernelGGL(dslash_march_kernel<GRG_BF16>, grd, blk, 0, st, a); break;
+        case GRG_FP64: hipLaunchKernelGGL(march_kernel<StoreEpi<GRG_FP64>>, grd, blk, 0, st, a); break;
+        case GRG_FP32: hipLaunchKernelGGL(march_kernel<StoreEpi<GRG_FP32>>, grd, blk, 0, st, a); break;
+        case GRG_BF16: hipLaunchKernelGGL(march_kernel<StoreEpi<GRG_BF16>>, grd, blk, 0, st, a); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
@@ -455,8 +559,9 @@ hipError_t launch_dslash(int prec, const DslashArgs &a, int grid, hipStream_t st
     if (a.SB != 256 && a.SB != 128 && a.SB != 64) return hipErrorInvalidValue;
     dim3 blk(a.SB), grd(grid);
 #define DSL(PP)                                                                                 \
-    if (a.split) hipLaunchKernelGGL((dslash_kernel<PP, true>), grd, blk, 0, st, a);             \
-    else hipLaunchKernelGGL((dslash_kernel<PP, false>), grd, blk, 0, st, a);
+    if (a.split == 2) hipLaunchKernelGGL((dslash_kernel<PP, 2>), grd, blk, 0, st, a);           \
+    else if (a.split) hipLaunchKernelGGL((dslash_kernel<PP, 1>), grd, blk, 0, st, a);           \
+    else hipLaunchKernelGGL((dslash_kernel<PP, 0>), grd, blk, 0, st, a);
     switch (prec) {
     case GRG_FP64: DSL(GRG_FP64) break;
     case GRG_FP32: DSL(GRG_FP32) break;
@@ -470,6 +575,17 @@ hipError_t launch_dslash(int prec, const DslashArgs &a, int grid, hipStream_t st
 hipError_t launch_dc_update(int prec, const DcArgs &a, int grid, int SB, hipStream_t st)
 {
     if (a.nrhs < 1 || a.nrhs > kMaxRhs || grid < 8 || grid % 8) return hipErrorInvalidValue;
+    if (a.march > 0) {
+        if (a.RG < 1 || 64 * a.RG > 512) return hipErrorInvalidValue;
+        dim3 blk(64 * a.RG), grd(grid);
+        switch (prec) {
+        case GRG_FP64: hipLaunchKernelGGL(march_kernel<DcEpi<GRG_FP64>>, grd, blk, 0, st, a); break;
+        case GRG_FP32: hipLaunchKernelGGL(march_kernel<DcEpi<GRG_FP32>>, grd, blk, 0, st, a); break;
+        case GRG_BF16: hipLaunchKernelGGL(march_kernel<DcEpi<GRG_BF16>>, grd, blk, 0, st, a); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     if (SB != 64 && SB != 128 && SB != 256) return hipErrorInvalidValue;
     switch (prec) {
     case GRG_FP64: hipLaunchKernelGGL(dc_update_kernel<GRG_FP64>, dim3(grid), dim3(SB), 0, st, a); break;

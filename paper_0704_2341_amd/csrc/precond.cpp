@@ -341,7 +341,7 @@ grg_status grg_precond_train(grg_precond P, const grg_train_params *tp, grg_trai
     const int dgrid = default_tune(L->g, GRG_BF16, B).grid;
     // the solver's tuned launches with fused dots need this grid for the reduce
     const DslashTune &tt = S->tune[GRG_BF16][B];
-    const int agrid = tt.valid && !(tt.march > 0 && tt.RG != B) ? tt.grid : dgrid;
+    const int agrid = tt.valid ? tt.grid : dgrid;
     std::mt19937_64 rng(tp->seed);
     // -1 per RHS for e = e_0 - x
     std::vector<double> neg(kMaxRhs, -1.0);

@@ -82,17 +82,16 @@ static grg_status launch_tuned(grg_lattice L, int prec, const DslashTune &t, con
     return GRG_OK;
 }
 
-// Validity of a launch shape for (prec, nrhs); the solver's fused dot
-// products additionally need a t-marching workgroup to hold every RHS.
-bool launch_ok(const Geom &g, int prec, int nrhs, const DslashTune &t, bool dots)
+// Validity of a launch shape for (prec, nrhs).
+bool launch_ok(const Geom &g, int prec, int nrhs, const DslashTune &t, bool)
 {
     if (t.grid < 8 || t.grid % 8 || t.grid > kMaxGridValue || t.chunk < 0 || t.march < 0) return false;
     if (t.march > 0) {
-        if (t.march > g.L[3] || t.RG < 1 || 64 * t.RG > (prec == GRG_FP64 ? 512 : 768)) return false;
-        return !dots || t.RG == nrhs;
+        return t.march <= g.L[3] && t.RG >= 1 && t.RG <= nrhs &&
+               64 * t.RG <= (prec == GRG_FP64 ? 512 : 768);
     }
     return (t.SB == 64 || t.SB == 128 || t.SB == 256) && t.RG >= 1 && t.RG <= nrhs &&
-           (t.split == 0 || t.split == 1);
+           (t.split == 0 || t.split == 1 || (t.split == 2 && prec == GRG_BF16));
 }
 
 // One stencil launch, bracketed by profiling events when enabled.
@@ -100,9 +99,7 @@ grg_status run_dslash(grg_schur S, int prec, const void *in, void *out, int sel,
                       double *partials, const void *dot_with = nullptr)
 {
     grg_lattice L = S->lat;
-    DslashTune t = S->tune[prec][nrhs].valid ? S->tune[prec][nrhs] : default_tune(L->g, prec, nrhs);
-    // fused dot products need every RHS of a t-marching workgroup
-    if (partials && t.march > 0 && t.RG != nrhs) t = default_tune(L->g, prec, nrhs);
+    const DslashTune t = S->tune[prec][nrhs].valid ? S->tune[prec][nrhs] : default_tune(L->g, prec, nrhs);
     ProfilePool &P = S->prof;
     const bool ev = P.on && P.used < (int)P.start.size();
     if (ev) GRG_TRY_HIP(hipEventRecord(P.start[P.used], L->stream));
@@ -164,7 +161,7 @@ grg_status tune_dslash(grg_schur S, int prec, int nrhs, int reps)
         for (int rg = 1; rg <= nrhs; ++rg) {
             if (nrhs % rg && rg != nrhs) continue;
             if (rg > 4 && rg != nrhs) continue;
-            for (int split = 0; split < 2; ++split) {
+            for (int split = 0; split < (prec == GRG_BF16 ? 3 : 2); ++split) {
                 DslashTune t;
                 t.SB = sb;
                 t.RG = rg;
@@ -176,17 +173,21 @@ grg_status tune_dslash(grg_schur S, int prec, int nrhs, int reps)
             }
         }
     }
-    // t-marching kernel: one workgroup = 64 sites x all RHS, time chunks of T
-    if (64 * nrhs <= (prec == GRG_FP64 ? 512 : 768)) {
-        const int V3 = g.L[0] * g.L[1] * g.L[2];
-        const int nb3 = (V3 + 63) / 64;
+    // t-marching kernel: one workgroup = 64 sites x RG RHS (one wavefront
+    // each), time chunks of T; RG = nrhs or a divisor of it that fits a
+    // workgroup
+    const int V3 = g.L[0] * g.L[1] * g.L[2];
+    const int nb3 = (V3 + 63) / 64;
+    const int max_rg = (prec == GRG_FP64 ? 512 : 768) / 64;
+    for (int rg = std::min(nrhs, max_rg); rg >= 1; --rg) {
+        if (nrhs % rg) continue;
         for (int T = 2; T <= g.L[3]; T *= 2) {
             DslashTune t;
             t.march = T;
             t.SB = 64;
-            t.RG = nrhs;
+            t.RG = rg;
             t.split = 0;
-            const long items = (long)nb3 * ((g.L[3] + T - 1) / T);
+            const long items = (long)nb3 * ((g.L[3] + T - 1) / T) * (nrhs / rg);
             t.grid = round8(std::min<long>(items, 2048));
             t.valid = 1;
             timeit(t);
@@ -219,6 +220,112 @@ grg_status tune_dslash(grg_schur S, int prec, int nrhs, int reps)
     if (status != GRG_OK) return status;
     best.valid = 1;
     S->tune[prec][nrhs] = best;
+    return GRG_OK;
+}
+
+// Launch of the fused defect-correction step: the site-parallel kernel
+// (march == 0: SB threads, grid-stride over sites) or the t-marching kernel.
+DslashTune default_dc_tune(const Geom &g)
+{
+    DslashTune t;
+    t.SB = 128;
+    t.RG = 1;
+    t.grid = round8(std::min<long>((g.V + 127) / 128, 2048));
+    return t;
+}
+
+bool dc_launch_ok(const Geom &g, int nrhs, const DslashTune &t)
+{
+    if (t.grid < 8 || t.grid % 8 || t.grid > kMaxGridValue || t.chunk < 0 || t.march < 0) return false;
+    if (t.march > 0) return t.march <= g.L[3] && t.RG >= 1 && t.RG <= nrhs && 64 * t.RG <= 512;
+    return t.SB == 64 || t.SB == 128 || t.SB == 256;
+}
+
+static void dc_fill_launch(DcArgs &d, const DslashTune &t)
+{
+    d.RG = t.RG;
+    d.chunk = t.chunk;
+    d.march = t.march;
+}
+
+// Autotuner of the defect-correction step (inner precision prec), timed on
+// the handle's workspaces; every candidate computes the same sums in the
+// same order per site.
+grg_status tune_dc(grg_schur S, int prec, int nrhs, int reps)
+{
+    grg_lattice L = S->lat;
+    hipStream_t st = L->stream;
+    const Geom &g = L->g;
+    GRG_TRY(ensure_inner(S, prec));
+    DcArgs d;
+    d.e = S->in_b[prec];
+    d.U = L->U[GRG_FP64];
+    d.r_in = S->b64;
+    d.x_in = nullptr;
+    d.r_out = S->t64;
+    d.x_out = S->r64;
+    d.f = S->bn2 + kMaxRhs;
+    d.r_next = S->in_q[prec];
+    d.s_next = S->bn2 + 3 * kMaxRhs;
+    d.mask = S->d_mask;
+    d.diag = 4.0 + S->m0;
+    d.g = g;
+    d.nrhs = nrhs;
+    d.partials = S->partials;
+    hipEvent_t e0, e1;
+    GRG_TRY_HIP(hipEventCreate(&e0));
+    GRG_TRY_HIP(hipEventCreate(&e1));
+    grg_status status = GRG_OK;
+    DslashTune best = default_dc_tune(g);
+    best.ms = 1e30f;
+    auto timeit = [&](DslashTune t) {
+        if (status != GRG_OK || !dc_launch_ok(g, nrhs, t)) return;
+        dc_fill_launch(d, t);
+        hipError_t e = launch_dc_update(prec, d, t.grid, t.SB, st);
+        for (int k = 0; k < reps && e == hipSuccess; ++k) {
+            if (k == 0) e = hipEventRecord(e0, st);
+            if (e == hipSuccess) e = launch_dc_update(prec, d, t.grid, t.SB, st);
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e != hipSuccess) {
+            set_error("defect-correction tuning: %s", hipGetErrorString(e));
+            status = GRG_EHIP;
+            return;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        t.ms = ms / reps;
+        if (t.ms < best.ms) best = t;
+    };
+    for (int sb : {64, 128, 256}) {
+        DslashTune t = default_dc_tune(g);
+        t.SB = sb;
+        t.grid = round8(std::min<long>((g.V + sb - 1) / sb, 2048));
+        timeit(t);
+    }
+    const int nb3 = (g.L[0] * g.L[1] * g.L[2] + 63) / 64;
+    for (int rg = std::min(nrhs, 8); rg >= 1; --rg) {
+        if (nrhs % rg) continue;
+        for (int T = 2; T <= g.L[3]; T *= 2) {
+            for (int ch : {0, 8}) {
+                DslashTune t;
+                t.march = T;
+                t.SB = 64;
+                t.RG = rg;
+                t.chunk = ch;
+                const long items = (long)nb3 * ((g.L[3] + T - 1) / T) * (nrhs / rg);
+                if (ch > 0 && ch * 8 >= items) continue;
+                t.grid = round8(std::min<long>(items, 2048));
+                timeit(t);
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status != GRG_OK) return status;
+    best.valid = 1;
+    S->dctune[prec][nrhs] = best;
     return GRG_OK;
 }
 
@@ -263,12 +370,12 @@ grg_status ensure_inner(grg_schur S, int prec)
     return GRG_OK;
 }
 
-// Inner GCR(m) on D_rr in precision prec: solves A x = b (in_b -> in_x) until
-// |r|^2 <= thr[k] per RHS (thr: host copy of the device array thr2) or maxit
-// iterations.
-// Returns the iterations taken in *iters.
+// Inner GCR(m) on D_rr in precision prec: solves A x = b, with b already in
+// in_r (it becomes the residual) and x in in_x, until |r|^2 <= thr[k] per RHS
+// (thr: host copy of the device array thr2) or maxit iterations.
+// Returns the iterations taken in *iters and the last |r|^2 read in rn2_out.
 static grg_status inner_gcr(grg_schur S, int prec, int nrhs, const double *thr, int maxit,
-                            int *iters)
+                            int *iters, double *rn2_out)
 {
     grg_lattice L = S->lat;
     hipStream_t st = L->stream;
@@ -279,13 +386,11 @@ static grg_status inner_gcr(grg_schur S, int prec, int nrhs, const double *thr, 
     const int m = std::max(1, S->prm.restart);
     const int check = std::max(1, S->prm.check_every);
     const DslashTune &tt = S->tune[prec][nrhs];
-    const int dgrid = tt.valid && !(tt.march > 0 && tt.RG != nrhs) ? tt.grid
-                                                                   : default_tune(g, prec, nrhs).grid;
-    void *b = S->in_b[prec], *x = S->in_x[prec], *r = S->in_r[prec], *q = S->in_q[prec];
+    const int dgrid = tt.valid ? tt.grid : default_tune(g, prec, nrhs).grid;
+    void *x = S->in_x[prec], *r = S->in_r[prec], *q = S->in_q[prec];
     char *Pm = (char *)S->in_P[prec], *Qm = (char *)S->in_Q[prec];
 
     GRG_TRY_HIP(launch_fill_zero(x, vbytes, st));
-    GRG_TRY_HIP(launch_copy(prec, sh, b, r, st));
     GRG_TRY_HIP(launch_norm2(prec, sh, r, S->partials, st));
     GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, S->thr2,
                               S->active, st));
@@ -336,6 +441,7 @@ static grg_status inner_gcr(grg_schur S, int prec, int nrhs, const double *thr, 
         }
     }
     *iters = it;
+    memcpy(rn2_out, h, sizeof(double) * nrhs);
     if (done < 0) {
         set_error("non-finite residual in the inner solve");
         return GRG_ENONFINITE;
@@ -347,23 +453,31 @@ static grg_status inner_gcr(grg_schur S, int prec, int nrhs, const double *thr, 
 // GCR fallback takes over.
 constexpr int kPrecondInnerCap = 100;
 
-// the inner right-hand side r / |r| again (the failed attempt overwrote nothing
-// of it, but keep the restart explicit)
-static grg_status launch_axpy_convert_guard(grg_schur S, int prec, const BlasShape &sh,
-                                            const void *r_src, const double *fr2)
+// The inner right-hand side s_k r_k in the inner precision, from the FP64
+// residual r (scale: device array of s_k).
+static grg_status convert_rhs(grg_schur S, int prec, const BlasShape &sh, const void *r_src,
+                              const double *scale)
 {
-    GRG_TRY_HIP(launch_axpy_convert(GRG_FP64, prec, sh, r_src, S->in_b[prec], fr2, 1, 0, nullptr,
+    GRG_TRY_HIP(launch_axpy_convert(GRG_FP64, prec, sh, r_src, S->in_r[prec], scale, 0, 0, nullptr,
                                     S->lat->stream));
     return GRG_OK;
 }
 
 // b64 (internal FP64, zero on coarse sites) -> x64 = D_rr^{-1} b64.
 //
-// Outer loop, FP64 (r_0 = b, x_0 = 0):
-//     e   ~= A^{-1} (r / |r|)                      inner GCR, inner precision
-//     r   <- r - |r| A e,   x <- x + |r| e         one fused FP64 kernel
-// until |r| <= tol |b|; then the residual is recomputed from x as b - A x,
-// and the loop resumes from that true residual if it is still above tol.
+// Outer loop, FP64 (r_0 = b, x_0 = 0), with a per-RHS scale s_k:
+//     e   ~= A^{-1} (s r)                          inner GCR, inner precision
+//     r   <- r - A e / s,   x <- x + e / s         one fused FP64 kernel, which
+//                                                  also writes s' r for the next
+//                                                  inner solve
+// until |r| <= tol |b|.  s_0 = 1 / |b|; s' = 1 / (the new |r| the inner
+// solve predicts), so the inner fields stay of order one (a scale off by a
+// few orders of magnitude is harmless: BF16 and FP32 share an exponent range
+// far wider than that); the inner thresholds are taken relative to the
+// actual |s r|.  The FP64 residual r is updated with the exact FP64 operator
+// at every step, so it is the residual of x up to FP64 rounding; with
+// params.verify it is also recomputed from x as b - A x at the end, and the
+// loop resumes from that residual if it is above tol.
 grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
 {
     grg_lattice L = S->lat;
@@ -374,25 +488,34 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
     const BlasShape sh = blas_shape(g, nrhs);
     const size_t vb64 = spinor_elems(g, nrhs) * 16;
     GRG_TRY(ensure_inner(S, prec));
-    double *fr2 = S->bn2 + kMaxRhs;  // device copy of the outer |r|^2
+    // device per-RHS scalars: |b|^2, then f = 1/s, s, and the next s
+    double *d_f = S->bn2 + kMaxRhs, *d_s = S->bn2 + 2 * kMaxRhs, *d_sn = S->bn2 + 3 * kMaxRhs;
 
     GRG_TRY_HIP(launch_norm2(GRG_FP64, sh, S->b64, S->partials, st));
     GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->bn2, nullptr, nullptr,
                               st));
-    double bn2[kMaxRhs], rn2[kMaxRhs];
+    double bn2[kMaxRhs], rn2[kMaxRhs], sc[kMaxRhs], scn[kMaxRhs], ih[kMaxRhs];
     GRG_TRY_HIP(hipMemcpyAsync(S->h_buf, S->bn2, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
     GRG_TRY_HIP(hipStreamSynchronize(st));
     memcpy(bn2, S->h_buf, sizeof(double) * nrhs);
     memcpy(rn2, bn2, sizeof(double) * nrhs);
+    for (int k = 0; k < nrhs; ++k) sc[k] = bn2[k] > 0 && isfinite(bn2[k]) ? 1.0 / sqrt(bn2[k]) : 1.0;
+    double *hb = S->h_buf + 4 * kMaxRhs;  // upload staging; reads use the front
+    auto upload = [&](double *dst, const double *src, int slot) -> grg_status {
+        memcpy(hb + slot * kMaxRhs, src, sizeof(double) * nrhs);
+        GRG_TRY_HIP(hipMemcpyAsync(dst, hb + slot * kMaxRhs, sizeof(double) * nrhs,
+                                   hipMemcpyHostToDevice, st));
+        return GRG_OK;
+    };
 
     const void *r_src = S->b64;  // the residual of the current iterate
     const void *x_src = nullptr; // the iterate (nullptr: zero)
+    bool rhs_ready = false;      // in_r holds s r_src in the inner precision
     int total = 0, outer = 0;
     bool verified = false;
     grg_status status = GRG_OK;
     double worst = 0;
-    const int dc_sb = 128;
-    const int dc_grid = round8(std::min<long>((g.V + dc_sb - 1) / dc_sb, 2048));
+    const DslashTune dct = S->dctune[prec][nrhs].valid ? S->dctune[prec][nrhs] : default_dc_tune(g);
     for (;;) {
         bool conv = true;
         worst = 0;
@@ -405,7 +528,7 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
             worst = std::max(worst, rel);
             if (rel > p.tol) conv = false;
         }
-        if (conv && (verified || x_src == nullptr)) break;
+        if (conv && (verified || x_src == nullptr || !p.verify)) break;
         if (conv) {
             // confirm with the residual recomputed from the iterate
             GRG_TRY(run_dslash(S, GRG_FP64, S->x64, S->t64, 0, nrhs, nullptr));
@@ -414,6 +537,7 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
                                       nullptr, st));
             GRG_TRY(read_norms(S, nrhs, rn2));
             r_src = S->r64;
+            rhs_ready = false;
             verified = true;
             continue;
         }
@@ -424,45 +548,53 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
                       "(residual %.3e > %.3e)", outer, total, worst, p.tol);
             break;
         }
-        // inner thresholds on the normalised residual r / |r|
-        double thr[kMaxRhs];
+        // inner thresholds on the scaled residual s r, |s r|^2 = s^2 |r|^2
+        double thr[kMaxRhs], f[kMaxRhs];
         for (int k = 0; k < nrhs; ++k) {
             const double need = bn2[k] > 0 && rn2[k] > 0 ? p.tol * sqrt(bn2[k] / rn2[k]) : 1.0;
             const double rel = prec == GRG_FP64 ? need : std::max(p.inner_tol, 0.5 * need);
             const bool on = bn2[k] > 0 && sqrt(rn2[k] / bn2[k]) > p.tol;
-            thr[k] = on ? rel * rel : 2.0;  // 2 > |r/|r||^2 = 1: inactive
+            ih[k] = sc[k] * sc[k] * rn2[k];
+            thr[k] = on ? rel * rel * ih[k] : 2.0 * ih[k] + 1.0;  // above |s r|^2: inactive
+            f[k] = 1.0 / sc[k];
         }
-        memcpy(S->h_buf + 2 * kMaxRhs, thr, sizeof(double) * nrhs);
-        GRG_TRY_HIP(hipMemcpyAsync(S->thr2, S->h_buf + 2 * kMaxRhs, sizeof(double) * nrhs,
-                                   hipMemcpyHostToDevice, st));
-        memcpy(S->h_buf + 3 * kMaxRhs, rn2, sizeof(double) * nrhs);
-        GRG_TRY_HIP(hipMemcpyAsync(fr2, S->h_buf + 3 * kMaxRhs, sizeof(double) * nrhs,
-                                   hipMemcpyHostToDevice, st));
-        // inner right-hand side r / |r| in the inner precision
-        GRG_TRY_HIP(launch_axpy_convert(GRG_FP64, prec, sh, r_src, S->in_b[prec], fr2, 1, 0,
-                                        nullptr, st));
+        GRG_TRY(upload(S->thr2, thr, 0));
+        GRG_TRY(upload(d_f, f, 1));
+        if (!rhs_ready) {
+            GRG_TRY(upload(d_s, sc, 2));
+            GRG_TRY(convert_rhs(S, prec, sh, r_src, d_s));
+        }
         int it = 0;
         grg_status is;
+        double h[kMaxRhs];
         if (S->precond) {
             // preconditioned inner solve, with plain GCR as the fallback
-            is = inner_gcr(S, prec, nrhs, thr, std::min(p.max_iter - total, kPrecondInnerCap), &it);
+            is = inner_gcr(S, prec, nrhs, thr, std::min(p.max_iter - total, kPrecondInnerCap), &it, h);
             total += it;
             if (is != GRG_OK) {
                 grg_precond keep = S->precond;
                 S->precond = nullptr;
                 ++S->fallbacks;
-                GRG_TRY(launch_axpy_convert_guard(S, prec, sh, r_src, fr2));
-                is = inner_gcr(S, prec, nrhs, thr, p.max_iter - total, &it);
+                GRG_TRY(upload(d_s, sc, 2));
+                GRG_TRY(convert_rhs(S, prec, sh, r_src, d_s));
+                is = inner_gcr(S, prec, nrhs, thr, p.max_iter - total, &it, h);
                 S->precond = keep;
                 total += it;
             }
         } else {
-            is = inner_gcr(S, prec, nrhs, thr, p.max_iter - total, &it);
+            is = inner_gcr(S, prec, nrhs, thr, p.max_iter - total, &it, h);
             total += it;
         }
         if (is != GRG_OK && is != GRG_ENOCONV) return is;
         ++outer;
-        // r -= |r| A e ; x += |r| e   (FP64, fused)
+        // scale of the next inner right-hand side: the new |r| is about
+        // |s r_inner| / s
+        for (int k = 0; k < nrhs; ++k) {
+            const double est = sqrt(h[k] > 0 ? h[k] : 0.0) / sc[k];
+            scn[k] = est > 0 && isfinite(est) && isfinite(1.0 / est) ? 1.0 / est : sc[k];
+        }
+        GRG_TRY(upload(d_sn, scn, 3));
+        // r -= A e / s ; x += e / s ; next inner rhs s' r   (FP64, fused)
         DcArgs d;
         d.e = S->in_x[prec];
         d.U = L->U[GRG_FP64];
@@ -470,18 +602,23 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
         d.x_in = x_src;
         d.r_out = S->r64;
         d.x_out = S->x64;
-        d.fr2 = fr2;
+        d.f = d_f;
+        d.r_next = S->in_r[prec];
+        d.s_next = d_sn;
         d.mask = S->d_mask;
         d.diag = 4.0 + S->m0;
         d.g = g;
         d.nrhs = nrhs;
         d.partials = S->partials;
-        GRG_TRY_HIP(launch_dc_update(prec, d, dc_grid, dc_sb, st));
-        GRG_TRY_HIP(launch_reduce(kNorm, S->partials, dc_grid, nrhs, nullptr, S->rn2, nullptr,
+        dc_fill_launch(d, dct);
+        GRG_TRY_HIP(launch_dc_update(prec, d, dct.grid, dct.SB, st));
+        GRG_TRY_HIP(launch_reduce(kNorm, S->partials, dct.grid, nrhs, nullptr, S->rn2, nullptr,
                                   nullptr, st));
         GRG_TRY(read_norms(S, nrhs, rn2));
+        memcpy(sc, scn, sizeof(double) * nrhs);
         r_src = S->r64;
         x_src = S->x64;
+        rhs_ready = true;
     }
     if (x_src == nullptr) GRG_TRY_HIP(launch_fill_zero(S->x64, vb64, st));
     if (stats) {
@@ -538,6 +675,49 @@ grg_status schur_apply_internal(grg_schur S, const double *xb, double *yb, int n
     c.nrhs = nrhs;
     GRG_TRY_HIP(launch_dslash_coarse(c, st));
     return s;
+}
+
+}  // namespace grg
+
+namespace grg {
+
+// y_b = S~_bb x_b, the second-order Schur complement approximation of
+// section 3, in FP64 without any solve:
+//     u = x_b on the coarse sites;  y = D_rb u;  d~ = D_rr 1 (row sums);
+//     t = y / d~;  z = D_rr t;  w = u - ((y - z) / d + t);  y_b = (D w)_b,
+// with d = 4 + m0 the diagonal of D_rr.  Three stencil launches on nrhs
+// fields and one on a single field (d~, recomputed per call since the links
+// may have been reset).
+grg_status reusken_apply_internal(grg_schur S, const double *xb, double *yb, int nrhs)
+{
+    grg_lattice L = S->lat;
+    hipStream_t st = L->stream;
+    const Geom &g = L->g;
+    const BlasShape sh = blas_shape(g, nrhs);
+    if (!S->dt64 && hipMalloc(&S->dt64, spinor_elems(g, 1) * 16) != hipSuccess) {
+        S->dt64 = nullptr;
+        set_error("row-sum field: hipMalloc failed");
+        return GRG_ENOMEM;
+    }
+    GRG_TRY_HIP(launch_rest_ones(g, S->d_mask, S->t64, st));
+    GRG_TRY(run_dslash(S, GRG_FP64, S->t64, S->dt64, 0, 1, nullptr));
+    GRG_TRY_HIP(launch_scatter_coarse(xb, S->u64, S->d_bidx, S->nb, g, nrhs, st));
+    GRG_TRY(run_dslash(S, GRG_FP64, S->u64, S->b64, 0, nrhs, nullptr));
+    GRG_TRY_HIP(launch_reusken_divide(sh, S->b64, S->dt64, S->d_mask, S->t64, st));
+    GRG_TRY(run_dslash(S, GRG_FP64, S->t64, S->r64, 0, nrhs, nullptr));
+    GRG_TRY_HIP(launch_reusken_combine(sh, S->u64, S->b64, S->r64, S->t64, S->d_mask,
+                                       1.0 / (4.0 + S->m0), S->x64, st));
+    CoarseArgs c;
+    c.in = S->x64;
+    c.out = yb;
+    c.U = L->U[GRG_FP64];
+    c.q = S->d_q;
+    c.nb = S->nb;
+    c.diag = 4.0 + S->m0;
+    c.g = g;
+    c.nrhs = nrhs;
+    GRG_TRY_HIP(launch_dslash_coarse(c, st));
+    return GRG_OK;
 }
 
 }  // namespace grg

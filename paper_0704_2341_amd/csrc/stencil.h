@@ -92,6 +92,145 @@ __device__ __forceinline__ void hop_math(cpx<R> (&acc)[12], const cpx<R> (&p)[12
     }
 }
 
+// ------------------------------------------------------------------ BF16 hop
+// The same hop with BF16 operands kept packed: one 32-bit word per complex
+// (re in the low half, im in the high half), multiplied with the gfx950
+// two-way BF16 dot product (products exact in FP32, sums in FP32).  By
+// linearity U h = U psi_up +/- U (B psi_lo), so the projected h is never
+// rounded: each complex multiply-add of a link entry m with a packed x is two
+// dot products against the link forms
+//     U x:      re = (m.re, -m.im).x    im = (m.im, m.re).x
+//     U^+ x:    re = (m.re,  m.im).x    im = (-m.im, m.re).x
+// and the B_mu phases of psi_lo are half swaps and sign flips of its words.
+__device__ __forceinline__ float dot2bf(uint32_t a, uint32_t b, float c)
+{
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_v, a),
+                                           __builtin_bit_cast(bf16x2_v, b), c, false);
+}
+__device__ __forceinline__ uint32_t swap_halves(uint32_t w) { return (w << 16) | (w >> 16); }
+constexpr uint32_t kNegHi = 0x80000000u, kNegLo = 0x00008000u, kNegBoth = 0x80008000u;
+
+template <int MU, bool FWD>
+__device__ __forceinline__ void hop_bf16(cpx<float> (&acc)[12], const uint32_t (&p)[12],
+                                         const uint32_t (&u)[9])
+{
+    // y_s = sg (B_mu psi_lo)_s, sg = -1 forward, +1 backward;  i (re, im) = (-im, re)
+    uint32_t y0[3], y1[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const uint32_t l0 = p[6 + c], l1 = p[9 + c];
+        if (MU == 0) {        // B psi_lo = (i l1, i l0)
+            y0[c] = swap_halves(l1) ^ (FWD ? kNegHi : kNegLo);
+            y1[c] = swap_halves(l0) ^ (FWD ? kNegHi : kNegLo);
+        } else if (MU == 1) { // (-l1, l0)
+            y0[c] = FWD ? l1 : l1 ^ kNegBoth;
+            y1[c] = FWD ? l0 ^ kNegBoth : l0;
+        } else if (MU == 2) { // (i l0, -i l1)
+            y0[c] = swap_halves(l0) ^ (FWD ? kNegHi : kNegLo);
+            y1[c] = swap_halves(l1) ^ (FWD ? kNegLo : kNegHi);
+        } else {              // (l0, l1)
+            y0[c] = FWD ? l0 ^ kNegBoth : l0;
+            y1[c] = FWD ? l1 ^ kNegBoth : l1;
+        }
+    }
+    cpx<float> w0[3], w1[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        float a0 = 0.f, b0 = 0.f, a1 = 0.f, b1 = 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const uint32_t m = FWD ? u[3 * r + c] : u[3 * c + r];
+            const uint32_t fr = FWD ? m ^ kNegHi : m;                        // real-part form
+            const uint32_t fi = FWD ? swap_halves(m) : swap_halves(m) ^ kNegLo;  // imaginary-part form
+            a0 = dot2bf(fr, p[c], a0);
+            a0 = dot2bf(fr, y0[c], a0);
+            b0 = dot2bf(fi, p[c], b0);
+            b0 = dot2bf(fi, y0[c], b0);
+            a1 = dot2bf(fr, p[3 + c], a1);
+            a1 = dot2bf(fr, y1[c], a1);
+            b1 = dot2bf(fi, p[3 + c], b1);
+            b1 = dot2bf(fi, y1[c], b1);
+        }
+        w0[r] = {a0, b0};
+        w1[r] = {a1, b1};
+    }
+    const float hl = FWD ? 0.5f : -0.5f;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        acc[r].re = fmaf(-0.5f, w0[r].re, acc[r].re);
+        acc[r].im = fmaf(-0.5f, w0[r].im, acc[r].im);
+        acc[3 + r].re = fmaf(-0.5f, w1[r].re, acc[3 + r].re);
+        acc[3 + r].im = fmaf(-0.5f, w1[r].im, acc[3 + r].im);
+        cpx<float> d0, d1;  // B^+ w
+        if (MU == 0) {
+            d0 = {w1[r].im, -w1[r].re};
+            d1 = {w0[r].im, -w0[r].re};
+        } else if (MU == 1) {
+            d0 = w1[r];
+            d1 = {-w0[r].re, -w0[r].im};
+        } else if (MU == 2) {
+            d0 = {w0[r].im, -w0[r].re};
+            d1 = {-w1[r].im, w1[r].re};
+        } else {
+            d0 = w0[r];
+            d1 = w1[r];
+        }
+        acc[6 + r].re = fmaf(hl, d0.re, acc[6 + r].re);
+        acc[6 + r].im = fmaf(hl, d0.im, acc[6 + r].im);
+        acc[9 + r].re = fmaf(hl, d1.re, acc[9 + r].re);
+        acc[9 + r].im = fmaf(hl, d1.im, acc[9 + r].im);
+    }
+}
+
+// Operands of a hop as the kernels hold them: converted complex numbers, or
+// for BF16 spinors with BF16 links and FP32 sums the packed words.
+template <class S, class R>
+struct Operand {
+    typedef cpx<R> T;
+    static constexpr bool kPacked = false;
+    __device__ static T load(const S *p, size_t i) { return ldr<R>(p, i); }
+};
+template <>
+struct Operand<bf16x2, float> {
+    typedef uint32_t T;
+    static constexpr bool kPacked = true;
+    __device__ static T load(const bf16x2 *p, size_t i) { return p[i]; }
+};
+// BF16 spinors in an FP64 stencil (the defect correction of a BF16 inner
+// solution): held packed, widened when used
+template <>
+struct Operand<bf16x2, double> {
+    typedef uint32_t T;
+    static constexpr bool kPacked = true;
+    __device__ static T load(const bf16x2 *p, size_t i) { return p[i]; }
+};
+
+template <int MU, bool FWD, class R>
+__device__ __forceinline__ void hop(cpx<R> (&acc)[12], const cpx<R> (&p)[12], const cpx<R> (&u)[9])
+{
+    hop_math<MU, FWD>(acc, p, u);
+}
+template <int MU, bool FWD>
+__device__ __forceinline__ void hop(cpx<float> (&acc)[12], const uint32_t (&p)[12], const uint32_t (&u)[9])
+{
+    hop_bf16<MU, FWD>(acc, p, u);
+}
+template <int MU, bool FWD>
+__device__ __forceinline__ void hop(cpx<double> (&acc)[12], const uint32_t (&p)[12],
+                                    const cpx<double> (&u)[9])
+{
+    cpx<double> q[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) q[c] = {__uint_as_float(p[c] << 16), __uint_as_float(p[c] & 0xffff0000u)};
+    hop_math<MU, FWD>(acc, q, u);
+}
+template <class R>
+__device__ __forceinline__ cpx<R> as_cpx(const cpx<R> &v) { return v; }
+__device__ __forceinline__ cpx<float> as_cpx(uint32_t w)
+{
+    return {__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u)};
+}
+
 // Site coordinates and the four lattice strides.
 struct SiteGeo {
     int c[4];
@@ -122,41 +261,95 @@ __device__ __forceinline__ void nbr(int s, int mu, const SiteGeo &q, const Geom 
     sm = x == 0 ? s + (L - 1) * st : s - st;
 }
 
-// acc = (D in)(s) for RHS r of a field with nrhs RHS.  The hop loop is not
-// unrolled: each iteration loads one direction's two neighbours and links
-// (24 + 18 complex; SPLIT: one hop, 12 + 9 complex) and consumes them, which
-// bounds the live registers and keeps several wavefronts per SIMD in flight.
-template <class S, class R, bool SPLIT, class SU = S>
+// Operands of hop h (0..7 = +x, -x, +y, -y, +z, -z, +t, -t) of site s.
+template <class OP, class OU, class S, class SU>
+__device__ __forceinline__ void load_hop(int h, typename OP::T (&p)[12], typename OU::T (&u)[9],
+                                         const S *__restrict__ in, const SU *__restrict__ U, int s,
+                                         const SiteGeo &q, const Geom &g, int r, int nrhs)
+{
+    const int mu = h >> 1;
+    int sp, sm;
+    nbr(s, mu, q, g, sp, sm);
+    const int n = (h & 1) ? sm : sp;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) p[c] = OP::load(in, fidx(n, r, c, nrhs));
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[e] = OU::load(U, lidx((h & 1) ? sm : s, mu, e));
+}
+
+// acc = (D in)(s) for RHS r of a field with nrhs RHS.  HOPS selects how the
+// eight hops are scheduled:
+//   0: loop over directions, each iteration loading one direction's two
+//      neighbours and links (24 + 18 complex) and consuming them;
+//   1: loop over single hops (12 + 9 complex per iteration);
+//   2: (packed BF16 operands: 21 registers per hop) single hops, double
+//      buffered: the operands of hop h + 1 are requested before hop h is
+//      computed, so every wavefront keeps a hop's loads in flight while it
+//      computes.
+// Loops 0 and 1 are not unrolled, which bounds the live registers and keeps
+// several wavefronts per SIMD in flight.  HOPS = 2 with unpacked operands
+// runs as 1.
+template <class S, class R, int HOPS, class SU = S>
 __device__ __forceinline__ void dslash_site(cpx<R> (&acc)[12], const S *__restrict__ in,
                                             const SU *__restrict__ U, int s, const SiteGeo &q,
                                             const Geom &g, int r, int nrhs, R diag)
 {
+    typedef Operand<S, R> OP;
+    typedef Operand<SU, R> OU;
+    typedef typename OP::T PT;
+    typedef typename OU::T UT;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
         const cpx<R> v = ldr<R>(in, fidx(s, r, c, nrhs));
         acc[c] = {diag * v.re, diag * v.im};
     }
-    if (SPLIT) {
+    if constexpr (HOPS == 2 && OP::kPacked && OU::kPacked) {
+        // double buffer: A holds the forward hop of direction mu, B the
+        // backward one; each buffer is refilled right after it is consumed
+        PT pa[12], pb[12];
+        UT ua[9], ub[9];
+        load_hop<OP, OU>(0, pa, ua, in, U, s, q, g, r, nrhs);
+#pragma unroll 1
+        for (int mu = 0; mu < 4; ++mu) {
+            load_hop<OP, OU>(2 * mu + 1, pb, ub, in, U, s, q, g, r, nrhs);
+            switch (mu) {
+            case 0: hop<0, true>(acc, pa, ua); break;
+            case 1: hop<1, true>(acc, pa, ua); break;
+            case 2: hop<2, true>(acc, pa, ua); break;
+            default: hop<3, true>(acc, pa, ua); break;
+            }
+            if (mu < 3) load_hop<OP, OU>(2 * mu + 2, pa, ua, in, U, s, q, g, r, nrhs);
+            switch (mu) {
+            case 0: hop<0, false>(acc, pb, ub); break;
+            case 1: hop<1, false>(acc, pb, ub); break;
+            case 2: hop<2, false>(acc, pb, ub); break;
+            default: hop<3, false>(acc, pb, ub); break;
+            }
+        }
+        return;
+    }
+    if (HOPS >= 1) {
 #pragma unroll 1
         for (int h = 0; h < 8; ++h) {
             const int mu = h >> 1;
             int sp, sm;
             nbr(s, mu, q, g, sp, sm);
             const int n = (h & 1) ? sm : sp;
-            cpx<R> p[12], u[9];
+            PT p[12];
+            UT u[9];
 #pragma unroll
-            for (int c = 0; c < 12; ++c) p[c] = ldr<R>(in, fidx(n, r, c, nrhs));
+            for (int c = 0; c < 12; ++c) p[c] = OP::load(in, fidx(n, r, c, nrhs));
 #pragma unroll
-            for (int e = 0; e < 9; ++e) u[e] = ldr<R>(U, lidx((h & 1) ? sm : s, mu, e));
+            for (int e = 0; e < 9; ++e) u[e] = OU::load(U, lidx((h & 1) ? sm : s, mu, e));
             switch (h) {
-            case 0: hop_math<0, true>(acc, p, u); break;
-            case 1: hop_math<0, false>(acc, p, u); break;
-            case 2: hop_math<1, true>(acc, p, u); break;
-            case 3: hop_math<1, false>(acc, p, u); break;
-            case 4: hop_math<2, true>(acc, p, u); break;
-            case 5: hop_math<2, false>(acc, p, u); break;
-            case 6: hop_math<3, true>(acc, p, u); break;
-            default: hop_math<3, false>(acc, p, u); break;
+            case 0: hop<0, true>(acc, p, u); break;
+            case 1: hop<0, false>(acc, p, u); break;
+            case 2: hop<1, true>(acc, p, u); break;
+            case 3: hop<1, false>(acc, p, u); break;
+            case 4: hop<2, true>(acc, p, u); break;
+            case 5: hop<2, false>(acc, p, u); break;
+            case 6: hop<3, true>(acc, p, u); break;
+            default: hop<3, false>(acc, p, u); break;
             }
         }
         return;
@@ -165,22 +358,23 @@ __device__ __forceinline__ void dslash_site(cpx<R> (&acc)[12], const S *__restri
     for (int mu = 0; mu < 4; ++mu) {
         int sp, sm;
         nbr(s, mu, q, g, sp, sm);
-        cpx<R> pf[12], pb[12], uf[9], ub[9];
+        PT pf[12], pb[12];
+        UT uf[9], ub[9];
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            pf[c] = ldr<R>(in, fidx(sp, r, c, nrhs));
-            pb[c] = ldr<R>(in, fidx(sm, r, c, nrhs));
+            pf[c] = OP::load(in, fidx(sp, r, c, nrhs));
+            pb[c] = OP::load(in, fidx(sm, r, c, nrhs));
         }
 #pragma unroll
         for (int e = 0; e < 9; ++e) {
-            uf[e] = ldr<R>(U, lidx(s, mu, e));
-            ub[e] = ldr<R>(U, lidx(sm, mu, e));
+            uf[e] = OU::load(U, lidx(s, mu, e));
+            ub[e] = OU::load(U, lidx(sm, mu, e));
         }
         switch (mu) {
-        case 0: hop_math<0, true>(acc, pf, uf); hop_math<0, false>(acc, pb, ub); break;
-        case 1: hop_math<1, true>(acc, pf, uf); hop_math<1, false>(acc, pb, ub); break;
-        case 2: hop_math<2, true>(acc, pf, uf); hop_math<2, false>(acc, pb, ub); break;
-        default: hop_math<3, true>(acc, pf, uf); hop_math<3, false>(acc, pb, ub); break;
+        case 0: hop<0, true>(acc, pf, uf); hop<0, false>(acc, pb, ub); break;
+        case 1: hop<1, true>(acc, pf, uf); hop<1, false>(acc, pb, ub); break;
+        case 2: hop<2, true>(acc, pf, uf); hop<2, false>(acc, pb, ub); break;
+        default: hop<3, true>(acc, pf, uf); hop<3, false>(acc, pb, ub); break;
         }
     }
 }

@@ -20,7 +20,7 @@ def shapes(dims, nrhs, prec):
     out = []
     for sb in (64, 128, 256):
         for rg in sorted({1, nrhs}):
-            for split in (0, 1):
+            for split in ((0, 1, 2) if prec == "bf16" else (0, 1)):
                 for chunk in (0, 1, 8):
                     items = -(-V // sb) * -(-nrhs // rg)
                     grid = max(8, min(2048, -(-items // 8) * 8))
@@ -95,15 +95,54 @@ def test_set_launch_rejects_bad_shapes():
     lat.close()
 
 
+@pytest.mark.parametrize("rg", [4, 2, 1])
 @pytest.mark.parametrize("inner", ["fp64", "bf16"])
-def test_solver_with_march_kernel(inner):
+def test_solver_with_march_kernel(inner, rg):
+    """The solver's fused dot products with t-marching workgroups that hold
+    all, half or one of the RHS (the per-RHS sums then come from several
+    workgroups' items)."""
     lat = Lattice((8, 8, 8, 16), 0.5, 7)
     s = lat.schur(-0.3, "I", False, tol=1e-12, inner=inner, inner_tol=1e-2, max_rhs=4)
     xb = gaussian_vectors(12 * s.nb, 4, 7)
-    y0, _ = s.apply(xb)
-    lat.grg.grg_schur_set_launch(s.h, inner, 4, dict(SB=64, RG=4, split=0, grid=64, chunk=0, march=4))
-    lat.grg.grg_schur_set_launch(s.h, "fp64", 4, dict(SB=64, RG=4, split=0, grid=64, chunk=1, march=3))
+    y0, st0 = s.apply(xb)
+    lat.grg.grg_schur_set_launch(s.h, inner, 4, dict(SB=64, RG=rg, split=0, grid=64, chunk=0, march=4))
+    lat.grg.grg_schur_set_launch(s.h, "fp64", 4, dict(SB=64, RG=rg, split=0, grid=40, chunk=1, march=3))
     y1, st = s.apply(xb)
     assert st["converged"] and rel_err(y1, y0) < 1e-11
+    # the same iterations: the dot products are the same sums
+    assert abs(st["iters"] - st0["iters"]) <= 1
+    s.close()
+    lat.close()
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32", "bf16"])
+def test_defect_correction_every_launch(inner):
+    """The fused FP64 defect-correction step in every launch shape (site-
+    parallel, and t-marching with all, some or one RHS per workgroup and
+    ragged time chunks) gives the same solve."""
+    lat = Lattice((8, 8, 8, 16), 0.5, 9)
+    inner_tol = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 1e-2}[inner]
+    s = lat.schur(-0.3, "I", False, tol=1e-12, inner=inner, inner_tol=inner_tol, max_rhs=4)
+    grg = lat.grg
+    xb = gaussian_vectors(12 * s.nb, 4, 9)
+    y0, st0 = s.apply(xb)
+    assert st0["converged"]
+    shapes = [dict(SB=sb, RG=1, split=0, grid=64, chunk=0, march=0) for sb in (64, 256)]
+    for T in (1, 3, 16):
+        for rg in (4, 2, 1):
+            for chunk in (0, 1):
+                shapes.append(dict(SB=64, RG=rg, split=0, grid=40, chunk=chunk, march=T))
+    for shp in shapes:
+        grg.grg_schur_set_dc_launch(s.h, inner, 4, shp)
+        assert grg.grg_schur_dc_launch_info(s.h, inner, 4)["march"] == shp["march"]
+        y, st = s.apply(xb)
+        assert st["converged"] and rel_err(y, y0) < 1e-11, (shp, st)
+        assert abs(st["iters"] - st0["iters"]) <= 1 and st["outer"] == st0["outer"], (shp, st, st0)
+    for bad in (dict(SB=96, RG=1, split=0, grid=64, chunk=0, march=0),
+                dict(SB=64, RG=12, split=0, grid=64, chunk=0, march=2),
+                dict(SB=64, RG=1, split=0, grid=60, chunk=0, march=2),
+                dict(SB=64, RG=1, split=0, grid=64, chunk=0, march=17)):
+        with pytest.raises(grg.GrgError):
+            grg.grg_schur_set_dc_launch(s.h, inner, 4, bad)
     s.close()
     lat.close()
