@@ -50,11 +50,29 @@ def dslash_bytes_per_launch(prec: str, volume: int, nrhs: int) -> int:
 PREC_ID = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 
-def launch_descriptor(info: dict, prec: str, launches: int) -> dict:
+def eo_bytes_per_launch(prec: str, volume: int, nrhs: int, iters: int, outer: int) -> float:
+    """Compulsory bytes of the even-odd half-lattice stencils, averaged over
+    one solve's launches: the reduced operator's first half reads one parity
+    and writes the other (V sites' fields in all), its second half and the two
+    per-outer-step halves (right-hand side and reconstruction) also read a
+    field of the output parity (1.5 V); every half reads all V sites' links
+    (the forward links of one parity, the backward ones of the other)."""
+    b = REAL_BYTES[prec]
+    spinor, links = nrhs * 24 * b, 72 * b
+    k1 = volume * spinor + volume * links
+    k2 = 1.5 * volume * spinor + volume * links
+    n1, n2 = iters, iters + 2 * outer
+    return (n1 * k1 + n2 * k2) / max(1, n1 + n2)
+
+
+def launch_descriptor(info: dict, prec: str, launches: int, eo: bool = False) -> dict:
     """The stencil kernel a tuned launch runs, as a profiler names it, and its
     work-items per dispatch."""
     p = PREC_ID[prec]
-    if info["march"] > 0:
+    if eo:
+        sym, gs = f"eo_hop_kernel<{p}, {2 if info['split'] == 2 and prec == 'bf16' else 1}>", \
+            info["grid"] * info["SB"]
+    elif info["march"] > 0:
         sym, gs = f"dslash_march_kernel<{p}>", info["grid"] * 64 * info["RG"]
     else:
         sym, gs = f"dslash_kernel<{p}, {'true' if info['split'] else 'false'}>", info["grid"] * info["SB"]
@@ -89,6 +107,7 @@ def time_applies(grg, s, xb, yb, nrhs, steps, warmup, profile):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = {p: grg.grg_profile_read(s, p) for p in ("fp64", "fp32", "bf16")}
+    prof.update({p + "_eo": grg.grg_profile_read(s, p, eo=True) for p in ("fp64", "fp32", "bf16")})
     grg.grg_profile_enable(s, False)
     return t1 - t0, stats, prof
 
@@ -205,7 +224,7 @@ def main():
 
     import paper_0704_2341_amd as grg
     from grg_inputs import point_sources, su3_links
-    from paper_0704_2341_amd.profiling import measured_traffic
+    from paper_0704_2341_amd.profiling import measured_traffic, traffic_key
 
     dims = tuple(int(d) for d in args.dims.split(","))
     volume = int(np.prod(dims))
@@ -233,6 +252,7 @@ def main():
         log(f"tuned in {time.perf_counter() - t:.1f} s: "
             f"{args.inner} {grg.grg_schur_tune_info(s, args.inner, nrhs)}, "
             f"fp64 {grg.grg_schur_tune_info(s, 'fp64', nrhs)}, "
+            f"even-odd {grg.grg_schur_tune_info(s, args.inner, nrhs, eo=True)}, "
             f"defect correction {grg.grg_schur_dc_launch_info(s, args.inner, nrhs)}")
     log(f"timing {args.inner} path: warmup {args.warmup}, steps {args.steps}")
     dt, stats, prof = time_applies(grg, s, xb, yb, nrhs, args.steps, args.warmup, True)
@@ -246,23 +266,31 @@ def main():
     for p, (cnt, ms) in prof.items():
         if cnt:
             avg = ms / cnt
-            gbs = dslash_bytes_per_launch(p, volume, nrhs) / (avg * 1e-3) / 1e9
-            kernels[f"dslash_{p}"] = {"launches": cnt, "avg_ms": avg, "alg_GBps": gbs,
-                                      "alg_bytes_per_launch": dslash_bytes_per_launch(p, volume, nrhs)}
-    dom = f"dslash_{args.inner}"
+            eo = p.endswith("_eo")
+            pr = p[:-3] if eo else p
+            alg = (eo_bytes_per_launch(pr, volume, nrhs, st["iters"], st["outer"]) if eo
+                   else dslash_bytes_per_launch(pr, volume, nrhs))
+            kernels[f"dslash_{p}"] = {"launches": cnt, "avg_ms": avg, "total_ms": ms,
+                                      "alg_GBps": alg / (avg * 1e-3) / 1e9, "alg_bytes_per_launch": alg}
+    # the dominant stencil: the one with the most time in the timed region
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     dk = kernels[dom]
-    traffic = measured_traffic(args.inner, nrhs, dims)
+    dom_eo = dom.endswith("_eo")
+    dom_prec = dom[len("dslash_"):].replace("_eo", "")
+    tkey = traffic_key(dom_prec + ("_eo" if dom_eo else ""), nrhs, dims)
+    traffic = measured_traffic(tkey)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBps"], "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": dk["alg_GBps"] / PEAK_HBM_GBS,
                 "traffic": traffic, "alg_bytes_per_launch": dk["alg_bytes_per_launch"],
-                "avg_launch_ms": dk["avg_ms"],
-                "launch": launch_descriptor(grg.grg_schur_tune_info(s, args.inner, nrhs), args.inner,
-                                            dk["launches"])}
+                "avg_launch_ms": dk["avg_ms"], "traffic_key": tkey,
+                "launch": launch_descriptor(grg.grg_schur_tune_info(s, dom_prec, nrhs, eo=dom_eo),
+                                            dom_prec, dk["launches"], eo=dom_eo)}
 
     fp64 = None
     if not args.no_fp64 and args.inner != "fp64":
+        # the baseline: plain FP64 minimal residual / GCR on D_rr (no even-odd reduction)
         prm64 = grg.grg_solver_params_default(tol=tol, inner="fp64", restart=args.fp64_restart,
-                                              max_rhs=nrhs, max_iter=4000)
+                                              max_rhs=nrhs, max_iter=4000, eo=0)
         s64 = grg.grg_schur_create(lat, m0, q, nb, prm64)
         if not args.no_tune:
             grg.grg_schur_tune(s64, nrhs)
@@ -344,6 +372,7 @@ def main():
                    "lattice": list(dims), "nrhs": nrhs, "inner": args.inner,
                    "inner_tol": inner_tol, "restart": args.restart, "tol": tol,
                    "dslash_launch": grg.grg_schur_tune_info(s, args.inner, nrhs),
+                   "eo_launch": grg.grg_schur_tune_info(s, args.inner, nrhs, eo=True),
                    "dc_launch": grg.grg_schur_dc_launch_info(s, args.inner, nrhs),
                    "parallelism": "1 GPU"},
         "solver": {"iters": st["iters"], "outer": st["outer"],

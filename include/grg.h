@@ -87,6 +87,11 @@ typedef struct {
                           if it misses tol; 0 (default): stop on the defect correction's
                           FP64 residual, which is updated with the exact FP64 operator
                           and equals b - D_rr x up to FP64 rounding */
+    int eo;            /* 1 (default): inner minimal-residual solves (restart 1, no learned
+                          preconditioner) run on the even-odd reduced system of D_rr when
+                          every extent is even (the hopping term couples opposite parities:
+                          solve (d - H_pq H_qp / d) z_p = b_p - H_pq b_q / d on one parity,
+                          then z_q = (b_q - H_qp z_p) / d); 0: on D_rr itself */
 } grg_solver_params;
 
 typedef struct {
@@ -201,7 +206,9 @@ grg_status grg_schur_tune(grg_schur s, int nrhs);
  * before the current hop's arithmetic), workgroups, items per XCD chunk (0 = one
  * contiguous eighth of the lattice per XCD), time-chunk length of the
  * t-marching kernel (0 = site-parallel kernel)}; *ms = its tuned time per
- * launch, or -1 if untuned (defaults in use). */
+ * launch, or -1 if untuned (defaults in use).  precision 3..5 reports the
+ * half-lattice stencil of the even-odd reduced solve in precision - 3
+ * (info[5] = 0). */
 grg_status grg_schur_tune_info(grg_schur s, int precision, int nrhs, int32_t info[6], float *ms);
 
 /* Pin the stencil launch for (precision, nrhs), e.g. from a saved tuning
@@ -313,7 +320,9 @@ grg_status grg_batch_tune(grg_batch b);
 
 /* Kernel timing: with profiling on, every dslash launch is bracketed by HIP
  * events on the lattice stream; grg_profile_read returns the count and the
- * summed milliseconds since the last reset, per dslash precision. */
+ * summed milliseconds since the last reset, per slot: precision 0..2 for
+ * full-lattice stencil launches in that grg_precision, 3..5 for the half-
+ * lattice stencils of the even-odd reduced solve in precision - 3. */
 grg_status grg_profile_enable(grg_schur s, int on);
 grg_status grg_profile_read(grg_schur s, int precision, int64_t *count, double *total_ms);
 grg_status grg_profile_reset(grg_schur s);

@@ -60,7 +60,7 @@ class grg_solver_params(C.Structure):
     _fields_ = [
         ("tol", C.c_double), ("max_iter", C.c_int), ("restart", C.c_int), ("inner", C.c_int),
         ("inner_tol", C.c_double), ("max_outer", C.c_int), ("max_rhs", C.c_int),
-        ("check_every", C.c_int), ("verify", C.c_int),
+        ("check_every", C.c_int), ("verify", C.c_int), ("eo", C.c_int),
     ]
 
 
@@ -315,11 +315,13 @@ def grg_schur_tune(s, nrhs):
     _check(load().grg_schur_tune(s, int(nrhs)))
 
 
-def grg_schur_tune_info(s, precision, nrhs):
-    """{'SB', 'RG', 'split', 'grid', 'chunk', 'ms'} of the stencil launch in use."""
+def grg_schur_tune_info(s, precision, nrhs, eo=False):
+    """{'SB', 'RG', 'split', 'grid', 'chunk', 'march', 'ms'} of the stencil launch in
+    use (eo=True: the half-lattice stencil of the even-odd reduced solve)."""
     info = (C.c_int32 * 6)()
     ms = C.c_float()
-    _check(load().grg_schur_tune_info(s, _prec(precision), int(nrhs), info, C.byref(ms)))
+    _check(load().grg_schur_tune_info(s, _prec(precision) + (3 if eo else 0), int(nrhs), info,
+                                      C.byref(ms)))
     return {"SB": info[0], "RG": info[1], "split": info[2], "grid": info[3], "chunk": info[4],
             "march": info[5], "ms": ms.value}
 
@@ -459,9 +461,11 @@ def grg_profile_enable(s, on=True):
     _check(load().grg_profile_enable(s, int(bool(on))))
 
 
-def grg_profile_read(s, precision):
+def grg_profile_read(s, precision, eo=False):
+    """(launches, summed ms) of the full-lattice stencil in `precision`, or with
+    eo=True of the even-odd half-lattice stencil."""
     n, ms = C.c_int64(), C.c_double()
-    _check(load().grg_profile_read(s, _prec(precision), C.byref(n), C.byref(ms)))
+    _check(load().grg_profile_read(s, _prec(precision) + (3 if eo else 0), C.byref(n), C.byref(ms)))
     return n.value, ms.value
 
 

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgrg.so")
-SOURCES = ["kernels_dslash.hip", "kernels_blas.hip", "kernels_ptc.hip", "kernels_batch.hip",
+SOURCES = ["kernels_dslash.hip", "kernels_blas.hip", "kernels_ptc.hip", "kernels_batch.hip", "kernels_eo.hip",
            "solver.cpp", "api.cpp", "precond.cpp", "batch.cpp"]
 ARCH = "gfx950"
 

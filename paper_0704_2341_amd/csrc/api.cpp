@@ -39,6 +39,8 @@ grg_status block_apply_internal(grg_schur S, int prec, int rows, int cols, const
 grg_status tune_dslash(grg_schur S, int prec, int nrhs, int reps);
 grg_status reusken_apply_internal(grg_schur S, const double *xb, double *yb, int nrhs);
 grg_status tune_dc(grg_schur S, int prec, int nrhs, int reps);
+grg_status tune_eo(grg_schur S, int prec, int nrhs, int reps);
+DslashTune default_eo_tune(const Geom &gh, int prec, int nrhs);
 DslashTune default_dc_tune(const Geom &g);
 bool dc_launch_ok(const Geom &g, int nrhs, const DslashTune &t);
 
@@ -75,6 +77,7 @@ static grg_status validate_params(const grg_solver_params &p)
         return set_error("max_rhs must be in 1..%d", kMaxRhs), GRG_EINVAL;
     if (p.check_every < 1) return set_error("check_every must be >= 1"), GRG_EINVAL;
     if (p.verify != 0 && p.verify != 1) return set_error("verify must be 0 or 1"), GRG_EINVAL;
+    if (p.eo != 0 && p.eo != 1) return set_error("eo must be 0 or 1"), GRG_EINVAL;
     return GRG_OK;
 }
 
@@ -151,6 +154,7 @@ grg_status grg_solver_params_default(grg_solver_params *p)
     p->max_rhs = 12;
     p->check_every = 1;
     p->verify = 0;
+    p->eo = 1;
     return GRG_OK;
 }
 
@@ -182,6 +186,12 @@ grg_status grg_lattice_create(const int32_t dims[4], const int32_t bc[4], void *
     const size_t ge = gauge_elems(L->g);
     grg_status s = GRG_OK;
     for (int p = 0; p < 3 && s == GRG_OK; ++p) s = dmalloc(&L->U[p], ge * prec_bytes(p), "links");
+    L->eo_ok = dims[0] % 2 == 0 && dims[1] % 2 == 0 && dims[2] % 2 == 0 && dims[3] % 2 == 0;
+    if (L->eo_ok) {
+        L->Vhs = (int)((V / 2 + 255) / 256 * 256);
+        for (int p = 0; p < 3 && s == GRG_OK; ++p)
+            s = dmalloc(&L->Ueo[p], (size_t)2 * 36 * L->Vhs * prec_bytes(p), "even-odd links");
+    }
     if (s != GRG_OK) {
         grg_lattice_destroy(L);
         return s;
@@ -196,6 +206,7 @@ grg_status grg_lattice_destroy(grg_lattice L)
     DeviceGuard dg(L->device);
     hipStreamSynchronize(L->stream);
     for (int p = 0; p < 3; ++p) dfree(L->U[p]);
+    for (int p = 0; p < 3; ++p) dfree(L->Ueo[p]);
     dfree(L->tmp_in);
     dfree(L->tmp_out);
     void *tl = L->tmp_links;
@@ -228,6 +239,9 @@ grg_status grg_gauge_set(grg_lattice L, const double *links, int on_device)
     }
     GRG_TRY_HIP(launch_pack_gauge(src, L->g, L->bc, L->U[GRG_FP64], L->U[GRG_FP32],
                                   L->U[GRG_BF16], L->stream));
+    if (L->eo_ok)
+        for (int p = 0; p < 3; ++p)
+            GRG_TRY_HIP(launch_eo_pack_links(p, L->g, L->Vhs, L->U[p], L->Ueo[p], L->stream));
     GRG_TRY_HIP(hipStreamSynchronize(L->stream));
     if (L->tmp_links) {
         void *tl = L->tmp_links;
@@ -315,6 +329,9 @@ static void schur_free(grg_schur S)
     dfree((void *&)S->cb_in);
     dfree((void *&)S->cb_out);
     dfree(S->dt64);
+    dfree((void *&)S->d_mask_eo);
+    for (int p = 0; p < 3; ++p)
+        for (int k = 0; k < 6; ++k) dfree(S->eo_f[p][k]);
     dfree((void *&)S->partials);
     dfree((void *&)S->alpha);
     dfree((void *&)S->beta);
@@ -386,6 +403,7 @@ grg_status grg_schur_create(grg_lattice L, double m0, const int32_t *q, int32_t 
     ALLOC(S->qn2, sizeof(double) * kMaxRhs * kMaxRhs);
     ALLOC(S->bn2, sizeof(double) * 4 * kMaxRhs);  // |b|^2, then per-RHS scales
     ALLOC(S->active, sizeof(int) * kMaxRhs);
+    if (L->eo_ok) ALLOC(S->d_mask_eo, (size_t)2 * L->Vhs);
 #undef ALLOC
     if (s == GRG_OK && hipHostMalloc((void **)&S->h_buf, sizeof(double) * 8 * kMaxRhs) != hipSuccess) {
         S->h_buf = nullptr;
@@ -403,6 +421,21 @@ grg_status grg_schur_create(grg_lattice L, double m0, const int32_t *q, int32_t 
     GRG_TRY_HIP(hipMemcpyAsync(S->d_bidx, bidx.data(), sizeof(int32_t) * V, hipMemcpyHostToDevice, st));
     void *f64s[5] = {S->b64, S->x64, S->r64, S->t64, S->u64};
     for (void *p : f64s) GRG_TRY_HIP(launch_fill_zero(p, f64, st));
+    if (L->eo_ok) {
+        GRG_TRY_HIP(launch_eo_pack_mask(g, L->Vhs, S->d_mask, S->d_mask_eo, st));
+        // the reduced system lives on the parity with fewer rest sites
+        long rest[2] = {0, 0};
+        for (int x = 0; x < V; ++x) {
+            if (mask[x]) continue;
+            int c = x, par = 0;
+            for (int mu = 0; mu < 4; ++mu) {
+                par += c % g.L[mu];
+                c /= g.L[mu];
+            }
+            ++rest[par & 1];
+        }
+        S->eo_par = rest[0] < rest[1] ? 0 : 1;
+    }
     GRG_TRY_HIP(hipStreamSynchronize(st));
     *out = S;
     return GRG_OK;
@@ -460,7 +493,7 @@ static grg_status finish_call(grg_schur S, grg_status st, clk::time_point t0, gr
         stats->t_total_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
         stats->n_dslash = S->n_dslash;
         double tot = 0;
-        for (int p = 0; p < 3; ++p) tot += S->prof.total_ms[p];
+        for (int p = 0; p < 6; ++p) tot += S->prof.total_ms[p];
         stats->t_dslash_ms = tot - dsl_before;
     }
     return st;
@@ -481,7 +514,7 @@ grg_status grg_drr_solve(grg_schur S, const double *rhs, double *x, int nrhs, gr
     if (stats) memset(stats, 0, sizeof *stats);
     const auto t0 = clk::now();
     double before = 0;
-    for (int p = 0; p < 3; ++p) before += S->prof.total_ms[p];
+    for (int p = 0; p < 6; ++p) before += S->prof.total_ms[p];
     S->n_dslash = 0;
     S->fallbacks = 0;
     grg_lattice L = S->lat;
@@ -500,7 +533,7 @@ grg_status grg_schur_apply(grg_schur S, const double *x_b, double *y_b, int nrhs
     if (stats) memset(stats, 0, sizeof *stats);
     const auto t0 = clk::now();
     double before = 0;
-    for (int p = 0; p < 3; ++p) before += S->prof.total_ms[p];
+    for (int p = 0; p < 6; ++p) before += S->prof.total_ms[p];
     S->n_dslash = 0;
     S->fallbacks = 0;
     grg_status st = schur_apply_internal(S, x_b, y_b, nrhs, stats);
@@ -514,7 +547,7 @@ grg_status grg_reusken_apply(grg_schur S, const double *x_b, double *y_b, int nr
     DeviceGuard dg(S->lat->device);
     const auto t0 = clk::now();
     double before = 0;
-    for (int p = 0; p < 3; ++p) before += S->prof.total_ms[p];
+    for (int p = 0; p < 6; ++p) before += S->prof.total_ms[p];
     S->n_dslash = 0;
     grg_status st = reusken_apply_internal(S, x_b, y_b, nrhs);
     return finish_call(S, st, t0, nullptr, before);
@@ -573,6 +606,7 @@ grg_status grg_schur_tune(grg_schur S, int nrhs)
     GRG_TRY(tune_dslash(S, GRG_FP64, nrhs, 3));
     if (S->prm.inner != GRG_FP64) GRG_TRY(tune_dslash(S, S->prm.inner, nrhs, 3));
     GRG_TRY(tune_dc(S, S->prm.inner, nrhs, 3));
+    if (S->prm.eo) GRG_TRY(tune_eo(S, S->prm.inner, nrhs, 3));
     GRG_TRY_HIP(hipStreamSynchronize(S->lat->stream));
     return GRG_OK;
 }
@@ -615,8 +649,19 @@ grg_status grg_schur_set_dc_launch(grg_schur S, int precision, int nrhs, const i
 grg_status grg_schur_tune_info(grg_schur S, int precision, int nrhs, int32_t info[6], float *ms)
 {
     if (!S || !info || !ms) return set_error("null argument"), GRG_EINVAL;
-    if (precision < 0 || precision > 2 || nrhs < 1 || nrhs > kMaxRhs)
+    if (precision < 0 || precision > 5 || nrhs < 1 || nrhs > kMaxRhs)
         return set_error("bad precision or nrhs"), GRG_EINVAL;
+    if (precision >= 3) {  // the half-lattice stencil of the even-odd reduced solve
+        Geom gh = S->lat->g;
+        gh.V /= 2;
+        gh.Vs = S->lat->Vhs;
+        const DslashTune &t = S->eotune[precision - 3][nrhs];
+        const DslashTune d = t.valid ? t : default_eo_tune(gh, precision - 3, nrhs);
+        const int32_t v[6] = {d.SB, d.RG, d.split, d.grid, d.chunk, 0};
+        memcpy(info, v, sizeof(v));
+        *ms = t.valid ? t.ms : -1.0f;
+        return GRG_OK;
+    }
     const DslashTune &t = S->tune[precision][nrhs];
     const DslashTune d = t.valid ? t : default_tune(S->lat->g, precision, nrhs);
     info[0] = d.SB;
@@ -690,7 +735,7 @@ grg_status grg_profile_enable(grg_schur S, int on)
 grg_status grg_profile_read(grg_schur S, int precision, int64_t *count, double *total_ms)
 {
     if (!S || !count || !total_ms) return set_error("null argument"), GRG_EINVAL;
-    if (precision < 0 || precision > 2) return set_error("bad precision"), GRG_EINVAL;
+    if (precision < 0 || precision > 5) return set_error("bad precision"), GRG_EINVAL;
     *count = S->prof.count[precision];
     *total_ms = S->prof.total_ms[precision];
     return GRG_OK;
@@ -699,7 +744,7 @@ grg_status grg_profile_read(grg_schur S, int precision, int64_t *count, double *
 grg_status grg_profile_reset(grg_schur S)
 {
     if (!S) return set_error("null argument"), GRG_EINVAL;
-    for (int p = 0; p < 3; ++p) {
+    for (int p = 0; p < 6; ++p) {
         S->prof.count[p] = 0;
         S->prof.total_ms[p] = 0;
     }

@@ -52,6 +52,24 @@ struct DslashArgs {
     const void *dot_with; // the fused dots use this field instead of `in` (or nullptr)
 };
 
+// Stencil between the compact parity halves of the even-odd reduction
+// (kernels_eo.hip): out = alpha in2 + beta (H in) on the rest sites of parity
+// po, H the hopping term (D minus its diagonal).
+struct EoArgs {
+    const void *in;       // compact field of parity 1 - po
+    const void *in2;      // compact field of parity po, or nullptr (alpha term dropped)
+    void *out;            // compact field of parity po
+    const void *U;        // links, [2][compact tiles][4][9][64]
+    const uint8_t *mask;  // [2][Vhs]: 1 on coarse sites and padding
+    int po;               // output parity
+    double alpha, beta;
+    Geom g;               // the full lattice
+    int Vh, Vhs;          // half volume, and padded to whole tiles (multiple of 256)
+    int nrhs, SB, RG, hops, chunk;
+    double *partials;     // [grid][nrhs][3] or nullptr
+    const void *dot_with; // parity po
+};
+
 // A tuned launch of the stencil for one precision and RHS count.
 struct DslashTune {
     int valid = 0;
@@ -93,6 +111,12 @@ hipError_t launch_dslash(int prec, const DslashArgs &a, int grid, hipStream_t st
 // the t-marching kernel runs with 64 * a.RG threads per workgroup.
 hipError_t launch_dc_update(int prec, const DcArgs &a, int grid, int SB, hipStream_t st);
 hipError_t launch_dslash_coarse(const CoarseArgs &a, hipStream_t st);
+hipError_t launch_eo_hop(int prec, const EoArgs &a, int grid, hipStream_t st);
+// merge = false: full -> (even, odd) compact halves; true: the reverse
+hipError_t launch_eo_split(int prec, const Geom &g, int Vhs, int nrhs, const void *full, void *even,
+                           void *odd, bool merge, hipStream_t st);
+hipError_t launch_eo_pack_links(int prec, const Geom &g, int Vhs, const void *U, void *Ueo, hipStream_t st);
+hipError_t launch_eo_pack_mask(const Geom &g, int Vhs, const uint8_t *mask, uint8_t *meo, hipStream_t st);
 hipError_t launch_pack_gauge(const double *src, const Geom &g, const int bc[4], void *u64,
                              void *u32, void *u16, hipStream_t st);
 hipError_t launch_pack_spinor(int prec, const double *src, void *dst, const Geom &g, int nrhs,

@@ -11,6 +11,11 @@ struct grg_lattice_s {
     int device;
     hipStream_t stream;
     void *U[3] = {nullptr, nullptr, nullptr};  // internal links per grg_precision
+    // even-odd reduction (every extent even): links per parity, compact
+    // half-lattice tiles ([2][Vhs / 64][4][9][64] per precision)
+    bool eo_ok = false;
+    int Vhs = 0;
+    void *Ueo[3] = {nullptr, nullptr, nullptr};
     bool gauge_set = false;
     // grow-only scratch of grg_dirac_apply
     void *tmp_in = nullptr, *tmp_out = nullptr;
@@ -25,8 +30,9 @@ struct ProfilePool {
     std::vector<hipEvent_t> start, stop;
     std::vector<int> prec;
     int used = 0;
-    long long count[3] = {0, 0, 0};
-    double total_ms[3] = {0, 0, 0};
+    // slots 0..2: full-lattice stencil per precision; 3..5: even-odd half-stencil
+    long long count[6] = {0, 0, 0, 0, 0, 0};
+    double total_ms[6] = {0, 0, 0, 0, 0, 0};
 };
 
 }  // namespace grg
@@ -75,6 +81,13 @@ struct grg_schur_s {
     double *cb_in = nullptr, *cb_out = nullptr;
     // row sums of D_rr (one FP64 field) for the section 3 approximation
     void *dt64 = nullptr;
+    // even-odd reduced inner solve: mask per parity ([2][Vhs]), the parity of
+    // the reduced system, and compact fields per inner precision:
+    // b_even, b_odd, r, x, q (reduced parity) and t (other parity)
+    uint8_t *d_mask_eo = nullptr;
+    int eo_par = 1;
+    void *eo_f[3][6] = {};
+    grg::DslashTune eotune[3][grg::kMaxRhs + 1];
     // reduction scratch
     double *partials = nullptr;
     size_t partials_elems = 0;

@@ -1,0 +1,294 @@
+// Even-odd (red-black) reduction of the D_rr solve.
+//
+// The hopping term of the Wilson operator only couples sites of opposite
+// parity (x + y + z + t mod 2), so on the rest sites R = R_e + R_o
+//     D_rr = [[d, H_eo], [H_oe, d]],   d = 4 + m0,
+// and D_rr z = b is solved through the Schur complement on one parity p
+// (the reduction this library applies to D_rr is the same block elimination
+// the coarse operator itself is built from):
+//     b^_p = b_p - H_pq b_q / d,   (d - H_pq H_qp / d) z_p = b^_p,
+//     z_q = (b_q - H_qp z_p) / d,               q = 1 - p.
+// The residual of the reduced system is the residual of the full one on R_p
+// and zero on R_q, so the inner tolerance carries over unchanged.
+//
+// Fields of one parity are compact: half-site index h = s / 2 (the x extent
+// is even, so sites 2h and 2h + 1 have opposite parities), tiled like the
+// full fields (fidx(h, ...)), so that a stencil over one parity reads and
+// writes only lines of that parity.  The links are kept in the same compact
+// form per parity (lidx(h, ...) in block p of a [2][...] array) and the
+// coarse/rest mask per parity ([2][Vhs], padding marked coarse).
+#include <algorithm>
+
+#include "common.h"
+#include "engine.h"
+#include "stencil.h"
+
+namespace grg {
+
+// site of half index h with parity p, and its coordinates
+__device__ __forceinline__ int eo_site(int h, int p, const Geom &g, SiteGeo &q)
+{
+    const int s0 = 2 * h;
+    q = site_geo(s0, g);
+    const int b = (p ^ q.c[1] ^ q.c[2] ^ q.c[3]) & 1;  // parity of s0 is y + z + t (x0 even)
+    q.c[0] += b;
+    return s0 + b;
+}
+
+__device__ __forceinline__ int site_parity(int s, const Geom &g)
+{
+    const SiteGeo q = site_geo(s, g);
+    return (q.c[0] ^ q.c[1] ^ q.c[2] ^ q.c[3]) & 1;
+}
+
+// Operands of hop k (0..7 = +x, -x, ..., -t) of the site s = (h, parity po):
+// the neighbour's compact input and the link, U_mu(s) from the output
+// parity's links for a forward hop, U_mu(s - mu) from the input parity's
+// links for a backward one.
+template <class OP, class S>
+__device__ __forceinline__ void eo_load_hop(int k, typename OP::T (&p)[12], typename OP::T (&u)[9],
+                                            const S *__restrict__ in, const S *__restrict__ Uo,
+                                            const S *__restrict__ Ui, int s, int h,
+                                            const SiteGeo &q, const Geom &g, int r, int nrhs)
+{
+    const int mu = k >> 1;
+    int sp, sm;
+    nbr(s, mu, q, g, sp, sm);
+    const int hn = ((k & 1) ? sm : sp) >> 1;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) p[c] = OP::load(in, fidx(hn, r, c, nrhs));
+    if (k & 1) {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) u[e] = OP::load(Ui, lidx(hn, mu, e));
+    } else {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) u[e] = OP::load(Uo, lidx(h, mu, e));
+    }
+}
+
+template <class R, class PT>
+__device__ __forceinline__ void eo_hop_k(int k, cpx<R> (&acc)[12], const PT (&p)[12], const PT (&u)[9])
+{
+    switch (k) {
+    case 0: hop<0, true>(acc, p, u); break;
+    case 1: hop<0, false>(acc, p, u); break;
+    case 2: hop<1, true>(acc, p, u); break;
+    case 3: hop<1, false>(acc, p, u); break;
+    case 4: hop<2, true>(acc, p, u); break;
+    case 5: hop<2, false>(acc, p, u); break;
+    case 6: hop<3, true>(acc, p, u); break;
+    default: hop<3, false>(acc, p, u); break;
+    }
+}
+
+// out = alpha in2 + beta (H in) on the rest sites of parity po (zero on its
+// coarse sites); in has parity 1 - po, in2 and out parity po.  With partials,
+// also the per-workgroup sums conj(out).w (re, im) and |out|^2 per RHS,
+// w = dot_with (parity po).  HOPS = 2 double-buffers the hop operands (packed
+// BF16), otherwise one hop per loop iteration.
+template <int P, int HOPS>
+__global__ void __launch_bounds__(256) eo_hop_kernel(EoArgs a)
+{
+    typedef typename Store<P>::S S;
+    typedef typename Store<P>::R R;
+    typedef Operand<S, R> OP;
+    typedef typename OP::T PT;
+    __shared__ double red[4][kMaxRhs][3];
+    const S *__restrict__ in = (const S *)a.in;
+    const S *__restrict__ in2 = (const S *)a.in2;
+    S *__restrict__ out = (S *)a.out;
+    const S *__restrict__ Uo = (const S *)a.U + (size_t)a.po * 36 * a.Vhs;
+    const S *__restrict__ Ui = (const S *)a.U + (size_t)(1 - a.po) * 36 * a.Vhs;
+    const uint8_t *__restrict__ mk = a.mask + (size_t)a.po * a.Vhs;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const bool dots = a.partials != nullptr;
+    if (dots) {
+        for (int i = lane; i < a.nrhs * 3; i += 64) red[wave][i / 3][i % 3] = 0.0;
+        __syncthreads();
+    }
+    const R al = (R)a.alpha, be = (R)a.beta;
+    const int ngroups = (a.nrhs + a.RG - 1) / a.RG;
+    const int nsb = (a.Vh + a.SB - 1) / a.SB;
+    const int nitems = nsb * ngroups;
+    const int C = a.chunk > 0 ? a.chunk : (nitems + 7) / 8;
+    for (int j = blockIdx.x >> 3;; j += gridDim.x >> 3) {
+        const int w = xcd_chunk_item(j, C, nitems);
+        if (w < 0) break;
+        const int sb = w / ngroups, grp = w - sb * ngroups;
+        const int h = sb * a.SB + (int)threadIdx.x;
+        const bool valid = h < a.Vh;
+        const bool on = valid && mk[h] == 0;
+        SiteGeo q;
+        int s = 0;
+        if (on) s = eo_site(h, a.po, a.g, q);
+        const int r0 = grp * a.RG, r1 = min(r0 + a.RG, a.nrhs);
+        for (int r = r0; r < r1; ++r) {
+            cpx<R> acc[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
+            if (on) {
+                if constexpr (HOPS == 2 && OP::kPacked) {
+                    PT pa[12], pb[12], ua[9], ub[9];
+                    eo_load_hop<OP>(0, pa, ua, in, Uo, Ui, s, h, q, a.g, r, a.nrhs);
+#pragma unroll 1
+                    for (int mu = 0; mu < 4; ++mu) {
+                        eo_load_hop<OP>(2 * mu + 1, pb, ub, in, Uo, Ui, s, h, q, a.g, r, a.nrhs);
+                        eo_hop_k(2 * mu, acc, pa, ua);
+                        if (mu < 3) eo_load_hop<OP>(2 * mu + 2, pa, ua, in, Uo, Ui, s, h, q, a.g, r, a.nrhs);
+                        eo_hop_k(2 * mu + 1, acc, pb, ub);
+                    }
+                } else {
+#pragma unroll 1
+                    for (int k = 0; k < 8; ++k) {
+                        PT p[12], u[9];
+                        eo_load_hop<OP>(k, p, u, in, Uo, Ui, s, h, q, a.g, r, a.nrhs);
+                        eo_hop_k(k, acc, p, u);
+                    }
+                }
+            }
+            R sre = 0, sim = 0, sqq = 0;
+            if (valid) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    const size_t i = fidx(h, r, c, a.nrhs);
+                    cpx<R> o = {0, 0};
+                    if (on) {
+                        o = {be * acc[c].re, be * acc[c].im};
+                        if (in2) {
+                            const cpx<R> v = ldr<R>(in2, i);
+                            o.re = fma(al, v.re, o.re);
+                            o.im = fma(al, v.im, o.im);
+                        }
+                    }
+                    stc(out, i, o);
+                    if (dots && on) {
+                        const cpx<R> v = ldr<R>((const S *)a.dot_with, i);
+                        sre = fma(o.re, v.re, fma(o.im, v.im, sre));
+                        sim = fma(o.re, v.im, fma(-o.im, v.re, sim));
+                        sqq = fma(o.re, o.re, fma(o.im, o.im, sqq));
+                    }
+                }
+            }
+            if (dots) {
+                const double dre = wave_sum((double)sre);
+                const double dim = wave_sum((double)sim);
+                const double dqq = wave_sum((double)sqq);
+                if (lane == 0) {
+                    red[wave][r][0] += dre;
+                    red[wave][r][1] += dim;
+                    red[wave][r][2] += dqq;
+                }
+            }
+        }
+    }
+    if (dots) {
+        __syncthreads();
+        const int nw = blockDim.x >> 6;
+        for (int i = threadIdx.x; i < a.nrhs * 3; i += blockDim.x) {
+            double t = 0;
+            for (int k = 0; k < nw; ++k) t += red[k][i / 3][i % 3];
+            a.partials[(size_t)blockIdx.x * a.nrhs * 3 + i] = t;
+        }
+    }
+}
+
+// full field <-> its two compact parity halves (every RHS)
+template <int P>
+__global__ void __launch_bounds__(256) eo_split_kernel(Geom g, int Vhs, int nrhs, const void *full_,
+                                                       void *even_, void *odd_, int merge)
+{
+    typedef typename Store<P>::S S;
+    S *full = (S *)full_, *half[2] = {(S *)even_, (S *)odd_};
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < g.V; s += gridDim.x * blockDim.x) {
+        S *hf = half[site_parity(s, g)];
+        const int h = s >> 1;
+        for (int r = 0; r < nrhs; ++r) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                if (merge) full[fidx(s, r, c, nrhs)] = hf[fidx(h, r, c, nrhs)];
+                else hf[fidx(h, r, c, nrhs)] = full[fidx(s, r, c, nrhs)];
+            }
+        }
+    }
+}
+
+// links [tiles][4][9][64] -> [2][half tiles][4][9][64]; mask -> [2][Vhs]
+template <class S>
+__global__ void __launch_bounds__(256) eo_pack_links_kernel(Geom g, int Vhs, const S *U, S *Ueo)
+{
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < g.V; s += gridDim.x * blockDim.x) {
+        S *dst = Ueo + (size_t)site_parity(s, g) * 36 * Vhs;
+        const int h = s >> 1;
+        for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+            for (int e = 0; e < 9; ++e) dst[lidx(h, mu, e)] = U[lidx(s, mu, e)];
+    }
+}
+
+__global__ void __launch_bounds__(256) eo_pack_mask_kernel(Geom g, int Vhs, const uint8_t *mask,
+                                                           uint8_t *meo)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 2 * Vhs) return;
+    const int p = i / Vhs, h = i - p * Vhs;
+    uint8_t v = 1;  // padding: never a rest site
+    if (h < g.V / 2) {
+        SiteGeo q;
+        const int s = eo_site(h, p, g, q);
+        v = mask[s];
+    }
+    meo[i] = v;
+}
+
+static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+hipError_t launch_eo_hop(int prec, const EoArgs &a, int grid, hipStream_t st)
+{
+    if (a.nrhs < 1 || a.nrhs > kMaxRhs || a.RG < 1 || grid < 8 || grid % 8) return hipErrorInvalidValue;
+    if (a.SB != 64 && a.SB != 128 && a.SB != 256) return hipErrorInvalidValue;
+    dim3 blk(a.SB), grd(grid);
+    const bool pipe = a.hops == 2 && prec == GRG_BF16;
+    switch (prec) {
+    case GRG_FP64: hipLaunchKernelGGL((eo_hop_kernel<GRG_FP64, 1>), grd, blk, 0, st, a); break;
+    case GRG_FP32: hipLaunchKernelGGL((eo_hop_kernel<GRG_FP32, 1>), grd, blk, 0, st, a); break;
+    case GRG_BF16:
+        if (pipe) hipLaunchKernelGGL((eo_hop_kernel<GRG_BF16, 2>), grd, blk, 0, st, a);
+        else hipLaunchKernelGGL((eo_hop_kernel<GRG_BF16, 1>), grd, blk, 0, st, a);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_eo_split(int prec, const Geom &g, int Vhs, int nrhs, const void *full, void *even,
+                           void *odd, bool merge, hipStream_t st)
+{
+    const int grid = std::min(cdiv(g.V, 256), 8192);
+    switch (prec) {
+    case GRG_FP64: hipLaunchKernelGGL(eo_split_kernel<GRG_FP64>, dim3(grid), dim3(256), 0, st, g, Vhs, nrhs, full, even, odd, (int)merge); break;
+    case GRG_FP32: hipLaunchKernelGGL(eo_split_kernel<GRG_FP32>, dim3(grid), dim3(256), 0, st, g, Vhs, nrhs, full, even, odd, (int)merge); break;
+    case GRG_BF16: hipLaunchKernelGGL(eo_split_kernel<GRG_BF16>, dim3(grid), dim3(256), 0, st, g, Vhs, nrhs, full, even, odd, (int)merge); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_eo_pack_links(int prec, const Geom &g, int Vhs, const void *U, void *Ueo, hipStream_t st)
+{
+    const int grid = std::min(cdiv(g.V, 256), 8192);
+    switch (prec) {
+    case GRG_FP64: hipLaunchKernelGGL(eo_pack_links_kernel<double2>, dim3(grid), dim3(256), 0, st, g, Vhs, (const double2 *)U, (double2 *)Ueo); break;
+    case GRG_FP32: hipLaunchKernelGGL(eo_pack_links_kernel<float2>, dim3(grid), dim3(256), 0, st, g, Vhs, (const float2 *)U, (float2 *)Ueo); break;
+    case GRG_BF16: hipLaunchKernelGGL(eo_pack_links_kernel<bf16x2>, dim3(grid), dim3(256), 0, st, g, Vhs, (const bf16x2 *)U, (bf16x2 *)Ueo); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_eo_pack_mask(const Geom &g, int Vhs, const uint8_t *mask, uint8_t *meo, hipStream_t st)
+{
+    hipLaunchKernelGGL(eo_pack_mask_kernel, dim3(cdiv(2L * Vhs, 256)), dim3(256), 0, st, g, Vhs, mask, meo);
+    return hipGetLastError();
+}
+
+}  // namespace grg

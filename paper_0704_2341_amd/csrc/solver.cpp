@@ -449,6 +449,225 @@ static grg_status inner_gcr(grg_schur S, int prec, int nrhs, const double *thr, 
     return done ? GRG_OK : GRG_ENOCONV;
 }
 
+// ------------------------------------------------------------------ even-odd inner solve
+// Geometry of the compact parity halves, for the vector kernels.
+static Geom half_geom(grg_lattice L)
+{
+    Geom gh = L->g;
+    gh.V = L->g.V / 2;
+    gh.Vs = L->Vhs;
+    return gh;
+}
+
+DslashTune default_eo_tune(const Geom &gh, int prec, int nrhs)
+{
+    DslashTune t;
+    t.SB = 256;
+    t.RG = std::min(nrhs, 3);
+    t.split = prec == GRG_BF16 ? 2 : 1;  // hop schedule
+    const long items = (long)((gh.V + t.SB - 1) / t.SB) * ((nrhs + t.RG - 1) / t.RG);
+    t.grid = round8(std::min<long>(items, 2048));
+    return t;
+}
+
+static grg_status ensure_eo(grg_schur S, int prec)
+{
+    grg_lattice L = S->lat;
+    const size_t bytes = spinor_elems(half_geom(L), S->prm.max_rhs) * prec_bytes(prec);
+    for (int k = 0; k < 6; ++k) {
+        void *&b = S->eo_f[prec][k];
+        if (b) continue;
+        if (hipMalloc(&b, bytes) != hipSuccess) {
+            b = nullptr;
+            set_error("even-odd workspace: hipMalloc of %zu bytes failed", bytes);
+            return GRG_ENOMEM;
+        }
+        GRG_TRY_HIP(launch_fill_zero(b, bytes, L->stream));
+    }
+    return GRG_OK;
+}
+
+// out = alpha in2 + beta H in on the rest sites of parity po (compact fields)
+static grg_status eo_hop(grg_schur S, int prec, const DslashTune &t, const void *in, const void *in2,
+                         void *out, int po, double alpha, double beta, int nrhs, double *partials,
+                         const void *dot_with)
+{
+    grg_lattice L = S->lat;
+    EoArgs a;
+    a.in = in;
+    a.in2 = in2;
+    a.out = out;
+    a.U = L->Ueo[prec];
+    a.mask = S->d_mask_eo;
+    a.po = po;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.g = L->g;
+    a.Vh = L->g.V / 2;
+    a.Vhs = L->Vhs;
+    a.nrhs = nrhs;
+    a.SB = t.SB;
+    a.RG = t.RG;
+    a.hops = t.split;
+    a.chunk = t.chunk;
+    a.partials = partials;
+    a.dot_with = dot_with;
+    ProfilePool &P = S->prof;
+    const bool ev = P.on && P.used < (int)P.start.size();
+    if (ev) GRG_TRY_HIP(hipEventRecord(P.start[P.used], L->stream));
+    GRG_TRY_HIP(launch_eo_hop(prec, a, t.grid, L->stream));
+    if (ev) {
+        GRG_TRY_HIP(hipEventRecord(P.stop[P.used], L->stream));
+        P.prec[P.used] = prec + 3;
+        ++P.used;
+    }
+    ++S->n_dslash;
+    return GRG_OK;
+}
+
+bool eo_launch_ok(const Geom &gh, int prec, int nrhs, const DslashTune &t)
+{
+    return (t.SB == 64 || t.SB == 128 || t.SB == 256) && t.RG >= 1 && t.RG <= nrhs &&
+           (t.split == 1 || (t.split == 2 && prec == GRG_BF16)) && t.grid >= 8 && t.grid % 8 == 0 &&
+           t.grid <= kMaxGridValue && t.chunk >= 0 && gh.V > 0;
+}
+
+// Autotuner of the reduced operator's half-stencil (timed as the solver runs
+// its second half: with the alpha term and the fused dot products).
+grg_status tune_eo(grg_schur S, int prec, int nrhs, int reps)
+{
+    grg_lattice L = S->lat;
+    if (!L->eo_ok) return GRG_OK;
+    GRG_TRY(ensure_eo(S, prec));
+    hipStream_t st = L->stream;
+    const Geom gh = half_geom(L);
+    void **f = S->eo_f[prec];
+    hipEvent_t e0, e1;
+    GRG_TRY_HIP(hipEventCreate(&e0));
+    GRG_TRY_HIP(hipEventCreate(&e1));
+    grg_status status = GRG_OK;
+    auto timeit = [&](DslashTune &t) {
+        if (status != GRG_OK) return;
+        t.ms = 1e30f;
+        if (!eo_launch_ok(gh, prec, nrhs, t)) return;
+        status = eo_hop(S, prec, t, f[5], f[2], f[4], S->eo_par, 4.0, -0.25, nrhs, S->partials, f[2]);
+        if (status == GRG_OK && hipEventRecord(e0, st) != hipSuccess) status = GRG_EHIP;
+        for (int k = 0; k < reps && status == GRG_OK; ++k)
+            status = eo_hop(S, prec, t, f[5], f[2], f[4], S->eo_par, 4.0, -0.25, nrhs, S->partials, f[2]);
+        if (status == GRG_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+            status = GRG_EHIP;
+        if (status != GRG_OK) return;
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        t.ms = ms / reps;
+    };
+    std::vector<DslashTune> cands;
+    for (int sb : {64, 128, 256}) {
+        for (int rg = 1; rg <= nrhs; ++rg) {
+            if ((nrhs % rg && rg != nrhs) || (rg > 4 && rg != nrhs)) continue;
+            for (int hops = 1; hops <= (prec == GRG_BF16 ? 2 : 1); ++hops) {
+                DslashTune t = default_eo_tune(gh, prec, nrhs);
+                t.SB = sb;
+                t.RG = rg;
+                t.split = hops;
+                const long items = (long)((gh.V + sb - 1) / sb) * ((nrhs + rg - 1) / rg);
+                t.grid = round8(std::min<long>(items, 2048));
+                timeit(t);
+                cands.push_back(t);
+            }
+        }
+    }
+    std::sort(cands.begin(), cands.end(), [](const DslashTune &a, const DslashTune &b) { return a.ms < b.ms; });
+    DslashTune best = cands.empty() ? default_eo_tune(gh, prec, nrhs) : cands[0];
+    for (size_t i = 0; i < std::min<size_t>(2, cands.size()); ++i) {
+        const long items = (long)((gh.V + cands[i].SB - 1) / cands[i].SB) *
+                           ((nrhs + cands[i].RG - 1) / cands[i].RG);
+        for (int cap : {1024, 2048, kMaxGridValue}) {
+            for (int ch : {0, 8, 64}) {
+                DslashTune t = cands[i];
+                t.grid = round8(std::min<long>(items, cap));
+                t.chunk = ch;
+                if (ch > 0 && ch * 8 >= items) continue;
+                timeit(t);
+                if (t.ms < best.ms) best = t;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status != GRG_OK) return status;
+    best.valid = 1;
+    S->eotune[prec][nrhs] = best;
+    return GRG_OK;
+}
+
+// Minimal residual on the even-odd reduced system.  The inner right-hand
+// side b is in in_r (full layout); the solution is written to in_x (full
+// layout, zero on the coarse sites), as inner_gcr does.
+static grg_status inner_mr_eo(grg_schur S, int prec, int nrhs, const double *thr, int maxit,
+                              int *iters, double *rn2_out)
+{
+    grg_lattice L = S->lat;
+    hipStream_t st = L->stream;
+    const Geom &g = L->g;
+    GRG_TRY(ensure_eo(S, prec));
+    const Geom gh = half_geom(L);
+    const BlasShape sh = blas_shape(gh, nrhs);
+    const size_t vbytes = spinor_elems(gh, nrhs) * prec_bytes(prec);
+    const DslashTune t = S->eotune[prec][nrhs].valid ? S->eotune[prec][nrhs]
+                                                     : default_eo_tune(gh, prec, nrhs);
+    const int P = S->eo_par, Q = 1 - P;
+    void **f = S->eo_f[prec];
+    void *bh[2] = {f[0], f[1]};
+    void *r = f[2], *x = f[3], *q = f[4], *w = f[5];
+    const double d = 4.0 + S->m0;
+    const int check = std::max(1, S->prm.check_every);
+    // the reduced right-hand side b_P - H_PQ b_Q / d
+    GRG_TRY_HIP(launch_eo_split(prec, g, L->Vhs, nrhs, S->in_r[prec], bh[0], bh[1], false, st));
+    GRG_TRY(eo_hop(S, prec, t, bh[Q], bh[P], r, P, 1.0, -1.0 / d, nrhs, nullptr, nullptr));
+    GRG_TRY_HIP(launch_fill_zero(x, vbytes, st));
+    GRG_TRY_HIP(launch_norm2(prec, sh, r, S->partials, st));
+    GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, S->thr2,
+                              S->active, st));
+    double h[kMaxRhs];
+    GRG_TRY(read_norms(S, nrhs, h));
+    auto all_done = [&](const double *n2) {
+        for (int k = 0; k < nrhs; ++k) {
+            if (!isfinite(n2[k])) return -1;
+            if (n2[k] > thr[k]) return 0;
+        }
+        return 1;
+    };
+    int it = 0;
+    int done = all_done(h);
+    while (done == 0 && it < maxit) {
+        // q = (d - H_PQ H_QP / d) r, with the sums for alpha
+        GRG_TRY(eo_hop(S, prec, t, r, nullptr, w, Q, 0.0, 1.0, nrhs, nullptr, nullptr));
+        GRG_TRY(eo_hop(S, prec, t, w, r, q, P, d, -1.0 / d, nrhs, S->partials, r));
+        GRG_TRY_HIP(launch_reduce(kAlpha, S->partials, t.grid, nrhs, S->alpha, nullptr, nullptr,
+                                  S->active, st));
+        GRG_TRY_HIP(launch_mr_update(prec, sh, x, r, q, nullptr, S->alpha, S->partials, st));
+        GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, S->thr2,
+                                  S->active, st));
+        ++it;
+        if (it % check == 0 || it == maxit) {
+            GRG_TRY(read_norms(S, nrhs, h));
+            done = all_done(h);
+        }
+    }
+    *iters = it;
+    memcpy(rn2_out, h, sizeof(double) * nrhs);
+    // z_Q = (b_Q - H_QP z_P) / d, then both halves into the full layout
+    GRG_TRY(eo_hop(S, prec, t, x, bh[Q], w, Q, 1.0 / d, -1.0 / d, nrhs, nullptr, nullptr));
+    GRG_TRY_HIP(launch_eo_split(prec, g, L->Vhs, nrhs, S->in_x[prec], P == 0 ? x : w,
+                                P == 0 ? w : x, true, st));
+    if (done < 0) {
+        set_error("non-finite residual in the inner solve");
+        return GRG_ENONFINITE;
+    }
+    return done ? GRG_OK : GRG_ENOCONV;
+}
+
 // Inner iterations allowed to a preconditioned inner solve before the plain
 // GCR fallback takes over.
 constexpr int kPrecondInnerCap = 100;
@@ -581,6 +800,9 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
                 S->precond = keep;
                 total += it;
             }
+        } else if (p.eo && L->eo_ok && std::max(1, p.restart) == 1) {
+            is = inner_mr_eo(S, prec, nrhs, thr, p.max_iter - total, &it, h);
+            total += it;
         } else {
             is = inner_gcr(S, prec, nrhs, thr, p.max_iter - total, &it, h);
             total += it;

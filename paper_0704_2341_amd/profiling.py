@@ -30,7 +30,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = [os.path.join(PKG, "csrc", f)
-                  for f in ("kernels_dslash.hip", "stencil.h", "common.h")]
+                  for f in ("kernels_dslash.hip", "kernels_eo.hip", "stencil.h", "common.h")]
 TRAFFIC_FILE = os.path.join(os.path.dirname(PKG), "profiles", "dslash_traffic.json")
 COPY_KERNEL = "neg_kernel"  # torch's negation: reads N bytes, writes N bytes
 
@@ -49,16 +49,17 @@ def traffic_key(prec: str, nrhs: int, dims) -> str:
     return f"{prec}_nrhs{nrhs}_{'x'.join(map(str, dims))}"
 
 
-def measured_traffic(prec: str, nrhs: int, dims, path: str = TRAFFIC_FILE):
-    """HBM bytes per launch from the committed counter runs, or None when the
-    stencil sources changed since they were taken."""
+def measured_traffic(key: str, path: str = TRAFFIC_FILE):
+    """HBM bytes per launch of the stencil `key` (traffic_key) from the
+    committed counter runs, or None when the stencil sources changed since
+    they were taken."""
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
     if t.get("kernel_source_sha256") != kernel_source_hash():
         return None
-    e = t.get("kernels", {}).get(traffic_key(prec, nrhs, dims))
+    e = t.get("kernels", {}).get(key)
     return None if e is None else e.get("hbm_bytes_per_launch")
 
 
@@ -162,8 +163,7 @@ def traffic_table(fetch_dir, write_dir, fetch_log, write_log, command, out=TRAFF
     fetch, nf = _counter_avg(fr, launch, "FETCH_SIZE")
     write, nw = _counter_avg(wr, launch, "WRITE_SIZE")
     hbm = fetch * 1024 * ff + write * 1024 * wf
-    cfg = bf["config"]
-    key = traffic_key(cfg["inner"], cfg["nrhs"], cfg["lattice"])
+    key = bf["roofline"]["traffic_key"]
     alg = bf["roofline"]["alg_bytes_per_launch"]
     entry = {"symbol": launch["symbol"], "grid_size": launch["grid_size"], "shape": launch["shape"],
              "dispatches": [nf, nw], "fetch_kib": fetch, "write_kib": write,

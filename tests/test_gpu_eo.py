@@ -1,0 +1,97 @@
+"""The even-odd reduced inner solve (D_rr eliminated to one parity) against
+the unreduced solve and the oracle: every inner precision, permutations whose
+coarse sites lie on one parity (Type I) or on both (the inverses), ragged
+volumes, the fallback on lattices with an odd extent, and its autotuned
+launch."""
+import numpy as np
+import pytest
+
+from grg_inputs import gaussian_vectors
+from oracle import matfree
+
+from gpu_support import Lattice, rel_err
+
+pytestmark = pytest.mark.gpu
+
+INNER_TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 1e-2}
+
+
+def rest_rhs(lat, s, nrhs, seed):
+    b = gaussian_vectors(12 * lat.V, nrhs, seed).reshape(nrhs, lat.V, 12)
+    b[:, np.asarray(s.q[: s.nb])] = 0
+    return b.reshape(nrhs, -1)
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("kind,inv", [("I", False), ("I", True), ("II", True)])
+def test_reduced_equals_unreduced(inner, kind, inv):
+    lat = Lattice((8, 8, 8, 8), 0.5, 21)
+    kw = dict(tol=1e-12, inner=inner, inner_tol=INNER_TOL[inner], max_rhs=3, max_iter=4000)
+    s1 = lat.schur(-0.2, kind, inv, eo=1, **kw)
+    s0 = lat.schur(-0.2, kind, inv, eo=0, **kw)
+    b = rest_rhs(lat, s1, 3, 21)
+    x1, st1 = s1.drr_solve(b)
+    x0, st0 = s0.drr_solve(b)
+    assert st1["converged"] and st0["converged"]
+    assert rel_err(x1, x0) < 1e-10
+    # the reduced system converges in fewer iterations
+    assert st1["iters"] < st0["iters"], (st1, st0)
+    rr = matfree.drr_residual(lat.links, lat.dims, -0.2, s1.q, s1.nb, b, x1)
+    assert np.all(rr <= 1e-12 * (1 + 1e-6)), rr
+    # zero on the coarse sites
+    assert not np.any(x1.reshape(3, lat.V, 12)[:, np.asarray(s1.q[: s1.nb])])
+    s1.close()
+    s0.close()
+    lat.close()
+
+
+@pytest.mark.parametrize("dims", [(8, 6, 4, 10), (4, 4, 4, 2)])
+def test_ragged_volumes(dims):
+    lat = Lattice(dims, 0.5, 22)
+    s = lat.schur(-0.1, "II", False, tol=1e-12, inner="bf16", inner_tol=1e-2, max_rhs=2, eo=1)
+    b = rest_rhs(lat, s, 2, 22)
+    x, st = s.drr_solve(b)
+    assert st["converged"]
+    rr = matfree.drr_residual(lat.links, dims, -0.1, s.q, s.nb, b, x)
+    assert np.all(rr <= 1e-12 * (1 + 1e-6)), rr
+    s.close()
+    lat.close()
+
+
+def test_odd_extent_falls_back():
+    """With an odd extent the lattice is not bipartite: the solve runs on
+    D_rr itself and still meets the tolerance."""
+    dims = (6, 4, 4, 5)
+    lat = Lattice(dims, 0.5, 23)
+    V = lat.V
+    rng = np.random.default_rng(23)
+    q = rng.permutation(V).astype(np.int32)
+    nb = V // 16
+    grg = lat.grg
+    h = grg.grg_schur_create(lat.h, -0.1, q, nb, grg.grg_solver_params_default(
+        tol=1e-12, inner="fp32", inner_tol=1e-5, max_rhs=2, eo=1))
+    from gpu_support import Schur
+
+    s = Schur(lat, h, q, nb, -0.1)
+    b = rest_rhs(lat, s, 2, 23)
+    x, st = s.drr_solve(b)
+    assert st["converged"]
+    rr = matfree.drr_residual(lat.links, dims, -0.1, q, nb, b, x)
+    assert np.all(rr <= 1e-12 * (1 + 1e-6)), rr
+    s.close()
+    lat.close()
+
+
+def test_tuned_reduced_solve_same_result():
+    lat = Lattice((16, 16, 8, 8), 0.5, 24)
+    s = lat.schur(-0.3, "I", False, tol=1e-12, inner="bf16", inner_tol=1e-2, max_rhs=4, eo=1)
+    xb = gaussian_vectors(12 * s.nb, 4, 24)
+    y0, st0 = s.apply(xb)
+    lat.grg.grg_schur_tune(s.h, 4)
+    y1, st1 = s.apply(xb)
+    assert st0["converged"] and st1["converged"]
+    assert rel_err(y1, y0) < 1e-11
+    want, _, _ = matfree.schur_apply(lat.links, lat.dims, -0.3, s.q, s.nb, xb[:1], restart=8, tol=1e-13)
+    assert rel_err(y1[:1], want) < 1e-10
+    s.close()
+    lat.close()
