@@ -25,7 +25,8 @@ void set_error(const char *fmt, ...)
     va_end(ap);
 }
 
-grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats);
+grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats,
+                              const void *u_minus = nullptr);
 grg_status schur_apply_internal(grg_schur S, const double *xb, double *yb, int nrhs,
                                 grg_solver_stats *stats);
 grg_status run_dslash(grg_schur S, int prec, const void *in, void *out, int sel, int nrhs,
@@ -330,6 +331,13 @@ static void schur_free(grg_schur S)
     dfree((void *&)S->cb_out);
     dfree(S->dt64);
     dfree((void *&)S->d_mask_eo);
+    for (int p = 0; p < 3; ++p) {
+        for (void *&b : S->epool[p]) dfree(b);
+        S->epool[p].clear();
+    }
+    dfree((void *&)S->d_fk);
+    if (S->h_fk) hipHostFree(S->h_fk);
+    S->h_fk = nullptr;
     for (int p = 0; p < 3; ++p)
         for (int k = 0; k < 6; ++k) dfree(S->eo_f[p][k]);
     dfree((void *&)S->partials);
@@ -340,6 +348,7 @@ static void schur_free(grg_schur S)
     dfree((void *&)S->qn2);
     dfree((void *&)S->bn2);
     dfree((void *&)S->active);
+    dfree((void *&)S->act0);
     if (S->h_buf) hipHostFree(S->h_buf);
     S->h_buf = nullptr;
     for (auto e : S->prof.start) hipEventDestroy(e);
@@ -403,9 +412,16 @@ grg_status grg_schur_create(grg_lattice L, double m0, const int32_t *q, int32_t 
     ALLOC(S->qn2, sizeof(double) * kMaxRhs * kMaxRhs);
     ALLOC(S->bn2, sizeof(double) * 4 * kMaxRhs);  // |b|^2, then per-RHS scales
     ALLOC(S->active, sizeof(int) * kMaxRhs);
+    ALLOC(S->act0, sizeof(int) * kMaxRhs);
     if (L->eo_ok) ALLOC(S->d_mask_eo, (size_t)2 * L->Vhs);
+    ALLOC(S->d_fk, sizeof(double) * kCorrPool * kMaxRhs);
 #undef ALLOC
-    if (s == GRG_OK && hipHostMalloc((void **)&S->h_buf, sizeof(double) * 8 * kMaxRhs) != hipSuccess) {
+    if (s == GRG_OK && hipHostMalloc((void **)&S->h_fk, sizeof(double) * kCorrPool * kMaxRhs) != hipSuccess) {
+        S->h_fk = nullptr;
+        set_error("hipHostMalloc failed");
+        s = GRG_ENOMEM;
+    }
+    if (s == GRG_OK && hipHostMalloc((void **)&S->h_buf, sizeof(double) * 12 * kMaxRhs) != hipSuccess) {
         S->h_buf = nullptr;
         set_error("hipHostMalloc failed");
         s = GRG_ENOMEM;

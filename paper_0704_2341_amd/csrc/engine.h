@@ -68,6 +68,19 @@ struct EoArgs {
     int nrhs, SB, RG, hops, chunk;
     double *partials;     // [grid][nrhs][3] or nullptr
     const void *dot_with; // parity po
+    const int *active;    // per RHS: 0 writes zero for that RHS (nullptr: all active)
+};
+
+// out = u + sigma (x + sum_j f[j][rhs] e_j) in FP64 (u, x nullable): the
+// defect correction's iterate from its kept corrections e_j (inner precision)
+constexpr int kCorrPool = 16;
+struct CombineArgs {
+    const void *e[kCorrPool];
+    const double *f;      // [kCorrPool][kMaxRhs]
+    int n;                // corrections in use
+    const void *u, *x;    // FP64 or nullptr
+    void *out;            // FP64, may alias x or u
+    double sigma;
 };
 
 // A tuned launch of the stencil for one precision and RHS count.
@@ -164,6 +177,7 @@ hipError_t launch_xmy(const BlasShape &sh, const void *x, void *y, hipStream_t s
 // Second-order Schur complement approximation (kernels_blas.hip): the
 // rest-site ones field, t = y / d~ and w = u - ((y - z) / d + t).
 hipError_t launch_rest_ones(const Geom &g, const uint8_t *mask, void *o, hipStream_t st);
+hipError_t launch_combine(int prec, const BlasShape &sh, const CombineArgs &a, hipStream_t st);
 hipError_t launch_reusken_divide(const BlasShape &sh, const void *y, const void *dt,
                                  const uint8_t *mask, void *t, hipStream_t st);
 hipError_t launch_reusken_combine(const BlasShape &sh, const void *u, const void *y, const void *z,

@@ -85,6 +85,10 @@ struct grg_schur_s {
     // the reduced system, and compact fields per inner precision:
     // b_even, b_odd, r, x, q (reduced parity) and t (other parity)
     uint8_t *d_mask_eo = nullptr;
+    // the defect correction's corrections e_k (inner precision, full layout)
+    // and their factors: the iterate is summed from them at the end
+    std::vector<void *> epool[3];
+    double *d_fk = nullptr, *h_fk = nullptr;  // [kCorrPool][kMaxRhs]
     int eo_par = 1;
     void *eo_f[3][6] = {};
     grg::DslashTune eotune[3][grg::kMaxRhs + 1];
@@ -96,7 +100,8 @@ struct grg_schur_s {
     // [|b|^2 | 1/s | s | next s] of the defect correction (4 kMaxRhs)
     double *rn2 = nullptr, *thr2 = nullptr, *qn2 = nullptr, *bn2 = nullptr;
     int *active = nullptr;
-    double *h_buf = nullptr;  // pinned host staging (8 * kMaxRhs doubles: reads, then uploads)
+    int *act0 = nullptr;      // RHS active when an inner solve started
+    double *h_buf = nullptr;  // pinned host staging (12 * kMaxRhs doubles: reads, uploads, flags)
     grg::ProfilePool prof;
     int n_dslash = 0;
     grg::DslashTune tune[3][grg::kMaxRhs + 1];    // per precision and nrhs

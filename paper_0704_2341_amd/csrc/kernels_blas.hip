@@ -347,6 +347,45 @@ __global__ void __launch_bounds__(256) reusken_combine_kernel(BlasShape sh, cons
     SITE_LOOP_END
 }
 
+template <int P>
+__global__ void __launch_bounds__(256) combine_kernel(BlasShape sh, CombineArgs a)
+{
+    typedef typename Store<P>::S S;
+    const double2 *u = (const double2 *)a.u, *x = (const double2 *)a.x;
+    double2 *out = (double2 *)a.out;
+    SITE_LOOP_BEGIN(sh)
+    if (valid) {
+        for (int k = 0; k < sh.nrhs; ++k) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const size_t i = fidx(s, k, c, sh.nrhs);
+                double2 v = x ? x[i] : make_double2(0.0, 0.0);
+                for (int j = 0; j < a.n; ++j) {
+                    const double f = a.f[j * kMaxRhs + k];
+                    const cpx<double> e = ldr<double>((const S *)a.e[j], i);
+                    v.x = fma(f, e.re, v.x);
+                    v.y = fma(f, e.im, v.y);
+                }
+                const double2 b = u ? u[i] : make_double2(0.0, 0.0);
+                out[i] = make_double2(fma(a.sigma, v.x, b.x), fma(a.sigma, v.y, b.y));
+            }
+        }
+    }
+    SITE_LOOP_END
+}
+
+hipError_t launch_combine(int prec, const BlasShape &sh, const CombineArgs &a, hipStream_t st)
+{
+    if (!shape_ok(sh) || a.n < 0 || a.n > kCorrPool) return hipErrorInvalidValue;
+    switch (prec) {
+    case GRG_FP64: hipLaunchKernelGGL(combine_kernel<GRG_FP64>, dim3(sh.grid), dim3(kBlasSB), 0, st, sh, a); break;
+    case GRG_FP32: hipLaunchKernelGGL(combine_kernel<GRG_FP32>, dim3(sh.grid), dim3(kBlasSB), 0, st, sh, a); break;
+    case GRG_BF16: hipLaunchKernelGGL(combine_kernel<GRG_BF16>, dim3(sh.grid), dim3(kBlasSB), 0, st, sh, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_rest_ones(const Geom &g, const uint8_t *mask, void *o, hipStream_t st)
 {
     BlasShape sh;

@@ -154,7 +154,8 @@ struct StoreEpi {
 };
 
 // DcEpi: one FP64 defect-correction step on the rest sites (see
-// dc_update_kernel): r_out = r_in - f acc, x_out = x_in + f e, r_next =
+// dc_update_kernel): r_out = r_in - f acc, x_out = x_in + f e (skipped when
+// x_out is null: the caller sums the corrections itself), r_next =
 // s_next r_out, and |r_out|^2.  The stencil of e runs in FP64 with FP64 links.
 template <int P>
 struct DcEpi {
@@ -193,12 +194,14 @@ struct DcEpi {
                 r_out[i] = d;
                 if (r_next) stc(r_next, i, cpx<RN>{(RN)(sn * d.x), (RN)(sn * d.y)});
                 nrm[0] += d.x * d.x + d.y * d.y;
-                const cpx<double> ev = ldr<double>(e, i);
-                const double2 xv = x_in ? x_in[i] : make_double2(0.0, 0.0);
-                x_out[i] = make_double2(xv.x + f * ev.re, xv.y + f * ev.im);
+                if (x_out) {
+                    const cpx<double> ev = ldr<double>(e, i);
+                    const double2 xv = x_in ? x_in[i] : make_double2(0.0, 0.0);
+                    x_out[i] = make_double2(xv.x + f * ev.re, xv.y + f * ev.im);
+                }
             } else {
                 r_out[i] = make_double2(0.0, 0.0);
-                x_out[i] = make_double2(0.0, 0.0);
+                if (x_out) x_out[i] = make_double2(0.0, 0.0);
                 if (r_next) stc(r_next, i, cpx<RN>{0, 0});
             }
         }
@@ -359,7 +362,8 @@ __global__ void __launch_bounds__(E::kThreads) march_kernel(typename E::Args a)
 // One FP64 defect-correction step, fused.  e is the inner solution (stored in
 // precision P, zero on coarse sites) of A e = r_in / f_k:
 //     r_out = r_in - f (D_rr e)        x_out = x_in + f e        (FP64)
-// on the r-sites; coarse sites are written as zero.  x_in == nullptr reads as
+// on the r-sites; coarse sites are written as zero.  x_out == nullptr skips
+// the iterate (the caller keeps the corrections); x_in == nullptr reads as
 // zero.  With r_next set, also r_next = s_next r_out in precision P (the next
 // inner right-hand side), and always the per-workgroup partial sums of
 // |r_out|^2 per RHS.  r_out may alias r_in and x_out may alias x_in (each
@@ -403,16 +407,18 @@ __global__ void __launch_bounds__(256) dc_update_kernel(DcArgs a)
                     r_out[i] = d;
                     if (r_next) stc(r_next, i, cpx<R>{(R)(sn * d.x), (R)(sn * d.y)});
                     nrm += d.x * d.x + d.y * d.y;
-                    const cpx<double> ev = ldr<double>(e, i);
-                    const double2 xv = x_in ? x_in[i] : make_double2(0.0, 0.0);
-                    x_out[i] = make_double2(xv.x + f * ev.re, xv.y + f * ev.im);
+                    if (x_out) {
+                        const cpx<double> ev = ldr<double>(e, i);
+                        const double2 xv = x_in ? x_in[i] : make_double2(0.0, 0.0);
+                        x_out[i] = make_double2(xv.x + f * ev.re, xv.y + f * ev.im);
+                    }
                 }
             } else if (valid) {
 #pragma unroll
                 for (int c = 0; c < 12; ++c) {
                     const size_t i = fidx(s, r, c, a.nrhs);
                     r_out[i] = make_double2(0.0, 0.0);
-                    x_out[i] = make_double2(0.0, 0.0);
+                    if (x_out) x_out[i] = make_double2(0.0, 0.0);
                     if (r_next) stc(r_next, i, cpx<R>{0, 0});
                 }
             }

@@ -147,12 +147,13 @@ __global__ void __launch_bounds__(256) eo_hop_kernel(EoArgs a)
                 }
             }
             R sre = 0, sim = 0, sqq = 0;
+            const bool act = a.active == nullptr || a.active[r] != 0;
             if (valid) {
 #pragma unroll
                 for (int c = 0; c < 12; ++c) {
                     const size_t i = fidx(h, r, c, a.nrhs);
                     cpx<R> o = {0, 0};
-                    if (on) {
+                    if (on && act) {
                         o = {be * acc[c].re, be * acc[c].im};
                         if (in2) {
                             const cpx<R> v = ldr<R>(in2, i);

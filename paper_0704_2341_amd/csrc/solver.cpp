@@ -263,7 +263,7 @@ grg_status tune_dc(grg_schur S, int prec, int nrhs, int reps)
     d.r_in = S->b64;
     d.x_in = nullptr;
     d.r_out = S->t64;
-    d.x_out = S->r64;
+    d.x_out = nullptr;  // as the solver runs it: the iterate is summed at the end
     d.f = S->bn2 + kMaxRhs;
     d.r_next = S->in_q[prec];
     d.s_next = S->bn2 + 3 * kMaxRhs;
@@ -371,11 +371,11 @@ grg_status ensure_inner(grg_schur S, int prec)
 }
 
 // Inner GCR(m) on D_rr in precision prec: solves A x = b, with b already in
-// in_r (it becomes the residual) and x in in_x, until |r|^2 <= thr[k] per RHS
+// in_r (it becomes the residual) and x in xdst, until |r|^2 <= thr[k] per RHS
 // (thr: host copy of the device array thr2) or maxit iterations.
 // Returns the iterations taken in *iters and the last |r|^2 read in rn2_out.
 static grg_status inner_gcr(grg_schur S, int prec, int nrhs, const double *thr, int maxit,
-                            int *iters, double *rn2_out)
+                            int *iters, double *rn2_out, void *xdst)
 {
     grg_lattice L = S->lat;
     hipStream_t st = L->stream;
@@ -387,7 +387,7 @@ static grg_status inner_gcr(grg_schur S, int prec, int nrhs, const double *thr, 
     const int check = std::max(1, S->prm.check_every);
     const DslashTune &tt = S->tune[prec][nrhs];
     const int dgrid = tt.valid ? tt.grid : default_tune(g, prec, nrhs).grid;
-    void *x = S->in_x[prec], *r = S->in_r[prec], *q = S->in_q[prec];
+    void *x = xdst, *r = S->in_r[prec], *q = S->in_q[prec];
     char *Pm = (char *)S->in_P[prec], *Qm = (char *)S->in_Q[prec];
 
     GRG_TRY_HIP(launch_fill_zero(x, vbytes, st));
@@ -490,7 +490,7 @@ static grg_status ensure_eo(grg_schur S, int prec)
 // out = alpha in2 + beta H in on the rest sites of parity po (compact fields)
 static grg_status eo_hop(grg_schur S, int prec, const DslashTune &t, const void *in, const void *in2,
                          void *out, int po, double alpha, double beta, int nrhs, double *partials,
-                         const void *dot_with)
+                         const void *dot_with, const int *active = nullptr)
 {
     grg_lattice L = S->lat;
     EoArgs a;
@@ -512,6 +512,7 @@ static grg_status eo_hop(grg_schur S, int prec, const DslashTune &t, const void 
     a.chunk = t.chunk;
     a.partials = partials;
     a.dot_with = dot_with;
+    a.active = active;
     ProfilePool &P = S->prof;
     const bool ev = P.on && P.used < (int)P.start.size();
     if (ev) GRG_TRY_HIP(hipEventRecord(P.start[P.used], L->stream));
@@ -602,10 +603,11 @@ grg_status tune_eo(grg_schur S, int prec, int nrhs, int reps)
 }
 
 // Minimal residual on the even-odd reduced system.  The inner right-hand
-// side b is in in_r (full layout); the solution is written to in_x (full
-// layout, zero on the coarse sites), as inner_gcr does.
+// side b is in in_r (full layout); the solution is written to xdst (full
+// layout, zero on the coarse sites and for RHS that were already converged),
+// as inner_gcr does.
 static grg_status inner_mr_eo(grg_schur S, int prec, int nrhs, const double *thr, int maxit,
-                              int *iters, double *rn2_out)
+                              int *iters, double *rn2_out, void *xdst)
 {
     grg_lattice L = S->lat;
     hipStream_t st = L->stream;
@@ -631,6 +633,12 @@ static grg_status inner_mr_eo(grg_schur S, int prec, int nrhs, const double *thr
                               S->active, st));
     double h[kMaxRhs];
     GRG_TRY(read_norms(S, nrhs, h));
+    // the RHS that take steps at all (the others keep a zero correction)
+    {
+        int *flags = (int *)(S->h_buf + 8 * kMaxRhs);
+        for (int k = 0; k < nrhs; ++k) flags[k] = h[k] > thr[k] ? 1 : 0;
+        GRG_TRY_HIP(hipMemcpyAsync(S->act0, flags, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
+    }
     auto all_done = [&](const double *n2) {
         for (int k = 0; k < nrhs; ++k) {
             if (!isfinite(n2[k])) return -1;
@@ -657,10 +665,13 @@ static grg_status inner_mr_eo(grg_schur S, int prec, int nrhs, const double *thr
     }
     *iters = it;
     memcpy(rn2_out, h, sizeof(double) * nrhs);
-    // z_Q = (b_Q - H_QP z_P) / d, then both halves into the full layout
-    GRG_TRY(eo_hop(S, prec, t, x, bh[Q], w, Q, 1.0 / d, -1.0 / d, nrhs, nullptr, nullptr));
-    GRG_TRY_HIP(launch_eo_split(prec, g, L->Vhs, nrhs, S->in_x[prec], P == 0 ? x : w,
-                                P == 0 ? w : x, true, st));
+    // z_Q = (b_Q - H_QP z_P) / d (zero for RHS that took no step: their
+    // x_P is zero and the correction must be too), then both halves into
+    // the full layout
+    GRG_TRY(eo_hop(S, prec, t, x, bh[Q], w, Q, 1.0 / d, -1.0 / d, nrhs, nullptr, nullptr,
+                   S->act0));
+    GRG_TRY_HIP(launch_eo_split(prec, g, L->Vhs, nrhs, xdst, P == 0 ? x : w, P == 0 ? w : x,
+                                true, st));
     if (done < 0) {
         set_error("non-finite residual in the inner solve");
         return GRG_ENONFINITE;
@@ -682,22 +693,42 @@ static grg_status convert_rhs(grg_schur S, int prec, const BlasShape &sh, const 
     return GRG_OK;
 }
 
-// b64 (internal FP64, zero on coarse sites) -> x64 = D_rr^{-1} b64.
+// A slot of the correction pool (inner precision, full layout, max_rhs).
+static grg_status pool_slot(grg_schur S, int prec, int k, void **out)
+{
+    auto &pool = S->epool[prec];
+    while ((int)pool.size() <= k) {
+        void *b = nullptr;
+        const size_t bytes = spinor_elems(S->lat->g, S->prm.max_rhs) * prec_bytes(prec);
+        if (hipMalloc(&b, bytes) != hipSuccess) {
+            set_error("correction pool: hipMalloc of %zu bytes failed", bytes);
+            return GRG_ENOMEM;
+        }
+        pool.push_back(b);
+    }
+    *out = pool[k];
+    return GRG_OK;
+}
+
+// b64 (internal FP64, zero on coarse sites) -> x64 = D_rr^{-1} b64, or with
+// u_minus set, x64 = u_minus - D_rr^{-1} b64 (what S_bb needs next).
 //
 // Outer loop, FP64 (r_0 = b, x_0 = 0), with a per-RHS scale s_k:
-//     e   ~= A^{-1} (s r)                          inner GCR, inner precision
-//     r   <- r - A e / s,   x <- x + e / s         one fused FP64 kernel, which
+//     e_k ~= A^{-1} (s r)                          inner solve, inner precision
+//     r   <- r - A e_k / s                         one fused FP64 kernel, which
 //                                                  also writes s' r for the next
 //                                                  inner solve
-// until |r| <= tol |b|.  s_0 = 1 / |b|; s' = 1 / (the new |r| the inner
-// solve predicts), so the inner fields stay of order one (a scale off by a
-// few orders of magnitude is harmless: BF16 and FP32 share an exponent range
-// far wider than that); the inner thresholds are taken relative to the
-// actual |s r|.  The FP64 residual r is updated with the exact FP64 operator
-// at every step, so it is the residual of x up to FP64 rounding; with
-// params.verify it is also recomputed from x as b - A x at the end, and the
-// loop resumes from that residual if it is above tol.
-grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
+// until |r| <= tol |b|; the iterate x = sum_k e_k / s_k is formed once at the
+// end from the kept corrections (in FP64, the same sum the steps would have
+// accumulated), so the steps do not stream x.  s_0 = 1 / |b|; s' = 1 / (the
+// new |r| the inner solve predicts), so the inner fields stay of order one (a
+// scale off by a few orders of magnitude is harmless: BF16 and FP32 share an
+// exponent range far wider than that); the inner thresholds are taken
+// relative to the actual |s r|.  The FP64 residual r is updated with the
+// exact FP64 operator at every step, so it is the residual of x up to FP64
+// rounding; with params.verify it is also recomputed from x as b - A x at the
+// end, and the loop resumes from that residual if it is above tol.
+grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, const void *u_minus)
 {
     grg_lattice L = S->lat;
     hipStream_t st = L->stream;
@@ -705,7 +736,6 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
     const grg_solver_params &p = S->prm;
     const int prec = p.inner;
     const BlasShape sh = blas_shape(g, nrhs);
-    const size_t vb64 = spinor_elems(g, nrhs) * 16;
     GRG_TRY(ensure_inner(S, prec));
     // device per-RHS scalars: |b|^2, then f = 1/s, s, and the next s
     double *d_f = S->bn2 + kMaxRhs, *d_s = S->bn2 + 2 * kMaxRhs, *d_sn = S->bn2 + 3 * kMaxRhs;
@@ -726,9 +756,29 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
                                    hipMemcpyHostToDevice, st));
         return GRG_OK;
     };
+    // the kept corrections and the part of x already summed into x64
+    int npool = 0;
+    bool have_x = false;
+    auto combine = [&](const void *u, double sigma) -> grg_status {
+        CombineArgs c;
+        for (int j = 0; j < kCorrPool; ++j) c.e[j] = j < npool ? S->epool[prec][j] : nullptr;
+        c.f = S->d_fk;
+        c.n = npool;
+        c.u = u;
+        c.x = have_x ? S->x64 : nullptr;
+        c.out = S->x64;
+        c.sigma = sigma;
+        if (npool > 0)
+            GRG_TRY_HIP(hipMemcpyAsync(S->d_fk, S->h_fk, sizeof(double) * kCorrPool * kMaxRhs,
+                                       hipMemcpyHostToDevice, st));
+        GRG_TRY_HIP(launch_combine(prec, sh, c, st));
+        if (npool > 0) GRG_TRY_HIP(hipStreamSynchronize(st));  // h_fk is reused next
+        npool = 0;
+        have_x = true;
+        return GRG_OK;
+    };
 
     const void *r_src = S->b64;  // the residual of the current iterate
-    const void *x_src = nullptr; // the iterate (nullptr: zero)
     bool rhs_ready = false;      // in_r holds s r_src in the inner precision
     int total = 0, outer = 0;
     bool verified = false;
@@ -747,9 +797,10 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
             worst = std::max(worst, rel);
             if (rel > p.tol) conv = false;
         }
-        if (conv && (verified || x_src == nullptr || !p.verify)) break;
+        if (conv && (verified || outer == 0 || !p.verify)) break;
         if (conv) {
             // confirm with the residual recomputed from the iterate
+            GRG_TRY(combine(nullptr, 1.0));
             GRG_TRY(run_dslash(S, GRG_FP64, S->x64, S->t64, 0, nrhs, nullptr));
             GRG_TRY_HIP(launch_sub_norm(sh, S->b64, S->t64, S->r64, S->partials, st));
             GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, nullptr,
@@ -767,6 +818,9 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
                       "(residual %.3e > %.3e)", outer, total, worst, p.tol);
             break;
         }
+        if (npool == kCorrPool) GRG_TRY(combine(nullptr, 1.0));  // pool full: sum it into x64
+        void *e = nullptr;
+        GRG_TRY(pool_slot(S, prec, npool, &e));
         // inner thresholds on the scaled residual s r, |s r|^2 = s^2 |r|^2
         double thr[kMaxRhs], f[kMaxRhs];
         for (int k = 0; k < nrhs; ++k) {
@@ -788,7 +842,7 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
         double h[kMaxRhs];
         if (S->precond) {
             // preconditioned inner solve, with plain GCR as the fallback
-            is = inner_gcr(S, prec, nrhs, thr, std::min(p.max_iter - total, kPrecondInnerCap), &it, h);
+            is = inner_gcr(S, prec, nrhs, thr, std::min(p.max_iter - total, kPrecondInnerCap), &it, h, e);
             total += it;
             if (is != GRG_OK) {
                 grg_precond keep = S->precond;
@@ -796,15 +850,15 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
                 ++S->fallbacks;
                 GRG_TRY(upload(d_s, sc, 2));
                 GRG_TRY(convert_rhs(S, prec, sh, r_src, d_s));
-                is = inner_gcr(S, prec, nrhs, thr, p.max_iter - total, &it, h);
+                is = inner_gcr(S, prec, nrhs, thr, p.max_iter - total, &it, h, e);
                 S->precond = keep;
                 total += it;
             }
         } else if (p.eo && L->eo_ok && std::max(1, p.restart) == 1) {
-            is = inner_mr_eo(S, prec, nrhs, thr, p.max_iter - total, &it, h);
+            is = inner_mr_eo(S, prec, nrhs, thr, p.max_iter - total, &it, h, e);
             total += it;
         } else {
-            is = inner_gcr(S, prec, nrhs, thr, p.max_iter - total, &it, h);
+            is = inner_gcr(S, prec, nrhs, thr, p.max_iter - total, &it, h, e);
             total += it;
         }
         if (is != GRG_OK && is != GRG_ENOCONV) return is;
@@ -816,14 +870,14 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
             scn[k] = est > 0 && isfinite(est) && isfinite(1.0 / est) ? 1.0 / est : sc[k];
         }
         GRG_TRY(upload(d_sn, scn, 3));
-        // r -= A e / s ; x += e / s ; next inner rhs s' r   (FP64, fused)
+        // r -= A e / s ; next inner rhs s' r   (FP64, fused; x is summed at the end)
         DcArgs d;
-        d.e = S->in_x[prec];
+        d.e = e;
         d.U = L->U[GRG_FP64];
         d.r_in = r_src;
-        d.x_in = x_src;
+        d.x_in = nullptr;
         d.r_out = S->r64;
-        d.x_out = S->x64;
+        d.x_out = nullptr;
         d.f = d_f;
         d.r_next = S->in_r[prec];
         d.s_next = d_sn;
@@ -836,13 +890,15 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats)
         GRG_TRY_HIP(launch_dc_update(prec, d, dct.grid, dct.SB, st));
         GRG_TRY_HIP(launch_reduce(kNorm, S->partials, dct.grid, nrhs, nullptr, S->rn2, nullptr,
                                   nullptr, st));
+        for (int k = 0; k < kMaxRhs; ++k) S->h_fk[npool * kMaxRhs + k] = k < nrhs ? f[k] : 0.0;
+        ++npool;
         GRG_TRY(read_norms(S, nrhs, rn2));
         memcpy(sc, scn, sizeof(double) * nrhs);
         r_src = S->r64;
-        x_src = S->x64;
         rhs_ready = true;
     }
-    if (x_src == nullptr) GRG_TRY_HIP(launch_fill_zero(S->x64, vb64, st));
+    // x64 = sum of the corrections, or u_minus minus it
+    GRG_TRY(combine(u_minus, u_minus ? -1.0 : 1.0));
     if (stats) {
         stats->fallbacks = S->fallbacks;
         stats->iters = total;
@@ -881,11 +937,10 @@ grg_status schur_apply_internal(grg_schur S, const double *xb, double *yb, int n
     GRG_TRY_HIP(launch_scatter_coarse(xb, S->u64, S->d_bidx, S->nb, g, nrhs, st));
     // b = (D u)_r
     GRG_TRY(run_dslash(S, GRG_FP64, S->u64, S->b64, 0, nrhs, nullptr));
-    // z = D_rr^{-1} b   (into x64)
-    grg_status s = drr_solve_internal(S, nrhs, stats);
+    // x64 = u - z,  z = D_rr^{-1} b
+    grg_status s = drr_solve_internal(S, nrhs, stats, S->u64);
     if (s != GRG_OK && s != GRG_ENOCONV) return s;
-    // x64 = u - z ; y_b = [D (u - z)]_b
-    GRG_TRY_HIP(launch_xmy(sh, S->u64, S->x64, st));
+    // y_b = [D (u - z)]_b
     CoarseArgs c;
     c.in = S->x64;
     c.out = yb;
