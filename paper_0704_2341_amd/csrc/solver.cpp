@@ -202,8 +202,16 @@ grg_status tune_dslash(grg_schur S, int prec, int nrhs, int reps)
             cands[i].march > 0
                 ? (long)((g.L[0] * g.L[1] * g.L[2] + 63) / 64) * ((g.L[3] + cands[i].march - 1) / cands[i].march)
                 : (long)((g.V + cands[i].SB - 1) / cands[i].SB) * ((nrhs + cands[i].RG - 1) / cands[i].RG);
-        const int caps[3] = {1024, 2048, kMaxGrid};
-        const int chunks[4] = {0, 1, 8, 64};
+        const int caps[4] = {512, 1024, 2048, kMaxGrid};
+        std::vector<int> chunks = {0, 1, 8, 64};
+        if (cands[i].march == 0) {
+            // one XCD per z-slab of a time slice, and multiples
+            const long slab = (long)(g.L[0] * g.L[1] * g.L[2] / 8 / cands[i].SB) *
+                              ((nrhs + cands[i].RG - 1) / cands[i].RG);
+            for (long c : {slab, 2 * slab, 4 * slab})
+                if (c >= 1 && std::find(chunks.begin(), chunks.end(), (int)c) == chunks.end())
+                    chunks.push_back((int)c);
+        }
         for (int cap : caps) {
             for (int ch : chunks) {
                 DslashTune t = cands[i];
@@ -308,7 +316,7 @@ grg_status tune_dc(grg_schur S, int prec, int nrhs, int reps)
     for (int rg = std::min(nrhs, 8); rg >= 1; --rg) {
         if (nrhs % rg) continue;
         for (int T = 2; T <= g.L[3]; T *= 2) {
-            for (int ch : {0, 8}) {
+            for (int ch : {0, 8, nb3 / 8, nb3 / 4, nb3 / 2}) {
                 DslashTune t;
                 t.march = T;
                 t.SB = 64;
@@ -583,8 +591,16 @@ grg_status tune_eo(grg_schur S, int prec, int nrhs, int reps)
     for (size_t i = 0; i < std::min<size_t>(2, cands.size()); ++i) {
         const long items = (long)((gh.V + cands[i].SB - 1) / cands[i].SB) *
                            ((nrhs + cands[i].RG - 1) / cands[i].RG);
-        for (int cap : {1024, 2048, kMaxGridValue}) {
-            for (int ch : {0, 8, 64}) {
+        // chunks: one XCD per z-slab of a time slice (an eighth of its
+        // half-sites) and multiples, besides the fixed sizes
+        const long slab = (long)(gh.L[0] * gh.L[1] * gh.L[2] / 16 / cands[i].SB) *
+                          ((nrhs + cands[i].RG - 1) / cands[i].RG);
+        std::vector<int> chunks = {0, 8, 64};
+        for (long c : {slab / 2, slab, 2 * slab, 4 * slab})
+            if (c >= 1 && std::find(chunks.begin(), chunks.end(), (int)c) == chunks.end())
+                chunks.push_back((int)c);
+        for (int cap : {512, 1024, 2048, kMaxGridValue}) {
+            for (int ch : chunks) {
                 DslashTune t = cands[i];
                 t.grid = round8(std::min<long>(items, cap));
                 t.chunk = ch;
