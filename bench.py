@@ -200,6 +200,7 @@ def main():
     ap.add_argument("--inner", default="bf16", choices=["bf16", "fp32", "fp64"])
     ap.add_argument("--inner-tol", type=float, default=None)
     ap.add_argument("--restart", type=int, default=1)
+    ap.add_argument("--check-every", type=int, default=2, help="inner iterations between norm reads")
     ap.add_argument("--fp64-restart", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--dims", default="32,32,32,32")
@@ -244,6 +245,7 @@ def main():
     yb = torch.empty_like(xb)
 
     prm = grg.grg_solver_params_default(tol=tol, inner=args.inner, inner_tol=inner_tol,
+                                        check_every=args.check_every,
                                         restart=args.restart, max_rhs=nrhs, max_iter=4000)
     s = grg.grg_schur_create(lat, m0, q, nb, prm)
     if not args.no_tune:
