@@ -70,8 +70,9 @@ def launch_descriptor(info: dict, prec: str, launches: int, eo: bool = False) ->
     work-items per dispatch."""
     p = PREC_ID[prec]
     if eo:
-        sym, gs = f"eo_hop_kernel<{p}, {2 if info['split'] == 2 and prec == 'bf16' else 1}>", \
-            info["grid"] * info["SB"]
+        # every instance of the half-lattice stencil (reduced operator, and the
+        # right-hand side / reconstruction steps) in this precision
+        sym, gs = f"eo_hop_kernel<{p}, ", info["grid"] * info["SB"]
     elif info["march"] > 0:
         sym, gs = f"dslash_march_kernel<{p}>", info["grid"] * 64 * info["RG"]
     else:

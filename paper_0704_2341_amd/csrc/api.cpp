@@ -339,7 +339,7 @@ static void schur_free(grg_schur S)
     if (S->h_fk) hipHostFree(S->h_fk);
     S->h_fk = nullptr;
     for (int p = 0; p < 3; ++p)
-        for (int k = 0; k < 6; ++k) dfree(S->eo_f[p][k]);
+        for (int k = 0; k < 4; ++k) dfree(S->eo_f[p][k]);
     dfree((void *&)S->partials);
     dfree((void *&)S->alpha);
     dfree((void *&)S->beta);

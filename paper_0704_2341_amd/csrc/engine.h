@@ -69,6 +69,12 @@ struct EoArgs {
     double *partials;     // [grid][nrhs][3] or nullptr
     const void *dot_with; // parity po
     const int *active;    // per RHS: 0 writes zero for that RHS (nullptr: all active)
+    // full-layout variants (the first and last steps of a reduced solve read
+    // and write the unreduced fields directly): in / in2 indexed by the full
+    // site; out written to the full field, together with the same-index site
+    // of the other parity, copied from `partner` (compact, parity 1 - po)
+    int in_full, in2_full, out_full;
+    const void *partner;
 };
 
 // out = u + sigma (x + sum_j f[j][rhs] e_j) in FP64 (u, x nullable): the
@@ -125,9 +131,6 @@ hipError_t launch_dslash(int prec, const DslashArgs &a, int grid, hipStream_t st
 hipError_t launch_dc_update(int prec, const DcArgs &a, int grid, int SB, hipStream_t st);
 hipError_t launch_dslash_coarse(const CoarseArgs &a, hipStream_t st);
 hipError_t launch_eo_hop(int prec, const EoArgs &a, int grid, hipStream_t st);
-// merge = false: full -> (even, odd) compact halves; true: the reverse
-hipError_t launch_eo_split(int prec, const Geom &g, int Vhs, int nrhs, const void *full, void *even,
-                           void *odd, bool merge, hipStream_t st);
 hipError_t launch_eo_pack_links(int prec, const Geom &g, int Vhs, const void *U, void *Ueo, hipStream_t st);
 hipError_t launch_eo_pack_mask(const Geom &g, int Vhs, const uint8_t *mask, uint8_t *meo, hipStream_t st);
 hipError_t launch_pack_gauge(const double *src, const Geom &g, const int bc[4], void *u64,

@@ -82,15 +82,15 @@ struct grg_schur_s {
     // row sums of D_rr (one FP64 field) for the section 3 approximation
     void *dt64 = nullptr;
     // even-odd reduced inner solve: mask per parity ([2][Vhs]), the parity of
-    // the reduced system, and compact fields per inner precision:
-    // b_even, b_odd, r, x, q (reduced parity) and t (other parity)
+    // the reduced system, and compact fields per inner precision: r, x, q
+    // (reduced parity) and w (other parity)
     uint8_t *d_mask_eo = nullptr;
     // the defect correction's corrections e_k (inner precision, full layout)
     // and their factors: the iterate is summed from them at the end
     std::vector<void *> epool[3];
     double *d_fk = nullptr, *h_fk = nullptr;  // [kCorrPool][kMaxRhs]
     int eo_par = 1;
-    void *eo_f[3][6] = {};
+    void *eo_f[3][4] = {};
     grg::DslashTune eotune[3][grg::kMaxRhs + 1];
     // reduction scratch
     double *partials = nullptr;

@@ -49,14 +49,17 @@ template <class OP, class S>
 __device__ __forceinline__ void eo_load_hop(int k, typename OP::T (&p)[12], typename OP::T (&u)[9],
                                             const S *__restrict__ in, const S *__restrict__ Uo,
                                             const S *__restrict__ Ui, int s, int h,
-                                            const SiteGeo &q, const Geom &g, int r, int nrhs)
+                                            const SiteGeo &q, const Geom &g, int r, int nrhs,
+                                            bool in_full)
 {
     const int mu = k >> 1;
     int sp, sm;
     nbr(s, mu, q, g, sp, sm);
-    const int hn = ((k & 1) ? sm : sp) >> 1;
+    const int n = (k & 1) ? sm : sp;
+    const int hn = n >> 1;
+    const int ni = in_full ? n : hn;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) p[c] = OP::load(in, fidx(hn, r, c, nrhs));
+    for (int c = 0; c < 12; ++c) p[c] = OP::load(in, fidx(ni, r, c, nrhs));
     if (k & 1) {
 #pragma unroll
         for (int e = 0; e < 9; ++e) u[e] = OP::load(Ui, lidx(hn, mu, e));
@@ -86,9 +89,14 @@ __device__ __forceinline__ void eo_hop_k(int k, cpx<R> (&acc)[12], const PT (&p)
 // also the per-workgroup sums conj(out).w (re, im) and |out|^2 per RHS,
 // w = dot_with (parity po).  HOPS = 2 double-buffers the hop operands (packed
 // BF16), otherwise one hop per loop iteration.
-template <int P, int HOPS>
+template <int P, int HOPS, int IO>
 __global__ void __launch_bounds__(256) eo_hop_kernel(EoArgs a)
 {
+    // IO = 0: compact fields; 1: in and in2 in the full layout; 2: in2 and
+    // out in the full layout (the full-layout modes run once per reduced
+    // solve, the compact one every iteration: separate instances keep the
+    // latter free of their indexing)
+    constexpr bool in_full = IO == 1, in2_full = IO >= 1, out_full = IO == 2;
     typedef typename Store<P>::S S;
     typedef typename Store<P>::R R;
     typedef Operand<S, R> OP;
@@ -107,6 +115,7 @@ __global__ void __launch_bounds__(256) eo_hop_kernel(EoArgs a)
         __syncthreads();
     }
     const R al = (R)a.alpha, be = (R)a.beta;
+    const bool inf = in_full;
     const int ngroups = (a.nrhs + a.RG - 1) / a.RG;
     const int nsb = (a.Vh + a.SB - 1) / a.SB;
     const int nitems = nsb * ngroups;
@@ -120,7 +129,7 @@ __global__ void __launch_bounds__(256) eo_hop_kernel(EoArgs a)
         const bool on = valid && mk[h] == 0;
         SiteGeo q;
         int s = 0;
-        if (on) s = eo_site(h, a.po, a.g, q);
+        if (on || (valid && out_full)) s = eo_site(h, a.po, a.g, q);
         const int r0 = grp * a.RG, r1 = min(r0 + a.RG, a.nrhs);
         for (int r = r0; r < r1; ++r) {
             cpx<R> acc[12];
@@ -129,19 +138,19 @@ __global__ void __launch_bounds__(256) eo_hop_kernel(EoArgs a)
             if (on) {
                 if constexpr (HOPS == 2 && OP::kPacked) {
                     PT pa[12], pb[12], ua[9], ub[9];
-                    eo_load_hop<OP>(0, pa, ua, in, Uo, Ui, s, h, q, a.g, r, a.nrhs);
+                    eo_load_hop<OP>(0, pa, ua, in, Uo, Ui, s, h, q, a.g, r, a.nrhs, inf);
 #pragma unroll 1
                     for (int mu = 0; mu < 4; ++mu) {
-                        eo_load_hop<OP>(2 * mu + 1, pb, ub, in, Uo, Ui, s, h, q, a.g, r, a.nrhs);
+                        eo_load_hop<OP>(2 * mu + 1, pb, ub, in, Uo, Ui, s, h, q, a.g, r, a.nrhs, inf);
                         eo_hop_k(2 * mu, acc, pa, ua);
-                        if (mu < 3) eo_load_hop<OP>(2 * mu + 2, pa, ua, in, Uo, Ui, s, h, q, a.g, r, a.nrhs);
+                        if (mu < 3) eo_load_hop<OP>(2 * mu + 2, pa, ua, in, Uo, Ui, s, h, q, a.g, r, a.nrhs, inf);
                         eo_hop_k(2 * mu + 1, acc, pb, ub);
                     }
                 } else {
 #pragma unroll 1
                     for (int k = 0; k < 8; ++k) {
                         PT p[12], u[9];
-                        eo_load_hop<OP>(k, p, u, in, Uo, Ui, s, h, q, a.g, r, a.nrhs);
+                        eo_load_hop<OP>(k, p, u, in, Uo, Ui, s, h, q, a.g, r, a.nrhs, inf);
                         eo_hop_k(k, acc, p, u);
                     }
                 }
@@ -156,12 +165,18 @@ __global__ void __launch_bounds__(256) eo_hop_kernel(EoArgs a)
                     if (on && act) {
                         o = {be * acc[c].re, be * acc[c].im};
                         if (in2) {
-                            const cpx<R> v = ldr<R>(in2, i);
+                            const cpx<R> v = ldr<R>(in2, in2_full ? fidx(s, r, c, a.nrhs) : i);
                             o.re = fma(al, v.re, o.re);
                             o.im = fma(al, v.im, o.im);
                         }
                     }
-                    stc(out, i, o);
+                    if (out_full) {
+                        // this site, and the other parity's site of the same index
+                        stc(out, fidx(s, r, c, a.nrhs), o);
+                        out[fidx(s ^ 1, r, c, a.nrhs)] = ((const S *)a.partner)[i];
+                    } else {
+                        stc(out, i, o);
+                    }
                     if (dots && on) {
                         const cpx<R> v = ldr<R>((const S *)a.dot_with, i);
                         sre = fma(o.re, v.re, fma(o.im, v.im, sre));
@@ -189,26 +204,6 @@ __global__ void __launch_bounds__(256) eo_hop_kernel(EoArgs a)
             double t = 0;
             for (int k = 0; k < nw; ++k) t += red[k][i / 3][i % 3];
             a.partials[(size_t)blockIdx.x * a.nrhs * 3 + i] = t;
-        }
-    }
-}
-
-// full field <-> its two compact parity halves (every RHS)
-template <int P>
-__global__ void __launch_bounds__(256) eo_split_kernel(Geom g, int Vhs, int nrhs, const void *full_,
-                                                       void *even_, void *odd_, int merge)
-{
-    typedef typename Store<P>::S S;
-    S *full = (S *)full_, *half[2] = {(S *)even_, (S *)odd_};
-    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < g.V; s += gridDim.x * blockDim.x) {
-        S *hf = half[site_parity(s, g)];
-        const int h = s >> 1;
-        for (int r = 0; r < nrhs; ++r) {
-#pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                if (merge) full[fidx(s, r, c, nrhs)] = hf[fidx(h, r, c, nrhs)];
-                else hf[fidx(h, r, c, nrhs)] = full[fidx(s, r, c, nrhs)];
-            }
         }
     }
 }
@@ -247,30 +242,30 @@ hipError_t launch_eo_hop(int prec, const EoArgs &a, int grid, hipStream_t st)
 {
     if (a.nrhs < 1 || a.nrhs > kMaxRhs || a.RG < 1 || grid < 8 || grid % 8) return hipErrorInvalidValue;
     if (a.SB != 64 && a.SB != 128 && a.SB != 256) return hipErrorInvalidValue;
+    int io = 0;
+    if (a.in_full && a.in2_full && !a.out_full) io = 1;
+    else if (!a.in_full && a.in2_full && a.out_full) io = 2;
+    else if (a.in_full || a.in2_full || a.out_full) return hipErrorInvalidValue;
     dim3 blk(a.SB), grd(grid);
-    const bool pipe = a.hops == 2 && prec == GRG_BF16;
+    const bool pipe = a.hops == 2 && prec == GRG_BF16 && io == 0;
+#define EOH(PP, H, IO) hipLaunchKernelGGL((eo_hop_kernel<PP, H, IO>), grd, blk, 0, st, a)
+#define EOIO(PP)                   \
+    if (io == 1) EOH(PP, 1, 1);    \
+    else if (io == 2) EOH(PP, 1, 2); \
+    else EOH(PP, 1, 0);
     switch (prec) {
-    case GRG_FP64: hipLaunchKernelGGL((eo_hop_kernel<GRG_FP64, 1>), grd, blk, 0, st, a); break;
-    case GRG_FP32: hipLaunchKernelGGL((eo_hop_kernel<GRG_FP32, 1>), grd, blk, 0, st, a); break;
+    case GRG_FP64: EOIO(GRG_FP64) break;
+    case GRG_FP32: EOIO(GRG_FP32) break;
     case GRG_BF16:
-        if (pipe) hipLaunchKernelGGL((eo_hop_kernel<GRG_BF16, 2>), grd, blk, 0, st, a);
-        else hipLaunchKernelGGL((eo_hop_kernel<GRG_BF16, 1>), grd, blk, 0, st, a);
+        if (pipe) EOH(GRG_BF16, 2, 0);
+        else {
+            EOIO(GRG_BF16)
+        }
         break;
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_eo_split(int prec, const Geom &g, int Vhs, int nrhs, const void *full, void *even,
-                           void *odd, bool merge, hipStream_t st)
-{
-    const int grid = std::min(cdiv(g.V, 256), 8192);
-    switch (prec) {
-    case GRG_FP64: hipLaunchKernelGGL(eo_split_kernel<GRG_FP64>, dim3(grid), dim3(256), 0, st, g, Vhs, nrhs, full, even, odd, (int)merge); break;
-    case GRG_FP32: hipLaunchKernelGGL(eo_split_kernel<GRG_FP32>, dim3(grid), dim3(256), 0, st, g, Vhs, nrhs, full, even, odd, (int)merge); break;
-    case GRG_BF16: hipLaunchKernelGGL(eo_split_kernel<GRG_BF16>, dim3(grid), dim3(256), 0, st, g, Vhs, nrhs, full, even, odd, (int)merge); break;
-    default: return hipErrorInvalidValue;
-    }
+#undef EOIO
+#undef EOH
     return hipGetLastError();
 }
 

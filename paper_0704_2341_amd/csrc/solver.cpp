@@ -482,7 +482,7 @@ static grg_status ensure_eo(grg_schur S, int prec)
 {
     grg_lattice L = S->lat;
     const size_t bytes = spinor_elems(half_geom(L), S->prm.max_rhs) * prec_bytes(prec);
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < 4; ++k) {  // r, x, q and the other parity's w
         void *&b = S->eo_f[prec][k];
         if (b) continue;
         if (hipMalloc(&b, bytes) != hipSuccess) {
@@ -498,7 +498,8 @@ static grg_status ensure_eo(grg_schur S, int prec)
 // out = alpha in2 + beta H in on the rest sites of parity po (compact fields)
 static grg_status eo_hop(grg_schur S, int prec, const DslashTune &t, const void *in, const void *in2,
                          void *out, int po, double alpha, double beta, int nrhs, double *partials,
-                         const void *dot_with, const int *active = nullptr)
+                         const void *dot_with, const int *active = nullptr, int in_full = 0,
+                         int in2_full = 0, const void *partner = nullptr)
 {
     grg_lattice L = S->lat;
     EoArgs a;
@@ -521,6 +522,10 @@ static grg_status eo_hop(grg_schur S, int prec, const DslashTune &t, const void 
     a.partials = partials;
     a.dot_with = dot_with;
     a.active = active;
+    a.in_full = in_full;
+    a.in2_full = in2_full;
+    a.out_full = partner != nullptr;
+    a.partner = partner;
     ProfilePool &P = S->prof;
     const bool ev = P.on && P.used < (int)P.start.size();
     if (ev) GRG_TRY_HIP(hipEventRecord(P.start[P.used], L->stream));
@@ -559,10 +564,10 @@ grg_status tune_eo(grg_schur S, int prec, int nrhs, int reps)
         if (status != GRG_OK) return;
         t.ms = 1e30f;
         if (!eo_launch_ok(gh, prec, nrhs, t)) return;
-        status = eo_hop(S, prec, t, f[5], f[2], f[4], S->eo_par, 4.0, -0.25, nrhs, S->partials, f[2]);
+        status = eo_hop(S, prec, t, f[3], f[0], f[2], S->eo_par, 4.0, -0.25, nrhs, S->partials, f[0]);
         if (status == GRG_OK && hipEventRecord(e0, st) != hipSuccess) status = GRG_EHIP;
         for (int k = 0; k < reps && status == GRG_OK; ++k)
-            status = eo_hop(S, prec, t, f[5], f[2], f[4], S->eo_par, 4.0, -0.25, nrhs, S->partials, f[2]);
+            status = eo_hop(S, prec, t, f[3], f[0], f[2], S->eo_par, 4.0, -0.25, nrhs, S->partials, f[0]);
         if (status == GRG_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
             status = GRG_EHIP;
         if (status != GRG_OK) return;
@@ -636,13 +641,12 @@ static grg_status inner_mr_eo(grg_schur S, int prec, int nrhs, const double *thr
                                                      : default_eo_tune(gh, prec, nrhs);
     const int P = S->eo_par, Q = 1 - P;
     void **f = S->eo_f[prec];
-    void *bh[2] = {f[0], f[1]};
-    void *r = f[2], *x = f[3], *q = f[4], *w = f[5];
+    void *r = f[0], *x = f[1], *q = f[2], *w = f[3];
+    const void *b = S->in_r[prec];  // the unreduced right-hand side (full layout)
     const double d = 4.0 + S->m0;
     const int check = std::max(1, S->prm.check_every);
-    // the reduced right-hand side b_P - H_PQ b_Q / d
-    GRG_TRY_HIP(launch_eo_split(prec, g, L->Vhs, nrhs, S->in_r[prec], bh[0], bh[1], false, st));
-    GRG_TRY(eo_hop(S, prec, t, bh[Q], bh[P], r, P, 1.0, -1.0 / d, nrhs, nullptr, nullptr));
+    // the reduced right-hand side b_P - H_PQ b_Q / d, read from the full field
+    GRG_TRY(eo_hop(S, prec, t, b, b, r, P, 1.0, -1.0 / d, nrhs, nullptr, nullptr, nullptr, 1, 1));
     GRG_TRY_HIP(launch_fill_zero(x, vbytes, st));
     GRG_TRY_HIP(launch_norm2(prec, sh, r, S->partials, st));
     GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, S->thr2,
@@ -682,12 +686,10 @@ static grg_status inner_mr_eo(grg_schur S, int prec, int nrhs, const double *thr
     *iters = it;
     memcpy(rn2_out, h, sizeof(double) * nrhs);
     // z_Q = (b_Q - H_QP z_P) / d (zero for RHS that took no step: their
-    // x_P is zero and the correction must be too), then both halves into
+    // x_P is zero and the correction must be too), written with z_P into
     // the full layout
-    GRG_TRY(eo_hop(S, prec, t, x, bh[Q], w, Q, 1.0 / d, -1.0 / d, nrhs, nullptr, nullptr,
-                   S->act0));
-    GRG_TRY_HIP(launch_eo_split(prec, g, L->Vhs, nrhs, xdst, P == 0 ? x : w, P == 0 ? w : x,
-                                true, st));
+    GRG_TRY(eo_hop(S, prec, t, x, b, xdst, Q, 1.0 / d, -1.0 / d, nrhs, nullptr, nullptr, S->act0,
+                   0, 1, x));
     if (done < 0) {
         set_error("non-finite residual in the inner solve");
         return GRG_ENONFINITE;
