@@ -114,8 +114,9 @@ def time_applies(grg, s, xb, yb, nrhs, steps, warmup, profile):
 
 
 def learned_leg(grg, torch, args, lat, s, xb, yb, y_plain, nrhs, plain_value, plain_stats):
-    """Train the network on a 16^4 field (m0 -0.3, seed 5) from solver pairs,
-    then use it as the right preconditioner of the same 32^4 solve."""
+    """Train the network on a 16^4 field (m0 -0.3, seed 5) from pairs of the
+    even-odd reduced inner solve, then use it as the right preconditioner of
+    that reduced solve inside the same 32^4 S_bb apply."""
     from grg_inputs import su3_links
 
     dims16 = (16, 16, 16, 16)
@@ -127,7 +128,7 @@ def learned_leg(grg, torch, args, lat, s, xb, yb, y_plain, nrhs, plain_value, pl
     p16 = grg.grg_precond_create(s16)
     log(f"training the preconditioner: {args.train_steps} steps x 12 pairs on 16^4")
     tr = grg.grg_precond_train(p16, steps=args.train_steps, batch=12, max_mr_steps=30, lr=2e-3, seed=5,
-                               log_every=50)
+                               log_every=50, reduced=True)
     w = grg.grg_precond_get_weights(p16)
     grg.grg_precond_destroy(p16)
     grg.grg_schur_destroy(s16)

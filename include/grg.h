@@ -113,6 +113,13 @@ typedef struct {
     double lr;          /* Adam learning rate (beta1 0.9, beta2 0.999, eps 1e-8) */
     uint64_t seed;      /* seeds the random errors and the step counts */
     int log_every;      /* loss read back every log_every steps (0: first/last only) */
+    int reduced;        /* 1: after a first quarter of the steps on pairs of D_rr itself, pairs
+                           of the even-odd reduced D_rr system (inputs, errors and the loss
+                           on the reduced parity's rest sites), for the reduced inner solve
+                           that uses the network restricted to that parity; needs even
+                           extents.  (On pairs of one parity alone the hop weights get no
+                           gradient while they are zero, as at the identity start.)
+                           0: pairs of D_rr itself */
 } grg_train_params;
 
 typedef struct {

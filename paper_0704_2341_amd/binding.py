@@ -77,7 +77,7 @@ class grg_solver_stats(C.Structure):
 
 class grg_train_params(C.Structure):
     _fields_ = [("steps", C.c_int), ("batch", C.c_int), ("max_mr_steps", C.c_int),
-                ("lr", C.c_double), ("seed", C.c_uint64), ("log_every", C.c_int)]
+                ("lr", C.c_double), ("seed", C.c_uint64), ("log_every", C.c_int), ("reduced", C.c_int)]
 
 
 class grg_train_stats(C.Structure):
@@ -393,9 +393,10 @@ def grg_precond_loss_grad(p, r, e, nrhs):
     return loss.value, g
 
 
-def grg_precond_train(p, steps, batch, max_mr_steps=20, lr=1e-3, seed=5, log_every=20):
+def grg_precond_train(p, steps, batch, max_mr_steps=20, lr=1e-3, seed=5, log_every=20,
+                      reduced=False):
     tp = grg_train_params(int(steps), int(batch), int(max_mr_steps), float(lr), int(seed),
-                          int(log_every))
+                          int(log_every), int(bool(reduced)))
     st = grg_train_stats()
     _check(load().grg_precond_train(p, C.byref(tp), C.byref(st)))
     return st.as_dict()

@@ -331,6 +331,7 @@ static void schur_free(grg_schur S)
     dfree((void *&)S->cb_out);
     dfree(S->dt64);
     dfree((void *&)S->d_mask_eo);
+    dfree((void *&)S->d_mask_par);
     for (int p = 0; p < 3; ++p) {
         for (void *&b : S->epool[p]) dfree(b);
         S->epool[p].clear();
@@ -339,7 +340,7 @@ static void schur_free(grg_schur S)
     if (S->h_fk) hipHostFree(S->h_fk);
     S->h_fk = nullptr;
     for (int p = 0; p < 3; ++p)
-        for (int k = 0; k < 4; ++k) dfree(S->eo_f[p][k]);
+        for (int k = 0; k < 5; ++k) dfree(S->eo_f[p][k]);
     dfree((void *&)S->partials);
     dfree((void *&)S->alpha);
     dfree((void *&)S->beta);
@@ -414,6 +415,7 @@ grg_status grg_schur_create(grg_lattice L, double m0, const int32_t *q, int32_t 
     ALLOC(S->active, sizeof(int) * kMaxRhs);
     ALLOC(S->act0, sizeof(int) * kMaxRhs);
     if (L->eo_ok) ALLOC(S->d_mask_eo, (size_t)2 * L->Vhs);
+    if (L->eo_ok) ALLOC(S->d_mask_par, (size_t)V);
     ALLOC(S->d_fk, sizeof(double) * kCorrPool * kMaxRhs);
 #undef ALLOC
     if (s == GRG_OK && hipHostMalloc((void **)&S->h_fk, sizeof(double) * kCorrPool * kMaxRhs) != hipSuccess) {
@@ -432,6 +434,7 @@ grg_status grg_schur_create(grg_lattice L, double m0, const int32_t *q, int32_t 
         return s;
     }
     hipStream_t st = L->stream;
+    std::vector<uint8_t> mask_par(L->eo_ok ? (size_t)V : 0);
     GRG_TRY_HIP(hipMemcpyAsync(S->d_mask, mask.data(), V, hipMemcpyHostToDevice, st));
     GRG_TRY_HIP(hipMemcpyAsync(S->d_q, q, sizeof(int32_t) * n_coarse, hipMemcpyHostToDevice, st));
     GRG_TRY_HIP(hipMemcpyAsync(S->d_bidx, bidx.data(), sizeof(int32_t) * V, hipMemcpyHostToDevice, st));
@@ -442,15 +445,17 @@ grg_status grg_schur_create(grg_lattice L, double m0, const int32_t *q, int32_t 
         // the reduced system lives on the parity with fewer rest sites
         long rest[2] = {0, 0};
         for (int x = 0; x < V; ++x) {
-            if (mask[x]) continue;
             int c = x, par = 0;
             for (int mu = 0; mu < 4; ++mu) {
                 par += c % g.L[mu];
                 c /= g.L[mu];
             }
-            ++rest[par & 1];
+            mask_par[x] = (uint8_t)(par & 1);
+            if (!mask[x]) ++rest[par & 1];
         }
         S->eo_par = rest[0] < rest[1] ? 0 : 1;
+        for (int x = 0; x < V; ++x) mask_par[x] = !mask[x] && mask_par[x] == S->eo_par ? 0 : 1;
+        GRG_TRY_HIP(hipMemcpyAsync(S->d_mask_par, mask_par.data(), V, hipMemcpyHostToDevice, st));
     }
     GRG_TRY_HIP(hipStreamSynchronize(st));
     *out = S;

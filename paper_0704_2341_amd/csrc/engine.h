@@ -131,6 +131,9 @@ hipError_t launch_dslash(int prec, const DslashArgs &a, int grid, hipStream_t st
 hipError_t launch_dc_update(int prec, const DcArgs &a, int grid, int SB, hipStream_t st);
 hipError_t launch_dslash_coarse(const CoarseArgs &a, hipStream_t st);
 hipError_t launch_eo_hop(int prec, const EoArgs &a, int grid, hipStream_t st);
+// compact field of parity par <-> full field (zero off that parity)
+hipError_t launch_eo_scatter(int prec, const Geom &g, int nrhs, int par, const void *src, void *dst,
+                             bool to_full, hipStream_t st);
 hipError_t launch_eo_pack_links(int prec, const Geom &g, int Vhs, const void *U, void *Ueo, hipStream_t st);
 hipError_t launch_eo_pack_mask(const Geom &g, int Vhs, const uint8_t *mask, uint8_t *meo, hipStream_t st);
 hipError_t launch_pack_gauge(const double *src, const Geom &g, const int bc[4], void *u64,

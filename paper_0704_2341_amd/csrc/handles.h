@@ -83,14 +83,17 @@ struct grg_schur_s {
     void *dt64 = nullptr;
     // even-odd reduced inner solve: mask per parity ([2][Vhs]), the parity of
     // the reduced system, and compact fields per inner precision: r, x, q
-    // (reduced parity) and w (other parity)
+    // (reduced parity), w (other parity) and the preconditioned direction p
     uint8_t *d_mask_eo = nullptr;
+    // full-lattice mask of the reduced system: 0 on the rest sites of parity
+    // eo_par, 1 elsewhere (training pairs of the reduced system)
+    uint8_t *d_mask_par = nullptr;
     // the defect correction's corrections e_k (inner precision, full layout)
     // and their factors: the iterate is summed from them at the end
     std::vector<void *> epool[3];
     double *d_fk = nullptr, *h_fk = nullptr;  // [kCorrPool][kMaxRhs]
     int eo_par = 1;
-    void *eo_f[3][4] = {};
+    void *eo_f[3][5] = {};
     grg::DslashTune eotune[3][grg::kMaxRhs + 1];
     // reduction scratch
     double *partials = nullptr;

@@ -208,6 +208,33 @@ __global__ void __launch_bounds__(256) eo_hop_kernel(EoArgs a)
     }
 }
 
+// A compact field of parity par <-> the full field that holds it on the
+// sites of that parity and zero on the others (every RHS).
+template <int P>
+__global__ void __launch_bounds__(256) eo_scatter_kernel(Geom g, int nrhs, int par, const void *src_,
+                                                         void *dst_, int to_full)
+{
+    typedef typename Store<P>::S S;
+    const S *src = (const S *)src_;
+    S *dst = (S *)dst_;
+    const int n = to_full ? g.V : g.V / 2;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        for (int r = 0; r < nrhs; ++r) {
+            if (to_full) {
+                const bool mine = site_parity(i, g) == par;
+#pragma unroll
+                for (int c = 0; c < 12; ++c)
+                    dst[fidx(i, r, c, nrhs)] = mine ? src[fidx(i >> 1, r, c, nrhs)] : S{};
+            } else {
+                SiteGeo q;
+                const int s = eo_site(i, par, g, q);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) dst[fidx(i, r, c, nrhs)] = src[fidx(s, r, c, nrhs)];
+            }
+        }
+    }
+}
+
 // links [tiles][4][9][64] -> [2][half tiles][4][9][64]; mask -> [2][Vhs]
 template <class S>
 __global__ void __launch_bounds__(256) eo_pack_links_kernel(Geom g, int Vhs, const S *U, S *Ueo)
@@ -266,6 +293,19 @@ hipError_t launch_eo_hop(int prec, const EoArgs &a, int grid, hipStream_t st)
     }
 #undef EOIO
 #undef EOH
+    return hipGetLastError();
+}
+
+hipError_t launch_eo_scatter(int prec, const Geom &g, int nrhs, int par, const void *src, void *dst,
+                             bool to_full, hipStream_t st)
+{
+    const int grid = std::min(cdiv(g.V, 256), 8192);
+    switch (prec) {
+    case GRG_FP64: hipLaunchKernelGGL(eo_scatter_kernel<GRG_FP64>, dim3(grid), dim3(256), 0, st, g, nrhs, par, src, dst, (int)to_full); break;
+    case GRG_FP32: hipLaunchKernelGGL(eo_scatter_kernel<GRG_FP32>, dim3(grid), dim3(256), 0, st, g, nrhs, par, src, dst, (int)to_full); break;
+    case GRG_BF16: hipLaunchKernelGGL(eo_scatter_kernel<GRG_BF16>, dim3(grid), dim3(256), 0, st, g, nrhs, par, src, dst, (int)to_full); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

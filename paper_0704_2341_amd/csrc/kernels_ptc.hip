@@ -22,6 +22,7 @@
 #include "common.h"
 #include "engine.h"
 #include "ptc.h"
+#include "stencil.h"
 
 namespace grg {
 
@@ -57,56 +58,72 @@ __device__ __forceinline__ void ptc_hop_site(int s, int h, const Geom &g, int &n
 // Phase 1: T_h X_f' for the 64 sites of a tile into LDS.  Row-major layout
 // B[row][col]: ROWK = true puts the (hop, f', re/im) index contiguous (rows =
 // (site, colour)), ROWK = false puts the (site, colour) index contiguous.
+//
+// The transports run on packed BF16 operands: each complex product of a link
+// entry m with a colour component x is two two-way BF16 dot products (exact
+// products, FP32 sums) against the forms (m.re, -m.im), (m.im, m.re) for U x
+// and (m.re, m.im), (-m.im, m.re) for U^+ x, made once per hop and shared by
+// the channels.  The work is split over the four wavefronts as (hop, half of
+// the channels) tasks, two per hop of the range [h0, h1); the (hop, f', re/im)
+// index is stored relative to kbase.
 template <int FIN, bool ROWK, int LD>
 __device__ __forceinline__ void ptc_gather(const bf16x2 *__restrict__ x, const bf16x2 *__restrict__ U,
                                            const Geom &g, int tile, int r, int nrhs,
-                                           __bf16 *lds)
+                                           __bf16 *lds, int h0 = 0, int h1 = 9, int kbase = 0)
 {
+    constexpr int FH = (FIN + 1) / 2;  // channels per task
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int s = tile * 64 + lane;
     const bool valid = s < g.V;
     const int sc = valid ? s : 0;
-    for (int h = wv; h < 9; h += 4) {
+    for (int task = wv; task < 2 * (h1 - h0); task += 4) {
+        const int h = h0 + (task >> 1), f0 = (task & 1) * FH, f1 = min(f0 + FH, FIN);
         int n, ls;
         ptc_hop_site(sc, h, g, n, ls);
         const int mu = h == 0 ? 0 : (h - 1) >> 1;
         const bool fwd = h > 0 && ((h - 1) & 1) == 0;
-        cpx<float> u[9];
+        uint32_t fr[9], fi[9];  // link forms, fr[3a + b] and fi[3a + b] for output colour a
         if (h > 0) {
 #pragma unroll
-            for (int e = 0; e < 9; ++e) u[e] = ldc(U, lidx(ls, mu, e));
+            for (int a = 0; a < 3; ++a) {
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const uint32_t m = U[lidx(ls, mu, fwd ? 3 * a + b : 3 * b + a)];
+                    fr[3 * a + b] = fwd ? m ^ kNegHi : m;
+                    fi[3 * a + b] = fwd ? swap_halves(m) : swap_halves(m) ^ kNegLo;
+                }
+            }
         }
+        for (int f = f0; f < f1; ++f) {
+            uint32_t v[3], w[3];
 #pragma unroll
-        for (int f = 0; f < FIN; ++f) {
-            cpx<float> v[3], w[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) v[a] = ldc(x, aidx(n, r, 3 * f + a, nrhs, 3 * FIN));
+            for (int a = 0; a < 3; ++a) v[a] = x[aidx(n, r, 3 * f + a, nrhs, 3 * FIN)];
             if (h == 0) {
 #pragma unroll
                 for (int a = 0; a < 3; ++a) w[a] = v[a];
             } else {
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    w[a] = {0.f, 0.f};
+                    float re = 0.f, im = 0.f;
 #pragma unroll
                     for (int b = 0; b < 3; ++b) {
-                        if (fwd) cmac(w[a], u[3 * a + b], v[b]);
-                        else cmacc(w[a], u[3 * b + a], v[b]);
+                        re = dot2bf(fr[3 * a + b], v[b], re);
+                        im = dot2bf(fi[3 * a + b], v[b], im);
                     }
+                    w[a] = pack_bf16(re, im);
                 }
             }
-            const int k0 = (h * FIN + f) * 2;
+            const int k0 = (h * FIN + f) * 2 - kbase;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int col = lane * 3 + a;
-                const __bf16 re = valid ? (__bf16)w[a].re : (__bf16)0.f;
-                const __bf16 im = valid ? (__bf16)w[a].im : (__bf16)0.f;
+                const uint32_t word = valid ? w[a] : 0u;
                 if (ROWK) {
-                    lds[col * LD + k0] = re;
-                    lds[col * LD + k0 + 1] = im;
+                    // (re, im) adjacent in a row: one 32-bit store (k0 even, LD even)
+                    *(uint32_t *)(lds + col * LD + k0) = word;
                 } else {
-                    lds[k0 * LD + col] = re;
-                    lds[(k0 + 1) * LD + col] = im;
+                    lds[k0 * LD + col] = __builtin_bit_cast(__bf16, (uint16_t)(word & 0xffffu));
+                    lds[(k0 + 1) * LD + col] = __builtin_bit_cast(__bf16, (uint16_t)(word >> 16));
                 }
             }
         }
@@ -119,13 +136,18 @@ __global__ void __launch_bounds__(256) ptc_layer_kernel(PtcLayerArgs a)
 {
     constexpr int KR = 9 * FIN * 2;
     constexpr int KP = (KR + 31) / 32 * 32;
-    constexpr int LD = KP + 8;  // bf16 elements per LDS row (16-byte aligned rows)
     constexpr int NS = KP / 32;
+    // The K dimension in two passes, hops 0..3 and 4..8 (K1 = 4 * FIN * 2 is a
+    // whole number of 32-wide MFMA steps), so that LDS holds half the
+    // transported fields at a time and four or five workgroups share a CU.
+    constexpr int K1 = 4 * FIN * 2, NS1 = K1 / 32, K2 = KP - K1;
+    constexpr int LD = (K1 > K2 ? K1 : K2) + 8;  // bf16 per LDS row (16-byte aligned rows)
+    static_assert(K1 % 32 == 0, "first pass must be whole MFMA steps");
     __shared__ __attribute__((aligned(16))) __bf16 lds[192 * LD];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    // zero the padding rows once; phase 1 never writes them
+    // zero the second pass's padding columns once; the gathers never write them
     for (int i = threadIdx.x; i < 192 * (KP - KR); i += blockDim.x)
-        lds[(i / (KP - KR)) * LD + KR + i % (KP - KR)] = (__bf16)0.f;
+        lds[(i / (KP - KR)) * LD + (KR - K1) + i % (KP - KR)] = (__bf16)0.f;
     // this lane's weight fragments: A[l%16][32 s + 8 (l/16) + j]
     bf16x8_v af[NS];
 #pragma unroll
@@ -138,18 +160,30 @@ __global__ void __launch_bounds__(256) ptc_layer_kernel(PtcLayerArgs a)
     const int nitems = ntiles * a.nrhs;
     for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
         const int tile = w / a.nrhs, r = w - tile * a.nrhs;
-        __syncthreads();  // the previous item's products are out of LDS
-        ptc_gather<FIN, true, LD>(x, U, a.g, tile, r, a.nrhs, lds);
-        __syncthreads();
-        for (int t = wv; t < 12; t += 4) {
-            f32x4_v c = {0.f, 0.f, 0.f, 0.f};
-            const __bf16 *brow = lds + (16 * t + (lane & 15)) * LD + 8 * (lane >> 4);
+        f32x4_v c[3];
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const bf16x8_v bf = *(const bf16x8_v *)(brow + 32 * s);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[s], bf, c, 0, 0, 0);
+        for (int i = 0; i < 3; ++i) c[i] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+            __syncthreads();  // the previous products are out of LDS
+            if (pass == 0) ptc_gather<FIN, true, LD>(x, U, a.g, tile, r, a.nrhs, lds, 0, 4, 0);
+            else ptc_gather<FIN, true, LD>(x, U, a.g, tile, r, a.nrhs, lds, 4, 9, K1);
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const int t = wv + 4 * i;
+                const __bf16 *brow = lds + (16 * t + (lane & 15)) * LD + 8 * (lane >> 4);
+#pragma unroll
+                for (int s = (pass == 0 ? 0 : NS1); s < (pass == 0 ? NS1 : NS); ++s) {
+                    const bf16x8_v bf = *(const bf16x8_v *)(brow + 32 * (s - (pass == 0 ? 0 : NS1)));
+                    c[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[s], bf, c[i], 0, 0, 0);
+                }
             }
-            // rows 4 (l/16) + i = (f, re/im): two complex outputs per lane
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int t = wv + 4 * i;
+            // rows 4 (l/16) + q = (f, re/im): two complex outputs per lane
             const int col = 16 * t + (lane & 15);
             const int site = tile * 64 + col / 3, colour = col % 3;
             if (site < a.g.V) {
@@ -159,7 +193,7 @@ __global__ void __launch_bounds__(256) ptc_layer_kernel(PtcLayerArgs a)
                 for (int q = 0; q < 2; ++q) {
                     const int f = f0 + q;
                     if (f < FOUT) {
-                        const float re = on ? c[2 * q] : 0.f, im = on ? c[2 * q + 1] : 0.f;
+                        const float re = on ? c[i][2 * q] : 0.f, im = on ? c[i][2 * q + 1] : 0.f;
                         y[aidx(site, r, 3 * f + colour, a.nrhs, 3 * FOUT)] = pack_bf16(re, im);
                     }
                 }

@@ -24,6 +24,7 @@ BlasShape blas_shape(const Geom &g, int nrhs);
 grg_status run_dslash(grg_schur S, int prec, const void *in, void *out, int sel, int nrhs,
                       double *partials, const void *dot_with = nullptr);
 DslashTune default_tune(const Geom &g, int prec, int nrhs);
+grg_status eo_training_pair(grg_schur S, void *e, void *r_full, int nrhs, int k, const double *neg_one);
 
 static const int kOff[3] = {0, 9 * 8 * 4, 9 * 8 * 4 + 9 * 8 * 8};
 
@@ -46,8 +47,10 @@ static grg_status embed_all(grg_precond P)
     return GRG_OK;
 }
 
-// act_out = M act_in (bf16 Dirac-field tiles), output zero on the coarse sites
-static grg_status forward(grg_precond P, const void *in, void *out, int nrhs)
+// act_out = M act_in (bf16 Dirac-field tiles), output zero where mask is not
+// 0 (default: the coarse sites)
+static grg_status forward(grg_precond P, const void *in, void *out, int nrhs,
+                          const uint8_t *mask = nullptr)
 {
     grg_schur S = P->schur;
     grg_lattice L = S->lat;
@@ -59,7 +62,7 @@ static grg_status forward(grg_precond P, const void *in, void *out, int nrhs)
         a.y = l == 2 ? out : P->act[l + 1];
         a.U = L->U[GRG_BF16];
         a.A = P->A[l];
-        a.mask = l == 2 ? S->d_mask : nullptr;
+        a.mask = l == 2 ? (mask ? mask : S->d_mask) : nullptr;
         a.sel = 0;
         a.g = L->g;
         a.nrhs = nrhs;
@@ -330,11 +333,13 @@ grg_status grg_precond_train(grg_precond P, const grg_train_params *tp, grg_trai
 {
     if (!P || !tp) return set_error("null argument"), GRG_EINVAL;
     if (tp->steps < 1 || tp->batch < 1 || tp->batch > P->max_rhs || tp->max_mr_steps < 0 ||
-        !(tp->lr > 0))
+        !(tp->lr > 0) || (tp->reduced != 0 && tp->reduced != 1))
         return set_error("bad training parameters"), GRG_EINVAL;
     DeviceScope ds(P->schur->lat->device);
     grg_schur S = P->schur;
     grg_lattice L = S->lat;
+    if (tp->reduced && !S->d_mask_par)
+        return set_error("reduced training needs even lattice extents"), GRG_EINVAL;
     hipStream_t st = L->stream;
     const int B = tp->batch;
     const BlasShape sh = blas_shape(L->g, B);
@@ -353,20 +358,35 @@ grg_status grg_precond_train(grg_precond P, const grg_train_params *tp, grg_trai
     void *x = P->gen[0], *r = P->gen[1], *q = P->gen[2];
     for (int step = 1; step <= tp->steps; ++step) {
         const int k = (int)(rng() % (uint64_t)(tp->max_mr_steps + 1));
-        GRG_TRY_HIP(launch_random_field(GRG_BF16, P->ebuf, S->d_mask, L->g, B, rng(), st));
-        GRG_TRY(run_dslash(S, GRG_BF16, P->ebuf, r, 0, B, nullptr));
-        GRG_TRY_HIP(launch_fill_zero(x, act_bytes(L->g, B, 4), st));
-        for (int j = 0; j < k; ++j) {
-            GRG_TRY(run_dslash(S, GRG_BF16, r, q, 0, B, S->partials));
-            GRG_TRY_HIP(launch_reduce(kAlpha, S->partials, agrid, B, S->alpha, nullptr, nullptr,
-                                      nullptr, st));
-            GRG_TRY_HIP(launch_mr_update(GRG_BF16, sh, x, r, q, nullptr, S->alpha, S->partials, st));
+        // Reduced training starts with a quarter of the steps on pairs of
+        // D_rr itself: every hop moves a field to the other parity, so on
+        // pairs that live on one parity the gradient of each hop weight
+        // pairs fields of opposite parities and vanishes while the hop
+        // weights are zero (the identity start), and the hop weights would
+        // never leave zero.
+        const bool red = tp->reduced && step > tp->steps / 4;
+        if (red) {
+            // pairs of the reduced system (errors and loss on the reduced
+            // parity's rest sites)
+            GRG_TRY_HIP(launch_random_field(GRG_BF16, P->ebuf, S->d_mask_par, L->g, B, rng(), st));
+            GRG_TRY(eo_training_pair(S, P->ebuf, r, B, k, P->neg_one));
+        } else {
+            GRG_TRY_HIP(launch_random_field(GRG_BF16, P->ebuf, S->d_mask, L->g, B, rng(), st));
+            GRG_TRY(run_dslash(S, GRG_BF16, P->ebuf, r, 0, B, nullptr));
+            GRG_TRY_HIP(launch_fill_zero(x, act_bytes(L->g, B, 4), st));
+            for (int j = 0; j < k; ++j) {
+                GRG_TRY(run_dslash(S, GRG_BF16, r, q, 0, B, S->partials));
+                GRG_TRY_HIP(launch_reduce(kAlpha, S->partials, agrid, B, S->alpha, nullptr, nullptr,
+                                          nullptr, st));
+                GRG_TRY_HIP(launch_mr_update(GRG_BF16, sh, x, r, q, nullptr, S->alpha, S->partials, st));
+            }
+            // e_k = e_0 - x_k and r_k = D_rr e_k: the pair the solver produced
+            // (r_k recomputed from e_k, so that the pair is consistent to rounding)
+            GRG_TRY_HIP(launch_axpy_convert(GRG_BF16, GRG_BF16, sh, x, P->ebuf, P->neg_one, 0, 1,
+                                            nullptr, st));
+            GRG_TRY(run_dslash(S, GRG_BF16, P->ebuf, r, 0, B, nullptr));
         }
-        // e_k = e_0 - x_k and r_k = D_rr e_k: the pair the solver produced
-        // (r_k recomputed from e_k, so that the pair is consistent to rounding)
-        GRG_TRY_HIP(launch_axpy_convert(GRG_BF16, GRG_BF16, sh, x, P->ebuf, P->neg_one, 0, 1, nullptr, st));
-        GRG_TRY(run_dslash(S, GRG_BF16, P->ebuf, r, 0, B, nullptr));
-        GRG_TRY(forward(P, r, P->act[3], B));
+        GRG_TRY(forward(P, r, P->act[3], B, red ? S->d_mask_par : nullptr));
         GRG_TRY(loss(P, B, P->act[3]));
         GRG_TRY(backward(P, r, B));
         ++P->adam_step;

@@ -482,7 +482,7 @@ static grg_status ensure_eo(grg_schur S, int prec)
 {
     grg_lattice L = S->lat;
     const size_t bytes = spinor_elems(half_geom(L), S->prm.max_rhs) * prec_bytes(prec);
-    for (int k = 0; k < 4; ++k) {  // r, x, q and the other parity's w
+    for (int k = 0; k < 5; ++k) {  // r, x, q, the other parity's w, and p
         void *&b = S->eo_f[prec][k];
         if (b) continue;
         if (hipMalloc(&b, bytes) != hipSuccess) {
@@ -697,6 +697,126 @@ static grg_status inner_mr_eo(grg_schur S, int prec, int nrhs, const double *thr
     return done ? GRG_OK : GRG_ENOCONV;
 }
 
+// Minimal residual on the even-odd reduced system with a right
+// preconditioner (flexible GCR(1)): p = M^ r, q = A^ p, x += alpha p,
+// r -= alpha q, alpha = <q, r> / <q, q>.  M^ restricts the learned network
+// to the reduced parity: r extended by zero to the other parity, the network,
+// and its output on the reduced parity again.  Since the inverse of the
+// reduced operator is the reduced-parity block of D_rr^{-1}, a network that
+// approximates D_rr^{-1} approximates it too.  Same conventions as
+// inner_mr_eo.
+static grg_status inner_fgcr_eo(grg_schur S, int prec, int nrhs, const double *thr, int maxit,
+                                int *iters, double *rn2_out, void *xdst)
+{
+    grg_lattice L = S->lat;
+    hipStream_t st = L->stream;
+    const Geom &g = L->g;
+    GRG_TRY(ensure_eo(S, prec));
+    const Geom gh = half_geom(L);
+    const BlasShape sh = blas_shape(gh, nrhs);
+    const size_t vbytes = spinor_elems(gh, nrhs) * prec_bytes(prec);
+    const DslashTune t = S->eotune[prec][nrhs].valid ? S->eotune[prec][nrhs]
+                                                     : default_eo_tune(gh, prec, nrhs);
+    const int P = S->eo_par, Q = 1 - P;
+    void **f = S->eo_f[prec];
+    void *r = f[0], *x = f[1], *q = f[2], *w = f[3], *pv = f[4];
+    void *full_in = S->in_b[prec], *full_out = S->in_q[prec];
+    const void *b = S->in_r[prec];
+    const double d = 4.0 + S->m0;
+    const int check = std::max(1, S->prm.check_every);
+    GRG_TRY(eo_hop(S, prec, t, b, b, r, P, 1.0, -1.0 / d, nrhs, nullptr, nullptr, nullptr, 1, 1));
+    GRG_TRY_HIP(launch_fill_zero(x, vbytes, st));
+    GRG_TRY_HIP(launch_norm2(prec, sh, r, S->partials, st));
+    GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, S->thr2,
+                              S->active, st));
+    double h[kMaxRhs];
+    GRG_TRY(read_norms(S, nrhs, h));
+    {
+        int *flags = (int *)(S->h_buf + 8 * kMaxRhs);
+        for (int k = 0; k < nrhs; ++k) flags[k] = h[k] > thr[k] ? 1 : 0;
+        GRG_TRY_HIP(hipMemcpyAsync(S->act0, flags, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
+    }
+    auto all_done = [&](const double *n2) {
+        for (int k = 0; k < nrhs; ++k) {
+            if (!isfinite(n2[k])) return -1;
+            if (n2[k] > thr[k]) return 0;
+        }
+        return 1;
+    };
+    int it = 0;
+    int done = all_done(h);
+    while (done == 0 && it < maxit) {
+        // p = M^ r
+        GRG_TRY_HIP(launch_eo_scatter(prec, g, nrhs, P, r, full_in, true, st));
+        GRG_TRY(precond_apply_inner(S, prec, full_in, full_out, nrhs));
+        GRG_TRY_HIP(launch_eo_scatter(prec, g, nrhs, P, full_out, pv, false, st));
+        // q = A^ p with the sums <q, r>, |q|^2
+        GRG_TRY(eo_hop(S, prec, t, pv, nullptr, w, Q, 0.0, 1.0, nrhs, nullptr, nullptr));
+        GRG_TRY(eo_hop(S, prec, t, w, pv, q, P, d, -1.0 / d, nrhs, S->partials, r));
+        GRG_TRY_HIP(launch_reduce(kAlpha, S->partials, t.grid, nrhs, S->alpha, nullptr, nullptr,
+                                  S->active, st));
+        GRG_TRY_HIP(launch_mr_update(prec, sh, x, r, q, pv, S->alpha, S->partials, st));
+        GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, S->thr2,
+                                  S->active, st));
+        ++it;
+        if (it % check == 0 || it == maxit) {
+            GRG_TRY(read_norms(S, nrhs, h));
+            done = all_done(h);
+        }
+    }
+    *iters = it;
+    memcpy(rn2_out, h, sizeof(double) * nrhs);
+    GRG_TRY(eo_hop(S, prec, t, x, b, xdst, Q, 1.0 / d, -1.0 / d, nrhs, nullptr, nullptr, S->act0,
+                   0, 1, x));
+    if (done < 0) {
+        set_error("non-finite residual in the inner solve");
+        return GRG_ENONFINITE;
+    }
+    return done ? GRG_OK : GRG_ENOCONV;
+}
+
+// A training pair of the reduced system for the learned preconditioner.
+// e (BF16, full layout) holds the error e_0 on the reduced parity's rest
+// sites.  k minimal-residual steps on A^ x = A^ e_0 from x = 0 (the reduced
+// inner solve without the network) leave e_k = e_0 - x_k in e and
+// r_k = A^ e_k in r, both in the full layout and zero on the other parity:
+// the residuals that the reduced inner solve hands the network, with the
+// errors it should map them to.
+grg_status eo_training_pair(grg_schur S, void *e, void *r_full, int nrhs, int k, const double *neg_one)
+{
+    grg_lattice L = S->lat;
+    hipStream_t st = L->stream;
+    const int prec = GRG_BF16;
+    GRG_TRY(ensure_eo(S, prec));
+    const Geom gh = half_geom(L);
+    const BlasShape sh = blas_shape(gh, nrhs);
+    const DslashTune t = S->eotune[prec][nrhs].valid ? S->eotune[prec][nrhs]
+                                                     : default_eo_tune(gh, prec, nrhs);
+    const int P = S->eo_par, Q = 1 - P;
+    const double d = 4.0 + S->m0;
+    void **f = S->eo_f[prec];
+    void *r = f[0], *x = f[1], *q = f[2], *w = f[3], *e0 = f[4];
+    GRG_TRY_HIP(launch_eo_scatter(prec, L->g, nrhs, P, e, e0, false, st));
+    GRG_TRY(eo_hop(S, prec, t, e0, nullptr, w, Q, 0.0, 1.0, nrhs, nullptr, nullptr));
+    GRG_TRY(eo_hop(S, prec, t, w, e0, r, P, d, -1.0 / d, nrhs, nullptr, nullptr));
+    GRG_TRY_HIP(launch_fill_zero(x, spinor_elems(gh, nrhs) * prec_bytes(prec), st));
+    for (int j = 0; j < k; ++j) {
+        GRG_TRY(eo_hop(S, prec, t, r, nullptr, w, Q, 0.0, 1.0, nrhs, nullptr, nullptr));
+        GRG_TRY(eo_hop(S, prec, t, w, r, q, P, d, -1.0 / d, nrhs, S->partials, r));
+        GRG_TRY_HIP(launch_reduce(kAlpha, S->partials, t.grid, nrhs, S->alpha, nullptr, nullptr,
+                                  nullptr, st));
+        GRG_TRY_HIP(launch_mr_update(prec, sh, x, r, q, nullptr, S->alpha, S->partials, st));
+    }
+    // e_k = e_0 - x_k and r_k = A^ e_k (recomputed, so that the pair is
+    // consistent to rounding)
+    GRG_TRY_HIP(launch_axpy_convert(prec, prec, sh, x, e0, neg_one, 0, 1, nullptr, st));
+    GRG_TRY(eo_hop(S, prec, t, e0, nullptr, w, Q, 0.0, 1.0, nrhs, nullptr, nullptr));
+    GRG_TRY(eo_hop(S, prec, t, w, e0, r, P, d, -1.0 / d, nrhs, nullptr, nullptr));
+    GRG_TRY_HIP(launch_eo_scatter(prec, L->g, nrhs, P, e0, e, true, st));
+    GRG_TRY_HIP(launch_eo_scatter(prec, L->g, nrhs, P, r, r_full, true, st));
+    return GRG_OK;
+}
+
 // Inner iterations allowed to a preconditioned inner solve before the plain
 // GCR fallback takes over.
 constexpr int kPrecondInnerCap = 100;
@@ -858,9 +978,12 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
         int it = 0;
         grg_status is;
         double h[kMaxRhs];
+        const bool reduce = p.eo && L->eo_ok && std::max(1, p.restart) == 1;
         if (S->precond) {
-            // preconditioned inner solve, with plain GCR as the fallback
-            is = inner_gcr(S, prec, nrhs, thr, std::min(p.max_iter - total, kPrecondInnerCap), &it, h, e);
+            // preconditioned inner solve, with the plain solve as the fallback
+            const int cap = std::min(p.max_iter - total, kPrecondInnerCap);
+            is = reduce ? inner_fgcr_eo(S, prec, nrhs, thr, cap, &it, h, e)
+                        : inner_gcr(S, prec, nrhs, thr, cap, &it, h, e);
             total += it;
             if (is != GRG_OK) {
                 grg_precond keep = S->precond;
@@ -868,11 +991,12 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
                 ++S->fallbacks;
                 GRG_TRY(upload(d_s, sc, 2));
                 GRG_TRY(convert_rhs(S, prec, sh, r_src, d_s));
-                is = inner_gcr(S, prec, nrhs, thr, p.max_iter - total, &it, h, e);
+                is = reduce ? inner_mr_eo(S, prec, nrhs, thr, p.max_iter - total, &it, h, e)
+                            : inner_gcr(S, prec, nrhs, thr, p.max_iter - total, &it, h, e);
                 S->precond = keep;
                 total += it;
             }
-        } else if (p.eo && L->eo_ok && std::max(1, p.restart) == 1) {
+        } else if (reduce) {
             is = inner_mr_eo(S, prec, nrhs, thr, p.max_iter - total, &it, h, e);
             total += it;
         } else {

@@ -120,12 +120,17 @@ def test_loss_and_gradients_vs_oracle(setup):
     assert cos > 0.998
 
 
-def test_training_reduces_loss_and_iterations():
+@pytest.mark.parametrize("reduced", [False, True])
+def test_training_reduces_loss_and_iterations(reduced):
+    """Pairs of D_rr itself, or of its even-odd reduced system (the inner
+    solve the network then serves)."""
     lat = Lattice((8, 8, 8, 8), 0.5, 5)
     s = lat.schur(-0.3, "I", False, tol=1e-10, inner="bf16", inner_tol=1e-2, max_rhs=12)
     grg = lat.grg
     p = grg.grg_precond_create(s.h)
-    st = grg.grg_precond_train(p, steps=200, batch=8, max_mr_steps=20, lr=3e-3, seed=5, log_every=20)
+    st = grg.grg_precond_train(p, steps=200, batch=8, max_mr_steps=20, lr=3e-3, seed=5, log_every=20,
+                               reduced=reduced)
+    print(f"reduced={reduced}: {st}", flush=True)
     assert st["pairs"] == 1600 and st["loss_last"] < 0.5 * st["loss_first"], st
     xb = point_sources(s.nb, 12)
     y0, st0 = s.apply(xb)
@@ -133,6 +138,7 @@ def test_training_reduces_loss_and_iterations():
     y1, st1 = s.apply(xb)
     assert st1["converged"] and st1["fallbacks"] == 0
     assert rel_err(y1, y0) < 1e-9
+    print(f"inner iterations: plain {st0['iters']}, learned {st1['iters']}", flush=True)
     assert st1["iters"] < st0["iters"], (st0, st1)
     grg.grg_schur_attach_precond(s.h, None)
     grg.grg_precond_destroy(p)

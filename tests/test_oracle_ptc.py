@@ -72,6 +72,29 @@ def test_identity_weights_and_linearity(links):
     assert np.allclose(f(a + 2j * b), f(a) + 2j * f(b), atol=1e-12)
 
 
+def test_one_parity_pairs_leave_zero_hop_weights_without_gradient(links):
+    """Each hop moves a field to the other parity, so at weights without hop
+    terms (the identity start) the hop-weight gradients from pairs that live
+    on one parity pair fields of opposite parities and vanish; pairs on both
+    parities give them a gradient."""
+    ws = []
+    for fi, fo in zip(ptc.CHANNELS[:-1], ptc.CHANNELS[1:]):
+        w = np.zeros((9, fo, fi), complex)
+        for f in range(min(fi, fo)):
+            w[0, f, f] = 1.0
+        ws.append(w)
+    c = np.indices(DIMS[::-1]).reshape(4, -1)[::-1]  # (x, y, z, t) of site x + 4 (y + 4 (z + 4 t))
+    even = (c.sum(axis=0) % 2 == 0).astype(float)[:, None, None]
+    r = np.stack([rfield(31) * even, rfield(32) * even])
+    e = np.stack([rfield(33) * even, rfield(34) * even])
+    _, g = ptc.loss_and_grads(r, e, ws, links, DIMS, out_mask=even[:, 0, 0])
+    for gl in g:
+        assert np.abs(gl[1:]).max() < 1e-14 and np.abs(gl[0]).max() > 1e-3
+    _, g = ptc.loss_and_grads(np.stack([rfield(35), rfield(36)]), np.stack([rfield(37), rfield(38)]),
+                              ws, links, DIMS)
+    assert all(np.abs(gl[1:]).max() > 1e-3 for gl in g)
+
+
 def test_layer_adjoint(links):
     ws = ptc.random_weights(10)
     x, dy = rfield(11, 8), rfield(12, 8)
