@@ -214,14 +214,18 @@ grg_status grg_schur_tune(grg_schur s, int nrhs);
  * contiguous eighth of the lattice per XCD), time-chunk length of the
  * t-marching kernel (0 = site-parallel kernel)}; *ms = its tuned time per
  * launch, or -1 if untuned (defaults in use).  precision 3..5 reports the
- * half-lattice stencil of the even-odd reduced solve in precision - 3
- * (info[5] = 0). */
+ * half-lattice stencil of the even-odd reduced solve in precision - 3: hop
+ * schedule 3 (BF16 only, info[0] = 256) is its t-marching form, a
+ * workgroup holding 64 columns of the half lattice and four RHS, walking
+ * info[5] time slices, with info[1] the RHS per workgroup of the one-hop
+ * form that its full-layout steps use; otherwise info[5] = 0. */
 grg_status grg_schur_tune_info(grg_schur s, int precision, int nrhs, int32_t info[6], float *ms);
 
 /* Pin the stencil launch for (precision, nrhs), e.g. from a saved tuning
  * result: info as returned by grg_schur_tune_info.  GRG_EINVAL if the shape
  * is not valid for this lattice (a t-marching workgroup holds 64 * RHS
- * threads, at most 512 in FP64 and 768 otherwise). */
+ * threads, at most 512 in FP64 and 768 otherwise; the t-marching
+ * half-lattice stencil needs a multiple of 64 half-sites per time slice). */
 grg_status grg_schur_set_launch(grg_schur s, int precision, int nrhs, const int32_t info[6]);
 
 /* The launch of the fused FP64 defect-correction step r -= D_rr e / s,
@@ -243,6 +247,19 @@ grg_status grg_schur_set_dc_launch(grg_schur s, int precision, int nrhs, const i
  * inverts; D_rb, D_br and D_bb enter S_bb. */
 grg_status grg_block_apply(grg_schur s, int precision, int rows, int cols, const double *in,
                            double *out, int nrhs);
+
+/* The even-odd reduced form of D_rr on one parity: D_rr couples a rest site
+ * only to itself (diagonal d = 4 + m0) and to rest sites of the other parity,
+ * so on the rest sites of parity p (x + y + z + t mod 2) and q = 1 - p its
+ * Schur complement is A_p = d - H_pq H_qp / d, with H the hopping part of
+ * D_rr (the same block elimination as S_bb, applied to D_rr; the reduced
+ * solve works on it).  out = A_p in for nrhs canonical lattice fields
+ * (device); in is read on the rest sites of parity p only and out is zero
+ * elsewhere.  Computed in the given precision with the two half-lattice
+ * stencils of the handle's launch (grg_schur_tune_info, precision 3..5).
+ * GRG_EINVAL if an extent is odd (no even-odd form) or parity is not 0 or 1. */
+grg_status grg_reduced_apply(grg_schur s, int precision, int parity, const double *in, double *out,
+                             int nrhs);
 
 /* ---------------------------------------------------------------------------
  * Learned preconditioner.  M is a linear, gauge-covariant network of three

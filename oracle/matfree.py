@@ -142,3 +142,28 @@ def reusken_apply(links, dims, m0, q, nb, xb, bc=(1, 1, 1, -1)):
     w = u - my.reshape(nrhs, -1)
     out = dirac_apply(links, dims, m0, w, bc).reshape(nrhs, v, 12)
     return np.ascontiguousarray(out[:, q[:nb]].reshape(nrhs, 12 * int(nb)))
+
+
+def site_parity(dims):
+    """(x + y + z + t) mod 2 of every site (lexicographic, x fastest)."""
+    c = np.indices(tuple(dims)[::-1]).reshape(4, -1)[::-1]
+    return c.sum(axis=0) % 2
+
+
+def reduced_apply(links, dims, m0, q, nb, parity, x, bc=(1, 1, 1, -1)):
+    """The even-odd Schur complement of D_rr on the rest sites of one parity,
+    A_p x = (D_rr z)_p with z = x_p - (D_rr x_p)_q / d: the hopping term only
+    couples sites of opposite parity, so D_qq = d (= 4 + m0) on the rest sites
+    and A_p = D_pp - D_pq D_qq^{-1} D_qp = d - H_pq H_qp / d.  x (nrhs, 12 V)
+    is read on the rest sites of parity p; the result is zero elsewhere."""
+    v = int(np.prod(dims))
+    x = _fields(x, 12 * v)
+    nrhs = x.shape[0]
+    par = site_parity(dims)
+    on_p = (par == parity)[None, :, None]
+    on_q = ~on_p
+    xp = (x.reshape(nrhs, v, 12) * on_p).reshape(nrhs, -1)
+    y = block_apply(links, dims, m0, q, nb, 0, 0, xp, bc).reshape(nrhs, v, 12)
+    z = xp.reshape(nrhs, v, 12) - y * on_q / (4.0 + m0)
+    out = block_apply(links, dims, m0, q, nb, 0, 0, z.reshape(nrhs, -1), bc).reshape(nrhs, v, 12)
+    return (out * on_p).reshape(nrhs, -1)

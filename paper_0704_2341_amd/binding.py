@@ -41,7 +41,7 @@ EXPORTS = (
     "grg_drr_solve", "grg_schur_apply", "grg_schur_assemble", "grg_reusken_apply",
     "grg_reusken_assemble", "grg_schur_tune",
     "grg_schur_tune_info", "grg_schur_set_launch", "grg_schur_dc_launch_info",
-    "grg_schur_set_dc_launch", "grg_block_apply", "grg_precond_create",
+    "grg_schur_set_dc_launch", "grg_block_apply", "grg_reduced_apply", "grg_precond_create",
     "grg_precond_destroy", "grg_precond_set_weights", "grg_precond_get_weights", "grg_precond_apply",
     "grg_precond_loss_grad", "grg_precond_train", "grg_precond_save", "grg_precond_load",
     "grg_schur_attach_precond", "grg_batch_create", "grg_batch_destroy", "grg_batch_layout",
@@ -139,6 +139,7 @@ def load():
         "grg_schur_dc_launch_info": (C.c_int, [vp, C.c_int, C.c_int, i32p, C.POINTER(C.c_float)]),
         "grg_schur_set_dc_launch": (C.c_int, [vp, C.c_int, C.c_int, i32p]),
         "grg_block_apply": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, vp, C.c_int]),
+        "grg_reduced_apply": (C.c_int, [vp, C.c_int, C.c_int, vp, vp, C.c_int]),
         "grg_precond_create": (C.c_int, [vp, C.POINTER(vp)]),
         "grg_precond_destroy": (C.c_int, [vp]),
         "grg_precond_set_weights": (C.c_int, [vp, vp]),
@@ -326,12 +327,19 @@ def grg_schur_tune_info(s, precision, nrhs, eo=False):
             "march": info[5], "ms": ms.value}
 
 
-def grg_schur_set_launch(s, precision, nrhs, info):
-    """info: dict as returned by grg_schur_tune_info (or a 6-sequence)."""
+def grg_reduced_apply(s, precision, parity, x, y, nrhs):
+    """y = (d - H_pq H_qp / d) x on the rest sites of parity p (canonical
+    device fields, complex128 [nrhs][12 V])."""
+    _check(load().grg_reduced_apply(s, _prec(precision), int(parity), _ptr(x), _ptr(y), int(nrhs)))
+
+
+def grg_schur_set_launch(s, precision, nrhs, info, eo=False):
+    """info: dict as returned by grg_schur_tune_info (or a 6-sequence); eo=True
+    pins the half-lattice stencil of the even-odd reduced solve."""
     if isinstance(info, dict):
         info = [info.get(k, 0) for k in ("SB", "RG", "split", "grid", "chunk", "march")]
     arr, ptr = _i32(info)
-    _check(load().grg_schur_set_launch(s, _prec(precision), int(nrhs), ptr))
+    _check(load().grg_schur_set_launch(s, _prec(precision) + (3 if eo else 0), int(nrhs), ptr))
 
 
 def grg_schur_dc_launch_info(s, precision, nrhs):

@@ -37,6 +37,8 @@ DslashTune default_tune(const Geom &g, int prec, int nrhs);
 bool launch_ok(const Geom &g, int prec, int nrhs, const DslashTune &t, bool dots);
 grg_status block_apply_internal(grg_schur S, int prec, int rows, int cols, const double *in,
                                 double *out, int nrhs);
+grg_status reduced_apply_internal(grg_schur S, int prec, int parity, const double *in, double *out,
+                                  int nrhs);
 grg_status tune_dslash(grg_schur S, int prec, int nrhs, int reps);
 grg_status reusken_apply_internal(grg_schur S, const double *xb, double *yb, int nrhs);
 grg_status tune_dc(grg_schur S, int prec, int nrhs, int reps);
@@ -44,6 +46,7 @@ grg_status tune_eo(grg_schur S, int prec, int nrhs, int reps);
 DslashTune default_eo_tune(const Geom &gh, int prec, int nrhs);
 DslashTune default_dc_tune(const Geom &g);
 bool dc_launch_ok(const Geom &g, int nrhs, const DslashTune &t);
+bool eo_launch_ok(const Geom &gh, int prec, int nrhs, const DslashTune &t);
 
 static grg_status dmalloc(void **p, size_t bytes, const char *what)
 {
@@ -678,7 +681,7 @@ grg_status grg_schur_tune_info(grg_schur S, int precision, int nrhs, int32_t inf
         gh.Vs = S->lat->Vhs;
         const DslashTune &t = S->eotune[precision - 3][nrhs];
         const DslashTune d = t.valid ? t : default_eo_tune(gh, precision - 3, nrhs);
-        const int32_t v[6] = {d.SB, d.RG, d.split, d.grid, d.chunk, 0};
+        const int32_t v[6] = {d.SB, d.RG, d.split, d.grid, d.chunk, d.march};
         memcpy(info, v, sizeof(v));
         *ms = t.valid ? t.ms : -1.0f;
         return GRG_OK;
@@ -698,7 +701,7 @@ grg_status grg_schur_tune_info(grg_schur S, int precision, int nrhs, int32_t inf
 grg_status grg_schur_set_launch(grg_schur S, int precision, int nrhs, const int32_t info[6])
 {
     if (!S || !info) return set_error("null argument"), GRG_EINVAL;
-    if (precision < 0 || precision > 2 || nrhs < 1 || nrhs > S->prm.max_rhs)
+    if (precision < 0 || precision > 5 || nrhs < 1 || nrhs > S->prm.max_rhs)
         return set_error("bad precision or nrhs"), GRG_EINVAL;
     DslashTune t;
     t.SB = info[0];
@@ -709,12 +712,42 @@ grg_status grg_schur_set_launch(grg_schur S, int precision, int nrhs, const int3
     t.march = info[5];
     t.valid = 1;
     t.ms = 0;
+    if (precision >= 3) {  // the half-lattice stencil of the even-odd reduced solve
+        if (!S->lat->eo_ok) return set_error("the lattice has no even-odd form (odd extent)"), GRG_EINVAL;
+        Geom gh = S->lat->g;
+        gh.V /= 2;
+        gh.Vs = S->lat->Vhs;
+        if (!eo_launch_ok(gh, precision - 3, nrhs, t))
+            return set_error("half-lattice launch {%d, %d, %d, %d, %d, %d} not valid for precision %d, nrhs %d",
+                             info[0], info[1], info[2], info[3], info[4], info[5], precision - 3, nrhs),
+                   GRG_EINVAL;
+        S->eotune[precision - 3][nrhs] = t;
+        return GRG_OK;
+    }
     if (!launch_ok(S->lat->g, precision, nrhs, t, false))
         return set_error("launch {%d, %d, %d, %d, %d, %d} not valid for precision %d, nrhs %d",
                          info[0], info[1], info[2], info[3], info[4], info[5], precision, nrhs),
                GRG_EINVAL;
     S->tune[precision][nrhs] = t;
     return GRG_OK;
+}
+
+grg_status grg_reduced_apply(grg_schur S, int precision, int parity, const double *in, double *out,
+                             int nrhs)
+{
+    GRG_TRY(check_call(S, in, out, nrhs));
+    if (precision < 0 || precision > 2) return set_error("bad precision"), GRG_EINVAL;
+    if (parity != 0 && parity != 1) return set_error("parity must be 0 or 1"), GRG_EINVAL;
+    if (!S->lat->eo_ok) return set_error("the lattice has no even-odd form (odd extent)"), GRG_EINVAL;
+    DeviceGuard dg(S->lat->device);
+    grg_status st = reduced_apply_internal(S, precision, parity, in, out, nrhs);
+    hipError_t e = hipStreamSynchronize(S->lat->stream);
+    if (st == GRG_OK && e != hipSuccess) {
+        set_error("stream synchronise failed: %s", hipGetErrorString(e));
+        st = GRG_EHIP;
+    }
+    collect_profile(S);
+    return st;
 }
 
 grg_status grg_block_apply(grg_schur S, int precision, int rows, int cols, const double *in,

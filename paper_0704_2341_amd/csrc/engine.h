@@ -66,6 +66,7 @@ struct EoArgs {
     Geom g;               // the full lattice
     int Vh, Vhs;          // half volume, and padded to whole tiles (multiple of 256)
     int nrhs, SB, RG, hops, chunk;
+    int march;            // hops == 3: time slices per workgroup item (t-marching form)
     double *partials;     // [grid][nrhs][3] or nullptr
     const void *dot_with; // parity po
     const int *active;    // per RHS: 0 writes zero for that RHS (nullptr: all active)

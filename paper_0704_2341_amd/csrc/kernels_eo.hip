@@ -84,6 +84,247 @@ __device__ __forceinline__ void eo_hop_k(int k, cpx<R> (&acc)[12], const PT (&p)
     }
 }
 
+// t-marching form of the compact half-stencil (packed BF16).  A workgroup
+// takes 64 columns (x/2, y, z) of the half lattice and four RHS (one per
+// wavefront) and walks `march` time slices.  The t-neighbours of an output
+// site are the sites of the other parity in the same column one slice up
+// and one down, so every input site of the column is loaded once: as the
+// forward neighbour of one output and, two slices later, the backward
+// neighbour of the next.  The two slices in between wait in LDS (a per-lane
+// ring of two slots: each lane reads and writes only its own words, so no
+// barrier is needed), which keeps the register count of the one-hop loop.
+// Each XCD walks the columns of its own z-slab (an eighth of a slice), so
+// that the x, y and z neighbours, loaded by the columns next to it at nearly
+// the same time, are in its own L2.  Per-RHS sums go to red[r] (one
+// wavefront per RHS of a workgroup, so no two wavefronts share a row).
+template <int P, class OP>
+__device__ __forceinline__ void eo_march(const EoArgs &a, double (*red)[3])
+{
+    typedef typename Store<P>::S S;
+    typedef typename Store<P>::R R;
+    typedef typename OP::T PT;
+    static_assert(sizeof(PT) == 4, "the LDS ring holds packed BF16 complex words");
+    __shared__ PT ring[4][2][12][64];
+    const S *__restrict__ in = (const S *)a.in;
+    const S *__restrict__ in2 = (const S *)a.in2;
+    S *__restrict__ out = (S *)a.out;
+    const S *__restrict__ Uo = (const S *)a.U + (size_t)a.po * 36 * a.Vhs;
+    const S *__restrict__ Ui = (const S *)a.U + (size_t)(1 - a.po) * 36 * a.Vhs;
+    const uint8_t *__restrict__ mk = a.mask + (size_t)a.po * a.Vhs;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const bool dots = a.partials != nullptr;
+    const R al = (R)a.alpha, be = (R)a.beta;
+    const int Lt = a.g.L[3];
+    const int Vs3 = a.Vh / Lt;  // half-sites per time slice (a multiple of 64)
+    const int nT = Vs3 >> 6;
+    const int xcd = (int)(blockIdx.x & 7), slot = (int)(blockIdx.x >> 3), slots = (int)(gridDim.x >> 3);
+    const int T0 = (xcd * nT) >> 3, ntx = (((xcd + 1) * nT) >> 3) - T0;
+    const int nq = (a.nrhs + 3) >> 2;
+    const int ML = a.march, nc = (Lt + ML - 1) / ML;
+    const int nx = ntx * nq * nc;
+    const int nr = a.nrhs;
+    PT (*q)[12][64] = ring[wave];
+    for (int j = slot; j < nx; j += slots) {
+        const int quad = j % nq, rest = j / nq;
+        const int T = T0 + rest % ntx, ch = rest / ntx;
+        const int r = 4 * quad + wave;
+        if (r >= nr) continue;
+        const int col = T * 64 + lane;
+        const int t0 = ch * ML, t1 = min(t0 + ML, Lt);
+        // the column's input one slice below t0 and at t0: slot (t & 1)
+        // holds slice t
+        {
+            const int tm = t0 == 0 ? Lt - 1 : t0 - 1;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                q[(t0 - 1) & 1][c][lane] = OP::load(in, fidx(tm * Vs3 + col, r, c, nr));
+                q[t0 & 1][c][lane] = OP::load(in, fidx(t0 * Vs3 + col, r, c, nr));
+            }
+        }
+        double dre = 0, dim = 0, dqq = 0;
+#pragma unroll 1
+        for (int t = t0; t < t1; ++t) {
+            const int h = t * Vs3 + col;
+            const int hf = (t + 1 == Lt ? 0 : (t + 1) * Vs3) + col;
+            const int hbk = (t == 0 ? Lt - 1 : t - 1) * Vs3 + col;
+            const bool on = mk[h] == 0;
+            // the forward t-neighbour: used at the end of this slice, then
+            // kept for the output two slices up
+            PT qc[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) qc[c] = OP::load(in, fidx(hf, r, c, nr));
+            cpx<R> acc[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
+            if (on) {
+                SiteGeo sq;
+                const int s = eo_site(h, a.po, a.g, sq);
+#pragma unroll 1
+                for (int k = 0; k < 6; ++k) {
+                    PT p[12], u[9];
+                    eo_load_hop<OP>(k, p, u, in, Uo, Ui, s, h, sq, a.g, r, nr, false);
+                    eo_hop_k(k, acc, p, u);
+                }
+                {
+                    PT u[9];
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) u[e] = OP::load(Uo, lidx(h, 3, e));
+                    eo_hop_k(6, acc, qc, u);
+                }
+                {
+                    PT p[12], u[9];
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) u[e] = OP::load(Ui, lidx(hbk, 3, e));
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) p[c] = q[(t - 1) & 1][c][lane];
+                    eo_hop_k(7, acc, p, u);
+                }
+            }
+            // slice t + 1 replaces slice t - 1 (read above, by this lane only)
+#pragma unroll
+            for (int c = 0; c < 12; ++c) q[(t + 1) & 1][c][lane] = qc[c];
+            R sre = 0, sim = 0, sqq = 0;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const size_t i = fidx(h, r, c, nr);
+                cpx<R> o = {0, 0};
+                if (on) {
+                    o = {be * acc[c].re, be * acc[c].im};
+                    if (in2) {
+                        const cpx<R> v = ldr<R>(in2, i);
+                        o.re = fma(al, v.re, o.re);
+                        o.im = fma(al, v.im, o.im);
+                    }
+                }
+                stc(out, i, o);
+                if (dots && on) {
+                    const cpx<R> v = ldr<R>((const S *)a.dot_with, i);
+                    sre = fma(o.re, v.re, fma(o.im, v.im, sre));
+                    sim = fma(o.re, v.im, fma(-o.im, v.re, sim));
+                    sqq = fma(o.re, o.re, fma(o.im, o.im, sqq));
+                }
+            }
+            dre += (double)sre;
+            dim += (double)sim;
+            dqq += (double)sqq;
+        }
+        if (dots) {
+            dre = wave_sum(dre);
+            dim = wave_sum(dim);
+            dqq = wave_sum(dqq);
+            if (lane == 0) {
+                red[r][0] += dre;
+                red[r][1] += dim;
+                red[r][2] += dqq;
+            }
+        }
+    }
+}
+
+// RHS-simultaneous form of the compact half-stencil: the RS right-hand sides
+// of a work item are carried through each hop together, so that the hop's
+// link is loaded once for all of them and a wavefront has RS spinor loads
+// plus one link load in flight per hop instead of one of each.
+template <int P, class OP, int RS>
+__device__ __forceinline__ void eo_multi(const EoArgs &a, double (*red)[kMaxRhs][3])
+{
+    typedef typename Store<P>::S S;
+    typedef typename Store<P>::R R;
+    typedef typename OP::T PT;
+    const S *__restrict__ in = (const S *)a.in;
+    const S *__restrict__ in2 = (const S *)a.in2;
+    S *__restrict__ out = (S *)a.out;
+    const S *__restrict__ Uo = (const S *)a.U + (size_t)a.po * 36 * a.Vhs;
+    const S *__restrict__ Ui = (const S *)a.U + (size_t)(1 - a.po) * 36 * a.Vhs;
+    const uint8_t *__restrict__ mk = a.mask + (size_t)a.po * a.Vhs;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const bool dots = a.partials != nullptr;
+    const R al = (R)a.alpha, be = (R)a.beta;
+    const int nr = a.nrhs;
+    const int ngroups = (nr + RS - 1) / RS;
+    const int nsb = (a.Vh + a.SB - 1) / a.SB;
+    const int nitems = nsb * ngroups;
+    const int C = a.chunk > 0 ? a.chunk : (nitems + 7) / 8;
+    for (int j = blockIdx.x >> 3;; j += gridDim.x >> 3) {
+        const int w = xcd_chunk_item(j, C, nitems);
+        if (w < 0) break;
+        const int sb = w / ngroups, grp = w - sb * ngroups;
+        const int h = sb * a.SB + (int)threadIdx.x;
+        const bool valid = h < a.Vh;
+        const bool on = valid && mk[h] == 0;
+        SiteGeo q;
+        int s = 0;
+        if (on) s = eo_site(h, a.po, a.g, q);
+        const int r0 = grp * RS;
+        cpx<R> acc[RS][12];
+#pragma unroll
+        for (int k = 0; k < RS; ++k)
+#pragma unroll
+            for (int c = 0; c < 12; ++c) acc[k][c] = {0, 0};
+        if (on) {
+#pragma unroll 1
+            for (int k = 0; k < 8; ++k) {
+                const int mu = k >> 1;
+                int sp, sm;
+                nbr(s, mu, q, a.g, sp, sm);
+                const int hn = ((k & 1) ? sm : sp) >> 1;
+                const S *__restrict__ Ul = (k & 1) ? Ui : Uo;
+                const int hl = (k & 1) ? hn : h;
+                PT u[9], p[RS][12];
+#pragma unroll
+                for (int e = 0; e < 9; ++e) u[e] = OP::load(Ul, lidx(hl, mu, e));
+#pragma unroll
+                for (int jr = 0; jr < RS; ++jr) {
+                    const int r = min(r0 + jr, nr - 1);  // a ragged last group repeats the last RHS
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) p[jr][c] = OP::load(in, fidx(hn, r, c, nr));
+                }
+#pragma unroll
+                for (int jr = 0; jr < RS; ++jr) eo_hop_k(k, acc[jr], p[jr], u);
+            }
+        }
+#pragma unroll
+        for (int jr = 0; jr < RS; ++jr) {
+            const int r = r0 + jr;
+            if (r >= nr) break;
+            R sre = 0, sim = 0, sqq = 0;
+            const bool act = a.active == nullptr || a.active[r] != 0;
+            if (valid) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    const size_t i = fidx(h, r, c, nr);
+                    cpx<R> o = {0, 0};
+                    if (on && act) {
+                        o = {be * acc[jr][c].re, be * acc[jr][c].im};
+                        if (in2) {
+                            const cpx<R> v = ldr<R>(in2, i);
+                            o.re = fma(al, v.re, o.re);
+                            o.im = fma(al, v.im, o.im);
+                        }
+                    }
+                    stc(out, i, o);
+                    if (dots && on) {
+                        const cpx<R> v = ldr<R>((const S *)a.dot_with, i);
+                        sre = fma(o.re, v.re, fma(o.im, v.im, sre));
+                        sim = fma(o.re, v.im, fma(-o.im, v.re, sim));
+                        sqq = fma(o.re, o.re, fma(o.im, o.im, sqq));
+                    }
+                }
+            }
+            if (dots) {
+                const double dre = wave_sum((double)sre);
+                const double dim = wave_sum((double)sim);
+                const double dqq = wave_sum((double)sqq);
+                if (lane == 0) {
+                    red[wave][r][0] += dre;
+                    red[wave][r][1] += dim;
+                    red[wave][r][2] += dqq;
+                }
+            }
+        }
+    }
+}
+
 // out = alpha in2 + beta (H in) on the rest sites of parity po (zero on its
 // coarse sites); in has parity 1 - po, in2 and out parity po.  With partials,
 // also the per-workgroup sums conj(out).w (re, im) and |out|^2 per RHS,
@@ -114,6 +355,13 @@ __global__ void __launch_bounds__(256) eo_hop_kernel(EoArgs a)
         for (int i = lane; i < a.nrhs * 3; i += 64) red[wave][i / 3][i % 3] = 0.0;
         __syncthreads();
     }
+    if constexpr (HOPS == 3) {
+        static_assert(IO == 0 && OP::kPacked, "t-marching form: packed compact fields only");
+        eo_march<P, OP>(a, red[0]);
+    } else if constexpr (HOPS >= 4) {
+        static_assert(IO == 0, "RHS-simultaneous form: compact fields only");
+        eo_multi<P, OP, HOPS - 2>(a, red);
+    } else {
     const R al = (R)a.alpha, be = (R)a.beta;
     const bool inf = in_full;
     const int ngroups = (a.nrhs + a.RG - 1) / a.RG;
@@ -197,6 +445,7 @@ __global__ void __launch_bounds__(256) eo_hop_kernel(EoArgs a)
             }
         }
     }
+    }
     if (dots) {
         __syncthreads();
         const int nw = blockDim.x >> 6;
@@ -275,6 +524,21 @@ hipError_t launch_eo_hop(int prec, const EoArgs &a, int grid, hipStream_t st)
     else if (a.in_full || a.in2_full || a.out_full) return hipErrorInvalidValue;
     dim3 blk(a.SB), grd(grid);
     const bool pipe = a.hops == 2 && prec == GRG_BF16 && io == 0;
+    if (a.hops == 3 && io == 0) {
+        // t-marching: packed BF16, 256 threads, whole 64-column tiles per slice
+        if (prec != GRG_BF16 || a.SB != 256 || a.march < 1 || a.g.L[3] < 2 || a.Vh % a.g.L[3] ||
+            (a.Vh / a.g.L[3]) % 64)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL((eo_hop_kernel<GRG_BF16, 3, 0>), grd, blk, 0, st, a);
+        return hipGetLastError();
+    }
+    if ((a.hops == 4 || a.hops == 5) && io == 0) {
+        // RHS-simultaneous: packed BF16, RG = 2 or 3 right-hand sides per hop
+        if (prec != GRG_BF16 || a.RG != a.hops - 2) return hipErrorInvalidValue;
+        if (a.hops == 4) hipLaunchKernelGGL((eo_hop_kernel<GRG_BF16, 4, 0>), grd, blk, 0, st, a);
+        else hipLaunchKernelGGL((eo_hop_kernel<GRG_BF16, 5, 0>), grd, blk, 0, st, a);
+        return hipGetLastError();
+    }
 #define EOH(PP, H, IO) hipLaunchKernelGGL((eo_hop_kernel<PP, H, IO>), grd, blk, 0, st, a)
 #define EOIO(PP)                   \
     if (io == 1) EOH(PP, 1, 1);    \

@@ -519,6 +519,7 @@ static grg_status eo_hop(grg_schur S, int prec, const DslashTune &t, const void 
     a.RG = t.RG;
     a.hops = t.split;
     a.chunk = t.chunk;
+    a.march = t.march;
     a.partials = partials;
     a.dot_with = dot_with;
     a.active = active;
@@ -541,9 +542,16 @@ static grg_status eo_hop(grg_schur S, int prec, const DslashTune &t, const void 
 
 bool eo_launch_ok(const Geom &gh, int prec, int nrhs, const DslashTune &t)
 {
+    // split 3: the t-marching form (its full-layout steps run the one-hop
+    // form with SB and RG)
+    const int Lt = gh.L[3];
+    const bool march_ok = t.split == 3 && prec == GRG_BF16 && t.SB == 256 && t.march >= 1 &&
+                          t.march <= Lt && Lt >= 2 && gh.V % Lt == 0 && (gh.V / Lt) % 64 == 0;
+    // split 4, 5: RG = 2, 3 right-hand sides carried through each hop together
+    const bool multi_ok = (t.split == 4 || t.split == 5) && prec == GRG_BF16 && t.RG == t.split - 2;
     return (t.SB == 64 || t.SB == 128 || t.SB == 256) && t.RG >= 1 && t.RG <= nrhs &&
-           (t.split == 1 || (t.split == 2 && prec == GRG_BF16)) && t.grid >= 8 && t.grid % 8 == 0 &&
-           t.grid <= kMaxGridValue && t.chunk >= 0 && gh.V > 0;
+           (t.split == 1 || (t.split == 2 && prec == GRG_BF16) || march_ok || multi_ok) && t.grid >= 8 &&
+           t.grid % 8 == 0 && t.grid <= kMaxGridValue && t.chunk >= 0 && t.march >= 0 && gh.V > 0;
 }
 
 // Autotuner of the reduced operator's half-stencil (timed as the solver runs
@@ -579,7 +587,8 @@ grg_status tune_eo(grg_schur S, int prec, int nrhs, int reps)
     for (int sb : {64, 128, 256}) {
         for (int rg = 1; rg <= nrhs; ++rg) {
             if ((nrhs % rg && rg != nrhs) || (rg > 4 && rg != nrhs)) continue;
-            for (int hops = 1; hops <= (prec == GRG_BF16 ? 2 : 1); ++hops) {
+            for (int hops = 1; hops <= (prec == GRG_BF16 ? 5 : 1); ++hops) {
+                if (hops == 3 || (hops >= 4 && rg != hops - 2)) continue;
                 DslashTune t = default_eo_tune(gh, prec, nrhs);
                 t.SB = sb;
                 t.RG = rg;
@@ -610,6 +619,29 @@ grg_status tune_eo(grg_schur S, int prec, int nrhs, int reps)
                 t.grid = round8(std::min<long>(items, cap));
                 t.chunk = ch;
                 if (ch > 0 && ch * 8 >= items) continue;
+                timeit(t);
+                if (t.ms < best.ms) best = t;
+            }
+        }
+    }
+    // the t-marching form: time slices per item, and grids of one, a half
+    // and a quarter workgroup per item of the largest XCD share
+    if (prec == GRG_BF16 && !cands.empty()) {
+        const int Lt = gh.L[3];
+        std::vector<int> mls;
+        for (int ml : {Lt, Lt / 2, Lt / 4})
+            if (ml >= 1 && std::find(mls.begin(), mls.end(), ml) == mls.end()) mls.push_back(ml);
+        for (int ml : mls) {
+            DslashTune t = cands[0];
+            t.SB = 256;
+            t.split = 3;
+            t.march = ml;
+            t.chunk = 0;
+            const long nT = gh.V / Lt / 64;
+            const long nx = (nT + 7) / 8 * ((nrhs + 3) / 4) * ((Lt + ml - 1) / ml);
+            for (long div : {1, 2, 4}) {
+                t.grid = round8(std::min<long>(8 * nx / div, kMaxGridValue));
+                if (!eo_launch_ok(gh, prec, nrhs, t)) continue;
                 timeit(t);
                 if (t.ms < best.ms) best = t;
             }
@@ -1064,6 +1096,30 @@ grg_status block_apply_internal(grg_schur S, int prec, int rows, int cols, const
                                    cols));
     GRG_TRY(run_dslash(S, prec, a, b, rows, nrhs, nullptr));
     GRG_TRY_HIP(launch_unpack_spinor(prec, b, out, L->g, nrhs, L->stream));
+    return GRG_OK;
+}
+
+// out = (d - H_pq H_qp / d) in on the rest sites of parity p (canonical
+// fields, device)
+grg_status reduced_apply_internal(grg_schur S, int prec, int parity, const double *in, double *out,
+                                  int nrhs)
+{
+    grg_lattice L = S->lat;
+    hipStream_t st = L->stream;
+    GRG_TRY(ensure_inner(S, prec));
+    GRG_TRY(ensure_eo(S, prec));
+    const Geom gh = half_geom(L);
+    const DslashTune t = S->eotune[prec][nrhs].valid ? S->eotune[prec][nrhs]
+                                                     : default_eo_tune(gh, prec, nrhs);
+    const double d = 4.0 + S->m0;
+    void **f = S->eo_f[prec];
+    void *a = S->in_b[prec], *b = S->in_q[prec];
+    GRG_TRY_HIP(launch_pack_spinor(prec, in, a, L->g, nrhs, st, S->d_mask, 0));
+    GRG_TRY_HIP(launch_eo_scatter(prec, L->g, nrhs, parity, a, f[0], false, st));
+    GRG_TRY(eo_hop(S, prec, t, f[0], nullptr, f[3], 1 - parity, 0.0, 1.0, nrhs, nullptr, nullptr));
+    GRG_TRY(eo_hop(S, prec, t, f[3], f[0], f[2], parity, d, -1.0 / d, nrhs, nullptr, nullptr));
+    GRG_TRY_HIP(launch_eo_scatter(prec, L->g, nrhs, parity, f[2], b, true, st));
+    GRG_TRY_HIP(launch_unpack_spinor(prec, b, out, L->g, nrhs, st));
     return GRG_OK;
 }
 

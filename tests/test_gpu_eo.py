@@ -95,3 +95,65 @@ def test_tuned_reduced_solve_same_result():
     assert rel_err(y1[:1], want) < 1e-10
     s.close()
     lat.close()
+
+
+RA_TOL = {"fp64": 1e-13, "fp32": 2e-6, "bf16": 1.5e-2}
+# half-lattice stencil launches {SB, RG, hop schedule, grid, chunk, time slices}:
+# one hop per iteration, double-buffered hops, and the t-marching form (whole
+# t range, ragged time chunks, a grid smaller than the work items)
+RA_LAUNCHES = {
+    "one-hop": (256, 2, 1, 64, 0, 0),
+    "double-buffered": (128, 3, 2, 56, 4, 0),
+    "march-all-t": (256, 3, 3, 64, 0, 8),
+    "march-ragged-chunks": (256, 1, 3, 24, 0, 3),
+    "march-small-grid": (256, 3, 3, 8, 0, 2),
+    "two-rhs-per-hop": (128, 2, 4, 48, 0, 0),
+    "three-rhs-per-hop": (64, 3, 5, 40, 8, 0),
+}
+
+
+@pytest.mark.parametrize("form", list(RA_LAUNCHES))
+@pytest.mark.parametrize("prec", ["bf16", "fp32", "fp64"])
+@pytest.mark.parametrize("nrhs", [5, 12])
+def test_reduced_apply_vs_oracle(form, prec, nrhs):
+    """A_p = d - H_pq H_qp / d on both parities, every launch form of the
+    half-lattice stencils, against the oracle's Schur complement of D_rr."""
+    launch = RA_LAUNCHES[form]
+    if launch[2] >= 2 and prec != "bf16":
+        pytest.skip("packed-BF16 hop schedules")
+    dims = (16, 8, 8, 8)  # 512 half-sites per time slice: whole 64-column tiles
+    lat = Lattice(dims, 0.5, 25)
+    s = lat.schur(-0.3, "I", False, tol=1e-10, inner=prec, max_rhs=12)
+    grg = lat.grg
+    grg.grg_schur_set_launch(s.h, prec, nrhs, launch, eo=True)
+    assert grg.grg_schur_tune_info(s.h, prec, nrhs, eo=True)["split"] == launch[2]
+    x = gaussian_vectors(12 * lat.V, nrhs, 25)
+    import torch
+
+    from gpu_support import to_dev, to_host
+
+    xd = to_dev(x)
+    yd = torch.empty_like(xd)
+    for parity in (0, 1):
+        print(f"reduced apply {form} {prec} nrhs {nrhs} parity {parity}", flush=True)
+        grg.grg_reduced_apply(s.h, prec, parity, xd, yd, nrhs)
+        y = to_host(yd)
+        want = matfree.reduced_apply(lat.links, dims, -0.3, s.q, s.nb, parity, x)
+        assert rel_err(y, want) < RA_TOL[prec]
+        # zero off the parity's rest sites
+        par = matfree.site_parity(dims)
+        off = (par != parity)
+        off[np.asarray(s.q[: s.nb])] = True
+        assert not np.any(y.reshape(nrhs, lat.V, 12)[:, off])
+    s.close()
+    lat.close()
+
+
+def test_march_launch_rejected_without_whole_tiles():
+    """The t-marching form needs a multiple of 64 half-sites per time slice."""
+    lat = Lattice((8, 6, 4, 10), 0.5, 26)
+    s = lat.schur(-0.1, "II", False, tol=1e-10, inner="bf16", max_rhs=2)
+    with pytest.raises(lat.grg.GrgError):
+        lat.grg.grg_schur_set_launch(s.h, "bf16", 2, (256, 1, 3, 8, 0, 5), eo=True)
+    s.close()
+    lat.close()

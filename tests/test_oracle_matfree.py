@@ -83,3 +83,24 @@ def test_restart_does_not_change_the_answer(setup4):
     y1, _, _ = matfree.schur_apply(u, dims, 0.1, q, nb, xb, restart=1, tol=1e-13)
     y2, _, _ = matfree.schur_apply(u, dims, 0.1, q, nb, xb, restart=16, tol=1e-13)
     assert np.linalg.norm(y1 - y2) < 1e-11 * np.linalg.norm(y1)
+
+
+@pytest.mark.parametrize("kind,inv", PERMS)
+@pytest.mark.parametrize("parity", [0, 1])
+def test_reduced_apply_is_dense_schur_complement(setup4, kind, inv, parity):
+    """The even-odd reduced operator against the Schur complement of the
+    dense D_rr on the two parities' rest sites, D_pp - D_pq D_qq^{-1} D_qp,
+    with D_qq inverted as a matrix (nothing assumed about its form)."""
+    dims, u, d = setup4
+    q, nb = dense.permutation_block(dims, kind, inv)
+    rest = np.ones(256, bool)
+    rest[q[:nb]] = False
+    par = np.array([sum(dense.coords(s, dims)) % 2 for s in range(256)])
+    ip = np.flatnonzero(np.repeat(rest & (par == parity), 12))
+    iq = np.flatnonzero(np.repeat(rest & (par != parity), 12))
+    a = d[np.ix_(ip, ip)] - d[np.ix_(ip, iq)] @ np.linalg.solve(d[np.ix_(iq, iq)], d[np.ix_(iq, ip)])
+    x = gaussian_vectors(12 * 256, 2, 5)
+    got = matfree.reduced_apply(u, dims, 0.1, q, nb, parity, x)
+    want = np.zeros_like(x)
+    want[:, ip] = (a @ x[:, ip].T).T
+    assert np.abs(got - want).max() < 1e-12 * np.abs(want).max()
