@@ -55,6 +55,90 @@ __device__ __forceinline__ void ptc_hop_site(int s, int h, const Geom &g, int &n
     ls = fwd ? s : sm;
 }
 
+// One gather task's operands: the raw link of the hop and the FH channels'
+// colour vectors of the neighbour.
+template <int FH>
+struct GatherOps {
+    uint32_t m[9];
+    uint32_t v[FH][3];
+};
+
+template <int FIN, int FH>
+__device__ __forceinline__ void ptc_task_load(int task, int h0, const bf16x2 *__restrict__ x,
+                                              const bf16x2 *__restrict__ U, const Geom &g, int sc,
+                                              int r, int nrhs, GatherOps<FH> &o)
+{
+    const int h = h0 + (task >> 1), f0 = (task & 1) * FH;
+    int n, ls;
+    ptc_hop_site(sc, h, g, n, ls);
+    if (h > 0) {
+        const int mu = (h - 1) >> 1;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) o.m[e] = U[lidx(ls, mu, e)];
+    }
+#pragma unroll
+    for (int i = 0; i < FH; ++i) {
+        const int f = min(f0 + i, FIN - 1);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) o.v[i][a] = x[aidx(n, r, 3 * f + a, nrhs, 3 * FIN)];
+    }
+}
+
+template <int FIN, int FH, bool ROWK, int LD>
+__device__ __forceinline__ void ptc_task_store(int task, int h0, const GatherOps<FH> &o, bool valid,
+                                               int lane, __bf16 *lds, int kbase)
+{
+    const int h = h0 + (task >> 1), f0 = (task & 1) * FH, f1 = min(f0 + FH, FIN);
+    const bool fwd = h > 0 && ((h - 1) & 1) == 0;
+    // link forms, fr[3a + b] and fi[3a + b] for output colour a
+    uint32_t fr[9], fi[9];
+    if (h > 0) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const uint32_t m = o.m[fwd ? 3 * a + b : 3 * b + a];
+                fr[3 * a + b] = fwd ? m ^ kNegHi : m;
+                fi[3 * a + b] = fwd ? swap_halves(m) : swap_halves(m) ^ kNegLo;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < FH; ++i) {
+        const int f = f0 + i;
+        if (f >= f1) break;
+        uint32_t w[3];
+        if (h == 0) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) w[a] = o.v[i][a];
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                float re = 0.f, im = 0.f;
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    re = dot2bf(fr[3 * a + b], o.v[i][b], re);
+                    im = dot2bf(fi[3 * a + b], o.v[i][b], im);
+                }
+                w[a] = pack_bf16(re, im);
+            }
+        }
+        const int k0 = (h * FIN + f) * 2 - kbase;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int col = lane * 3 + a;
+            const uint32_t word = valid ? w[a] : 0u;
+            if (ROWK) {
+                // (re, im) adjacent in a row: one 32-bit store (k0 even, LD even)
+                *(uint32_t *)(lds + col * LD + k0) = word;
+            } else {
+                lds[k0 * LD + col] = __builtin_bit_cast(__bf16, (uint16_t)(word & 0xffffu));
+                lds[(k0 + 1) * LD + col] = __builtin_bit_cast(__bf16, (uint16_t)(word >> 16));
+            }
+        }
+    }
+}
+
 // Phase 1: T_h X_f' for the 64 sites of a tile into LDS.  Row-major layout
 // B[row][col]: ROWK = true puts the (hop, f', re/im) index contiguous (rows =
 // (site, colour)), ROWK = false puts the (site, colour) index contiguous.
@@ -65,7 +149,9 @@ __device__ __forceinline__ void ptc_hop_site(int s, int h, const Geom &g, int &n
 // and (m.re, m.im), (-m.im, m.re) for U^+ x, made once per hop and shared by
 // the channels.  The work is split over the four wavefronts as (hop, half of
 // the channels) tasks, two per hop of the range [h0, h1); the (hop, f', re/im)
-// index is stored relative to kbase.
+// index is stored relative to kbase.  A wavefront loads its next task's
+// operands before it transports the current one, so that the memory latency
+// of its tasks overlaps.
 template <int FIN, bool ROWK, int LD>
 __device__ __forceinline__ void ptc_gather(const bf16x2 *__restrict__ x, const bf16x2 *__restrict__ U,
                                            const Geom &g, int tile, int r, int nrhs,
@@ -76,57 +162,22 @@ __device__ __forceinline__ void ptc_gather(const bf16x2 *__restrict__ x, const b
     const int s = tile * 64 + lane;
     const bool valid = s < g.V;
     const int sc = valid ? s : 0;
-    for (int task = wv; task < 2 * (h1 - h0); task += 4) {
-        const int h = h0 + (task >> 1), f0 = (task & 1) * FH, f1 = min(f0 + FH, FIN);
-        int n, ls;
-        ptc_hop_site(sc, h, g, n, ls);
-        const int mu = h == 0 ? 0 : (h - 1) >> 1;
-        const bool fwd = h > 0 && ((h - 1) & 1) == 0;
-        uint32_t fr[9], fi[9];  // link forms, fr[3a + b] and fi[3a + b] for output colour a
-        if (h > 0) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    const uint32_t m = U[lidx(ls, mu, fwd ? 3 * a + b : 3 * b + a)];
-                    fr[3 * a + b] = fwd ? m ^ kNegHi : m;
-                    fi[3 * a + b] = fwd ? swap_halves(m) : swap_halves(m) ^ kNegLo;
-                }
-            }
-        }
-        for (int f = f0; f < f1; ++f) {
-            uint32_t v[3], w[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) v[a] = x[aidx(n, r, 3 * f + a, nrhs, 3 * FIN)];
-            if (h == 0) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) w[a] = v[a];
-            } else {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    float re = 0.f, im = 0.f;
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) {
-                        re = dot2bf(fr[3 * a + b], v[b], re);
-                        im = dot2bf(fi[3 * a + b], v[b], im);
-                    }
-                    w[a] = pack_bf16(re, im);
-                }
-            }
-            const int k0 = (h * FIN + f) * 2 - kbase;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const int col = lane * 3 + a;
-                const uint32_t word = valid ? w[a] : 0u;
-                if (ROWK) {
-                    // (re, im) adjacent in a row: one 32-bit store (k0 even, LD even)
-                    *(uint32_t *)(lds + col * LD + k0) = word;
-                } else {
-                    lds[k0 * LD + col] = __builtin_bit_cast(__bf16, (uint16_t)(word & 0xffffu));
-                    lds[(k0 + 1) * LD + col] = __builtin_bit_cast(__bf16, (uint16_t)(word >> 16));
-                }
-            }
-        }
+    const int ntask = 2 * (h1 - h0);
+    int task = wv;
+    if (task >= ntask) return;
+    GatherOps<FH> A, B;
+    ptc_task_load<FIN, FH>(task, h0, x, U, g, sc, r, nrhs, A);
+    for (;;) {
+        const bool more = task + 4 < ntask;
+        if (more) ptc_task_load<FIN, FH>(task + 4, h0, x, U, g, sc, r, nrhs, B);
+        ptc_task_store<FIN, FH, ROWK, LD>(task, h0, A, valid, lane, lds, kbase);
+        if (!more) break;
+        task += 4;
+        const bool more2 = task + 4 < ntask;
+        if (more2) ptc_task_load<FIN, FH>(task + 4, h0, x, U, g, sc, r, nrhs, A);
+        ptc_task_store<FIN, FH, ROWK, LD>(task, h0, B, valid, lane, lds, kbase);
+        if (!more2) break;
+        task += 4;
     }
 }
 
@@ -149,10 +200,12 @@ __global__ void __launch_bounds__(256) ptc_layer_kernel(PtcLayerArgs a)
     for (int i = threadIdx.x; i < 192 * (KP - KR); i += blockDim.x)
         lds[(i / (KP - KR)) * LD + (KR - K1) + i % (KP - KR)] = (__bf16)0.f;
     // this lane's weight fragments: A[l%16][32 s + 8 (l/16) + j]
-    bf16x8_v af[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
-        af[s] = *(const bf16x8_v *)(a.A + (lane & 15) * KP + 32 * s + 8 * (lane >> 4));
+    // the embedded weights A[16][KP] in LDS (read per MFMA step rather than
+    // held in registers: the gather's double-buffered operands need them)
+    __shared__ __attribute__((aligned(16))) __bf16 wl[16 * KP];
+    for (int i = threadIdx.x; i < 16 * KP / 8; i += blockDim.x)
+        *(bf16x8_v *)(wl + 8 * i) = *(const bf16x8_v *)(a.A + 8 * i);
+    const __bf16 *arow = wl + (lane & 15) * KP + 8 * (lane >> 4);
     const bf16x2 *x = (const bf16x2 *)a.x;
     bf16x2 *y = (bf16x2 *)a.y;
     const bf16x2 *U = (const bf16x2 *)a.U;
@@ -176,7 +229,8 @@ __global__ void __launch_bounds__(256) ptc_layer_kernel(PtcLayerArgs a)
 #pragma unroll
                 for (int s = (pass == 0 ? 0 : NS1); s < (pass == 0 ? NS1 : NS); ++s) {
                     const bf16x8_v bf = *(const bf16x8_v *)(brow + 32 * (s - (pass == 0 ? 0 : NS1)));
-                    c[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[s], bf, c[i], 0, 0, 0);
+                    const bf16x8_v af = *(const bf16x8_v *)(arow + 32 * s);
+                    c[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, c[i], 0, 0, 0);
                 }
             }
         }
