@@ -213,6 +213,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 48-lattice batch leg")
     ap.add_argument("--no-reusken", action="store_true", help="skip the section 3 approximation leg")
     ap.add_argument("--train-steps", type=int, default=1667, help="12-pair Adam steps (1667 = 20k pairs)")
+    ap.add_argument("--eo-launch", default="", metavar="SB,RG,SPLIT,GRID,CHUNK,MARCH",
+                    help="pin the half-lattice stencil's launch after tuning")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain copy kernel of MIB MiB (for counter calibration)")
     args = ap.parse_args()
@@ -258,6 +260,11 @@ def main():
             f"fp64 {grg.grg_schur_tune_info(s, 'fp64', nrhs)}, "
             f"even-odd {grg.grg_schur_tune_info(s, args.inner, nrhs, eo=True)}, "
             f"defect correction {grg.grg_schur_dc_launch_info(s, args.inner, nrhs)}")
+    if args.eo_launch:
+        # pin the half-lattice stencil (runs that must time the same launch,
+        # such as the two counter passes of one traffic measurement)
+        grg.grg_schur_set_launch(s, args.inner, nrhs, [int(v) for v in args.eo_launch.split(",")], eo=True)
+        log(f"even-odd launch pinned: {grg.grg_schur_tune_info(s, args.inner, nrhs, eo=True)}")
     log(f"timing {args.inner} path: warmup {args.warmup}, steps {args.steps}")
     dt, stats, prof = time_applies(grg, s, xb, yb, nrhs, args.steps, args.warmup, True)
     y_mixed = yb.cpu().numpy()
