@@ -198,6 +198,17 @@ grg_status grg_reusken_apply(grg_schur s, const double *x_b, double *y_b, int nr
 /* Dense S~_bb (host, column-major complex128), as grg_schur_assemble. */
 grg_status grg_reusken_assemble(grg_schur s, double *S, size_t cap_bytes);
 
+/* The approximation that section 3 contrasts with the second-order one:
+ * the couplings inside D_rr ignored, which keeps the sparsity pattern of the
+ * coarse operator (it couples coarse sites at most two fine hops apart):
+ *     S0_bb = D_bb - D_br d^{-1} D_rb,   d = 4 + m0, the diagonal of D_rr.
+ * y_b = S0_bb x_b for nrhs coarse-space fields (device, layout as
+ * grg_schur_apply), in FP64: two stencil launches, no solve.  GRG_EINVAL if
+ * 4 + m0 = 0.  Uses the handle's workspaces. */
+grg_status grg_diag_schur_apply(grg_schur s, const double *x_b, double *y_b, int nrhs);
+/* The dense S0_bb, as grg_schur_assemble. */
+grg_status grg_diag_schur_assemble(grg_schur s, double *S, size_t cap_bytes);
+
 /* Autotuner: time every candidate launch shape of the stencil (sites per
  * workgroup, right-hand sides per thread, hop grouping, grid size) for nrhs
  * right-hand sides, in FP64 and in the inner precision, and of the fused

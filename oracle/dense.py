@@ -211,3 +211,11 @@ def reusken_dense(d: np.ndarray, q, n_b: int) -> np.ndarray:
     """S~_bb = D_bb - D_br M D_rb (section 3)."""
     dbb, dbr, drb, drr = blocks(d, q, n_b)
     return dbb - dbr @ reusken_inverse(drr) @ drb
+
+
+def diag_schur_dense(d: np.ndarray, q, n_b: int) -> np.ndarray:
+    """The Schur complement with D_rr replaced by its diagonal (the older
+    approximation section 3 contrasts with, which ignores the couplings inside
+    D_rr and keeps the coarse operator's sparsity): D_bb - D_br diag(D_rr)^{-1} D_rb."""
+    dbb, dbr, drb, drr = blocks(d, q, n_b)
+    return dbb - dbr @ (drb / np.diag(drr)[:, None])

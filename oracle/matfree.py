@@ -167,3 +167,20 @@ def reduced_apply(links, dims, m0, q, nb, parity, x, bc=(1, 1, 1, -1)):
     z = xp.reshape(nrhs, v, 12) - y * on_q / (4.0 + m0)
     out = block_apply(links, dims, m0, q, nb, 0, 0, z.reshape(nrhs, -1), bc).reshape(nrhs, v, 12)
     return (out * on_p).reshape(nrhs, -1)
+
+
+def diag_schur_apply(links, dims, m0, q, nb, xb, bc=(1, 1, 1, -1)):
+    """D_bb x_b - D_br (D_rb x_b) / d with d = 4 + m0, the diagonal of D_rr:
+    u = x_b on the coarse sites, y = D_rb u, y_b = [D (u - y / d)]_b.
+    Returns (nrhs, 12 nb)."""
+    v = int(np.prod(dims))
+    q = np.asarray(q)
+    xb = _fields(xb, 12 * int(nb))
+    nrhs = xb.shape[0]
+    u = np.zeros((nrhs, v, 12), np.complex128)
+    u[:, q[:nb]] = xb.reshape(nrhs, nb, 12)
+    u = u.reshape(nrhs, 12 * v)
+    y = block_apply(links, dims, m0, q, nb, 0, 1, u, bc)
+    w = u - y / (4.0 + m0)
+    out = dirac_apply(links, dims, m0, w, bc).reshape(nrhs, v, 12)
+    return out[:, q[:nb]].reshape(nrhs, -1)

@@ -39,7 +39,7 @@ EXPORTS = (
     "grg_lattice_destroy", "grg_lattice_volume", "grg_gauge_set", "grg_permutation_block",
     "grg_dirac_apply", "grg_schur_create", "grg_schur_destroy", "grg_schur_set_params",
     "grg_drr_solve", "grg_schur_apply", "grg_schur_assemble", "grg_reusken_apply",
-    "grg_reusken_assemble", "grg_schur_tune",
+    "grg_reusken_assemble", "grg_diag_schur_apply", "grg_diag_schur_assemble", "grg_schur_tune",
     "grg_schur_tune_info", "grg_schur_set_launch", "grg_schur_dc_launch_info",
     "grg_schur_set_dc_launch", "grg_block_apply", "grg_reduced_apply", "grg_precond_create",
     "grg_precond_destroy", "grg_precond_set_weights", "grg_precond_get_weights", "grg_precond_apply",
@@ -133,6 +133,8 @@ def load():
         "grg_schur_assemble": (C.c_int, [vp, vp, C.c_size_t]),
         "grg_reusken_apply": (C.c_int, [vp, vp, vp, C.c_int]),
         "grg_reusken_assemble": (C.c_int, [vp, vp, C.c_size_t]),
+        "grg_diag_schur_apply": (C.c_int, [vp, vp, vp, C.c_int]),
+        "grg_diag_schur_assemble": (C.c_int, [vp, vp, C.c_size_t]),
         "grg_schur_tune": (C.c_int, [vp, C.c_int]),
         "grg_schur_tune_info": (C.c_int, [vp, C.c_int, C.c_int, i32p, C.POINTER(C.c_float)]),
         "grg_schur_set_launch": (C.c_int, [vp, C.c_int, C.c_int, i32p]),
@@ -309,6 +311,20 @@ def grg_reusken_assemble(s, n_coarse):
     n = 12 * int(n_coarse)
     buf = np.zeros(n * n, dtype=np.complex128)
     _check(load().grg_reusken_assemble(s, C.c_void_p(buf.ctypes.data), buf.nbytes))
+    return buf.reshape(n, n).T  # column-major storage
+
+
+def grg_diag_schur_apply(s, x_b, y_b, nrhs):
+    """y_b = (D_bb - D_br D_rb / d) x_b, the approximation that ignores the
+    couplings inside D_rr (FP64, no solve)."""
+    _check(load().grg_diag_schur_apply(s, _ptr(x_b), _ptr(y_b), int(nrhs)))
+
+
+def grg_diag_schur_assemble(s, n_coarse):
+    """Dense D_bb - D_br D_rb / d as a numpy complex128 (12 N_b, 12 N_b) array."""
+    n = 12 * int(n_coarse)
+    buf = np.zeros(n * n, dtype=np.complex128)
+    _check(load().grg_diag_schur_assemble(s, C.c_void_p(buf.ctypes.data), buf.nbytes))
     return buf.reshape(n, n).T  # column-major storage
 
 

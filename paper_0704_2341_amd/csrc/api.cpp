@@ -41,6 +41,7 @@ grg_status reduced_apply_internal(grg_schur S, int prec, int parity, const doubl
                                   int nrhs);
 grg_status tune_dslash(grg_schur S, int prec, int nrhs, int reps);
 grg_status reusken_apply_internal(grg_schur S, const double *xb, double *yb, int nrhs);
+grg_status diag_schur_apply_internal(grg_schur S, const double *xb, double *yb, int nrhs);
 grg_status tune_dc(grg_schur S, int prec, int nrhs, int reps);
 grg_status tune_eo(grg_schur S, int prec, int nrhs, int reps);
 DslashTune default_eo_tune(const Geom &gh, int prec, int nrhs);
@@ -577,9 +578,25 @@ grg_status grg_reusken_apply(grg_schur S, const double *x_b, double *y_b, int nr
     return finish_call(S, st, t0, nullptr, before);
 }
 
+grg_status grg_diag_schur_apply(grg_schur S, const double *x_b, double *y_b, int nrhs)
+{
+    GRG_TRY(check_call(S, x_b, y_b, nrhs));
+    if (4.0 + S->m0 == 0.0) return set_error("4 + m0 = 0: D_rr has a zero diagonal"), GRG_EINVAL;
+    DeviceGuard dg(S->lat->device);
+    const auto t0 = clk::now();
+    double before = 0;
+    for (int p = 0; p < 6; ++p) before += S->prof.total_ms[p];
+    S->n_dslash = 0;
+    grg_status st = diag_schur_apply_internal(S, x_b, y_b, nrhs);
+    return finish_call(S, st, t0, nullptr, before);
+}
+
+enum AssembleKind { kExact, kSecondOrder, kDiagonal };
+
 // Dense coarse operator from its applies to unit vectors, max_rhs columns at
-// a time.  exact: S_bb (solves), else the section 3 approximation.
-static grg_status assemble(grg_schur S, double *out, size_t cap_bytes, bool exact)
+// a time: S_bb (solves), the section 3 approximation, or the one that
+// ignores the couplings inside D_rr.
+static grg_status assemble(grg_schur S, double *out, size_t cap_bytes, AssembleKind kind)
 {
     if (!S || !out) return set_error("null argument"), GRG_EINVAL;
     const size_t n = (size_t)12 * S->nb;
@@ -601,8 +618,9 @@ static grg_status assemble(grg_schur S, double *out, size_t cap_bytes, bool exac
         for (int k = 0; k < cnt; ++k) unit[((size_t)k * n + j0 + k) * 2] = 1.0;
         GRG_TRY_HIP(hipMemcpyAsync(S->cb_in, unit.data(), n * 16 * cnt, hipMemcpyHostToDevice, st));
         grg_solver_stats sst;
-        grg_status s = exact ? grg_schur_apply(S, S->cb_in, S->cb_out, cnt, &sst)
-                             : grg_reusken_apply(S, S->cb_in, S->cb_out, cnt);
+        grg_status s = kind == kExact        ? grg_schur_apply(S, S->cb_in, S->cb_out, cnt, &sst)
+                       : kind == kSecondOrder ? grg_reusken_apply(S, S->cb_in, S->cb_out, cnt)
+                                              : grg_diag_schur_apply(S, S->cb_in, S->cb_out, cnt);
         if (s != GRG_OK && s != GRG_ENOCONV) return s;
         if (s == GRG_ENOCONV) worst = s;
         // column j0 + k of the column-major matrix is output vector k
@@ -613,12 +631,17 @@ static grg_status assemble(grg_schur S, double *out, size_t cap_bytes, bool exac
 
 grg_status grg_schur_assemble(grg_schur S, double *out, size_t cap_bytes)
 {
-    return assemble(S, out, cap_bytes, true);
+    return assemble(S, out, cap_bytes, kExact);
 }
 
 grg_status grg_reusken_assemble(grg_schur S, double *out, size_t cap_bytes)
 {
-    return assemble(S, out, cap_bytes, false);
+    return assemble(S, out, cap_bytes, kSecondOrder);
+}
+
+grg_status grg_diag_schur_assemble(grg_schur S, double *out, size_t cap_bytes)
+{
+    return assemble(S, out, cap_bytes, kDiagonal);
 }
 
 grg_status grg_schur_tune(grg_schur S, int nrhs)

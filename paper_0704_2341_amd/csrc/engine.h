@@ -182,7 +182,8 @@ hipError_t launch_axpy_convert(int prec_in, int prec_out, const BlasShape &sh, c
 // y = x - y (FP64), used for u - z
 hipError_t launch_xmy(const BlasShape &sh, const void *x, void *y, hipStream_t st);
 // Second-order Schur complement approximation (kernels_blas.hip): the
-// rest-site ones field, t = y / d~ and w = u - ((y - z) / d + t).
+// rest-site ones field, t = y / d~ and w = u - ((y - z) / d + t) (z, t
+// nullable: zero; w = u - y / d is the approximation that ignores D_rr).
 hipError_t launch_rest_ones(const Geom &g, const uint8_t *mask, void *o, hipStream_t st);
 hipError_t launch_combine(int prec, const BlasShape &sh, const CombineArgs &a, hipStream_t st);
 hipError_t launch_reusken_divide(const BlasShape &sh, const void *y, const void *dt,

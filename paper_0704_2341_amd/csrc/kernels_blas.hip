@@ -336,7 +336,9 @@ __global__ void __launch_bounds__(256) reusken_combine_kernel(BlasShape sh, cons
                 const double2 uv = u[i];
                 double2 o = uv;
                 if (rest) {
-                    const double2 yv = y[i], zv = z[i], tv = t[i];
+                    const double2 yv = y[i];
+                    const double2 zv = z ? z[i] : make_double2(0.0, 0.0);
+                    const double2 tv = t ? t[i] : make_double2(0.0, 0.0);
                     o = make_double2(uv.x - ((yv.x - zv.x) * inv_d + tv.x),
                                      uv.y - ((yv.y - zv.y) * inv_d + tv.y));
                 }

@@ -1163,6 +1163,32 @@ namespace grg {
 // with d = 4 + m0 the diagonal of D_rr.  Three stencil launches on nrhs
 // fields and one on a single field (d~, recomputed per call since the links
 // may have been reset).
+// D_bb x_b - D_br (D_rb x_b) / d: the Schur complement with the couplings
+// inside D_rr ignored (D_rr^{-1} -> 1 / d, d = 4 + m0 its diagonal), which
+// keeps the coarse operator's sparsity; two stencil launches, no solve.
+grg_status diag_schur_apply_internal(grg_schur S, const double *xb, double *yb, int nrhs)
+{
+    grg_lattice L = S->lat;
+    hipStream_t st = L->stream;
+    const Geom &g = L->g;
+    const BlasShape sh = blas_shape(g, nrhs);
+    GRG_TRY_HIP(launch_scatter_coarse(xb, S->u64, S->d_bidx, S->nb, g, nrhs, st));
+    GRG_TRY(run_dslash(S, GRG_FP64, S->u64, S->b64, 0, nrhs, nullptr));
+    GRG_TRY_HIP(launch_reusken_combine(sh, S->u64, S->b64, nullptr, nullptr, S->d_mask,
+                                       1.0 / (4.0 + S->m0), S->x64, st));
+    CoarseArgs c;
+    c.in = S->x64;
+    c.out = yb;
+    c.U = L->U[GRG_FP64];
+    c.q = S->d_q;
+    c.nb = S->nb;
+    c.diag = 4.0 + S->m0;
+    c.g = g;
+    c.nrhs = nrhs;
+    GRG_TRY_HIP(launch_dslash_coarse(c, st));
+    return GRG_OK;
+}
+
 grg_status reusken_apply_internal(grg_schur S, const double *xb, double *yb, int nrhs)
 {
     grg_lattice L = S->lat;
