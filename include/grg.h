@@ -87,11 +87,17 @@ typedef struct {
                           if it misses tol; 0 (default): stop on the defect correction's
                           FP64 residual, which is updated with the exact FP64 operator
                           and equals b - D_rr x up to FP64 rounding */
-    int eo;            /* 1 (default): inner minimal-residual solves (restart 1, no learned
-                          preconditioner) run on the even-odd reduced system of D_rr when
-                          every extent is even (the hopping term couples opposite parities:
-                          solve (d - H_pq H_qp / d) z_p = b_p - H_pq b_q / d on one parity,
-                          then z_q = (b_q - H_qp z_p) / d); 0: on D_rr itself */
+    int eo;            /* 1 (default): inner solves with restart 1 (minimal residual, its
+                          flexible form with the learned preconditioner) and BiCGstab run on
+                          the even-odd reduced system of D_rr when every extent is even (the
+                          hopping term couples opposite parities: solve
+                          (d - H_pq H_qp / d) z_p = b_p - H_pq b_q / d on one parity, then
+                          z_q = (b_q - H_qp z_p) / d); 0: on D_rr itself */
+    int method;        /* 0 (default): GCR(restart) as above; 1: BiCGstab (van der Vorst's
+                          stabilised biconjugate gradients, the D_rr solver of the paper's
+                          section 4 experiment: two operator applications per iteration,
+                          shadow residual = the initial residual); ignores restart and the
+                          learned preconditioner */
 } grg_solver_params;
 
 typedef struct {

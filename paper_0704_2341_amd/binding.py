@@ -60,7 +60,7 @@ class grg_solver_params(C.Structure):
     _fields_ = [
         ("tol", C.c_double), ("max_iter", C.c_int), ("restart", C.c_int), ("inner", C.c_int),
         ("inner_tol", C.c_double), ("max_outer", C.c_int), ("max_rhs", C.c_int),
-        ("check_every", C.c_int), ("verify", C.c_int), ("eo", C.c_int),
+        ("check_every", C.c_int), ("verify", C.c_int), ("eo", C.c_int), ("method", C.c_int),
     ]
 
 
@@ -212,6 +212,8 @@ def grg_solver_params_default(**overrides) -> grg_solver_params:
     for k, v in overrides.items():
         if k == "inner":
             v = _prec(v)
+        if k == "method" and isinstance(v, str):
+            v = {"gcr": 0, "bicgstab": 1}[v]
         setattr(p, k, v)
     return p
 

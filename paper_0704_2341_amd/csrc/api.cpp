@@ -83,6 +83,7 @@ static grg_status validate_params(const grg_solver_params &p)
     if (p.check_every < 1) return set_error("check_every must be >= 1"), GRG_EINVAL;
     if (p.verify != 0 && p.verify != 1) return set_error("verify must be 0 or 1"), GRG_EINVAL;
     if (p.eo != 0 && p.eo != 1) return set_error("eo must be 0 or 1"), GRG_EINVAL;
+    if (p.method != 0 && p.method != 1) return set_error("method must be 0 (GCR) or 1 (BiCGstab)"), GRG_EINVAL;
     return GRG_OK;
 }
 
@@ -160,6 +161,7 @@ grg_status grg_solver_params_default(grg_solver_params *p)
     p->check_every = 1;
     p->verify = 0;
     p->eo = 1;
+    p->method = 0;
     return GRG_OK;
 }
 
@@ -343,10 +345,13 @@ static void schur_free(grg_schur S)
     dfree((void *&)S->d_fk);
     if (S->h_fk) hipHostFree(S->h_fk);
     S->h_fk = nullptr;
-    for (int p = 0; p < 3; ++p)
+    for (int p = 0; p < 3; ++p) {
         for (int k = 0; k < 5; ++k) dfree(S->eo_f[p][k]);
+        for (int k = 0; k < 5; ++k) dfree(S->bicg_f[p][k]);
+    }
     dfree((void *&)S->partials);
     dfree((void *&)S->alpha);
+    dfree((void *&)S->bicg_sc);
     dfree((void *&)S->beta);
     dfree((void *&)S->rn2);
     dfree((void *&)S->thr2);
@@ -411,6 +416,7 @@ grg_status grg_schur_create(grg_lattice L, double m0, const int32_t *q, int32_t 
     S->partials_elems = (size_t)partial_rows(g, prm.max_rhs) * prm.max_rhs * std::max(3, 2 * kMaxRhs);
     ALLOC(S->partials, S->partials_elems * sizeof(double));
     ALLOC(S->alpha, sizeof(double2) * kMaxRhs);
+    ALLOC(S->bicg_sc, sizeof(double2) * 4 * kMaxRhs);
     ALLOC(S->beta, sizeof(double2) * kMaxRhs * kMaxRhs);
     ALLOC(S->rn2, sizeof(double) * kMaxRhs);
     ALLOC(S->thr2, sizeof(double) * kMaxRhs);

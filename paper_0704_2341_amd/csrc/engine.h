@@ -194,6 +194,22 @@ hipError_t launch_reusken_combine(const BlasShape &sh, const void *u, const void
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 hipError_t launch_copy(int prec, const BlasShape &sh, const void *x, void *y, hipStream_t st);
 
+// BiCGstab vector steps and scalar reductions (kernels_blas.hip); sc holds
+// rho, alpha, omega, beta per RHS as double2[4][kMaxRhs]:
+//   kBicgS   s = r - alpha v               (r := s, a := r, b := v)
+//   kBicgUpd x += alpha p + omega s, r = s - omega t, partials <r0, r>, |r|^2
+//            (x, r, a := p, b := s, c := t, d := r0)
+//   kBicgP   p = r + beta (p - omega v)    (r := p, a := r, b := v)
+// and reductions kBicgInit (rho = |r0|^2), kBicgAlpha (alpha = rho / <r0, v>
+// from the stencil's fused sums against r0), kBicgBeta (beta, rho, |r|^2).
+enum { kBicgS = 0, kBicgUpd = 1, kBicgP = 2 };
+enum { kBicgInit = 0, kBicgAlpha = 1, kBicgBeta = 2 };
+hipError_t launch_bicg(int prec, int mode, const BlasShape &sh, void *x, void *r, const void *a,
+                       const void *b, const void *c, const void *d, const double2 *sc,
+                       double *partials, hipStream_t st);
+hipError_t launch_bicg_reduce(int mode, const double *partials, int nparts, int nrhs, double2 *sc,
+                              double *out2, const double *thr2, int *active, hipStream_t st);
+
 // GCR(m > 1): <q_j, q> for j < k, then q -= sum beta_j q_j, p -= sum beta_j p_j
 // with beta_j = <q_j, q>/|q_j|^2, fused with the partials of
 // (re<q,r>, im<q,r>, |q|^2) for the step length.

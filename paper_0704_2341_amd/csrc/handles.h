@@ -94,6 +94,10 @@ struct grg_schur_s {
     double *d_fk = nullptr, *h_fk = nullptr;  // [kCorrPool][kMaxRhs]
     int eo_par = 1;
     void *eo_f[3][5] = {};
+    // BiCGstab: p, v, s, t and the shadow residual (inner precision, full
+    // size, also used as compact halves), and rho, alpha, omega, beta per RHS
+    void *bicg_f[3][5] = {};
+    double2 *bicg_sc = nullptr;
     grg::DslashTune eotune[3][grg::kMaxRhs + 1];
     // reduction scratch
     double *partials = nullptr;

@@ -172,6 +172,168 @@ __global__ void __launch_bounds__(256) mr_update_kernel(BlasShape sh, void *x_, 
         partials[(size_t)blockIdx.x * sh.nrhs + i] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
 }
 
+// BiCGstab vector steps (per-RHS scalars sc[0..3][kMaxRhs] = rho, alpha,
+// omega, beta), in the unit walk of mr_update_kernel:
+//   kBicgS:   s = r - alpha v                      (a = r, b = v, out = s)
+//   kBicgUpd: x += alpha p + omega s, r = s - omega t, and the partial sums
+//             of <r0, r> (re, im) and |r|^2 of the stored r
+//             (x_ = x, r_ = r, a = p, b = s, c = t, d = r0)
+//   kBicgP:   p = r + beta (p - omega v)          (r_ = p, a = r, b = v)
+template <int P, int MODE>
+__global__ void __launch_bounds__(256) bicg_kernel(BlasShape sh, void *x_, void *r_, const void *a_,
+                                                   const void *b_, const void *c_, const void *d_,
+                                                   const double2 *sc, double *partials)
+{
+    typedef VecIO<P> IO;
+    typedef typename IO::R R;
+    constexpr int N = IO::N;
+    constexpr int UV = 12 * 64 / N;
+    constexpr int NV = UV / 64;
+    __shared__ double red[4][kMaxRhs][3];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (MODE == kBicgUpd)
+        for (int i = lane; i < sh.nrhs * 3; i += 64) red[wave][i / 3][i % 3] = 0.0;
+    uint4 *x = (uint4 *)x_, *r = (uint4 *)r_;
+    const uint4 *a = (const uint4 *)a_, *b = (const uint4 *)b_, *c = (const uint4 *)c_,
+                *d = (const uint4 *)d_;
+    const int ntiles = (sh.g.V + 63) >> 6;
+    const int nunits = ntiles * sh.nrhs;
+    const ItemRange it = xcd_items((nunits + 3) >> 2);
+    for (int w = it.begin; w < it.end; w += it.step) {
+        const int u = w * 4 + wave;
+        if (u >= nunits) continue;
+        const int tile = u / sh.nrhs, k = u - tile * sh.nrhs;
+        const double2 al2 = sc[kMaxRhs + k], om2 = sc[2 * kMaxRhs + k], be2 = sc[3 * kMaxRhs + k];
+        const cpx<R> al = {(R)al2.x, (R)al2.y}, om = {(R)om2.x, (R)om2.y}, be = {(R)be2.x, (R)be2.y};
+        const size_t base = (size_t)u * UV;
+        R sre = 0, sim = 0, srr = 0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int site = tile * 64 + (((v * 64 + lane) * N) & 63);
+            if (site >= sh.g.V) continue;
+            const size_t i = base + v * 64 + lane;
+            cpx<R> ac[N], bc[N];
+            IO::get(a[i], ac);
+            IO::get(b[i], bc);
+            if (MODE == kBicgS) {
+                cpx<R> o[N];
+#pragma unroll
+                for (int e = 0; e < N; ++e) {
+                    o[e] = ac[e];
+                    cmac(o[e], cpx<R>{-al.re, -al.im}, bc[e]);
+                }
+                r[i] = IO::put(o);
+            } else if (MODE == kBicgUpd) {
+                cpx<R> xc[N], cc[N], dc[N], rc[N];
+                IO::get(x[i], xc);
+                IO::get(c[i], cc);
+                IO::get(d[i], dc);
+#pragma unroll
+                for (int e = 0; e < N; ++e) {
+                    cmac(xc[e], al, ac[e]);
+                    cmac(xc[e], om, bc[e]);
+                    rc[e] = bc[e];
+                    cmac(rc[e], cpx<R>{-om.re, -om.im}, cc[e]);
+                }
+                x[i] = IO::put(xc);
+                const uint4 ro = IO::put(rc);
+                r[i] = ro;
+                IO::get(ro, rc);  // the sums of the values as stored
+#pragma unroll
+                for (int e = 0; e < N; ++e) {
+                    // conj(r0) r
+                    sre = fma(dc[e].re, rc[e].re, fma(dc[e].im, rc[e].im, sre));
+                    sim = fma(dc[e].re, rc[e].im, fma(-dc[e].im, rc[e].re, sim));
+                    srr = fma(rc[e].re, rc[e].re, fma(rc[e].im, rc[e].im, srr));
+                }
+            } else {
+                cpx<R> pc[N];
+                IO::get(r[i], pc);
+#pragma unroll
+                for (int e = 0; e < N; ++e) {
+                    cpx<R> t = pc[e];
+                    cmac(t, cpx<R>{-om.re, -om.im}, bc[e]);  // p - omega v
+                    pc[e] = ac[e];
+                    cmac(pc[e], be, t);                       // r + beta (p - omega v)
+                }
+                r[i] = IO::put(pc);
+            }
+        }
+        if (MODE == kBicgUpd) {
+            const double t0 = wave_sum((double)sre), t1 = wave_sum((double)sim), t2 = wave_sum((double)srr);
+            if (lane == 0) {
+                red[wave][k][0] += t0;
+                red[wave][k][1] += t1;
+                red[wave][k][2] += t2;
+            }
+        }
+    }
+    if (MODE == kBicgUpd) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < sh.nrhs * 3; i += blockDim.x) {
+            const int k = i / 3, j = i % 3;
+            partials[(size_t)blockIdx.x * sh.nrhs * 3 + i] =
+                ((red[0][k][j] + red[1][k][j]) + red[2][k][j]) + red[3][k][j];
+        }
+    }
+}
+
+// BiCGstab scalars from per-workgroup partials, one workgroup per RHS:
+//   kBicgInit:  K = 1 (|r0|^2): rho = |r0|^2, out2 = |r0|^2, active = |r0|^2 > thr2
+//   kBicgAlpha: K = 3 (sum conj(v) r0, |v|^2): alpha = rho / <r0, v>
+//   kBicgBeta:  K = 3 (<r0, r>, |r|^2): beta = (rho' / rho) (alpha / omega),
+//               rho = rho', out2 = |r|^2, active = |r|^2 > thr2
+// An inactive RHS (or a zero denominator) gets alpha = beta = 0, which
+// freezes its x and r in the vector steps (omega comes from the MR reduction
+// with the same active flags).
+__global__ void __launch_bounds__(256) bicg_reduce_kernel(int mode, const double *partials, int nparts,
+                                                          int nrhs, double2 *sc, double *out2,
+                                                          const double *thr2, int *active)
+{
+    __shared__ double sm[3][256];
+    const int r = blockIdx.x;
+    const int K = mode == kBicgInit ? 1 : 3;
+    double acc[3] = {0, 0, 0};
+    for (int i = threadIdx.x; i < nparts; i += 256)
+        for (int k = 0; k < K; ++k) acc[k] += partials[((size_t)i * nrhs + r) * K + k];
+    for (int k = 0; k < K; ++k) sm[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int k = 0; k < K; ++k) sm[k][threadIdx.x] += sm[k][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    double2 *rho = sc, *alpha = sc + kMaxRhs, *omega = sc + 2 * kMaxRhs, *beta = sc + 3 * kMaxRhs;
+    const bool on = active == nullptr || active[r];
+    if (mode == kBicgInit) {
+        rho[r] = make_double2(sm[0][0], 0.0);
+        out2[r] = sm[0][0];
+        if (active) active[r] = sm[0][0] > thr2[r] ? 1 : 0;
+    } else if (mode == kBicgAlpha) {
+        // <r0, v> = conj(sum conj(v) r0)
+        const double sr = sm[0][0], si = -sm[1][0];
+        const double den = sr * sr + si * si;
+        const double2 rh = rho[r];
+        alpha[r] = on && den > 0 ? make_double2((rh.x * sr + rh.y * si) / den, (rh.y * sr - rh.x * si) / den)
+                                 : make_double2(0.0, 0.0);
+    } else {
+        const double2 rn = make_double2(sm[0][0], sm[1][0]), rh = rho[r], al = alpha[r], om = omega[r];
+        const double d1 = rh.x * rh.x + rh.y * rh.y, d2 = om.x * om.x + om.y * om.y;
+        double2 b = make_double2(0.0, 0.0);
+        if (on && d1 > 0 && d2 > 0) {
+            // (rn / rh) (al / om)
+            const double2 q1 = make_double2((rn.x * rh.x + rn.y * rh.y) / d1, (rn.y * rh.x - rn.x * rh.y) / d1);
+            const double2 q2 = make_double2((al.x * om.x + al.y * om.y) / d2, (al.y * om.x - al.x * om.y) / d2);
+            b = make_double2(q1.x * q2.x - q1.y * q2.y, q1.x * q2.y + q1.y * q2.x);
+        }
+        beta[r] = b;
+        rho[r] = rn;
+        out2[r] = sm[2][0];
+        if (active) active[r] = sm[2][0] > thr2[r] ? 1 : 0;
+    }
+}
+
 template <int P>
 __global__ void __launch_bounds__(256) norm2_kernel(BlasShape sh, const void *v_, double *partials)
 {
@@ -640,6 +802,35 @@ hipError_t launch_mr_update(int prec, const BlasShape &sh, void *x, void *r, con
     default: return hipErrorInvalidValue;
     }
 #undef MRU
+    return hipGetLastError();
+}
+
+hipError_t launch_bicg(int prec, int mode, const BlasShape &sh, void *x, void *r, const void *a,
+                       const void *b, const void *c, const void *d, const double2 *sc,
+                       double *partials, hipStream_t st)
+{
+    if (!shape_ok(sh) || mode < kBicgS || mode > kBicgP) return hipErrorInvalidValue;
+    dim3 g(sh.grid), bl(kBlasSB);
+#define BIC(PP)                                                                                         \
+    if (mode == kBicgS) hipLaunchKernelGGL((bicg_kernel<PP, kBicgS>), g, bl, 0, st, sh, x, r, a, b, c, d, sc, partials); \
+    else if (mode == kBicgUpd) hipLaunchKernelGGL((bicg_kernel<PP, kBicgUpd>), g, bl, 0, st, sh, x, r, a, b, c, d, sc, partials); \
+    else hipLaunchKernelGGL((bicg_kernel<PP, kBicgP>), g, bl, 0, st, sh, x, r, a, b, c, d, sc, partials);
+    switch (prec) {
+    case GRG_FP64: BIC(GRG_FP64) break;
+    case GRG_FP32: BIC(GRG_FP32) break;
+    case GRG_BF16: BIC(GRG_BF16) break;
+    default: return hipErrorInvalidValue;
+    }
+#undef BIC
+    return hipGetLastError();
+}
+
+hipError_t launch_bicg_reduce(int mode, const double *partials, int nparts, int nrhs, double2 *sc,
+                              double *out2, const double *thr2, int *active, hipStream_t st)
+{
+    if (nrhs < 1 || nrhs > kMaxRhs || mode < kBicgInit || mode > kBicgBeta) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(bicg_reduce_kernel, dim3(nrhs), dim3(256), 0, st, mode, partials, nparts, nrhs, sc,
+                       out2, thr2, active);
     return hipGetLastError();
 }
 

@@ -807,6 +807,121 @@ static grg_status inner_fgcr_eo(grg_schur S, int prec, int nrhs, const double *t
     return done ? GRG_OK : GRG_ENOCONV;
 }
 
+// BiCGstab (van der Vorst) for the inner solve, on D_rr or, with reduce, on
+// its even-odd reduced system; same conventions as inner_gcr (right-hand
+// side in in_r, correction to xdst, zero for RHS that took no step) and
+// inner_mr_eo.  The shadow residual is the initial residual.  Per iteration:
+// v = A p with the sums against r0 fused into the stencil, alpha =
+// rho / <r0, v>, s = r - alpha v, t = A s with <t, s> and |t|^2 fused,
+// omega = <t, s> / |t|^2, x += alpha p + omega s, r = s - omega t (with
+// <r0, r> and |r|^2), beta = (rho' / rho)(alpha / omega), p = r + beta (p -
+// omega v).  All scalars stay on the device.
+static grg_status inner_bicgstab(grg_schur S, int prec, int nrhs, const double *thr, int maxit,
+                                 int *iters, double *rn2_out, void *xdst, bool reduce)
+{
+    grg_lattice L = S->lat;
+    hipStream_t st = L->stream;
+    const Geom &g = L->g;
+    const size_t full_bytes = spinor_elems(g, S->prm.max_rhs) * prec_bytes(prec);
+    for (int k = 0; k < 5; ++k) {
+        void *&b = S->bicg_f[prec][k];
+        if (b) continue;
+        if (hipMalloc(&b, full_bytes) != hipSuccess) {
+            b = nullptr;
+            set_error("BiCGstab workspace: hipMalloc of %zu bytes failed", full_bytes);
+            return GRG_ENOMEM;
+        }
+        GRG_TRY_HIP(launch_fill_zero(b, full_bytes, st));
+    }
+    void **bf = S->bicg_f[prec];
+    void *pv = bf[0], *v = bf[1], *sv = bf[2], *tv = bf[3], *r0 = bf[4];
+    const double d = 4.0 + S->m0;
+    const int P = S->eo_par, Q = 1 - P;
+    const void *b = S->in_r[prec];
+    void *r, *x, *w = nullptr;
+    Geom gv = g;
+    DslashTune te;
+    int nparts;
+    if (reduce) {
+        GRG_TRY(ensure_eo(S, prec));
+        gv = half_geom(L);
+        te = S->eotune[prec][nrhs].valid ? S->eotune[prec][nrhs] : default_eo_tune(gv, prec, nrhs);
+        nparts = te.grid;
+        r = S->eo_f[prec][0];
+        x = S->eo_f[prec][1];
+        w = S->eo_f[prec][3];
+    } else {
+        const DslashTune &tt = S->tune[prec][nrhs];
+        nparts = tt.valid ? tt.grid : default_tune(g, prec, nrhs).grid;
+        r = S->in_r[prec];
+        x = xdst;
+    }
+    const BlasShape sh = blas_shape(gv, nrhs);
+    const size_t vbytes = spinor_elems(gv, nrhs) * prec_bytes(prec);
+    const int check = std::max(1, S->prm.check_every);
+    double2 *sc = S->bicg_sc;
+    auto apply = [&](const void *in, void *out, const void *dot_with) -> grg_status {
+        if (reduce) {
+            GRG_TRY(eo_hop(S, prec, te, in, nullptr, w, Q, 0.0, 1.0, nrhs, nullptr, nullptr));
+            return eo_hop(S, prec, te, w, in, out, P, d, -1.0 / d, nrhs, S->partials, dot_with);
+        }
+        return run_dslash(S, prec, in, out, 0, nrhs, S->partials, dot_with);
+    };
+    // r: the (reduced) right-hand side; x = 0; r0 = p = r
+    if (reduce)
+        GRG_TRY(eo_hop(S, prec, te, b, b, r, P, 1.0, -1.0 / d, nrhs, nullptr, nullptr, nullptr, 1, 1));
+    GRG_TRY_HIP(launch_fill_zero(x, vbytes, st));
+    GRG_TRY_HIP(launch_norm2(prec, sh, r, S->partials, st));
+    GRG_TRY_HIP(launch_bicg_reduce(kBicgInit, S->partials, sh.grid, nrhs, sc, S->rn2, S->thr2, S->active,
+                                   st));
+    GRG_TRY_HIP(launch_copy(prec, sh, r, r0, st));
+    GRG_TRY_HIP(launch_copy(prec, sh, r, pv, st));
+    double h[kMaxRhs];
+    GRG_TRY(read_norms(S, nrhs, h));
+    if (reduce) {
+        int *flags = (int *)(S->h_buf + 8 * kMaxRhs);
+        for (int k = 0; k < nrhs; ++k) flags[k] = h[k] > thr[k] ? 1 : 0;
+        GRG_TRY_HIP(hipMemcpyAsync(S->act0, flags, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
+    }
+    auto all_done = [&](const double *n2) {
+        for (int k = 0; k < nrhs; ++k) {
+            if (!isfinite(n2[k])) return -1;
+            if (n2[k] > thr[k]) return 0;
+        }
+        return 1;
+    };
+    int it = 0;
+    int done = all_done(h);
+    while (done == 0 && it < maxit) {
+        GRG_TRY(apply(pv, v, r0));
+        GRG_TRY_HIP(launch_bicg_reduce(kBicgAlpha, S->partials, nparts, nrhs, sc, nullptr, nullptr,
+                                       S->active, st));
+        GRG_TRY_HIP(launch_bicg(prec, kBicgS, sh, nullptr, sv, r, v, nullptr, nullptr, sc, nullptr, st));
+        GRG_TRY(apply(sv, tv, sv));
+        GRG_TRY_HIP(launch_reduce(kAlpha, S->partials, nparts, nrhs, sc + 2 * kMaxRhs, nullptr, nullptr,
+                                  S->active, st));
+        GRG_TRY_HIP(launch_bicg(prec, kBicgUpd, sh, x, r, pv, sv, tv, r0, sc, S->partials, st));
+        GRG_TRY_HIP(launch_bicg_reduce(kBicgBeta, S->partials, sh.grid, nrhs, sc, S->rn2, S->thr2,
+                                       S->active, st));
+        GRG_TRY_HIP(launch_bicg(prec, kBicgP, sh, nullptr, pv, r, v, nullptr, nullptr, sc, nullptr, st));
+        ++it;
+        if (it % check == 0 || it == maxit) {
+            GRG_TRY(read_norms(S, nrhs, h));
+            done = all_done(h);
+        }
+    }
+    *iters = it;
+    memcpy(rn2_out, h, sizeof(double) * nrhs);
+    if (reduce)
+        GRG_TRY(eo_hop(S, prec, te, x, b, xdst, Q, 1.0 / d, -1.0 / d, nrhs, nullptr, nullptr, S->act0,
+                       0, 1, x));
+    if (done < 0) {
+        set_error("non-finite residual in the inner solve");
+        return GRG_ENONFINITE;
+    }
+    return done ? GRG_OK : GRG_ENOCONV;
+}
+
 // A training pair of the reduced system for the learned preconditioner.
 // e (BF16, full layout) holds the error e_0 on the reduced parity's rest
 // sites.  k minimal-residual steps on A^ x = A^ e_0 from x = 0 (the reduced
@@ -1011,7 +1126,10 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
         grg_status is;
         double h[kMaxRhs];
         const bool reduce = p.eo && L->eo_ok && std::max(1, p.restart) == 1;
-        if (S->precond) {
+        if (p.method == 1) {
+            is = inner_bicgstab(S, prec, nrhs, thr, p.max_iter - total, &it, h, e, p.eo && L->eo_ok);
+            total += it;
+        } else if (S->precond) {
             // preconditioned inner solve, with the plain solve as the fallback
             const int cap = std::min(p.max_iter - total, kPrecondInnerCap);
             is = reduce ? inner_fgcr_eo(S, prec, nrhs, thr, cap, &it, h, e)
