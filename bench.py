@@ -154,6 +154,37 @@ def learned_leg(grg, torch, args, lat, s, xb, yb, y_plain, nrhs, plain_value, pl
             "speedup_vs_plain_mixed": val / plain_value}
 
 
+def vcycle_leg(grg, torch):
+    """Section 4's experiment on synthetic fields: D x = f to 1e-8 at
+    kappa = 1/6 (m0 = -1) by BiCGstab, plain and right-preconditioned by the
+    3-level cyclic-reduction V-cycle (A_rr solves by BiCGstab to 1e-2, top
+    level to 1e-12); average convergence rate R per solve."""
+    from grg_inputs import gaussian_vectors, su3_links
+
+    out = {}
+    for dims in ((8, 8, 8, 8), (16, 16, 16, 16)):
+        lat = grg.grg_lattice_create(dims)
+        grg.grg_gauge_set(lat, su3_links(dims, 0.5, 7))
+        v = grg.grg_vcycle_create(lat, -1.0, grg.grg_vcycle_params_default(levels=3, max_rhs=4))
+        V = int(np.prod(dims))
+        f = torch.from_numpy(gaussian_vectors(12 * V, 4, 7)).to("cuda")
+        x = torch.empty_like(f)
+        row = {}
+        for name, pre in (("bicgstab", False), ("vcycle_bicgstab", True)):
+            st = grg.grg_vcycle_solve(v, f, x, 4, tol=1e-8, precondition=pre)
+            row[name] = {"iters": st["iters"], "rate": st["rate"], "ms": st["t_ms"],
+                         "true_rel_resid": st["true_rel_resid"], "cycles": st["cycles"]}
+        key = "x".join(map(str, dims))
+        out[key] = row
+        log(f"V-cycle {key}, m0 -1: BiCGstab {row['bicgstab']['iters']} iters, R {row['bicgstab']['rate']:.3f}, "
+            f"{row['bicgstab']['ms']:.1f} ms; preconditioned {row['vcycle_bicgstab']['iters']} iters, "
+            f"R {row['vcycle_bicgstab']['rate']:.3f}, {row['vcycle_bicgstab']['ms']:.1f} ms")
+        grg.grg_vcycle_destroy(v)
+        grg.grg_lattice_destroy(lat)
+    out["workload"] = "synthetic links eps 0.5 seed 7, m0 = -1 (kappa = 1/6), 4 Gaussian RHS, tol 1e-8, Type I at every level"
+    return out
+
+
 def batch_leg(grg, torch, args):
     """48 lattices, sizes uniform over {8^4, 12^4, 16^4, 8^3x16}, own seeds,
     m0 in [-0.3, 0.1], 4 RHS each, FP32 inner / FP64 outer, one batch."""
@@ -212,6 +243,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the 48-lattice batch leg")
     ap.add_argument("--no-reusken", action="store_true", help="skip the section 3 approximation leg")
+    ap.add_argument("--no-vcycle", action="store_true", help="skip the section 4 V-cycle leg")
     ap.add_argument("--train-steps", type=int, default=1667, help="12-pair Adam steps (1667 = 20k pairs)")
     ap.add_argument("--eo-launch", default="", metavar="SB,RG,SPLIT,GRID,CHUNK,MARCH",
                     help="pin the half-lattice stencil's launch after tuning")
@@ -375,6 +407,9 @@ def main():
     learned = None
     if not args.no_learned:
         learned = learned_leg(grg, torch, args, lat, s, xb, yb, y_mixed, nrhs, value, st)
+    vc = None
+    if not args.no_vcycle:
+        vc = vcycle_leg(grg, torch)
     batch = None
     if not args.no_batch:
         batch = batch_leg(grg, torch, args)
@@ -429,6 +464,7 @@ def main():
         "reusken_approximation": reusken,
         "learned_preconditioner": learned,
         "batch_48": batch,
+        "vcycle_section4": vc,
         "cpu_baseline": cpu,
     }
     if copy_bytes:

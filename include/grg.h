@@ -279,6 +279,58 @@ grg_status grg_reduced_apply(grg_schur s, int precision, int parity, const doubl
                              int nrhs);
 
 /* ---------------------------------------------------------------------------
+ * Cyclic-reduction V-cycle (section 4): a multilevel preconditioner built from
+ * the Schur complement approximation.  Level 0 is D on the lattice; each
+ * level is partitioned with the all-even coarse set (Type I) and the next
+ * level is its Schur complement approximation, which on that set is again a
+ * Wilson operator: D_bb - D_br D_rb / d = (1/d) D_W(V, d^2 - 4) on the coarse
+ * lattice, d = 4 + m, V_mu(c) = U_mu(2c) U_mu(2c + mu) (the second-order
+ * formula of section 3 reduces to it on this set).  One cycle on level k:
+ * y = A_rr^{-1} f_r, g = f_b - A_br y, x_b = cycle(k + 1, g),
+ * x_r = A_rr^{-1}(f_r - A_rb x_b), with the A_rr solves by BiCGstab to
+ * drr_tol (section 4 used one percent) and the top level solved to top_tol
+ * ("inverted exactly").  The paper's runs used the inverse permutations,
+ * whose recursion it does not state; this cycle uses Type I at every level. */
+typedef struct grg_vcycle_s *grg_vcycle;
+
+typedef struct {
+    int levels;        /* 2 or 3 (default 3): every extent must be divisible by 2^levels */
+    double drr_tol;    /* relative accuracy of the A_rr solves in the cycle (default 1e-2) */
+    double top_tol;    /* relative accuracy of the top level's solve (default 1e-12) */
+    int max_rhs;       /* largest nrhs per call (default 12, <= 16) */
+    int max_iter;      /* cap on the iterations of each BiCGstab solve (default 10000) */
+} grg_vcycle_params;
+
+typedef struct {
+    int iters;             /* outer BiCGstab iterations */
+    int converged;         /* every RHS reached tol */
+    double rate;           /* average convergence rate R: the mean over RHS of
+                              (|r_n| / |r_0|)^(1/n), the geometric mean of the ratio of
+                              each iteration's residual to the previous one */
+    double true_rel_resid; /* max over RHS of |f - D x| / |f|, recomputed */
+    double t_ms;
+    int cycles;            /* V-cycle applications */
+} grg_vcycle_stats;
+
+grg_status grg_vcycle_params_default(grg_vcycle_params *p);
+/* Build the hierarchy on lat (gauge field set) for mass m0: the coarse
+ * lattices, their blocked links and masses m_{k+1} = (4 + m_k)^2 - 4 with
+ * the scale of each level.  GRG_EINVAL if an extent is not divisible by
+ * 2^levels or 4 + m0 = 0.  lat must outlive the handle. */
+grg_status grg_vcycle_create(grg_lattice lat, double m0, const grg_vcycle_params *params,
+                             grg_vcycle *out);
+grg_status grg_vcycle_destroy(grg_vcycle v);
+/* x = M f: one V-cycle on level 0 for nrhs canonical lattice fields (device). */
+grg_status grg_vcycle_apply(grg_vcycle v, const double *f, double *x, int nrhs);
+/* Solve D x = f (all sites, FP64) to ||f - D x|| <= tol ||f|| per RHS by
+ * BiCGstab, right-preconditioned by the V-cycle when precondition != 0 (each
+ * iteration applies D twice and, preconditioned, the cycle twice); x starts
+ * from zero.  Canonical device fields.  stats may be NULL.  GRG_ENOCONV after
+ * max_iter iterations keeps the last iterate. */
+grg_status grg_vcycle_solve(grg_vcycle v, int precondition, double tol, const double *f, double *x,
+                            int nrhs, grg_vcycle_stats *stats);
+
+/* ---------------------------------------------------------------------------
  * Learned preconditioner.  M is a linear, gauge-covariant network of three
  * parallel-transport convolutions with 4 -> 8 -> 8 -> 4 colour-vector channels
  * (12 -> 24 -> 24 -> 12 complex per site; the spin index of a Dirac field is

@@ -46,7 +46,8 @@ EXPORTS = (
     "grg_precond_loss_grad", "grg_precond_train", "grg_precond_save", "grg_precond_load",
     "grg_schur_attach_precond", "grg_batch_create", "grg_batch_destroy", "grg_batch_layout",
     "grg_batch_apply", "grg_batch_tune", "grg_profile_enable",
-    "grg_profile_read", "grg_profile_reset",
+    "grg_profile_read", "grg_profile_reset", "grg_vcycle_params_default", "grg_vcycle_create",
+    "grg_vcycle_destroy", "grg_vcycle_apply", "grg_vcycle_solve",
 )
 
 
@@ -70,6 +71,19 @@ class grg_solver_stats(C.Structure):
         ("true_rel_resid", C.c_double), ("t_total_ms", C.c_double), ("t_dslash_ms", C.c_double),
         ("fallbacks", C.c_int),
     ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class grg_vcycle_params(C.Structure):
+    _fields_ = [("levels", C.c_int), ("drr_tol", C.c_double), ("top_tol", C.c_double),
+                ("max_rhs", C.c_int), ("max_iter", C.c_int)]
+
+
+class grg_vcycle_stats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("rate", C.c_double),
+                ("true_rel_resid", C.c_double), ("t_ms", C.c_double), ("cycles", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -143,6 +157,12 @@ def load():
         "grg_block_apply": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, vp, C.c_int]),
         "grg_reduced_apply": (C.c_int, [vp, C.c_int, C.c_int, vp, vp, C.c_int]),
         "grg_precond_create": (C.c_int, [vp, C.POINTER(vp)]),
+        "grg_vcycle_params_default": (C.c_int, [C.POINTER(grg_vcycle_params)]),
+        "grg_vcycle_create": (C.c_int, [vp, C.c_double, C.POINTER(grg_vcycle_params), C.POINTER(vp)]),
+        "grg_vcycle_destroy": (C.c_int, [vp]),
+        "grg_vcycle_apply": (C.c_int, [vp, vp, vp, C.c_int]),
+        "grg_vcycle_solve": (C.c_int, [vp, C.c_int, C.c_double, vp, vp, C.c_int,
+                                       C.POINTER(grg_vcycle_stats)]),
         "grg_precond_destroy": (C.c_int, [vp]),
         "grg_precond_set_weights": (C.c_int, [vp, vp]),
         "grg_precond_get_weights": (C.c_int, [vp, vp]),
@@ -498,3 +518,38 @@ def grg_profile_read(s, precision, eo=False):
 
 def grg_profile_reset(s):
     _check(load().grg_profile_reset(s))
+
+
+# ---------------------------------------------------------------- V-cycle (section 4)
+def grg_vcycle_params_default(**overrides) -> grg_vcycle_params:
+    p = grg_vcycle_params()
+    _check(load().grg_vcycle_params_default(C.byref(p)))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def grg_vcycle_create(lat, m0, params=None):
+    h = C.c_void_p()
+    _check(load().grg_vcycle_create(lat, float(m0), C.byref(params) if params is not None else None,
+                                    C.byref(h)))
+    return h
+
+
+def grg_vcycle_destroy(v):
+    _check(load().grg_vcycle_destroy(v))
+
+
+def grg_vcycle_apply(v, f, x, nrhs):
+    """x = M f, one V-cycle (canonical device fields)."""
+    _check(load().grg_vcycle_apply(v, _ptr(f), _ptr(x), int(nrhs)))
+
+
+def grg_vcycle_solve(v, f, x, nrhs, tol=1e-8, precondition=True, allow_noconv=False):
+    """Solve D x = f by BiCGstab, right-preconditioned by the V-cycle."""
+    st = grg_vcycle_stats()
+    status = load().grg_vcycle_solve(v, int(bool(precondition)), float(tol), _ptr(f), _ptr(x), int(nrhs),
+                                     C.byref(st))
+    if not (allow_noconv and status == -5):
+        _check(status)
+    return st.as_dict()

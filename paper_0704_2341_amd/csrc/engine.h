@@ -210,6 +210,24 @@ hipError_t launch_bicg(int prec, int mode, const BlasShape &sh, void *x, void *r
 hipError_t launch_bicg_reduce(int mode, const double *partials, int nparts, int nrhs, double2 *sc,
                               double *out2, const double *thr2, int *active, hipStream_t st);
 
+// V-cycle (kernels_vcycle.hip): blocked links of the next level, restriction
+// to / prolongation from the coarse sites (canonical fields), and linear
+// combinations and dot products of canonical FP64 fields.
+struct VcCoef {
+    int n;                     // inputs in use, 1..3
+    double2 c[3][kMaxRhs];     // per input and RHS
+};
+hipError_t launch_vc_block_links(const Geom &gf, const void *U64, const Geom &gc, double *out, hipStream_t st);
+hipError_t launch_vc_restrict(const double *full, double *coarse, const int32_t *q, int nb, int V, int nrhs,
+                              hipStream_t st);
+hipError_t launch_vc_prolong(const double *coarse, double *full, const int32_t *q, int nb, int V, int nrhs,
+                             hipStream_t st);
+hipError_t launch_vc_lincomb(size_t len, int nrhs, const VcCoef &cf, double *out, const double *in0,
+                             const double *in1, const double *in2, hipStream_t st);
+int vc_dot_grid(size_t len);
+hipError_t launch_vc_dot(size_t len, int nrhs, const double *a, const double *b, double *partials,
+                         hipStream_t st);
+
 // GCR(m > 1): <q_j, q> for j < k, then q -= sum beta_j q_j, p -= sum beta_j p_j
 // with beta_j = <q_j, q>/|q_j|^2, fused with the partials of
 // (re<q,r>, im<q,r>, |q|^2) for the step length.

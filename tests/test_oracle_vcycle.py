@@ -1,0 +1,74 @@
+"""Pins of the V-cycle oracle (section 4).
+
+* The level operator defined by block elimination with the couplings inside
+  the rest block ignored equals the coarse-lattice Wilson form
+  (1/d) D_W(V, d^2 - 4), V_mu(c) = U_mu(2c) U_mu(2c + mu): two independent
+  routes (probing and masks on the fine operator, against a Wilson operator on
+  blocked links), so a wrong link product, boundary sign, mass or scale fails.
+* With the exact Schur complement on the top level, one cycle is the exact
+  inverse (the block LU of section 1): D cycle(f) = f.
+* Whatever the top level, the rest rows of D cycle(f) - f vanish (x_r solves
+  them exactly), and the coarse rows carry (S - S0) x_b."""
+import numpy as np
+import pytest
+
+from grg_inputs import gaussian_vectors, su3_links
+from oracle import dense, matfree, vcycle
+
+pytestmark = pytest.mark.slow
+
+DIMS = (8, 8, 8, 8)
+M0 = -0.4
+
+
+@pytest.fixture(scope="module")
+def links():
+    return su3_links(DIMS, 0.5, 41)
+
+
+def test_level_one_is_the_coarse_wilson_operator(links):
+    lv = vcycle.hierarchy(links, DIMS, M0, 2)
+    x = gaussian_vectors(12 * lv[1].n, 2, 41)
+    for v in x:
+        got = lv[1].apply(v)
+        want = vcycle.coarse_wilson_apply(links, DIMS, M0, v[None, :])[0]
+        assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
+        # and the same as the oracle's approximation that ignores D_rr's couplings
+        q, nb = dense.permutation_block(DIMS, "I")
+        alt = matfree.diag_schur_apply(links, DIMS, M0, q, nb, v[None, :])[0]
+        assert np.linalg.norm(got - alt) <= 1e-12 * np.linalg.norm(alt)
+
+
+def test_level_two_is_the_twice_blocked_wilson_operator(links):
+    lv = vcycle.hierarchy(links, DIMS, M0, 3)
+    d0 = 4 + M0
+    cd = tuple(L // 2 for L in DIMS)
+    links1 = vcycle.block_links(links, DIMS)
+    x = gaussian_vectors(12 * lv[2].n, 1, 42)[0]
+    # A_2 = (1/d0) * (1/d1) D_W(V2, d1^2 - 4) with d1 = 4 + m1 = d0^2, periodic
+    # coarse boundary handled by the same bc on every level
+    want = vcycle.coarse_wilson_apply(links1, cd, d0 * d0 - 4, x[None, :])[0] / d0
+    got = lv[2].apply(x)
+    assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
+
+
+def test_cycle_with_the_exact_complement_inverts_d(links):
+    dims = (4, 4, 4, 4)
+    lk = su3_links(dims, 0.5, 43)
+    lv = vcycle.hierarchy(lk, dims, M0, 2)
+    q, nb = dense.permutation_block(dims, "I")
+    lv[1].apply = lambda xb: matfree.schur_apply(lk, dims, M0, q, nb, xb[None, :], restart=8, tol=1e-14)[0][0]
+    f = gaussian_vectors(12 * lv[0].n, 1, 43)[0]
+    x = vcycle.cycle(lv, 0, f)
+    r = matfree.dirac_apply(lk, dims, M0, x[None, :])[0] - f
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(f)
+
+
+def test_cycle_solves_the_rest_rows_exactly(links):
+    lv = vcycle.hierarchy(links, DIMS, M0, 2)
+    f = gaussian_vectors(12 * lv[0].n, 1, 44)[0]
+    x = vcycle.cycle(lv, 0, f)
+    r = (matfree.dirac_apply(links, DIMS, M0, x[None, :])[0] - f).reshape(lv[0].n, 12)
+    assert np.linalg.norm(r[lv[0].rest]) <= 1e-11 * np.linalg.norm(f)
+    # the coarse rows do not vanish: S0 is an approximation
+    assert np.linalg.norm(r[~lv[0].rest]) > 1e-3 * np.linalg.norm(f)
