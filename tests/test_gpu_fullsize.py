@@ -104,3 +104,29 @@ def test_drr_solve_oracle_residual(big):
     print(f"oracle residuals {rr}", flush=True)
     assert np.all(rr <= 1e-10 * (1 + 1e-6))
     assert not np.any(x.reshape(NRHS, -1, 12)[:, np.asarray(s.q[:s.nb])])
+
+
+def test_reduced_operator_tuned_launch(big):
+    """The half-lattice stencils of the reduced operator, in the tuned launch
+    the benchmark times (the dominant kernel), at the full size."""
+    import torch
+
+    from oracle import matfree
+
+    lat, s = big
+    grg = lat.grg
+    info = grg.grg_schur_tune_info(s.h, "bf16", NRHS, eo=True)
+    print(f"32^4 reduced operator, bf16, 12 RHS, launch {info}", flush=True)
+    assert info["ms"] > 0
+    x = gaussian_vectors(12 * lat.V, NRHS, 33)
+    xd = to_dev(x)
+    yd = torch.empty_like(xd)
+    for parity in (0, 1):
+        grg.grg_reduced_apply(s.h, "bf16", parity, xd, yd, NRHS)
+        y = to_host(yd)
+        want = matfree.reduced_apply(lat.links, DIMS, M0, s.q, s.nb, parity, x[list(SAMPLE)])
+        assert rel_err(y[list(SAMPLE)], want) < TOL["bf16"]
+        par = matfree.site_parity(DIMS)
+        off = par != parity
+        off[np.asarray(s.q[: s.nb])] = True
+        assert not np.any(y.reshape(NRHS, -1, 12)[:, off])
