@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgrg.so")
 SOURCES = ["kernels_dslash.hip", "kernels_blas.hip", "kernels_ptc.hip", "kernels_batch.hip", "kernels_eo.hip",
-           "kernels_vcycle.hip", "solver.cpp", "api.cpp", "precond.cpp", "batch.cpp", "vcycle.cpp"]
+           "kernels_vcycle.hip", "kernels_coarse.hip", "solver.cpp", "api.cpp", "precond.cpp", "batch.cpp", "vcycle.cpp"]
 ARCH = "gfx950"
 
 # Packed-FP32 instructions are disabled for every HIP translation unit.

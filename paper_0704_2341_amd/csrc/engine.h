@@ -131,6 +131,10 @@ hipError_t launch_dslash(int prec, const DslashArgs &a, int grid, hipStream_t st
 // the t-marching kernel runs with 64 * a.RG threads per workgroup.
 hipError_t launch_dc_update(int prec, const DcArgs &a, int grid, int SB, hipStream_t st);
 hipError_t launch_dslash_coarse(const CoarseArgs &a, hipStream_t st);
+// b = D_rb x_b from the canonical coarse vector (kernels_coarse.hip): internal
+// FP64 field, zero on the coarse sites
+hipError_t launch_rb_apply(const Geom &g, const double *xb, const int32_t *bidx, int nb, const void *U64,
+                           void *out, int nrhs, hipStream_t st);
 hipError_t launch_eo_hop(int prec, const EoArgs &a, int grid, hipStream_t st);
 // compact field of parity par <-> full field (zero off that parity)
 hipError_t launch_eo_scatter(int prec, const Geom &g, int nrhs, int par, const void *src, void *dst,

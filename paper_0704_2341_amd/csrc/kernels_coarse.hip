@@ -1,0 +1,80 @@
+// b = D_rb x_b: the hopping term from the coarse sites onto the rest sites
+// (section 1, step 1's block D_rb) for a field that is nonzero on the coarse
+// sites only.  A rest site takes the hops from those of its eight neighbours
+// that are coarse (with the all-even coarse set, two neighbours for a site
+// with one odd coordinate, none otherwise), read straight from the canonical
+// coarse vector; the full stencil over a field that is zero on 15 of 16 sites
+// would read every neighbour.  Output: the internal FP64 field, zero on the
+// coarse sites.
+#include "common.h"
+#include "engine.h"
+#include "stencil.h"
+
+namespace grg {
+
+template <int MU>
+__device__ __forceinline__ void rb_hops(cpx<double> (&acc)[12], int s, const SiteGeo &q, const Geom &g,
+                                        const double2 *__restrict__ xb, const int32_t *__restrict__ bidx,
+                                        int nb, int r, const double2 *__restrict__ U)
+{
+    int sp, sm;
+    nbr(s, MU, q, g, sp, sm);
+    const int kp = bidx[sp], km = bidx[sm];
+    if (kp >= 0) {
+        cpx<double> p[12], u[9];
+        const double2 *v = xb + ((size_t)r * nb + kp) * 12;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) p[c] = {v[c].x, v[c].y};
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            const double2 w = U[lidx(s, MU, e)];
+            u[e] = {w.x, w.y};
+        }
+        hop_math<MU, true>(acc, p, u);
+    }
+    if (km >= 0) {
+        cpx<double> p[12], u[9];
+        const double2 *v = xb + ((size_t)r * nb + km) * 12;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) p[c] = {v[c].x, v[c].y};
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            const double2 w = U[lidx(sm, MU, e)];
+            u[e] = {w.x, w.y};
+        }
+        hop_math<MU, false>(acc, p, u);
+    }
+}
+
+__global__ void __launch_bounds__(256) rb_apply_kernel(Geom g, const double2 *__restrict__ xb,
+                                                       const int32_t *__restrict__ bidx, int nb,
+                                                       const double2 *__restrict__ U, double2 *__restrict__ out,
+                                                       int nrhs)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (s >= g.V) return;
+    cpx<double> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
+    if (bidx[s] < 0) {
+        const SiteGeo q = site_geo(s, g);
+        rb_hops<0>(acc, s, q, g, xb, bidx, nb, r, U);
+        rb_hops<1>(acc, s, q, g, xb, bidx, nb, r, U);
+        rb_hops<2>(acc, s, q, g, xb, bidx, nb, r, U);
+        rb_hops<3>(acc, s, q, g, xb, bidx, nb, r, U);
+    }
+#pragma unroll
+    for (int c = 0; c < 12; ++c) out[fidx(s, r, c, nrhs)] = make_double2(acc[c].re, acc[c].im);
+}
+
+hipError_t launch_rb_apply(const Geom &g, const double *xb, const int32_t *bidx, int nb, const void *U64,
+                           void *out, int nrhs, hipStream_t st)
+{
+    if (nrhs < 1 || nrhs > kMaxRhs || nb < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(rb_apply_kernel, dim3((g.V + 255) / 256, nrhs), dim3(256), 0, st, g,
+                       (const double2 *)xb, bidx, nb, (const double2 *)U64, (double2 *)out, nrhs);
+    return hipGetLastError();
+}
+
+}  // namespace grg

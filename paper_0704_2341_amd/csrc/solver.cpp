@@ -1251,8 +1251,8 @@ grg_status schur_apply_internal(grg_schur S, const double *xb, double *yb, int n
     const BlasShape sh = blas_shape(g, nrhs);
     // u = x on coarse sites
     GRG_TRY_HIP(launch_scatter_coarse(xb, S->u64, S->d_bidx, S->nb, g, nrhs, st));
-    // b = (D u)_r
-    GRG_TRY(run_dslash(S, GRG_FP64, S->u64, S->b64, 0, nrhs, nullptr));
+    // b = (D u)_r = D_rb x_b, from the coarse vector's hops only
+    GRG_TRY_HIP(launch_rb_apply(g, xb, S->d_bidx, S->nb, L->U[GRG_FP64], S->b64, nrhs, st));
     // x64 = u - z,  z = D_rr^{-1} b
     grg_status s = drr_solve_internal(S, nrhs, stats, S->u64);
     if (s != GRG_OK && s != GRG_ENOCONV) return s;
@@ -1291,7 +1291,7 @@ grg_status diag_schur_apply_internal(grg_schur S, const double *xb, double *yb, 
     const Geom &g = L->g;
     const BlasShape sh = blas_shape(g, nrhs);
     GRG_TRY_HIP(launch_scatter_coarse(xb, S->u64, S->d_bidx, S->nb, g, nrhs, st));
-    GRG_TRY(run_dslash(S, GRG_FP64, S->u64, S->b64, 0, nrhs, nullptr));
+    GRG_TRY_HIP(launch_rb_apply(g, xb, S->d_bidx, S->nb, L->U[GRG_FP64], S->b64, nrhs, st));
     GRG_TRY_HIP(launch_reusken_combine(sh, S->u64, S->b64, nullptr, nullptr, S->d_mask,
                                        1.0 / (4.0 + S->m0), S->x64, st));
     CoarseArgs c;
@@ -1321,7 +1321,7 @@ grg_status reusken_apply_internal(grg_schur S, const double *xb, double *yb, int
     GRG_TRY_HIP(launch_rest_ones(g, S->d_mask, S->t64, st));
     GRG_TRY(run_dslash(S, GRG_FP64, S->t64, S->dt64, 0, 1, nullptr));
     GRG_TRY_HIP(launch_scatter_coarse(xb, S->u64, S->d_bidx, S->nb, g, nrhs, st));
-    GRG_TRY(run_dslash(S, GRG_FP64, S->u64, S->b64, 0, nrhs, nullptr));
+    GRG_TRY_HIP(launch_rb_apply(g, xb, S->d_bidx, S->nb, L->U[GRG_FP64], S->b64, nrhs, st));
     GRG_TRY_HIP(launch_reusken_divide(sh, S->b64, S->dt64, S->d_mask, S->t64, st));
     GRG_TRY(run_dslash(S, GRG_FP64, S->t64, S->r64, 0, nrhs, nullptr));
     GRG_TRY_HIP(launch_reusken_combine(sh, S->u64, S->b64, S->r64, S->t64, S->d_mask,
