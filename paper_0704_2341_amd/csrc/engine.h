@@ -135,6 +135,11 @@ hipError_t launch_dslash_coarse(const CoarseArgs &a, hipStream_t st);
 // FP64 field, zero on the coarse sites
 hipError_t launch_rb_apply(const Geom &g, const double *xb, const int32_t *bidx, int nb, const void *U64,
                            void *out, int nrhs, hipStream_t st);
+// y_b = [D (u + sigma sum_j f_j e_j)]_b, u = x_b on the coarse sites, from the
+// kept corrections (inner precision prec) at the coarse sites' neighbours
+hipError_t launch_coarse_combine_apply(int prec, const Geom &g, const double *xb, const int32_t *qsites,
+                                       const int32_t *bidx, int nb, const void *U64, double diag,
+                                       const CombineArgs &a, double *yb, int nrhs, hipStream_t st);
 hipError_t launch_eo_hop(int prec, const EoArgs &a, int grid, hipStream_t st);
 // compact field of parity par <-> full field (zero off that parity)
 hipError_t launch_eo_scatter(int prec, const Geom &g, int nrhs, int par, const void *src, void *dst,

@@ -78,3 +78,103 @@ hipError_t launch_rb_apply(const Geom &g, const double *xb, const int32_t *bidx,
 }
 
 }  // namespace grg
+
+namespace grg {
+
+// y_b = [D w]_b with w = u + sigma sum_j f_j e_j, u = x_b on the coarse sites
+// (zero elsewhere) and the kept corrections e_j of the D_rr solve (zero on the
+// coarse sites): the S_bb apply's last step, [D (u - z)]_b, read from the
+// corrections at the coarse sites' neighbours only, instead of summing the
+// iterate over the whole lattice first.
+template <int P, int MU, bool FWD>
+__device__ __forceinline__ void coarse_hop(cpx<double> (&acc)[12], int n, int ls, const double2 *__restrict__ xb,
+                                           const int32_t *__restrict__ bidx, int nb, int r, int nrhs,
+                                           const CombineArgs &a, const double2 *__restrict__ U)
+{
+    typedef typename Store<P>::S S;
+    cpx<double> w[12], u[9];
+    const int kb = bidx[n];
+    if (kb >= 0) {
+        const double2 *v = xb + ((size_t)r * nb + kb) * 12;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) w[c] = {v[c].x, v[c].y};
+    } else {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) w[c] = {0, 0};
+        for (int j = 0; j < a.n; ++j) {
+            const double f = a.sigma * a.f[j * kMaxRhs + r];
+            const S *e = (const S *)a.e[j];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const cpx<double> ev = ldr<double>(e, fidx(n, r, c, nrhs));
+                w[c].re = fma(f, ev.re, w[c].re);
+                w[c].im = fma(f, ev.im, w[c].im);
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        const double2 x = U[lidx(ls, MU, e)];
+        u[e] = {x.x, x.y};
+    }
+    hop_math<MU, FWD>(acc, w, u);
+}
+
+template <int P, int MU>
+__device__ __forceinline__ void coarse_dir(cpx<double> (&acc)[12], int s, const SiteGeo &q, const Geom &g,
+                                           const double2 *__restrict__ xb, const int32_t *__restrict__ bidx,
+                                           int nb, int r, int nrhs, const CombineArgs &a,
+                                           const double2 *__restrict__ U)
+{
+    int sp, sm;
+    nbr(s, MU, q, g, sp, sm);
+    coarse_hop<P, MU, true>(acc, sp, s, xb, bidx, nb, r, nrhs, a, U);
+    coarse_hop<P, MU, false>(acc, sm, sm, xb, bidx, nb, r, nrhs, a, U);
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) coarse_combine_apply_kernel(Geom g, const double2 *__restrict__ xb,
+                                                                   const int32_t *__restrict__ qsites,
+                                                                   const int32_t *__restrict__ bidx, int nb,
+                                                                   const double2 *__restrict__ U, double diag,
+                                                                   CombineArgs a, double2 *__restrict__ yb,
+                                                                   int nrhs)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (k >= nb) return;
+    const int s = qsites[k];
+    const SiteGeo q = site_geo(s, g);
+    cpx<double> acc[12];
+    const double2 *v = xb + ((size_t)r * nb + k) * 12;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = {diag * v[c].x, diag * v[c].y};
+    coarse_dir<P, 0>(acc, s, q, g, xb, bidx, nb, r, nrhs, a, U);
+    coarse_dir<P, 1>(acc, s, q, g, xb, bidx, nb, r, nrhs, a, U);
+    coarse_dir<P, 2>(acc, s, q, g, xb, bidx, nb, r, nrhs, a, U);
+    coarse_dir<P, 3>(acc, s, q, g, xb, bidx, nb, r, nrhs, a, U);
+    double2 *o = yb + ((size_t)r * nb + k) * 12;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) o[c] = make_double2(acc[c].re, acc[c].im);
+}
+
+hipError_t launch_coarse_combine_apply(int prec, const Geom &g, const double *xb, const int32_t *qsites,
+                                       const int32_t *bidx, int nb, const void *U64, double diag,
+                                       const CombineArgs &a, double *yb, int nrhs, hipStream_t st)
+{
+    if (nrhs < 1 || nrhs > kMaxRhs || nb < 1 || a.n < 0 || a.n > kCorrPool) return hipErrorInvalidValue;
+    dim3 grd((nb + 255) / 256, nrhs), blk(256);
+#define CCA(PP)                                                                                        \
+    hipLaunchKernelGGL(coarse_combine_apply_kernel<PP>, grd, blk, 0, st, g, (const double2 *)xb, qsites, bidx, nb, \
+                       (const double2 *)U64, diag, a, (double2 *)yb, nrhs)
+    switch (prec) {
+    case GRG_FP64: CCA(GRG_FP64); break;
+    case GRG_FP32: CCA(GRG_FP32); break;
+    case GRG_BF16: CCA(GRG_BF16); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef CCA
+    return hipGetLastError();
+}
+
+}  // namespace grg

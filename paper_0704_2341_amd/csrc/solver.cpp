@@ -1013,7 +1013,12 @@ static grg_status pool_slot(grg_schur S, int prec, int k, void **out)
 // exact FP64 operator at every step, so it is the residual of x up to FP64
 // rounding; with params.verify it is also recomputed from x as b - A x at the
 // end, and the loop resumes from that residual if it is above tol.
-grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, const void *u_minus)
+// With xb and yb (the S_bb apply): u_minus = x_b on the coarse sites is
+// scattered into S->u64 only if the iterate is summed over the lattice, and
+// when it is not (no pool overflow, no verification) the final step writes
+// y_b = [D (u - z)]_b from the corrections directly and sets *fused.
+grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, const void *u_minus,
+                              const double *xb, double *yb, bool *fused)
 {
     grg_lattice L = S->lat;
     hipStream_t st = L->stream;
@@ -1044,7 +1049,13 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
     // the kept corrections and the part of x already summed into x64
     int npool = 0;
     bool have_x = false;
+    bool u_ready = xb == nullptr;
+    if (fused) *fused = false;
     auto combine = [&](const void *u, double sigma) -> grg_status {
+        if (u && !u_ready) {
+            GRG_TRY_HIP(launch_scatter_coarse(xb, (void *)u, S->d_bidx, S->nb, g, nrhs, st));
+            u_ready = true;
+        }
         CombineArgs c;
         for (int j = 0; j < kCorrPool; ++j) c.e[j] = j < npool ? S->epool[prec][j] : nullptr;
         c.f = S->d_fk;
@@ -1189,8 +1200,27 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
         r_src = S->r64;
         rhs_ready = true;
     }
-    // x64 = sum of the corrections, or u_minus minus it
-    GRG_TRY(combine(u_minus, u_minus ? -1.0 : 1.0));
+    if (xb && yb && fused && u_minus && !have_x) {
+        // y_b = [D (u - sum_j f_j e_j)]_b straight from the corrections
+        CombineArgs c;
+        for (int j = 0; j < kCorrPool; ++j) c.e[j] = j < npool ? S->epool[prec][j] : nullptr;
+        c.f = S->d_fk;
+        c.n = npool;
+        c.u = nullptr;
+        c.x = nullptr;
+        c.out = nullptr;
+        c.sigma = -1.0;
+        if (npool > 0)
+            GRG_TRY_HIP(hipMemcpyAsync(S->d_fk, S->h_fk, sizeof(double) * kCorrPool * kMaxRhs,
+                                       hipMemcpyHostToDevice, st));
+        GRG_TRY_HIP(launch_coarse_combine_apply(prec, g, xb, S->d_q, S->d_bidx, S->nb, L->U[GRG_FP64],
+                                                4.0 + S->m0, c, yb, nrhs, st));
+        if (npool > 0) GRG_TRY_HIP(hipStreamSynchronize(st));  // h_fk is reused next
+        *fused = true;
+    } else {
+        // x64 = sum of the corrections, or u_minus minus it
+        GRG_TRY(combine(u_minus, u_minus ? -1.0 : 1.0));
+    }
     if (stats) {
         stats->fallbacks = S->fallbacks;
         stats->iters = total;
@@ -1249,13 +1279,16 @@ grg_status schur_apply_internal(grg_schur S, const double *xb, double *yb, int n
     hipStream_t st = L->stream;
     const Geom &g = L->g;
     const BlasShape sh = blas_shape(g, nrhs);
-    // u = x on coarse sites
-    GRG_TRY_HIP(launch_scatter_coarse(xb, S->u64, S->d_bidx, S->nb, g, nrhs, st));
-    // b = (D u)_r = D_rb x_b, from the coarse vector's hops only
+    // b = (D u)_r = D_rb x_b (u = x_b on the coarse sites), from the coarse
+    // vector's hops only
     GRG_TRY_HIP(launch_rb_apply(g, xb, S->d_bidx, S->nb, L->U[GRG_FP64], S->b64, nrhs, st));
-    // x64 = u - z,  z = D_rr^{-1} b
-    grg_status s = drr_solve_internal(S, nrhs, stats, S->u64);
+    // z = D_rr^{-1} b, and y_b = [D (u - z)]_b fused into its last step, or
+    // x64 = u - z (u scattered into u64 when needed)
+    bool fused = false;
+    grg_status s = drr_solve_internal(S, nrhs, stats, S->u64, xb, yb, &fused);
     if (s != GRG_OK && s != GRG_ENOCONV) return s;
+    (void)sh;
+    if (fused) return s;
     // y_b = [D (u - z)]_b
     CoarseArgs c;
     c.in = S->x64;
