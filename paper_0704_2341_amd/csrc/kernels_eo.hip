@@ -90,9 +90,11 @@ __device__ __forceinline__ void eo_hop_k(int k, cpx<R> (&acc)[12], const PT (&p)
 // site are the sites of the other parity in the same column one slice up
 // and one down, so every input site of the column is loaded once: as the
 // forward neighbour of one output and, two slices later, the backward
-// neighbour of the next.  The two slices in between wait in LDS (a per-lane
-// ring of two slots: each lane reads and writes only its own words, so no
-// barrier is needed), which keeps the register count of the one-hop loop.
+// neighbour of the next.  The two slices in between wait in LDS (a ring of
+// two slots per wavefront, written by each lane for its own column, so no
+// barrier is needed), which keeps the register count of the one-hop loop;
+// the x hops read the slot of the current slice at the lanes of the same
+// x-row instead of loading.
 // Each XCD walks the columns of its own z-slab (an eighth of a slice), so
 // that the x, y and z neighbours, loaded by the columns next to it at nearly
 // the same time, are in its own L2.  Per-RHS sums go to red[r] (one
@@ -159,8 +161,32 @@ __device__ __forceinline__ void eo_march(const EoArgs &a, double (*red)[3])
             if (on) {
                 SiteGeo sq;
                 const int s = eo_site(h, a.po, a.g, sq);
+                // x hops from the ring: the other parity's sites of slice t in
+                // this wavefront's columns are in slot t & 1, and an x
+                // neighbour is the site of this column or of the next or
+                // previous column of the same x-row (which one: the parity of
+                // x; x-rows of Lx / 2 columns tile the 64 lanes)
+                {
+                    const int Lh = a.g.L[0] >> 1;
+                    const int xh = col % Lh, rs = lane - xh;
+                    const bool b = (s & 1) != 0;
+                    const int lp = b ? rs + (xh + 1 == Lh ? 0 : xh + 1) : lane;
+                    const int lm = b ? lane : rs + (xh == 0 ? Lh - 1 : xh - 1);
+                    PT p[12], u[9];
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) u[e] = OP::load(Uo, lidx(h, 0, e));
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) p[c] = q[t & 1][c][lp];
+                    eo_hop_k(0, acc, p, u);
+                    // U_x(s - x) at the x- neighbour's compact index
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) u[e] = OP::load(Ui, lidx(h - lane + lm, 0, e));
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) p[c] = q[t & 1][c][lm];
+                    eo_hop_k(1, acc, p, u);
+                }
 #pragma unroll 1
-                for (int k = 0; k < 6; ++k) {
+                for (int k = 2; k < 6; ++k) {
                     PT p[12], u[9];
                     eo_load_hop<OP>(k, p, u, in, Uo, Ui, s, h, sq, a.g, r, nr, false);
                     eo_hop_k(k, acc, p, u);
@@ -358,7 +384,7 @@ __global__ void __launch_bounds__(256) eo_hop_kernel(EoArgs a)
     if constexpr (HOPS == 3) {
         static_assert(IO == 0 && OP::kPacked, "t-marching form: packed compact fields only");
         eo_march<P, OP>(a, red[0]);
-    } else if constexpr (HOPS >= 4) {
+    } else if constexpr (HOPS == 4 || HOPS == 5) {
         static_assert(IO == 0, "RHS-simultaneous form: compact fields only");
         eo_multi<P, OP, HOPS - 2>(a, red);
     } else {
@@ -377,14 +403,64 @@ __global__ void __launch_bounds__(256) eo_hop_kernel(EoArgs a)
         const bool on = valid && mk[h] == 0;
         SiteGeo q;
         int s = 0;
-        if (on || (valid && out_full)) s = eo_site(h, a.po, a.g, q);
+        if (on || (valid && (out_full || HOPS == 6))) s = eo_site(h, a.po, a.g, q);
         const int r0 = grp * a.RG, r1 = min(r0 + a.RG, a.nrhs);
+#pragma unroll 1
         for (int r = r0; r < r1; ++r) {
             cpx<R> acc[12];
 #pragma unroll
             for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
+            // HOPS = 6: the x hops' spinors from lane shuffles.  The other
+            // parity's site with this site's compact index is its x neighbour
+            // on one side (which side: the parity of x); the x neighbour on the
+            // other side is the next or previous half-site of the same x-row,
+            // held by another lane of this wavefront (x-rows of Lx / 2
+            // half-sites tile the 64 lanes).  Done with every lane active
+            // (the result of a lane whose site is not computed is dropped).
+            if constexpr (HOPS == 6) {
+                const int Lh = a.g.L[0] >> 1;
+                const int xh = h % Lh, rs = lane - xh;
+                const int lp = rs + (xh + 1 == Lh ? 0 : xh + 1);
+                const int lm = rs + (xh == 0 ? Lh - 1 : xh - 1);
+                const bool b = (s & 1) != 0;
+                const int hv = valid ? h : 0;
+                PT self[12];
+#pragma unroll
+                for (int c = 0; c < 12; ++c) self[c] = OP::load(in, fidx(hv, r, c, a.nrhs));
+                {
+                    PT xs[12], u[9];
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) u[e] = OP::load(Uo, lidx(hv, 0, e));
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) {
+                        const PT v = (PT)__shfl((int)self[c], lp, 64);
+                        xs[c] = b ? v : self[c];
+                    }
+                    eo_hop_k(0, acc, xs, u);
+                }
+                {
+                    // U_x(s - x) sits at the x- neighbour's compact index
+                    const int hm = b ? hv : hv - xh + (xh == 0 ? Lh - 1 : xh - 1);
+                    PT xs[12], u[9];
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) u[e] = OP::load(Ui, lidx(hm, 0, e));
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) {
+                        const PT v = (PT)__shfl((int)self[c], lm, 64);
+                        xs[c] = b ? self[c] : v;
+                    }
+                    eo_hop_k(1, acc, xs, u);
+                }
+            }
             if (on) {
-                if constexpr (HOPS == 2 && OP::kPacked) {
+                if constexpr (HOPS == 6) {
+#pragma unroll 1
+                    for (int k = 2; k < 8; ++k) {
+                        PT p[12], u[9];
+                        eo_load_hop<OP>(k, p, u, in, Uo, Ui, s, h, q, a.g, r, a.nrhs, inf);
+                        eo_hop_k(k, acc, p, u);
+                    }
+                } else if constexpr (HOPS == 2 && OP::kPacked) {
                     PT pa[12], pb[12], ua[9], ub[9];
                     eo_load_hop<OP>(0, pa, ua, in, Uo, Ui, s, h, q, a.g, r, a.nrhs, inf);
 #pragma unroll 1
@@ -527,9 +603,15 @@ hipError_t launch_eo_hop(int prec, const EoArgs &a, int grid, hipStream_t st)
     if (a.hops == 3 && io == 0) {
         // t-marching: packed BF16, 256 threads, whole 64-column tiles per slice
         if (prec != GRG_BF16 || a.SB != 256 || a.march < 1 || a.g.L[3] < 2 || a.Vh % a.g.L[3] ||
-            (a.Vh / a.g.L[3]) % 64)
+            (a.Vh / a.g.L[3]) % 64 || a.g.L[0] < 2 || 64 % (a.g.L[0] / 2))
             return hipErrorInvalidValue;
         hipLaunchKernelGGL((eo_hop_kernel<GRG_BF16, 3, 0>), grd, blk, 0, st, a);
+        return hipGetLastError();
+    }
+    if (a.hops == 6 && io == 0) {
+        // x hops from lane shuffles: packed BF16, x-rows tiling the wavefront
+        if (prec != GRG_BF16 || 64 % (a.g.L[0] / 2) != 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((eo_hop_kernel<GRG_BF16, 6, 0>), grd, blk, 0, st, a);
         return hipGetLastError();
     }
     if ((a.hops == 4 || a.hops == 5) && io == 0) {

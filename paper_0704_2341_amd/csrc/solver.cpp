@@ -546,9 +546,13 @@ bool eo_launch_ok(const Geom &gh, int prec, int nrhs, const DslashTune &t)
     // form with SB and RG)
     const int Lt = gh.L[3];
     const bool march_ok = t.split == 3 && prec == GRG_BF16 && t.SB == 256 && t.march >= 1 &&
-                          t.march <= Lt && Lt >= 2 && gh.V % Lt == 0 && (gh.V / Lt) % 64 == 0;
-    // split 4, 5: RG = 2, 3 right-hand sides carried through each hop together
-    const bool multi_ok = (t.split == 4 || t.split == 5) && prec == GRG_BF16 && t.RG == t.split - 2;
+                          t.march <= Lt && Lt >= 2 && gh.V % Lt == 0 && (gh.V / Lt) % 64 == 0 &&
+                          gh.L[0] >= 2 && 64 % (gh.L[0] / 2) == 0;
+    // split 4, 5: RG = 2, 3 right-hand sides carried through each hop together;
+    // split 6: one hop per iteration with the x hops' spinors from lane
+    // shuffles (x-rows of half-sites must tile a wavefront)
+    const bool multi_ok = ((t.split == 4 || t.split == 5) && prec == GRG_BF16 && t.RG == t.split - 2) ||
+                          (t.split == 6 && prec == GRG_BF16 && gh.L[0] >= 2 && 64 % (gh.L[0] / 2) == 0);
     return (t.SB == 64 || t.SB == 128 || t.SB == 256) && t.RG >= 1 && t.RG <= nrhs &&
            (t.split == 1 || (t.split == 2 && prec == GRG_BF16) || march_ok || multi_ok) && t.grid >= 8 &&
            t.grid % 8 == 0 && t.grid <= kMaxGridValue && t.chunk >= 0 && t.march >= 0 && gh.V > 0;
@@ -587,8 +591,8 @@ grg_status tune_eo(grg_schur S, int prec, int nrhs, int reps)
     for (int sb : {64, 128, 256}) {
         for (int rg = 1; rg <= nrhs; ++rg) {
             if ((nrhs % rg && rg != nrhs) || (rg > 4 && rg != nrhs)) continue;
-            for (int hops = 1; hops <= (prec == GRG_BF16 ? 5 : 1); ++hops) {
-                if (hops == 3 || (hops >= 4 && rg != hops - 2)) continue;
+            for (int hops = 1; hops <= (prec == GRG_BF16 ? 6 : 1); ++hops) {
+                if (hops == 3 || ((hops == 4 || hops == 5) && rg != hops - 2)) continue;
                 DslashTune t = default_eo_tune(gh, prec, nrhs);
                 t.SB = sb;
                 t.RG = rg;

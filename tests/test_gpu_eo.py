@@ -109,6 +109,8 @@ RA_LAUNCHES = {
     "march-small-grid": (256, 3, 3, 8, 0, 2),
     "two-rhs-per-hop": (128, 2, 4, 48, 0, 0),
     "three-rhs-per-hop": (64, 3, 5, 40, 8, 0),
+    "x-hops-from-lanes": (256, 3, 6, 64, 0, 0),
+    "x-hops-from-lanes-sb64": (64, 1, 6, 24, 8, 0),
 }
 
 
