@@ -51,18 +51,18 @@ PREC_ID = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 
 def eo_bytes_per_launch(prec: str, volume: int, nrhs: int, iters: int, outer: int) -> float:
-    """Compulsory bytes of the even-odd half-lattice stencils, averaged over
-    one solve's launches: the reduced operator's first half reads one parity
-    and writes the other (V sites' fields in all), its second half and the two
-    per-outer-step halves (right-hand side and reconstruction) also read a
-    field of the output parity (1.5 V); every half reads all V sites' links
-    (the forward links of one parity, the backward ones of the other)."""
+    """Compulsory bytes of the reduced operator's half-lattice stencils (the
+    timed launches: every iteration runs one first and one second half),
+    averaged: the first half reads one parity and writes the other (V sites'
+    fields in all), the second also reads a field of the output parity
+    (1.5 V); each half reads all V sites' links (the forward links of one
+    parity, the backward ones of the other).  The once-per-outer-step
+    full-layout halves are not among the timed launches."""
     b = REAL_BYTES[prec]
     spinor, links = nrhs * 24 * b, 72 * b
     k1 = volume * spinor + volume * links
     k2 = 1.5 * volume * spinor + volume * links
-    n1, n2 = iters, iters + 2 * outer
-    return (n1 * k1 + n2 * k2) / max(1, n1 + n2)
+    return (k1 + k2) / 2
 
 
 def launch_descriptor(info: dict, prec: str, launches: int, eo: bool = False) -> dict:
@@ -70,9 +70,9 @@ def launch_descriptor(info: dict, prec: str, launches: int, eo: bool = False) ->
     work-items per dispatch."""
     p = PREC_ID[prec]
     if eo:
-        # every instance of the half-lattice stencil (reduced operator, and the
-        # right-hand side / reconstruction steps) in this precision
-        sym, gs = f"eo_hop_kernel<{p}, ", info["grid"] * info["SB"]
+        # the compact half-stencils of the reduced operator in the tuned form
+        # (hop schedule info["split"], compact fields: IO 0)
+        sym, gs = f"eo_hop_kernel<{p}, {info['split']}, 0>", info["grid"] * info["SB"]
     elif info["march"] > 0:
         sym, gs = f"dslash_march_kernel<{p}>", info["grid"] * 64 * info["RG"]
     else:

@@ -99,6 +99,9 @@ struct grg_schur_s {
     void *bicg_f[3][5] = {};
     double2 *bicg_sc = nullptr;
     grg::DslashTune eotune[3][grg::kMaxRhs + 1];
+    // the launch of the full-layout half-stencils (first and last step of a
+    // reduced solve) when eotune holds the t-marching form
+    grg::DslashTune eotune_io[3][grg::kMaxRhs + 1];
     // reduction scratch
     double *partials = nullptr;
     size_t partials_elems = 0;

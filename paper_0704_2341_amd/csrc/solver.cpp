@@ -502,6 +502,10 @@ static grg_status eo_hop(grg_schur S, int prec, const DslashTune &t, const void 
                          int in2_full = 0, const void *partner = nullptr)
 {
     grg_lattice L = S->lat;
+    // the full-layout steps run the one-hop form: with the t-marching form
+    // tuned, in the best one-hop shape the tuner found
+    const bool io = in_full || in2_full || partner;
+    const DslashTune &tu = io && t.split == 3 && S->eotune_io[prec][nrhs].valid ? S->eotune_io[prec][nrhs] : t;
     EoArgs a;
     a.in = in;
     a.in2 = in2;
@@ -515,11 +519,11 @@ static grg_status eo_hop(grg_schur S, int prec, const DslashTune &t, const void 
     a.Vh = L->g.V / 2;
     a.Vhs = L->Vhs;
     a.nrhs = nrhs;
-    a.SB = t.SB;
-    a.RG = t.RG;
-    a.hops = t.split;
-    a.chunk = t.chunk;
-    a.march = t.march;
+    a.SB = tu.SB;
+    a.RG = tu.RG;
+    a.hops = tu.split;
+    a.chunk = tu.chunk;
+    a.march = tu.march;
     a.partials = partials;
     a.dot_with = dot_with;
     a.active = active;
@@ -527,10 +531,12 @@ static grg_status eo_hop(grg_schur S, int prec, const DslashTune &t, const void 
     a.in2_full = in2_full;
     a.out_full = partner != nullptr;
     a.partner = partner;
+    // profiled: the compact half-stencils of the reduced operator (the
+    // per-iteration launches), not the full-layout first and last steps
     ProfilePool &P = S->prof;
-    const bool ev = P.on && P.used < (int)P.start.size();
+    const bool ev = !io && P.on && P.used < (int)P.start.size();
     if (ev) GRG_TRY_HIP(hipEventRecord(P.start[P.used], L->stream));
-    GRG_TRY_HIP(launch_eo_hop(prec, a, t.grid, L->stream));
+    GRG_TRY_HIP(launch_eo_hop(prec, a, tu.grid, L->stream));
     if (ev) {
         GRG_TRY_HIP(hipEventRecord(P.stop[P.used], L->stream));
         P.prec[P.used] = prec + 3;
@@ -606,6 +612,10 @@ grg_status tune_eo(grg_schur S, int prec, int nrhs, int reps)
     }
     std::sort(cands.begin(), cands.end(), [](const DslashTune &a, const DslashTune &b) { return a.ms < b.ms; });
     DslashTune best = cands.empty() ? default_eo_tune(gh, prec, nrhs) : cands[0];
+    DslashTune best_io;  // the best one-hop shape, for the full-layout steps
+    best_io.ms = 1e30f;
+    for (const DslashTune &c : cands)
+        if (c.split == 1 && c.ms < best_io.ms) best_io = c;
     for (size_t i = 0; i < std::min<size_t>(2, cands.size()); ++i) {
         const long items = (long)((gh.V + cands[i].SB - 1) / cands[i].SB) *
                            ((nrhs + cands[i].RG - 1) / cands[i].RG);
@@ -625,6 +635,7 @@ grg_status tune_eo(grg_schur S, int prec, int nrhs, int reps)
                 if (ch > 0 && ch * 8 >= items) continue;
                 timeit(t);
                 if (t.ms < best.ms) best = t;
+                if (t.split == 1 && t.ms < best_io.ms) best_io = t;
             }
         }
     }
@@ -656,6 +667,8 @@ grg_status tune_eo(grg_schur S, int prec, int nrhs, int reps)
     if (status != GRG_OK) return status;
     best.valid = 1;
     S->eotune[prec][nrhs] = best;
+    best_io.valid = best_io.ms < 1e29f ? 1 : 0;
+    S->eotune_io[prec][nrhs] = best_io;
     return GRG_OK;
 }
 

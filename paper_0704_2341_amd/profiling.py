@@ -5,6 +5,7 @@ Runs on the host, on CSV files that ``rocprofv3 --output-format csv`` wrote:
   stats    kernel-trace summary of one command: the busiest kernels, and the
            average duration of the dominant stencil launch (the same launches
            that the benchmark times with HIP events)
+  counters per-dispatch averages of any counter sets for chosen kernels
   traffic  HBM bytes per launch of the dominant stencil from two counter runs
            (FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch), each scaled by
            what the same counter reads for a plain copy kernel of known size
@@ -185,6 +186,28 @@ def traffic_table(fetch_dir, write_dir, fetch_log, write_log, command, out=TRAFF
     return table, key
 
 
+def counters_summary(dirs, kernels, command_lines, title, note=""):
+    """Average of every counter per dispatch, per kernel (name substring)
+    and grid, over the counter runs in `dirs` (one counter set per run)."""
+    rows = []
+    for d in dirs:
+        rows.extend(_csv(d, "_counter_collection.csv"))
+    agg = {}
+    for r in rows:
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        if not any(k in name for k in kernels):
+            continue
+        key = (name, _grid_size(r), r["Counter_Name"])
+        agg.setdefault(key, []).append(float(r["Counter_Value"]))
+    lines = ["# " + title, "", "Commands (from the repository root, `cd /tmp && export TMPDIR=/tmp` "
+             "first), one counter set per run:", ""]
+    lines += ["    " + c for c in command_lines]
+    lines += ["", note, "", "| kernel | work-items | dispatches | counter | average |", "|---|---:|---:|---|---:|"]
+    for (name, gs, cn), v in sorted(agg.items()):
+        lines.append(f"| `{name.replace('|', '/')}` | {gs} | {len(v)} | {cn} | {sum(v) / len(v):.4g} |")
+    return "\n".join(lines) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -197,7 +220,21 @@ def main(argv=None):
     for k in ("--fetch", "--write", "--fetch-log", "--write-log", "--command"):
         t.add_argument(k, required=True)
     t.add_argument("--out", default=TRAFFIC_FILE)
+    c = sub.add_parser("counters")
+    c.add_argument("--dirs", nargs="+", required=True)
+    c.add_argument("--kernels", nargs="+", required=True)
+    c.add_argument("--command", action="append", required=True)
+    c.add_argument("--title", required=True)
+    c.add_argument("--note", default="")
+    c.add_argument("--out")
     a = ap.parse_args(argv)
+    if a.cmd == "counters":
+        text = counters_summary(a.dirs, a.kernels, a.command, a.title, a.note)
+        if a.out:
+            with open(a.out, "w") as f:
+                f.write(text)
+        sys.stdout.write(text)
+        return
     if a.cmd == "stats":
         text = stats_summary(a.trace, a.bench_log, a.command)
         if a.out:
