@@ -395,7 +395,9 @@ typedef struct {
 } grg_batch_member;
 
 /* params->inner / inner_tol / tol / max_iter / max_outer as for one lattice;
- * check_every = inner iterations per graph replay.  stream: the caller's
+ * check_every = inner iterations per graph replay; the inner solve is
+ * minimal residual on D_rr (params->method other than 0 gives
+ * GRG_EUNSUPPORTED; restart and eo are not used).  stream: the caller's
  * stream, waited on at entry and made to wait for the result at exit. */
 grg_status grg_batch_create(const grg_batch_member *members, int count, int nrhs,
                             const grg_solver_params *params, void *stream, grg_batch *out);

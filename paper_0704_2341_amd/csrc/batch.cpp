@@ -357,6 +357,8 @@ grg_status grg_batch_create(const grg_batch_member *m, int count, int nrhs,
     if (!(prm.tol > 0 && prm.tol < 1) || prm.max_iter < 1 || prm.max_outer < 1 || prm.check_every < 1 ||
         prm.inner < 0 || prm.inner > 2 || (prm.inner != GRG_FP64 && !(prm.inner_tol > 0 && prm.inner_tol < 1)))
         return set_error("bad solver parameters"), GRG_EINVAL;
+    if (prm.method != 0)
+        return set_error("the batch runs minimal residual only (params.method must be 0)"), GRG_EUNSUPPORTED;
     std::vector<BatchMember> mem(count);
     long long Vtot = 0, nbtot = 0, coff = 0;
     for (int i = 0; i < count; ++i) {

@@ -131,3 +131,14 @@ def test_48_lattice_workload():
                                          xs[i][:1], tol=1e-13)
         assert rel_err(ys[i][:1], want) < 1e-9, i
     grg.grg_batch_destroy(b)
+
+
+def test_bicgstab_is_rejected():
+    """The batch's captured inner loop is minimal residual only."""
+    import paper_0704_2341_amd as grg
+
+    ensure_built()
+    ms = members([dict(dims=(4, 4, 4, 4), m0=0.1, seed=4005)], [(1, False)])
+    p = grg.grg_solver_params_default(tol=1e-10, inner="fp32", inner_tol=1e-5, method="bicgstab")
+    with pytest.raises(grg.GrgError):
+        grg.grg_batch_create(ms, 2, p)
