@@ -231,11 +231,14 @@ grg_status grg_schur_tune(grg_schur s, int nrhs);
  * contiguous eighth of the lattice per XCD), time-chunk length of the
  * t-marching kernel (0 = site-parallel kernel)}; *ms = its tuned time per
  * launch, or -1 if untuned (defaults in use).  precision 3..5 reports the
- * half-lattice stencil of the even-odd reduced solve in precision - 3: hop
- * schedule 3 (BF16 only, info[0] = 256) is its t-marching form, a
- * workgroup holding 64 columns of the half lattice and four RHS, walking
- * info[5] time slices, with info[1] the RHS per workgroup of the one-hop
- * form that its full-layout steps use; otherwise info[5] = 0. */
+ * half-lattice stencil of the even-odd reduced solve in precision - 3, whose
+ * hop schedules 3..6 are BF16 only: 3 is its t-marching form (info[0] =
+ * 256), a workgroup holding 64 columns of the half lattice and four RHS,
+ * walking info[5] time slices; 4 and 5 carry info[1] = 2 or 3 RHS through
+ * each hop together; 6 takes the x hops' spinors from lane shuffles;
+ * info[5] = 0 except with 3.  With schedule 3, the full-layout first and
+ * last steps of a reduced solve run the one-hop shape that tuning found
+ * faster for them, if it found one, else schedule 3 as well. */
 grg_status grg_schur_tune_info(grg_schur s, int precision, int nrhs, int32_t info[6], float *ms);
 
 /* Pin the stencil launch for (precision, nrhs), e.g. from a saved tuning

@@ -100,7 +100,8 @@ struct grg_schur_s {
     double2 *bicg_sc = nullptr;
     grg::DslashTune eotune[3][grg::kMaxRhs + 1];
     // the launch of the full-layout half-stencils (first and last step of a
-    // reduced solve) when eotune holds the t-marching form
+    // reduced solve) when eotune holds the t-marching form and the tuner found
+    // this one-hop shape faster for them (not valid: they run eotune too)
     grg::DslashTune eotune_io[3][grg::kMaxRhs + 1];
     // reduction scratch
     double *partials = nullptr;

@@ -99,9 +99,12 @@ __device__ __forceinline__ void eo_hop_k(int k, cpx<R> (&acc)[12], const PT (&p)
 // that the x, y and z neighbours, loaded by the columns next to it at nearly
 // the same time, are in its own L2.  Per-RHS sums go to red[r] (one
 // wavefront per RHS of a workgroup, so no two wavefronts share a row).
-template <int P, class OP>
+template <int P, class OP, int IO>
 __device__ __forceinline__ void eo_march(const EoArgs &a, double (*red)[3])
 {
+    // IO as for eo_hop_kernel: 0 compact fields, 1 in and in2 in the full
+    // layout, 2 in2 and out in the full layout (with the partner copy)
+    constexpr bool in_full = IO == 1, in2_full = IO >= 1, out_full = IO == 2;
     typedef typename Store<P>::S S;
     typedef typename Store<P>::R R;
     typedef typename OP::T PT;
@@ -126,6 +129,15 @@ __device__ __forceinline__ void eo_march(const EoArgs &a, double (*red)[3])
     const int nx = ntx * nq * nc;
     const int nr = a.nrhs;
     PT (*q)[12][64] = ring[wave];
+    // element index of the input site with compact index hq (other parity)
+    auto iidx = [&](int hq) -> int {
+        if constexpr (in_full) {
+            SiteGeo tq;
+            return eo_site(hq, 1 - a.po, a.g, tq);
+        } else {
+            return hq;
+        }
+    };
     for (int j = slot; j < nx; j += slots) {
         const int quad = j % nq, rest = j / nq;
         const int T = T0 + rest % ntx, ch = rest / ntx;
@@ -139,8 +151,8 @@ __device__ __forceinline__ void eo_march(const EoArgs &a, double (*red)[3])
             const int tm = t0 == 0 ? Lt - 1 : t0 - 1;
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                q[(t0 - 1) & 1][c][lane] = OP::load(in, fidx(tm * Vs3 + col, r, c, nr));
-                q[t0 & 1][c][lane] = OP::load(in, fidx(t0 * Vs3 + col, r, c, nr));
+                q[(t0 - 1) & 1][c][lane] = OP::load(in, fidx(iidx(tm * Vs3 + col), r, c, nr));
+                q[t0 & 1][c][lane] = OP::load(in, fidx(iidx(t0 * Vs3 + col), r, c, nr));
             }
         }
         double dre = 0, dim = 0, dqq = 0;
@@ -153,14 +165,17 @@ __device__ __forceinline__ void eo_march(const EoArgs &a, double (*red)[3])
             // the forward t-neighbour: used at the end of this slice, then
             // kept for the output two slices up
             PT qc[12];
+            {
+                const int fi = iidx(hf);
 #pragma unroll
-            for (int c = 0; c < 12; ++c) qc[c] = OP::load(in, fidx(hf, r, c, nr));
+                for (int c = 0; c < 12; ++c) qc[c] = OP::load(in, fidx(fi, r, c, nr));
+            }
+            SiteGeo sq;
+            const int s = eo_site(h, a.po, a.g, sq);
             cpx<R> acc[12];
 #pragma unroll
             for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
             if (on) {
-                SiteGeo sq;
-                const int s = eo_site(h, a.po, a.g, sq);
                 // x hops from the ring: the other parity's sites of slice t in
                 // this wavefront's columns are in slot t & 1, and an x
                 // neighbour is the site of this column or of the next or
@@ -188,7 +203,7 @@ __device__ __forceinline__ void eo_march(const EoArgs &a, double (*red)[3])
 #pragma unroll 1
                 for (int k = 2; k < 6; ++k) {
                     PT p[12], u[9];
-                    eo_load_hop<OP>(k, p, u, in, Uo, Ui, s, h, sq, a.g, r, nr, false);
+                    eo_load_hop<OP>(k, p, u, in, Uo, Ui, s, h, sq, a.g, r, nr, in_full);
                     eo_hop_k(k, acc, p, u);
                 }
                 {
@@ -210,19 +225,26 @@ __device__ __forceinline__ void eo_march(const EoArgs &a, double (*red)[3])
 #pragma unroll
             for (int c = 0; c < 12; ++c) q[(t + 1) & 1][c][lane] = qc[c];
             R sre = 0, sim = 0, sqq = 0;
+            const bool act = a.active == nullptr || a.active[r] != 0;
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 const size_t i = fidx(h, r, c, nr);
                 cpx<R> o = {0, 0};
-                if (on) {
+                if (on && act) {
                     o = {be * acc[c].re, be * acc[c].im};
                     if (in2) {
-                        const cpx<R> v = ldr<R>(in2, i);
+                        const cpx<R> v = ldr<R>(in2, in2_full ? fidx(s, r, c, nr) : i);
                         o.re = fma(al, v.re, o.re);
                         o.im = fma(al, v.im, o.im);
                     }
                 }
-                stc(out, i, o);
+                if constexpr (out_full) {
+                    // this site, and the other parity's site of the same index
+                    stc(out, fidx(s, r, c, nr), o);
+                    out[fidx(s ^ 1, r, c, nr)] = ((const S *)a.partner)[i];
+                } else {
+                    stc(out, i, o);
+                }
                 if (dots && on) {
                     const cpx<R> v = ldr<R>((const S *)a.dot_with, i);
                     sre = fma(o.re, v.re, fma(o.im, v.im, sre));
@@ -382,8 +404,8 @@ __global__ void __launch_bounds__(256) eo_hop_kernel(EoArgs a)
         __syncthreads();
     }
     if constexpr (HOPS == 3) {
-        static_assert(IO == 0 && OP::kPacked, "t-marching form: packed compact fields only");
-        eo_march<P, OP>(a, red[0]);
+        static_assert(OP::kPacked, "t-marching form: packed fields only");
+        eo_march<P, OP, IO>(a, red[0]);
     } else if constexpr (HOPS == 4 || HOPS == 5) {
         static_assert(IO == 0, "RHS-simultaneous form: compact fields only");
         eo_multi<P, OP, HOPS - 2>(a, red);
@@ -600,12 +622,14 @@ hipError_t launch_eo_hop(int prec, const EoArgs &a, int grid, hipStream_t st)
     else if (a.in_full || a.in2_full || a.out_full) return hipErrorInvalidValue;
     dim3 blk(a.SB), grd(grid);
     const bool pipe = a.hops == 2 && prec == GRG_BF16 && io == 0;
-    if (a.hops == 3 && io == 0) {
+    if (a.hops == 3) {
         // t-marching: packed BF16, 256 threads, whole 64-column tiles per slice
         if (prec != GRG_BF16 || a.SB != 256 || a.march < 1 || a.g.L[3] < 2 || a.Vh % a.g.L[3] ||
             (a.Vh / a.g.L[3]) % 64 || a.g.L[0] < 2 || 64 % (a.g.L[0] / 2))
             return hipErrorInvalidValue;
-        hipLaunchKernelGGL((eo_hop_kernel<GRG_BF16, 3, 0>), grd, blk, 0, st, a);
+        if (io == 1) hipLaunchKernelGGL((eo_hop_kernel<GRG_BF16, 3, 1>), grd, blk, 0, st, a);
+        else if (io == 2) hipLaunchKernelGGL((eo_hop_kernel<GRG_BF16, 3, 2>), grd, blk, 0, st, a);
+        else hipLaunchKernelGGL((eo_hop_kernel<GRG_BF16, 3, 0>), grd, blk, 0, st, a);
         return hipGetLastError();
     }
     if (a.hops == 6 && io == 0) {

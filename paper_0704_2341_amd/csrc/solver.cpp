@@ -502,8 +502,8 @@ static grg_status eo_hop(grg_schur S, int prec, const DslashTune &t, const void 
                          int in2_full = 0, const void *partner = nullptr)
 {
     grg_lattice L = S->lat;
-    // the full-layout steps run the one-hop form: with the t-marching form
-    // tuned, in the best one-hop shape the tuner found
+    // the full-layout steps: with the t-marching form tuned, in the one-hop
+    // shape the tuner recorded for them if it found that one faster
     const bool io = in_full || in2_full || partner;
     const DslashTune &tu = io && t.split == 3 && S->eotune_io[prec][nrhs].valid ? S->eotune_io[prec][nrhs] : t;
     EoArgs a;
@@ -548,8 +548,7 @@ static grg_status eo_hop(grg_schur S, int prec, const DslashTune &t, const void 
 
 bool eo_launch_ok(const Geom &gh, int prec, int nrhs, const DslashTune &t)
 {
-    // split 3: the t-marching form (its full-layout steps run the one-hop
-    // form with SB and RG)
+    // split 3: the t-marching form
     const int Lt = gh.L[3];
     const bool march_ok = t.split == 3 && prec == GRG_BF16 && t.SB == 256 && t.march >= 1 &&
                           t.march <= Lt && Lt >= 2 && gh.V % Lt == 0 && (gh.V / Lt) % 64 == 0 &&
@@ -662,12 +661,45 @@ grg_status tune_eo(grg_schur S, int prec, int nrhs, int reps)
             }
         }
     }
+    best_io.valid = best_io.ms < 1e29f ? 1 : 0;
+    // the full-layout first and last steps with the t-marching form tuned:
+    // that form or the best one-hop shape, whichever runs the pair faster
+    if (status == GRG_OK && best.split == 3 && best_io.valid) {
+        status = ensure_inner(S, prec);
+        const int P = S->eo_par, Q = 1 - P;
+        const double d = 4.0 + S->m0;
+        void *fb = S->in_r[prec], *fo = S->in_q[prec];
+        auto time_io = [&](const DslashTune &t) -> float {
+            float ms = 1e30f;
+            for (int k = 0; k <= reps && status == GRG_OK; ++k) {
+                if (k == 1 && hipEventRecord(e0, st) != hipSuccess) status = GRG_EHIP;
+                if (status == GRG_OK)
+                    status = eo_hop(S, prec, t, fb, fb, f[0], P, 1.0, -1.0 / d, nrhs, nullptr, nullptr,
+                                    nullptr, 1, 1);
+                if (status == GRG_OK)
+                    status = eo_hop(S, prec, t, f[1], fb, fo, Q, 1.0 / d, -1.0 / d, nrhs, nullptr,
+                                    nullptr, nullptr, 0, 1, f[1]);
+            }
+            if (status == GRG_OK &&
+                (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                status = GRG_EHIP;
+            if (status == GRG_OK) {
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                ms /= reps;
+            }
+            return ms;
+        };
+        // with no one-hop shape recorded the full-layout steps run best itself
+        S->eotune_io[prec][nrhs].valid = 0;
+        const float ms_march = time_io(best);
+        const float ms_one = time_io(best_io);
+        if (ms_march <= ms_one) best_io.valid = 0;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (status != GRG_OK) return status;
     best.valid = 1;
     S->eotune[prec][nrhs] = best;
-    best_io.valid = best_io.ms < 1e29f ? 1 : 0;
     S->eotune_io[prec][nrhs] = best_io;
     return GRG_OK;
 }

@@ -159,3 +159,34 @@ def test_march_launch_rejected_without_whole_tiles():
         lat.grg.grg_schur_set_launch(s.h, "bf16", 2, (256, 1, 3, 8, 0, 5), eo=True)
     s.close()
     lat.close()
+
+
+@pytest.mark.parametrize("method", ["gcr", "bicgstab"])
+@pytest.mark.parametrize("kind,inv", [("I", False), ("II", True)])
+def test_march_full_layout_steps(method, kind, inv):
+    """With the t-marching launch pinned before any tuning, the first and
+    last steps of every reduced solve (full-layout input, and output with the
+    other parity copied in) run that form too: same solution as the
+    unreduced solve, including a zero right-hand side that takes no step and
+    a ragged last group of four RHS."""
+    dims = (16, 8, 8, 8)
+    lat = Lattice(dims, 0.5, 27)
+    kw = dict(tol=1e-12, inner="bf16", inner_tol=1e-2, max_rhs=5, max_iter=4000, method=method)
+    s1 = lat.schur(-0.2, kind, inv, eo=1, **kw)
+    s0 = lat.schur(-0.2, kind, inv, eo=0, **kw)
+    lat.grg.grg_schur_set_launch(s1.h, "bf16", 5, (256, 3, 3, 40, 0, 3), eo=True)
+    assert lat.grg.grg_schur_tune_info(s1.h, "bf16", 5, eo=True)["split"] == 3
+    b = rest_rhs(lat, s1, 5, 27)
+    b[3] = 0
+    print(f"march full-layout steps {method} {kind} inv={inv}", flush=True)
+    x1, st1 = s1.drr_solve(b)
+    x0, st0 = s0.drr_solve(b)
+    assert st1["converged"] and st0["converged"]
+    assert rel_err(x1, x0) < 1e-10
+    assert not np.any(x1[3])
+    rr = matfree.drr_residual(lat.links, dims, -0.2, s1.q, s1.nb, b, x1)
+    assert np.all(rr <= 1e-12 * (1 + 1e-6)), rr
+    assert not np.any(x1.reshape(5, lat.V, 12)[:, np.asarray(s1.q[: s1.nb])])
+    s1.close()
+    s0.close()
+    lat.close()
