@@ -98,10 +98,14 @@ __device__ __forceinline__ void hop_math(cpx<R> (&acc)[12], const cpx<R> (&p)[12
 // two-way BF16 dot product (products exact in FP32, sums in FP32).  By
 // linearity U h = U psi_up +/- U (B psi_lo), so the projected h is never
 // rounded: each complex multiply-add of a link entry m with a packed x is two
-// dot products against the link forms
+// dot products,
 //     U x:      re = (m.re, -m.im).x    im = (m.im, m.re).x
 //     U^+ x:    re = (m.re,  m.im).x    im = (-m.im, m.re).x
-// and the B_mu phases of psi_lo are half swaps and sign flips of its words.
+// The sign flips are the dot product's negation of the low or high half of a
+// source, not instructions of their own; the B_mu phases of psi_lo are half
+// swaps and sign flips too, and a half swap of x is moved onto the link
+// (a.swap(x) = swap(a).x), so a hop spends one half swap per link entry
+// beyond its 72 dot products.
 __device__ __forceinline__ float dot2bf(uint32_t a, uint32_t b, float c)
 {
     return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_v, a),
@@ -110,47 +114,93 @@ __device__ __forceinline__ float dot2bf(uint32_t a, uint32_t b, float c)
 __device__ __forceinline__ uint32_t swap_halves(uint32_t w) { return (w << 16) | (w >> 16); }
 constexpr uint32_t kNegHi = 0x80000000u, kNegLo = 0x00008000u, kNegBoth = 0x80008000u;
 
+// c + (-1)^NL a.lo b.lo + (-1)^NH a.hi b.hi (Z: c = 0), the VOP3P dot
+// product with its source negations.  Written as assembly, so the compiler's
+// hazard tracking does not see it as a dot product: a chain of these reads
+// only its own results as the accumulator (forwarded between dot products of
+// one opcode), and dot_fence closes a chain before any other instruction
+// reads its result.
+template <int NL, int NH, bool Z = false>
+__device__ __forceinline__ float dot2n(uint32_t a, uint32_t b, float c = 0.f)
+{
+    float d;
+    if constexpr (Z) {
+        if constexpr (NL && NH)
+            asm("v_dot2_f32_bf16 %0, %1, %2, 0 neg_lo:[1,0,0] neg_hi:[1,0,0]" : "=v"(d) : "v"(a), "v"(b));
+        else if constexpr (NL)
+            asm("v_dot2_f32_bf16 %0, %1, %2, 0 neg_lo:[1,0,0]" : "=v"(d) : "v"(a), "v"(b));
+        else if constexpr (NH)
+            asm("v_dot2_f32_bf16 %0, %1, %2, 0 neg_hi:[1,0,0]" : "=v"(d) : "v"(a), "v"(b));
+        else
+            asm("v_dot2_f32_bf16 %0, %1, %2, 0" : "=v"(d) : "v"(a), "v"(b));
+    } else {
+        if constexpr (NL && NH)
+            asm("v_dot2_f32_bf16 %0, %1, %2, %3 neg_lo:[1,0,0] neg_hi:[1,0,0]" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+        else if constexpr (NL)
+            asm("v_dot2_f32_bf16 %0, %1, %2, %3 neg_lo:[1,0,0]" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+        else if constexpr (NH)
+            asm("v_dot2_f32_bf16 %0, %1, %2, %3 neg_hi:[1,0,0]" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+        else
+            asm("v_dot2_f32_bf16 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    }
+    return d;
+}
+// Three wait states between the last dot products of the chains a0 .. b1
+// and the first other VALU instruction that reads them (the results pass
+// through this statement, so every reader comes after it).
+__device__ __forceinline__ void dot_fence(float &a0, float &b0, float &a1, float &b1)
+{
+    asm("s_nop 2" : "+v"(a0), "+v"(b0), "+v"(a1), "+v"(b1));
+}
+
 template <int MU, bool FWD>
 __device__ __forceinline__ void hop_bf16(cpx<float> (&acc)[12], const uint32_t (&p)[12],
                                          const uint32_t (&u)[9])
 {
-    // y_s = sg (B_mu psi_lo)_s, sg = -1 forward, +1 backward;  i (re, im) = (-im, re)
-    uint32_t y0[3], y1[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const uint32_t l0 = p[6 + c], l1 = p[9 + c];
-        if (MU == 0) {        // B psi_lo = (i l1, i l0)
-            y0[c] = swap_halves(l1) ^ (FWD ? kNegHi : kNegLo);
-            y1[c] = swap_halves(l0) ^ (FWD ? kNegHi : kNegLo);
-        } else if (MU == 1) { // (-l1, l0)
-            y0[c] = FWD ? l1 : l1 ^ kNegBoth;
-            y1[c] = FWD ? l0 ^ kNegBoth : l0;
-        } else if (MU == 2) { // (i l0, -i l1)
-            y0[c] = swap_halves(l0) ^ (FWD ? kNegHi : kNegLo);
-            y1[c] = swap_halves(l1) ^ (FWD ? kNegLo : kNegHi);
-        } else {              // (l0, l1)
-            y0[c] = FWD ? l0 ^ kNegBoth : l0;
-            y1[c] = FWD ? l1 ^ kNegBoth : l1;
-        }
-    }
+    // y_s = sg (B_mu psi_lo)_s, sg = -1 forward, +1 backward, i (re, im) =
+    // (-im, re): the lower spin YS feeding y_s, swapped halves (SW), and the
+    // signs of y_s's low / high halves (Fs*)
+    constexpr int Y0 = (MU == 0 || MU == 1) ? 1 : 0, Y1 = 1 - Y0;
+    constexpr bool SW = MU == 0 || MU == 2;
+    constexpr int F0L = MU == 0 ? !FWD : MU == 1 ? !FWD : MU == 2 ? !FWD : FWD;
+    constexpr int F0H = MU == 0 ? FWD : MU == 1 ? !FWD : MU == 2 ? FWD : FWD;
+    constexpr int F1L = MU == 0 ? !FWD : MU == 1 ? FWD : MU == 2 ? FWD : FWD;
+    constexpr int F1H = MU == 0 ? FWD : MU == 1 ? FWD : MU == 2 ? !FWD : FWD;
+    // the link forms: re on m with signs PR*, im on swap(m) with signs PI*
+    constexpr int PRL = 0, PRH = FWD, PIL = !FWD, PIH = 0;
     cpx<float> w0[3], w1[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-        float a0 = 0.f, b0 = 0.f, a1 = 0.f, b1 = 0.f;
+        float a0, b0, a1, b1;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const uint32_t m = FWD ? u[3 * r + c] : u[3 * c + r];
-            const uint32_t fr = FWD ? m ^ kNegHi : m;                        // real-part form
-            const uint32_t fi = FWD ? swap_halves(m) : swap_halves(m) ^ kNegLo;  // imaginary-part form
-            a0 = dot2bf(fr, p[c], a0);
-            a0 = dot2bf(fr, y0[c], a0);
-            b0 = dot2bf(fi, p[c], b0);
-            b0 = dot2bf(fi, y0[c], b0);
-            a1 = dot2bf(fr, p[3 + c], a1);
-            a1 = dot2bf(fr, y1[c], a1);
-            b1 = dot2bf(fi, p[3 + c], b1);
-            b1 = dot2bf(fi, y1[c], b1);
+            const uint32_t ms = swap_halves(m);
+            const uint32_t l0 = p[6 + 3 * Y0 + c], l1 = p[6 + 3 * Y1 + c];
+            if (c == 0) {
+                a0 = dot2n<PRL, PRH, true>(m, p[c]);
+                b0 = dot2n<PIL, PIH, true>(ms, p[c]);
+                a1 = dot2n<PRL, PRH, true>(m, p[3 + c]);
+                b1 = dot2n<PIL, PIH, true>(ms, p[3 + c]);
+            } else {
+                a0 = dot2n<PRL, PRH>(m, p[c], a0);
+                b0 = dot2n<PIL, PIH>(ms, p[c], b0);
+                a1 = dot2n<PRL, PRH>(m, p[3 + c], a1);
+                b1 = dot2n<PIL, PIH>(ms, p[3 + c], b1);
+            }
+            if constexpr (SW) {
+                a0 = dot2n<PRH ^ F0H, PRL ^ F0L>(ms, l0, a0);
+                b0 = dot2n<PIH ^ F0H, PIL ^ F0L>(m, l0, b0);
+                a1 = dot2n<PRH ^ F1H, PRL ^ F1L>(ms, l1, a1);
+                b1 = dot2n<PIH ^ F1H, PIL ^ F1L>(m, l1, b1);
+            } else {
+                a0 = dot2n<PRL ^ F0L, PRH ^ F0H>(m, l0, a0);
+                b0 = dot2n<PIL ^ F0L, PIH ^ F0H>(ms, l0, b0);
+                a1 = dot2n<PRL ^ F1L, PRH ^ F1H>(m, l1, a1);
+                b1 = dot2n<PIL ^ F1L, PIH ^ F1H>(ms, l1, b1);
+            }
         }
+        dot_fence(a0, b0, a1, b1);
         w0[r] = {a0, b0};
         w1[r] = {a1, b1};
     }
