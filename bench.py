@@ -69,7 +69,11 @@ def launch_descriptor(info: dict, prec: str, launches: int, eo: bool = False) ->
     """The stencil kernel a tuned launch runs, as a profiler names it, and its
     work-items per dispatch."""
     p = PREC_ID[prec]
-    if eo:
+    if eo and info["split"] == 7:
+        # the plane form of the reduced operator's half-stencil (compact
+        # fields: IO 0), one workgroup of SB lanes per x-y plane
+        sym, gs = "eo_plane_kernel<0>", info["grid"] * info["SB"]
+    elif eo:
         # the compact half-stencils of the reduced operator in the tuned form
         # (hop schedule info["split"], compact fields: IO 0)
         sym, gs = f"eo_hop_kernel<{p}, {info['split']}, 0>", info["grid"] * info["SB"]

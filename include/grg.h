@@ -235,17 +235,22 @@ grg_status grg_schur_tune(grg_schur s, int nrhs);
  * hop schedules 3..6 are BF16 only: 3 is its t-marching form (info[0] =
  * 256), a workgroup holding 64 columns of the half lattice and four RHS,
  * walking info[5] time slices; 4 and 5 carry info[1] = 2 or 3 RHS through
- * each hop together; 6 takes the x hops' spinors from lane shuffles;
- * info[5] = 0 except with 3.  With schedule 3, the full-layout first and
- * last steps of a reduced solve run the one-hop shape that tuning found
- * faster for them, if it found one, else schedule 3 as well. */
+ * each hop together; 6 takes the x hops' spinors from lane shuffles; 7 is
+ * the plane form of the t-marching stencil (info[0] = Lx / 2 * Ly, a multiple
+ * of 64 and at most 512, info[1] = 1), a workgroup holding a whole x-y plane
+ * of the half lattice for one RHS, walking info[5] time slices with the x, y
+ * and backward t hops read from LDS; info[5] = 0 except with 3 and 7.  With
+ * schedule 3 or 7, the full-layout first and last steps of a reduced solve
+ * run the one-hop shape that tuning found faster for them, if it found one,
+ * else the same schedule as well. */
 grg_status grg_schur_tune_info(grg_schur s, int precision, int nrhs, int32_t info[6], float *ms);
 
 /* Pin the stencil launch for (precision, nrhs), e.g. from a saved tuning
  * result: info as returned by grg_schur_tune_info.  GRG_EINVAL if the shape
  * is not valid for this lattice (a t-marching workgroup holds 64 * RHS
  * threads, at most 512 in FP64 and 768 otherwise; the t-marching
- * half-lattice stencil needs a multiple of 64 half-sites per time slice). */
+ * half-lattice stencil needs a multiple of 64 half-sites per time slice, its
+ * plane form an x-y plane of 64 to 512 half-sites, a multiple of 64). */
 grg_status grg_schur_set_launch(grg_schur s, int precision, int nrhs, const int32_t info[6]);
 
 /* The launch of the fused FP64 defect-correction step r -= D_rr e / s,

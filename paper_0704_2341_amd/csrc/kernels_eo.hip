@@ -555,6 +555,210 @@ __global__ void __launch_bounds__(256) eo_hop_kernel(EoArgs a)
     }
 }
 
+// Plane form of the t-marching half-stencil (packed BF16).  A workgroup holds
+// one x-y plane of the half lattice (P = Lx / 2 * Ly columns, one lane each,
+// P a multiple of 64 and at most kMaxPlane) for one RHS and walks `march` time
+// slices.  The other parity's sites of the plane at slices t - 1, t and t + 1
+// wait in an LDS ring of three slots (slice t in slot (t - t0 + 1) mod 3 for
+// a chunk starting at t0), so the x and y hops (the y neighbours
+// of a column are the columns one x-row up and down, the plane being periodic
+// in y) and the backward t hop read LDS; only the z hops, the forward t
+// neighbour (which then enters the ring) and the links are loaded.  One
+// barrier per slice: the slot of slice t is written during slice t - 1 and
+// read across lanes in slice t; the slot of slice t + 1, that of slice t - 2
+// before, was last read across lanes in slice t - 2, which every wave has
+// left once the barrier of slice t opens.  Workgroups of the same plane and time chunk (consecutive
+// RHS) run side by side on one XCD and share its links through L2; each XCD
+// walks its own z-slab.
+constexpr int kMaxPlane = 512;
+
+template <int IO>
+__global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
+{
+    constexpr bool in_full = IO == 1, in2_full = IO >= 1, out_full = IO == 2;
+    typedef bf16x2 S;
+    typedef float R;
+    typedef Operand<S, R> OP;
+    typedef uint32_t PT;
+    __shared__ PT ring[3][12][kMaxPlane];
+    __shared__ double red[kMaxPlane / 64][kMaxRhs][3];
+    const S *__restrict__ in = (const S *)a.in;
+    const S *__restrict__ in2 = (const S *)a.in2;
+    S *__restrict__ out = (S *)a.out;
+    const S *__restrict__ Uo = (const S *)a.U + (size_t)a.po * 36 * a.Vhs;
+    const S *__restrict__ Ui = (const S *)a.U + (size_t)(1 - a.po) * 36 * a.Vhs;
+    const uint8_t *__restrict__ mk = a.mask + (size_t)a.po * a.Vhs;
+    const int P = blockDim.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int nw = P >> 6, nr = a.nrhs;
+    const bool dots = a.partials != nullptr;
+    if (dots) {
+        for (int i = tid; i < nw * nr * 3; i += P) red[i / (nr * 3)][(i / 3) % nr][i % 3] = 0.0;
+    }
+    const R al = (R)a.alpha, be = (R)a.beta;
+    const int Lt = a.g.L[3], Lz = a.g.L[2], Lh = a.g.L[0] >> 1;
+    const int Vs3 = a.Vh / Lt;  // half-sites per time slice = P * Lz
+    const int xcd = (int)(blockIdx.x & 7), slot = (int)(blockIdx.x >> 3), slots = (int)(gridDim.x >> 3);
+    const int Z0 = (xcd * Lz) >> 3, nz = (((xcd + 1) * Lz) >> 3) - Z0;
+    const int ML = a.march, nc = (Lt + ML - 1) / ML;
+    const int nx = nz * nr * nc;
+    // this column's neighbours in the plane: along its x-row (x hops) and
+    // one x-row up and down (y hops)
+    const int xh = tid % Lh, rs = tid - xh;
+    const int xp = rs + (xh + 1 == Lh ? 0 : xh + 1), xm = rs + (xh == 0 ? Lh - 1 : xh - 1);
+    const int yp = tid + Lh >= P ? tid + Lh - P : tid + Lh, ym = tid < Lh ? tid - Lh + P : tid - Lh;
+    // element index of the input site with compact index hq (other parity)
+    auto iidx = [&](int hq) -> int {
+        if constexpr (in_full) {
+            SiteGeo tq;
+            return eo_site(hq, 1 - a.po, a.g, tq);
+        } else {
+            return hq;
+        }
+    };
+    for (int j = slot; j < nx; j += slots) {
+        const int r = j % nr, rest = j / nr;
+        const int z = Z0 + rest % nz, ch = rest / nz;
+        const int col = z * P + tid;
+        const int t0 = ch * ML, t1 = min(t0 + ML, Lt);
+        {
+            const int tm = t0 == 0 ? Lt - 1 : t0 - 1;
+            const int im = iidx(tm * Vs3 + col), i0 = iidx(t0 * Vs3 + col);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                ring[0][c][tid] = OP::load(in, fidx(im, r, c, nr));
+                ring[1][c][tid] = OP::load(in, fidx(i0, r, c, nr));
+            }
+        }
+        // the slots of slices t - 1, t and t + 1
+        int prv = 0, cur = 1, nxt = 2;
+        double dre = 0, dim = 0, dqq = 0;
+#pragma unroll 1
+        for (int t = t0; t < t1; ++t) {
+            __syncthreads();
+            const int base = t * Vs3 + z * P;  // compact index of the plane's column 0
+            const int h = base + tid;
+            const int tf = t + 1 == Lt ? 0 : t + 1, tb = t == 0 ? Lt - 1 : t - 1;
+            const bool on = mk[h] == 0;
+            // the forward t-neighbour: used at the end of this slice, then
+            // kept in the ring for the two slices after it
+            PT qc[12];
+            {
+                const int fi = iidx(tf * Vs3 + col);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) qc[c] = OP::load(in, fidx(fi, r, c, nr));
+            }
+            SiteGeo sq;
+            const int s = eo_site(h, a.po, a.g, sq);
+            cpx<R> acc[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
+            if (on) {
+                // x and y hops from the ring: neighbour column n, and the link
+                // U_mu(s) (forward) or U_mu(s - mu) at the neighbour's index
+                const bool b = (s & 1) != 0;
+                // loads in batches: the x and y hops' links, the z+ hop's
+                // operands, then the z- hop's with the t hops' links
+                PT u4[4][9];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int n = k == 0 ? (b ? xp : tid) : k == 1 ? (b ? tid : xm) : k == 2 ? yp : ym;
+                    const int mu = k >> 1;
+#pragma unroll
+                    for (int e = 0; e < 9; ++e)
+                        u4[k][e] = (k & 1) ? OP::load(Ui, lidx(base + n, mu, e)) : OP::load(Uo, lidx(h, mu, e));
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int n = k == 0 ? (b ? xp : tid) : k == 1 ? (b ? tid : xm) : k == 2 ? yp : ym;
+                    PT p[12];
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) p[c] = ring[cur][c][n];
+                    eo_hop_k(k, acc, p, u4[k]);
+                }
+                PT pz[12], uz[9];
+                eo_load_hop<OP>(4, pz, uz, in, Uo, Ui, s, h, sq, a.g, r, nr, in_full);
+                eo_hop_k(4, acc, pz, uz);
+                PT ut[2][9];
+                eo_load_hop<OP>(5, pz, uz, in, Uo, Ui, s, h, sq, a.g, r, nr, in_full);
+#pragma unroll
+                for (int e = 0; e < 9; ++e) {
+                    ut[0][e] = OP::load(Uo, lidx(h, 3, e));
+                    ut[1][e] = OP::load(Ui, lidx(tb * Vs3 + col, 3, e));
+                }
+                eo_hop_k(5, acc, pz, uz);
+                eo_hop_k(6, acc, qc, ut[0]);
+                {
+                    PT p[12];
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) p[c] = ring[prv][c][tid];
+                    eo_hop_k(7, acc, p, ut[1]);
+                }
+            }
+            // slice t + 1 into the slot of slice t - 2 (read across lanes in
+            // slice t - 2 only, which every wave has left)
+#pragma unroll
+            for (int c = 0; c < 12; ++c) ring[nxt][c][tid] = qc[c];
+            {
+                const int o = prv;
+                prv = cur;
+                cur = nxt;
+                nxt = o;
+            }
+            R sre = 0, sim = 0, sqq = 0;
+            const bool act = a.active == nullptr || a.active[r] != 0;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const size_t i = fidx(h, r, c, nr);
+                cpx<R> o = {0, 0};
+                if (on && act) {
+                    o = {be * acc[c].re, be * acc[c].im};
+                    if (in2) {
+                        const cpx<R> v = ldr<R>(in2, in2_full ? fidx(s, r, c, nr) : i);
+                        o.re = fma(al, v.re, o.re);
+                        o.im = fma(al, v.im, o.im);
+                    }
+                }
+                if constexpr (out_full) {
+                    // this site, and the other parity's site of the same index
+                    stc(out, fidx(s, r, c, nr), o);
+                    out[fidx(s ^ 1, r, c, nr)] = ((const S *)a.partner)[i];
+                } else {
+                    stc(out, i, o);
+                }
+                if (dots && on) {
+                    const cpx<R> v = ldr<R>((const S *)a.dot_with, i);
+                    sre = fma(o.re, v.re, fma(o.im, v.im, sre));
+                    sim = fma(o.re, v.im, fma(-o.im, v.re, sim));
+                    sqq = fma(o.re, o.re, fma(o.im, o.im, sqq));
+                }
+            }
+            dre += (double)sre;
+            dim += (double)sim;
+            dqq += (double)sqq;
+        }
+        // the next item's first loads overwrite slots read across lanes
+        __syncthreads();
+        if (dots) {
+            dre = wave_sum(dre);
+            dim = wave_sum(dim);
+            dqq = wave_sum(dqq);
+            if (lane == 0) {
+                red[wave][r][0] += dre;
+                red[wave][r][1] += dim;
+                red[wave][r][2] += dqq;
+            }
+        }
+    }
+    if (dots) {
+        __syncthreads();
+        for (int i = tid; i < nr * 3; i += P) {
+            double t = 0;
+            for (int k = 0; k < nw; ++k) t += red[k][i / 3][i % 3];
+            a.partials[(size_t)blockIdx.x * nr * 3 + i] = t;
+        }
+    }
+}
+
 // A compact field of parity par <-> the full field that holds it on the
 // sites of that parity and zero on the others (every RHS).
 template <int P>
@@ -615,11 +819,24 @@ static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 hipError_t launch_eo_hop(int prec, const EoArgs &a, int grid, hipStream_t st)
 {
     if (a.nrhs < 1 || a.nrhs > kMaxRhs || a.RG < 1 || grid < 8 || grid % 8) return hipErrorInvalidValue;
-    if (a.SB != 64 && a.SB != 128 && a.SB != 256) return hipErrorInvalidValue;
     int io = 0;
     if (a.in_full && a.in2_full && !a.out_full) io = 1;
     else if (!a.in_full && a.in2_full && a.out_full) io = 2;
     else if (a.in_full || a.in2_full || a.out_full) return hipErrorInvalidValue;
+    if (a.hops == 7) {
+        // plane form: packed BF16, one workgroup of P = Lx / 2 * Ly lanes
+        // per x-y plane
+        const int P = (a.g.L[0] / 2) * a.g.L[1];
+        if (prec != GRG_BF16 || a.SB != P || P % 64 || P > kMaxPlane || a.march < 1 || a.g.L[3] < 2 ||
+            a.g.L[0] < 2 || a.Vh != P * a.g.L[2] * a.g.L[3])
+            return hipErrorInvalidValue;
+        dim3 pb(P), pg(grid);
+        if (io == 1) hipLaunchKernelGGL((eo_plane_kernel<1>), pg, pb, 0, st, a);
+        else if (io == 2) hipLaunchKernelGGL((eo_plane_kernel<2>), pg, pb, 0, st, a);
+        else hipLaunchKernelGGL((eo_plane_kernel<0>), pg, pb, 0, st, a);
+        return hipGetLastError();
+    }
+    if (a.SB != 64 && a.SB != 128 && a.SB != 256) return hipErrorInvalidValue;
     dim3 blk(a.SB), grd(grid);
     const bool pipe = a.hops == 2 && prec == GRG_BF16 && io == 0;
     if (a.hops == 3) {

@@ -505,7 +505,8 @@ static grg_status eo_hop(grg_schur S, int prec, const DslashTune &t, const void 
     // the full-layout steps: with the t-marching form tuned, in the one-hop
     // shape the tuner recorded for them if it found that one faster
     const bool io = in_full || in2_full || partner;
-    const DslashTune &tu = io && t.split == 3 && S->eotune_io[prec][nrhs].valid ? S->eotune_io[prec][nrhs] : t;
+    const DslashTune &tu =
+        io && (t.split == 3 || t.split == 7) && S->eotune_io[prec][nrhs].valid ? S->eotune_io[prec][nrhs] : t;
     EoArgs a;
     a.in = in;
     a.in2 = in2;
@@ -558,6 +559,13 @@ bool eo_launch_ok(const Geom &gh, int prec, int nrhs, const DslashTune &t)
     // shuffles (x-rows of half-sites must tile a wavefront)
     const bool multi_ok = ((t.split == 4 || t.split == 5) && prec == GRG_BF16 && t.RG == t.split - 2) ||
                           (t.split == 6 && prec == GRG_BF16 && gh.L[0] >= 2 && 64 % (gh.L[0] / 2) == 0);
+    // split 7: the plane form, one workgroup of Lx / 2 * Ly lanes per x-y plane
+    const int plane = (gh.L[0] / 2) * gh.L[1];
+    const bool plane_ok = t.split == 7 && prec == GRG_BF16 && t.SB == plane && plane % 64 == 0 &&
+                          plane <= 512 && t.march >= 1 && t.march <= Lt && Lt >= 2;
+    if (plane_ok)
+        return t.RG >= 1 && t.RG <= nrhs && t.grid >= 8 && t.grid % 8 == 0 && t.grid <= kMaxGridValue &&
+               t.chunk >= 0;
     return (t.SB == 64 || t.SB == 128 || t.SB == 256) && t.RG >= 1 && t.RG <= nrhs &&
            (t.split == 1 || (t.split == 2 && prec == GRG_BF16) || march_ok || multi_ok) && t.grid >= 8 &&
            t.grid % 8 == 0 && t.grid <= kMaxGridValue && t.chunk >= 0 && t.march >= 0 && gh.V > 0;
@@ -661,10 +669,33 @@ grg_status tune_eo(grg_schur S, int prec, int nrhs, int reps)
             }
         }
     }
+    // the plane form: time slices per item, and grids of one, a half and a
+    // quarter workgroup per item of the largest XCD share
+    if (prec == GRG_BF16 && !cands.empty()) {
+        const int Lt = gh.L[3];
+        std::vector<int> mls;
+        for (int ml : {Lt, Lt / 2, Lt / 4, Lt / 8})
+            if (ml >= 1 && std::find(mls.begin(), mls.end(), ml) == mls.end()) mls.push_back(ml);
+        for (int ml : mls) {
+            DslashTune t = cands[0];
+            t.SB = (gh.L[0] / 2) * gh.L[1];
+            t.RG = 1;
+            t.split = 7;
+            t.march = ml;
+            t.chunk = 0;
+            const long nx = (long)((gh.L[2] + 7) / 8) * nrhs * ((Lt + ml - 1) / ml);
+            for (long div : {1, 2, 4}) {
+                t.grid = round8(std::min<long>(8 * nx / div, kMaxGridValue));
+                if (!eo_launch_ok(gh, prec, nrhs, t)) continue;
+                timeit(t);
+                if (t.ms < best.ms) best = t;
+            }
+        }
+    }
     best_io.valid = best_io.ms < 1e29f ? 1 : 0;
-    // the full-layout first and last steps with the t-marching form tuned:
+    // the full-layout first and last steps with a t-marching form tuned:
     // that form or the best one-hop shape, whichever runs the pair faster
-    if (status == GRG_OK && best.split == 3 && best_io.valid) {
+    if (status == GRG_OK && (best.split == 3 || best.split == 7) && best_io.valid) {
         status = ensure_inner(S, prec);
         const int P = S->eo_par, Q = 1 - P;
         const double d = 4.0 + S->m0;

@@ -111,6 +111,8 @@ RA_LAUNCHES = {
     "three-rhs-per-hop": (64, 3, 5, 40, 8, 0),
     "x-hops-from-lanes": (256, 3, 6, 64, 0, 0),
     "x-hops-from-lanes-sb64": (64, 1, 6, 24, 8, 0),
+    "plane-all-t": (64, 1, 7, 64, 0, 8),
+    "plane-ragged-chunks": (64, 1, 7, 24, 0, 3),
 }
 
 
@@ -151,6 +153,54 @@ def test_reduced_apply_vs_oracle(form, prec, nrhs):
     lat.close()
 
 
+@pytest.mark.parametrize("dims,launch", [
+    ((8, 32, 4, 6), (128, 1, 7, 40, 0, 6)),     # two wavefronts per plane
+    ((16, 32, 4, 4), (256, 1, 7, 16, 0, 3)),    # four, ragged time chunks
+    ((32, 32, 2, 4), (512, 1, 7, 8, 0, 1)),     # eight, one slice per item
+])
+def test_plane_form_vs_oracle(dims, launch):
+    """The plane form with several wavefronts per x-y plane (y neighbours
+    across wavefronts, read from LDS after the slice's barrier), both
+    parities, with and without the alpha term, against the oracle."""
+    lat = Lattice(dims, 0.5, 28)
+    nrhs = 3
+    s = lat.schur(-0.3, "I", False, tol=1e-10, inner="bf16", max_rhs=nrhs)
+    grg = lat.grg
+    grg.grg_schur_set_launch(s.h, "bf16", nrhs, launch, eo=True)
+    x = gaussian_vectors(12 * lat.V, nrhs, 28)
+    import torch
+
+    from gpu_support import to_dev, to_host
+
+    xd = to_dev(x)
+    yd = torch.empty_like(xd)
+    for parity in (0, 1):
+        print(f"plane form {dims} {launch} parity {parity}", flush=True)
+        grg.grg_reduced_apply(s.h, "bf16", parity, xd, yd, nrhs)
+        want = matfree.reduced_apply(lat.links, dims, -0.3, s.q, s.nb, parity, x)
+        assert rel_err(to_host(yd), want) < RA_TOL["bf16"]
+    s.close()
+    lat.close()
+
+
+def test_plane_launch_rejected_for_wrong_plane():
+    """The plane form's workgroup is exactly one x-y plane of at most 512
+    half-sites, a multiple of 64."""
+    lat = Lattice((16, 8, 8, 8), 0.5, 29)
+    s = lat.schur(-0.1, "I", False, tol=1e-10, inner="bf16", max_rhs=2)
+    for bad in ((128, 1, 7, 8, 0, 4), (64, 1, 7, 8, 0, 0), (64, 1, 7, 12, 0, 4)):
+        with pytest.raises(lat.grg.GrgError):
+            lat.grg.grg_schur_set_launch(s.h, "bf16", 2, bad, eo=True)
+    s.close()
+    lat.close()
+    lat = Lattice((8, 6, 4, 10), 0.5, 29)  # 24 half-sites per plane
+    s = lat.schur(-0.1, "II", False, tol=1e-10, inner="bf16", max_rhs=2)
+    with pytest.raises(lat.grg.GrgError):
+        lat.grg.grg_schur_set_launch(s.h, "bf16", 2, (24, 1, 7, 8, 0, 5), eo=True)
+    s.close()
+    lat.close()
+
+
 def test_march_launch_rejected_without_whole_tiles():
     """The t-marching form needs a multiple of 64 half-sites per time slice."""
     lat = Lattice((8, 6, 4, 10), 0.5, 26)
@@ -161,9 +211,10 @@ def test_march_launch_rejected_without_whole_tiles():
     lat.close()
 
 
+@pytest.mark.parametrize("launch", [(256, 3, 3, 40, 0, 3), (64, 1, 7, 40, 0, 3)])
 @pytest.mark.parametrize("method", ["gcr", "bicgstab"])
 @pytest.mark.parametrize("kind,inv", [("I", False), ("II", True)])
-def test_march_full_layout_steps(method, kind, inv):
+def test_march_full_layout_steps(method, kind, inv, launch):
     """With the t-marching launch pinned before any tuning, the first and
     last steps of every reduced solve (full-layout input, and output with the
     other parity copied in) run that form too: same solution as the
@@ -174,11 +225,11 @@ def test_march_full_layout_steps(method, kind, inv):
     kw = dict(tol=1e-12, inner="bf16", inner_tol=1e-2, max_rhs=5, max_iter=4000, method=method)
     s1 = lat.schur(-0.2, kind, inv, eo=1, **kw)
     s0 = lat.schur(-0.2, kind, inv, eo=0, **kw)
-    lat.grg.grg_schur_set_launch(s1.h, "bf16", 5, (256, 3, 3, 40, 0, 3), eo=True)
-    assert lat.grg.grg_schur_tune_info(s1.h, "bf16", 5, eo=True)["split"] == 3
+    lat.grg.grg_schur_set_launch(s1.h, "bf16", 5, launch, eo=True)
+    assert lat.grg.grg_schur_tune_info(s1.h, "bf16", 5, eo=True)["split"] == launch[2]
     b = rest_rhs(lat, s1, 5, 27)
     b[3] = 0
-    print(f"march full-layout steps {method} {kind} inv={inv}", flush=True)
+    print(f"march full-layout steps {launch} {method} {kind} inv={inv}", flush=True)
     x1, st1 = s1.drr_solve(b)
     x0, st0 = s0.drr_solve(b)
     assert st1["converged"] and st0["converged"]
