@@ -324,14 +324,15 @@ def main():
     dk = kernels[dom]
     dom_eo = dom.endswith("_eo")
     dom_prec = dom[len("dslash_"):].replace("_eo", "")
-    tkey = traffic_key(dom_prec + ("_eo" if dom_eo else ""), nrhs, dims)
+    dlaunch = launch_descriptor(grg.grg_schur_tune_info(s, dom_prec, nrhs, eo=dom_eo), dom_prec,
+                                dk["launches"], eo=dom_eo)
+    # traffic of this very launch shape (counter runs are per shape)
+    tkey = traffic_key(dom_prec + ("_eo" if dom_eo else ""), nrhs, dims, dlaunch["shape"])
     traffic = measured_traffic(tkey)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBps"], "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": dk["alg_GBps"] / PEAK_HBM_GBS,
                 "traffic": traffic, "alg_bytes_per_launch": dk["alg_bytes_per_launch"],
-                "avg_launch_ms": dk["avg_ms"], "traffic_key": tkey,
-                "launch": launch_descriptor(grg.grg_schur_tune_info(s, dom_prec, nrhs, eo=dom_eo),
-                                            dom_prec, dk["launches"], eo=dom_eo)}
+                "avg_launch_ms": dk["avg_ms"], "traffic_key": tkey, "launch": dlaunch}
 
     fp64 = None
     bicg = None

@@ -226,16 +226,18 @@ __device__ __forceinline__ void eo_march(const EoArgs &a, double (*red)[3])
             for (int c = 0; c < 12; ++c) q[(t + 1) & 1][c][lane] = qc[c];
             R sre = 0, sim = 0, sqq = 0;
             const bool act = a.active == nullptr || a.active[r] != 0;
+            // the sums against in2 itself reuse its loaded value
+            const bool dot_in2 = !in2_full && a.dot_with == a.in2;
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 const size_t i = fidx(h, r, c, nr);
-                cpx<R> o = {0, 0};
+                cpx<R> o = {0, 0}, v2 = {0, 0};
+                if (in2 && on) v2 = ldr<R>(in2, in2_full ? fidx(s, r, c, nr) : i);
                 if (on && act) {
                     o = {be * acc[c].re, be * acc[c].im};
                     if (in2) {
-                        const cpx<R> v = ldr<R>(in2, in2_full ? fidx(s, r, c, nr) : i);
-                        o.re = fma(al, v.re, o.re);
-                        o.im = fma(al, v.im, o.im);
+                        o.re = fma(al, v2.re, o.re);
+                        o.im = fma(al, v2.im, o.im);
                     }
                 }
                 if constexpr (out_full) {
@@ -246,7 +248,7 @@ __device__ __forceinline__ void eo_march(const EoArgs &a, double (*red)[3])
                     stc(out, i, o);
                 }
                 if (dots && on) {
-                    const cpx<R> v = ldr<R>((const S *)a.dot_with, i);
+                    const cpx<R> v = dot_in2 ? v2 : ldr<R>((const S *)a.dot_with, i);
                     sre = fma(o.re, v.re, fma(o.im, v.im, sre));
                     sim = fma(o.re, v.im, fma(-o.im, v.re, sim));
                     sqq = fma(o.re, o.re, fma(o.im, o.im, sqq));
@@ -706,16 +708,19 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
             }
             R sre = 0, sim = 0, sqq = 0;
             const bool act = a.active == nullptr || a.active[r] != 0;
+            // the sums against in2 itself (the reduced operator's second
+            // half) reuse its loaded value
+            const bool dot_in2 = !in2_full && a.dot_with == a.in2;
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 const size_t i = fidx(h, r, c, nr);
-                cpx<R> o = {0, 0};
+                cpx<R> o = {0, 0}, v2 = {0, 0};
+                if (in2 && on) v2 = ldr<R>(in2, in2_full ? fidx(s, r, c, nr) : i);
                 if (on && act) {
                     o = {be * acc[c].re, be * acc[c].im};
                     if (in2) {
-                        const cpx<R> v = ldr<R>(in2, in2_full ? fidx(s, r, c, nr) : i);
-                        o.re = fma(al, v.re, o.re);
-                        o.im = fma(al, v.im, o.im);
+                        o.re = fma(al, v2.re, o.re);
+                        o.im = fma(al, v2.im, o.im);
                     }
                 }
                 if constexpr (out_full) {
@@ -726,7 +731,7 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
                     stc(out, i, o);
                 }
                 if (dots && on) {
-                    const cpx<R> v = ldr<R>((const S *)a.dot_with, i);
+                    const cpx<R> v = dot_in2 ? v2 : ldr<R>((const S *)a.dot_with, i);
                     sre = fma(o.re, v.re, fma(o.im, v.im, sre));
                     sim = fma(o.re, v.im, fma(-o.im, v.re, sim));
                     sqq = fma(o.re, o.re, fma(o.im, o.im, sqq));

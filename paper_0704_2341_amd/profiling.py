@@ -46,8 +46,16 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def traffic_key(prec: str, nrhs: int, dims) -> str:
-    return f"{prec}_nrhs{nrhs}_{'x'.join(map(str, dims))}"
+def traffic_key(prec: str, nrhs: int, dims, shape=None) -> str:
+    """Name of a stencil launch in the traffic table: precision, RHS count,
+    lattice and (optionally) the launch shape, since the bytes a launch moves
+    depend on its shape."""
+    key = f"{prec}_nrhs{nrhs}_{'x'.join(map(str, dims))}"
+    return key + "_" + shape_tag(shape) if shape else key
+
+
+def shape_tag(shape) -> str:
+    return "_".join(f"{k}{shape[k]}" for k in ("SB", "RG", "split", "grid", "chunk", "march"))
 
 
 def measured_traffic(key: str, path: str = TRAFFIC_FILE):
@@ -165,15 +173,19 @@ def traffic_table(fetch_dir, write_dir, fetch_log, write_log, command, out=TRAFF
     write, nw = _counter_avg(wr, launch, "WRITE_SIZE")
     hbm = fetch * 1024 * ff + write * 1024 * wf
     key = bf["roofline"]["traffic_key"]
+    tag = shape_tag(launch["shape"])
+    if not key.endswith(tag):
+        key += "_" + tag
     alg = bf["roofline"]["alg_bytes_per_launch"]
     entry = {"symbol": launch["symbol"], "grid_size": launch["grid_size"], "shape": launch["shape"],
              "dispatches": [nf, nw], "fetch_kib": fetch, "write_kib": write,
-             "hbm_bytes_per_launch": hbm, "alg_bytes_per_launch": alg, "ratio_to_alg": hbm / alg}
+             "hbm_bytes_per_launch": hbm, "alg_bytes_per_launch": alg, "ratio_to_alg": hbm / alg,
+             "command": command}
     table = {"kernel_source_sha256": kernel_source_hash(),
              "calibration": {"kernel": COPY_KERNEL, "bytes_read": cb, "bytes_written": cb,
                              "fetch_kib": fk, "write_kib": wk, "fetch_factor": ff, "write_factor": wf,
                              "dispatches": [fn, wn]},
-             "commands": command, "kernels": {}}
+             "kernels": {}}
     if os.path.exists(out):
         with open(out) as f:
             old = json.load(f)
