@@ -183,6 +183,40 @@ def test_plane_form_vs_oracle(dims, launch):
     lat.close()
 
 
+def test_bf16_forms_bit_identical():
+    """Every BF16 form of the half-lattice stencil sums the hops of a site in
+    the same order with the same arithmetic, so their outputs agree bit for
+    bit (the autotuner's choice changes speed only)."""
+    import torch
+
+    from gpu_support import to_dev, to_host
+
+    dims = (16, 8, 8, 8)
+    lat = Lattice(dims, 0.5, 30)
+    nrhs = 5
+    s = lat.schur(-0.3, "I", False, tol=1e-10, inner="bf16", max_rhs=nrhs)
+    grg = lat.grg
+    xd = to_dev(gaussian_vectors(12 * lat.V, nrhs, 30))
+    yd = torch.empty_like(xd)
+    ref = None
+    for form, launch in RA_LAUNCHES.items():
+        if launch[1] > nrhs:
+            continue
+        grg.grg_schur_set_launch(s.h, "bf16", nrhs, launch, eo=True)
+        print(f"bit identity {form}", flush=True)
+        outs = []
+        for parity in (0, 1):
+            grg.grg_reduced_apply(s.h, "bf16", parity, xd, yd, nrhs)
+            outs.append(to_host(yd))
+        if ref is None:
+            ref = outs
+        else:
+            for a, b in zip(outs, ref):
+                assert np.array_equal(a, b), form
+    s.close()
+    lat.close()
+
+
 def test_plane_launch_rejected_for_wrong_plane():
     """The plane form's workgroup is exactly one x-y plane of at most 512
     half-sites, a multiple of 64."""
