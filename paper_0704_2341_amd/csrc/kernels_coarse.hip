@@ -86,50 +86,43 @@ namespace grg {
 // coarse sites): the S_bb apply's last step, [D (u - z)]_b, read from the
 // corrections at the coarse sites' neighbours only, instead of summing the
 // iterate over the whole lattice first.
-template <int P, int MU, bool FWD>
-__device__ __forceinline__ void coarse_hop(cpx<double> (&acc)[12], int n, int ls, const double2 *__restrict__ xb,
-                                           const int32_t *__restrict__ bidx, int nb, int r, int nrhs,
-                                           const CombineArgs &a, const double2 *__restrict__ U)
+// w at the neighbour n of a coarse site: x_b there if n is coarse, else
+// sigma sum_j f_j e_j(n), with the loads of e_(j+1) issued before e_j is added
+template <int P>
+__device__ __forceinline__ void coarse_w(cpx<double> (&w)[12], int n, const double2 *__restrict__ xb,
+                                         const int32_t *__restrict__ bidx, int nb, int r, int nrhs,
+                                         const CombineArgs &a)
 {
     typedef typename Store<P>::S S;
-    cpx<double> w[12], u[9];
     const int kb = bidx[n];
     if (kb >= 0) {
         const double2 *v = xb + ((size_t)r * nb + kb) * 12;
 #pragma unroll
         for (int c = 0; c < 12; ++c) w[c] = {v[c].x, v[c].y};
-    } else {
+        return;
+    }
 #pragma unroll
-        for (int c = 0; c < 12; ++c) w[c] = {0, 0};
-        for (int j = 0; j < a.n; ++j) {
-            const double f = a.sigma * a.f[j * kMaxRhs + r];
-            const S *e = (const S *)a.e[j];
+    for (int c = 0; c < 12; ++c) w[c] = {0, 0};
+    if (a.n < 1) return;
+    S cur[12], nxt[12];
 #pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                const cpx<double> ev = ldr<double>(e, fidx(n, r, c, nrhs));
-                w[c].re = fma(f, ev.re, w[c].re);
-                w[c].im = fma(f, ev.im, w[c].im);
-            }
+    for (int c = 0; c < 12; ++c) cur[c] = ((const S *)a.e[0])[fidx(n, r, c, nrhs)];
+#pragma unroll 1
+    for (int j = 0; j < a.n; ++j) {
+        if (j + 1 < a.n) {
+            const S *e = (const S *)a.e[j + 1];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) nxt[c] = e[fidx(n, r, c, nrhs)];
+        }
+        const double f = a.sigma * a.f[j * kMaxRhs + r];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const cpx<double> ev = ldr<double>(cur, c);
+            w[c].re = fma(f, ev.re, w[c].re);
+            w[c].im = fma(f, ev.im, w[c].im);
+            cur[c] = nxt[c];
         }
     }
-#pragma unroll
-    for (int e = 0; e < 9; ++e) {
-        const double2 x = U[lidx(ls, MU, e)];
-        u[e] = {x.x, x.y};
-    }
-    hop_math<MU, FWD>(acc, w, u);
-}
-
-template <int P, int MU>
-__device__ __forceinline__ void coarse_dir(cpx<double> (&acc)[12], int s, const SiteGeo &q, const Geom &g,
-                                           const double2 *__restrict__ xb, const int32_t *__restrict__ bidx,
-                                           int nb, int r, int nrhs, const CombineArgs &a,
-                                           const double2 *__restrict__ U)
-{
-    int sp, sm;
-    nbr(s, MU, q, g, sp, sm);
-    coarse_hop<P, MU, true>(acc, sp, s, xb, bidx, nb, r, nrhs, a, U);
-    coarse_hop<P, MU, false>(acc, sm, sm, xb, bidx, nb, r, nrhs, a, U);
 }
 
 template <int P>
@@ -149,10 +142,32 @@ __global__ void __launch_bounds__(256) coarse_combine_apply_kernel(Geom g, const
     const double2 *v = xb + ((size_t)r * nb + k) * 12;
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = {diag * v[c].x, diag * v[c].y};
-    coarse_dir<P, 0>(acc, s, q, g, xb, bidx, nb, r, nrhs, a, U);
-    coarse_dir<P, 1>(acc, s, q, g, xb, bidx, nb, r, nrhs, a, U);
-    coarse_dir<P, 2>(acc, s, q, g, xb, bidx, nb, r, nrhs, a, U);
-    coarse_dir<P, 3>(acc, s, q, g, xb, bidx, nb, r, nrhs, a, U);
+    // one hop per iteration (+x, -x, ..., -t): the FP64 operands of a hop
+    // are 84 registers, so the hops are not unrolled
+#pragma unroll 1
+    for (int h = 0; h < 8; ++h) {
+        const int mu = h >> 1;
+        int sp, sm;
+        nbr(s, mu, q, g, sp, sm);
+        const int n = (h & 1) ? sm : sp;
+        cpx<double> w[12], u[9];
+        coarse_w<P>(w, n, xb, bidx, nb, r, nrhs, a);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            const double2 x = U[lidx((h & 1) ? sm : s, mu, e)];
+            u[e] = {x.x, x.y};
+        }
+        switch (h) {
+        case 0: hop_math<0, true>(acc, w, u); break;
+        case 1: hop_math<0, false>(acc, w, u); break;
+        case 2: hop_math<1, true>(acc, w, u); break;
+        case 3: hop_math<1, false>(acc, w, u); break;
+        case 4: hop_math<2, true>(acc, w, u); break;
+        case 5: hop_math<2, false>(acc, w, u); break;
+        case 6: hop_math<3, true>(acc, w, u); break;
+        default: hop_math<3, false>(acc, w, u); break;
+        }
+    }
     double2 *o = yb + ((size_t)r * nb + k) * 12;
 #pragma unroll
     for (int c = 0; c < 12; ++c) o[c] = make_double2(acc[c].re, acc[c].im);
