@@ -258,7 +258,10 @@ grg_status grg_schur_set_launch(grg_schur s, int precision, int nrhs, const int3
  * in grg_schur_tune_info, where info[5] = 0 selects the site-parallel kernel
  * (info[0] threads per workgroup: 64, 128 or 256) and info[5] = T > 0 the
  * t-marching kernel (64 * info[1] <= 512 threads, time chunks of T);
- * info[2] is ignored.  *ms = tuned time per step, or -1 if untuned. */
+ * info[2] = 1 selects the LDS-ring form of the t-marching kernel (BF16 inner
+ * precision, Lx dividing 64 and a multiple of 64 sites per x-y-z slice;
+ * the column's e at t - 1 and t kept in LDS, each site finished within its
+ * slice), else 0.  *ms = tuned time per step, or -1 if untuned. */
 grg_status grg_schur_dc_launch_info(grg_schur s, int precision, int nrhs, int32_t info[6],
                                     float *ms);
 /* Pin that launch; GRG_EINVAL if the shape is not valid for this lattice. */

@@ -47,7 +47,7 @@ grg_status tune_dc(grg_schur S, int prec, int nrhs, int reps);
 grg_status tune_eo(grg_schur S, int prec, int nrhs, int reps);
 DslashTune default_eo_tune(const Geom &gh, int prec, int nrhs);
 DslashTune default_dc_tune(const Geom &g);
-bool dc_launch_ok(const Geom &g, int nrhs, const DslashTune &t);
+bool dc_launch_ok(const Geom &g, int prec, int nrhs, const DslashTune &t);
 bool eo_launch_ok(const Geom &gh, int prec, int nrhs, const DslashTune &t);
 
 static grg_status dmalloc(void **p, size_t bytes, const char *what)
@@ -686,13 +686,13 @@ grg_status grg_schur_set_dc_launch(grg_schur S, int precision, int nrhs, const i
     DslashTune t;
     t.SB = info[0];
     t.RG = info[1];
-    t.split = 0;
+    t.split = info[2];
     t.grid = info[3];
     t.chunk = info[4];
     t.march = info[5];
     t.valid = 1;
     t.ms = 0;
-    if (!dc_launch_ok(S->lat->g, nrhs, t))
+    if (!dc_launch_ok(S->lat->g, precision, nrhs, t))
         return set_error("defect-correction launch {%d, %d, %d, %d, %d, %d} not valid for nrhs %d",
                          info[0], info[1], info[2], info[3], info[4], info[5], nrhs),
                GRG_EINVAL;

@@ -124,11 +124,13 @@ struct DcArgs {
     int nrhs;
     double *partials;     // [grid][nrhs]: |r_out|^2
     int RG, chunk, march; // t-marching launch (march > 0), as in DslashArgs
+    int ring;             // with march > 0 and BF16 e: the LDS-ring form of the t-marching step
 };
 
 hipError_t launch_dslash(int prec, const DslashArgs &a, int grid, hipStream_t st);
 // SB: workgroup of the site-parallel kernel (a.march == 0); with a.march > 0
-// the t-marching kernel runs with 64 * a.RG threads per workgroup.
+// the t-marching kernel runs with 64 * a.RG threads per workgroup (a.ring: its
+// LDS-ring form, BF16 e only, 64 sites per x-y-z tile made of whole x-rows).
 hipError_t launch_dc_update(int prec, const DcArgs &a, int grid, int SB, hipStream_t st);
 hipError_t launch_dslash_coarse(const CoarseArgs &a, hipStream_t st);
 // b = D_rb x_b from the canonical coarse vector (kernels_coarse.hip): internal

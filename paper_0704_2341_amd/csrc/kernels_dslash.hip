@@ -359,6 +359,155 @@ __global__ void __launch_bounds__(E::kThreads) march_kernel(typename E::Args a)
     }
 }
 
+// LDS-ring form of the t-marching stencil for packed BF16 input (the fused
+// defect-correction step of a BF16 inner solve).  As march_kernel, a
+// workgroup holds 64 sites of a 3-d slice for RG RHS and walks t, but each
+// site is finished within its own slice: the column's input at t - 1 and t
+// waits in an LDS ring (two slots per wavefront, each lane writing its own
+// column), so the backward t hop and the x hops (the sites of the same
+// x-row, lanes of the same wavefront) read LDS, and no second FP64
+// accumulator is carried from one slice to the next.  The hops of a site are
+// summed in march_kernel's order (backward t, diagonal, x, y, z, forward t).
+template <class E>
+__global__ void __launch_bounds__(512) ring_march_kernel(typename E::Args a)
+{
+    typedef typename E::SIN S;
+    typedef typename E::SU SU;
+    typedef typename E::R R;
+    typedef Operand<S, R> OP;
+    typedef Operand<SU, R> OU;
+    typedef typename OP::T PT;
+    typedef typename OU::T UT;
+    static_assert(sizeof(PT) == 4, "the LDS ring holds packed BF16 words");
+    constexpr int K = E::K;
+    __shared__ PT ring[8][2][12][64];
+    __shared__ double red[kMaxRhs][K];
+    const S *__restrict__ in = E::input(a);
+    const SU *__restrict__ U = E::links(a);
+    double *partials = E::partials(a);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (partials) {
+        for (int i = threadIdx.x; i < kMaxRhs * K; i += blockDim.x) red[i / K][i % K] = 0.0;
+        __syncthreads();
+    }
+    const int Lx = a.g.L[0];
+    const int V3 = Lx * a.g.L[1] * a.g.L[2], Lt = a.g.L[3];
+    const int nb3 = V3 >> 6;  // whole tiles (V3 a multiple of 64)
+    const int T = a.march;
+    const int ntc = (Lt + T - 1) / T;
+    const int ngroups = (a.nrhs + a.RG - 1) / a.RG;
+    const int nitems = nb3 * ntc * ngroups;
+    const R diag = (R)a.diag;
+    // the x neighbours' lanes: x-rows of Lx sites tile the 64 lanes
+    const int xh = lane % Lx, rs = lane - xh;
+    const int lp = rs + (xh + 1 == Lx ? 0 : xh + 1), lm = rs + (xh == 0 ? Lx - 1 : xh - 1);
+    PT (*q)[12][64] = ring[wv];
+    double dot[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) dot[k] = 0.0;
+    const int C = a.chunk > 0 ? a.chunk : (nitems + 7) / 8;
+    for (int j = blockIdx.x >> 3;; j += gridDim.x >> 3) {
+        const int w = xcd_chunk_item(j, C, nitems);
+        if (w < 0) break;
+        const int b3 = w % nb3, rest = w / nb3;
+        const int grp = rest % ngroups, tc = rest / ngroups;
+        const int s3 = b3 * 64 + lane;
+        const int r = grp * a.RG + wv;
+        if (r >= a.nrhs) continue;  // whole wavefront idles
+        const int t0 = tc * T, t1 = min(t0 + T, Lt);
+        SiteGeo g3 = site_geo(s3, a.g);
+        // slot (t & 1) holds slice t (counted from t0, so an odd Lt wraps too)
+        {
+            const int tm = t0 == 0 ? Lt - 1 : t0 - 1;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                q[(t0 - 1) & 1][c][lane] = OP::load(in, fidx(s3 + V3 * tm, r, c, a.nrhs));
+                q[t0 & 1][c][lane] = OP::load(in, fidx(s3 + V3 * t0, r, c, a.nrhs));
+            }
+        }
+#pragma unroll 1
+        for (int t = t0; t < t1; ++t) {
+            const int s = s3 + V3 * t;
+            g3.c[3] = t;
+            const int tf = t + 1 == Lt ? 0 : t + 1, tb = t == 0 ? Lt - 1 : t - 1;
+            // the forward t-neighbour: used at the end of this slice, then
+            // kept in the ring for the next two
+            PT qc[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) qc[c] = OP::load(in, fidx(s3 + V3 * tf, r, c, a.nrhs));
+            cpx<R> acc[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
+            {
+                PT p[12];
+                UT u[9];
+#pragma unroll
+                for (int e = 0; e < 9; ++e) u[e] = OU::load(U, lidx(s3 + V3 * tb, 3, e));
+#pragma unroll
+                for (int c = 0; c < 12; ++c) p[c] = q[(t - 1) & 1][c][lane];
+                hop<3, false>(acc, p, u);
+            }
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const auto v = as_cpx(q[t & 1][c][lane]);
+                acc[c].re += diag * (R)v.re;
+                acc[c].im += diag * (R)v.im;
+            }
+#pragma unroll 1
+            for (int h = 0; h < 6; ++h) {  // x hops from the ring, y and z hops loaded
+                const int mu = h >> 1;
+                int sp, sm;
+                nbr(s, mu, g3, a.g, sp, sm);
+                PT p[12];
+                UT u[9];
+                if (h < 2) {
+                    const int l = h == 0 ? lp : lm;
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) p[c] = q[t & 1][c][l];
+                } else {
+                    const int n = (h & 1) ? sm : sp;
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) p[c] = OP::load(in, fidx(n, r, c, a.nrhs));
+                }
+#pragma unroll
+                for (int e = 0; e < 9; ++e) u[e] = OU::load(U, lidx((h & 1) ? sm : s, mu, e));
+                switch (h) {
+                case 0: hop<0, true>(acc, p, u); break;
+                case 1: hop<0, false>(acc, p, u); break;
+                case 2: hop<1, true>(acc, p, u); break;
+                case 3: hop<1, false>(acc, p, u); break;
+                case 4: hop<2, true>(acc, p, u); break;
+                default: hop<2, false>(acc, p, u); break;
+                }
+            }
+            {
+                UT u[9];
+#pragma unroll
+                for (int e = 0; e < 9; ++e) u[e] = OU::load(U, lidx(s, 3, e));
+                hop<3, true>(acc, qc, u);
+            }
+            // slice t + 1 into the slot of slice t - 1 (read above by this
+            // lane only)
+#pragma unroll
+            for (int c = 0; c < 12; ++c) q[(t + 1) & 1][c][lane] = qc[c];
+            E::store(a, acc, s, r, true, dot);
+        }
+        if (partials) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const double t = wave_sum(dot[k]);
+                if (lane == 0) red[r][k] += t;
+                dot[k] = 0.0;
+            }
+        }
+    }
+    if (partials) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < a.nrhs * K; i += blockDim.x)
+            partials[(size_t)blockIdx.x * a.nrhs * K + i] = red[i / K][i % K];
+    }
+}
+
 // One FP64 defect-correction step, fused.  e is the inner solution (stored in
 // precision P, zero on coarse sites) of A e = r_in / f_k:
 //     r_out = r_in - f (D_rr e)        x_out = x_in + f e        (FP64)
@@ -581,6 +730,13 @@ hipError_t launch_dslash(int prec, const DslashArgs &a, int grid, hipStream_t st
 hipError_t launch_dc_update(int prec, const DcArgs &a, int grid, int SB, hipStream_t st)
 {
     if (a.nrhs < 1 || a.nrhs > kMaxRhs || grid < 8 || grid % 8) return hipErrorInvalidValue;
+    if (a.march > 0 && a.ring) {
+        const int V3 = a.g.L[0] * a.g.L[1] * a.g.L[2];
+        if (prec != GRG_BF16 || a.RG < 1 || 64 * a.RG > 512 || V3 % 64 || 64 % a.g.L[0])
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(ring_march_kernel<DcEpi<GRG_BF16>>, dim3(grid), dim3(64 * a.RG), 0, st, a);
+        return hipGetLastError();
+    }
     if (a.march > 0) {
         if (a.RG < 1 || 64 * a.RG > 512) return hipErrorInvalidValue;
         dim3 blk(64 * a.RG), grd(grid);

@@ -242,9 +242,14 @@ DslashTune default_dc_tune(const Geom &g)
     return t;
 }
 
-bool dc_launch_ok(const Geom &g, int nrhs, const DslashTune &t)
+// split 1: the LDS-ring form of the t-marching step (BF16 e, whole tiles of
+// x-rows); otherwise split is 0
+bool dc_launch_ok(const Geom &g, int prec, int nrhs, const DslashTune &t)
 {
     if (t.grid < 8 || t.grid % 8 || t.grid > kMaxGridValue || t.chunk < 0 || t.march < 0) return false;
+    if (t.split != 0 && t.split != 1) return false;
+    const int V3 = g.L[0] * g.L[1] * g.L[2];
+    if (t.split == 1 && (t.march < 1 || prec != GRG_BF16 || V3 % 64 || 64 % g.L[0])) return false;
     if (t.march > 0) return t.march <= g.L[3] && t.RG >= 1 && t.RG <= nrhs && 64 * t.RG <= 512;
     return t.SB == 64 || t.SB == 128 || t.SB == 256;
 }
@@ -254,6 +259,7 @@ static void dc_fill_launch(DcArgs &d, const DslashTune &t)
     d.RG = t.RG;
     d.chunk = t.chunk;
     d.march = t.march;
+    d.ring = t.split == 1;
 }
 
 // Autotuner of the defect-correction step (inner precision prec), timed on
@@ -287,7 +293,7 @@ grg_status tune_dc(grg_schur S, int prec, int nrhs, int reps)
     DslashTune best = default_dc_tune(g);
     best.ms = 1e30f;
     auto timeit = [&](DslashTune t) {
-        if (status != GRG_OK || !dc_launch_ok(g, nrhs, t)) return;
+        if (status != GRG_OK || !dc_launch_ok(g, prec, nrhs, t)) return;
         dc_fill_launch(d, t);
         hipError_t e = launch_dc_update(prec, d, t.grid, t.SB, st);
         for (int k = 0; k < reps && e == hipSuccess; ++k) {
@@ -326,6 +332,8 @@ grg_status tune_dc(grg_schur S, int prec, int nrhs, int reps)
                 if (ch > 0 && ch * 8 >= items) continue;
                 t.grid = round8(std::min<long>(items, 2048));
                 timeit(t);
+                t.split = 1;  // the LDS-ring form (where valid)
+                if (ch <= 8) timeit(t);
             }
         }
     }

@@ -16,80 +16,85 @@ namespace grg {
 
 // ------------------------------------------------------------------ stencil
 // One hop's arithmetic on loaded data: p = psi at the neighbour, u = link.
+// Projection: h = psi_up -/+ B_mu psi_lo   (- for the forward hop, + for the
+// backward), from the neighbour's four spin components l0..l3 (colour a).
 template <int MU, bool FWD, class R>
-__device__ __forceinline__ void hop_math(cpx<R> (&acc)[12], const cpx<R> (&p)[12],
+__device__ __forceinline__ void project1(cpx<R> &h0, cpx<R> &h1, cpx<R> u0, cpx<R> u1, cpx<R> l0, cpx<R> l1)
+{
+    const R sg = FWD ? R(-1) : R(1);
+    cpx<R> b0, b1;
+    if (MU == 0) {        // (i l1, i l0)
+        b0 = {-l1.im, l1.re};
+        b1 = {-l0.im, l0.re};
+    } else if (MU == 1) { // (-l1, l0)
+        b0 = {-l1.re, -l1.im};
+        b1 = l0;
+    } else if (MU == 2) { // (i l0, -i l1)
+        b0 = {-l0.im, l0.re};
+        b1 = {l1.im, -l1.re};
+    } else {              // (l0, l1)
+        b0 = l0;
+        b1 = l1;
+    }
+    h0 = {u0.re + sg * b0.re, u0.im + sg * b0.im};
+    h1 = {u1.re + sg * b1.re, u1.im + sg * b1.im};
+}
+
+// w = U h (forward) or U^+ h (backward), one colour vector per spin, each
+// complex multiply-add four fused multiply-adds; then the upper spins take
+// -1/2 w and the lower spins -1/2 (-/+ B^+ w) = +/- 1/2 B^+ w.
+template <int MU, bool FWD, class R>
+__device__ __forceinline__ void hop_mult(cpx<R> (&acc)[12], const cpx<R> (&h0)[3], const cpx<R> (&h1)[3],
                                          const cpx<R> (&u)[9])
 {
-    // h = psi_up -/+ B_mu psi_lo   (- for the forward hop, + for the backward)
-    const R sg = FWD ? R(-1) : R(1);
-    cpx<R> h0[3], h1[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const cpx<R> l0 = p[6 + a], l1 = p[9 + a];
-        cpx<R> b0, b1;
-        if (MU == 0) {        // (i l1, i l0)
-            b0 = {-l1.im, l1.re};
-            b1 = {-l0.im, l0.re};
-        } else if (MU == 1) { // (-l1, l0)
-            b0 = {-l1.re, -l1.im};
-            b1 = l0;
-        } else if (MU == 2) { // (i l0, -i l1)
-            b0 = {-l0.im, l0.re};
-            b1 = {l1.im, -l1.re};
-        } else {              // (l0, l1)
-            b0 = l0;
-            b1 = l1;
-        }
-        h0[a] = {p[a].re + sg * b0.re, p[a].im + sg * b0.im};
-        h1[a] = {p[3 + a].re + sg * b1.re, p[3 + a].im + sg * b1.im};
-    }
-    // w = U h (forward) or U^+ h (backward), one colour vector per spin;
-    // each complex multiply-add is four fused multiply-adds
-    cpx<R> w0[3], w1[3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        cpx<R> s0 = {0, 0}, s1 = {0, 0};
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            if (FWD) {
-                cmac(s0, u[3 * r + c], h0[c]);
-                cmac(s1, u[3 * r + c], h1[c]);
-            } else {
-                cmacc(s0, u[3 * c + r], h0[c]);
-                cmacc(s1, u[3 * c + r], h1[c]);
-            }
-        }
-        w0[r] = s0;
-        w1[r] = s1;
-    }
-    // upper spins: -1/2 w ; lower spins: -1/2 (-/+ B^+ w) = +/- 1/2 B^+ w
     const R hu = R(-0.5);
     const R hl = FWD ? R(0.5) : R(-0.5);
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-        acc[r].re = fma(hu, w0[r].re, acc[r].re);
-        acc[r].im = fma(hu, w0[r].im, acc[r].im);
-        acc[3 + r].re = fma(hu, w1[r].re, acc[3 + r].re);
-        acc[3 + r].im = fma(hu, w1[r].im, acc[3 + r].im);
+        cpx<R> w0 = {0, 0}, w1 = {0, 0};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (FWD) {
+                cmac(w0, u[3 * r + c], h0[c]);
+                cmac(w1, u[3 * r + c], h1[c]);
+            } else {
+                cmacc(w0, u[3 * c + r], h0[c]);
+                cmacc(w1, u[3 * c + r], h1[c]);
+            }
+        }
+        acc[r].re = fma(hu, w0.re, acc[r].re);
+        acc[r].im = fma(hu, w0.im, acc[r].im);
+        acc[3 + r].re = fma(hu, w1.re, acc[3 + r].re);
+        acc[3 + r].im = fma(hu, w1.im, acc[3 + r].im);
         cpx<R> d0, d1;  // B^+ w
         if (MU == 0) {        // (-i w1, -i w0)
-            d0 = {w1[r].im, -w1[r].re};
-            d1 = {w0[r].im, -w0[r].re};
+            d0 = {w1.im, -w1.re};
+            d1 = {w0.im, -w0.re};
         } else if (MU == 1) { // (w1, -w0)
-            d0 = w1[r];
-            d1 = {-w0[r].re, -w0[r].im};
+            d0 = w1;
+            d1 = {-w0.re, -w0.im};
         } else if (MU == 2) { // (-i w0, i w1)
-            d0 = {w0[r].im, -w0[r].re};
-            d1 = {-w1[r].im, w1[r].re};
+            d0 = {w0.im, -w0.re};
+            d1 = {-w1.im, w1.re};
         } else {              // (w0, w1)
-            d0 = w0[r];
-            d1 = w1[r];
+            d0 = w0;
+            d1 = w1;
         }
         acc[6 + r].re = fma(hl, d0.re, acc[6 + r].re);
         acc[6 + r].im = fma(hl, d0.im, acc[6 + r].im);
         acc[9 + r].re = fma(hl, d1.re, acc[9 + r].re);
         acc[9 + r].im = fma(hl, d1.im, acc[9 + r].im);
     }
+}
+
+template <int MU, bool FWD, class R>
+__device__ __forceinline__ void hop_math(cpx<R> (&acc)[12], const cpx<R> (&p)[12],
+                                         const cpx<R> (&u)[9])
+{
+    cpx<R> h0[3], h1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) project1<MU, FWD>(h0[a], h1[a], p[a], p[3 + a], p[6 + a], p[9 + a]);
+    hop_mult<MU, FWD>(acc, h0, h1, u);
 }
 
 // ------------------------------------------------------------------ BF16 hop
@@ -269,10 +274,16 @@ template <int MU, bool FWD>
 __device__ __forceinline__ void hop(cpx<double> (&acc)[12], const uint32_t (&p)[12],
                                     const cpx<double> (&u)[9])
 {
-    cpx<double> q[12];
+    // the projection straight from the packed words (sums of two BF16
+    // values, exact in FP64), without widening all twelve components first
+    auto wd = [](uint32_t w) -> cpx<double> {
+        return {(double)__uint_as_float(w << 16), (double)__uint_as_float(w & 0xffff0000u)};
+    };
+    cpx<double> h0[3], h1[3];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) q[c] = {__uint_as_float(p[c] << 16), __uint_as_float(p[c] & 0xffff0000u)};
-    hop_math<MU, FWD>(acc, q, u);
+    for (int a = 0; a < 3; ++a)
+        project1<MU, FWD>(h0[a], h1[a], wd(p[a]), wd(p[3 + a]), wd(p[6 + a]), wd(p[9 + a]));
+    hop_mult<MU, FWD>(acc, h0, h1, u);
 }
 template <class R>
 __device__ __forceinline__ cpx<R> as_cpx(const cpx<R> &v) { return v; }

@@ -119,7 +119,8 @@ def test_solver_with_march_kernel(inner, rg):
 def test_defect_correction_every_launch(inner):
     """The fused FP64 defect-correction step in every launch shape (site-
     parallel, and t-marching with all, some or one RHS per workgroup and
-    ragged time chunks) gives the same solve."""
+    ragged time chunks, for BF16 e also its LDS-ring form) gives the same
+    solve."""
     lat = Lattice((8, 8, 8, 16), 0.5, 9)
     inner_tol = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 1e-2}[inner]
     s = lat.schur(-0.3, "I", False, tol=1e-12, inner=inner, inner_tol=inner_tol, max_rhs=4)
@@ -132,6 +133,8 @@ def test_defect_correction_every_launch(inner):
         for rg in (4, 2, 1):
             for chunk in (0, 1):
                 shapes.append(dict(SB=64, RG=rg, split=0, grid=40, chunk=chunk, march=T))
+                if inner == "bf16":  # the LDS-ring form (BF16 e only)
+                    shapes.append(dict(SB=64, RG=rg, split=1, grid=40, chunk=chunk, march=T))
     for shp in shapes:
         grg.grg_schur_set_dc_launch(s.h, inner, 4, shp)
         assert grg.grg_schur_dc_launch_info(s.h, inner, 4)["march"] == shp["march"]
@@ -141,8 +144,13 @@ def test_defect_correction_every_launch(inner):
     for bad in (dict(SB=96, RG=1, split=0, grid=64, chunk=0, march=0),
                 dict(SB=64, RG=12, split=0, grid=64, chunk=0, march=2),
                 dict(SB=64, RG=1, split=0, grid=60, chunk=0, march=2),
-                dict(SB=64, RG=1, split=0, grid=64, chunk=0, march=17)):
+                dict(SB=64, RG=1, split=0, grid=64, chunk=0, march=17),
+                dict(SB=64, RG=1, split=1, grid=64, chunk=0, march=0),
+                dict(SB=64, RG=1, split=2, grid=64, chunk=0, march=2)):
         with pytest.raises(grg.GrgError):
             grg.grg_schur_set_dc_launch(s.h, inner, 4, bad)
+    if inner != "bf16":
+        with pytest.raises(grg.GrgError):
+            grg.grg_schur_set_dc_launch(s.h, inner, 4, dict(SB=64, RG=1, split=1, grid=64, chunk=0, march=2))
     s.close()
     lat.close()
