@@ -68,7 +68,7 @@ struct EoArgs {
     int nrhs, SB, RG, hops, chunk;
     int march;            // hops == 3: time slices per workgroup item (t-marching form)
     double *partials;     // [grid][nrhs][3] or nullptr
-    const void *dot_with; // parity po
+    const void *dot_with; // parity po, or nullptr: the sums are |out|^2 only (re, im zero)
     const int *active;    // per RHS: 0 writes zero for that RHS (nullptr: all active)
     // full-layout variants (the first and last steps of a reduced solve read
     // and write the unreduced fields directly): in / in2 indexed by the full
@@ -171,7 +171,8 @@ struct BlasShape {
 //  mode kAlpha: in k = 3 (re<q,r>, im<q,r>, |q|^2); alpha[r] = <q,r>/|q|^2 if
 //               active[r], else 0.  Also stores |q|^2 in aux[r].
 //  mode kNorm : in k = 1; out2[r] = sum; active[r] = sum > thr2[r].
-enum { kAlpha = 0, kNorm = 1 };
+//  mode kNorm3: as kNorm from the third of k = 3 sums (a stencil's fused |out|^2).
+enum { kAlpha = 0, kNorm = 1, kNorm3 = 2 };
 hipError_t launch_reduce(int mode, const double *partials, int nparts, int nrhs, double2 *alpha,
                          double *out2, const double *thr2, int *active, hipStream_t st);
 

@@ -710,7 +710,7 @@ __global__ void __launch_bounds__(256) reduce_kernel(int mode, const double *par
 {
     __shared__ double sm[3][256];
     const int r = blockIdx.x;
-    const int K = mode == kAlpha ? 3 : 1;
+    const int K = mode == kNorm ? 1 : 3;
     double acc[3] = {0, 0, 0};
     for (int i = threadIdx.x; i < nparts; i += 256)
         for (int k = 0; k < K; ++k) acc[k] += partials[((size_t)i * nrhs + r) * K + k];
@@ -728,8 +728,9 @@ __global__ void __launch_bounds__(256) reduce_kernel(int mode, const double *par
             alpha[r] = on ? make_double2(sm[0][0] / qq, sm[1][0] / qq) : make_double2(0.0, 0.0);
             if (out2) out2[r] = qq;
         } else {
-            out2[r] = sm[0][0];
-            if (active) active[r] = sm[0][0] > thr2[r] ? 1 : 0;
+            const double n2 = sm[mode == kNorm3 ? 2 : 0][0];
+            out2[r] = n2;
+            if (active) active[r] = n2 > thr2[r] ? 1 : 0;
         }
     }
 }

@@ -248,7 +248,7 @@ __device__ __forceinline__ void eo_march(const EoArgs &a, double (*red)[3])
                     stc(out, i, o);
                 }
                 if (dots && on) {
-                    const cpx<R> v = dot_in2 ? v2 : ldr<R>((const S *)a.dot_with, i);
+                    const cpx<R> v = dot_in2 ? v2 : a.dot_with ? ldr<R>((const S *)a.dot_with, i) : cpx<R>{0, 0};
                     sre = fma(o.re, v.re, fma(o.im, v.im, sre));
                     sim = fma(o.re, v.im, fma(-o.im, v.re, sim));
                     sqq = fma(o.re, o.re, fma(o.im, o.im, sqq));
@@ -354,7 +354,7 @@ __device__ __forceinline__ void eo_multi(const EoArgs &a, double (*red)[kMaxRhs]
                     }
                     stc(out, i, o);
                     if (dots && on) {
-                        const cpx<R> v = ldr<R>((const S *)a.dot_with, i);
+                        const cpx<R> v = a.dot_with ? ldr<R>((const S *)a.dot_with, i) : cpx<R>{0, 0};
                         sre = fma(o.re, v.re, fma(o.im, v.im, sre));
                         sim = fma(o.re, v.im, fma(-o.im, v.re, sim));
                         sqq = fma(o.re, o.re, fma(o.im, o.im, sqq));
@@ -526,7 +526,7 @@ __global__ void __launch_bounds__(256) eo_hop_kernel(EoArgs a)
                         stc(out, i, o);
                     }
                     if (dots && on) {
-                        const cpx<R> v = ldr<R>((const S *)a.dot_with, i);
+                        const cpx<R> v = a.dot_with ? ldr<R>((const S *)a.dot_with, i) : cpx<R>{0, 0};
                         sre = fma(o.re, v.re, fma(o.im, v.im, sre));
                         sim = fma(o.re, v.im, fma(-o.im, v.re, sim));
                         sqq = fma(o.re, o.re, fma(o.im, o.im, sqq));
@@ -731,7 +731,7 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
                     stc(out, i, o);
                 }
                 if (dots && on) {
-                    const cpx<R> v = dot_in2 ? v2 : ldr<R>((const S *)a.dot_with, i);
+                    const cpx<R> v = dot_in2 ? v2 : a.dot_with ? ldr<R>((const S *)a.dot_with, i) : cpx<R>{0, 0};
                     sre = fma(o.re, v.re, fma(o.im, v.im, sre));
                     sim = fma(o.re, v.im, fma(-o.im, v.re, sim));
                     sqq = fma(o.re, o.re, fma(o.im, o.im, sqq));

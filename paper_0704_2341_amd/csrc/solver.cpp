@@ -504,10 +504,12 @@ static grg_status ensure_eo(grg_schur S, int prec)
 }
 
 // out = alpha in2 + beta H in on the rest sites of parity po (compact fields)
+// partials: per-workgroup sums, grid_out (if set) the number of workgroups
+// that wrote them
 static grg_status eo_hop(grg_schur S, int prec, const DslashTune &t, const void *in, const void *in2,
                          void *out, int po, double alpha, double beta, int nrhs, double *partials,
                          const void *dot_with, const int *active = nullptr, int in_full = 0,
-                         int in2_full = 0, const void *partner = nullptr)
+                         int in2_full = 0, const void *partner = nullptr, int *grid_out = nullptr)
 {
     grg_lattice L = S->lat;
     // the full-layout steps: with the t-marching form tuned, in the one-hop
@@ -546,6 +548,7 @@ static grg_status eo_hop(grg_schur S, int prec, const DslashTune &t, const void 
     const bool ev = !io && P.on && P.used < (int)P.start.size();
     if (ev) GRG_TRY_HIP(hipEventRecord(P.start[P.used], L->stream));
     GRG_TRY_HIP(launch_eo_hop(prec, a, tu.grid, L->stream));
+    if (grid_out) *grid_out = tu.grid;
     if (ev) {
         GRG_TRY_HIP(hipEventRecord(P.stop[P.used], L->stream));
         P.prec[P.used] = prec + 3;
@@ -766,11 +769,12 @@ static grg_status inner_mr_eo(grg_schur S, int prec, int nrhs, const double *thr
     const double d = 4.0 + S->m0;
     const int check = std::max(1, S->prm.check_every);
     // the reduced right-hand side b_P - H_PQ b_Q / d, read from the full field
-    GRG_TRY(eo_hop(S, prec, t, b, b, r, P, 1.0, -1.0 / d, nrhs, nullptr, nullptr, nullptr, 1, 1));
+    // (with |r|^2 summed by the same launch)
+    int pgrid = 0;
+    GRG_TRY(eo_hop(S, prec, t, b, b, r, P, 1.0, -1.0 / d, nrhs, S->partials, nullptr, nullptr, 1, 1, nullptr,
+                   &pgrid));
     GRG_TRY_HIP(launch_fill_zero(x, vbytes, st));
-    GRG_TRY_HIP(launch_norm2(prec, sh, r, S->partials, st));
-    GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, S->thr2,
-                              S->active, st));
+    GRG_TRY_HIP(launch_reduce(kNorm3, S->partials, pgrid, nrhs, nullptr, S->rn2, S->thr2, S->active, st));
     double h[kMaxRhs];
     GRG_TRY(read_norms(S, nrhs, h));
     // the RHS that take steps at all (the others keep a zero correction)
@@ -844,11 +848,12 @@ static grg_status inner_fgcr_eo(grg_schur S, int prec, int nrhs, const double *t
     const void *b = S->in_r[prec];
     const double d = 4.0 + S->m0;
     const int check = std::max(1, S->prm.check_every);
-    GRG_TRY(eo_hop(S, prec, t, b, b, r, P, 1.0, -1.0 / d, nrhs, nullptr, nullptr, nullptr, 1, 1));
+    // (with |r|^2 summed by the same launch)
+    int pgrid = 0;
+    GRG_TRY(eo_hop(S, prec, t, b, b, r, P, 1.0, -1.0 / d, nrhs, S->partials, nullptr, nullptr, 1, 1, nullptr,
+                   &pgrid));
     GRG_TRY_HIP(launch_fill_zero(x, vbytes, st));
-    GRG_TRY_HIP(launch_norm2(prec, sh, r, S->partials, st));
-    GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, S->thr2,
-                              S->active, st));
+    GRG_TRY_HIP(launch_reduce(kNorm3, S->partials, pgrid, nrhs, nullptr, S->rn2, S->thr2, S->active, st));
     double h[kMaxRhs];
     GRG_TRY(read_norms(S, nrhs, h));
     {
