@@ -176,10 +176,11 @@ enum { kAlpha = 0, kNorm = 1, kNorm3 = 2 };
 hipError_t launch_reduce(int mode, const double *partials, int nparts, int nrhs, double2 *alpha,
                          double *out2, const double *thr2, int *active, hipStream_t st);
 
-// x += alpha r ; r -= alpha q ; partial |r|^2     (one MR/GCR step)
+// x += alpha r ; r -= alpha q ; partial |r|^2     (one MR/GCR step; x_zero:
+// x is taken as zero and not read, the first step from x = 0)
 hipError_t launch_mr_update(int prec, const BlasShape &sh, void *x, void *r, const void *q,
                             const void *p, const double2 *alpha, double *partials,
-                            hipStream_t st);
+                            hipStream_t st, bool x_zero = false);
 // partial |v|^2
 hipError_t launch_norm2(int prec, const BlasShape &sh, const void *v, double *partials,
                         hipStream_t st);

@@ -114,7 +114,9 @@ struct VecIO<GRG_FP64> {
 // units with 16-byte accesses, so every load and store instruction of the
 // wavefront moves 1 KB of consecutive memory, and alpha and the norm of a
 // unit belong to one RHS.  Units are walked in tile order, XCD-aware.
-template <int P, bool HAS_P>
+// X0: x is taken as zero (not read): the first update of a solve started
+// from x = 0.
+template <int P, bool HAS_P, bool X0 = false>
 __global__ void __launch_bounds__(256) mr_update_kernel(BlasShape sh, void *x_, void *r_,
                                                         const void *q_, const void *p_,
                                                         const double2 *alpha, double *partials)
@@ -145,7 +147,7 @@ __global__ void __launch_bounds__(256) mr_update_kernel(BlasShape sh, void *x_, 
             const int site = tile * 64 + (((v * 64 + lane) * N) & 63);
             if (site < sh.g.V) {
                 const size_t i = base + v * 64 + lane;
-                const uint4 xv = x[i], rv = r[i], qv = q[i];
+                const uint4 xv = X0 ? make_uint4(0, 0, 0, 0) : x[i], rv = r[i], qv = q[i];
                 cpx<R> xc[N], rc[N], qc[N], pc[N];
                 IO::get(xv, xc);
                 IO::get(rv, rc);
@@ -789,12 +791,14 @@ hipError_t launch_reduce(int mode, const double *partials, int nparts, int nrhs,
 
 hipError_t launch_mr_update(int prec, const BlasShape &sh, void *x, void *r, const void *q,
                             const void *p, const double2 *alpha, double *partials,
-                            hipStream_t st)
+                            hipStream_t st, bool x_zero)
 {
     if (!shape_ok(sh)) return hipErrorInvalidValue;
     dim3 g(sh.grid), b(kBlasSB);
 #define MRU(PP)                                                                                    \
     if (p) hipLaunchKernelGGL((mr_update_kernel<PP, true>), g, b, 0, st, sh, x, r, q, p, alpha, partials); \
+    else if (x_zero)                                                                                      \
+        hipLaunchKernelGGL((mr_update_kernel<PP, false, true>), g, b, 0, st, sh, x, r, q, p, alpha, partials); \
     else hipLaunchKernelGGL((mr_update_kernel<PP, false>), g, b, 0, st, sh, x, r, q, p, alpha, partials);
     switch (prec) {
     case GRG_FP64: MRU(GRG_FP64) break;

@@ -773,7 +773,6 @@ static grg_status inner_mr_eo(grg_schur S, int prec, int nrhs, const double *thr
     int pgrid = 0;
     GRG_TRY(eo_hop(S, prec, t, b, b, r, P, 1.0, -1.0 / d, nrhs, S->partials, nullptr, nullptr, 1, 1, nullptr,
                    &pgrid));
-    GRG_TRY_HIP(launch_fill_zero(x, vbytes, st));
     GRG_TRY_HIP(launch_reduce(kNorm3, S->partials, pgrid, nrhs, nullptr, S->rn2, S->thr2, S->active, st));
     double h[kMaxRhs];
     GRG_TRY(read_norms(S, nrhs, h));
@@ -798,7 +797,8 @@ static grg_status inner_mr_eo(grg_schur S, int prec, int nrhs, const double *thr
         GRG_TRY(eo_hop(S, prec, t, w, r, q, P, d, -1.0 / d, nrhs, S->partials, r));
         GRG_TRY_HIP(launch_reduce(kAlpha, S->partials, t.grid, nrhs, S->alpha, nullptr, nullptr,
                                   S->active, st));
-        GRG_TRY_HIP(launch_mr_update(prec, sh, x, r, q, nullptr, S->alpha, S->partials, st));
+        // x starts at zero: the first step writes x = alpha r without reading it
+        GRG_TRY_HIP(launch_mr_update(prec, sh, x, r, q, nullptr, S->alpha, S->partials, st, it == 0));
         GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, S->thr2,
                                   S->active, st));
         ++it;
@@ -807,6 +807,7 @@ static grg_status inner_mr_eo(grg_schur S, int prec, int nrhs, const double *thr
             done = all_done(h);
         }
     }
+    if (it == 0) GRG_TRY_HIP(launch_fill_zero(x, vbytes, st));
     *iters = it;
     memcpy(rn2_out, h, sizeof(double) * nrhs);
     // z_Q = (b_Q - H_QP z_P) / d (zero for RHS that took no step: their
