@@ -6,6 +6,8 @@
 // coarse vector; the full stencil over a field that is zero on 15 of 16 sites
 // would read every neighbour.  Output: the internal FP64 field, zero on the
 // coarse sites.
+#include <algorithm>
+
 #include "common.h"
 #include "engine.h"
 #include "stencil.h"
@@ -49,31 +51,47 @@ __device__ __forceinline__ void rb_hops(cpx<double> (&acc)[12], int s, const Sit
 __global__ void __launch_bounds__(256) rb_apply_kernel(Geom g, const double2 *__restrict__ xb,
                                                        const int32_t *__restrict__ bidx, int nb,
                                                        const double2 *__restrict__ U, double2 *__restrict__ out,
-                                                       int nrhs)
+                                                       int nrhs, double *partials)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double red[256];
     const int r = blockIdx.y;
-    if (s >= g.V) return;
-    cpx<double> acc[12];
+    double n2 = 0;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < g.V; s += gridDim.x * blockDim.x) {
+        cpx<double> acc[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
-    if (bidx[s] < 0) {
-        const SiteGeo q = site_geo(s, g);
-        rb_hops<0>(acc, s, q, g, xb, bidx, nb, r, U);
-        rb_hops<1>(acc, s, q, g, xb, bidx, nb, r, U);
-        rb_hops<2>(acc, s, q, g, xb, bidx, nb, r, U);
-        rb_hops<3>(acc, s, q, g, xb, bidx, nb, r, U);
+        for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
+        if (bidx[s] < 0) {
+            const SiteGeo q = site_geo(s, g);
+            rb_hops<0>(acc, s, q, g, xb, bidx, nb, r, U);
+            rb_hops<1>(acc, s, q, g, xb, bidx, nb, r, U);
+            rb_hops<2>(acc, s, q, g, xb, bidx, nb, r, U);
+            rb_hops<3>(acc, s, q, g, xb, bidx, nb, r, U);
+        }
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            out[fidx(s, r, c, nrhs)] = make_double2(acc[c].re, acc[c].im);
+            n2 += acc[c].re * acc[c].re + acc[c].im * acc[c].im;
+        }
     }
-#pragma unroll
-    for (int c = 0; c < 12; ++c) out[fidx(s, r, c, nrhs)] = make_double2(acc[c].re, acc[c].im);
+    if (partials) {  // per-workgroup |out|^2 of RHS r: partials[blockIdx.x][r]
+        red[threadIdx.x] = n2;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partials[(size_t)blockIdx.x * nrhs + r] = red[0];
+    }
 }
 
+int rb_apply_grid(const Geom &g) { return (int)std::min<long>(((long)g.V + 255) / 256, 2048); }
+
 hipError_t launch_rb_apply(const Geom &g, const double *xb, const int32_t *bidx, int nb, const void *U64,
-                           void *out, int nrhs, hipStream_t st)
+                           void *out, int nrhs, hipStream_t st, double *partials)
 {
     if (nrhs < 1 || nrhs > kMaxRhs || nb < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(rb_apply_kernel, dim3((g.V + 255) / 256, nrhs), dim3(256), 0, st, g,
-                       (const double2 *)xb, bidx, nb, (const double2 *)U64, (double2 *)out, nrhs);
+    hipLaunchKernelGGL(rb_apply_kernel, dim3(rb_apply_grid(g), nrhs), dim3(256), 0, st, g,
+                       (const double2 *)xb, bidx, nb, (const double2 *)U64, (double2 *)out, nrhs, partials);
     return hipGetLastError();
 }
 

@@ -1112,7 +1112,7 @@ static grg_status pool_slot(grg_schur S, int prec, int k, void **out)
 // when it is not (no pool overflow, no verification) the final step writes
 // y_b = [D (u - z)]_b from the corrections directly and sets *fused.
 grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, const void *u_minus,
-                              const double *xb, double *yb, bool *fused)
+                              const double *xb, double *yb, bool *fused, int bn2_parts)
 {
     grg_lattice L = S->lat;
     hipStream_t st = L->stream;
@@ -1124,9 +1124,10 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
     // device per-RHS scalars: |b|^2, then f = 1/s, s, and the next s
     double *d_f = S->bn2 + kMaxRhs, *d_s = S->bn2 + 2 * kMaxRhs, *d_sn = S->bn2 + 3 * kMaxRhs;
 
-    GRG_TRY_HIP(launch_norm2(GRG_FP64, sh, S->b64, S->partials, st));
-    GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->bn2, nullptr, nullptr,
-                              st));
+    // |b|^2: from the partial sums the producer of b left (bn2_parts > 0), or a pass over b
+    if (bn2_parts <= 0) GRG_TRY_HIP(launch_norm2(GRG_FP64, sh, S->b64, S->partials, st));
+    GRG_TRY_HIP(launch_reduce(kNorm, S->partials, bn2_parts > 0 ? bn2_parts : sh.grid, nrhs, nullptr, S->bn2,
+                              nullptr, nullptr, st));
     double bn2[kMaxRhs], rn2[kMaxRhs], sc[kMaxRhs], scn[kMaxRhs], ih[kMaxRhs];
     GRG_TRY_HIP(hipMemcpyAsync(S->h_buf, S->bn2, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
     GRG_TRY_HIP(hipStreamSynchronize(st));
@@ -1375,11 +1376,11 @@ grg_status schur_apply_internal(grg_schur S, const double *xb, double *yb, int n
     const BlasShape sh = blas_shape(g, nrhs);
     // b = (D u)_r = D_rb x_b (u = x_b on the coarse sites), from the coarse
     // vector's hops only
-    GRG_TRY_HIP(launch_rb_apply(g, xb, S->d_bidx, S->nb, L->U[GRG_FP64], S->b64, nrhs, st));
-    // z = D_rr^{-1} b, and y_b = [D (u - z)]_b fused into its last step, or
-    // x64 = u - z (u scattered into u64 when needed)
+    GRG_TRY_HIP(launch_rb_apply(g, xb, S->d_bidx, S->nb, L->U[GRG_FP64], S->b64, nrhs, st, S->partials));
+    // z = D_rr^{-1} b (|b|^2 from rb_apply's sums), and y_b = [D (u - z)]_b
+    // fused into its last step, or x64 = u - z (u scattered into u64 when needed)
     bool fused = false;
-    grg_status s = drr_solve_internal(S, nrhs, stats, S->u64, xb, yb, &fused);
+    grg_status s = drr_solve_internal(S, nrhs, stats, S->u64, xb, yb, &fused, rb_apply_grid(g));
     if (s != GRG_OK && s != GRG_ENOCONV) return s;
     (void)sh;
     if (fused) return s;
