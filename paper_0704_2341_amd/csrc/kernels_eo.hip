@@ -715,7 +715,11 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
             for (int c = 0; c < 12; ++c) {
                 const size_t i = fidx(h, r, c, nr);
                 cpx<R> o = {0, 0}, v2 = {0, 0};
-                if (in2 && on) v2 = ldr<R>(in2, in2_full ? fidx(s, r, c, nr) : i);
+                if (in2 && on) {
+                    // read once: streamed past L2
+                    const uint32_t w = __builtin_nontemporal_load((const uint32_t *)in2 + (in2_full ? fidx(s, r, c, nr) : i));
+                    v2 = as_cpx(w);
+                }
                 if (on && act) {
                     o = {be * acc[c].re, be * acc[c].im};
                     if (in2) {
@@ -723,12 +727,14 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
                         o.im = fma(al, v2.im, o.im);
                     }
                 }
+                // written once here (streamed past L2, which keeps the
+                // links and the input planes the next workgroups read)
                 if constexpr (out_full) {
                     // this site, and the other parity's site of the same index
-                    stc(out, fidx(s, r, c, nr), o);
-                    out[fidx(s ^ 1, r, c, nr)] = ((const S *)a.partner)[i];
+                    __builtin_nontemporal_store(pack_bf16(o.re, o.im), (uint32_t *)out + fidx(s, r, c, nr));
+                    __builtin_nontemporal_store(((const uint32_t *)a.partner)[i], (uint32_t *)out + fidx(s ^ 1, r, c, nr));
                 } else {
-                    stc(out, i, o);
+                    __builtin_nontemporal_store(pack_bf16(o.re, o.im), (uint32_t *)out + i);
                 }
                 if (dots && on) {
                     const cpx<R> v = dot_in2 ? v2 : a.dot_with ? ldr<R>((const S *)a.dot_with, i) : cpx<R>{0, 0};
