@@ -258,7 +258,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "the multi-GPU path is a design, not part of this build", file=sys.stderr)
+              "the path across several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

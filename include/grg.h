@@ -56,7 +56,7 @@ typedef enum {
     GRG_ENOCONV = -5,      /* solver hit its iteration cap; best iterate kept */
     GRG_ENONFINITE = -6,   /* NaN or Inf met in a residual */
     GRG_ETOO_LARGE = -7,   /* output would exceed the caller's capacity */
-    GRG_EUNSUPPORTED = -8  /* valid request this build does not support */
+    GRG_EUNSUPPORTED = -8  /* valid request that this library does not support */
 } grg_status;
 
 typedef enum { GRG_PERM_I = 1, GRG_PERM_II = 2 } grg_perm_type;
