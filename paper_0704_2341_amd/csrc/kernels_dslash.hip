@@ -188,12 +188,10 @@ struct DcEpi {
             // streams' loads from being hoisted all at once (registers)
             if (c % 3 == 0) asm volatile("" ::: "memory");
             const size_t i = fidx(s, r, c, a.nrhs);
-            // the FP64 residual streams (read once, written once) go past L2
-            typedef double d2v __attribute__((ext_vector_type(2)));
             if (on) {
-                const d2v rv = __builtin_nontemporal_load((const d2v *)(r_in + i));
+                const double2 rv = r_in[i];
                 const double2 d = make_double2(rv.x - f * acc[c].re, rv.y - f * acc[c].im);
-                __builtin_nontemporal_store(d2v{d.x, d.y}, (d2v *)(r_out + i));
+                r_out[i] = d;
                 if (r_next) stc(r_next, i, cpx<RN>{(RN)(sn * d.x), (RN)(sn * d.y)});
                 nrm[0] += d.x * d.x + d.y * d.y;
                 if (x_out) {
@@ -202,7 +200,7 @@ struct DcEpi {
                     x_out[i] = make_double2(xv.x + f * ev.re, xv.y + f * ev.im);
                 }
             } else {
-                __builtin_nontemporal_store(d2v{0.0, 0.0}, (d2v *)(r_out + i));
+                r_out[i] = make_double2(0.0, 0.0);
                 if (x_out) x_out[i] = make_double2(0.0, 0.0);
                 if (r_next) stc(r_next, i, cpx<RN>{0, 0});
             }

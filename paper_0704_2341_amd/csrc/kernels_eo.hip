@@ -569,9 +569,9 @@ __global__ void __launch_bounds__(256) eo_hop_kernel(EoArgs a)
 // barrier per slice: the slot of slice t is written during slice t - 1 and
 // read across lanes in slice t; the slot of slice t + 1, that of slice t - 2
 // before, was last read across lanes in slice t - 2, which every wave has
-// left once the barrier of slice t opens.  Workgroups of the same plane and time chunk (consecutive
-// RHS) run side by side on one XCD and share its links through L2; each XCD
-// walks its own z-slab.
+// left once the barrier of slice t opens.  Workgroups of the same plane and
+// time chunk (consecutive RHS) run side by side on one XCD and share its
+// links through L2; each XCD walks its own z-slab.
 constexpr int kMaxPlane = 512;
 
 template <int IO>
@@ -708,6 +708,9 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
             }
             R sre = 0, sim = 0, sqq = 0;
             const bool act = a.active == nullptr || a.active[r] != 0;
+            // the partner copy of the last step is the input itself at this
+            // column and slice, which the ring holds (now in slot prv)
+            const bool partner_in = out_full && a.partner == a.in;
             // the sums against in2 itself (the reduced operator's second
             // half) reuse its loaded value
             const bool dot_in2 = !in2_full && a.dot_with == a.in2;
@@ -716,9 +719,14 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
                 const size_t i = fidx(h, r, c, nr);
                 cpx<R> o = {0, 0}, v2 = {0, 0};
                 if (in2 && on) {
-                    // read once: streamed past L2
-                    const uint32_t w = __builtin_nontemporal_load((const uint32_t *)in2 + (in2_full ? fidx(s, r, c, nr) : i));
-                    v2 = as_cpx(w);
+                    if constexpr (IO == 0) {
+                        // read once, whole lines: streamed past L2
+                        v2 = as_cpx(__builtin_nontemporal_load((const uint32_t *)in2 + i));
+                    } else {
+                        // the full layout: half of each line, the other half
+                        // read by the neighbouring lanes' hops
+                        v2 = ldr<R>(in2, in2_full ? fidx(s, r, c, nr) : i);
+                    }
                 }
                 if (on && act) {
                     o = {be * acc[c].re, be * acc[c].im};
@@ -727,13 +735,14 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
                         o.im = fma(al, v2.im, o.im);
                     }
                 }
-                // written once here (streamed past L2, which keeps the
-                // links and the input planes the next workgroups read)
                 if constexpr (out_full) {
                     // this site, and the other parity's site of the same index
-                    __builtin_nontemporal_store(pack_bf16(o.re, o.im), (uint32_t *)out + fidx(s, r, c, nr));
-                    __builtin_nontemporal_store(((const uint32_t *)a.partner)[i], (uint32_t *)out + fidx(s ^ 1, r, c, nr));
+                    // (two halves of each line: ordinary stores, merged in L2)
+                    stc(out, fidx(s, r, c, nr), o);
+                    out[fidx(s ^ 1, r, c, nr)] = partner_in ? (S)ring[prv][c][tid] : ((const S *)a.partner)[i];
                 } else {
+                    // written once, whole lines: streamed past L2, which keeps
+                    // the links and the input planes the next workgroups read
                     __builtin_nontemporal_store(pack_bf16(o.re, o.im), (uint32_t *)out + i);
                 }
                 if (dots && on) {
