@@ -154,3 +154,16 @@ def test_defect_correction_every_launch(inner):
             grg.grg_schur_set_dc_launch(s.h, inner, 4, dict(SB=64, RG=1, split=1, grid=64, chunk=0, march=2))
     s.close()
     lat.close()
+
+
+def test_ring_defect_correction_needs_whole_x_rows_per_tile():
+    """The LDS-ring form of the defect-correction step takes the x hops from
+    the lanes of the same x-row: Lx must divide the 64 sites of a tile."""
+    lat = Lattice((12, 4, 4, 8), 0.5, 10)  # 192 sites per slice, 64 % 12 != 0
+    s = lat.schur(-0.3, "I", False, tol=1e-10, inner="bf16", inner_tol=1e-2, max_rhs=2)
+    with pytest.raises(lat.grg.GrgError):
+        lat.grg.grg_schur_set_dc_launch(s.h, "bf16", 2, dict(SB=64, RG=2, split=1, grid=8, chunk=0, march=2))
+    # the t-marching form without the ring is fine there
+    lat.grg.grg_schur_set_dc_launch(s.h, "bf16", 2, dict(SB=64, RG=2, split=0, grid=8, chunk=0, march=2))
+    s.close()
+    lat.close()
