@@ -113,7 +113,33 @@ def _select(rows, launch, key_id="Dispatch_Id"):
     return hit[-n:]
 
 
-def stats_summary(trace_dir: str, bench_log: str, command: str, top: int = 15) -> str:
+def step_breakdown(tr, marker: str, steps: int, top: int = 12):
+    """Per-step kernel time over the last `steps` steps of a trace, a step
+    ending with the dispatch of the kernel named by `marker` (substring)."""
+    tr = sorted(tr, key=lambda r: int(r["Start_Timestamp"]))
+    ends = [i for i, r in enumerate(tr) if marker in r["Kernel_Name"]]
+    if len(ends) < steps + 1:
+        return None
+    lo, hi = ends[-steps - 1] + 1, ends[-1] + 1
+    agg = {}
+    for r in tr[lo:hi]:
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("|", "\\|")
+        d = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        n, t = agg.get(name, (0, 0))
+        agg[name] = (n + 1, t + d)
+    busy = sum(t for _, t in agg.values())
+    wall = int(tr[hi - 1]["End_Timestamp"]) - int(tr[lo]["Start_Timestamp"])
+    lines = [f"Per step over the last {steps} steps (a step ends with `{marker}`): "
+             f"{busy / steps / 1e6:.2f} ms of kernels in {wall / steps / 1e6:.2f} ms.", "",
+             "| kernel | launches per step | avg us | ms per step | % of kernel time |",
+             "|---|---:|---:|---:|---:|"]
+    for name, (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
+        lines.append(f"| `{name}` | {n / steps:.0f} | {t / n / 1e3:.1f} | {t / steps / 1e6:.2f} | "
+                     f"{100 * t / busy:.1f} |")
+    return lines
+
+
+def stats_summary(trace_dir: str, bench_log: str, command: str, top: int = 15, marker: str = "") -> str:
     b = bench_line(bench_log)
     launch = b["roofline"]["launch"]
     st = _csv(trace_dir, "_kernel_stats.csv")
@@ -141,6 +167,10 @@ def stats_summary(trace_dir: str, bench_log: str, command: str, top: int = 15) -
                   f"({100 * (avg / live - 1):+.1f} %).",
               f"Algorithmic bytes per launch {b['roofline']['alg_bytes_per_launch']:,}: "
               f"{b['roofline']['alg_bytes_per_launch'] / avg / 1e6:.0f} GB/s on the trace's average."]
+    if marker:
+        steps = step_breakdown(tr, marker, int(b["steps"]))
+        if steps:
+            lines += [""] + steps
     return "\n".join(lines) + "\n"
 
 
@@ -227,6 +257,8 @@ def main(argv=None):
     s.add_argument("--trace", required=True)
     s.add_argument("--bench-log", required=True)
     s.add_argument("--command", required=True)
+    s.add_argument("--step-marker", default="",
+                   help="kernel name (substring) whose dispatch ends a step: adds a per-step breakdown")
     s.add_argument("--out")
     t = sub.add_parser("traffic")
     for k in ("--fetch", "--write", "--fetch-log", "--write-log", "--command"):
@@ -248,7 +280,7 @@ def main(argv=None):
         sys.stdout.write(text)
         return
     if a.cmd == "stats":
-        text = stats_summary(a.trace, a.bench_log, a.command)
+        text = stats_summary(a.trace, a.bench_log, a.command, marker=a.step_marker)
         if a.out:
             with open(a.out, "w") as f:
                 f.write(text)
