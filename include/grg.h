@@ -107,8 +107,16 @@ typedef struct {
     int n_dslash;          /* dslash launches in the call */
     double true_rel_resid; /* max over RHS of the FP64 ||b - D_rr x|| / ||b|| */
     double t_total_ms;     /* wall time of the call on the stream */
-    double t_dslash_ms;    /* summed dslash time (only with profiling on) */
+    double t_dslash_ms;    /* summed stencil time: D_rr, D_rb and the reduced operator's
+                              half-lattice stencils (only with profiling on) */
     int fallbacks;         /* inner solves redone without the preconditioner */
+    double t_dc_ms;        /* summed time of the FP64 defect-correction steps (stencil and
+                              residual update fused; profiling on) */
+    double t_blas_ms;      /* summed time of the Krylov vector kernels: updates, norms,
+                              reductions, conversions, the final sum of the corrections
+                              (profiling on) */
+    double t_prec_ms;      /* summed time of the learned preconditioner's applications
+                              inside the solve (profiling on) */
 } grg_solver_stats;
 
 /* Training of the learned preconditioner (see grg_precond_train). */
@@ -164,32 +172,55 @@ grg_status grg_gauge_set(grg_lattice lat, const double *links, int on_device);
 grg_status grg_permutation_block(const int32_t dims[4], int type, int inverse, int32_t *q,
                                  int32_t *n_coarse);
 
-/* out = D in for nrhs canonical lattice fields (device pointers), computed
- * in the given precision (inputs rounded to it, result widened to FP64). */
+/* out = D in for nrhs canonical lattice fields (device pointers): the
+ * Wilson-Dirac operator written out at the top of this header, the fine
+ * operator D that section 1 partitions and whose spectrum section 2's
+ * Figure 2 shows before and after blocking.  Computed in the given precision:
+ * inputs and links are rounded to it (BF16 through FP32, round to nearest
+ * even), the arithmetic is FP64, FP32 or FP32 on BF16 operands, and the result
+ * is widened to FP64.  Uses a grow-only scratch of the lattice handle (two
+ * fields of nrhs in that precision, allocated on the first call that needs
+ * more).  GRG_EINVAL: null pointer, nrhs outside 1..16, bad precision, gauge
+ * field not set, m0 not finite. */
 grg_status grg_dirac_apply(grg_lattice lat, double m0, int precision, const double *in,
                            double *out, int nrhs);
 
-/* A coarse operator for ordering q (host, V entries, a permutation of the
- * sites) with the first n_coarse entries coarse.  Allocates every workspace
- * for params->max_rhs right-hand sides.  params NULL = defaults. */
+/* The coarse operator S_bb = D_bb - D_br D_rr^{-1} D_rb (section 1) of the
+ * partition of D induced by the ordering q: section 1, step 1 splits D into
+ * the 2x2 blocks of the coarse sites (the first n_coarse entries of q) and
+ * the rest, with q from section 2's Permutation_block (coarse sites labelled
+ * first).  q: host, V entries, a permutation of the sites (checked);
+ * n_coarse in 1..V-1.  Allocates every workspace for params->max_rhs
+ * right-hand sides (params NULL = defaults), and the inner-precision
+ * workspaces on the first solve that needs them.  GRG_EINVAL on a bad q,
+ * n_coarse or parameter; GRG_ENOMEM if a workspace cannot be allocated. */
 grg_status grg_schur_create(grg_lattice lat, double m0, const int32_t *q, int32_t n_coarse,
                             const grg_solver_params *params, grg_schur *out);
 grg_status grg_schur_destroy(grg_schur s);
 grg_status grg_schur_set_params(grg_schur s, const grg_solver_params *params);
 
-/* x = D_rr^{-1} rhs for nrhs canonical lattice fields (device).  Entries of
- * rhs on coarse sites are ignored; x is zero there.  GRG_ENOCONV keeps the
- * best iterate.  stats may be NULL. */
+/* x = D_rr^{-1} rhs for nrhs canonical lattice fields (device): the solve
+ * with the rest-site block that S_bb needs (section 1, the S_bb formula), and
+ * the cost section 2 points at (computing S_bb requires inverting D_rr).
+ * Solved to ||rhs - D_rr x|| <= params.tol ||rhs|| per RHS in FP64 (the
+ * defect correction's FP64 residual, see grg_solver_params).  Entries of rhs
+ * on coarse sites are ignored; x is zero there.  GRG_ENOCONV keeps the best
+ * iterate; GRG_ENONFINITE on a NaN or Inf residual.  stats may be NULL. */
 grg_status grg_drr_solve(grg_schur s, const double *rhs, double *x, int nrhs,
                          grg_solver_stats *stats);
 
-/* y_b = S_bb x_b for nrhs coarse fields [nrhs][12 N_b] (device), computed as
- * S x = [ D (u - D_rr^{-1} (D u)_r) ]_b with u = x on the coarse sites. */
+/* y_b = S_bb x_b for nrhs coarse fields [nrhs][12 N_b] (device), the
+ * Schur complement of section 1 applied matrix-free:
+ * S x = [ D (u - D_rr^{-1} (D u)_r) ]_b with u = x on the coarse sites (the
+ * block-UL factorisation of section 1: its lower factor's first block
+ * column).  The D_rr solve as grg_drr_solve; errors as grg_drr_solve. */
 grg_status grg_schur_apply(grg_schur s, const double *x_b, double *y_b, int nrhs,
                            grg_solver_stats *stats);
 
-/* The dense S_bb, column-major (12 N_b)^2 complex128 in HOST memory, by
- * applying S_bb to unit vectors.  GRG_ETOO_LARGE if it exceeds cap_bytes. */
+/* The dense S_bb, column-major (12 N_b)^2 complex128 in HOST memory
+ * (caller-owned), by applying S_bb to unit vectors: what section 2's
+ * Schur_complement computes, for the spectra of section 2 (Figure 2) at small
+ * volume.  GRG_ETOO_LARGE if (12 N_b)^2 * 16 bytes exceeds cap_bytes. */
 grg_status grg_schur_assemble(grg_schur s, double *S, size_t cap_bytes);
 
 /* The second-order Schur complement approximation of section 3,
@@ -424,11 +455,13 @@ grg_status grg_batch_apply(grg_batch b, const double *x_b, double *y_b, int use_
 /* Time the batched stencil launch shapes and keep the fastest. */
 grg_status grg_batch_tune(grg_batch b);
 
-/* Kernel timing: with profiling on, every dslash launch is bracketed by HIP
- * events on the lattice stream; grg_profile_read returns the count and the
- * summed milliseconds since the last reset, per slot: precision 0..2 for
- * full-lattice stencil launches in that grg_precision, 3..5 for the half-
- * lattice stencils of the even-odd reduced solve in precision - 3. */
+/* Kernel timing: with profiling on, every dslash launch and every phase of
+ * the solve is bracketed by HIP events on the lattice stream;
+ * grg_profile_read returns the count and the summed milliseconds since the
+ * last reset, per slot: 0..2 full-lattice stencil launches in that
+ * grg_precision, 3..5 the half-lattice stencils of the even-odd reduced solve
+ * in precision - 3, 6 the FP64 defect-correction steps, 7 the Krylov vector
+ * kernels, 8 the learned preconditioner's applications. */
 grg_status grg_profile_enable(grg_schur s, int on);
 grg_status grg_profile_read(grg_schur s, int precision, int64_t *count, double *total_ms);
 grg_status grg_profile_reset(grg_schur s);

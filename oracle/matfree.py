@@ -27,6 +27,8 @@ def lib():
         L.orc_dirac_apply.argtypes = [i32p, i32p, cdp, C.c_double, cdp, cdp, C.c_int]
         L.orc_block_apply.argtypes = [i32p, i32p, cdp, C.c_double, i32p, C.c_int32, C.c_int,
                                       C.c_int, cdp, cdp, C.c_int]
+        L.orc_block_apply_abs.argtypes = [i32p, i32p, cdp, C.c_double, i32p, C.c_int32, C.c_int,
+                                          C.c_int, C.c_int, cdp, f64p, C.c_int]
         L.orc_drr_solve.argtypes = [i32p, i32p, cdp, C.c_double, i32p, C.c_int32, cdp, cdp,
                                     C.c_int, C.c_int, C.c_double, C.c_int, i32p, f64p]
         L.orc_drr_residual.argtypes = [i32p, i32p, cdp, C.c_double, i32p, C.c_int32, cdp, cdp,
@@ -72,6 +74,21 @@ def block_apply(links, dims, m0, q, nb, osel, isel, x, bc=(1, 1, 1, -1)):
     lib().orc_block_apply(d, b, np.ascontiguousarray(links), float(m0),
                           np.ascontiguousarray(q, dtype=np.int32), int(nb), int(osel), int(isel),
                           x, out, x.shape[0])
+    return out
+
+
+def block_apply_abs(links, dims, m0, q, nb, osel, isel, x, diag=True, bc=(1, 1, 1, -1)):
+    """Per output entry of block_apply, the sum of the absolute values of the
+    products it is made of (|1 -/+ gamma| |U| |x|, plus |4 + m0| |x| with
+    diag): the scale of the rounding error of any evaluation from inputs with
+    a given relative error.  Real array (nrhs, 12 V)."""
+    d, b = _geom(dims, bc)
+    v = int(np.prod(dims))
+    x = _fields(x, 12 * v)
+    out = np.empty(x.shape, np.float64)
+    lib().orc_block_apply_abs(d, b, np.ascontiguousarray(links), float(m0),
+                              np.ascontiguousarray(q, dtype=np.int32), int(nb), int(osel), int(isel),
+                              int(bool(diag)), x, out, x.shape[0])
     return out
 
 
@@ -184,3 +201,37 @@ def diag_schur_apply(links, dims, m0, q, nb, xb, bc=(1, 1, 1, -1)):
     w = u - y / (4.0 + m0)
     out = dirac_apply(links, dims, m0, w, bc).reshape(nrhs, v, 12)
     return out[:, q[:nb]].reshape(nrhs, -1)
+
+
+def reduced_apply_abs(links, dims, m0, q, nb, parity, x, bc=(1, 1, 1, -1)):
+    """The absolute-value sums of the reduced operator A_p x = d x_p - H_pq H_qp x_p / d
+    (d = 4 + m0, H the hopping part of D_rr): |d| |x_p| + |H_pq| (|H_qp| |x_p|) / |d|
+    on the rest sites of parity p, zero elsewhere.  Real (nrhs, 12 V)."""
+    v = int(np.prod(dims))
+    x = _fields(x, 12 * v)
+    nrhs = x.shape[0]
+    par = site_parity(dims)
+    on_p = (par == parity)[None, :, None]
+    ax = (np.abs(x).reshape(nrhs, v, 12) * on_p).reshape(nrhs, -1).astype(np.complex128)
+    h1 = block_apply_abs(links, dims, m0, q, nb, 0, 0, ax, diag=False, bc=bc).reshape(nrhs, v, 12)
+    h1 = (h1 * ~on_p).reshape(nrhs, -1).astype(np.complex128)
+    h2 = block_apply_abs(links, dims, m0, q, nb, 0, 0, h1, diag=False, bc=bc).reshape(nrhs, v, 12)
+    d = abs(4.0 + m0)
+    rest = np.ones(v, bool)
+    rest[np.asarray(q)[:nb]] = False
+    out = (d * np.abs(ax.real).reshape(nrhs, v, 12) + h2 / d) * on_p * rest[None, :, None]
+    return out.reshape(nrhs, -1)
+
+
+def reduced_intermediate(links, dims, m0, q, nb, parity, x, bc=(1, 1, 1, -1)):
+    """The intermediate field of the reduced operator, H_qp x_p on the rest
+    sites of the other parity q (zero elsewhere): the first of its two
+    stencil steps."""
+    v = int(np.prod(dims))
+    x = _fields(x, 12 * v)
+    nrhs = x.shape[0]
+    par = site_parity(dims)
+    on_p = (par == parity)[None, :, None]
+    xp = (x.reshape(nrhs, v, 12) * on_p).reshape(nrhs, -1)
+    y = block_apply(links, dims, m0, q, nb, 0, 0, xp, bc).reshape(nrhs, v, 12)
+    return (y * ~on_p).reshape(nrhs, -1)

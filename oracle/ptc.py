@@ -151,3 +151,57 @@ def unpack_weights(flat, channels=CHANNELS):
 def to_channels(field, dims):
     """Dirac field (12 V,) -> (V, 4, 3) channels (spin = channel)."""
     return np.asarray(field).reshape(int(np.prod(dims)), 4, 3)
+
+
+def _neighbours(sites, dims, mu, step, bc):
+    """Lexicographic index of site + step*mu for each site, and the boundary
+    sign of the hop (bc[mu] where it wraps, else 1)."""
+    c = []
+    r = np.asarray(sites, dtype=np.int64)
+    for nu in range(4):
+        c.append(r % dims[nu])
+        r = r // dims[nu]
+    n = c[mu] + step
+    wrap = (n < 0) | (n >= dims[mu])
+    c[mu] = n % dims[mu]
+    idx = c[0] + dims[0] * (c[1] + dims[1] * (c[2] + dims[2] * c[3]))
+    return idx, np.where(wrap, float(bc[mu]), 1.0)
+
+
+def net_forward_sites(x, ws, links, dims, sites, bc=(1, 1, 1, -1)):
+    """The network output at the given sites only, (len(sites), F, 3).
+
+    Each layer's output at a site needs the previous activation at that site
+    and its eight neighbours, so the input is read on the sites within three
+    hops.  The activations are evaluated on those shrinking site sets one
+    layer after the other, each hop as an explicit neighbour gather with its
+    link and boundary sign, for lattices too large for the whole-lattice
+    evaluation."""
+    links = np.asarray(links)
+    sets = [np.unique(np.asarray(sites, dtype=np.int64))]
+    for _ in ws:
+        s = sets[-1]
+        grown = [s] + [_neighbours(s, dims, mu, st, bc)[0] for mu in range(4) for st in (1, -1)]
+        sets.append(np.unique(np.concatenate(grown)))
+    sets = sets[::-1]  # sets[0]: input sites, sets[-1]: output sites
+    act = np.asarray(x)[sets[0]]
+    for l, w in enumerate(ws):
+        src, dst = sets[l], sets[l + 1]
+        pos = {int(s): i for i, s in enumerate(src)}
+        out = np.zeros((len(dst), w.shape[1], 3), complex)
+        for h, (mu, step) in enumerate(HOPS):
+            if mu is None:
+                t = act[[pos[int(s)] for s in dst]]
+            else:
+                n, sign = _neighbours(dst, dims, mu, step, bc)
+                xs = act[[pos[int(s)] for s in n]] * sign[:, None, None]
+                if step > 0:
+                    u = links[dst, mu]                      # U_mu(x)
+                    t = np.einsum("vab,vfb->vfa", u, xs)
+                else:
+                    u = links[n, mu]                        # U_mu(x - mu)
+                    t = np.einsum("vba,vfb->vfa", u.conj(), xs)
+            out += np.einsum("gf,vfa->vga", w[h], t)
+        act = out
+    order = np.searchsorted(sets[-1], np.asarray(sites, dtype=np.int64))
+    return act[order]

@@ -37,7 +37,8 @@ PRECISIONS = {"fp64": GRG_FP64, "fp32": GRG_FP32, "bf16": GRG_BF16}
 EXPORTS = (
     "grg_last_error", "grg_version", "grg_solver_params_default", "grg_lattice_create",
     "grg_lattice_destroy", "grg_lattice_volume", "grg_gauge_set", "grg_permutation_block",
-    "grg_dirac_apply", "grg_schur_create", "grg_schur_destroy", "grg_schur_set_params",
+    "grg_dirac_apply", "grg_schur_create", "grg_schur_destroy",
+    "grg_schur_set_params",
     "grg_drr_solve", "grg_schur_apply", "grg_schur_assemble", "grg_reusken_apply",
     "grg_reusken_assemble", "grg_diag_schur_apply", "grg_diag_schur_assemble", "grg_schur_tune",
     "grg_schur_tune_info", "grg_schur_set_launch", "grg_schur_dc_launch_info",
@@ -69,7 +70,8 @@ class grg_solver_stats(C.Structure):
     _fields_ = [
         ("iters", C.c_int), ("outer", C.c_int), ("converged", C.c_int), ("n_dslash", C.c_int),
         ("true_rel_resid", C.c_double), ("t_total_ms", C.c_double), ("t_dslash_ms", C.c_double),
-        ("fallbacks", C.c_int),
+        ("fallbacks", C.c_int), ("t_dc_ms", C.c_double), ("t_blas_ms", C.c_double),
+        ("t_prec_ms", C.c_double),
     ]
 
     def as_dict(self):
@@ -508,11 +510,16 @@ def grg_profile_enable(s, on=True):
     _check(load().grg_profile_enable(s, int(bool(on))))
 
 
+PROFILE_PHASES = {"dc": 6, "blas": 7, "precond": 8}
+
+
 def grg_profile_read(s, precision, eo=False):
-    """(launches, summed ms) of the full-lattice stencil in `precision`, or with
-    eo=True of the even-odd half-lattice stencil."""
+    """(count, summed ms) of the full-lattice stencil in `precision`, or with
+    eo=True of the even-odd half-lattice stencil; precision "dc", "blas" or
+    "precond" reads the solve's phase of that name instead."""
     n, ms = C.c_int64(), C.c_double()
-    _check(load().grg_profile_read(s, _prec(precision) + (3 if eo else 0), C.byref(n), C.byref(ms)))
+    slot = PROFILE_PHASES[precision] if precision in PROFILE_PHASES else _prec(precision) + (3 if eo else 0)
+    _check(load().grg_profile_read(s, slot, C.byref(n), C.byref(ms)))
     return n.value, ms.value
 
 

@@ -512,8 +512,19 @@ static void collect_profile(grg_schur S)
 
 typedef std::chrono::steady_clock clk;
 
+// Summed milliseconds per profile slot when a call starts.
+struct ProfSnap {
+    double ms[kProfSlots];
+};
+static ProfSnap prof_snap(grg_schur S)
+{
+    ProfSnap p;
+    for (int k = 0; k < kProfSlots; ++k) p.ms[k] = S->prof.total_ms[k];
+    return p;
+}
+
 static grg_status finish_call(grg_schur S, grg_status st, clk::time_point t0, grg_solver_stats *stats,
-                              double dsl_before)
+                              const ProfSnap &before)
 {
     hipError_t e = hipStreamSynchronize(S->lat->stream);
     if (e != hipSuccess && st == GRG_OK) {
@@ -524,9 +535,15 @@ static grg_status finish_call(grg_schur S, grg_status st, clk::time_point t0, gr
     if (stats) {
         stats->t_total_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
         stats->n_dslash = S->n_dslash;
-        double tot = 0;
-        for (int p = 0; p < 6; ++p) tot += S->prof.total_ms[p];
-        stats->t_dslash_ms = tot - dsl_before;
+        double tot = 0, tot0 = 0;
+        for (int p = 0; p < kProfStencilSlots; ++p) {
+            tot += S->prof.total_ms[p];
+            tot0 += before.ms[p];
+        }
+        stats->t_dslash_ms = tot - tot0;
+        stats->t_dc_ms = S->prof.total_ms[kProfDc] - before.ms[kProfDc];
+        stats->t_blas_ms = S->prof.total_ms[kProfBlas] - before.ms[kProfBlas];
+        stats->t_prec_ms = S->prof.total_ms[kProfPrec] - before.ms[kProfPrec];
     }
     return st;
 }
@@ -545,8 +562,7 @@ grg_status grg_drr_solve(grg_schur S, const double *rhs, double *x, int nrhs, gr
     DeviceGuard dg(S->lat->device);
     if (stats) memset(stats, 0, sizeof *stats);
     const auto t0 = clk::now();
-    double before = 0;
-    for (int p = 0; p < 6; ++p) before += S->prof.total_ms[p];
+    const ProfSnap before = prof_snap(S);
     S->n_dslash = 0;
     S->fallbacks = 0;
     grg_lattice L = S->lat;
@@ -564,8 +580,7 @@ grg_status grg_schur_apply(grg_schur S, const double *x_b, double *y_b, int nrhs
     DeviceGuard dg(S->lat->device);
     if (stats) memset(stats, 0, sizeof *stats);
     const auto t0 = clk::now();
-    double before = 0;
-    for (int p = 0; p < 6; ++p) before += S->prof.total_ms[p];
+    const ProfSnap before = prof_snap(S);
     S->n_dslash = 0;
     S->fallbacks = 0;
     grg_status st = schur_apply_internal(S, x_b, y_b, nrhs, stats);
@@ -578,8 +593,7 @@ grg_status grg_reusken_apply(grg_schur S, const double *x_b, double *y_b, int nr
     if (4.0 + S->m0 == 0.0) return set_error("4 + m0 = 0: D_rr has a zero diagonal"), GRG_EINVAL;
     DeviceGuard dg(S->lat->device);
     const auto t0 = clk::now();
-    double before = 0;
-    for (int p = 0; p < 6; ++p) before += S->prof.total_ms[p];
+    const ProfSnap before = prof_snap(S);
     S->n_dslash = 0;
     grg_status st = reusken_apply_internal(S, x_b, y_b, nrhs);
     return finish_call(S, st, t0, nullptr, before);
@@ -591,8 +605,7 @@ grg_status grg_diag_schur_apply(grg_schur S, const double *x_b, double *y_b, int
     if (4.0 + S->m0 == 0.0) return set_error("4 + m0 = 0: D_rr has a zero diagonal"), GRG_EINVAL;
     DeviceGuard dg(S->lat->device);
     const auto t0 = clk::now();
-    double before = 0;
-    for (int p = 0; p < 6; ++p) before += S->prof.total_ms[p];
+    const ProfSnap before = prof_snap(S);
     S->n_dslash = 0;
     grg_status st = diag_schur_apply_internal(S, x_b, y_b, nrhs);
     return finish_call(S, st, t0, nullptr, before);
@@ -819,7 +832,7 @@ grg_status grg_profile_enable(grg_schur S, int on)
 grg_status grg_profile_read(grg_schur S, int precision, int64_t *count, double *total_ms)
 {
     if (!S || !count || !total_ms) return set_error("null argument"), GRG_EINVAL;
-    if (precision < 0 || precision > 5) return set_error("bad precision"), GRG_EINVAL;
+    if (precision < 0 || precision >= kProfSlots) return set_error("bad profile slot"), GRG_EINVAL;
     *count = S->prof.count[precision];
     *total_ms = S->prof.total_ms[precision];
     return GRG_OK;
@@ -828,7 +841,7 @@ grg_status grg_profile_read(grg_schur S, int precision, int64_t *count, double *
 grg_status grg_profile_reset(grg_schur S)
 {
     if (!S) return set_error("null argument"), GRG_EINVAL;
-    for (int p = 0; p < 6; ++p) {
+    for (int p = 0; p < kProfSlots; ++p) {
         S->prof.count[p] = 0;
         S->prof.total_ms[p] = 0;
     }

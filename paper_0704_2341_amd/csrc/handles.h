@@ -25,14 +25,40 @@ struct grg_lattice_s {
 
 namespace grg {
 
+// Slots of the event-timed profile: 0..2 full-lattice stencil per precision,
+// 3..5 even-odd half-stencil, then the phases of a solve.
+constexpr int kProfDc = 6, kProfBlas = 7, kProfPrec = 8, kProfSlots = 9;
+constexpr int kProfStencilSlots = 6;
+
 struct ProfilePool {
     bool on = false;
     std::vector<hipEvent_t> start, stop;
     std::vector<int> prec;
     int used = 0;
-    // slots 0..2: full-lattice stencil per precision; 3..5: even-odd half-stencil
-    long long count[6] = {0, 0, 0, 0, 0, 0};
-    double total_ms[6] = {0, 0, 0, 0, 0, 0};
+    long long count[kProfSlots] = {};
+    double total_ms[kProfSlots] = {};
+};
+
+// Times the enclosed region of a solve (the work it enqueues on the stream)
+// into a profile slot when profiling is on.  Reserves its event pair at
+// construction, so stencil launches timed inside it keep their own pairs.
+struct PhaseTimer {
+    ProfilePool *P = nullptr;
+    hipStream_t st = nullptr;
+    int idx = -1;
+    PhaseTimer(ProfilePool &pool, hipStream_t stream, int slot) : P(&pool), st(stream)
+    {
+        if (!pool.on || pool.used >= (int)pool.start.size()) return;
+        idx = pool.used++;
+        pool.prec[idx] = slot;
+        (void)hipEventRecord(pool.start[idx], st);
+    }
+    ~PhaseTimer()
+    {
+        if (idx >= 0) (void)hipEventRecord(P->stop[idx], st);
+    }
+    PhaseTimer(const PhaseTimer &) = delete;
+    PhaseTimer &operator=(const PhaseTimer &) = delete;
 };
 
 }  // namespace grg

@@ -425,19 +425,27 @@ static grg_status inner_gcr(grg_schur S, int prec, int nrhs, const double *thr, 
         const int k = it % m;
         if (m == 1 && !S->precond) {
             GRG_TRY(run_dslash(S, prec, r, q, 0, nrhs, S->partials));
+            PhaseTimer pt(S->prof, st, kProfBlas);
             GRG_TRY_HIP(launch_reduce(kAlpha, S->partials, dgrid, nrhs, S->alpha, nullptr, nullptr,
                                       S->active, st));
             GRG_TRY_HIP(launch_mr_update(prec, sh, x, r, q, nullptr, S->alpha, S->partials, st));
         } else {
             void *pk = Pm + (size_t)k * vstride, *qk = Qm + (size_t)k * vstride;
-            if (S->precond) GRG_TRY(precond_apply_inner(S, prec, r, pk, nrhs));  // p = M r
-            else GRG_TRY_HIP(launch_copy(prec, sh, r, pk, st));
+            if (S->precond) {
+                PhaseTimer pt(S->prof, st, kProfPrec);
+                GRG_TRY(precond_apply_inner(S, prec, r, pk, nrhs));  // p = M r
+            } else {
+                PhaseTimer pt(S->prof, st, kProfBlas);
+                GRG_TRY_HIP(launch_copy(prec, sh, r, pk, st));
+            }
             if (k == 0) {
                 GRG_TRY(run_dslash(S, prec, pk, qk, 0, nrhs, S->partials, r));
+                PhaseTimer pt(S->prof, st, kProfBlas);
                 GRG_TRY_HIP(launch_reduce(kAlpha, S->partials, dgrid, nrhs, S->alpha, S->qn2,
                                           nullptr, S->active, st));
             } else {
                 GRG_TRY(run_dslash(S, prec, pk, qk, 0, nrhs, nullptr));
+                PhaseTimer pt(S->prof, st, kProfBlas);
                 GRG_TRY_HIP(launch_multidot(prec, sh, Qm, k, qk, S->partials, st));
                 GRG_TRY_HIP(launch_reduce_multi(S->partials, sh.grid, nrhs, k, S->qn2, S->active,
                                                 S->beta, st));
@@ -446,10 +454,14 @@ static grg_status inner_gcr(grg_schur S, int prec, int nrhs, const double *thr, 
                 GRG_TRY_HIP(launch_reduce(kAlpha, S->partials, sh.grid, nrhs, S->alpha,
                                           S->qn2 + (size_t)k * kMaxRhs, nullptr, S->active, st));
             }
+            PhaseTimer pt(S->prof, st, kProfBlas);
             GRG_TRY_HIP(launch_mr_update(prec, sh, x, r, qk, pk, S->alpha, S->partials, st));
         }
-        GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, S->thr2,
-                                  S->active, st));
+        {
+            PhaseTimer pt(S->prof, st, kProfBlas);
+            GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, S->thr2,
+                                      S->active, st));
+        }
         ++it;
         if (it % check == 0 || it == maxit) {
             GRG_TRY(read_norms(S, nrhs, h));
@@ -795,12 +807,15 @@ static grg_status inner_mr_eo(grg_schur S, int prec, int nrhs, const double *thr
         // q = (d - H_PQ H_QP / d) r, with the sums for alpha
         GRG_TRY(eo_hop(S, prec, t, r, nullptr, w, Q, 0.0, 1.0, nrhs, nullptr, nullptr));
         GRG_TRY(eo_hop(S, prec, t, w, r, q, P, d, -1.0 / d, nrhs, S->partials, r));
-        GRG_TRY_HIP(launch_reduce(kAlpha, S->partials, t.grid, nrhs, S->alpha, nullptr, nullptr,
-                                  S->active, st));
-        // x starts at zero: the first step writes x = alpha r without reading it
-        GRG_TRY_HIP(launch_mr_update(prec, sh, x, r, q, nullptr, S->alpha, S->partials, st, it == 0));
-        GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, S->thr2,
-                                  S->active, st));
+        {
+            PhaseTimer pt(S->prof, st, kProfBlas);
+            GRG_TRY_HIP(launch_reduce(kAlpha, S->partials, t.grid, nrhs, S->alpha, nullptr, nullptr,
+                                      S->active, st));
+            // x starts at zero: the first step writes x = alpha r without reading it
+            GRG_TRY_HIP(launch_mr_update(prec, sh, x, r, q, nullptr, S->alpha, S->partials, st, it == 0));
+            GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, S->thr2,
+                                      S->active, st));
+        }
         ++it;
         if (it % check == 0 || it == maxit) {
             GRG_TRY(read_norms(S, nrhs, h));
@@ -873,17 +888,23 @@ static grg_status inner_fgcr_eo(grg_schur S, int prec, int nrhs, const double *t
     int done = all_done(h);
     while (done == 0 && it < maxit) {
         // p = M^ r
-        GRG_TRY_HIP(launch_eo_scatter(prec, g, nrhs, P, r, full_in, true, st));
-        GRG_TRY(precond_apply_inner(S, prec, full_in, full_out, nrhs));
-        GRG_TRY_HIP(launch_eo_scatter(prec, g, nrhs, P, full_out, pv, false, st));
+        {
+            PhaseTimer pt(S->prof, st, kProfPrec);
+            GRG_TRY_HIP(launch_eo_scatter(prec, g, nrhs, P, r, full_in, true, st));
+            GRG_TRY(precond_apply_inner(S, prec, full_in, full_out, nrhs));
+            GRG_TRY_HIP(launch_eo_scatter(prec, g, nrhs, P, full_out, pv, false, st));
+        }
         // q = A^ p with the sums <q, r>, |q|^2
         GRG_TRY(eo_hop(S, prec, t, pv, nullptr, w, Q, 0.0, 1.0, nrhs, nullptr, nullptr));
         GRG_TRY(eo_hop(S, prec, t, w, pv, q, P, d, -1.0 / d, nrhs, S->partials, r));
-        GRG_TRY_HIP(launch_reduce(kAlpha, S->partials, t.grid, nrhs, S->alpha, nullptr, nullptr,
-                                  S->active, st));
-        GRG_TRY_HIP(launch_mr_update(prec, sh, x, r, q, pv, S->alpha, S->partials, st));
-        GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, S->thr2,
-                                  S->active, st));
+        {
+            PhaseTimer pt(S->prof, st, kProfBlas);
+            GRG_TRY_HIP(launch_reduce(kAlpha, S->partials, t.grid, nrhs, S->alpha, nullptr, nullptr,
+                                      S->active, st));
+            GRG_TRY_HIP(launch_mr_update(prec, sh, x, r, q, pv, S->alpha, S->partials, st));
+            GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, S->thr2,
+                                      S->active, st));
+        }
         ++it;
         if (it % check == 0 || it == maxit) {
             GRG_TRY(read_norms(S, nrhs, h));
@@ -988,16 +1009,22 @@ static grg_status inner_bicgstab(grg_schur S, int prec, int nrhs, const double *
     int done = all_done(h);
     while (done == 0 && it < maxit) {
         GRG_TRY(apply(pv, v, r0));
-        GRG_TRY_HIP(launch_bicg_reduce(kBicgAlpha, S->partials, nparts, nrhs, sc, nullptr, nullptr,
-                                       S->active, st));
-        GRG_TRY_HIP(launch_bicg(prec, kBicgS, sh, nullptr, sv, r, v, nullptr, nullptr, sc, nullptr, st));
+        {
+            PhaseTimer pt(S->prof, st, kProfBlas);
+            GRG_TRY_HIP(launch_bicg_reduce(kBicgAlpha, S->partials, nparts, nrhs, sc, nullptr, nullptr,
+                                           S->active, st));
+            GRG_TRY_HIP(launch_bicg(prec, kBicgS, sh, nullptr, sv, r, v, nullptr, nullptr, sc, nullptr, st));
+        }
         GRG_TRY(apply(sv, tv, sv));
-        GRG_TRY_HIP(launch_reduce(kAlpha, S->partials, nparts, nrhs, sc + 2 * kMaxRhs, nullptr, nullptr,
-                                  S->active, st));
-        GRG_TRY_HIP(launch_bicg(prec, kBicgUpd, sh, x, r, pv, sv, tv, r0, sc, S->partials, st));
-        GRG_TRY_HIP(launch_bicg_reduce(kBicgBeta, S->partials, sh.grid, nrhs, sc, S->rn2, S->thr2,
-                                       S->active, st));
-        GRG_TRY_HIP(launch_bicg(prec, kBicgP, sh, nullptr, pv, r, v, nullptr, nullptr, sc, nullptr, st));
+        {
+            PhaseTimer pt(S->prof, st, kProfBlas);
+            GRG_TRY_HIP(launch_reduce(kAlpha, S->partials, nparts, nrhs, sc + 2 * kMaxRhs, nullptr, nullptr,
+                                      S->active, st));
+            GRG_TRY_HIP(launch_bicg(prec, kBicgUpd, sh, x, r, pv, sv, tv, r0, sc, S->partials, st));
+            GRG_TRY_HIP(launch_bicg_reduce(kBicgBeta, S->partials, sh.grid, nrhs, sc, S->rn2, S->thr2,
+                                           S->active, st));
+            GRG_TRY_HIP(launch_bicg(prec, kBicgP, sh, nullptr, pv, r, v, nullptr, nullptr, sc, nullptr, st));
+        }
         ++it;
         if (it % check == 0 || it == maxit) {
             GRG_TRY(read_norms(S, nrhs, h));
@@ -1067,6 +1094,7 @@ constexpr int kPrecondInnerCap = 100;
 static grg_status convert_rhs(grg_schur S, int prec, const BlasShape &sh, const void *r_src,
                               const double *scale)
 {
+    PhaseTimer pt(S->prof, S->lat->stream, kProfBlas);
     GRG_TRY_HIP(launch_axpy_convert(GRG_FP64, prec, sh, r_src, S->in_r[prec], scale, 0, 0, nullptr,
                                     S->lat->stream));
     return GRG_OK;
@@ -1162,7 +1190,10 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
         if (npool > 0)
             GRG_TRY_HIP(hipMemcpyAsync(S->d_fk, S->h_fk, sizeof(double) * kCorrPool * kMaxRhs,
                                        hipMemcpyHostToDevice, st));
-        GRG_TRY_HIP(launch_combine(prec, sh, c, st));
+        {
+            PhaseTimer pt(S->prof, st, kProfBlas);
+            GRG_TRY_HIP(launch_combine(prec, sh, c, st));
+        }
         if (npool > 0) GRG_TRY_HIP(hipStreamSynchronize(st));  // h_fk is reused next
         npool = 0;
         have_x = true;
@@ -1285,9 +1316,12 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
         d.nrhs = nrhs;
         d.partials = S->partials;
         dc_fill_launch(d, dct);
-        GRG_TRY_HIP(launch_dc_update(prec, d, dct.grid, dct.SB, st));
-        GRG_TRY_HIP(launch_reduce(kNorm, S->partials, dct.grid, nrhs, nullptr, S->rn2, nullptr,
-                                  nullptr, st));
+        {
+            PhaseTimer pt(S->prof, st, kProfDc);
+            GRG_TRY_HIP(launch_dc_update(prec, d, dct.grid, dct.SB, st));
+            GRG_TRY_HIP(launch_reduce(kNorm, S->partials, dct.grid, nrhs, nullptr, S->rn2, nullptr,
+                                      nullptr, st));
+        }
         for (int k = 0; k < kMaxRhs; ++k) S->h_fk[npool * kMaxRhs + k] = k < nrhs ? f[k] : 0.0;
         ++npool;
         GRG_TRY(read_norms(S, nrhs, rn2));

@@ -123,12 +123,21 @@ def test_reduced_apply_vs_oracle(form, prec, nrhs):
     """A_p = d - H_pq H_qp / d on both parities, every launch form of the
     half-lattice stencils, against the oracle's Schur complement of D_rr."""
     launch = RA_LAUNCHES[form]
-    if launch[2] >= 2 and prec != "bf16":
-        pytest.skip("packed-BF16 hop schedules")
     dims = (16, 8, 8, 8)  # 512 half-sites per time slice: whole 64-column tiles
     lat = Lattice(dims, 0.5, 25)
     s = lat.schur(-0.3, "I", False, tol=1e-10, inner=prec, max_rhs=12)
     grg = lat.grg
+    if launch[2] >= 2 and prec != "bf16":
+        # the packed-BF16 hop schedules exist for BF16 fields only: any other
+        # precision is refused with GRG_EINVAL and the launch in use is kept
+        before = grg.grg_schur_tune_info(s.h, prec, nrhs, eo=True)
+        with pytest.raises(grg.GrgError) as ei:
+            grg.grg_schur_set_launch(s.h, prec, nrhs, launch, eo=True)
+        assert ei.value.status == grg.GRG_EINVAL
+        assert grg.grg_schur_tune_info(s.h, prec, nrhs, eo=True) == before
+        s.close()
+        lat.close()
+        return
     grg.grg_schur_set_launch(s.h, prec, nrhs, launch, eo=True)
     assert grg.grg_schur_tune_info(s.h, prec, nrhs, eo=True)["split"] == launch[2]
     x = gaussian_vectors(12 * lat.V, nrhs, 25)

@@ -104,3 +104,27 @@ def test_reduced_apply_is_dense_schur_complement(setup4, kind, inv, parity):
     want = np.zeros_like(x)
     want[:, ip] = (a @ x[:, ip].T).T
     assert np.abs(got - want).max() < 1e-12 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("kind,inv", PERMS)
+def test_drr_residual_vs_dense(setup4, kind, inv):
+    """The residual routine on an arbitrary x (not a solver iterate) against
+    ||b - D_rr x|| / ||b|| formed from the dense blocks, and a zero b."""
+    dims, u, d = setup4
+    q, nb = dense.permutation_block(dims, kind, inv)
+    _, _, _, drr = dense.blocks(d, q, nb)
+    o = dense.dof_order(q)[12 * nb:]
+    b = np.zeros((3, 12 * 256), np.complex128)
+    x = np.zeros_like(b)
+    b[:, o] = gaussian_vectors(len(o), 3, 5)
+    x[:, o] = gaussian_vectors(len(o), 3, 6) * np.array([1e-3, 0.3, 1.0])[:, None]
+    got = matfree.drr_residual(u, dims, 0.1, q, nb, b, x)
+    want = np.linalg.norm(b[:, o] - (drr @ x[:, o].T).T, axis=1) / np.linalg.norm(b[:, o], axis=1)
+    assert np.allclose(got, want, rtol=1e-13, atol=0)
+    # entries of x on coarse sites are outside D_rr's columns: ignored
+    x2 = x.copy()
+    x2[:, dense.dof_order(q)[: 12 * nb]] = 7.0
+    assert np.allclose(matfree.drr_residual(u, dims, 0.1, q, nb, b, x2), want, rtol=1e-13, atol=0)
+    # zero right-hand side: the absolute residual
+    z = matfree.drr_residual(u, dims, 0.1, q, nb, np.zeros_like(b[:1]), x[:1])
+    assert np.isclose(z[0], np.linalg.norm((drr @ x[0, o])), rtol=1e-13)

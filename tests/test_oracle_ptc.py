@@ -146,3 +146,25 @@ def test_planted_mistake_in_transport_is_caught(links, monkeypatch):
     y = ptc.layer_forward(x, w, links, DIMS)
     d = dense.wilson_dense(links, DIMS, 0.0)
     assert np.abs(y.reshape(-1) - d @ x.reshape(-1)).max() > 1e-3
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 8)])
+def test_forward_at_sites_equals_whole_lattice(dims):
+    """The sampled-site evaluation (explicit neighbour gathers on the sites
+    within three hops) against the whole-lattice evaluation (array shifts),
+    on every site and on an unsorted sample with repeats; antiperiodic and
+    periodic t."""
+    from grg_inputs import su3_links
+
+    v = int(np.prod(dims))
+    links = su3_links(dims, 0.5, 3)
+    ws = ptc.random_weights(4, scale=0.3)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((v, 4, 3)) + 1j * rng.standard_normal((v, 4, 3))
+    for bc in ((1, 1, 1, -1), (1, 1, 1, 1)):
+        full = ptc.net_forward(x, ws, links, dims, bc)[-1]
+        assert np.allclose(ptc.net_forward_sites(x, ws, links, dims, np.arange(v), bc), full,
+                           rtol=0, atol=1e-12 * np.abs(full).max())
+        smp = np.array([v - 1, 0, 17 % v, 0, v // 2])
+        assert np.allclose(ptc.net_forward_sites(x, ws, links, dims, smp, bc), full[smp],
+                           rtol=0, atol=1e-12 * np.abs(full).max())
