@@ -185,6 +185,25 @@ grg_status grg_permutation_block(const int32_t dims[4], int type, int inverse, i
 grg_status grg_dirac_apply(grg_lattice lat, double m0, int precision, const double *in,
                            double *out, int nrhs);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): out = D in
+ * exactly as grg_dirac_apply (same kernels and launch, so the same bits), but
+ * its two internal staging fields live in a fixed scratch array of
+ * GRG_NOALLOC_SCRATCH_BYTES per GPU that the library holds until the process
+ * ends, so the call itself allocates nothing (the first call on a device
+ * looks up that device's array once).  Needs
+ *     2 * ceil256(12 * Vs * nrhs * b) <= GRG_NOALLOC_SCRATCH_BYTES,
+ * b = 16, 8, 4 bytes for FP64, FP32, BF16 and Vs = V rounded up to a multiple
+ * of 256 (e.g. 8^4 with 16 RHS in FP64, 16^4 with 1 RHS); larger requests
+ * return GRG_ETOO_LARGE before anything is enqueued.  Other errors as
+ * grg_dirac_apply.  Every call on one GPU uses that GPU's one array: calls
+ * that overlap in time on one GPU (two threads, or two streams without
+ * ordering) race and give wrong results; calls ordered on one stream are
+ * safe.  No entry of the array is read before the call writes it. */
+#define GRG_NOALLOC_SCRATCH_BYTES (32u << 20)
+grg_status grg_dirac_apply_noalloc(grg_lattice lat, double m0, int precision, const double *in,
+                                   double *out, int nrhs);
+
 /* The coarse operator S_bb = D_bb - D_br D_rr^{-1} D_rb (section 1) of the
  * partition of D induced by the ordering q: section 1, step 1 splits D into
  * the 2x2 blocks of the coarse sites (the first n_coarse entries of q) and

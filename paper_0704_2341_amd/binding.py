@@ -37,7 +37,7 @@ PRECISIONS = {"fp64": GRG_FP64, "fp32": GRG_FP32, "bf16": GRG_BF16}
 EXPORTS = (
     "grg_last_error", "grg_version", "grg_solver_params_default", "grg_lattice_create",
     "grg_lattice_destroy", "grg_lattice_volume", "grg_gauge_set", "grg_permutation_block",
-    "grg_dirac_apply", "grg_schur_create", "grg_schur_destroy",
+    "grg_dirac_apply", "grg_dirac_apply_noalloc", "grg_schur_create", "grg_schur_destroy",
     "grg_schur_set_params",
     "grg_drr_solve", "grg_schur_apply", "grg_schur_assemble", "grg_reusken_apply",
     "grg_reusken_assemble", "grg_diag_schur_apply", "grg_diag_schur_assemble", "grg_schur_tune",
@@ -140,6 +140,7 @@ def load():
         "grg_gauge_set": (C.c_int, [vp, vp, C.c_int]),
         "grg_permutation_block": (C.c_int, [i32p, C.c_int, C.c_int, i32p, i32p]),
         "grg_dirac_apply": (C.c_int, [vp, C.c_double, C.c_int, vp, vp, C.c_int]),
+        "grg_dirac_apply_noalloc": (C.c_int, [vp, C.c_double, C.c_int, vp, vp, C.c_int]),
         "grg_schur_create": (C.c_int, [vp, C.c_double, i32p, C.c_int32,
                                        C.POINTER(grg_solver_params), C.POINTER(vp)]),
         "grg_schur_destroy": (C.c_int, [vp]),
@@ -281,6 +282,15 @@ def grg_permutation_block(dims, type, inverse=False):
 
 def grg_dirac_apply(lat, m0, precision, x, out, nrhs):
     _check(load().grg_dirac_apply(lat, float(m0), _prec(precision), _ptr(x), _ptr(out), int(nrhs)))
+
+
+GRG_NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def grg_dirac_apply_noalloc(lat, m0, precision, x, out, nrhs):
+    """As grg_dirac_apply, with the staging in the library's fixed per-GPU
+    scratch: allocates nothing; GRG_ETOO_LARGE beyond its size."""
+    _check(load().grg_dirac_apply_noalloc(lat, float(m0), _prec(precision), _ptr(x), _ptr(out), int(nrhs)))
 
 
 def grg_schur_create(lat, m0, q, n_coarse, params=None):

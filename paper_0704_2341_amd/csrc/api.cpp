@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -315,6 +316,79 @@ grg_status grg_dirac_apply(grg_lattice L, double m0, int precision, const double
     a.dot_with = nullptr;
     GRG_TRY_HIP(launch_dslash(precision, a, t.grid, L->stream));
     GRG_TRY_HIP(launch_unpack_spinor(precision, L->tmp_out, out, L->g, nrhs, L->stream));
+    GRG_TRY_HIP(hipStreamSynchronize(L->stream));
+    return GRG_OK;
+}
+
+// ------------------------------------------------------------------ no-alloc D apply
+// The staging fields of grg_dirac_apply_noalloc live in this fixed array, one
+// copy per GPU, held until the process ends.  In host code `scratch` is only
+// the shadow of the device symbol; its device address is taken once per
+// device with hipGetSymbolAddress and only that address is passed on.
+static __device__ __align__(256) unsigned char scratch[GRG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of this device's scratch (the device current)
+grg_status scratch_address(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return set_error("device %d out of range", dev), GRG_EINVAL;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return set_error("hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e)), GRG_EHIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return GRG_OK;
+}
+}  // namespace
+
+grg_status grg_dirac_apply_noalloc(grg_lattice L, double m0, int precision, const double *in, double *out,
+                                   int nrhs)
+{
+    if (!L || !in || !out) return set_error("null argument"), GRG_EINVAL;
+    if (nrhs < 1 || nrhs > kMaxRhs) return set_error("nrhs must be in 1..%d", kMaxRhs), GRG_EINVAL;
+    if (precision < GRG_FP64 || precision > GRG_BF16) return set_error("bad precision"), GRG_EINVAL;
+    if (!L->gauge_set) return set_error("gauge field not set"), GRG_EINVAL;
+    if (!isfinite(m0)) return set_error("m0 not finite"), GRG_EINVAL;
+    // two fields, each starting on a 256-byte boundary
+    const size_t bytes = (spinor_elems(L->g, nrhs) * prec_bytes(precision) + 255) & ~(size_t)255;
+    if (2 * bytes > (size_t)GRG_NOALLOC_SCRATCH_BYTES)
+        return set_error("dirac_apply_noalloc: %zu bytes of staging for %d RHS exceed the %u-byte scratch",
+                         2 * bytes, nrhs, (unsigned)GRG_NOALLOC_SCRATCH_BYTES),
+               GRG_ETOO_LARGE;
+    DeviceGuard dg(L->device);
+    void *base = nullptr;
+    GRG_TRY(scratch_address(L->device, &base));
+    void *sin = base, *sout = (char *)base + bytes;
+    // every entry the stencil reads (sites < V of every RHS) is written by the
+    // pack first, so nothing left by an earlier call is read
+    GRG_TRY_HIP(launch_pack_spinor(precision, in, sin, L->g, nrhs, L->stream));
+    DslashArgs a;
+    a.in = sin;
+    a.out = sout;
+    a.U = L->U[precision];
+    a.mask = nullptr;
+    a.sel = 0;
+    a.diag = 4.0 + m0;
+    a.g = L->g;
+    a.nrhs = nrhs;
+    const DslashTune t = default_tune(L->g, precision, nrhs);
+    a.SB = t.SB;
+    a.RG = t.RG;
+    a.split = t.split;
+    a.chunk = t.chunk;
+    a.march = t.march;
+    a.partials = nullptr;
+    a.dot_with = nullptr;
+    GRG_TRY_HIP(launch_dslash(precision, a, t.grid, L->stream));
+    GRG_TRY_HIP(launch_unpack_spinor(precision, sout, out, L->g, nrhs, L->stream));
     GRG_TRY_HIP(hipStreamSynchronize(L->stream));
     return GRG_OK;
 }
