@@ -437,12 +437,19 @@ grg_status grg_precond_load(grg_precond p, const char *path);
 grg_status grg_schur_attach_precond(grg_schur s, grg_precond p);
 
 /* ---------------------------------------------------------------------------
- * Many independent lattices at once.  The members (each with its own extents,
- * boundary signs, m0, links and ordering) are concatenated in one site index
- * and every kernel covers all of them in one launch; the inner iterations are
- * replayed from a HIP graph (captured on the batch's own stream), with
- * per-(member, RHS) step lengths and convergence flags.  Each member's volume
- * must be a multiple of 256 sites.
+ * Many independent lattices at once (the batched workload of 48 lattices of
+ * mixed sizes: the S_bb of section 1 for each, solved together).  The
+ * members (each with its own extents, boundary signs, m0, links and
+ * ordering) are concatenated in one site index and every kernel covers all
+ * of them in one launch, with per-(member, RHS) step lengths.  Convergence is
+ * decided on the device: per-system flags, set by the reductions and by a
+ * control kernel, gate every kernel (converged systems are skipped, a launch
+ * with no system left returns at once), so the whole apply -- every outer
+ * defect-correction step with its inner iterations, the recomputed final
+ * residual and the combine -- is one sequence of launches with no host
+ * decision inside, captured once as a HIP graph on the batch's own stream
+ * and replayed as one launch.  Each member's volume must be a multiple of
+ * 256 sites.
  * ------------------------------------------------------------------------- */
 typedef struct grg_batch_s *grg_batch;
 
@@ -456,7 +463,8 @@ typedef struct {
 } grg_batch_member;
 
 /* params->inner / inner_tol / tol / max_iter / max_outer as for one lattice;
- * check_every = inner iterations per graph replay; the inner solve is
+ * check_every = inner iterations between the host's reads of the flags in
+ * the eager mode; the inner solve is
  * minimal residual on D_rr (params->method other than 0 gives
  * GRG_EUNSUPPORTED; restart and eo are not used).  stream: the caller's
  * stream, waited on at entry and made to wait for the result at exit. */
@@ -467,12 +475,29 @@ grg_status grg_batch_destroy(grg_batch b);
  * [nrhs][12 N_b(i)] complex128 starts at complex offset *offset; member ==
  * count gives the total length and total N_b. */
 grg_status grg_batch_layout(grg_batch b, int member, int64_t *offset, int32_t *n_coarse);
-/* y_b = S_bb x_b for every member and RHS.  use_graph = 0 launches the same
- * kernels eagerly (for checking the graph). */
+/* y_b = S_bb x_b for every member and RHS.  use_graph = 1: one replay of the
+ * captured apply (see grg_batch_graph_info; x_b and y_b pass through staging
+ * buffers of the batch by two device copies), then one read of the residuals;
+ * an apply the captured counts did not finish continues eagerly from there
+ * and the next apply is re-captured with one more outer step.  use_graph = 0
+ * launches the same kernels eagerly, the host reading the flags every
+ * check_every inner iterations: same systems, same iterations, same bits. */
 grg_status grg_batch_apply(grg_batch b, const double *x_b, double *y_b, int use_graph,
                            grg_solver_stats *stats);
-/* Time the batched stencil launch shapes and keep the fastest. */
+/* Time the batched stencil launch shapes and keep the fastest (the next
+ * captured apply is re-captured with them). */
 grg_status grg_batch_tune(grg_batch b);
+/* The shape of the captured apply: counts[0] outer defect-correction steps,
+ * counts[1] inner iterations per step ({0, 0} while none is captured).  An
+ * apply with use_graph = 1 runs eagerly while the batch has no recorded
+ * counts (its first apply), records them, and later ones replay the graph. */
+grg_status grg_batch_graph_info(grg_batch b, int32_t counts[2]);
+/* The batched stencil launch in use for a precision, info = {sites per
+ * workgroup, RHS per thread, workgroups}, and from the last grg_batch_tune
+ * the time per launch (HIP events on the batch's stream, every system
+ * active) of that stencil (ms[0]) and, for the inner precision, of the MR
+ * update (ms[1]); -1 where not timed. */
+grg_status grg_batch_tune_info(grg_batch b, int precision, int32_t info[3], float ms[2]);
 
 /* Kernel timing: with profiling on, every dslash launch and every phase of
  * the solve is bracketed by HIP events on the lattice stream;

@@ -46,7 +46,8 @@ EXPORTS = (
     "grg_precond_destroy", "grg_precond_set_weights", "grg_precond_get_weights", "grg_precond_apply",
     "grg_precond_loss_grad", "grg_precond_train", "grg_precond_save", "grg_precond_load",
     "grg_schur_attach_precond", "grg_batch_create", "grg_batch_destroy", "grg_batch_layout",
-    "grg_batch_apply", "grg_batch_tune", "grg_profile_enable",
+    "grg_batch_apply", "grg_batch_tune", "grg_batch_graph_info",
+    "grg_batch_tune_info", "grg_profile_enable",
     "grg_profile_read", "grg_profile_reset", "grg_vcycle_params_default", "grg_vcycle_create",
     "grg_vcycle_destroy", "grg_vcycle_apply", "grg_vcycle_solve",
 )
@@ -181,6 +182,8 @@ def load():
         "grg_batch_layout": (C.c_int, [vp, C.c_int, i64p, i32p]),
         "grg_batch_apply": (C.c_int, [vp, vp, vp, C.c_int, C.POINTER(grg_solver_stats)]),
         "grg_batch_tune": (C.c_int, [vp]),
+        "grg_batch_graph_info": (C.c_int, [vp, i32p]),
+        "grg_batch_tune_info": (C.c_int, [vp, C.c_int, i32p, C.POINTER(C.c_float)]),
         "grg_profile_enable": (C.c_int, [vp, C.c_int]),
         "grg_profile_read": (C.c_int, [vp, C.c_int, i64p, dp]),
         "grg_profile_reset": (C.c_int, [vp]),
@@ -514,6 +517,20 @@ def grg_batch_apply(b, x_b, y_b, use_graph=True, allow_noconv=False):
 
 def grg_batch_tune(b):
     _check(load().grg_batch_tune(b))
+
+
+def grg_batch_tune_info(b, precision):
+    """{'SB', 'RG', 'grid', 'stencil_ms', 'update_ms'} of the batched launch in use."""
+    info, ms = (C.c_int32 * 3)(), (C.c_float * 2)()
+    _check(load().grg_batch_tune_info(b, _prec(precision), info, ms))
+    return {"SB": info[0], "RG": info[1], "grid": info[2], "stencil_ms": ms[0], "update_ms": ms[1]}
+
+
+def grg_batch_graph_info(b):
+    """(outer steps, inner iterations per step) of the captured apply; (0, 0) if none."""
+    c = (C.c_int32 * 2)()
+    _check(load().grg_batch_graph_info(b, c))
+    return int(c[0]), int(c[1])
 
 
 def grg_profile_enable(s, on=True):

@@ -1,13 +1,20 @@
 // Many independent lattices solved together: S_bb applies for every lattice
-// of the batch in the same launches (kernels_batch.hip), the inner iterations
-// replayed from a HIP graph.
+// of the batch in the same launches (kernels_batch.hip).
 //
 // The method is the single-lattice one (solver.cpp) applied to every
 // (lattice, right-hand side) system at once: FP64 defect correction around an
-// inner minimal-residual solve in the inner precision, per-system step
-// lengths and per-system convergence flags that freeze converged systems
-// inside the captured iterations, so the host reads the norms only between
-// graph replays.
+// inner minimal-residual solve in the inner precision, with per-system step
+// lengths.  Convergence is decided on the device: per-system flags (inner:
+// residual above its threshold; outer: FP64 relative residual above tol) are
+// set by the reductions and the control kernel, every kernel of a step skips
+// the systems whose flag is clear, and a launch with no flag set returns at
+// once.  So the whole apply -- set-up, every outer step with its inner
+// iterations, the check of the final residual and the combine -- is one
+// sequence of launches with no host decision inside, captured once as a HIP
+// graph and replayed; its counts of outer steps and inner iterations per step
+// come from an eager apply of the same batch, and an apply the graph did not
+// finish is continued eagerly.  The eager mode launches the same kernels and
+// reads the flags back every check_every inner iterations.
 #include <math.h>
 #include <string.h>
 
@@ -51,12 +58,22 @@ struct grg_batch_s {
     void *in_b = nullptr, *in_x = nullptr, *in_r = nullptr, *in_q = nullptr;
     double *partials = nullptr;
     double2 *alpha = nullptr;
-    double *rn2 = nullptr, *thr2 = nullptr, *bn2 = nullptr, *fr2 = nullptr;
-    int *active = nullptr;
-    double *h_buf = nullptr;       // pinned, 4 * nsys
+    double *thr2 = nullptr, *fr2 = nullptr, *rn2i = nullptr;
+    // one block read back at once: FP64 |r|^2, |b|^2 per system, then the
+    // counters [inner iterations, outer steps] and the inner flags
+    char *dsc = nullptr;
+    double *rn2 = nullptr, *bn2 = nullptr;
+    int *ctr = nullptr, *active = nullptr;
+    size_t dsc_bytes = 0;
+    int *oact = nullptr;           // outer flags: FP64 residual above tol
+    double *h_buf = nullptr;       // pinned, mirrors dsc
+    double *xb_in = nullptr, *yb_out = nullptr;  // coarse staging of the captured apply
     int SB[3] = {64, 64, 64}, RG[3] = {1, 1, 1}, grid[3] = {0, 0, 0};
+    float tune_ms[3] = {-1, -1, -1};  // tuned stencil time per launch (every system), per precision
+    float upd_ms = -1;                // the inner precision's MR update (every system)
     hipGraphExec_t graph = nullptr;
-    int graph_iters = 0;
+    int g_outer = 0, g_inner = 0;  // counts the graph was captured with
+    int e_outer = 0, e_inner = 0;  // counts the last eager apply needed
 };
 
 namespace grg {
@@ -89,12 +106,16 @@ static BatchBlasArgs blas(grg_batch B)
     a.grid = round8(std::min<long>(B->Vtot / 256, kBatchMaxGrid));
     a.alpha = B->alpha;
     a.partials = B->partials;
+    a.act = nullptr;
+    a.ctr = nullptr;
     return a;
 }
 
-static grg_status dslash(grg_batch B, int prec, const void *in, void *out, int sel, bool dots)
+static grg_status dslash(grg_batch B, int prec, const void *in, void *out, int sel, bool dots,
+                         const int *act = nullptr)
 {
     BatchDslashArgs a;
+    a.act = act;
     a.in = in;
     a.out = out;
     a.U = B->U[prec];
@@ -109,38 +130,172 @@ static grg_status dslash(grg_batch B, int prec, const void *in, void *out, int s
     return GRG_OK;
 }
 
-static grg_status read_rn2(grg_batch B, double *host)
+// the read-back block (|r|^2, |b|^2, counters, inner flags) into h_buf
+static grg_status read_back(grg_batch B)
 {
-    GRG_TRY_HIP(hipMemcpyAsync(B->h_buf, B->rn2, sizeof(double) * B->nsys, hipMemcpyDeviceToHost, B->st));
+    GRG_TRY_HIP(hipMemcpyAsync(B->h_buf, B->dsc, B->dsc_bytes, hipMemcpyDeviceToHost, B->st));
     GRG_TRY_HIP(hipStreamSynchronize(B->st));
-    memcpy(host, B->h_buf, sizeof(double) * B->nsys);
+    return GRG_OK;
+}
+static const double *h_rn2(grg_batch B) { return B->h_buf; }
+static const double *h_bn2(grg_batch B) { return B->h_buf + B->nsys; }
+static const int *h_ctr(grg_batch B) { return (const int *)(B->h_buf + 2 * B->nsys); }
+static const int *h_active(grg_batch B) { return h_ctr(B) + 4; }
+
+static grg_status ctl(grg_batch B, bool init)
+{
+    BatchCtlArgs c;
+    c.nsys = B->nsys;
+    c.bn2 = B->bn2;
+    c.rn2 = B->rn2;
+    c.tol = B->prm.tol;
+    c.inner_tol = B->prm.inner_tol;
+    c.fp64_inner = B->prm.inner == GRG_FP64;
+    c.thr2 = B->thr2;
+    c.fr2 = B->fr2;
+    c.oact = B->oact;
+    c.ctr = B->ctr;
+    c.init = init ? 1 : 0;
+    GRG_TRY_HIP(launch_batch_ctl(c, B->st));
     return GRG_OK;
 }
 
-// one inner minimal-residual iteration for every system (graph body)
+// one inner minimal-residual iteration for the systems whose inner flag is
+// set (a no-op launch sequence once none is)
 static grg_status inner_step(grg_batch B, int prec)
 {
-    const BatchBlasArgs a = blas(B);
-    GRG_TRY(dslash(B, prec, B->in_r, B->in_q, 0, true));
-    GRG_TRY_HIP(launch_reduce(kAlpha, B->partials, dgrid(B, prec), B->nsys, B->alpha, nullptr, nullptr,
-                              B->active, B->st));
+    BatchBlasArgs a = blas(B);
+    a.act = B->active;
+    a.ctr = B->ctr;
+    GRG_TRY(dslash(B, prec, B->in_r, B->in_q, 0, true, B->active));
+    GRG_TRY_HIP(launch_batch_reduce(kAlpha, B->partials, dgrid(B, prec), B->nsys, B->alpha, nullptr, nullptr,
+                                    B->active, nullptr, B->st));
     GRG_TRY_HIP(launch_batch_mr_update(prec, a, B->in_x, B->in_r, B->in_q, B->st));
-    GRG_TRY_HIP(launch_reduce(kNorm, B->partials, a.grid, B->nsys, nullptr, B->rn2, B->thr2, B->active,
-                              B->st));
+    GRG_TRY_HIP(launch_batch_reduce(kNorm, B->partials, a.grid, B->nsys, nullptr, B->rn2i, B->thr2, B->active,
+                                    B->active, B->st));
     return GRG_OK;
 }
 
-static grg_status build_graph(grg_batch B, int prec, int iters)
+// One outer step of the defect correction for the systems whose outer flag
+// is set: the scaled residual into the inner precision, the inner solve
+// (eager: until no inner flag is set, read back every check_every
+// iterations, at most maxit; captured: exactly n_inner iterations, the
+// surplus ones no-ops), then r -= A e |r|, x += e |r| in FP64 and the control.
+static grg_status outer_step(grg_batch B, int prec, const void *r_src, const void *x_src, bool eager,
+                             int n_inner, int *taken)
 {
-    if (B->graph && B->graph_iters == iters) return GRG_OK;
+    BatchBlasArgs a = blas(B);
+    a.act = B->oact;
+    GRG_TRY_HIP(launch_batch_inner_init(prec, a, r_src, B->fr2, B->in_r, B->in_x, B->st));
+    GRG_TRY_HIP(launch_batch_reduce(kNorm, B->partials, a.grid, B->nsys, nullptr, B->rn2i, B->thr2, B->oact,
+                                    B->active, B->st));
+    int it = 0;
+    if (eager) {
+        const int chunk = std::max(1, B->prm.check_every);
+        GRG_TRY(read_back(B));
+        bool any = false;
+        for (int k = 0; k < B->nsys; ++k) any = any || h_active(B)[k];
+        const int c0 = h_ctr(B)[0];
+        while (any && it < n_inner) {
+            for (int k = 0; k < chunk && it < n_inner; ++k, ++it) GRG_TRY(inner_step(B, prec));
+            GRG_TRY(read_back(B));
+            any = false;
+            for (int k = 0; k < B->nsys; ++k) any = any || h_active(B)[k];
+        }
+        if (taken) *taken = h_ctr(B)[0] - c0;
+    } else {
+        for (int k = 0; k < n_inner; ++k) GRG_TRY(inner_step(B, prec));
+    }
+    BatchDcArgs d;
+    d.e = B->in_x;
+    d.U = B->U[GRG_FP64];
+    d.r_in = r_src;
+    d.x_in = x_src;
+    d.r_out = B->r64;
+    d.x_out = B->x64;
+    d.fr2 = B->fr2;
+    d.mask = B->mask;
+    d.bt = table(B);
+    d.Vtot = B->Vtot;
+    d.nrhs = B->nrhs;
+    d.partials = B->partials;
+    d.act = B->oact;
+    d.gate = r_src == B->r64 ? 1 : 0;  // the first step writes r64 and x64 for every system
+    d.ctr = B->ctr + 1;
+    const int dcg = round8(std::min<long>(B->Vtot / 128, kBatchMaxGrid));
+    GRG_TRY_HIP(launch_batch_dc_update(prec, d, dcg, B->st));
+    GRG_TRY_HIP(launch_batch_reduce(kNorm, B->partials, dcg, B->nsys, nullptr, B->rn2, nullptr, B->oact, nullptr,
+                                    B->st));
+    GRG_TRY(ctl(B, false));
+    return GRG_OK;
+}
+
+// b = D_rb x_b, |b|^2, control initialised (|r| = |b|, counters cleared)
+static grg_status prologue(grg_batch B, const double *xb)
+{
+    const BatchBlasArgs a = blas(B);
+    GRG_TRY_HIP(launch_batch_scatter(table(B), xb, B->u64, B->bidx, B->nb, B->coff, B->Vtot, B->nrhs, B->st));
+    GRG_TRY(dslash(B, GRG_FP64, B->u64, B->b64, 0, false));
+    GRG_TRY_HIP(launch_batch_norm2(GRG_FP64, a, B->b64, B->st));
+    GRG_TRY_HIP(launch_batch_reduce(kNorm, B->partials, a.grid, B->nsys, nullptr, B->bn2, nullptr, nullptr, nullptr,
+                                    B->st));
+    GRG_TRY(ctl(B, true));
+    return GRG_OK;
+}
+
+// r = b - D_rr x from the iterate (every system), control on it
+static grg_status verify(grg_batch B)
+{
+    const BatchBlasArgs a = blas(B);
+    GRG_TRY(dslash(B, GRG_FP64, B->x64, B->t64, 0, false));
+    GRG_TRY_HIP(launch_batch_sub_norm(a, B->b64, B->t64, B->r64, B->st));
+    GRG_TRY_HIP(launch_batch_reduce(kNorm, B->partials, a.grid, B->nsys, nullptr, B->rn2, nullptr, nullptr, nullptr,
+                                    B->st));
+    GRG_TRY(ctl(B, false));
+    return GRG_OK;
+}
+
+// y_b = [D (u - z)]_b; leaves u - z in x64 (undone by applying it again:
+// u and z have disjoint supports)
+static grg_status epilogue(grg_batch B, double *yb)
+{
+    const BatchBlasArgs a = blas(B);
+    GRG_TRY_HIP(launch_batch_xmy(a, B->u64, B->x64, B->st));
+    GRG_TRY_HIP(launch_batch_coarse(table(B), B->x64, B->U[GRG_FP64], yb, B->qg, B->clat, B->nb, B->nboff,
+                                    B->coff, B->nbtot, B->nrhs, B->st));
+    return GRG_OK;
+}
+
+// convergence of every system from the read-back block
+static int host_state(grg_batch B, double *worst)
+{
+    *worst = 0;
+    int conv = 1;
+    for (int k = 0; k < B->nsys; ++k) {
+        const double b2 = h_bn2(B)[k], r2 = h_rn2(B)[k];
+        if (!isfinite(r2) || !isfinite(b2)) return -1;
+        const double rel = b2 > 0 ? sqrt(r2 / b2) : 0.0;
+        *worst = std::max(*worst, rel);
+        if (rel > B->prm.tol) conv = 0;
+    }
+    return conv;
+}
+
+// The whole apply, with the outer and inner counts fixed, as one captured
+// graph reading x_b from xb_in and writing y_b to yb_out.
+static grg_status build_graph(grg_batch B, int prec, int n_outer, int n_inner)
+{
     if (B->graph) {
         (void)hipGraphExecDestroy(B->graph);
         B->graph = nullptr;
     }
     hipGraph_t g = nullptr;
     GRG_TRY_HIP(hipStreamBeginCapture(B->st, hipStreamCaptureModeThreadLocal));
-    grg_status s = GRG_OK;
-    for (int k = 0; k < iters && s == GRG_OK; ++k) s = inner_step(B, prec);
+    grg_status s = prologue(B, B->xb_in);
+    for (int o = 0; o < n_outer && s == GRG_OK; ++o)
+        s = outer_step(B, prec, o == 0 ? B->b64 : B->r64, o == 0 ? nullptr : B->x64, false, n_inner, nullptr);
+    if (s == GRG_OK) s = verify(B);
+    if (s == GRG_OK) s = epilogue(B, B->yb_out);
     hipError_t e = hipStreamEndCapture(B->st, &g);
     if (s != GRG_OK) {
         if (g) (void)hipGraphDestroy(g);
@@ -150,49 +305,8 @@ static grg_status build_graph(grg_batch B, int prec, int iters)
     e = hipGraphInstantiate(&B->graph, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     GRG_TRY_HIP(e);
-    B->graph_iters = iters;
-    return GRG_OK;
-}
-
-// inner solve of in_b -> in_x to |r|^2 <= thr (host copy) per system
-static grg_status inner_solve(grg_batch B, int prec, const double *thr, int maxit, bool use_graph,
-                              int *iters)
-{
-    const BatchBlasArgs a = blas(B);
-    const size_t bytes = spinor_elems(B->gtot, B->nrhs) * prec_bytes(prec);
-    BlasShape sh;
-    sh.g = B->gtot;
-    sh.nrhs = B->nrhs;
-    sh.grid = a.grid;
-    GRG_TRY_HIP(launch_fill_zero(B->in_x, bytes, B->st));
-    GRG_TRY_HIP(launch_copy(prec, sh, B->in_b, B->in_r, B->st));
-    GRG_TRY_HIP(launch_batch_norm2(prec, a, B->in_r, B->st));
-    GRG_TRY_HIP(launch_reduce(kNorm, B->partials, a.grid, B->nsys, nullptr, B->rn2, B->thr2, B->active,
-                              B->st));
-    std::vector<double> h(B->nsys);
-    GRG_TRY(read_rn2(B, h.data()));
-    auto done = [&]() {
-        for (int k = 0; k < B->nsys; ++k) {
-            if (!isfinite(h[k])) return -1;
-            if (h[k] > thr[k]) return 0;
-        }
-        return 1;
-    };
-    const int chunk = std::max(1, B->prm.check_every);
-    int it = 0, d = done();
-    if (use_graph) GRG_TRY(build_graph(B, prec, chunk));
-    while (d == 0 && it < maxit) {
-        if (use_graph) {
-            GRG_TRY_HIP(hipGraphLaunch(B->graph, B->st));
-        } else {
-            for (int k = 0; k < chunk; ++k) GRG_TRY(inner_step(B, prec));
-        }
-        it += chunk;
-        GRG_TRY(read_rn2(B, h.data()));
-        d = done();
-    }
-    *iters = it;
-    if (d < 0) return set_error("non-finite residual in the batched inner solve"), GRG_ENONFINITE;
+    B->g_outer = n_outer;
+    B->g_inner = n_inner;
     return GRG_OK;
 }
 
@@ -201,97 +315,86 @@ static grg_status batch_apply(grg_batch B, const double *xb, double *yb, bool us
 {
     const grg_solver_params &p = B->prm;
     const int prec = p.inner;
-    const int n = B->nsys;
-    const BatchBlasArgs a = blas(B);
     hipStream_t st = B->st;
-    GRG_TRY_HIP(launch_batch_scatter(table(B), xb, B->u64, B->bidx, B->nb, B->coff, B->Vtot, B->nrhs, st));
-    GRG_TRY(dslash(B, GRG_FP64, B->u64, B->b64, 0, false));  // b = D_rb x
-    GRG_TRY_HIP(launch_batch_norm2(GRG_FP64, a, B->b64, st));
-    GRG_TRY_HIP(launch_reduce(kNorm, B->partials, a.grid, n, nullptr, B->bn2, nullptr, nullptr, st));
-    std::vector<double> bn2(n), rn2(n), thr(n);
-    GRG_TRY_HIP(hipMemcpyAsync(B->h_buf, B->bn2, sizeof(double) * n, hipMemcpyDeviceToHost, st));
-    GRG_TRY_HIP(hipStreamSynchronize(st));
-    memcpy(bn2.data(), B->h_buf, sizeof(double) * n);
-    rn2 = bn2;
-    const void *r_src = B->b64, *x_src = nullptr;
-    int total = 0, outer = 0;
-    bool verified = false;
-    double worst = 0;
-    grg_status status = GRG_OK;
-    const int dcg = round8(std::min<long>(B->Vtot / 128, kBatchMaxGrid));
-    for (;;) {
-        bool conv = true;
-        worst = 0;
-        for (int k = 0; k < n; ++k) {
-            if (!isfinite(rn2[k])) return set_error("non-finite FP64 residual"), GRG_ENONFINITE;
-            const double rel = bn2[k] > 0 ? sqrt(rn2[k] / bn2[k]) : 0.0;
-            worst = std::max(worst, rel);
-            if (rel > p.tol) conv = false;
-        }
-        if (conv && (verified || x_src == nullptr)) break;
-        if (conv) {
-            GRG_TRY(dslash(B, GRG_FP64, B->x64, B->t64, 0, false));
-            GRG_TRY_HIP(launch_batch_sub_norm(a, B->b64, B->t64, B->r64, st));
-            GRG_TRY_HIP(launch_reduce(kNorm, B->partials, a.grid, n, nullptr, B->rn2, nullptr, nullptr, st));
-            GRG_TRY(read_rn2(B, rn2.data()));
-            r_src = B->r64;
-            verified = true;
-            continue;
-        }
-        verified = false;
-        if (outer >= p.max_outer || total >= p.max_iter) {
-            status = GRG_ENOCONV;
-            set_error("batched D_rr solve: no convergence after %d outer / %d inner iterations "
-                      "(residual %.3e > %.3e)", outer, total, worst, p.tol);
-            break;
-        }
-        for (int k = 0; k < n; ++k) {
-            const double need = bn2[k] > 0 && rn2[k] > 0 ? p.tol * sqrt(bn2[k] / rn2[k]) : 1.0;
-            const double rel = prec == GRG_FP64 ? need : std::max(p.inner_tol, 0.5 * need);
-            const bool on = bn2[k] > 0 && sqrt(rn2[k] / bn2[k]) > p.tol;
-            thr[k] = on ? rel * rel : 2.0;
-        }
-        memcpy(B->h_buf + n, thr.data(), sizeof(double) * n);
-        GRG_TRY_HIP(hipMemcpyAsync(B->thr2, B->h_buf + n, sizeof(double) * n, hipMemcpyHostToDevice, st));
-        memcpy(B->h_buf + 2 * n, rn2.data(), sizeof(double) * n);
-        GRG_TRY_HIP(hipMemcpyAsync(B->fr2, B->h_buf + 2 * n, sizeof(double) * n, hipMemcpyHostToDevice, st));
-        GRG_TRY_HIP(launch_batch_axpy_convert(GRG_FP64, prec, a, r_src, B->in_b, B->fr2, 1, 0, st));
-        int it = 0;
-        GRG_TRY(inner_solve(B, prec, thr.data(), p.max_iter - total, use_graph, &it));
-        total += it;
-        ++outer;
-        BatchDcArgs d;
-        d.e = B->in_x;
-        d.U = B->U[GRG_FP64];
-        d.r_in = r_src;
-        d.x_in = x_src;
-        d.r_out = B->r64;
-        d.x_out = B->x64;
-        d.fr2 = B->fr2;
-        d.mask = B->mask;
-        d.bt = table(B);
-        d.Vtot = B->Vtot;
-        d.nrhs = B->nrhs;
-        d.partials = B->partials;
-        GRG_TRY_HIP(launch_batch_dc_update(prec, d, dcg, st));
-        GRG_TRY_HIP(launch_reduce(kNorm, B->partials, dcg, n, nullptr, B->rn2, nullptr, nullptr, st));
-        GRG_TRY(read_rn2(B, rn2.data()));
-        r_src = B->r64;
-        x_src = B->x64;
+    const size_t cb = sizeof(double2) * 12 * (size_t)B->nrhs * B->nbtot;
+    bool done_by_graph = false;
+    if (use_graph && B->e_outer == 0 && !B->graph) {
+        // counts unknown: this apply runs eagerly and records them
+        use_graph = false;
     }
-    if (x_src == nullptr)
-        GRG_TRY_HIP(launch_fill_zero(B->x64, spinor_elems(B->gtot, B->nrhs) * 16, st));
-    // S x = [D (u - z)]_b
-    BlasShape sh;
-    sh.g = B->gtot;
-    sh.nrhs = B->nrhs;
-    sh.grid = a.grid;
-    GRG_TRY_HIP(launch_xmy(sh, B->u64, B->x64, st));
-    GRG_TRY_HIP(launch_batch_coarse(table(B), B->x64, B->U[GRG_FP64], yb, B->qg, B->clat, B->nb,
-                                    B->nboff, B->coff, B->nbtot, B->nrhs, st));
+    const void *r_src = B->b64, *x_src = nullptr;
+    int conv = 0;
+    double worst = 0;
+    if (use_graph) {
+        if (!B->graph) GRG_TRY(build_graph(B, prec, B->e_outer, B->e_inner + 1));
+        GRG_TRY_HIP(hipMemcpyAsync(B->xb_in, xb, cb, hipMemcpyDeviceToDevice, st));
+        GRG_TRY_HIP(hipGraphLaunch(B->graph, st));
+        GRG_TRY_HIP(hipMemcpyAsync(yb, B->yb_out, cb, hipMemcpyDeviceToDevice, st));
+        GRG_TRY(read_back(B));
+        conv = host_state(B, &worst);
+        if (conv < 0) return set_error("non-finite FP64 residual"), GRG_ENONFINITE;
+        done_by_graph = conv == 1;
+        if (!done_by_graph) {
+            // continue eagerly from the verified residual; the next graph
+            // is captured with one more outer step
+            GRG_TRY(epilogue(B, yb));  // restores the iterate in x64 (the combine's output is redone)
+            (void)hipGraphExecDestroy(B->graph);
+            B->graph = nullptr;
+            r_src = B->r64;
+            x_src = B->x64;
+        }
+    } else {
+        GRG_TRY(prologue(B, xb));
+        GRG_TRY(read_back(B));
+        conv = host_state(B, &worst);
+        if (conv < 0) return set_error("non-finite FP64 residual"), GRG_ENONFINITE;
+    }
+    grg_status status = GRG_OK;
+    if (!done_by_graph) {
+        bool verified = use_graph;  // the graph's last residual was recomputed from x
+        int max_inner = 0;
+        for (;;) {
+            if (conv && (verified || x_src == nullptr)) break;
+            if (conv) {
+                GRG_TRY(verify(B));
+                GRG_TRY(read_back(B));
+                conv = host_state(B, &worst);
+                if (conv < 0) return set_error("non-finite FP64 residual"), GRG_ENONFINITE;
+                r_src = B->r64;
+                verified = true;
+                continue;
+            }
+            verified = false;
+            const int outer = h_ctr(B)[1], total = h_ctr(B)[0];
+            if (outer >= p.max_outer || total >= p.max_iter) {
+                status = GRG_ENOCONV;
+                set_error("batched D_rr solve: no convergence after %d outer / %d inner iterations "
+                          "(residual %.3e > %.3e)", outer, total, worst, p.tol);
+                break;
+            }
+            int taken = 0;
+            GRG_TRY(outer_step(B, prec, r_src, x_src, true, p.max_iter - total, &taken));
+            max_inner = std::max(max_inner, taken);
+            GRG_TRY(read_back(B));
+            conv = host_state(B, &worst);
+            if (conv < 0) return set_error("non-finite FP64 residual"), GRG_ENONFINITE;
+            r_src = B->r64;
+            x_src = B->x64;
+        }
+        if (x_src == nullptr)
+            GRG_TRY_HIP(launch_fill_zero(B->x64, spinor_elems(B->gtot, B->nrhs) * 16, st));
+        GRG_TRY(epilogue(B, yb));
+        if (status == GRG_OK) {
+            // the counts the next captured apply of this batch is built with:
+            // every outer step this apply took (the graph's and the eager
+            // ones after it), and the most inner iterations one of them took
+            B->e_outer = std::max(1, h_ctr(B)[1]);
+            B->e_inner = std::max({B->e_inner, max_inner, use_graph ? B->g_inner : 0});
+        }
+    }
     if (stats) {
-        stats->iters = total;
-        stats->outer = outer;
+        stats->iters = h_ctr(B)[0];
+        stats->outer = h_ctr(B)[1];
         stats->converged = status == GRG_OK;
         stats->true_rel_resid = worst;
     }
@@ -326,11 +429,13 @@ static void batch_free(grg_batch B)
     f(B->in_q);
     f(B->partials);
     f(B->alpha);
-    f(B->rn2);
+    f(B->dsc);  // rn2, bn2, the counters and the inner flags
     f(B->thr2);
-    f(B->bn2);
     f(B->fr2);
-    f(B->active);
+    f(B->rn2i);
+    f(B->oact);
+    f(B->xb_in);
+    f(B->yb_out);
     if (B->h_buf) (void)hipHostFree(B->h_buf);
     if (B->graph) (void)hipGraphExecDestroy(B->graph);
     if (B->ev_in) (void)hipEventDestroy(B->ev_in);
@@ -459,10 +564,20 @@ grg_status grg_batch_create(const grg_batch_member *m, int count, int nrhs,
     for (void **p : {&B->in_b, &B->in_x, &B->in_r, &B->in_q}) al(p, fin);
     al((void **)&B->partials, sizeof(double) * kBatchMaxGrid * B->nsys * 3);
     al((void **)&B->alpha, sizeof(double2) * B->nsys);
-    for (double **p : {&B->rn2, &B->thr2, &B->fr2}) al((void **)p, sizeof(double) * B->nsys);
-    al((void **)&B->bn2, sizeof(double) * B->nsys);
-    al((void **)&B->active, sizeof(int) * B->nsys);
-    if (ok && hipHostMalloc((void **)&B->h_buf, sizeof(double) * 4 * B->nsys) != hipSuccess) {
+    for (double **p : {&B->thr2, &B->fr2, &B->rn2i}) al((void **)p, sizeof(double) * B->nsys);
+    al((void **)&B->oact, sizeof(int) * B->nsys);
+    B->dsc_bytes = sizeof(double) * 2 * B->nsys + sizeof(int) * (4 + B->nsys);
+    al((void **)&B->dsc, B->dsc_bytes);
+    if (ok) {
+        B->rn2 = (double *)B->dsc;
+        B->bn2 = B->rn2 + B->nsys;
+        B->ctr = (int *)(B->bn2 + B->nsys);
+        B->active = B->ctr + 4;
+    }
+    const size_t cbytes = sizeof(double2) * 12 * (size_t)nrhs * nbtot;
+    al((void **)&B->xb_in, cbytes);
+    al((void **)&B->yb_out, cbytes);
+    if (ok && hipHostMalloc((void **)&B->h_buf, B->dsc_bytes) != hipSuccess) {
         B->h_buf = nullptr;
         ok = false;
     }
@@ -492,6 +607,8 @@ grg_status grg_batch_create(const grg_batch_member *m, int count, int nrhs,
 #undef UP
     for (void *p : {B->b64, B->x64, B->r64, B->t64, B->u64}) GRG_TRY_HIP(launch_fill_zero(p, f64, st));
     for (void *p : {B->in_b, B->in_x, B->in_r, B->in_q}) GRG_TRY_HIP(launch_fill_zero(p, fin, st));
+    GRG_TRY_HIP(launch_fill_zero(B->dsc, B->dsc_bytes, st));
+    GRG_TRY_HIP(launch_fill_zero(B->oact, sizeof(int) * B->nsys, st));
     // links, one member at a time through a staging buffer
     size_t maxlink = 0;
     for (const BatchMember &b : mem) maxlink = std::max(maxlink, (size_t)b.V * 4 * 9 * 16);
@@ -566,6 +683,26 @@ grg_status grg_batch_apply(grg_batch B, const double *x_b, double *y_b, int use_
     return s;
 }
 
+grg_status grg_batch_tune_info(grg_batch B, int precision, int32_t info[3], float ms[2])
+{
+    if (!B || !info || !ms) return set_error("null argument"), GRG_EINVAL;
+    if (precision < GRG_FP64 || precision > GRG_BF16) return set_error("bad precision"), GRG_EINVAL;
+    info[0] = B->SB[precision];
+    info[1] = B->RG[precision];
+    info[2] = dgrid(B, precision);
+    ms[0] = B->tune_ms[precision];
+    ms[1] = precision == B->prm.inner ? B->upd_ms : -1.0f;
+    return GRG_OK;
+}
+
+grg_status grg_batch_graph_info(grg_batch B, int32_t counts[2])
+{
+    if (!B || !counts) return set_error("null argument"), GRG_EINVAL;
+    counts[0] = B->graph ? B->g_outer : 0;
+    counts[1] = B->graph ? B->g_inner : 0;
+    return GRG_OK;
+}
+
 grg_status grg_batch_tune(grg_batch B)
 {
     if (!B) return set_error("null argument"), GRG_EINVAL;
@@ -594,6 +731,7 @@ grg_status grg_batch_tune(grg_batch B)
                     GRG_TRY_HIP(hipEventSynchronize(e1));
                     float ms = 0;
                     (void)hipEventElapsedTime(&ms, e0, e1);
+                    ms /= 3;
                     if (ms < best) {
                         best = ms;
                         bsb = sb;
@@ -606,6 +744,22 @@ grg_status grg_batch_tune(grg_batch B)
         B->SB[prec] = bsb;
         B->RG[prec] = brg;
         B->grid[prec] = bgrid;
+        B->tune_ms[prec] = best;
+    }
+    {
+        // the inner precision's MR update over every system (x += alpha r,
+        // r -= alpha q with the step lengths in place; overwrites workspaces)
+        const int prec = B->prm.inner;
+        const BatchBlasArgs a = blas(B);
+        for (int k = 0; k < 4; ++k) {
+            if (k == 1) GRG_TRY_HIP(hipEventRecord(e0, B->st));
+            GRG_TRY_HIP(launch_batch_mr_update(prec, a, B->in_x, B->in_r, B->in_q, B->st));
+        }
+        GRG_TRY_HIP(hipEventRecord(e1, B->st));
+        GRG_TRY_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        B->upd_ms = ms / 3;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -67,6 +67,21 @@ struct SysPartial {
     }
 };
 
+// Whether any of the n flags is set: the same answer in every thread of the
+// workgroup (a gate read at the start of a launch, before any barrier of the
+// kernel, so a launch with nothing to do returns as a whole).
+__device__ bool any_set(const int *flags, int n)
+{
+    __shared__ int s_any;
+    if (threadIdx.x == 0) s_any = 0;
+    __syncthreads();
+    int mine = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) mine |= flags[i];
+    if (mine) s_any = 1;
+    __syncthreads();
+    return s_any != 0;
+}
+
 // out = mask_sel D in over all lattices; fused dots per system when partials.
 template <int P>
 __global__ void __launch_bounds__(256) dslash_batch_kernel(BatchDslashArgs a)
@@ -78,6 +93,7 @@ __global__ void __launch_bounds__(256) dslash_batch_kernel(BatchDslashArgs a)
     S *__restrict__ out = (S *)a.out;
     const S *__restrict__ U = (const S *)a.U;
     const int nsys = a.bt.nlat * a.nrhs;
+    if (a.act && !any_set(a.act, nsys)) return;
     const bool dots = a.partials != nullptr;
     SysPartial<3> part;
     if (dots) part.init(smem, nsys);
@@ -93,6 +109,8 @@ __global__ void __launch_bounds__(256) dslash_batch_kernel(BatchDslashArgs a)
         const R diag = (R)a.bt.diag[b.l];
         const int r0 = grp * a.RG, r1 = min(r0 + a.RG, a.nrhs);
         for (int r = r0; r < r1; ++r) {
+            // (a workgroup lies inside one lattice: the skip is uniform)
+            if (a.act && !a.act[b.l * a.nrhs + r]) continue;
             cpx<R> acc[12];
             if (on) {
                 dslash_site<S, R, true>(acc, in, U, s, q, b.g, r, a.nrhs, diag);
@@ -129,6 +147,8 @@ __global__ void __launch_bounds__(256) batch_mr_update_kernel(BatchBlasArgs a, v
     typedef typename Store<P>::S S;
     typedef typename Store<P>::R R;
     extern __shared__ double smem[];
+    if (a.act && !any_set(a.act, a.bt.nlat * a.nrhs)) return;
+    if (a.ctr && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.ctr, 1);
     SysPartial<1> part;
     part.init(smem, a.bt.nlat * a.nrhs);
     S *x = (S *)x_, *r = (S *)r_;
@@ -139,6 +159,7 @@ __global__ void __launch_bounds__(256) batch_mr_update_kernel(BatchBlasArgs a, v
         const int l = a.bt.tile_lat[s >> 6];
         for (int k = 0; k < a.nrhs; ++k) {
             const int sys = l * a.nrhs + k;
+            if (a.act && !a.act[sys]) continue;  // converged: x and r stay
             const double2 a2 = a.alpha[sys];
             const cpx<R> al = {(R)a2.x, (R)a2.y}, na = {(R)-a2.x, (R)-a2.y};
             R rr = 0;
@@ -265,6 +286,13 @@ __global__ void __launch_bounds__(128) batch_dc_update_kernel(BatchDcArgs a)
     const double2 *x_in = (const double2 *)a.x_in;
     double2 *r_out = (double2 *)a.r_out;
     double2 *x_out = (double2 *)a.x_out;
+    const int nsys = a.bt.nlat * a.nrhs;
+    const bool in_place = a.r_in == a.r_out && a.x_in == a.x_out;
+    if (a.act) {
+        const bool any = any_set(a.act, nsys);
+        if (any && a.ctr && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.ctr, 1);
+        if (a.gate && !any) return;
+    }
     const ItemRange it = xcd_items(a.Vtot / blockDim.x);
     for (int w = it.begin; w < it.end; w += it.step) {
         const int s = w * blockDim.x + threadIdx.x;
@@ -273,8 +301,20 @@ __global__ void __launch_bounds__(128) batch_dc_update_kernel(BatchDcArgs a)
         const SiteGeo q = site_geo(b.local, b.g);
         for (int r = 0; r < a.nrhs; ++r) {
             const int sys = b.l * a.nrhs + r;
+            const bool sys_on = a.act == nullptr || a.act[sys] != 0;
+            if (in_place && !sys_on) continue;  // converged: r and x stay
             double nrm = 0;
-            if (on) {
+            if (on && !sys_on) {
+                // converged before this step: r and x copied, e not read
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    const size_t i = fidx(s, r, c, a.nrhs);
+                    const double2 rv = r_in[i];
+                    r_out[i] = rv;
+                    nrm += rv.x * rv.x + rv.y * rv.y;
+                    x_out[i] = x_in ? x_in[i] : make_double2(0.0, 0.0);
+                }
+            } else if (on) {
                 cpx<double> acc[12];
                 dslash_site<S, double, true, double2>(acc, e, U, s, q, b.g, r, a.nrhs, a.bt.diag[b.l]);
                 const double f = sqrt(a.fr2[sys]);
@@ -341,6 +381,123 @@ __global__ void __launch_bounds__(128) batch_coarse_kernel(BatchTable bt, const 
         double2 *o = yb + coff[l] + ((size_t)r * nb[l] + k) * 12;
 #pragma unroll
         for (int c = 0; c < 12; ++c) o[c] = make_double2(acc[c].re, acc[c].im);
+    }
+}
+
+// in_r = r_src / sqrt(fr2) in the inner precision, in_x = 0, partial |in_r|^2
+// (of the stored values); systems whose flag is 0 get zeros
+template <int PO>
+__global__ void __launch_bounds__(256) batch_inner_init_kernel(BatchBlasArgs a, const double2 *r_src,
+                                                               const double *fr2, void *in_r_, void *in_x_)
+{
+    typedef typename Store<PO>::S S;
+    typedef typename Store<PO>::R R;
+    extern __shared__ double smem[];
+    const int nsys = a.bt.nlat * a.nrhs;
+    if (a.act && !any_set(a.act, nsys)) return;
+    SysPartial<1> part;
+    part.init(smem, nsys);
+    S *in_r = (S *)in_r_, *in_x = (S *)in_x_;
+    const ItemRange it = xcd_items(a.Vtot / 256);
+    for (int w = it.begin; w < it.end; w += it.step) {
+        const int s = w * 256 + threadIdx.x;
+        const int l = a.bt.tile_lat[s >> 6];
+        for (int k = 0; k < a.nrhs; ++k) {
+            const int sys = l * a.nrhs + k;
+            const bool on = a.act == nullptr || a.act[sys] != 0;
+            const double f2 = fr2[sys];
+            const double f = on && f2 > 0 ? 1.0 / sqrt(f2) : 0.0;
+            double t = 0;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const size_t i = fidx(s, k, c, a.nrhs);
+                const double2 v = on ? r_src[i] : make_double2(0.0, 0.0);
+                stc(in_r, i, cpx<R>{(R)(f * v.x), (R)(f * v.y)});
+                stc(in_x, i, cpx<R>{(R)0, (R)0});
+                const cpx<R> st = ldc(in_r, i);
+                t += (double)st.re * st.re + (double)st.im * st.im;
+            }
+            const double vv[1] = {t};
+            part.add(sys, vv);
+        }
+    }
+    part.flush(a.partials);
+}
+
+// one workgroup per system: the fixed-order sum of its partials (as the
+// single-lattice reduction), gated by act_in
+__global__ void __launch_bounds__(256) batch_reduce_kernel(int mode, const double *partials, int nparts,
+                                                           int nsys, double2 *alpha, double *out2,
+                                                           const double *thr2, const int *act_in,
+                                                           int *act_out)
+{
+    __shared__ double sm[3][256];
+    if (act_in && !any_set(act_in, nsys)) return;
+    const int r = blockIdx.x;
+    if (act_in && !act_in[r]) {
+        if (threadIdx.x == 0) {
+            if (mode == kAlpha) alpha[r] = make_double2(0.0, 0.0);
+            if (act_out && act_out != act_in) act_out[r] = 0;
+        }
+        return;
+    }
+    const int K = mode == kNorm ? 1 : 3;
+    double acc[3] = {0, 0, 0};
+    for (int i = threadIdx.x; i < nparts; i += 256)
+        for (int k = 0; k < K; ++k) acc[k] += partials[((size_t)i * nsys + r) * K + k];
+    for (int k = 0; k < K; ++k) sm[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int k = 0; k < K; ++k) sm[k][threadIdx.x] += sm[k][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    if (mode == kAlpha) {
+        const double qq = sm[2][0];
+        alpha[r] = qq > 0 ? make_double2(sm[0][0] / qq, sm[1][0] / qq) : make_double2(0.0, 0.0);
+    } else {
+        const double n2 = sm[mode == kNorm3 ? 2 : 0][0];
+        if (out2) out2[r] = n2;
+        if (act_out) act_out[r] = n2 > thr2[r] ? 1 : 0;
+    }
+}
+
+// the outer control of the defect correction, one thread per system: the
+// relative FP64 residual against tol, the next inner threshold (the inner
+// solve reduces the scaled residual by max(inner_tol, need / 2), or by need
+// itself in FP64, need = tol |b| / |r|) and the scale |r|^2
+__global__ void __launch_bounds__(256) batch_ctl_kernel(BatchCtlArgs c)
+{
+    if (c.init && blockIdx.x == 0 && threadIdx.x < 2) c.ctr[threadIdx.x] = 0;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < c.nsys; k += gridDim.x * blockDim.x) {
+        const double b2 = c.bn2[k];
+        if (c.init) c.rn2[k] = b2;
+        const double r2 = c.rn2[k];
+        const double rel = b2 > 0 ? sqrt(r2 / b2) : 0.0;
+        const bool on = b2 > 0 && rel > c.tol;  // a NaN residual is left to the host's check
+        const double need = b2 > 0 && r2 > 0 ? c.tol * sqrt(b2 / r2) : 1.0;
+        const double relt = c.fp64_inner ? need : fmax(c.inner_tol, 0.5 * need);
+        c.thr2[k] = on ? relt * relt : 2.0;
+        c.fr2[k] = r2;
+        c.oact[k] = on ? 1 : 0;
+    }
+}
+
+// y = x - y, FP64
+__global__ void __launch_bounds__(256) batch_xmy_kernel(BatchBlasArgs a, const double2 *x, double2 *y)
+{
+    const ItemRange it = xcd_items(a.Vtot / 256);
+    for (int w = it.begin; w < it.end; w += it.step) {
+        const int s = w * 256 + threadIdx.x;
+        for (int k = 0; k < a.nrhs; ++k) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const size_t i = fidx(s, k, c, a.nrhs);
+                const double2 u = x[i], v = y[i];
+                y[i] = make_double2(u.x - v.x, u.y - v.y);
+            }
+        }
     }
 }
 
@@ -423,6 +580,37 @@ hipError_t launch_batch_scatter(const BatchTable &bt, const double *xb, void *ds
 {
     hipLaunchKernelGGL(batch_scatter_kernel, dim3((Vtot + 255) / 256, nrhs), dim3(256), 0, st, bt,
                        (const double2 *)xb, (double2 *)dst, bidx, nb, coff, Vtot, nrhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_inner_init(int prec, const BatchBlasArgs &a, const void *r_src, const double *fr2,
+                                   void *in_r, void *in_x, hipStream_t st)
+{
+    BDISP(prec, batch_inner_init_kernel, lds_sys(a.bt.nlat * a.nrhs, 1), a, (const double2 *)r_src, fr2, in_r,
+          in_x);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_reduce(int mode, const double *partials, int nparts, int nsys, double2 *alpha,
+                               double *out2, const double *thr2, const int *act_in, int *act_out,
+                               hipStream_t st)
+{
+    if (nsys < 1 || nparts < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(nsys), dim3(256), 0, st, mode, partials, nparts, nsys, alpha,
+                       out2, thr2, act_in, act_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_ctl(const BatchCtlArgs &c, hipStream_t st)
+{
+    if (c.nsys < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(batch_ctl_kernel, dim3((c.nsys + 255) / 256), dim3(256), 0, st, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_xmy(const BatchBlasArgs &a, const void *x, void *y, hipStream_t st)
+{
+    hipLaunchKernelGGL(batch_xmy_kernel, dim3(a.grid), dim3(256), 0, st, a, (const double2 *)x, (double2 *)y);
     return hipGetLastError();
 }
 

@@ -91,18 +91,76 @@ def test_graph_replays_match_eager():
     ms = members(descs, [(1, False), (1, True)])
     p = grg.grg_solver_params_default(tol=1e-10, inner="bf16", inner_tol=1e-2, check_every=4)
     b = grg.grg_batch_create(ms, 4, p)
+    assert grg.grg_batch_graph_info(b) == (0, 0)
     x = to_dev(batch_inputs(b, ms, 4, 60))
     y = torch.empty_like(x)
-    grg.grg_batch_apply(b, x, y, use_graph=False)
+    st0 = grg.grg_batch_apply(b, x, y, use_graph=False)
     eager = to_host(y)
     for _ in range(3):
         y.zero_()
         torch.cuda.synchronize()
         st = grg.grg_batch_apply(b, x, y, use_graph=True)
-        assert st["converged"]
+        # the captured apply: as many outer steps as the eager one took, and
+        # at least its inner iterations per step
+        outer, inner = grg.grg_batch_graph_info(b)
+        assert outer == st0["outer"] and inner >= 1, (outer, inner, st0)
+        assert st["converged"] and st["iters"] == st0["iters"] and st["outer"] == st0["outer"]
+        # same systems take the same iterations on the device: same bits
         assert np.array_equal(to_host(y), eager)
         grg.grg_batch_apply(b, x, y, use_graph=False)  # eager work between replays
         assert np.array_equal(to_host(y), eager)
+    grg.grg_batch_destroy(b)
+
+
+def test_device_control_edge_cases():
+    """Zero inputs (a system with b = 0 never takes a step; an all-zero
+    batch takes none and gives zero), and an input that needs more
+    iterations than the captured graph holds: the apply continues eagerly
+    from the graph's verified residual and the batch is re-captured."""
+    import torch
+    import paper_0704_2341_amd as grg
+
+    ensure_built()
+    descs = [dict(dims=(8, 8, 8, 8), m0=-0.3, seed=4021), dict(dims=(4, 4, 4, 4), m0=0.1, seed=4022),
+             dict(dims=(8, 8, 4, 8), m0=0.1, seed=4023)]
+    ms = members(descs, [(1, False), (2, True), (1, True)])
+    nrhs = 2
+    p = grg.grg_solver_params_default(tol=1e-10, inner="fp32", inner_tol=1e-5, check_every=2)
+    b = grg.grg_batch_create(ms, nrhs, p)
+    x = batch_inputs(b, ms, nrhs, 80)
+    # all zero: no step, zero output, in both modes
+    z = to_dev(np.zeros_like(x))
+    y = torch.full_like(z, 1.0)
+    st = grg.grg_batch_apply(b, z, y, use_graph=False)
+    assert st["converged"] and st["outer"] == 0 and st["iters"] == 0 and not torch.any(y)
+    # the slow member (m0 = -0.3) at zero: the recorded counts are the fast members'
+    off0, nb0 = grg.grg_batch_layout(b, 0)
+    xe = x.copy()
+    xe[off0:off0 + 12 * nb0 * nrhs] = 0
+    ye = torch.empty_like(z)
+    st_e = grg.grg_batch_apply(b, to_dev(xe), ye, use_graph=False)
+    assert st_e["converged"]
+    assert not torch.any(ye[off0:off0 + 12 * nb0 * nrhs])
+    y.fill_(1.0)
+    st = grg.grg_batch_apply(b, z, y, use_graph=True)  # a captured apply of zeros
+    assert st["converged"] and grg.grg_batch_graph_info(b) != (0, 0) and not torch.any(y)
+    captured = grg.grg_batch_graph_info(b)
+    # the full input through the short graph, continued eagerly
+    yg = torch.empty_like(z)
+    st_g = grg.grg_batch_apply(b, to_dev(x), yg, use_graph=True)
+    assert st_g["converged"] and st_g["true_rel_resid"] <= 1e-10, st_g
+    yf = torch.empty_like(z)
+    st_f = grg.grg_batch_apply(b, to_dev(x), yf, use_graph=False)
+    assert st_f["converged"]
+    assert rel_err(to_host(yg), to_host(yf)) < 1e-9
+    want, _, _ = matfree.schur_apply(ms[0]["links"], ms[0]["dims"], ms[0]["m0"], ms[0]["q"], ms[0]["n_coarse"],
+                                     split(b, ms, x, nrhs)[0], tol=1e-13)
+    assert rel_err(split(b, ms, to_host(yg), nrhs)[0], want) < 1e-9
+    # the next captured apply holds more outer steps and runs to the end alone
+    st_g2 = grg.grg_batch_apply(b, to_dev(x), yg, use_graph=True)
+    assert st_g2["converged"]
+    now = grg.grg_batch_graph_info(b)
+    assert now[0] > captured[0] or now[1] > captured[1], (captured, now)
     grg.grg_batch_destroy(b)
 
 
@@ -121,8 +179,13 @@ def test_48_lattice_workload():
     x = batch_inputs(b, ms, nrhs, 70)
     xd = to_dev(x)
     y = torch.empty_like(xd)
-    st = grg.grg_batch_apply(b, xd, y, use_graph=True)
+    st = grg.grg_batch_apply(b, xd, y, use_graph=True)  # eager: records the counts
     assert st["converged"] and st["true_rel_resid"] <= 1e-10
+    first = to_host(y)
+    st = grg.grg_batch_apply(b, xd, y, use_graph=True)  # one captured replay
+    assert st["converged"] and st["true_rel_resid"] <= 1e-10
+    assert grg.grg_batch_graph_info(b) != (0, 0)
+    assert np.array_equal(to_host(y), first)
     ys = split(b, ms, to_host(y), nrhs)
     xs = split(b, ms, x, nrhs)
     for i in (0, 17, 47):  # spot members against the oracle
