@@ -71,8 +71,10 @@ def launch_descriptor(info: dict, prec: str, launches: int, eo: bool = False) ->
     p = PREC_ID[prec]
     if eo and info["split"] == 7:
         # the plane form of the reduced operator's half-stencil (compact
-        # fields: IO 0), one workgroup of SB lanes per x-y plane
-        sym, gs = "eo_plane_kernel<0>", info["grid"] * info["SB"]
+        # fields: IO 0), one workgroup of SB lanes per x-y plane; the first
+        # half of each operator application has no alpha term (epilogue 0),
+        # the second the alpha term and the fused sums (epilogue 2)
+        sym, gs = "eo_plane_kernel<0, 0> + eo_plane_kernel<0, 2>", info["grid"] * info["SB"]
     elif eo:
         # the compact half-stencils of the reduced operator in the tuned form
         # (hop schedule info["split"], compact fields: IO 0)
@@ -214,7 +216,10 @@ def batch_leg(grg, torch, args):
     out = {"lattices": 48, "rhs_per_lattice": nrhs, "systems": 48 * nrhs,
            "sites": int(sum(int(np.prod(m["dims"])) for m in ms))}
     for mode, graph in (("graph", True), ("eager", False)):
-        grg.grg_batch_apply(b, xd, yd, use_graph=graph)
+        # graph: the first apply runs eagerly and records the outer and inner
+        # counts, the second captures the whole apply; the timed ones replay it
+        for _ in range(2):
+            grg.grg_batch_apply(b, xd, yd, use_graph=graph)
         torch.cuda.synchronize()
         k = max(1, args.steps // 2)
         t0 = time.perf_counter()
@@ -224,7 +229,27 @@ def batch_leg(grg, torch, args):
         dt = (time.perf_counter() - t0) / k
         out[mode] = {"ms_per_batch": dt * 1e3, "applies_per_s": 48 * nrhs / dt, "inner_iters": st["iters"],
                      "outer": st["outer"], "true_rel_resid": st["true_rel_resid"]}
+        if graph:
+            out[mode]["captured_outer_inner"] = list(grg.grg_batch_graph_info(b))
         log(f"batch ({mode}): {dt * 1e3:.2f} ms per 48 x {nrhs} applies, {48 * nrhs / dt:.1f} applies/s")
+    # roofline of the batch's per-iteration kernels at the tuned launch, every
+    # system active (HIP events on the batch's stream, timed by the tuner):
+    # the stencil reads 12 complex and writes 12 per site and RHS and reads
+    # 4 links per site; the MR update reads x, r, q and writes x, r
+    ti = grg.grg_batch_tune_info(b, "fp32")
+    vt = out["sites"]
+    kb = {"stencil": dslash_bytes_per_launch("fp32", vt, nrhs),
+          "mr_update": vt * nrhs * 5 * 24 * REAL_BYTES["fp32"]}
+    kms = {"stencil": ti["stencil_ms"], "mr_update": ti["update_ms"]}
+    dom = max(kms, key=kms.get)
+    ach = kb[dom] / (kms[dom] * 1e-3) / 1e9
+    out["roofline"] = {"bound": "hbm", "kernel": f"batch {dom} (fp32, all 192 systems)", "achieved": ach,
+                       "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+                       "alg_bytes_per_launch": kb[dom], "avg_launch_ms": kms[dom],
+                       "other": {k: {"ms": kms[k], "alg_GBps": kb[k] / (kms[k] * 1e-3) / 1e9} for k in kms},
+                       "launch": {k: ti[k] for k in ("SB", "RG", "grid")}}
+    log(f"batch roofline: {dom} {kms[dom]:.3f} ms, {ach:.0f} GB/s ({ach / PEAK_HBM_GBS:.2f} of peak); "
+        + ", ".join(f"{k} {kms[k]:.3f} ms" for k in kms))
     grg.grg_batch_destroy(b)
     return out
 

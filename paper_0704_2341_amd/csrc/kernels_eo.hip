@@ -574,25 +574,30 @@ __global__ void __launch_bounds__(256) eo_hop_kernel(EoArgs a)
 // links through L2; each XCD walks its own z-slab.
 constexpr int kMaxPlane = 512;
 
-template <int IO>
+// The slice body is straight-line: the site's coordinates come from the
+// lane (x / 2, y), the plane z and the slice t with no divisions; the z and t
+// neighbours are the same column one plane or one slice away; the epilogue
+// (EPI 0: out = beta H in; 1: + alpha in2; 2: + alpha in2 with the fused
+// sums) is chosen at compile time, and the twelve in2 words (and the
+// dot_with words) are loaded together before they are used.
+template <int IO, int EPI>
 __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
 {
     constexpr bool in_full = IO == 1, in2_full = IO >= 1, out_full = IO == 2;
+    constexpr bool has_in2 = EPI >= 1, dots = EPI == 2;
     typedef bf16x2 S;
     typedef float R;
-    typedef Operand<S, R> OP;
     typedef uint32_t PT;
     __shared__ PT ring[3][12][kMaxPlane];
     __shared__ double red[kMaxPlane / 64][kMaxRhs][3];
-    const S *__restrict__ in = (const S *)a.in;
-    const S *__restrict__ in2 = (const S *)a.in2;
-    S *__restrict__ out = (S *)a.out;
-    const S *__restrict__ Uo = (const S *)a.U + (size_t)a.po * 36 * a.Vhs;
-    const S *__restrict__ Ui = (const S *)a.U + (size_t)(1 - a.po) * 36 * a.Vhs;
+    const PT *__restrict__ in = (const PT *)a.in;
+    const PT *__restrict__ in2 = (const PT *)a.in2;
+    PT *__restrict__ out = (PT *)a.out;
+    const PT *__restrict__ Uo = (const PT *)a.U + (size_t)a.po * 36 * a.Vhs;
+    const PT *__restrict__ Ui = (const PT *)a.U + (size_t)(1 - a.po) * 36 * a.Vhs;
     const uint8_t *__restrict__ mk = a.mask + (size_t)a.po * a.Vhs;
     const int P = blockDim.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int nw = P >> 6, nr = a.nrhs;
-    const bool dots = a.partials != nullptr;
     if (dots) {
         for (int i = tid; i < nw * nr * 3; i += P) red[i / (nr * 3)][(i / 3) % nr][i % 3] = 0.0;
     }
@@ -603,32 +608,35 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
     const int Z0 = (xcd * Lz) >> 3, nz = (((xcd + 1) * Lz) >> 3) - Z0;
     const int ML = a.march, nc = (Lt + ML - 1) / ML;
     const int nx = nz * nr * nc;
-    // this column's neighbours in the plane: along its x-row (x hops) and
-    // one x-row up and down (y hops)
-    const int xh = tid % Lh, rs = tid - xh;
+    // this lane's column: x / 2 and y; its neighbours in the plane along its
+    // x-row (x hops) and one x-row up and down (y hops)
+    const int xh = tid % Lh, yy = tid / Lh, rs = tid - xh;
     const int xp = rs + (xh + 1 == Lh ? 0 : xh + 1), xm = rs + (xh == 0 ? Lh - 1 : xh - 1);
     const int yp = tid + Lh >= P ? tid + Lh - P : tid + Lh, ym = tid < Lh ? tid - Lh + P : tid - Lh;
-    // element index of the input site with compact index hq (other parity)
-    auto iidx = [&](int hq) -> int {
-        if constexpr (in_full) {
-            SiteGeo tq;
-            return eo_site(hq, 1 - a.po, a.g, tq);
-        } else {
-            return hq;
-        }
+    // the sums' second vector: in2 itself (its loaded words), none (|out|^2
+    // only), or a field of its own
+    const int dmode = !dots || a.dot_with == nullptr ? 0 : (!in2_full && a.dot_with == a.in2) ? 1 : 2;
+    // input element of the other parity's site at compact index hq in slice
+    // tq (full layout: the site itself, 2 hq plus its x bit)
+    auto iidx = [&](int hq, int tq, int zq) -> int {
+        if constexpr (in_full) return 2 * hq + (((1 - a.po) ^ yy ^ zq ^ tq) & 1);
+        else return hq;
     };
     for (int j = slot; j < nx; j += slots) {
         const int r = j % nr, rest = j / nr;
         const int z = Z0 + rest % nz, ch = rest / nz;
         const int col = z * P + tid;
         const int t0 = ch * ML, t1 = min(t0 + ML, Lt);
+        const bool act = a.active == nullptr || a.active[r] != 0;
+        const int zf = z + 1 == Lz ? 0 : z + 1, zb = z == 0 ? Lz - 1 : z - 1;
+        const int dzf = (zf - z) * P, dzb = (zb - z) * P;
         {
             const int tm = t0 == 0 ? Lt - 1 : t0 - 1;
-            const int im = iidx(tm * Vs3 + col), i0 = iidx(t0 * Vs3 + col);
+            const int im = iidx(tm * Vs3 + col, tm, z), i0 = iidx(t0 * Vs3 + col, t0, z);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                ring[0][c][tid] = OP::load(in, fidx(im, r, c, nr));
-                ring[1][c][tid] = OP::load(in, fidx(i0, r, c, nr));
+                ring[0][c][tid] = in[fidx(im, r, c, nr)];
+                ring[1][c][tid] = in[fidx(i0, r, c, nr)];
             }
         }
         // the slots of slices t - 1, t and t + 1
@@ -641,23 +649,21 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
             const int h = base + tid;
             const int tf = t + 1 == Lt ? 0 : t + 1, tb = t == 0 ? Lt - 1 : t - 1;
             const bool on = mk[h] == 0;
+            // the output site: x = 2 xh + b, with b from the parity
+            const int b = (a.po ^ yy ^ z ^ t) & 1;
+            const int s = 2 * h + b;
             // the forward t-neighbour: used at the end of this slice, then
             // kept in the ring for the two slices after it
             PT qc[12];
             {
-                const int fi = iidx(tf * Vs3 + col);
+                const int fi = iidx(tf * Vs3 + col, tf, z);
 #pragma unroll
-                for (int c = 0; c < 12; ++c) qc[c] = OP::load(in, fidx(fi, r, c, nr));
+                for (int c = 0; c < 12; ++c) qc[c] = in[fidx(fi, r, c, nr)];
             }
-            SiteGeo sq;
-            const int s = eo_site(h, a.po, a.g, sq);
             cpx<R> acc[12];
-#pragma unroll
-            for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
             if (on) {
                 // x and y hops from the ring: neighbour column n, and the link
-                // U_mu(s) (forward) or U_mu(s - mu) at the neighbour's index
-                const bool b = (s & 1) != 0;
+                // U_mu(s) (forward) or U_mu(s - mu) at the neighbour's index;
                 // loads in batches: the x and y hops' links, the z+ hop's
                 // operands, then the z- hop's with the t hops' links
                 PT u4[4][9];
@@ -667,7 +673,7 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
                     const int mu = k >> 1;
 #pragma unroll
                     for (int e = 0; e < 9; ++e)
-                        u4[k][e] = (k & 1) ? OP::load(Ui, lidx(base + n, mu, e)) : OP::load(Uo, lidx(h, mu, e));
+                        u4[k][e] = (k & 1) ? Ui[lidx(base + n, mu, e)] : Uo[lidx(h, mu, e)];
                 }
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
@@ -675,26 +681,46 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
                     PT p[12];
 #pragma unroll
                     for (int c = 0; c < 12; ++c) p[c] = ring[cur][c][n];
-                    eo_hop_k(k, acc, p, u4[k]);
+                    if (k == 0) hop_bf16<0, true, true>(acc, p, u4[0]);
+                    else if (k == 1) hop_bf16<0, false>(acc, p, u4[1]);
+                    else if (k == 2) hop_bf16<1, true>(acc, p, u4[2]);
+                    else hop_bf16<1, false>(acc, p, u4[3]);
                 }
                 PT pz[12], uz[9];
-                eo_load_hop<OP>(4, pz, uz, in, Uo, Ui, s, h, sq, a.g, r, nr, in_full);
-                eo_hop_k(4, acc, pz, uz);
+                {
+                    // z+: the same column one plane up, U_z(s)
+                    const int hn = h + dzf, ni = iidx(hn, t, zf);
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) pz[c] = in[fidx(ni, r, c, nr)];
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) uz[e] = Uo[lidx(h, 2, e)];
+                }
+                hop_bf16<2, true>(acc, pz, uz);
                 PT ut[2][9];
-                eo_load_hop<OP>(5, pz, uz, in, Uo, Ui, s, h, sq, a.g, r, nr, in_full);
+                {
+                    // z-: one plane down, U_z(s - z) at the neighbour's index
+                    const int hn = h + dzb, ni = iidx(hn, t, zb);
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) pz[c] = in[fidx(ni, r, c, nr)];
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) uz[e] = Ui[lidx(hn, 2, e)];
+                }
 #pragma unroll
                 for (int e = 0; e < 9; ++e) {
-                    ut[0][e] = OP::load(Uo, lidx(h, 3, e));
-                    ut[1][e] = OP::load(Ui, lidx(tb * Vs3 + col, 3, e));
+                    ut[0][e] = Uo[lidx(h, 3, e)];
+                    ut[1][e] = Ui[lidx(tb * Vs3 + col, 3, e)];
                 }
-                eo_hop_k(5, acc, pz, uz);
-                eo_hop_k(6, acc, qc, ut[0]);
+                hop_bf16<2, false>(acc, pz, uz);
+                hop_bf16<3, true>(acc, qc, ut[0]);
                 {
                     PT p[12];
 #pragma unroll
                     for (int c = 0; c < 12; ++c) p[c] = ring[prv][c][tid];
-                    eo_hop_k(7, acc, p, ut[1]);
+                    hop_bf16<3, false>(acc, p, ut[1]);
                 }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
             }
             // slice t + 1 into the slot of slice t - 2 (read across lanes in
             // slice t - 2 only, which every wave has left)
@@ -706,59 +732,74 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
                 cur = nxt;
                 nxt = o;
             }
+            // epilogue: every word of in2 (and of the sums' vector) first
+            PT w2[12], wd[12];
+            if constexpr (has_in2) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    if constexpr (IO == 0)
+                        // read once, whole lines: streamed past L2
+                        w2[c] = __builtin_nontemporal_load(in2 + fidx(h, r, c, nr));
+                    else
+                        // the full layout: half of each line, the other half
+                        // read by the neighbouring lanes' hops
+                        w2[c] = in2[fidx(s, r, c, nr)];
+                }
+            }
+            if constexpr (dots) {
+                if (dmode == 2) {
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) wd[c] = ((const PT *)a.dot_with)[fidx(h, r, c, nr)];
+                } else if (dmode == 1) {
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) wd[c] = w2[c];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) wd[c] = 0u;
+                }
+            }
+            const bool keep = on && act;
             R sre = 0, sim = 0, sqq = 0;
-            const bool act = a.active == nullptr || a.active[r] != 0;
             // the partner copy of the last step is the input itself at this
             // column and slice, which the ring holds (now in slot prv)
             const bool partner_in = out_full && a.partner == a.in;
-            // the sums against in2 itself (the reduced operator's second
-            // half) reuse its loaded value
-            const bool dot_in2 = !in2_full && a.dot_with == a.in2;
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                const size_t i = fidx(h, r, c, nr);
-                cpx<R> o = {0, 0}, v2 = {0, 0};
-                if (in2 && on) {
-                    if constexpr (IO == 0) {
-                        // read once, whole lines: streamed past L2
-                        v2 = as_cpx(__builtin_nontemporal_load((const uint32_t *)in2 + i));
-                    } else {
-                        // the full layout: half of each line, the other half
-                        // read by the neighbouring lanes' hops
-                        v2 = ldr<R>(in2, in2_full ? fidx(s, r, c, nr) : i);
-                    }
+                cpx<R> o = {be * acc[c].re, be * acc[c].im};
+                if constexpr (has_in2) {
+                    const cpx<R> v2 = as_cpx(w2[c]);
+                    o.re = fmaf(al, v2.re, o.re);
+                    o.im = fmaf(al, v2.im, o.im);
                 }
-                if (on && act) {
-                    o = {be * acc[c].re, be * acc[c].im};
-                    if (in2) {
-                        o.re = fma(al, v2.re, o.re);
-                        o.im = fma(al, v2.im, o.im);
-                    }
-                }
+                if (!keep) o = {0, 0};
+                const PT ow = pack_bf16(o.re, o.im);
                 if constexpr (out_full) {
                     // this site, and the other parity's site of the same index
                     // (two halves of each line: ordinary stores, merged in L2)
-                    stc(out, fidx(s, r, c, nr), o);
-                    out[fidx(s ^ 1, r, c, nr)] = partner_in ? (S)ring[prv][c][tid] : ((const S *)a.partner)[i];
+                    out[fidx(s, r, c, nr)] = ow;
+                    out[fidx(s ^ 1, r, c, nr)] =
+                        partner_in ? ring[prv][c][tid] : ((const PT *)a.partner)[fidx(h, r, c, nr)];
                 } else {
                     // written once, whole lines: streamed past L2, which keeps
                     // the links and the input planes the next workgroups read
-                    __builtin_nontemporal_store(pack_bf16(o.re, o.im), (uint32_t *)out + i);
+                    __builtin_nontemporal_store(ow, out + fidx(h, r, c, nr));
                 }
-                if (dots && on) {
-                    const cpx<R> v = dot_in2 ? v2 : a.dot_with ? ldr<R>((const S *)a.dot_with, i) : cpx<R>{0, 0};
-                    sre = fma(o.re, v.re, fma(o.im, v.im, sre));
-                    sim = fma(o.re, v.im, fma(-o.im, v.re, sim));
-                    sqq = fma(o.re, o.re, fma(o.im, o.im, sqq));
+                if constexpr (dots) {
+                    const cpx<R> v = as_cpx(wd[c]);
+                    sre = fmaf(o.re, v.re, fmaf(o.im, v.im, sre));
+                    sim = fmaf(o.re, v.im, fmaf(-o.im, v.re, sim));
+                    sqq = fmaf(o.re, o.re, fmaf(o.im, o.im, sqq));
                 }
             }
-            dre += (double)sre;
-            dim += (double)sim;
-            dqq += (double)sqq;
+            if constexpr (dots) {
+                dre += (double)sre;
+                dim += (double)sim;
+                dqq += (double)sqq;
+            }
         }
         // the next item's first loads overwrite slots read across lanes
         __syncthreads();
-        if (dots) {
+        if constexpr (dots) {
             dre = wave_sum(dre);
             dim = wave_sum(dim);
             dqq = wave_sum(dqq);
@@ -769,7 +810,7 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
             }
         }
     }
-    if (dots) {
+    if constexpr (dots) {
         __syncthreads();
         for (int i = tid; i < nr * 3; i += P) {
             double t = 0;
@@ -851,9 +892,17 @@ hipError_t launch_eo_hop(int prec, const EoArgs &a, int grid, hipStream_t st)
             a.g.L[0] < 2 || a.Vh != P * a.g.L[2] * a.g.L[3])
             return hipErrorInvalidValue;
         dim3 pb(P), pg(grid);
-        if (io == 1) hipLaunchKernelGGL((eo_plane_kernel<1>), pg, pb, 0, st, a);
-        else if (io == 2) hipLaunchKernelGGL((eo_plane_kernel<2>), pg, pb, 0, st, a);
-        else hipLaunchKernelGGL((eo_plane_kernel<0>), pg, pb, 0, st, a);
+        const int epi = a.partials ? 2 : a.in2 ? 1 : 0;
+        if (epi == 2 && !a.in2) return hipErrorInvalidValue;  // the sums come with the alpha term
+#define PLANE(I, E) hipLaunchKernelGGL((eo_plane_kernel<I, E>), pg, pb, 0, st, a)
+        if (io == 1) {
+            if (epi == 2) PLANE(1, 2); else if (epi == 1) PLANE(1, 1); else return hipErrorInvalidValue;
+        } else if (io == 2) {
+            if (epi == 1) PLANE(2, 1); else return hipErrorInvalidValue;
+        } else {
+            if (epi == 2) PLANE(0, 2); else if (epi == 1) PLANE(0, 1); else PLANE(0, 0);
+        }
+#undef PLANE
         return hipGetLastError();
     }
     if (a.SB != 64 && a.SB != 128 && a.SB != 256) return hipErrorInvalidValue;

@@ -158,7 +158,9 @@ __device__ __forceinline__ void dot_fence(float &a0, float &b0, float &a1, float
     asm("s_nop 2" : "+v"(a0), "+v"(b0), "+v"(a1), "+v"(b1));
 }
 
-template <int MU, bool FWD>
+// FIRST: the first hop of a site writes the accumulators instead of adding
+// to them (the same values as adding to zero, without clearing them first).
+template <int MU, bool FWD, bool FIRST = false>
 __device__ __forceinline__ void hop_bf16(cpx<float> (&acc)[12], const uint32_t (&p)[12],
                                          const uint32_t (&u)[9])
 {
@@ -210,12 +212,14 @@ __device__ __forceinline__ void hop_bf16(cpx<float> (&acc)[12], const uint32_t (
         w1[r] = {a1, b1};
     }
     const float hl = FWD ? 0.5f : -0.5f;
+    // a + b f with a = 0 on the first hop (exact: f is a power of two)
+    auto mad = [](float f, float b, float a) { return FIRST ? f * b : fmaf(f, b, a); };
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-        acc[r].re = fmaf(-0.5f, w0[r].re, acc[r].re);
-        acc[r].im = fmaf(-0.5f, w0[r].im, acc[r].im);
-        acc[3 + r].re = fmaf(-0.5f, w1[r].re, acc[3 + r].re);
-        acc[3 + r].im = fmaf(-0.5f, w1[r].im, acc[3 + r].im);
+        acc[r].re = mad(-0.5f, w0[r].re, acc[r].re);
+        acc[r].im = mad(-0.5f, w0[r].im, acc[r].im);
+        acc[3 + r].re = mad(-0.5f, w1[r].re, acc[3 + r].re);
+        acc[3 + r].im = mad(-0.5f, w1[r].im, acc[3 + r].im);
         cpx<float> d0, d1;  // B^+ w
         if (MU == 0) {
             d0 = {w1[r].im, -w1[r].re};
@@ -230,10 +234,10 @@ __device__ __forceinline__ void hop_bf16(cpx<float> (&acc)[12], const uint32_t (
             d0 = w0[r];
             d1 = w1[r];
         }
-        acc[6 + r].re = fmaf(hl, d0.re, acc[6 + r].re);
-        acc[6 + r].im = fmaf(hl, d0.im, acc[6 + r].im);
-        acc[9 + r].re = fmaf(hl, d1.re, acc[9 + r].re);
-        acc[9 + r].im = fmaf(hl, d1.im, acc[9 + r].im);
+        acc[6 + r].re = mad(hl, d0.re, acc[6 + r].re);
+        acc[6 + r].im = mad(hl, d0.im, acc[6 + r].im);
+        acc[9 + r].re = mad(hl, d1.re, acc[9 + r].re);
+        acc[9 + r].im = mad(hl, d1.im, acc[9 + r].im);
     }
 }
 

@@ -39,7 +39,7 @@ def test_algorithmic_bytes():
     assert b.eo_bytes_per_launch("fp64", V, 1, 20, 5) == V * ((1 + 1.5) / 2 * 12 * 16 + 4 * 9 * 16)
 
 
-@pytest.mark.parametrize("split,sym", [(7, "eo_plane_kernel<0>"), (3, "eo_hop_kernel<2, 3, 0>"),
+@pytest.mark.parametrize("split,sym", [(7, "eo_plane_kernel<0, 0> + eo_plane_kernel<0, 2>"), (3, "eo_hop_kernel<2, 3, 0>"),
                                        (1, "eo_hop_kernel<2, 1, 0>")])
 def test_dominant_launch_names(split, sym):
     b = _bench()
