@@ -577,14 +577,17 @@ constexpr int kMaxPlane = 512;
 // The slice body is straight-line: the site's coordinates come from the
 // lane (x / 2, y), the plane z and the slice t with no divisions; the z and t
 // neighbours are the same column one plane or one slice away; the epilogue
-// (EPI 0: out = beta H in; 1: + alpha in2; 2: + alpha in2 with the fused
-// sums) is chosen at compile time, and the twelve in2 words (and the
-// dot_with words) are loaded together before they are used.
+// (EPI 0: out = H in; 3: out = beta H in; 1: out = alpha in2 + beta H in; 2:
+// the same with the fused sums) is chosen at compile time, and the twelve
+// in2 words (and the dot_with words) are loaded together before they are
+// used.  The fused sums <out, v> and |out|^2 are formed from the stored BF16
+// words of out, two-way dot products exact in FP32: the values the solver's
+// update then reads.
 template <int IO, int EPI>
 __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
 {
     constexpr bool in_full = IO == 1, in2_full = IO >= 1, out_full = IO == 2;
-    constexpr bool has_in2 = EPI >= 1, dots = EPI == 2;
+    constexpr bool has_in2 = EPI == 1 || EPI == 2, dots = EPI == 2, scaled = EPI != 0;
     typedef bf16x2 S;
     typedef float R;
     typedef uint32_t PT;
@@ -660,29 +663,37 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
 #pragma unroll
                 for (int c = 0; c < 12; ++c) qc[c] = in[fidx(fi, r, c, nr)];
             }
+            // the x and y hops from the ring: neighbour column n, and the
+            // link U_mu(s) (forward) or U_mu(s - mu) at the neighbour's index;
+            // loads in batches: the x and y hops' links, the z+ hop's
+            // operands, then the z- hop's with the t hops' links.  The first
+            // hop runs on every lane (its operands are valid for a coarse
+            // site too) and writes the accumulators; a coarse site's output
+            // is replaced by zero below.
+            PT u4[4][9];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int n = k == 0 ? (b ? xp : tid) : k == 1 ? (b ? tid : xm) : k == 2 ? yp : ym;
+                const int mu = k >> 1;
+#pragma unroll
+                for (int e = 0; e < 9; ++e)
+                    u4[k][e] = (k & 1) ? Ui[lidx(base + n, mu, e)] : Uo[lidx(h, mu, e)];
+            }
             cpx<R> acc[12];
+            {
+                PT p[12];
+#pragma unroll
+                for (int c = 0; c < 12; ++c) p[c] = ring[cur][c][b ? xp : tid];
+                hop_bf16<0, true, true>(acc, p, u4[0]);
+            }
             if (on) {
-                // x and y hops from the ring: neighbour column n, and the link
-                // U_mu(s) (forward) or U_mu(s - mu) at the neighbour's index;
-                // loads in batches: the x and y hops' links, the z+ hop's
-                // operands, then the z- hop's with the t hops' links
-                PT u4[4][9];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int n = k == 0 ? (b ? xp : tid) : k == 1 ? (b ? tid : xm) : k == 2 ? yp : ym;
-                    const int mu = k >> 1;
-#pragma unroll
-                    for (int e = 0; e < 9; ++e)
-                        u4[k][e] = (k & 1) ? Ui[lidx(base + n, mu, e)] : Uo[lidx(h, mu, e)];
-                }
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int n = k == 0 ? (b ? xp : tid) : k == 1 ? (b ? tid : xm) : k == 2 ? yp : ym;
+                for (int k = 1; k < 4; ++k) {
+                    const int n = k == 1 ? (b ? tid : xm) : k == 2 ? yp : ym;
                     PT p[12];
 #pragma unroll
                     for (int c = 0; c < 12; ++c) p[c] = ring[cur][c][n];
-                    if (k == 0) hop_bf16<0, true, true>(acc, p, u4[0]);
-                    else if (k == 1) hop_bf16<0, false>(acc, p, u4[1]);
+                    if (k == 1) hop_bf16<0, false>(acc, p, u4[1]);
                     else if (k == 2) hop_bf16<1, true>(acc, p, u4[2]);
                     else hop_bf16<1, false>(acc, p, u4[3]);
                 }
@@ -718,9 +729,6 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
                     for (int c = 0; c < 12; ++c) p[c] = ring[prv][c][tid];
                     hop_bf16<3, false>(acc, p, ut[1]);
                 }
-            } else {
-#pragma unroll
-                for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
             }
             // slice t + 1 into the slot of slice t - 2 (read across lanes in
             // slice t - 2 only, which every wave has left)
@@ -765,7 +773,8 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
             const bool partner_in = out_full && a.partner == a.in;
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                cpx<R> o = {be * acc[c].re, be * acc[c].im};
+                cpx<R> o = acc[c];
+                if constexpr (scaled) o = {be * acc[c].re, be * acc[c].im};
                 if constexpr (has_in2) {
                     const cpx<R> v2 = as_cpx(w2[c]);
                     o.re = fmaf(al, v2.re, o.re);
@@ -785,13 +794,14 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
                     __builtin_nontemporal_store(ow, out + fidx(h, r, c, nr));
                 }
                 if constexpr (dots) {
-                    const cpx<R> v = as_cpx(wd[c]);
-                    sre = fmaf(o.re, v.re, fmaf(o.im, v.im, sre));
-                    sim = fmaf(o.re, v.im, fmaf(-o.im, v.re, sim));
-                    sqq = fmaf(o.re, o.re, fmaf(o.im, o.im, sqq));
+                    // re <o, v> = o.re v.re + o.im v.im, im = o.re v.im - o.im v.re
+                    sre = dot2bf(ow, wd[c], sre);
+                    sqq = dot2bf(ow, ow, sqq);
+                    sim = dot2n<0, 1>(ow, swap_halves(wd[c]), sim);
                 }
             }
             if constexpr (dots) {
+                asm("s_nop 2" : "+v"(sim));  // closes the chain of sim (see dot_fence)
                 dre += (double)sre;
                 dim += (double)sim;
                 dqq += (double)sqq;
@@ -892,7 +902,7 @@ hipError_t launch_eo_hop(int prec, const EoArgs &a, int grid, hipStream_t st)
             a.g.L[0] < 2 || a.Vh != P * a.g.L[2] * a.g.L[3])
             return hipErrorInvalidValue;
         dim3 pb(P), pg(grid);
-        const int epi = a.partials ? 2 : a.in2 ? 1 : 0;
+        const int epi = a.partials ? 2 : a.in2 ? 1 : a.beta == 1.0 ? 0 : 3;
         if (epi == 2 && !a.in2) return hipErrorInvalidValue;  // the sums come with the alpha term
 #define PLANE(I, E) hipLaunchKernelGGL((eo_plane_kernel<I, E>), pg, pb, 0, st, a)
         if (io == 1) {
@@ -900,7 +910,8 @@ hipError_t launch_eo_hop(int prec, const EoArgs &a, int grid, hipStream_t st)
         } else if (io == 2) {
             if (epi == 1) PLANE(2, 1); else return hipErrorInvalidValue;
         } else {
-            if (epi == 2) PLANE(0, 2); else if (epi == 1) PLANE(0, 1); else PLANE(0, 0);
+            if (epi == 2) PLANE(0, 2); else if (epi == 1) PLANE(0, 1); else if (epi == 3) PLANE(0, 3);
+            else PLANE(0, 0);
         }
 #undef PLANE
         return hipGetLastError();
