@@ -287,9 +287,11 @@ grg_status grg_schur_tune(grg_schur s, int nrhs);
  * walking info[5] time slices; 4 and 5 carry info[1] = 2 or 3 RHS through
  * each hop together; 6 takes the x hops' spinors from lane shuffles; 7 is
  * the plane form of the t-marching stencil (info[0] = Lx / 2 * Ly, a multiple
- * of 64 and at most 512, info[1] = 1), a workgroup holding a whole x-y plane
- * of the half lattice for one RHS, walking info[5] time slices with the x, y
- * and backward t hops read from LDS; info[5] = 0 except with 3 and 7.  With
+ * of 64 and at most 512), a workgroup holding a whole x-y plane of the half
+ * lattice for one RHS (info[1] = 1), or two planes z, z + 1 of it (info[1] =
+ * 2, Lz a multiple of 16, the z hop between the two from LDS), walking
+ * info[5] time slices with the x, y and backward t hops read from LDS;
+ * info[5] = 0 except with 3 and 7.  With
  * schedule 3 or 7, the full-layout first and last steps of a reduced solve
  * run the one-hop shape that tuning found faster for them, if it found one,
  * else the same schedule as well. */

@@ -583,39 +583,44 @@ constexpr int kMaxPlane = 512;
 // used.  The fused sums <out, v> and |out|^2 are formed from the stored BF16
 // words of out, two-way dot products exact in FP32: the values the solver's
 // update then reads.
-template <int IO, int EPI>
-__global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
+template <int IO, int EPI, int NPL>
+__global__ void __launch_bounds__(kMaxPlane * NPL, 4) eo_plane_kernel(EoArgs a)
 {
     constexpr bool in_full = IO == 1, in2_full = IO >= 1, out_full = IO == 2;
     constexpr bool has_in2 = EPI == 1 || EPI == 2, dots = EPI == 2, scaled = EPI != 0;
     typedef bf16x2 S;
     typedef float R;
     typedef uint32_t PT;
-    __shared__ PT ring[3][12][kMaxPlane];
-    __shared__ double red[kMaxPlane / 64][kMaxRhs][3];
+    __shared__ PT ring[3][12][kMaxPlane * NPL];
+    __shared__ double red[kMaxPlane * NPL / 64][kMaxRhs][3];
     const PT *__restrict__ in = (const PT *)a.in;
     const PT *__restrict__ in2 = (const PT *)a.in2;
     PT *__restrict__ out = (PT *)a.out;
     const PT *__restrict__ Uo = (const PT *)a.U + (size_t)a.po * 36 * a.Vhs;
     const PT *__restrict__ Ui = (const PT *)a.U + (size_t)(1 - a.po) * 36 * a.Vhs;
     const uint8_t *__restrict__ mk = a.mask + (size_t)a.po * a.Vhs;
-    const int P = blockDim.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int nw = P >> 6, nr = a.nrhs;
+    // NPL planes per workgroup (z0, z0 + 1 with two): lane tid holds column
+    // l of plane pl, in the ring at index tid
+    const int P = blockDim.x / NPL, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int pl = NPL == 1 ? 0 : tid / P, l = tid - pl * P;  // pl: the same in a wavefront
+    const int nw = blockDim.x >> 6, nr = a.nrhs;
     if (dots) {
-        for (int i = tid; i < nw * nr * 3; i += P) red[i / (nr * 3)][(i / 3) % nr][i % 3] = 0.0;
+        for (int i = tid; i < nw * nr * 3; i += blockDim.x) red[i / (nr * 3)][(i / 3) % nr][i % 3] = 0.0;
     }
     const R al = (R)a.alpha, be = (R)a.beta;
     const int Lt = a.g.L[3], Lz = a.g.L[2], Lh = a.g.L[0] >> 1;
     const int Vs3 = a.Vh / Lt;  // half-sites per time slice = P * Lz
     const int xcd = (int)(blockIdx.x & 7), slot = (int)(blockIdx.x >> 3), slots = (int)(gridDim.x >> 3);
-    const int Z0 = (xcd * Lz) >> 3, nz = (((xcd + 1) * Lz) >> 3) - Z0;
+    const int Z0 = (xcd * Lz) >> 3, nz = ((((xcd + 1) * Lz) >> 3) - Z0) / NPL;
     const int ML = a.march, nc = (Lt + ML - 1) / ML;
     const int nx = nz * nr * nc;
     // this lane's column: x / 2 and y; its neighbours in the plane along its
-    // x-row (x hops) and one x-row up and down (y hops)
-    const int xh = tid % Lh, yy = tid / Lh, rs = tid - xh;
+    // x-row (x hops) and one x-row up and down (y hops), as ring indices
+    const int xh = l % Lh, yy = l / Lh, rs = tid - xh;
     const int xp = rs + (xh + 1 == Lh ? 0 : xh + 1), xm = rs + (xh == 0 ? Lh - 1 : xh - 1);
-    const int yp = tid + Lh >= P ? tid + Lh - P : tid + Lh, ym = tid < Lh ? tid - Lh + P : tid - Lh;
+    const int yp = pl * P + (l + Lh >= P ? l + Lh - P : l + Lh), ym = pl * P + (l < Lh ? l - Lh + P : l - Lh);
+    // with two planes, the ring index of the same column in the other plane
+    const int other = NPL == 2 ? (pl == 0 ? tid + P : tid - P) : tid;
     // the sums' second vector: in2 itself (its loaded words), none (|out|^2
     // only), or a field of its own
     const int dmode = !dots || a.dot_with == nullptr ? 0 : (!in2_full && a.dot_with == a.in2) ? 1 : 2;
@@ -627,8 +632,8 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
     };
     for (int j = slot; j < nx; j += slots) {
         const int r = j % nr, rest = j / nr;
-        const int z = Z0 + rest % nz, ch = rest / nz;
-        const int col = z * P + tid;
+        const int z = Z0 + NPL * (rest % nz) + pl, ch = rest / nz;
+        const int col = z * P + l;
         const int t0 = ch * ML, t1 = min(t0 + ML, Lt);
         const bool act = a.active == nullptr || a.active[r] != 0;
         const int zf = z + 1 == Lz ? 0 : z + 1, zb = z == 0 ? Lz - 1 : z - 1;
@@ -648,7 +653,7 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
 #pragma unroll 1
         for (int t = t0; t < t1; ++t) {
             __syncthreads();
-            const int base = t * Vs3 + z * P;  // compact index of the plane's column 0
+            const int base = t * Vs3 + z * P - pl * P;  // compact index of ring index 0
             const int h = base + tid;
             const int tf = t + 1 == Lt ? 0 : t + 1, tb = t == 0 ? Lt - 1 : t - 1;
             const bool on = mk[h] == 0;
@@ -699,20 +704,33 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
                 }
                 PT pz[12], uz[9];
                 {
-                    // z+: the same column one plane up, U_z(s)
-                    const int hn = h + dzf, ni = iidx(hn, t, zf);
+                    // z+: the same column one plane up, U_z(s); with two
+                    // planes, the lower plane's from the upper plane's ring
+                    if (NPL == 2 && pl == 0) {
 #pragma unroll
-                    for (int c = 0; c < 12; ++c) pz[c] = in[fidx(ni, r, c, nr)];
+                        for (int c = 0; c < 12; ++c) pz[c] = ring[cur][c][other];
+                    } else {
+                        const int ni = iidx(h + dzf, t, zf);
+#pragma unroll
+                        for (int c = 0; c < 12; ++c) pz[c] = in[fidx(ni, r, c, nr)];
+                    }
 #pragma unroll
                     for (int e = 0; e < 9; ++e) uz[e] = Uo[lidx(h, 2, e)];
                 }
                 hop_bf16<2, true>(acc, pz, uz);
                 PT ut[2][9];
                 {
-                    // z-: one plane down, U_z(s - z) at the neighbour's index
-                    const int hn = h + dzb, ni = iidx(hn, t, zb);
+                    // z-: one plane down, U_z(s - z) at the neighbour's index;
+                    // with two planes, the upper plane's from the lower's ring
+                    const int hn = h + dzb;
+                    if (NPL == 2 && pl == 1) {
 #pragma unroll
-                    for (int c = 0; c < 12; ++c) pz[c] = in[fidx(ni, r, c, nr)];
+                        for (int c = 0; c < 12; ++c) pz[c] = ring[cur][c][other];
+                    } else {
+                        const int ni = iidx(hn, t, zb);
+#pragma unroll
+                        for (int c = 0; c < 12; ++c) pz[c] = in[fidx(ni, r, c, nr)];
+                    }
 #pragma unroll
                     for (int e = 0; e < 9; ++e) uz[e] = Ui[lidx(hn, 2, e)];
                 }
@@ -822,7 +840,7 @@ __global__ void __launch_bounds__(kMaxPlane, 4) eo_plane_kernel(EoArgs a)
     }
     if constexpr (dots) {
         __syncthreads();
-        for (int i = tid; i < nr * 3; i += P) {
+        for (int i = tid; i < nr * 3; i += blockDim.x) {
             double t = 0;
             for (int k = 0; k < nw; ++k) t += red[k][i / 3][i % 3];
             a.partials[(size_t)blockIdx.x * nr * 3 + i] = t;
@@ -901,10 +919,18 @@ hipError_t launch_eo_hop(int prec, const EoArgs &a, int grid, hipStream_t st)
         if (prec != GRG_BF16 || a.SB != P || P % 64 || P > kMaxPlane || a.march < 1 || a.g.L[3] < 2 ||
             a.g.L[0] < 2 || a.Vh != P * a.g.L[2] * a.g.L[3])
             return hipErrorInvalidValue;
-        dim3 pb(P), pg(grid);
+        // RG = 2: two planes per workgroup, which needs an even number of
+        // planes in every XCD's z-slab
+        const int npl = a.RG == 2 ? 2 : 1;
+        if (npl == 2 && (a.g.L[2] % 16 || a.g.L[2] < 16)) return hipErrorInvalidValue;
+        dim3 pb(P * npl), pg(grid);
         const int epi = a.partials ? 2 : a.in2 ? 1 : a.beta == 1.0 ? 0 : 3;
         if (epi == 2 && !a.in2) return hipErrorInvalidValue;  // the sums come with the alpha term
-#define PLANE(I, E) hipLaunchKernelGGL((eo_plane_kernel<I, E>), pg, pb, 0, st, a)
+#define PLANE(I, E)                                                                \
+    do {                                                                           \
+        if (npl == 2) hipLaunchKernelGGL((eo_plane_kernel<I, E, 2>), pg, pb, 0, st, a); \
+        else hipLaunchKernelGGL((eo_plane_kernel<I, E, 1>), pg, pb, 0, st, a);    \
+    } while (0)
         if (io == 1) {
             if (epi == 2) PLANE(1, 2); else if (epi == 1) PLANE(1, 1); else return hipErrorInvalidValue;
         } else if (io == 2) {

@@ -583,12 +583,14 @@ bool eo_launch_ok(const Geom &gh, int prec, int nrhs, const DslashTune &t)
     const bool multi_ok = ((t.split == 4 || t.split == 5) && prec == GRG_BF16 && t.RG == t.split - 2) ||
                           (t.split == 6 && prec == GRG_BF16 && gh.L[0] >= 2 && 64 % (gh.L[0] / 2) == 0);
     // split 7: the plane form, one workgroup of Lx / 2 * Ly lanes per x-y plane
+    // (RG = 1 one plane per workgroup, RG = 2 two planes z, z + 1, which
+    // needs an even number of planes in every XCD's z-slab: Lz a multiple of 16)
     const int plane = (gh.L[0] / 2) * gh.L[1];
     const bool plane_ok = t.split == 7 && prec == GRG_BF16 && t.SB == plane && plane % 64 == 0 &&
-                          plane <= 512 && t.march >= 1 && t.march <= Lt && Lt >= 2;
-    if (plane_ok)
-        return t.RG >= 1 && t.RG <= nrhs && t.grid >= 8 && t.grid % 8 == 0 && t.grid <= kMaxGridValue &&
-               t.chunk >= 0;
+                          plane <= 512 && t.march >= 1 && t.march <= Lt && Lt >= 2 &&
+                          (t.RG == 1 || (t.RG == 2 && gh.L[2] % 16 == 0));
+    if (t.split == 7)
+        return plane_ok && t.grid >= 8 && t.grid % 8 == 0 && t.grid <= kMaxGridValue && t.chunk >= 0;
     return (t.SB == 64 || t.SB == 128 || t.SB == 256) && t.RG >= 1 && t.RG <= nrhs &&
            (t.split == 1 || (t.split == 2 && prec == GRG_BF16) || march_ok || multi_ok) && t.grid >= 8 &&
            t.grid % 8 == 0 && t.grid <= kMaxGridValue && t.chunk >= 0 && t.march >= 0 && gh.V > 0;
@@ -700,18 +702,20 @@ grg_status tune_eo(grg_schur S, int prec, int nrhs, int reps)
         for (int ml : {Lt, Lt / 2, Lt / 4, Lt / 8})
             if (ml >= 1 && std::find(mls.begin(), mls.end(), ml) == mls.end()) mls.push_back(ml);
         for (int ml : mls) {
-            DslashTune t = cands[0];
-            t.SB = (gh.L[0] / 2) * gh.L[1];
-            t.RG = 1;
-            t.split = 7;
-            t.march = ml;
-            t.chunk = 0;
-            const long nx = (long)((gh.L[2] + 7) / 8) * nrhs * ((Lt + ml - 1) / ml);
-            for (long div : {1, 2, 4}) {
-                t.grid = round8(std::min<long>(8 * nx / div, kMaxGridValue));
-                if (!eo_launch_ok(gh, prec, nrhs, t)) continue;
-                timeit(t);
-                if (t.ms < best.ms) best = t;
+            for (int npl : {1, 2}) {
+                DslashTune t = cands[0];
+                t.SB = (gh.L[0] / 2) * gh.L[1];
+                t.RG = npl;
+                t.split = 7;
+                t.march = ml;
+                t.chunk = 0;
+                const long nx = (long)((gh.L[2] + 7) / 8 / npl) * nrhs * ((Lt + ml - 1) / ml);
+                for (long div : {1, 2, 4}) {
+                    t.grid = round8(std::min<long>(8 * nx / div, kMaxGridValue));
+                    if (!eo_launch_ok(gh, prec, nrhs, t)) continue;
+                    timeit(t);
+                    if (t.ms < best.ms) best = t;
+                }
             }
         }
     }

@@ -104,9 +104,11 @@ def _grid_size(r) -> int:
 
 
 def _select(rows, launch, key_id="Dispatch_Id"):
-    """The last `launches` dispatches of the dominant launch."""
-    sym, gs, n = launch["symbol"], int(launch["grid_size"]), int(launch["launches"])
-    hit = [r for r in rows if sym in r["Kernel_Name"] and _grid_size(r) == gs]
+    """The last `launches` dispatches of the dominant launch (its symbol may
+    name several kernel instances joined by ' + ', launched alternately)."""
+    syms = [x.strip() for x in launch["symbol"].split(" + ")]
+    gs, n = int(launch["grid_size"]), int(launch["launches"])
+    hit = [r for r in rows if any(x in r["Kernel_Name"] for x in syms) and _grid_size(r) == gs]
     hit.sort(key=lambda r: int(r[key_id]))
     if not hit:
         raise SystemExit(f"no dispatch of {sym} with {gs} work-items")

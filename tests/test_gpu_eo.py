@@ -166,11 +166,16 @@ def test_reduced_apply_vs_oracle(form, prec, nrhs):
     ((8, 32, 4, 6), (128, 1, 7, 40, 0, 6)),     # two wavefronts per plane
     ((16, 32, 4, 4), (256, 1, 7, 16, 0, 3)),    # four, ragged time chunks
     ((32, 32, 2, 4), (512, 1, 7, 8, 0, 1)),     # eight, one slice per item
+    ((16, 8, 16, 6), (64, 2, 7, 24, 0, 4)),     # two planes per workgroup, ragged chunks
+    ((16, 16, 32, 4), (128, 2, 7, 16, 0, 2)),   # two planes of two wavefronts, two pairs per XCD
+    ((32, 32, 16, 2), (512, 2, 7, 8, 0, 1)),    # two planes of eight wavefronts (1024 lanes)
 ])
 def test_plane_form_vs_oracle(dims, launch):
     """The plane form with several wavefronts per x-y plane (y neighbours
-    across wavefronts, read from LDS after the slice's barrier), both
-    parities, with and without the alpha term, against the oracle."""
+    across wavefronts, read from LDS after the slice's barrier), and with two
+    planes per workgroup (the z hop between them read from the other plane's
+    slot), both parities, with and without the alpha term, against the
+    oracle; the two-plane form bit for bit against the one-plane form."""
     lat = Lattice(dims, 0.5, 28)
     nrhs = 3
     s = lat.schur(-0.3, "I", False, tol=1e-10, inner="bf16", max_rhs=nrhs)
@@ -183,11 +188,19 @@ def test_plane_form_vs_oracle(dims, launch):
 
     xd = to_dev(x)
     yd = torch.empty_like(xd)
+    outs = []
     for parity in (0, 1):
         print(f"plane form {dims} {launch} parity {parity}", flush=True)
         grg.grg_reduced_apply(s.h, "bf16", parity, xd, yd, nrhs)
         want = matfree.reduced_apply(lat.links, dims, -0.3, s.q, s.nb, parity, x)
-        assert rel_err(to_host(yd), want) < RA_TOL["bf16"]
+        outs.append(to_host(yd))
+        assert rel_err(outs[-1], want) < RA_TOL["bf16"]
+    if launch[1] == 2:
+        one = (launch[0], 1, 7, launch[3], launch[4], launch[5])
+        grg.grg_schur_set_launch(s.h, "bf16", nrhs, one, eo=True)
+        for parity in (0, 1):
+            grg.grg_reduced_apply(s.h, "bf16", parity, xd, yd, nrhs)
+            assert np.array_equal(to_host(yd), outs[parity]), parity
     s.close()
     lat.close()
 
@@ -231,7 +244,10 @@ def test_plane_launch_rejected_for_wrong_plane():
     half-sites, a multiple of 64."""
     lat = Lattice((16, 8, 8, 8), 0.5, 29)
     s = lat.schur(-0.1, "I", False, tol=1e-10, inner="bf16", max_rhs=2)
-    for bad in ((128, 1, 7, 8, 0, 4), (64, 1, 7, 8, 0, 0), (64, 1, 7, 12, 0, 4)):
+    # a wrong plane size, no time slices, a grid not a multiple of 8, two
+    # planes per workgroup with Lz = 8 (one plane per XCD), three planes
+    for bad in ((128, 1, 7, 8, 0, 4), (64, 1, 7, 8, 0, 0), (64, 1, 7, 12, 0, 4), (64, 2, 7, 8, 0, 4),
+                (64, 3, 7, 8, 0, 4)):
         with pytest.raises(lat.grg.GrgError):
             lat.grg.grg_schur_set_launch(s.h, "bf16", 2, bad, eo=True)
     s.close()
