@@ -313,7 +313,9 @@ grg_status grg_schur_set_launch(grg_schur s, int precision, int nrhs, const int3
  * info[2] = 1 selects the LDS-ring form of the t-marching kernel (BF16 inner
  * precision, Lx dividing 64 and a multiple of 64 sites per x-y-z slice;
  * the column's e at t - 1 and t kept in LDS, each site finished within its
- * slice), else 0.  *ms = tuned time per step, or -1 if untuned. */
+ * slice), 3 the same with the work items ordered RHS group first (the groups
+ * of a tile run together on one XCD and share its links), else 0.
+ * *ms = tuned time per step, or -1 if untuned. */
 grg_status grg_schur_dc_launch_info(grg_schur s, int precision, int nrhs, int32_t info[6],
                                     float *ms);
 /* Pin that launch; GRG_EINVAL if the shape is not valid for this lattice. */

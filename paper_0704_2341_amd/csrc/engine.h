@@ -125,6 +125,8 @@ struct DcArgs {
     double *partials;     // [grid][nrhs]: |r_out|^2
     int RG, chunk, march; // t-marching launch (march > 0), as in DslashArgs
     int ring;             // with march > 0 and BF16 e: the LDS-ring form of the t-marching step
+    int grp_first;        // ring form: work items ordered with the RHS group fastest, so the
+                          // groups of one tile run together on one XCD and share its links
 };
 
 hipError_t launch_dslash(int prec, const DslashArgs &a, int grid, hipStream_t st);

@@ -165,6 +165,7 @@ struct DcEpi {
     typedef DcArgs Args;
     static constexpr int K = 1;
     static constexpr int kThreads = 512;
+    static constexpr bool kGroupOrder = true;  // Args carries grp_first
     __device__ static const SIN *input(const Args &a) { return (const SIN *)a.e; }
     __device__ static const SU *links(const Args &a) { return (const SU *)a.U; }
     __device__ static double *partials(const Args &a) { return a.partials; }
@@ -409,8 +410,22 @@ __global__ void __launch_bounds__(512) ring_march_kernel(typename E::Args a)
     for (int j = blockIdx.x >> 3;; j += gridDim.x >> 3) {
         const int w = xcd_chunk_item(j, C, nitems);
         if (w < 0) break;
-        const int b3 = w % nb3, rest = w / nb3;
-        const int grp = rest % ngroups, tc = rest / ngroups;
+        int b3, grp, tc;
+        if (E::kGroupOrder && a.grp_first) {
+            // the RHS groups of a tile adjacent: they run together on one
+            // XCD and share the tile's links through its L2; with one
+            // contiguous eighth of the items per XCD, each XCD walks a slab
+            // of z-planes
+            grp = w % ngroups;
+            const int rest = w / ngroups;
+            b3 = rest % nb3;
+            tc = rest / nb3;
+        } else {
+            b3 = w % nb3;
+            const int rest = w / nb3;
+            grp = rest % ngroups;
+            tc = rest / ngroups;
+        }
         const int s3 = b3 * 64 + lane;
         const int r = grp * a.RG + wv;
         if (r >= a.nrhs) continue;  // whole wavefront idles

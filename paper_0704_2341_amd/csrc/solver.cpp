@@ -247,9 +247,11 @@ DslashTune default_dc_tune(const Geom &g)
 bool dc_launch_ok(const Geom &g, int prec, int nrhs, const DslashTune &t)
 {
     if (t.grid < 8 || t.grid % 8 || t.grid > kMaxGridValue || t.chunk < 0 || t.march < 0) return false;
-    if (t.split != 0 && t.split != 1) return false;
+    // split: 0 the t-marching form, 1 its LDS-ring form, 3 the ring form with
+    // the RHS groups of a tile adjacent in the item order
+    if (t.split != 0 && t.split != 1 && t.split != 3) return false;
     const int V3 = g.L[0] * g.L[1] * g.L[2];
-    if (t.split == 1 && (t.march < 1 || prec != GRG_BF16 || V3 % 64 || 64 % g.L[0])) return false;
+    if ((t.split & 1) && (t.march < 1 || prec != GRG_BF16 || V3 % 64 || 64 % g.L[0])) return false;
     if (t.march > 0) return t.march <= g.L[3] && t.RG >= 1 && t.RG <= nrhs && 64 * t.RG <= 512;
     return t.SB == 64 || t.SB == 128 || t.SB == 256;
 }
@@ -259,7 +261,8 @@ static void dc_fill_launch(DcArgs &d, const DslashTune &t)
     d.RG = t.RG;
     d.chunk = t.chunk;
     d.march = t.march;
-    d.ring = t.split == 1;
+    d.ring = (t.split & 1) != 0;
+    d.grp_first = (t.split & 2) != 0;
 }
 
 // Autotuner of the defect-correction step (inner precision prec), timed on
@@ -334,6 +337,25 @@ grg_status tune_dc(grg_schur S, int prec, int nrhs, int reps)
                 timeit(t);
                 t.split = 1;  // the LDS-ring form (where valid)
                 if (ch <= 8) timeit(t);
+                // the ring form with the RHS groups of a tile together
+                // (chunks: an eighth per XCD, or whole z-planes of tiles)
+                t.split = 3;
+                if (ch == 0 || ch == 8) timeit(t);
+            }
+            if (nrhs / rg > 1) {
+                const int plane = (g.L[0] * g.L[1] + 63) / 64 * (nrhs / rg);
+                for (int ch : {plane, 2 * plane}) {
+                    DslashTune t;
+                    t.march = T;
+                    t.SB = 64;
+                    t.RG = rg;
+                    t.chunk = ch;
+                    t.split = 3;
+                    const long items = (long)nb3 * ((g.L[3] + T - 1) / T) * (nrhs / rg);
+                    if (ch * 8 >= items) continue;
+                    t.grid = round8(std::min<long>(items, 2048));
+                    timeit(t);
+                }
             }
         }
     }

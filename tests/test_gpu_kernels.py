@@ -133,8 +133,11 @@ def test_defect_correction_every_launch(inner):
         for rg in (4, 2, 1):
             for chunk in (0, 1):
                 shapes.append(dict(SB=64, RG=rg, split=0, grid=40, chunk=chunk, march=T))
-                if inner == "bf16":  # the LDS-ring form (BF16 e only)
+                if inner == "bf16":  # the LDS-ring form (BF16 e only), also RHS group first
                     shapes.append(dict(SB=64, RG=rg, split=1, grid=40, chunk=chunk, march=T))
+                    shapes.append(dict(SB=64, RG=rg, split=3, grid=40, chunk=chunk, march=T))
+                    if chunk == 0 and rg < 4:  # whole z-planes of tiles per chunk
+                        shapes.append(dict(SB=64, RG=rg, split=3, grid=16, chunk=8 * (4 // rg), march=T))
     for shp in shapes:
         grg.grg_schur_set_dc_launch(s.h, inner, 4, shp)
         assert grg.grg_schur_dc_launch_info(s.h, inner, 4)["march"] == shp["march"]
@@ -150,8 +153,10 @@ def test_defect_correction_every_launch(inner):
         with pytest.raises(grg.GrgError):
             grg.grg_schur_set_dc_launch(s.h, inner, 4, bad)
     if inner != "bf16":
-        with pytest.raises(grg.GrgError):
-            grg.grg_schur_set_dc_launch(s.h, inner, 4, dict(SB=64, RG=1, split=1, grid=64, chunk=0, march=2))
+        for split in (1, 3):
+            with pytest.raises(grg.GrgError):
+                grg.grg_schur_set_dc_launch(s.h, inner, 4, dict(SB=64, RG=1, split=split, grid=64, chunk=0,
+                                                                 march=2))
     s.close()
     lat.close()
 
