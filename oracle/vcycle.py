@@ -15,7 +15,11 @@ through the coarse-lattice Wilson form the GPU builds it from:
 
 Solves are plain restarted GCR in numpy to a tight tolerance, so the cycle is
 the deterministic operator the GPU's cycle approaches when its own inner
-tolerances are tight.  Also `block_links` and `coarse_wilson_apply`: the
+tolerances are tight.  `two_level_cycle` (matrix-free) and `two_level_cycle_dense` take one
+level of the same cycle on the partition of any section 2 ordering, with
+section 3's S~_bb (or the exact complement) on top.
+
+Also `block_links` and `coarse_wilson_apply`: the
 coarse-lattice Wilson form, (1/d) D_W(V, d^2 - 4) with V_mu(c) = U_mu(2c)
 U_mu(2c + mu), that the pins compare with the level operator above.
 """
@@ -156,3 +160,65 @@ def cycle(lv, k, f, tol=1e-13):
     h = f - L.apply(u.reshape(-1))
     xr = L.rr_solve(h, tol)
     return L.mask(xr, True) + u.reshape(-1)
+
+
+# ---------------------------------------------------------------- two levels, any partition
+def two_level_cycle(links, dims, m0, q, nb, f, top="reusken", tol=1e-13, bc=(1, 1, 1, -1)):
+    """One two-level cycle of section 4 on the partition (q, nb) of any of
+    the section 2 orderings (Type I, II and their inverses), for one vector f
+    of 12 V entries:
+
+        y = D_rr^{-1} f_r,  g = f_b - D_br y,  x_b = S_top^{-1} g,
+        x_r = D_rr^{-1} (f_r - D_rb x_b),  x = x_r + x_b,
+
+    where the top operator S_top is the section 3 approximation S~_bb
+    ("reusken", matrix-free) or the exact Schur complement ("exact"), and
+    every solve runs GCR to tol (the cycle the GPU approaches when its own
+    tolerances are tight)."""
+    v = int(np.prod(dims))
+    q = np.asarray(q)
+    nb = int(nb)
+    coarse = q[:nb]
+    f = np.asarray(f, np.complex128).reshape(v, 12)
+    fr = f.copy()
+    fr[coarse] = 0
+    y = matfree.drr_solve(links, dims, m0, q, nb, fr.reshape(1, -1), tol=tol, bc=bc)[0][0]
+    t = matfree.block_apply(links, dims, m0, q, nb, 1, 0, y[None, :], bc)[0].reshape(v, 12)
+    g = (f - t)[coarse].reshape(-1)
+    if top == "reusken":
+        def apply(xb):
+            return matfree.reusken_apply(links, dims, m0, q, nb, xb[None, :], bc)[0]
+    elif top == "exact":
+        def apply(xb):
+            return matfree.schur_apply(links, dims, m0, q, nb, xb[None, :], tol=tol, bc=bc)[0][0]
+    else:
+        raise ValueError(f"unknown top level {top!r}")
+    xb = gcr(apply, g, tol)
+    u = np.zeros((v, 12), np.complex128)
+    u[coarse] = xb.reshape(nb, 12)
+    h = fr - matfree.block_apply(links, dims, m0, q, nb, 0, 1, u.reshape(1, -1), bc)[0].reshape(v, 12)
+    xr = matfree.drr_solve(links, dims, m0, q, nb, h.reshape(1, -1), tol=tol, bc=bc)[0][0].reshape(v, 12)
+    xr[coarse] = 0
+    return (xr + u).reshape(-1)
+
+
+def two_level_cycle_dense(d, q, nb, f, top="reusken"):
+    """The same cycle from the dense operator d (small lattices): the blocks
+    of P D P^T, S_top dense (section 3's S~_bb or the exact S_bb), every solve
+    by LU."""
+    import scipy.linalg as sla
+
+    nb = int(nb)
+    dbb, dbr, drb, drr = dense.blocks(d, q, nb)
+    s_top = dense.reusken_dense(d, q, nb) if top == "reusken" else dense.schur_dense(d, q, nb)
+    o = dense.dof_order(q)
+    f = np.asarray(f, np.complex128).reshape(-1)
+    fb, fr = f[o[: 12 * nb]], f[o[12 * nb:]]
+    lu = sla.lu_factor(drr)
+    y = sla.lu_solve(lu, fr)
+    xb = np.linalg.solve(s_top, fb - dbr @ y)
+    xr = sla.lu_solve(lu, fr - drb @ xb)
+    x = np.zeros_like(f)
+    x[o[: 12 * nb]] = xb
+    x[o[12 * nb:]] = xr
+    return x

@@ -72,3 +72,60 @@ def test_cycle_solves_the_rest_rows_exactly(links):
     assert np.linalg.norm(r[lv[0].rest]) <= 1e-11 * np.linalg.norm(f)
     # the coarse rows do not vanish: S0 is an approximation
     assert np.linalg.norm(r[~lv[0].rest]) > 1e-3 * np.linalg.norm(f)
+
+
+# ---------------------------------------------------------------- two levels on any ordering
+# Type I, II and their inverses (section 2) at kappa = 1/6 (m0 = -1), 4^4:
+# the dense operator is small enough to take every block by LU.
+PERMS = [("I", False), ("I", True), ("II", False), ("II", True)]
+DIMS4 = (4, 4, 4, 4)
+M1 = -1.0
+
+
+@pytest.fixture(scope="module")
+def small():
+    lk = su3_links(DIMS4, 0.5, 51)
+    return lk, dense.wilson_dense(lk, DIMS4, M1)
+
+
+@pytest.mark.parametrize("kind,inv", PERMS)
+def test_two_level_cycle_with_the_exact_complement_inverts_d(small, kind, inv):
+    """Exact S_bb on top: the cycle is the block LU solve of section 1, in
+    both the matrix-free and the dense form."""
+    lk, d = small
+    q, nb = dense.permutation_block(DIMS4, kind, inv)
+    f = gaussian_vectors(12 * 256, 1, 52)[0]
+    x = vcycle.two_level_cycle(lk, DIMS4, M1, q, nb, f, top="exact")
+    assert np.linalg.norm(d @ x - f) <= 1e-10 * np.linalg.norm(f)
+    xd = vcycle.two_level_cycle_dense(d, q, nb, f, top="exact")
+    assert np.linalg.norm(d @ xd - f) <= 1e-11 * np.linalg.norm(f)
+
+
+@pytest.mark.parametrize("kind,inv", PERMS)
+def test_two_level_cycle_matches_the_dense_cycle(small, kind, inv):
+    """Section 3's S~_bb on top: the matrix-free cycle (stencil blocks,
+    GCR) against the dense one (explicit blocks, LU)."""
+    lk, d = small
+    q, nb = dense.permutation_block(DIMS4, kind, inv)
+    f = gaussian_vectors(12 * 256, 1, 53)[0]
+    x = vcycle.two_level_cycle(lk, DIMS4, M1, q, nb, f)
+    xd = vcycle.two_level_cycle_dense(d, q, nb, f)
+    assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
+
+
+@pytest.mark.parametrize("kind,inv", PERMS)
+def test_two_level_cycle_residual_is_the_complement_error(small, kind, inv):
+    """With exact rest solves the residual of one cycle vanishes on the rest
+    rows, and on the coarse rows it is (S_bb - S~_bb) x_b: the error of the
+    approximation alone."""
+    lk, d = small
+    q, nb = dense.permutation_block(DIMS4, kind, inv)
+    f = gaussian_vectors(12 * 256, 1, 54)[0]
+    x = vcycle.two_level_cycle_dense(d, q, nb, f)
+    o = dense.dof_order(q)
+    r = d @ x - f
+    assert np.linalg.norm(r[o[12 * nb:]]) <= 1e-11 * np.linalg.norm(f)
+    xb = x[o[: 12 * nb]]
+    want = (dense.schur_dense(d, q, nb) - dense.reusken_dense(d, q, nb)) @ xb
+    assert np.linalg.norm(r[o[: 12 * nb]] - want) <= 1e-10 * np.linalg.norm(want)
+    assert np.linalg.norm(want) > 1e-3 * np.linalg.norm(f)  # an approximation, not the exact complement
