@@ -152,6 +152,7 @@ def learned_leg(grg, torch, args, lat, s, xb, yb, y_plain, nrhs, plain_value, pl
     diff = float(np.max(np.linalg.norm(y - y_plain, axis=1) / np.linalg.norm(y_plain, axis=1)))
     log(f"learned: {dt / k * 1e3:.1f} ms/step, {val:.1f} applies/s, iters {st['iters']} "
         f"(plain {plain_stats['iters']}), fallbacks {st['fallbacks']}")
+    args._trained_weights = w
     return {"train": {"pairs": tr["pairs"], "steps": tr["steps"], "loss_first": tr["loss_first"],
                       "loss_last": tr["loss_last"], "seconds": tr["t_ms"] / 1e3, "lattice": "16^4"},
             "value": val, "ms_per_step": dt / k * 1e3, "inner_iters": st["iters"],
@@ -188,6 +189,131 @@ def vcycle_leg(grg, torch):
         grg.grg_vcycle_destroy(v)
         grg.grg_lattice_destroy(lat)
     out["workload"] = "synthetic links eps 0.5 seed 7, m0 = -1 (kappa = 1/6), 4 Gaussian RHS, tol 1e-8, Type I at every level"
+    return out
+
+
+def stream_ceiling(torch, mib: int = 1024, reps: int = 10) -> dict:
+    """A plain streaming kernel's bandwidth on this GPU (torch's negation of
+    a 1 GiB FP32 array: reads and writes it once), the practical ceiling the
+    stencils are compared with beside the 8 TB/s peak."""
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = 2 * (mib << 20) / (ms * 1e-3) / 1e9
+    del src, dst
+    return {"kernel": "torch.neg on 1 GiB fp32 (reads + writes 1 GiB)", "GBps": gbs,
+            "frac_of_peak": gbs / PEAK_HBM_GBS}
+
+
+def stencil_table(grg, torch, lat, m0, q, nb, volume, dims, reps: int = 10) -> dict:
+    """The full masked D_rr stencil at this lattice in FP64, FP32 and BF16
+    with 1 and 12 right-hand sides, each in the launch the autotuner picks
+    for it: average time per launch (HIP events on the library's stream
+    around every stencil launch) and algorithmic GB/s."""
+    from grg_inputs import gaussian_vectors
+
+    out = {}
+    x12 = torch.from_numpy(gaussian_vectors(12 * volume, 12, 91)).to("cuda")
+    y12 = torch.empty_like(x12)
+    for prec in ("fp64", "fp32", "bf16"):
+        prm = grg.grg_solver_params_default(tol=1e-10, inner=prec, max_rhs=12)
+        s = grg.grg_schur_create(lat, m0, q, nb, prm)
+        for nrhs in (1, 12):
+            grg.grg_schur_tune(s, nrhs)
+            x, y = x12[:nrhs], y12[:nrhs]
+            grg.grg_block_apply(s, prec, 0, 0, x, y, nrhs)
+            grg.grg_profile_enable(s, True)
+            grg.grg_profile_reset(s)
+            for _ in range(reps):
+                grg.grg_block_apply(s, prec, 0, 0, x, y, nrhs)
+            torch.cuda.synchronize()
+            cnt, ms = grg.grg_profile_read(s, prec)
+            grg.grg_profile_enable(s, False)
+            avg = ms / cnt
+            alg = dslash_bytes_per_launch(prec, volume, nrhs)
+            info = grg.grg_schur_tune_info(s, prec, nrhs)
+            out[f"{prec}_nrhs{nrhs}"] = {"avg_ms": avg, "alg_bytes_per_launch": alg,
+                                        "alg_GBps": alg / (avg * 1e-3) / 1e9,
+                                        "frac_of_peak": alg / (avg * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                                        "launch": launch_descriptor(info, prec, cnt)}
+            log(f"stencil {prec} nrhs {nrhs}: {avg * 1e3:.1f} us per launch, "
+                f"{out[f'{prec}_nrhs{nrhs}']['alg_GBps']:.0f} GB/s algorithmic")
+        grg.grg_schur_destroy(s)
+    del x12, y12
+    return out
+
+
+def solver_legs(grg, torch, args, lat, m0, q, nb, xb, yb, y_ref, nrhs, tol, k):
+    """The same S_bb apply with the inner solve in FP32 (FP64 refinement to
+    tol), and in FP64 on the even-odd reduced system of D_rr: with the plain
+    FP64 leg (no reduction) they split the mixed path's gain into the
+    reduction's and the precision's."""
+    out = {}
+    for name, kw in (("fp32_mixed_reduced", dict(inner="fp32", inner_tol=1e-5, eo=1)),
+                     ("fp64_reduced", dict(inner="fp64", eo=1))):
+        prm = grg.grg_solver_params_default(tol=tol, max_rhs=nrhs, max_iter=4000, check_every=args.check_every,
+                                            **kw)
+        s2 = grg.grg_schur_create(lat, m0, q, nb, prm)
+        if not args.no_tune:
+            grg.grg_schur_tune(s2, nrhs)
+        dt2, st2, _ = time_applies(grg, s2, xb, yb, nrhs, k, 1, False)
+        y2 = yb.cpu().numpy()
+        d2 = np.linalg.norm(y2 - y_ref, axis=1) / np.linalg.norm(y_ref, axis=1)
+        out[name] = {"value": nrhs * k / dt2, "ms_per_step": dt2 / k * 1e3, "iters": st2[-1]["iters"],
+                     "outer": st2[-1]["outer"], "true_rel_resid": st2[-1]["true_rel_resid"],
+                     "max_rel_diff_vs_product": float(d2.max())}
+        log(f"{name}: {dt2 / k * 1e3:.2f} ms/step, {nrhs * k / dt2:.1f} applies/s, iters {st2[-1]['iters']} "
+            f"outer {st2[-1]['outer']}, diff {d2.max():.2e}")
+        grg.grg_schur_destroy(s2)
+    return out
+
+
+def learned_leg_24(grg, torch, args, w, nrhs=12, steps=3):
+    """The trained network at 24^4 (m0 -0.3, links seed 3, 12 point sources,
+    1e-10): the mixed solve with and without it as the right preconditioner
+    of the reduced inner solve; iterations and wall time."""
+    from grg_inputs import point_sources, su3_links
+
+    dims = (24, 24, 24, 24)
+    lat = grg.grg_lattice_create(dims, (1, 1, 1, -1))
+    grg.grg_gauge_set(lat, su3_links(dims, 0.5, 3))
+    q, nb = grg.grg_permutation_block(dims, grg.GRG_PERM_I, False)
+    xb = torch.from_numpy(point_sources(nb, nrhs)).to("cuda")
+    yb = torch.empty_like(xb)
+    prm = grg.grg_solver_params_default(tol=1e-10, inner="bf16", inner_tol=1e-2, max_rhs=nrhs, max_iter=4000)
+    s = grg.grg_schur_create(lat, -0.3, q, nb, prm)
+    if not args.no_tune:
+        grg.grg_schur_tune(s, nrhs)
+    out = {"lattice": "24^4"}
+    dt0, st0, _ = time_applies(grg, s, xb, yb, nrhs, steps, 1, False)
+    y0 = yb.cpu().numpy()
+    p = grg.grg_precond_create(s)
+    grg.grg_precond_set_weights(p, w)
+    grg.grg_schur_attach_precond(s, p)
+    dt1, st1, _ = time_applies(grg, s, xb, yb, nrhs, steps, 1, False)
+    y1 = yb.cpu().numpy()
+    grg.grg_schur_attach_precond(s, None)
+    grg.grg_precond_destroy(p)
+    out["plain"] = {"ms_per_step": dt0 / steps * 1e3, "value": nrhs * steps / dt0, "inner_iters": st0[-1]["iters"],
+                    "outer": st0[-1]["outer"], "true_rel_resid": st0[-1]["true_rel_resid"]}
+    out["learned"] = {"ms_per_step": dt1 / steps * 1e3, "value": nrhs * steps / dt1,
+                      "inner_iters": st1[-1]["iters"], "outer": st1[-1]["outer"],
+                      "fallbacks": st1[-1]["fallbacks"], "true_rel_resid": st1[-1]["true_rel_resid"],
+                      "max_rel_diff_vs_plain": float(np.max(np.linalg.norm(y1 - y0, axis=1)
+                                                            / np.linalg.norm(y0, axis=1)))}
+    log(f"24^4: plain {out['plain']['ms_per_step']:.1f} ms, {st0[-1]['iters']} inner iters; learned "
+        f"{out['learned']['ms_per_step']:.1f} ms, {st1[-1]['iters']} inner iters")
+    grg.grg_schur_destroy(s)
+    grg.grg_lattice_destroy(lat)
     return out
 
 
@@ -273,6 +399,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 48-lattice batch leg")
     ap.add_argument("--no-reusken", action="store_true", help="skip the section 3 approximation leg")
     ap.add_argument("--no-vcycle", action="store_true", help="skip the section 4 V-cycle leg")
+    ap.add_argument("--no-stencils", action="store_true",
+                    help="skip the stencil table (FP64 / FP32 / BF16 x 1 / 12 RHS) and the copy ceiling")
+    ap.add_argument("--no-solver-legs", action="store_true",
+                    help="skip the FP32-inner and FP64-reduced solver legs")
     ap.add_argument("--train-steps", type=int, default=1667, help="12-pair Adam steps (1667 = 20k pairs)")
     ap.add_argument("--eo-launch", default="", metavar="SB,RG,SPLIT,GRID,CHUNK,MARCH",
                     help="pin the half-lattice stencil's launch after tuning")
@@ -403,6 +533,11 @@ def main():
                 f"iters {stb[-1]['iters']}, diff {db.max():.2e}")
             grg.grg_schur_destroy(sbg)
 
+    solver = None
+    if not args.no_solver_legs and args.inner != "fp64":
+        solver = solver_legs(grg, torch, args, lat, m0, q, nb, xb, yb, y_mixed, nrhs, tol,
+                             args.fp64_steps or max(1, args.steps // 2))
+
     reusken = None
     if not args.no_reusken:
         # the section 3 approximation on the same workload: no solve
@@ -437,12 +572,19 @@ def main():
     learned = None
     if not args.no_learned:
         learned = learned_leg(grg, torch, args, lat, s, xb, yb, y_mixed, nrhs, value, st)
+        learned["at_24"] = learned_leg_24(grg, torch, args, args._trained_weights)
     vc = None
     if not args.no_vcycle:
         vc = vcycle_leg(grg, torch)
     batch = None
     if not args.no_batch:
         batch = batch_leg(grg, torch, args)
+
+    stencils = ceiling = None
+    if not args.no_stencils:
+        ceiling = stream_ceiling(torch)
+        log(f"copy ceiling: {ceiling['GBps']:.0f} GB/s")
+        stencils = stencil_table(grg, torch, lat, m0, q, nb, volume, dims)
 
     copy_bytes = copy_calibration(torch, args.calibrate_copy) if args.calibrate_copy else None
 
@@ -491,6 +633,9 @@ def main():
         "fp64_gcr": fp64,
         "bicgstab": bicg,
         "speedup_vs_fp64": (value / fp64["value"]) if fp64 else None,
+        "solver_legs": solver,
+        "stencils_32": stencils,
+        "copy_ceiling": ceiling,
         "reusken_approximation": reusken,
         "learned_preconditioner": learned,
         "batch_48": batch,
