@@ -34,25 +34,48 @@ __device__ __forceinline__ size_t aidx(int s, int r, int k, int nrhs, int F3)
     return ((((size_t)(s >> 6) * nrhs + r) * F3 + k) << 6) + (s & 63);
 }
 
-// neighbour of s for hop h (0 = s itself) and the site whose link it uses
-__device__ __forceinline__ void ptc_hop_site(int s, int h, const Geom &g, int &n, int &ls)
+// A lane's site and its coordinates (computed once per tile).
+struct LaneSite {
+    int s, x[4];
+};
+
+__device__ __forceinline__ LaneSite lane_site(int s, const Geom &g)
+{
+    LaneSite c;
+    c.s = s;
+    const int t1 = s / g.L[0], t2 = t1 / g.L[1];
+    c.x[0] = s - t1 * g.L[0];
+    c.x[1] = t1 - t2 * g.L[1];
+    c.x[3] = t2 / g.L[2];
+    c.x[2] = t2 - c.x[3] * g.L[2];
+    return c;
+}
+
+// An opaque copy: what is derived from the site (neighbour and link
+// addresses) is recomputed where it is used instead of being hoisted out of
+// the right-hand-side loop into registers for every task.
+__device__ __forceinline__ void opaque_site(LaneSite &c)
+{
+    asm volatile("" : "+v"(c.s), "+v"(c.x[0]), "+v"(c.x[1]), "+v"(c.x[2]), "+v"(c.x[3]));
+}
+
+// neighbour of the lane's site for hop h (0 = the site itself) and the site
+// whose link the hop uses
+__device__ __forceinline__ void ptc_hop_site(const LaneSite &c, int h, const Geom &g, int &n, int &ls)
 {
     if (h == 0) {
-        n = ls = s;
+        n = ls = c.s;
         return;
     }
     const int mu = (h - 1) >> 1;
     const bool fwd = ((h - 1) & 1) == 0;
-    const int t1 = s / g.L[0], x0 = s - t1 * g.L[0];
-    const int t2 = t1 / g.L[1], x1 = t1 - t2 * g.L[1];
-    const int x3 = t2 / g.L[2], x2 = t2 - x3 * g.L[2];
     const int L = mu == 0 ? g.L[0] : mu == 1 ? g.L[1] : mu == 2 ? g.L[2] : g.L[3];
-    const int x = mu == 0 ? x0 : mu == 1 ? x1 : mu == 2 ? x2 : x3;
+    const int x = mu == 0 ? c.x[0] : mu == 1 ? c.x[1] : mu == 2 ? c.x[2] : c.x[3];
     const int st = mu == 0 ? 1 : mu == 1 ? g.L[0] : mu == 2 ? g.L[0] * g.L[1] : g.L[0] * g.L[1] * g.L[2];
-    const int sp = x == L - 1 ? s - (L - 1) * st : s + st;
-    const int sm = x == 0 ? s + (L - 1) * st : s - st;
+    const int sp = x == L - 1 ? c.s - (L - 1) * st : c.s + st;
+    const int sm = x == 0 ? c.s + (L - 1) * st : c.s - st;
     n = fwd ? sp : sm;
-    ls = fwd ? s : sm;
+    ls = fwd ? c.s : sm;
 }
 
 // One gather task's operands: the raw link of the hop and the FH channels'
@@ -64,13 +87,10 @@ struct GatherOps {
 };
 
 template <int FIN, int FH>
-__device__ __forceinline__ void ptc_task_load(int task, int h0, const bf16x2 *__restrict__ x,
-                                              const bf16x2 *__restrict__ U, const Geom &g, int sc,
-                                              int r, int nrhs, GatherOps<FH> &o)
+__device__ __forceinline__ void ptc_task_load(int h, int f0, int n, int ls, const bf16x2 *__restrict__ x,
+                                              const bf16x2 *__restrict__ U, int r, int nrhs,
+                                              GatherOps<FH> &o)
 {
-    const int h = h0 + (task >> 1), f0 = (task & 1) * FH;
-    int n, ls;
-    ptc_hop_site(sc, h, g, n, ls);
     if (h > 0) {
         const int mu = (h - 1) >> 1;
 #pragma unroll
@@ -85,10 +105,10 @@ __device__ __forceinline__ void ptc_task_load(int task, int h0, const bf16x2 *__
 }
 
 template <int FIN, int FH, bool ROWK, int LD>
-__device__ __forceinline__ void ptc_task_store(int task, int h0, const GatherOps<FH> &o, bool valid,
+__device__ __forceinline__ void ptc_task_store(int h, int f0, const GatherOps<FH> &o, bool valid,
                                                int lane, __bf16 *lds, int kbase)
 {
-    const int h = h0 + (task >> 1), f0 = (task & 1) * FH, f1 = min(f0 + FH, FIN);
+    const int f1 = min(f0 + FH, FIN);
     const bool fwd = h > 0 && ((h - 1) & 1) == 0;
     // link forms, fr[3a + b] and fi[3a + b] for output colour a
     uint32_t fr[9], fi[9];
@@ -139,43 +159,46 @@ __device__ __forceinline__ void ptc_task_store(int task, int h0, const GatherOps
     }
 }
 
-// Phase 1: T_h X_f' for the 64 sites of a tile into LDS.  Row-major layout
-// B[row][col]: ROWK = true puts the (hop, f', re/im) index contiguous (rows =
-// (site, colour)), ROWK = false puts the (site, colour) index contiguous.
+// Phase 1: T_h X_f' for hops [H0, H1), right-hand side r, the 64 sites of a
+// tile into LDS.  Row-major layout B[row][col]: ROWK = true puts the (hop,
+// f', re/im) index contiguous (rows = (site, colour)), ROWK = false puts the
+// (site, colour) index contiguous; the (hop, f', re/im) index is stored
+// relative to kbase.
 //
 // The transports run on packed BF16 operands: each complex product of a link
 // entry m with a colour component x is two two-way BF16 dot products (exact
 // products, FP32 sums) against the forms (m.re, -m.im), (m.im, m.re) for U x
-// and (m.re, m.im), (-m.im, m.re) for U^+ x, made once per hop and shared by
-// the channels.  The work is split over the four wavefronts as (hop, half of
-// the channels) tasks, two per hop of the range [h0, h1); the (hop, f', re/im)
-// index is stored relative to kbase.  A wavefront loads its next task's
-// operands before it transports the current one, so that the memory latency
-// of its tasks overlaps.
+// and (m.re, m.im), (-m.im, m.re) for U^+ x, made once per task and shared by
+// its channels.  A wavefront loads its next slot's operands before it
+// transports the current one, so that the memory latency of its tasks
+// overlaps.
 template <int FIN, bool ROWK, int LD>
 __device__ __forceinline__ void ptc_gather(const bf16x2 *__restrict__ x, const bf16x2 *__restrict__ U,
-                                           const Geom &g, int tile, int r, int nrhs,
-                                           __bf16 *lds, int h0 = 0, int h1 = 9, int kbase = 0)
+                                           const Geom &g, const LaneSite &c, bool valid, int r, int nrhs,
+                                           __bf16 *lds, int h0, int h1, int kbase)
 {
     constexpr int FH = (FIN + 1) / 2;  // channels per task
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int s = tile * 64 + lane;
-    const bool valid = s < g.V;
-    const int sc = valid ? s : 0;
     const int ntask = 2 * (h1 - h0);
     int task = wv;
     if (task >= ntask) return;
+    auto load = [&](int t, GatherOps<FH> &o) {
+        const int h = h0 + (t >> 1);
+        int n, ls;
+        ptc_hop_site(c, h, g, n, ls);
+        ptc_task_load<FIN, FH>(h, (t & 1) * FH, n, ls, x, U, r, nrhs, o);
+    };
     GatherOps<FH> A, B;
-    ptc_task_load<FIN, FH>(task, h0, x, U, g, sc, r, nrhs, A);
+    load(task, A);
     for (;;) {
         const bool more = task + 4 < ntask;
-        if (more) ptc_task_load<FIN, FH>(task + 4, h0, x, U, g, sc, r, nrhs, B);
-        ptc_task_store<FIN, FH, ROWK, LD>(task, h0, A, valid, lane, lds, kbase);
+        if (more) load(task + 4, B);
+        ptc_task_store<FIN, FH, ROWK, LD>(h0 + (task >> 1), (task & 1) * FH, A, valid, lane, lds, kbase);
         if (!more) break;
         task += 4;
         const bool more2 = task + 4 < ntask;
-        if (more2) ptc_task_load<FIN, FH>(task + 4, h0, x, U, g, sc, r, nrhs, A);
-        ptc_task_store<FIN, FH, ROWK, LD>(task, h0, B, valid, lane, lds, kbase);
+        if (more2) load(task + 4, A);
+        ptc_task_store<FIN, FH, ROWK, LD>(h0 + (task >> 1), (task & 1) * FH, B, valid, lane, lds, kbase);
         if (!more2) break;
         task += 4;
     }
@@ -183,7 +206,7 @@ __device__ __forceinline__ void ptc_gather(const bf16x2 *__restrict__ x, const b
 
 // ------------------------------------------------------------------ layer
 template <int FIN, int FOUT>
-__global__ void __launch_bounds__(256) ptc_layer_kernel(PtcLayerArgs a)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) ptc_layer_kernel(PtcLayerArgs a)
 {
     constexpr int KR = 9 * FIN * 2;
     constexpr int KP = (KR + 31) / 32 * 32;
@@ -209,46 +232,69 @@ __global__ void __launch_bounds__(256) ptc_layer_kernel(PtcLayerArgs a)
     const bf16x2 *x = (const bf16x2 *)a.x;
     bf16x2 *y = (bf16x2 *)a.y;
     const bf16x2 *U = (const bf16x2 *)a.U;
+    // work items: (tile, group of rc right-hand sides); the sites a tile's
+    // gather reads are found once per item
     const int ntiles = (a.g.V + 63) >> 6;
-    const int nitems = ntiles * a.nrhs;
+    const int ngrp = (a.nrhs + a.rc - 1) / a.rc;
+    const int nitems = ntiles * ngrp;
     for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
-        const int tile = w / a.nrhs, r = w - tile * a.nrhs;
-        f32x4_v c[3];
+        const int tile = w / ngrp, grp = w - tile * ngrp;
+        const int r0 = grp * a.rc, r1 = min(r0 + a.rc, a.nrhs);
+        const int s = tile * 64 + lane;
+        const bool valid = s < a.g.V;
+        const LaneSite ls = lane_site(valid ? s : 0, a.g);
+        // this lane's output columns 16 t + l%16 = (site, colour), t = wv + 4 i
+        bool on[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) c[i] = {0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < 3; ++i) {
+            const int site = tile * 64 + (16 * (wv + 4 * i) + (lane & 15)) / 3;
+            on[i] = site < a.g.V && (a.mask == nullptr || a.mask[site] == a.sel);
+        }
+        for (int r = r0; r < r1; ++r) {
+            // the links are re-read for every right-hand side (L1 hits): an
+            // opaque copy of the pointer keeps the compiler from hoisting
+            // the loads, and the link forms made from them, out of this loop
+            // into registers the occupancy cannot spare
+            const bf16x2 *Ur = U;
+            asm volatile("" : "+s"(Ur));
+            LaneSite lc = ls;
+            opaque_site(lc);
+            f32x4_v c[3];
 #pragma unroll
-        for (int pass = 0; pass < 2; ++pass) {
-            __syncthreads();  // the previous products are out of LDS
-            if (pass == 0) ptc_gather<FIN, true, LD>(x, U, a.g, tile, r, a.nrhs, lds, 0, 4, 0);
-            else ptc_gather<FIN, true, LD>(x, U, a.g, tile, r, a.nrhs, lds, 4, 9, K1);
-            __syncthreads();
+            for (int i = 0; i < 3; ++i) c[i] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int pass = 0; pass < 2; ++pass) {
+                __syncthreads();  // the previous products are out of LDS
+                if (pass == 0) ptc_gather<FIN, true, LD>(x, Ur, a.g, lc, valid, r, a.nrhs, lds, 0, 4, 0);
+                else ptc_gather<FIN, true, LD>(x, Ur, a.g, lc, valid, r, a.nrhs, lds, 4, 9, K1);
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const int t = wv + 4 * i;
+                    const __bf16 *brow = lds + (16 * t + (lane & 15)) * LD + 8 * (lane >> 4);
+#pragma unroll
+                    for (int k = (pass == 0 ? 0 : NS1); k < (pass == 0 ? NS1 : NS); ++k) {
+                        const bf16x8_v bf = *(const bf16x8_v *)(brow + 32 * (k - (pass == 0 ? 0 : NS1)));
+                        const bf16x8_v af = *(const bf16x8_v *)(arow + 32 * k);
+                        c[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, c[i], 0, 0, 0);
+                    }
+                }
+            }
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 const int t = wv + 4 * i;
-                const __bf16 *brow = lds + (16 * t + (lane & 15)) * LD + 8 * (lane >> 4);
+                // rows 4 (l/16) + q = (f, re/im): two complex outputs per lane
+                const int col = 16 * t + (lane & 15);
+                const int site = tile * 64 + col / 3, colour = col % 3;
+                if (site < a.g.V) {
+                    const int f0 = 2 * (lane >> 4);
 #pragma unroll
-                for (int s = (pass == 0 ? 0 : NS1); s < (pass == 0 ? NS1 : NS); ++s) {
-                    const bf16x8_v bf = *(const bf16x8_v *)(brow + 32 * (s - (pass == 0 ? 0 : NS1)));
-                    const bf16x8_v af = *(const bf16x8_v *)(arow + 32 * s);
-                    c[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, c[i], 0, 0, 0);
-                }
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const int t = wv + 4 * i;
-            // rows 4 (l/16) + q = (f, re/im): two complex outputs per lane
-            const int col = 16 * t + (lane & 15);
-            const int site = tile * 64 + col / 3, colour = col % 3;
-            if (site < a.g.V) {
-                const bool on = a.mask == nullptr || a.mask[site] == a.sel;
-                const int f0 = 2 * (lane >> 4);
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const int f = f0 + q;
-                    if (f < FOUT) {
-                        const float re = on ? c[i][2 * q] : 0.f, im = on ? c[i][2 * q + 1] : 0.f;
-                        y[aidx(site, r, 3 * f + colour, a.nrhs, 3 * FOUT)] = pack_bf16(re, im);
+                    for (int q = 0; q < 2; ++q) {
+                        const int f = f0 + q;
+                        if (f < FOUT) {
+                            const float re = on[i] ? c[i][2 * q] : 0.f, im = on[i] ? c[i][2 * q + 1] : 0.f;
+                            y[aidx(site, r, 3 * f + colour, a.nrhs, 3 * FOUT)] = pack_bf16(re, im);
+                        }
                     }
                 }
             }
@@ -278,15 +324,22 @@ __global__ void __launch_bounds__(256) ptc_wgrad_kernel(PtcGradArgs a)
     const bf16x2 *dyg = (const bf16x2 *)a.dy;
     const bf16x2 *U = (const bf16x2 *)a.U;
     const int ntiles = (a.g.V + 63) >> 6;
-    const int nitems = ntiles * a.nrhs;
+    const int ngrp = (a.nrhs + a.rc - 1) / a.rc;
+    const int nitems = ntiles * ngrp;
     for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
-        const int tile = w / a.nrhs, r = w - tile * a.nrhs;
-        __syncthreads();
-        ptc_gather<FIN, false, LD>(x, U, a.g, tile, r, a.nrhs, tx);
-        // dY rows (g, re/im), columns (site, colour)
-        {
-            const int s = tile * 64 + lane;
-            const bool valid = s < a.g.V;
+        const int tile = w / ngrp, grp = w - tile * ngrp;
+        const int r0 = grp * a.rc, r1 = min(r0 + a.rc, a.nrhs);
+        const int s = tile * 64 + lane;
+        const bool valid = s < a.g.V;
+        const LaneSite ls = lane_site(valid ? s : 0, a.g);
+        for (int r = r0; r < r1; ++r) {
+            const bf16x2 *Ur = U;  // not hoisted (as in the layer kernel)
+            asm volatile("" : "+s"(Ur));
+            LaneSite lc = ls;
+            opaque_site(lc);
+            __syncthreads();
+            ptc_gather<FIN, false, LD>(x, Ur, a.g, lc, valid, r, a.nrhs, tx, 0, 9, 0);
+            // dY rows (g, re/im), columns (site, colour)
             for (int gch = wv; gch < FOUT; gch += 4) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -296,15 +349,16 @@ __global__ void __launch_bounds__(256) ptc_wgrad_kernel(PtcGradArgs a)
                     dy[(2 * gch + 1) * LD + lane * 3 + c] = (__bf16)v.im;
                 }
             }
-        }
-        __syncthreads();
-        int k = 0;
-        for (int t = wv; t < NT; t += 4, ++k) {
+            __syncthreads();
+            int k = 0;
+            for (int t = wv; t < NT; t += 4, ++k) {
 #pragma unroll
-            for (int s = 0; s < 6; ++s) {
-                const bf16x8_v af = *(const bf16x8_v *)(dy + (lane & 15) * LD + 32 * s + 8 * (lane >> 4));
-                const bf16x8_v bf = *(const bf16x8_v *)(tx + (16 * t + (lane & 15)) * LD + 32 * s + 8 * (lane >> 4));
-                acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, acc[k], 0, 0, 0);
+                for (int q = 0; q < 6; ++q) {
+                    const bf16x8_v af = *(const bf16x8_v *)(dy + (lane & 15) * LD + 32 * q + 8 * (lane >> 4));
+                    const bf16x8_v bf =
+                        *(const bf16x8_v *)(tx + (16 * t + (lane & 15)) * LD + 32 * q + 8 * (lane >> 4));
+                    acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, acc[k], 0, 0, 0);
+                }
             }
         }
     }
@@ -507,6 +561,47 @@ __global__ void random_field_kernel(void *out, const uint8_t *mask, Geom g, int 
 }
 
 // ------------------------------------------------------------------ launchers
+// Resident workgroups of a network kernel on the current device (cached per
+// kernel: the occupancy depends on the kernel's registers and LDS only).
+template <typename K>
+static int ptc_resident(K kernel, int slot)
+{
+    static int cache[8] = {};
+    if (cache[slot] > 0) return cache[slot];
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0) != hipSuccess || per < 1 ||
+        cus < 1)
+        return 1024;
+    cache[slot] = per * cus;
+    return cache[slot];
+}
+
+int ptc_launch_shape(int kind, int fin, int fout, const Geom &g, int nrhs, int *rc)
+{
+    int res = 1024;
+    const int slot = kind * 3 + (fin == 4 ? 0 : fout == 8 ? 1 : 2);
+    if (kind == 0) {
+        if (fin == 4) res = ptc_resident(ptc_layer_kernel<4, 8>, slot);
+        else if (fout == 8) res = ptc_resident(ptc_layer_kernel<8, 8>, slot);
+        else res = ptc_resident(ptc_layer_kernel<8, 4>, slot);
+    } else {
+        if (fin == 4) res = ptc_resident(ptc_wgrad_kernel<4, 8>, slot);
+        else if (fout == 8) res = ptc_resident(ptc_wgrad_kernel<8, 8>, slot);
+        else res = ptc_resident(ptc_wgrad_kernel<8, 4>, slot);
+    }
+    res = std::max(1, std::min(res, kPtcMaxGrid));
+    const long ntiles = (g.V + 63) / 64;
+    // RHS groups: enough work items for about four per workgroup
+    const long want = 4L * res;
+    const int ngrp = (int)std::max(1L, std::min<long>(nrhs, (want + ntiles - 1) / ntiles));
+    const int r = (nrhs + ngrp - 1) / ngrp;
+    *rc = std::max(1, r);
+    const long items = ntiles * ((nrhs + *rc - 1) / *rc);
+    return (int)std::max(1L, std::min<long>(items, res));
+}
+
 hipError_t launch_ptc_layer(int fin, int fout, const PtcLayerArgs &a, int grid, hipStream_t st)
 {
     dim3 g(grid), b(256);

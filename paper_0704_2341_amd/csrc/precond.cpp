@@ -28,12 +28,6 @@ grg_status eo_training_pair(grg_schur S, void *e, void *r_full, int nrhs, int k,
 
 static const int kOff[3] = {0, 9 * 8 * 4, 9 * 8 * 4 + 9 * 8 * 8};
 
-static int layer_grid(const Geom &g, int nrhs)
-{
-    const long items = (long)((g.V + 63) / 64) * nrhs;
-    return (int)std::max<long>(1, std::min<long>(items, 1024));
-}
-
 static size_t act_bytes(const Geom &g, int nrhs, int F) { return (size_t)nrhs * 3 * F * g.Vs * 4; }
 
 static grg_status embed_all(grg_precond P)
@@ -54,10 +48,10 @@ static grg_status forward(grg_precond P, const void *in, void *out, int nrhs,
 {
     grg_schur S = P->schur;
     grg_lattice L = S->lat;
-    const int grid = layer_grid(L->g, nrhs);
     const void *x = in;
     for (int l = 0; l < 3; ++l) {
         PtcLayerArgs a;
+        const int grid = ptc_launch_shape(0, kPtcChannels[l], kPtcChannels[l + 1], L->g, nrhs, &a.rc);
         a.x = x;
         a.y = l == 2 ? out : P->act[l + 1];
         a.U = L->U[GRG_BF16];
@@ -78,10 +72,10 @@ static grg_status backward(grg_precond P, const void *act0, int nrhs)
 {
     grg_schur S = P->schur;
     grg_lattice L = S->lat;
-    const int grid = layer_grid(L->g, nrhs);
     for (int l = 2; l >= 0; --l) {
         const int fin = kPtcChannels[l], fout = kPtcChannels[l + 1];
         PtcGradArgs ga;
+        const int grid = ptc_launch_shape(1, fin, fout, L->g, nrhs, &ga.rc);
         ga.x = l == 0 ? act0 : P->act[l];
         ga.dy = P->dact[l + 1];
         ga.U = L->U[GRG_BF16];
@@ -100,7 +94,8 @@ static grg_status backward(grg_precond P, const void *act0, int nrhs)
             a.sel = 0;
             a.g = L->g;
             a.nrhs = nrhs;
-            GRG_TRY_HIP(launch_ptc_layer(fout, fin, a, grid, L->stream));
+            const int lgrid = ptc_launch_shape(0, fout, fin, L->g, nrhs, &a.rc);
+            GRG_TRY_HIP(launch_ptc_layer(fout, fin, a, lgrid, L->stream));
         }
     }
     return GRG_OK;
@@ -209,7 +204,6 @@ grg_status grg_precond_create(grg_schur S, grg_precond *out)
     P->max_rhs = S->prm.max_rhs;
     const Geom &g = S->lat->g;
     const int R = P->max_rhs;
-    const int grid = layer_grid(g, R);
     bool ok = true;
     auto al = [&](void **p, size_t bytes) {
         if (ok && hipMalloc(p, bytes) != hipSuccess) {
@@ -231,7 +225,7 @@ grg_status grg_precond_create(grg_schur S, grg_precond *out)
     }
     al(&P->ebuf, act_bytes(g, R, 4));
     for (int k = 0; k < 3; ++k) al(&P->gen[k], act_bytes(g, R, 4));
-    al((void **)&P->wpart, sizeof(float) * (size_t)grid * 16 * ptc_np(8));
+    al((void **)&P->wpart, sizeof(float) * (size_t)kPtcMaxGrid * 16 * ptc_np(8));
     al((void **)&P->lpart, sizeof(double) * 1024 * kMaxRhs * 2);
     al((void **)&P->lsums, sizeof(double) * kMaxRhs * 2);
     al((void **)&P->loss, sizeof(double) * 2);

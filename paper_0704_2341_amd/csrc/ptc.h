@@ -23,6 +23,7 @@ struct PtcLayerArgs {
     int sel;
     Geom g;
     int nrhs;
+    int rc;  // right-hand sides per work item (ptc_launch_shape)
 };
 
 struct PtcGradArgs {
@@ -31,9 +32,18 @@ struct PtcGradArgs {
     const void *U;
     Geom g;
     int nrhs;
+    int rc;           // right-hand sides per work item (ptc_launch_shape)
     float *partials;  // [grid][16][NP]
 };
 
+// Largest grid of the layer and weight-gradient kernels (sizes the partials).
+constexpr int kPtcMaxGrid = 1024;
+// Grid of a layer (kind 0) or weight-gradient (kind 1) launch and, in *rc, the
+// right-hand sides each work item takes: as many workgroups as the device
+// holds at once (at most kPtcMaxGrid, at most one per work item) and all
+// right-hand sides per tile unless the tiles alone give a workgroup fewer
+// than about four items.
+int ptc_launch_shape(int kind, int fin, int fout, const Geom &g, int nrhs, int *rc);
 hipError_t launch_ptc_layer(int fin, int fout, const PtcLayerArgs &a, int grid, hipStream_t st);
 hipError_t launch_ptc_wgrad(int fin, int fout, const PtcGradArgs &a, int grid, hipStream_t st);
 hipError_t launch_ptc_wgrad_reduce(int fin, int fout, const float *partials, int nparts,
