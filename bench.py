@@ -164,31 +164,38 @@ def learned_leg(grg, torch, args, lat, s, xb, yb, y_plain, nrhs, plain_value, pl
 def vcycle_leg(grg, torch):
     """Section 4's experiment on synthetic fields: D x = f to 1e-8 at
     kappa = 1/6 (m0 = -1) by BiCGstab, plain and right-preconditioned by the
-    3-level cyclic-reduction V-cycle (A_rr solves by BiCGstab to 1e-2, top
-    level to 1e-12); average convergence rate R per solve."""
+    3-level cyclic-reduction V-cycle (Type I at every level) and by the
+    two-level cycles on the orderings of Table 1 (Type I^-1 and II^-1, with
+    section 3's S~_bb on top); A_rr solves by BiCGstab to 1e-2, top level to
+    1e-12; average convergence rate R per solve."""
     from grg_inputs import gaussian_vectors, su3_links
 
     out = {}
+    cycles = (("vcycle_bicgstab", dict(levels=3)),
+              ("two_level_I_inv_bicgstab", dict(levels=2, perm=1, inverse=1)),
+              ("two_level_II_inv_bicgstab", dict(levels=2, perm=2, inverse=1)))
     for dims in ((8, 8, 8, 8), (16, 16, 16, 16)):
         lat = grg.grg_lattice_create(dims)
         grg.grg_gauge_set(lat, su3_links(dims, 0.5, 7))
-        v = grg.grg_vcycle_create(lat, -1.0, grg.grg_vcycle_params_default(levels=3, max_rhs=4))
         V = int(np.prod(dims))
         f = torch.from_numpy(gaussian_vectors(12 * V, 4, 7)).to("cuda")
         x = torch.empty_like(f)
         row = {}
-        for name, pre in (("bicgstab", False), ("vcycle_bicgstab", True)):
-            st = grg.grg_vcycle_solve(v, f, x, 4, tol=1e-8, precondition=pre)
-            row[name] = {"iters": st["iters"], "rate": st["rate"], "ms": st["t_ms"],
-                         "true_rel_resid": st["true_rel_resid"], "cycles": st["cycles"]}
+        for name, kw in cycles:
+            v = grg.grg_vcycle_create(lat, -1.0, grg.grg_vcycle_params_default(max_rhs=4, **kw))
+            runs = (("bicgstab", False), (name, True)) if name == "vcycle_bicgstab" else ((name, True),)
+            for key, pre in runs:
+                st = grg.grg_vcycle_solve(v, f, x, 4, tol=1e-8, precondition=pre)
+                row[key] = {"iters": st["iters"], "rate": st["rate"], "ms": st["t_ms"],
+                            "true_rel_resid": st["true_rel_resid"], "cycles": st["cycles"]}
+            grg.grg_vcycle_destroy(v)
         key = "x".join(map(str, dims))
         out[key] = row
-        log(f"V-cycle {key}, m0 -1: BiCGstab {row['bicgstab']['iters']} iters, R {row['bicgstab']['rate']:.3f}, "
-            f"{row['bicgstab']['ms']:.1f} ms; preconditioned {row['vcycle_bicgstab']['iters']} iters, "
-            f"R {row['vcycle_bicgstab']['rate']:.3f}, {row['vcycle_bicgstab']['ms']:.1f} ms")
-        grg.grg_vcycle_destroy(v)
+        log(f"V-cycle {key}, m0 -1: " + "; ".join(
+            f"{k} {r['iters']} iters, R {r['rate']:.3f}, {r['ms']:.1f} ms" for k, r in row.items()))
         grg.grg_lattice_destroy(lat)
-    out["workload"] = "synthetic links eps 0.5 seed 7, m0 = -1 (kappa = 1/6), 4 Gaussian RHS, tol 1e-8, Type I at every level"
+    out["workload"] = ("synthetic links eps 0.5 seed 7, m0 = -1 (kappa = 1/6), 4 Gaussian RHS, tol 1e-8; "
+                       "3-level Type I cycle, and two-level cycles on Type I^-1 and II^-1")
     return out
 
 

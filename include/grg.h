@@ -354,8 +354,13 @@ grg_status grg_reduced_apply(grg_schur s, int precision, int parity, const doubl
  * y = A_rr^{-1} f_r, g = f_b - A_br y, x_b = cycle(k + 1, g),
  * x_r = A_rr^{-1}(f_r - A_rb x_b), with the A_rr solves by BiCGstab to
  * drr_tol (section 4 used one percent) and the top level solved to top_tol
- * ("inverted exactly").  The paper's runs used the inverse permutations,
- * whose recursion it does not state; this cycle uses Type I at every level. */
+ * ("inverted exactly").  With perm = GRG_PERM_I and inverse = 0 the cycle uses
+ * Type I at every level (2 or 3 levels).  Any other ordering of section 2
+ * (Type II, or the inverse permutations section 4's runs used, whose
+ * recursion to further levels the paper does not state) gives a two-level
+ * cycle: the partition of that ordering on the lattice, and on top the
+ * section 3 approximation S~_bb of its Schur complement (grg_reusken_apply,
+ * matrix-free) solved by BiCGstab to top_tol. */
 typedef struct grg_vcycle_s *grg_vcycle;
 
 typedef struct {
@@ -364,6 +369,9 @@ typedef struct {
     double top_tol;    /* relative accuracy of the top level's solve (default 1e-12) */
     int max_rhs;       /* largest nrhs per call (default 12, <= 16) */
     int max_iter;      /* cap on the iterations of each BiCGstab solve (default 10000) */
+    int perm;          /* ordering of the partition: GRG_PERM_I (default) or GRG_PERM_II */
+    int inverse;       /* nonzero: the inverse permutation of that type (default 0); any
+                          ordering but Type I needs levels = 2 */
 } grg_vcycle_params;
 
 typedef struct {
@@ -380,8 +388,11 @@ typedef struct {
 grg_status grg_vcycle_params_default(grg_vcycle_params *p);
 /* Build the hierarchy on lat (gauge field set) for mass m0: the coarse
  * lattices, their blocked links and masses m_{k+1} = (4 + m_k)^2 - 4 with
- * the scale of each level.  GRG_EINVAL if an extent is not divisible by
- * 2^levels or 4 + m0 = 0.  lat must outlive the handle. */
+ * the scale of each level (Type I), or the partition and its D_rr solver
+ * (other orderings).  GRG_EINVAL if an extent is not divisible by 2^levels
+ * (Type I; other orderings: by 2), if levels is not 2 for an ordering other
+ * than Type I, for an unknown perm, or if 4 + m0 = 0.  lat must outlive the
+ * handle. */
 grg_status grg_vcycle_create(grg_lattice lat, double m0, const grg_vcycle_params *params,
                              grg_vcycle *out);
 grg_status grg_vcycle_destroy(grg_vcycle v);

@@ -81,7 +81,7 @@ class grg_solver_stats(C.Structure):
 
 class grg_vcycle_params(C.Structure):
     _fields_ = [("levels", C.c_int), ("drr_tol", C.c_double), ("top_tol", C.c_double),
-                ("max_rhs", C.c_int), ("max_iter", C.c_int)]
+                ("max_rhs", C.c_int), ("max_iter", C.c_int), ("perm", C.c_int), ("inverse", C.c_int)]
 
 
 class grg_vcycle_stats(C.Structure):

@@ -12,6 +12,12 @@
 // handle of its own with blocked links, m_{k+1} = d_k^2 - 4 and
 // c_{k+1} = c_k / d_k, and the A_rr solves of level k are the D_rr solves of a
 // Type I coarse-operator handle on lattice k (BiCGstab, FP64, to drr_tol).
+//
+// Any other ordering of section 2 (Type II, the inverse permutations) gives
+// a two-level cycle: level 0 is partitioned by that ordering, and the top
+// level is the section 3 approximation S~_bb of its Schur complement on the
+// coarse sites (matrix-free through the level-0 handle, in the handle's
+// coarse-field layout [nrhs][N_b][12]), solved by BiCGstab to top_tol.
 #include <math.h>
 #include <string.h>
 
@@ -24,6 +30,7 @@
 struct grg_vcycle_s {
     grg_vcycle_params prm;
     int levels = 0;
+    bool approx_top = false;  // the top level is S~_bb of level 0's partition (no lattice)
     grg_lattice lat[3] = {nullptr, nullptr, nullptr};  // lat[0] is the caller's
     grg_schur schur[3] = {nullptr, nullptr, nullptr};  // levels below the top
     double m[3] = {0, 0, 0}, c[3] = {1, 1, 1};
@@ -98,6 +105,7 @@ grg_status dots(grg_vcycle_s *v, int k, int nrhs, const double *a, const double 
 // out = A_k in
 grg_status apply_level(grg_vcycle_s *v, int k, int nrhs, const double *in, double *out)
 {
+    if (k > 0 && v->approx_top) return grg_reusken_apply(v->schur[0], in, out, nrhs);
     GRG_TRY(grg_dirac_apply(v->lat[k], v->m[k], GRG_FP64, in, out, nrhs));
     if (v->c[k] != 1.0) {
         double2 s[kMaxRhs];
@@ -294,6 +302,8 @@ grg_status grg_vcycle_params_default(grg_vcycle_params *p)
     p->top_tol = 1e-12;
     p->max_rhs = 12;
     p->max_iter = 10000;
+    p->perm = GRG_PERM_I;
+    p->inverse = 0;
     return GRG_OK;
 }
 
@@ -309,9 +319,15 @@ grg_status grg_vcycle_create(grg_lattice L, double m0, const grg_vcycle_params *
         return set_error("tolerances must be in (0, 1)"), GRG_EINVAL;
     if (p.max_rhs < 1 || p.max_rhs > kMaxRhs) return set_error("max_rhs must be in 1..%d", kMaxRhs), GRG_EINVAL;
     if (p.max_iter < 1) return set_error("max_iter must be positive"), GRG_EINVAL;
+    if (p.perm != GRG_PERM_I && p.perm != GRG_PERM_II) return set_error("unknown perm %d", p.perm), GRG_EINVAL;
+    const bool approx_top = !(p.perm == GRG_PERM_I && p.inverse == 0);
+    if (approx_top && p.levels != 2)
+        return set_error("an ordering other than Type I gives a two-level cycle: levels must be 2"), GRG_EINVAL;
     if (!L->gauge_set) return set_error("gauge field not set"), GRG_EINVAL;
     if (!isfinite(m0) || 4.0 + m0 == 0.0) return set_error("4 + m0 must be finite and nonzero"), GRG_EINVAL;
-    const int div = 1 << p.levels;  // every level even below the top, the top at least 2 wide
+    // Type I: every level even below the top, the top at least 2 wide;
+    // otherwise the partition needs even extents
+    const int div = approx_top ? 2 : 1 << p.levels;
     for (int mu = 0; mu < 4; ++mu)
         if (L->g.L[mu] % div)
             return set_error("extent %d of direction %d is not divisible by %d", L->g.L[mu], mu, div), GRG_EINVAL;
@@ -320,6 +336,7 @@ grg_status grg_vcycle_create(grg_lattice L, double m0, const grg_vcycle_params *
     if (!v) return set_error("out of host memory"), GRG_ENOMEM;
     v->prm = p;
     v->levels = p.levels;
+    v->approx_top = approx_top;
     v->lat[0] = L;
     v->m[0] = m0;
     v->c[0] = 1.0;
@@ -341,10 +358,12 @@ grg_status grg_vcycle_create(grg_lattice L, double m0, const grg_vcycle_params *
     for (int k = 0; k < p.levels; ++k) {
         v->V[k] = dims[0] * dims[1] * dims[2] * dims[3];
         if (k + 1 < p.levels) {
-            // this level's Type I partition and its D_rr solves
+            // this level's partition and its D_rr solves
             std::vector<int32_t> q(v->V[k]);
             int32_t nb = 0;
-            if ((s = grg_permutation_block(dims, GRG_PERM_I, 0, q.data(), &nb)) != GRG_OK) return fail(s);
+            if ((s = grg_permutation_block(dims, k == 0 ? p.perm : GRG_PERM_I, k == 0 ? p.inverse : 0, q.data(),
+                                           &nb)) != GRG_OK)
+                return fail(s);
             v->nb[k] = nb;
             grg_solver_params sp;
             grg_solver_params_default(&sp);
@@ -359,26 +378,32 @@ grg_status grg_vcycle_create(grg_lattice L, double m0, const grg_vcycle_params *
             if (!alloc((void **)&v->d_q[k], sizeof(int32_t) * nb)) return fail(GRG_ENOMEM);
             if (hipMemcpy(v->d_q[k], q.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice) != hipSuccess)
                 return set_error("V-cycle: copy of the coarse sites failed"), fail(GRG_EHIP);
-            // the next level: the coarse lattice, its blocked links and mass
-            int cd[4] = {dims[0] / 2, dims[1] / 2, dims[2] / 2, dims[3] / 2};
-            const int32_t periodic[4] = {1, 1, 1, 1};  // the signs ride in the blocked links
-            if ((s = grg_lattice_create(cd, periodic, L->stream, &v->lat[k + 1])) != GRG_OK) return fail(s);
-            double *links = nullptr;
-            const size_t lb = (size_t)nb * 4 * 9 * 16;
-            if (!alloc((void **)&links, lb)) return fail(GRG_ENOMEM);
-            if (launch_vc_block_links(v->lat[k]->g, v->lat[k]->U[GRG_FP64], v->lat[k + 1]->g, links, L->stream) !=
-                    hipSuccess ||
-                hipStreamSynchronize(L->stream) != hipSuccess) {
+            if (approx_top) {
+                // the top level: the N_b coarse sites, no lattice of their own
+                dims[0] = nb;
+                dims[1] = dims[2] = dims[3] = 1;
+            } else {
+                // the next level: the coarse lattice, its blocked links and mass
+                int cd[4] = {dims[0] / 2, dims[1] / 2, dims[2] / 2, dims[3] / 2};
+                const int32_t periodic[4] = {1, 1, 1, 1};  // the signs ride in the blocked links
+                if ((s = grg_lattice_create(cd, periodic, L->stream, &v->lat[k + 1])) != GRG_OK) return fail(s);
+                double *links = nullptr;
+                const size_t lb = (size_t)nb * 4 * 9 * 16;
+                if (!alloc((void **)&links, lb)) return fail(GRG_ENOMEM);
+                if (launch_vc_block_links(v->lat[k]->g, v->lat[k]->U[GRG_FP64], v->lat[k + 1]->g, links, L->stream) !=
+                        hipSuccess ||
+                    hipStreamSynchronize(L->stream) != hipSuccess) {
+                    (void)hipFree(links);
+                    return set_error("V-cycle: link blocking failed"), fail(GRG_EHIP);
+                }
+                s = grg_gauge_set(v->lat[k + 1], links, 1);
                 (void)hipFree(links);
-                return set_error("V-cycle: link blocking failed"), fail(GRG_EHIP);
+                if (s != GRG_OK) return fail(s);
+                const double d = 4.0 + v->m[k];
+                v->m[k + 1] = d * d - 4.0;
+                v->c[k + 1] = v->c[k] / d;
+                for (int mu = 0; mu < 4; ++mu) dims[mu] = cd[mu];
             }
-            s = grg_gauge_set(v->lat[k + 1], links, 1);
-            (void)hipFree(links);
-            if (s != GRG_OK) return fail(s);
-            const double d = 4.0 + v->m[k];
-            v->m[k + 1] = d * d - 4.0;
-            v->c[k + 1] = v->c[k] / d;
-            for (int mu = 0; mu < 4; ++mu) dims[mu] = cd[mu];
         }
         void **f[5] = {(void **)&v->fin[k], (void **)&v->xout[k], (void **)&v->t0[k], (void **)&v->t1[k],
                        (void **)&v->t2[k]};

@@ -75,3 +75,65 @@ def test_invalid_parameters(lat):
     with pytest.raises(grg.GrgError):  # 6 is not divisible by 2^3
         grg.grg_vcycle_create(odd.h, M0, grg.grg_vcycle_params_default(levels=3))
     odd.close()
+
+
+# ---------------------------------------------------------------- two levels on the other orderings
+# Type II and the inverse permutations (section 4's runs used Type I^-1 and
+# II^-1): section 3's S~_bb on top, at kappa = 1/6 (m0 = -1).
+ORDERINGS = [("I", 1, True), ("II", 2, False), ("II", 2, True)]
+M1 = -1.0
+
+
+@pytest.mark.parametrize("name,perm,inv", ORDERINGS)
+def test_two_level_cycle_vs_oracle(lat, name, perm, inv):
+    import torch
+
+    from oracle import dense
+
+    grg = lat.grg
+    prm = grg.grg_vcycle_params_default(levels=2, drr_tol=1e-12, top_tol=1e-13, max_rhs=2, perm=perm,
+                                        inverse=int(inv))
+    v = grg.grg_vcycle_create(lat.h, M1, prm)
+    f = gaussian_vectors(12 * lat.V, 2, 48)
+    fd = to_dev(f)
+    xd = torch.empty_like(fd)
+    print(f"two-level cycle, Type {name}{'^-1' if inv else ''}, 8^4", flush=True)
+    grg.grg_vcycle_apply(v, fd, xd, 2)
+    x = to_host(xd)
+    q, nb = dense.permutation_block(DIMS, name, inv)
+    for r in range(2):
+        want = vcycle.two_level_cycle(lat.links, DIMS, M1, q, nb, f[r], top="reusken", tol=1e-13)
+        assert rel_err(x[r], want) < 1e-9
+    grg.grg_vcycle_destroy(v)
+
+
+@pytest.mark.parametrize("name,perm,inv", ORDERINGS)
+def test_two_level_preconditioned_solve(lat, name, perm, inv):
+    import torch
+
+    grg = lat.grg
+    v = grg.grg_vcycle_create(lat.h, M1, grg.grg_vcycle_params_default(levels=2, max_rhs=2, perm=perm,
+                                                                       inverse=int(inv)))
+    f = gaussian_vectors(12 * lat.V, 2, 49)
+    fd = to_dev(f)
+    xd = torch.empty_like(fd)
+    print(f"two-level preconditioned BiCGstab, Type {name}{'^-1' if inv else ''}, 8^4", flush=True)
+    st = grg.grg_vcycle_solve(v, fd, xd, 2, tol=1e-8, precondition=True)
+    x0 = torch.empty_like(fd)
+    st0 = grg.grg_vcycle_solve(v, fd, x0, 2, tol=1e-8, precondition=False)
+    print(f"preconditioned: {st}\nplain: {st0}", flush=True)
+    assert st["converged"] and st["true_rel_resid"] <= 1e-8 * 1.01
+    assert st["rate"] < st0["rate"] and st["iters"] < st0["iters"]
+    r = matfree.dirac_apply(lat.links, DIMS, M1, to_host(xd)) - f
+    assert np.all(np.linalg.norm(r, axis=1) <= 1.01e-8 * np.linalg.norm(f, axis=1))
+    grg.grg_vcycle_destroy(v)
+
+
+def test_two_level_invalid_parameters(lat):
+    grg = lat.grg
+    with pytest.raises(grg.GrgError):  # a two-level cycle only
+        grg.grg_vcycle_create(lat.h, M1, grg.grg_vcycle_params_default(levels=3, perm=2))
+    with pytest.raises(grg.GrgError):
+        grg.grg_vcycle_create(lat.h, M1, grg.grg_vcycle_params_default(levels=2, perm=3))
+    with pytest.raises(grg.GrgError):
+        grg.grg_vcycle_create(lat.h, M1, grg.grg_vcycle_params_default(levels=3, perm=1, inverse=1))
