@@ -71,18 +71,22 @@ def launch_descriptor(info: dict, prec: str, launches: int, eo: bool = False) ->
     p = PREC_ID[prec]
     if eo and info["split"] == 7:
         # the plane form of the reduced operator's half-stencil (compact
-        # fields: IO 0), one workgroup of SB lanes per x-y plane; the first
-        # half of each operator application has no alpha term (epilogue 0),
-        # the second the alpha term and the fused sums (epilogue 2)
-        sym, gs = "eo_plane_kernel<0, 0> + eo_plane_kernel<0, 2>", info["grid"] * info["SB"]
+        # fields: IO 0), one workgroup of SB lanes per x-y plane, RG planes
+        # per workgroup; the first half of each operator application has no
+        # alpha term (epilogue 0), the second the alpha term and the fused
+        # sums (epilogue 2)
+        npl = info["RG"]
+        sym = f"eo_plane_kernel<0, 0, {npl}> + eo_plane_kernel<0, 2, {npl}>"
+        gs = info["grid"] * info["SB"]
     elif eo:
         # the compact half-stencils of the reduced operator in the tuned form
         # (hop schedule info["split"], compact fields: IO 0)
         sym, gs = f"eo_hop_kernel<{p}, {info['split']}, 0>", info["grid"] * info["SB"]
     elif info["march"] > 0:
-        sym, gs = f"dslash_march_kernel<{p}>", info["grid"] * 64 * info["RG"]
+        # t-marching form: one wavefront per RHS of a group of RG
+        sym, gs = f"march_kernel<grg::StoreEpi<{p}> >", info["grid"] * 64 * info["RG"]
     else:
-        sym, gs = f"dslash_kernel<{p}, {'true' if info['split'] else 'false'}>", info["grid"] * info["SB"]
+        sym, gs = f"dslash_kernel<{p}, {info['split']}>", info["grid"] * info["SB"]
     shape = {k: info[k] for k in ("SB", "RG", "split", "grid", "chunk", "march")}
     return {"symbol": sym, "grid_size": gs, "launches": launches, "shape": shape}
 
@@ -221,21 +225,42 @@ def stream_ceiling(torch, mib: int = 1024, reps: int = 10) -> dict:
             "frac_of_peak": gbs / PEAK_HBM_GBS}
 
 
-def stencil_table(grg, torch, lat, m0, q, nb, volume, dims, reps: int = 10) -> dict:
+def parse_stencil_launches(spec: str) -> dict:
+    """'fp64_nrhs1=SB,RG,SPLIT,GRID,CHUNK,MARCH;...' -> {row: [6 ints]}."""
+    out = {}
+    for item in filter(None, (x.strip() for x in spec.split(";"))):
+        name, vals = item.split("=")
+        out[name.strip()] = [int(v) for v in vals.split(",")]
+    return out
+
+
+def stencil_table(grg, torch, lat, m0, q, nb, volume, dims, reps: int = 10, pin: dict | None = None):
     """The full masked D_rr stencil at this lattice in FP64, FP32 and BF16
     with 1 and 12 right-hand sides, each in the launch the autotuner picks
     for it: average time per launch (HIP events on the library's stream
-    around every stencil launch) and algorithmic GB/s."""
+    around every stencil launch) and algorithmic GB/s.  Every launch is tuned
+    first, then the copy ceiling runs, then the timed launches in table
+    order, so that a counter run finds each row's launches in sequence after
+    the copy's.  Returns (table, ceiling)."""
     from grg_inputs import gaussian_vectors
 
     out = {}
     x12 = torch.from_numpy(gaussian_vectors(12 * volume, 12, 91)).to("cuda")
     y12 = torch.empty_like(x12)
+    handles = {}
     for prec in ("fp64", "fp32", "bf16"):
         prm = grg.grg_solver_params_default(tol=1e-10, inner=prec, max_rhs=12)
-        s = grg.grg_schur_create(lat, m0, q, nb, prm)
+        handles[prec] = grg.grg_schur_create(lat, m0, q, nb, prm)
         for nrhs in (1, 12):
-            grg.grg_schur_tune(s, nrhs)
+            grg.grg_schur_tune(handles[prec], nrhs)
+            row = f"{prec}_nrhs{nrhs}"
+            if pin and row in pin:
+                grg.grg_schur_set_launch(handles[prec], prec, nrhs, pin[row])
+    torch.cuda.synchronize()
+    ceiling = stream_ceiling(torch)
+    log(f"copy ceiling: {ceiling['GBps']:.0f} GB/s")
+    for prec, s in handles.items():
+        for nrhs in (1, 12):
             x, y = x12[:nrhs], y12[:nrhs]
             grg.grg_block_apply(s, prec, 0, 0, x, y, nrhs)
             grg.grg_profile_enable(s, True)
@@ -254,9 +279,10 @@ def stencil_table(grg, torch, lat, m0, q, nb, volume, dims, reps: int = 10) -> d
                                         "launch": launch_descriptor(info, prec, cnt)}
             log(f"stencil {prec} nrhs {nrhs}: {avg * 1e3:.1f} us per launch, "
                 f"{out[f'{prec}_nrhs{nrhs}']['alg_GBps']:.0f} GB/s algorithmic")
+    for s in handles.values():
         grg.grg_schur_destroy(s)
     del x12, y12
-    return out
+    return out, ceiling
 
 
 def solver_legs(grg, torch, args, lat, m0, q, nb, xb, yb, y_ref, nrhs, tol, k):
@@ -408,6 +434,8 @@ def main():
     ap.add_argument("--no-vcycle", action="store_true", help="skip the section 4 V-cycle leg")
     ap.add_argument("--no-stencils", action="store_true",
                     help="skip the stencil table (FP64 / FP32 / BF16 x 1 / 12 RHS) and the copy ceiling")
+    ap.add_argument("--stencil-launches", default="", metavar="ROW=SB,RG,SPLIT,GRID,CHUNK,MARCH;...",
+                    help="pin launches of the stencil table after tuning (rows fp64_nrhs1 ... bf16_nrhs12)")
     ap.add_argument("--no-solver-legs", action="store_true",
                     help="skip the FP32-inner and FP64-reduced solver legs")
     ap.add_argument("--train-steps", type=int, default=1667, help="12-pair Adam steps (1667 = 20k pairs)")
@@ -589,9 +617,8 @@ def main():
 
     stencils = ceiling = None
     if not args.no_stencils:
-        ceiling = stream_ceiling(torch)
-        log(f"copy ceiling: {ceiling['GBps']:.0f} GB/s")
-        stencils = stencil_table(grg, torch, lat, m0, q, nb, volume, dims)
+        stencils, ceiling = stencil_table(grg, torch, lat, m0, q, nb, volume, dims,
+                                          pin=parse_stencil_launches(args.stencil_launches))
 
     copy_bytes = copy_calibration(torch, args.calibrate_copy) if args.calibrate_copy else None
 

@@ -10,6 +10,7 @@ Runs on the host, on CSV files that ``rocprofv3 --output-format csv`` wrote:
            (FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch), each scaled by
            what the same counter reads for a plain copy kernel of known size
            run in the same process
+  stencil-table  the same for every launch of the benchmark's stencil table
 
     python -m paper_0704_2341_amd.profiling stats --trace DIR --bench-log LOG --command CMD
     python -m paper_0704_2341_amd.profiling traffic --fetch DIR --write DIR \
@@ -111,7 +112,7 @@ def _select(rows, launch, key_id="Dispatch_Id"):
     hit = [r for r in rows if any(x in r["Kernel_Name"] for x in syms) and _grid_size(r) == gs]
     hit.sort(key=lambda r: int(r[key_id]))
     if not hit:
-        raise SystemExit(f"no dispatch of {sym} with {gs} work-items")
+        raise SystemExit(f"no dispatch of {launch['symbol']} with {gs} work-items")
     return hit[-n:]
 
 
@@ -230,12 +231,105 @@ def traffic_table(fetch_dir, write_dir, fetch_log, write_log, command, out=TRAFF
     return table, key
 
 
-def counters_summary(dirs, kernels, command_lines, title, note=""):
+def _first_copy(rows, counter):
+    ids = [int(r["Dispatch_Id"]) for r in rows if COPY_KERNEL in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    if not ids:
+        raise SystemExit(f"no {COPY_KERNEL} dispatch with {counter}")
+    return min(ids)
+
+
+def _window_avg(rows, launch, counter, after):
+    """Average of `counter` over the `launches` timed dispatches of `launch`
+    that follow its warm-up dispatch, the first match after dispatch `after`;
+    returns (average, id of the last dispatch taken)."""
+    syms = [x.strip() for x in launch["symbol"].split(" + ")]
+    gs, n = int(launch["grid_size"]), int(launch["launches"])
+    hit = sorted((r for r in rows if r["Counter_Name"] == counter and int(r["Dispatch_Id"]) > after
+                  and any(x in r["Kernel_Name"] for x in syms) and _grid_size(r) == gs),
+                 key=lambda r: int(r["Dispatch_Id"]))[1:n + 1]
+    if len(hit) < n:
+        raise SystemExit(f"only {len(hit)} dispatches of {launch['symbol']} ({gs} work-items) after {after}")
+    return sum(float(r["Counter_Value"]) for r in hit) / n, int(hit[-1]["Dispatch_Id"])
+
+
+def stencil_table_traffic(fetch_dir, write_dir, fetch_log, write_log, command, out=TRAFFIC_FILE,
+                          time_log=None, time_command=None):
+    """HBM bytes per launch of every stencil of the benchmark's stencil table
+    (full masked D_rr stencil per precision and RHS count, each in its tuned
+    launch), from the same two counter runs and copy calibration as the
+    dominant launch; adds them to the traffic table and returns a summary."""
+    bf, bw = bench_line(fetch_log), bench_line(write_log)
+    tab = bf.get("stencils_32")
+    if not tab:
+        raise SystemExit("the counter runs have no stencil table")
+    # the times come from a run without counters (counter runs serialise the
+    # dispatches) whose launches must be the ones the counters saw
+    timed = bench_line(time_log)["stencils_32"] if time_log else tab
+    for name, e in tab.items():
+        if timed[name]["launch"]["shape"] != e["launch"]["shape"]:
+            raise SystemExit(f"{name}: the timed run and the counter runs used different launches")
+    cb = int(bf["calibration_copy_bytes"])
+    fr, wr = _csv(fetch_dir, "_counter_collection.csv"), _csv(write_dir, "_counter_collection.csv")
+    ff, fk, _ = _copy_factor(fr, cb, "FETCH_SIZE")
+    wf, wk, _ = _copy_factor(wr, cb, "WRITE_SIZE")
+    dims = bf["config"]["lattice"]
+    with open(out) as f:
+        table = json.load(f)
+    if table.get("kernel_source_sha256") != kernel_source_hash():
+        raise SystemExit("the traffic table is stale: write the dominant launch's entry first")
+    lines = ["# Full D_rr stencil at " + "x".join(map(str, dims)) + ": time and HBM traffic per launch", "",
+             "Commands (from the repository root, `cd /tmp && export TMPDIR=/tmp` first), one counter per run:", "",
+             "    " + command, ""] + (["Times from the same benchmark without counters:", "",
+                                   "    " + time_command, ""] if time_command else []) + [
+             "Each row is the masked D_rr stencil (rest rows and columns of the Type I partition) in the",
+             "launch the autotuner picks for that precision and RHS count.  Time: HIP events on the",
+             "library's stream around each launch (bench run without counters).  Traffic: FETCH_SIZE and",
+             "WRITE_SIZE per dispatch, scaled by what they read for torch's negation of 1 GiB in the same",
+             f"process (fetch factor {ff:.3f}, write factor {wf:.3f}).  Algorithmic bytes: every site reads",
+             "its input spinors and 4 links and writes its output spinors once.", "",
+             "| precision | RHS | kernel (launch) | avg us | alg. GB | alg. GB/s | frac of 8 TB/s | HBM GB (counters) | HBM / alg. | HBM GB/s |",
+             "|---|---:|---|---:|---:|---:|---:|---:|---:|---:|"]
+    # the table's launches follow the copy ceiling's (the first copy
+    # dispatches of the run), row after row: each row takes its warm-up and
+    # timed dispatches from a window that starts after the previous row's
+    ends = {"FETCH_SIZE": _first_copy(fr, "FETCH_SIZE"), "WRITE_SIZE": _first_copy(wr, "WRITE_SIZE")}
+    for name, e in tab.items():
+        prec, nrhs = name.split("_nrhs")
+        launch = e["launch"]
+        fetch, ends["FETCH_SIZE"] = _window_avg(fr, launch, "FETCH_SIZE", ends["FETCH_SIZE"])
+        write, ends["WRITE_SIZE"] = _window_avg(wr, launch, "WRITE_SIZE", ends["WRITE_SIZE"])
+        hbm = fetch * 1024 * ff + write * 1024 * wf
+        alg, ms = e["alg_bytes_per_launch"], timed[name]["avg_ms"]
+        key = traffic_key(prec, int(nrhs), dims, launch["shape"])
+        table["kernels"][key] = {"symbol": launch["symbol"], "grid_size": launch["grid_size"],
+                                 "shape": launch["shape"], "fetch_kib": fetch, "write_kib": write,
+                                 "hbm_bytes_per_launch": hbm, "alg_bytes_per_launch": alg,
+                                 "ratio_to_alg": hbm / alg, "command": command}
+        lines.append(f"| {prec} | {nrhs} | `{launch['symbol']}` {shape_tag(launch['shape'])} | {ms * 1e3:.1f} | "
+                     f"{alg / 1e9:.3f} | {alg / ms / 1e6:.0f} | {alg / ms / 1e6 / 8000:.3f} | {hbm / 1e9:.3f} | "
+                     f"{hbm / alg:.2f} | {hbm / ms / 1e6:.0f} |")
+    if bf.get("copy_ceiling"):
+        c = bf["copy_ceiling"]
+        lines += ["", f"Copy ceiling in the same run: {c['kernel']}, {c['GBps']:.0f} GB/s "
+                      f"({c['frac_of_peak']:.2f} of peak)."]
+    with open(out, "w") as f:
+        json.dump(table, f, indent=1)
+    return "\n".join(lines) + "\n"
+
+
+def counters_summary(dirs, kernels, command_lines, title, note="", copy_bytes=0):
     """Average of every counter per dispatch, per kernel (name substring)
-    and grid, over the counter runs in `dirs` (one counter set per run)."""
+    and grid, over the counter runs in `dirs` (one counter set per run);
+    with copy_bytes (a copy kernel of that size ran in each run), FETCH_SIZE
+    and WRITE_SIZE also scaled to HBM bytes by the copy's reading."""
     rows = []
     for d in dirs:
         rows.extend(_csv(d, "_counter_collection.csv"))
+    factors = {}
+    if copy_bytes:
+        for cn in ("FETCH_SIZE", "WRITE_SIZE"):
+            if any(r["Counter_Name"] == cn and COPY_KERNEL in r["Kernel_Name"] for r in rows):
+                factors[cn] = _copy_factor(rows, copy_bytes, cn)[0]
     agg = {}
     for r in rows:
         name = r["Kernel_Name"].split("(")[0].replace("void ", "")
@@ -246,9 +340,14 @@ def counters_summary(dirs, kernels, command_lines, title, note=""):
     lines = ["# " + title, "", "Commands (from the repository root, `cd /tmp && export TMPDIR=/tmp` "
              "first), one counter set per run:", ""]
     lines += ["    " + c for c in command_lines]
-    lines += ["", note, "", "| kernel | work-items | dispatches | counter | average |", "|---|---:|---:|---|---:|"]
+    if factors:
+        note += " " + ", ".join(f"{cn} scale {f:.3f} (copy of {copy_bytes} bytes)" for cn, f in factors.items())
+    lines += ["", note, "", "| kernel | work-items | dispatches | counter | average | HBM bytes (scaled) |",
+              "|---|---:|---:|---|---:|---:|"]
     for (name, gs, cn), v in sorted(agg.items()):
-        lines.append(f"| `{name.replace('|', '/')}` | {gs} | {len(v)} | {cn} | {sum(v) / len(v):.4g} |")
+        avg = sum(v) / len(v)
+        scaled = f"{avg * 1024 * factors[cn]:.4g}" if cn in factors else ""
+        lines.append(f"| `{name.replace('|', '/')}` | {gs} | {len(v)} | {cn} | {avg:.4g} | {scaled} |")
     return "\n".join(lines) + "\n"
 
 
@@ -272,10 +371,24 @@ def main(argv=None):
     c.add_argument("--command", action="append", required=True)
     c.add_argument("--title", required=True)
     c.add_argument("--note", default="")
+    c.add_argument("--copy-bytes", type=int, default=0)
     c.add_argument("--out")
+    tt = sub.add_parser("stencil-table")
+    for k in ("--fetch", "--write", "--fetch-log", "--write-log", "--command", "--out-md"):
+        tt.add_argument(k, required=True)
+    tt.add_argument("--out", default=TRAFFIC_FILE)
+    tt.add_argument("--time-log")
+    tt.add_argument("--time-command")
     a = ap.parse_args(argv)
+    if a.cmd == "stencil-table":
+        text = stencil_table_traffic(a.fetch, a.write, a.fetch_log, a.write_log, a.command, a.out,
+                                     a.time_log, a.time_command)
+        with open(a.out_md, "w") as f:
+            f.write(text)
+        sys.stdout.write(text)
+        return
     if a.cmd == "counters":
-        text = counters_summary(a.dirs, a.kernels, a.command, a.title, a.note)
+        text = counters_summary(a.dirs, a.kernels, a.command, a.title, a.note, a.copy_bytes)
         if a.out:
             with open(a.out, "w") as f:
                 f.write(text)
