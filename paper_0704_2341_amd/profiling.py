@@ -120,7 +120,8 @@ def step_breakdown(tr, marker: str, steps: int, top: int = 12):
     """Per-step kernel time over the last `steps` steps of a trace, a step
     ending with the dispatch of the kernel named by `marker` (substring)."""
     tr = sorted(tr, key=lambda r: int(r["Start_Timestamp"]))
-    ends = [i for i, r in enumerate(tr) if marker in r["Kernel_Name"]]
+    name, _, gs = marker.partition(":")
+    ends = [i for i, r in enumerate(tr) if name in r["Kernel_Name"] and (not gs or _grid_size(r) == int(gs))]
     if len(ends) < steps + 1:
         return None
     lo, hi = ends[-steps - 1] + 1, ends[-1] + 1
@@ -142,12 +143,13 @@ def step_breakdown(tr, marker: str, steps: int, top: int = 12):
     return lines
 
 
-def stats_summary(trace_dir: str, bench_log: str, command: str, top: int = 15, marker: str = "") -> str:
+def stats_summary(trace_dir: str, bench_log: str, command: str, top: int = 15, marker: str = "",
+                  steps: int = 0, title: str = "") -> str:
     b = bench_line(bench_log)
     launch = b["roofline"]["launch"]
     st = _csv(trace_dir, "_kernel_stats.csv")
     tot = sum(float(r["TotalDurationNs"]) for r in st)
-    lines = ["# rocprofv3 kernel trace: " + b["config"]["workload"], "",
+    lines = ["# rocprofv3 kernel trace: " + (title or b["config"]["workload"]), "",
              "Command (from the repository root, `cd /tmp && export TMPDIR=/tmp` first):", "",
              "    " + command, "",
              f"Bench line of this run: {b['value']:.1f} {b['unit']}, {b['ms_per_step']:.2f} ms/step "
@@ -171,9 +173,9 @@ def stats_summary(trace_dir: str, bench_log: str, command: str, top: int = 15, m
               f"Algorithmic bytes per launch {b['roofline']['alg_bytes_per_launch']:,}: "
               f"{b['roofline']['alg_bytes_per_launch'] / avg / 1e6:.0f} GB/s on the trace's average."]
     if marker:
-        steps = step_breakdown(tr, marker, int(b["steps"]))
-        if steps:
-            lines += [""] + steps
+        st = step_breakdown(tr, marker, steps or int(b["steps"]))
+        if st:
+            lines += [""] + st
     return "\n".join(lines) + "\n"
 
 
@@ -317,19 +319,30 @@ def stencil_table_traffic(fetch_dir, write_dir, fetch_log, write_log, command, o
     return "\n".join(lines) + "\n"
 
 
-def counters_summary(dirs, kernels, command_lines, title, note="", copy_bytes=0):
+def _between(rows, marker):
+    """The rows dispatched between the last two dispatches of the kernel
+    `marker` = 'NAME:WORK_ITEMS' (one step of a run), per counter run."""
+    name, gs = marker.rsplit(":", 1)
+    ids = sorted({int(r["Dispatch_Id"]) for r in rows if name in r["Kernel_Name"] and _grid_size(r) == int(gs)})
+    if len(ids) < 2:
+        raise SystemExit(f"fewer than two dispatches of {marker}")
+    return [r for r in rows if ids[-2] < int(r["Dispatch_Id"]) < ids[-1]]
+
+
+def counters_summary(dirs, kernels, command_lines, title, note="", copy_bytes=0, between=""):
     """Average of every counter per dispatch, per kernel (name substring)
     and grid, over the counter runs in `dirs` (one counter set per run);
     with copy_bytes (a copy kernel of that size ran in each run), FETCH_SIZE
-    and WRITE_SIZE also scaled to HBM bytes by the copy's reading."""
+    and WRITE_SIZE also scaled to HBM bytes by the copy's reading; with
+    between, only the dispatches of the last step of each run (see _between)."""
     rows = []
-    for d in dirs:
-        rows.extend(_csv(d, "_counter_collection.csv"))
     factors = {}
-    if copy_bytes:
+    for d in dirs:
+        rd = _csv(d, "_counter_collection.csv")
         for cn in ("FETCH_SIZE", "WRITE_SIZE"):
-            if any(r["Counter_Name"] == cn and COPY_KERNEL in r["Kernel_Name"] for r in rows):
-                factors[cn] = _copy_factor(rows, copy_bytes, cn)[0]
+            if copy_bytes and any(r["Counter_Name"] == cn and COPY_KERNEL in r["Kernel_Name"] for r in rd):
+                factors[cn] = _copy_factor(rd, copy_bytes, cn)[0]
+        rows.extend(_between(rd, between) if between else rd)
     agg = {}
     for r in rows:
         name = r["Kernel_Name"].split("(")[0].replace("void ", "")
@@ -359,7 +372,10 @@ def main(argv=None):
     s.add_argument("--bench-log", required=True)
     s.add_argument("--command", required=True)
     s.add_argument("--step-marker", default="",
-                   help="kernel name (substring) whose dispatch ends a step: adds a per-step breakdown")
+                   help="kernel name (substring), optionally :WORK_ITEMS, whose dispatch ends a step: "
+                        "adds a per-step breakdown")
+    s.add_argument("--steps", type=int, default=0, help="steps of the breakdown (default: the bench's)")
+    s.add_argument("--title", default="")
     s.add_argument("--out")
     t = sub.add_parser("traffic")
     for k in ("--fetch", "--write", "--fetch-log", "--write-log", "--command"):
@@ -372,6 +388,8 @@ def main(argv=None):
     c.add_argument("--title", required=True)
     c.add_argument("--note", default="")
     c.add_argument("--copy-bytes", type=int, default=0)
+    c.add_argument("--between", default="", metavar="KERNEL:WORK_ITEMS",
+                   help="only the dispatches between the last two dispatches of this kernel")
     c.add_argument("--out")
     tt = sub.add_parser("stencil-table")
     for k in ("--fetch", "--write", "--fetch-log", "--write-log", "--command", "--out-md"):
@@ -388,14 +406,15 @@ def main(argv=None):
         sys.stdout.write(text)
         return
     if a.cmd == "counters":
-        text = counters_summary(a.dirs, a.kernels, a.command, a.title, a.note, a.copy_bytes)
+        text = counters_summary(a.dirs, a.kernels, a.command, a.title, a.note, a.copy_bytes, a.between)
         if a.out:
             with open(a.out, "w") as f:
                 f.write(text)
         sys.stdout.write(text)
         return
     if a.cmd == "stats":
-        text = stats_summary(a.trace, a.bench_log, a.command, marker=a.step_marker)
+        text = stats_summary(a.trace, a.bench_log, a.command, marker=a.step_marker, steps=a.steps,
+                             title=a.title)
         if a.out:
             with open(a.out, "w") as f:
                 f.write(text)
