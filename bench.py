@@ -243,6 +243,7 @@ def stencil_table(grg, torch, lat, m0, q, nb, volume, dims, reps: int = 10, pin:
     order, so that a counter run finds each row's launches in sequence after
     the copy's.  Returns (table, ceiling)."""
     from grg_inputs import gaussian_vectors
+    from paper_0704_2341_amd.profiling import measured_traffic, traffic_key
 
     out = {}
     x12 = torch.from_numpy(gaussian_vectors(12 * volume, 12, 91)).to("cuda")
@@ -273,10 +274,14 @@ def stencil_table(grg, torch, lat, m0, q, nb, volume, dims, reps: int = 10, pin:
             avg = ms / cnt
             alg = dslash_bytes_per_launch(prec, volume, nrhs)
             info = grg.grg_schur_tune_info(s, prec, nrhs)
+            launch = launch_descriptor(info, prec, cnt)
             out[f"{prec}_nrhs{nrhs}"] = {"avg_ms": avg, "alg_bytes_per_launch": alg,
                                         "alg_GBps": alg / (avg * 1e-3) / 1e9,
                                         "frac_of_peak": alg / (avg * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                                        "launch": launch_descriptor(info, prec, cnt)}
+                                        "launch": launch,
+                                        # counter-measured bytes of this launch shape, or None
+                                        "traffic": measured_traffic(traffic_key(prec, nrhs, dims,
+                                                                                launch["shape"]))}
             log(f"stencil {prec} nrhs {nrhs}: {avg * 1e3:.1f} us per launch, "
                 f"{out[f'{prec}_nrhs{nrhs}']['alg_GBps']:.0f} GB/s algorithmic")
     for s in handles.values():

@@ -39,16 +39,35 @@ def test_algorithmic_bytes():
     assert b.eo_bytes_per_launch("fp64", V, 1, 20, 5) == V * ((1 + 1.5) / 2 * 12 * 16 + 4 * 9 * 16)
 
 
-@pytest.mark.parametrize("split,sym", [(7, "eo_plane_kernel<0, 0> + eo_plane_kernel<0, 2>"), (3, "eo_hop_kernel<2, 3, 0>"),
-                                       (1, "eo_hop_kernel<2, 1, 0>")])
-def test_dominant_launch_names(split, sym):
+@pytest.mark.parametrize("split,rg,sym", [(7, 1, "eo_plane_kernel<0, 0, 1> + eo_plane_kernel<0, 2, 1>"),
+                                          (7, 2, "eo_plane_kernel<0, 0, 2> + eo_plane_kernel<0, 2, 2>"),
+                                          (3, 3, "eo_hop_kernel<2, 3, 0>"), (1, 3, "eo_hop_kernel<2, 1, 0>")])
+def test_dominant_launch_names(split, rg, sym):
+    """The kernel names the profiler reports (template arguments as the
+    demangler prints them: the plane form's planes per workgroup are its RG)."""
     b = _bench()
-    info = dict(SB=512 if split == 7 else 256, RG=1 if split == 7 else 3, split=split, grid=3072, chunk=0,
+    info = dict(SB=512 if split == 7 else 256, RG=rg, split=split, grid=3072, chunk=0,
                 march=4 if split in (3, 7) else 0)
     d = b.launch_descriptor(info, "bf16", 40, eo=True)
     assert d["symbol"] == sym
     assert d["grid_size"] == info["grid"] * info["SB"]
     assert d["shape"] == info
+
+
+@pytest.mark.parametrize("prec,info,sym,gs", [
+    ("fp64", dict(SB=64, RG=6, split=0, grid=2048, chunk=0, march=16), "march_kernel<grg::StoreEpi<0> >", 2048 * 64 * 6),
+    ("bf16", dict(SB=256, RG=3, split=2, grid=4096, chunk=0, march=0), "dslash_kernel<2, 2>", 4096 * 256),
+    ("fp32", dict(SB=64, RG=1, split=1, grid=2048, chunk=64, march=0), "dslash_kernel<1, 1>", 2048 * 64)])
+def test_full_stencil_launch_names(prec, info, sym, gs):
+    b = _bench()
+    d = b.launch_descriptor(info, prec, 10)
+    assert d["symbol"] == sym and d["grid_size"] == gs
+
+
+def test_stencil_launch_pins_parse():
+    b = _bench()
+    got = b.parse_stencil_launches("fp64_nrhs1=128,1,0,512,1,0; bf16_nrhs12=256,3,2,4096,0,0;")
+    assert got == {"fp64_nrhs1": [128, 1, 0, 512, 1, 0], "bf16_nrhs12": [256, 3, 2, 4096, 0, 0]}
 
 
 def test_traffic_lookup_by_shape_and_sources(tmp_path):
