@@ -400,6 +400,7 @@ static void schur_free(grg_schur S)
     dfree((void *&)S->d_bidx);
     void **f64[5] = {&S->b64, &S->x64, &S->r64, &S->t64, &S->u64};
     for (void **p : f64) dfree(*p);
+    dfree(S->r32);
     for (int p = 0; p < 3; ++p) {
         dfree(S->in_b[p]);
         dfree(S->in_x[p]);

@@ -127,6 +127,8 @@ struct DcArgs {
     int ring;             // with march > 0 and BF16 e: the LDS-ring form of the t-marching step
     int grp_first;        // ring form: work items ordered with the RHS group fastest, so the
                           // groups of one tile run together on one XCD and share its links
+    int r_in32 = 0;       // r_in is stored in FP32 (float2 per complex), else FP64
+    int r_out32 = 0;      // r_out is stored in FP32 (rounded from the FP64 result), else FP64
 };
 
 hipError_t launch_dslash(int prec, const DslashArgs &a, int grid, hipStream_t st);

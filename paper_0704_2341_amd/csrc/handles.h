@@ -95,6 +95,9 @@ struct grg_schur_s {
     int32_t *d_bidx = nullptr;    // site -> coarse index or -1
     // FP64 outer fields, [max_rhs][12][Vs] each
     void *b64 = nullptr, *x64 = nullptr, *r64 = nullptr, *t64 = nullptr, *u64 = nullptr;
+    // the defect correction's residual in FP32 once it is small ([max_rhs][12][Vs]
+    // float2, allocated on first use)
+    void *r32 = nullptr;
     // inner fields (one set per precision, allocated on first use)
     void *in_b[3] = {nullptr, nullptr, nullptr};
     void *in_x[3] = {nullptr, nullptr, nullptr};

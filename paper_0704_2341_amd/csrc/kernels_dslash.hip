@@ -157,6 +157,22 @@ struct StoreEpi {
 // dc_update_kernel): r_out = r_in - f acc, x_out = x_in + f e (skipped when
 // x_out is null: the caller sums the corrections itself), r_next =
 // s_next r_out, and |r_out|^2.  The stencil of e runs in FP64 with FP64 links.
+// The defect correction's residual element i, stored in FP64 or (late steps,
+// DcArgs::r_in32 / r_out32) in FP32 at the same element index.
+__device__ __forceinline__ double2 dc_load_r(const DcArgs &a, const double2 *r, size_t i)
+{
+    if (a.r_in32) {
+        const float2 v = ((const float2 *)r)[i];
+        return make_double2((double)v.x, (double)v.y);
+    }
+    return r[i];
+}
+__device__ __forceinline__ void dc_store_r(const DcArgs &a, double2 *r, size_t i, double2 v)
+{
+    if (a.r_out32) ((float2 *)r)[i] = make_float2((float)v.x, (float)v.y);
+    else r[i] = v;
+}
+
 template <int P>
 struct DcEpi {
     typedef typename Store<P>::S SIN;
@@ -190,9 +206,9 @@ struct DcEpi {
             if (c % 3 == 0) asm volatile("" ::: "memory");
             const size_t i = fidx(s, r, c, a.nrhs);
             if (on) {
-                const double2 rv = r_in[i];
+                const double2 rv = dc_load_r(a, r_in, i);
                 const double2 d = make_double2(rv.x - f * acc[c].re, rv.y - f * acc[c].im);
-                r_out[i] = d;
+                dc_store_r(a, r_out, i, d);
                 if (r_next) stc(r_next, i, cpx<RN>{(RN)(sn * d.x), (RN)(sn * d.y)});
                 nrm[0] += d.x * d.x + d.y * d.y;
                 if (x_out) {
@@ -201,7 +217,7 @@ struct DcEpi {
                     x_out[i] = make_double2(xv.x + f * ev.re, xv.y + f * ev.im);
                 }
             } else {
-                r_out[i] = make_double2(0.0, 0.0);
+                dc_store_r(a, r_out, i, make_double2(0.0, 0.0));
                 if (x_out) x_out[i] = make_double2(0.0, 0.0);
                 if (r_next) stc(r_next, i, cpx<RN>{0, 0});
             }
@@ -525,7 +541,8 @@ __global__ void __launch_bounds__(512) ring_march_kernel(typename E::Args a)
 
 // One FP64 defect-correction step, fused.  e is the inner solution (stored in
 // precision P, zero on coarse sites) of A e = r_in / f_k:
-//     r_out = r_in - f (D_rr e)        x_out = x_in + f e        (FP64)
+//     r_out = r_in - f (D_rr e)        x_out = x_in + f e        (FP64;
+// r_in / r_out stored in FP32 instead with DcArgs::r_in32 / r_out32)
 // on the r-sites; coarse sites are written as zero.  x_out == nullptr skips
 // the iterate (the caller keeps the corrections); x_in == nullptr reads as
 // zero.  With r_next set, also r_next = s_next r_out in precision P (the next
@@ -566,9 +583,9 @@ __global__ void __launch_bounds__(256) dc_update_kernel(DcArgs a)
 #pragma unroll
                 for (int c = 0; c < 12; ++c) {
                     const size_t i = fidx(s, r, c, a.nrhs);
-                    const double2 rv = r_in[i];
+                    const double2 rv = dc_load_r(a, r_in, i);
                     const double2 d = make_double2(rv.x - f * acc[c].re, rv.y - f * acc[c].im);
-                    r_out[i] = d;
+                    dc_store_r(a, r_out, i, d);
                     if (r_next) stc(r_next, i, cpx<R>{(R)(sn * d.x), (R)(sn * d.y)});
                     nrm += d.x * d.x + d.y * d.y;
                     if (x_out) {
@@ -581,7 +598,7 @@ __global__ void __launch_bounds__(256) dc_update_kernel(DcArgs a)
 #pragma unroll
                 for (int c = 0; c < 12; ++c) {
                     const size_t i = fidx(s, r, c, a.nrhs);
-                    r_out[i] = make_double2(0.0, 0.0);
+                    dc_store_r(a, r_out, i, make_double2(0.0, 0.0));
                     if (x_out) x_out[i] = make_double2(0.0, 0.0);
                     if (r_next) stc(r_next, i, cpx<R>{0, 0});
                 }

@@ -1118,13 +1118,21 @@ constexpr int kPrecondInnerCap = 100;
 // The inner right-hand side s_k r_k in the inner precision, from the FP64
 // residual r (scale: device array of s_k).
 static grg_status convert_rhs(grg_schur S, int prec, const BlasShape &sh, const void *r_src,
-                              const double *scale)
+                              const double *scale, int r_prec = GRG_FP64)
 {
     PhaseTimer pt(S->prof, S->lat->stream, kProfBlas);
-    GRG_TRY_HIP(launch_axpy_convert(GRG_FP64, prec, sh, r_src, S->in_r[prec], scale, 0, 0, nullptr,
+    GRG_TRY_HIP(launch_axpy_convert(r_prec, prec, sh, r_src, S->in_r[prec], scale, 0, 0, nullptr,
                                     S->lat->stream));
     return GRG_OK;
 }
+
+// The defect correction keeps its residual in FP64 until it is small: once
+// |r_k| <= theta |b| for every RHS, the next steps store it in FP32.  Each
+// later store rounds by at most 2^-24 |r_j| (relative), so the recursively
+// updated residual drifts from b - A x by at most 2^-24 sum_j |r_j| <= 2^-24
+// theta |b| (1 + inner_tol + ...) ~ 6e-8 theta |b|: theta = 1e5 tol keeps
+// that below 1 % of the tolerance.
+static double dc_fp32_threshold(double tol) { return std::min(1e-3, 1e5 * tol); }
 
 // A slot of the correction pool (inner precision, full layout, max_rhs).
 static grg_status pool_slot(grg_schur S, int prec, int k, void **out)
@@ -1227,6 +1235,7 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
     };
 
     const void *r_src = S->b64;  // the residual of the current iterate
+    int r_prec = GRG_FP64;       // its storage (FP32 in the late steps, see dc_fp32_threshold)
     bool rhs_ready = false;      // in_r holds s r_src in the inner precision
     int total = 0, outer = 0;
     bool verified = false;
@@ -1255,6 +1264,7 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
                                       nullptr, st));
             GRG_TRY(read_norms(S, nrhs, rn2));
             r_src = S->r64;
+            r_prec = GRG_FP64;
             rhs_ready = false;
             verified = true;
             continue;
@@ -1283,7 +1293,7 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
         GRG_TRY(upload(d_f, f, 1));
         if (!rhs_ready) {
             GRG_TRY(upload(d_s, sc, 2));
-            GRG_TRY(convert_rhs(S, prec, sh, r_src, d_s));
+            GRG_TRY(convert_rhs(S, prec, sh, r_src, d_s, r_prec));
         }
         int it = 0;
         grg_status is;
@@ -1303,7 +1313,7 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
                 S->precond = nullptr;
                 ++S->fallbacks;
                 GRG_TRY(upload(d_s, sc, 2));
-                GRG_TRY(convert_rhs(S, prec, sh, r_src, d_s));
+                GRG_TRY(convert_rhs(S, prec, sh, r_src, d_s, r_prec));
                 is = reduce ? inner_mr_eo(S, prec, nrhs, thr, p.max_iter - total, &it, h, e)
                             : inner_gcr(S, prec, nrhs, thr, p.max_iter - total, &it, h, e);
                 S->precond = keep;
@@ -1326,12 +1336,30 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
         }
         GRG_TRY(upload(d_sn, scn, 3));
         // r -= A e / s ; next inner rhs s' r   (FP64, fused; x is summed at the end)
+        // the residual's storage from here on: FP32 once it is small for
+        // every RHS (r_src is that of the step's input)
+        bool small = r_prec == GRG_FP32;
+        if (!small && prec != GRG_FP64) {
+            small = true;
+            const double theta = dc_fp32_threshold(p.tol);
+            for (int k = 0; k < nrhs; ++k)
+                if (bn2[k] > 0 && !(rn2[k] <= theta * theta * bn2[k])) small = false;
+        }
+        if (small && !S->r32) {
+            const size_t bytes = spinor_elems(g, S->prm.max_rhs) * prec_bytes(GRG_FP32);
+            if (hipMalloc(&S->r32, bytes) != hipSuccess) {
+                S->r32 = nullptr;
+                small = false;  // keep FP64
+            }
+        }
         DcArgs d;
         d.e = e;
         d.U = L->U[GRG_FP64];
         d.r_in = r_src;
+        d.r_in32 = r_prec == GRG_FP32;
         d.x_in = nullptr;
-        d.r_out = S->r64;
+        d.r_out = small ? S->r32 : S->r64;
+        d.r_out32 = small;
         d.x_out = nullptr;
         d.f = d_f;
         d.r_next = S->in_r[prec];
@@ -1352,7 +1380,8 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
         ++npool;
         GRG_TRY(read_norms(S, nrhs, rn2));
         memcpy(sc, scn, sizeof(double) * nrhs);
-        r_src = S->r64;
+        r_src = small ? S->r32 : S->r64;
+        r_prec = small ? GRG_FP32 : GRG_FP64;
         rhs_ready = true;
     }
     if (xb && yb && fused && u_minus && !have_x) {
