@@ -479,10 +479,14 @@ typedef struct {
 
 /* params->inner / inner_tol / tol / max_iter / max_outer as for one lattice;
  * check_every = inner iterations between the host's reads of the flags in
- * the eager mode; the inner solve is
- * minimal residual on D_rr (params->method other than 0 gives
- * GRG_EUNSUPPORTED; restart and eo are not used).  stream: the caller's
- * stream, waited on at entry and made to wait for the result at exit. */
+ * the eager mode; the inner solve is minimal residual (params->method other
+ * than 0 gives GRG_EUNSUPPORTED; restart is not used): with params->eo and
+ * every extent of every member even, on the even-odd reduced system of each
+ * lattice's D_rr (d - H_pq H_qp / d on the parity with fewer rest sites, as
+ * grg_reduced_apply; the same block elimination as S_bb applied to D_rr),
+ * the other parity reconstructed after each inner solve; else on D_rr.
+ * stream: the caller's stream, waited on at entry and made to wait for the
+ * result at exit. */
 grg_status grg_batch_create(const grg_batch_member *members, int count, int nrhs,
                             const grg_solver_params *params, void *stream, grg_batch *out);
 grg_status grg_batch_destroy(grg_batch b);

@@ -56,6 +56,15 @@ struct grg_batch_s {
     long long *coff = nullptr;
     void *b64 = nullptr, *x64 = nullptr, *r64 = nullptr, *t64 = nullptr, *u64 = nullptr;
     void *in_b = nullptr, *in_x = nullptr, *in_r = nullptr, *in_q = nullptr;
+    // the even-odd reduced inner solve (every extent even, params.eo): per lattice
+    // the parity with fewer rest sites carries the reduced system; mask_eo is 1 on
+    // coarse sites, 0 / 2 on the rest sites of that parity / the other one; coef
+    // holds per lattice [1, 0, d, 1 / d, -1 / d] (d = 4 + m0) as five arrays;
+    // in_w the intermediate H_qp r, in_t the inner right-hand side's other-parity part
+    bool eo = false;
+    uint8_t *mask_eo = nullptr;
+    double *coef = nullptr;
+    void *in_w = nullptr, *in_t = nullptr;
     double *partials = nullptr;
     double2 *alpha = nullptr;
     double *thr2 = nullptr, *fr2 = nullptr, *rn2i = nullptr;
@@ -111,6 +120,8 @@ static BatchBlasArgs blas(grg_batch B)
     return a;
 }
 
+enum { kC1 = 0, kC0 = 1, kCd = 2, kCinv = 3, kCminv = 4 };  // rows of B->coef
+
 static grg_status dslash(grg_batch B, int prec, const void *in, void *out, int sel, bool dots,
                          const int *act = nullptr)
 {
@@ -126,6 +137,31 @@ static grg_status dslash(grg_batch B, int prec, const void *in, void *out, int s
     a.nrhs = B->nrhs;
     a.RG = B->RG[prec];
     a.partials = dots ? B->partials : nullptr;
+    GRG_TRY_HIP(launch_dslash_batch(prec, a, dgrid(B, prec), B->SB[prec], B->st));
+    return GRG_OK;
+}
+
+// The reduced mode of the batched stencil on the rows mask_eo == sel:
+// out = c[ka] in2 + c[kb] H in per lattice (see BatchDslashArgs).
+static grg_status dslash_red(grg_batch B, int prec, const void *in, const void *in2, void *out, int sel, int ka,
+                             int kb, bool dots, bool keep, const int *act)
+{
+    BatchDslashArgs a;
+    a.act = act;
+    a.in = in;
+    a.in2 = in2;
+    a.out = out;
+    a.U = B->U[prec];
+    a.mask = B->mask_eo;
+    a.sel = sel;
+    a.bt = table(B);
+    a.Vtot = B->Vtot;
+    a.nrhs = B->nrhs;
+    a.RG = B->RG[prec];
+    a.partials = dots ? B->partials : nullptr;
+    a.ca = B->coef + (size_t)ka * B->nlat;
+    a.cb = B->coef + (size_t)kb * B->nlat;
+    a.keep = keep ? 1 : 0;
     GRG_TRY_HIP(launch_dslash_batch(prec, a, dgrid(B, prec), B->SB[prec], B->st));
     return GRG_OK;
 }
@@ -167,7 +203,14 @@ static grg_status inner_step(grg_batch B, int prec)
     BatchBlasArgs a = blas(B);
     a.act = B->active;
     a.ctr = B->ctr;
-    GRG_TRY(dslash(B, prec, B->in_r, B->in_q, 0, true, B->active));
+    if (B->eo) {
+        // q = (d - H_pq H_qp / d) r on the reduced parity, with <q, r>, |q|^2
+        // (the other parity's rows of w and q stay zero: not written)
+        GRG_TRY(dslash_red(B, prec, B->in_r, nullptr, B->in_w, 2, kC0, kC1, false, true, B->active));
+        GRG_TRY(dslash_red(B, prec, B->in_w, B->in_r, B->in_q, 0, kCd, kCminv, true, true, B->active));
+    } else {
+        GRG_TRY(dslash(B, prec, B->in_r, B->in_q, 0, true, B->active));
+    }
     GRG_TRY_HIP(launch_batch_reduce(kAlpha, B->partials, dgrid(B, prec), B->nsys, B->alpha, nullptr, nullptr,
                                     B->active, nullptr, B->st));
     GRG_TRY_HIP(launch_batch_mr_update(prec, a, B->in_x, B->in_r, B->in_q, B->st));
@@ -189,6 +232,14 @@ static grg_status outer_step(grg_batch B, int prec, const void *r_src, const voi
     GRG_TRY_HIP(launch_batch_inner_init(prec, a, r_src, B->fr2, B->in_r, B->in_x, B->st));
     GRG_TRY_HIP(launch_batch_reduce(kNorm, B->partials, a.grid, B->nsys, nullptr, B->rn2i, B->thr2, B->oact,
                                     B->active, B->st));
+    if (B->eo) {
+        // the reduced right-hand side b_p - H_pq b_q / d in place (b_q kept in
+        // in_t for the reconstruction), its |.|^2 setting the inner flags
+        GRG_TRY_HIP(launch_batch_select(prec, a, B->mask_eo, 2, B->in_r, B->in_t, B->st));
+        GRG_TRY(dslash_red(B, prec, B->in_t, B->in_r, B->in_r, 0, kC1, kCminv, true, false, B->oact));
+        GRG_TRY_HIP(launch_batch_reduce(kNorm3, B->partials, dgrid(B, prec), B->nsys, nullptr, B->rn2i, B->thr2,
+                                        B->oact, B->active, B->st));
+    }
     int it = 0;
     if (eager) {
         const int chunk = std::max(1, B->prm.check_every);
@@ -205,6 +256,11 @@ static grg_status outer_step(grg_batch B, int prec, const void *r_src, const voi
         if (taken) *taken = h_ctr(B)[0] - c0;
     } else {
         for (int k = 0; k < n_inner; ++k) GRG_TRY(inner_step(B, prec));
+    }
+    if (B->eo) {
+        // the other parity of the correction, e_q = (b_q - H_qp e_p) / d,
+        // into in_x beside e_p
+        GRG_TRY(dslash_red(B, prec, B->in_x, B->in_t, B->in_x, 2, kCinv, kCminv, false, true, B->oact));
     }
     BatchDcArgs d;
     d.e = B->in_x;
@@ -427,6 +483,10 @@ static void batch_free(grg_batch B)
     f(B->in_x);
     f(B->in_r);
     f(B->in_q);
+    f(B->mask_eo);
+    f(B->coef);
+    f(B->in_w);
+    f(B->in_t);
     f(B->partials);
     f(B->alpha);
     f(B->dsc);  // rn2, bn2, the counters and the inner flags
@@ -539,6 +599,39 @@ grg_status grg_batch_create(const grg_batch_member *m, int count, int nrhs,
         diag[i] = 4.0 + b.m0;
         coffs[i] = b.coff;
     }
+    // the even-odd reduced inner solve: every lattice with even extents
+    bool eo = prm.eo != 0;
+    for (int i = 0; i < count && eo; ++i)
+        for (int mu = 0; mu < 4; ++mu)
+            if (mem[i].dims[mu] % 2) eo = false;
+    std::vector<uint8_t> mask_eo(eo ? Vtot : 0);
+    std::vector<double> coef(eo ? 5 * (size_t)count : 0);
+    if (eo) {
+        for (int i = 0; i < count; ++i) {
+            const BatchMember &b = mem[i];
+            long rest[2] = {0, 0};
+            std::vector<uint8_t> par(b.V);
+            for (int x = 0; x < b.V; ++x) {
+                int c = x, sum = 0;
+                for (int mu = 0; mu < 4; ++mu) {
+                    sum += c % b.dims[mu];
+                    c /= b.dims[mu];
+                }
+                par[x] = (uint8_t)(sum & 1);
+                if (!mask[b.off + x]) ++rest[sum & 1];
+            }
+            // the reduced system on the parity with fewer rest sites (as one lattice)
+            const int p = rest[0] < rest[1] ? 0 : 1;
+            for (int x = 0; x < b.V; ++x)
+                mask_eo[b.off + x] = mask[b.off + x] ? 1 : (par[x] == p ? 0 : 2);
+            const double d = diag[i];
+            coef[kC1 * (size_t)count + i] = 1.0;
+            coef[kC0 * (size_t)count + i] = 0.0;
+            coef[kCd * (size_t)count + i] = d;
+            coef[kCinv * (size_t)count + i] = 1.0 / d;
+            coef[kCminv * (size_t)count + i] = -1.0 / d;
+        }
+    }
     const size_t f64 = spinor_elems(B->gtot, nrhs) * 16;
     const size_t fin = spinor_elems(B->gtot, nrhs) * prec_bytes(prm.inner);
     bool ok = true;
@@ -562,6 +655,13 @@ grg_status grg_batch_create(const grg_batch_member *m, int count, int nrhs,
     al((void **)&B->coff, sizeof(long long) * count);
     for (void **p : {&B->b64, &B->x64, &B->r64, &B->t64, &B->u64}) al(p, f64);
     for (void **p : {&B->in_b, &B->in_x, &B->in_r, &B->in_q}) al(p, fin);
+    B->eo = eo;
+    if (eo) {
+        al((void **)&B->mask_eo, Vtot);
+        al((void **)&B->coef, sizeof(double) * 5 * count);
+        al(&B->in_w, fin);
+        al(&B->in_t, fin);
+    }
     al((void **)&B->partials, sizeof(double) * kBatchMaxGrid * B->nsys * 3);
     al((void **)&B->alpha, sizeof(double2) * B->nsys);
     for (double **p : {&B->thr2, &B->fr2, &B->rn2i}) al((void **)p, sizeof(double) * B->nsys);
@@ -603,10 +703,15 @@ grg_status grg_batch_create(const grg_batch_member *m, int count, int nrhs,
     UP(B->dims, dims.data(), sizeof(int4) * count);
     UP(B->diag, diag.data(), sizeof(double) * count);
     UP(B->coff, coffs.data(), sizeof(long long) * count);
+    if (eo) {
+        UP(B->mask_eo, mask_eo.data(), Vtot);
+        UP(B->coef, coef.data(), sizeof(double) * 5 * count);
+    }
     GRG_TRY_HIP(hipStreamSynchronize(st));
 #undef UP
     for (void *p : {B->b64, B->x64, B->r64, B->t64, B->u64}) GRG_TRY_HIP(launch_fill_zero(p, f64, st));
-    for (void *p : {B->in_b, B->in_x, B->in_r, B->in_q}) GRG_TRY_HIP(launch_fill_zero(p, fin, st));
+    for (void *p : {B->in_b, B->in_x, B->in_r, B->in_q, B->in_w, B->in_t})
+        if (p) GRG_TRY_HIP(launch_fill_zero(p, fin, st));
     GRG_TRY_HIP(launch_fill_zero(B->dsc, B->dsc_bytes, st));
     GRG_TRY_HIP(launch_fill_zero(B->oact, sizeof(int) * B->nsys, st));
     // links, one member at a time through a staging buffer
@@ -766,6 +871,13 @@ grg_status grg_batch_tune(grg_batch B)
     if (B->graph) {
         (void)hipGraphExecDestroy(B->graph);  // launch shapes are baked into the graph
         B->graph = nullptr;
+    }
+    // the reduced inner solve writes only its own rows of q and w: the rows of
+    // the other parity must read zero, as at creation
+    if (B->eo) {
+        const size_t fin = spinor_elems(B->gtot, B->nrhs) * prec_bytes(B->prm.inner);
+        GRG_TRY_HIP(launch_fill_zero(B->in_q, fin, B->st));
+        GRG_TRY_HIP(launch_fill_zero(B->in_w, fin, B->st));
     }
     return GRG_OK;
 }

@@ -18,7 +18,8 @@ struct BatchDslashArgs {
     const void *in;
     void *out;
     const void *U;
-    const uint8_t *mask;  // 1 on coarse sites
+    const uint8_t *mask;  // 1 on coarse sites (the reduced mode: 0 / 2 on the rest sites of the
+                          // reduced parity / the other parity)
     int sel;              // rows kept: mask[s] == sel
     BatchTable bt;
     int Vtot;             // total sites (a multiple of 256)
@@ -27,6 +28,13 @@ struct BatchDslashArgs {
     double *partials;     // [grid][nlat * nrhs][3] or nullptr
     const int *act;       // per-system flags, or nullptr: with flags, systems whose flag is 0
                           // are skipped and a launch with no flag set returns at once
+    // the even-odd reduced mode (ca != nullptr): out = ca[l] in2 + cb[l] H in on the
+    // kept rows, H the hopping term of D (no diagonal), in2 == nullptr read as zero;
+    // the fused sums are taken with in2; with keep, rows not kept are left as they are
+    // (else written as zero)
+    const void *in2 = nullptr;
+    const double *ca = nullptr, *cb = nullptr;
+    int keep = 0;
 };
 
 struct BatchBlasArgs {
@@ -99,6 +107,9 @@ hipError_t launch_batch_reduce(int mode, const double *partials, int nparts, int
 hipError_t launch_batch_ctl(const BatchCtlArgs &c, hipStream_t st);
 // y = x - y (FP64, every site and RHS)
 hipError_t launch_batch_xmy(const BatchBlasArgs &a, const void *x, void *y, hipStream_t st);
+// y = x on the sites with mask[s] == sel, zero elsewhere (every RHS, precision prec)
+hipError_t launch_batch_select(int prec, const BatchBlasArgs &a, const uint8_t *mask, int sel, const void *x,
+                               void *y, hipStream_t st);
 hipError_t launch_batch_coarse(const BatchTable &bt, const void *in, const void *U, double *yb,
                                const int32_t *qg, const int *clat, const int *nb, const int *nboff,
                                const long long *coff, int nbtot, int nrhs, hipStream_t st);

@@ -83,6 +83,9 @@ __device__ bool any_set(const int *flags, int n)
 }
 
 // out = mask_sel D in over all lattices; fused dots per system when partials.
+// The reduced mode (a.ca set): out = ca in2 + cb H in per lattice on the kept
+// rows (the two half-steps of d - H_pq H_qp / d, the reduced right-hand side
+// and the reconstruction of the other parity), the sums taken with in2.
 template <int P>
 __global__ void __launch_bounds__(256) dslash_batch_kernel(BatchDslashArgs a)
 {
@@ -90,8 +93,10 @@ __global__ void __launch_bounds__(256) dslash_batch_kernel(BatchDslashArgs a)
     typedef typename Store<P>::R R;
     extern __shared__ double smem[];
     const S *__restrict__ in = (const S *)a.in;
-    S *__restrict__ out = (S *)a.out;
+    const S *in2 = (const S *)a.in2;  // may alias out (read before the write of the same element)
+    S *out = (S *)a.out;
     const S *__restrict__ U = (const S *)a.U;
+    const bool red = a.ca != nullptr;
     const int nsys = a.bt.nlat * a.nrhs;
     if (a.act && !any_set(a.act, nsys)) return;
     const bool dots = a.partials != nullptr;
@@ -106,7 +111,8 @@ __global__ void __launch_bounds__(256) dslash_batch_kernel(BatchDslashArgs a)
         const BSite b = bsite(a.bt, s);
         const bool on = a.mask[s] == a.sel;
         const SiteGeo q = site_geo(b.local, b.g);
-        const R diag = (R)a.bt.diag[b.l];
+        const R diag = red ? (R)0 : (R)a.bt.diag[b.l];
+        const R ca = red ? (R)a.ca[b.l] : (R)0, cb = red ? (R)a.cb[b.l] : (R)0;
         const int r0 = grp * a.RG, r1 = min(r0 + a.RG, a.nrhs);
         for (int r = r0; r < r1; ++r) {
             // (a workgroup lies inside one lattice: the skip is uniform)
@@ -114,18 +120,28 @@ __global__ void __launch_bounds__(256) dslash_batch_kernel(BatchDslashArgs a)
             cpx<R> acc[12];
             if (on) {
                 dslash_site<S, R, true>(acc, in, U, s, q, b.g, r, a.nrhs, diag);
+                if (red) {
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) {
+                        const cpx<R> v2 = in2 ? ldc(in2, fidx(s, r, c, a.nrhs)) : cpx<R>{0, 0};
+                        acc[c] = {ca * v2.re + cb * acc[c].re, ca * v2.im + cb * acc[c].im};
+                    }
+                }
             } else {
 #pragma unroll
                 for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
             }
+            if (on || !(red && a.keep)) {
 #pragma unroll
-            for (int c = 0; c < 12; ++c) stc(out, fidx(s, r, c, a.nrhs), acc[c]);
+                for (int c = 0; c < 12; ++c) stc(out, fidx(s, r, c, a.nrhs), acc[c]);
+            }
             if (dots) {
                 R sre = 0, sim = 0, sqq = 0;
                 if (on) {
+                    const S *dv = red ? in2 : in;
 #pragma unroll
                     for (int c = 0; c < 12; ++c) {
-                        const cpx<R> v = ldc(in, fidx(s, r, c, a.nrhs));
+                        const cpx<R> v = dv ? ldc(dv, fidx(s, r, c, a.nrhs)) : cpx<R>{0, 0};
                         sre = fma(acc[c].re, v.re, fma(acc[c].im, v.im, sre));
                         sim = fma(acc[c].re, v.im, fma(-acc[c].im, v.re, sim));
                         sqq = fma(acc[c].re, acc[c].re, fma(acc[c].im, acc[c].im, sqq));
@@ -605,6 +621,35 @@ hipError_t launch_batch_ctl(const BatchCtlArgs &c, hipStream_t st)
 {
     if (c.nsys < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(batch_ctl_kernel, dim3((c.nsys + 255) / 256), dim3(256), 0, st, c);
+    return hipGetLastError();
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) batch_select_kernel(BatchBlasArgs a, const uint8_t *mask, int sel,
+                                                           const void *x_, void *y_)
+{
+    typedef typename Store<P>::S S;
+    typedef typename Store<P>::R R;
+    const S *x = (const S *)x_;
+    S *y = (S *)y_;
+    const size_t n = (size_t)a.Vtot * a.nrhs * 12;
+    for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (size_t)gridDim.x * blockDim.x) {
+        // j = fidx order: tile, RHS, component, lane
+        const int s = (int)((j >> 6) / ((size_t)a.nrhs * 12)) * 64 + (int)(j & 63);
+        stc(y, j, mask[s] == sel ? ldc(x, j) : cpx<R>{0, 0});
+    }
+}
+
+hipError_t launch_batch_select(int prec, const BatchBlasArgs &a, const uint8_t *mask, int sel, const void *x,
+                               void *y, hipStream_t st)
+{
+    dim3 g(a.grid), b(256);
+    switch (prec) {
+    case GRG_FP64: hipLaunchKernelGGL(batch_select_kernel<GRG_FP64>, g, b, 0, st, a, mask, sel, x, y); break;
+    case GRG_FP32: hipLaunchKernelGGL(batch_select_kernel<GRG_FP32>, g, b, 0, st, a, mask, sel, x, y); break;
+    case GRG_BF16: hipLaunchKernelGGL(batch_select_kernel<GRG_BF16>, g, b, 0, st, a, mask, sel, x, y); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
