@@ -56,15 +56,18 @@ struct grg_batch_s {
     long long *coff = nullptr;
     void *b64 = nullptr, *x64 = nullptr, *r64 = nullptr, *t64 = nullptr, *u64 = nullptr;
     void *in_b = nullptr, *in_x = nullptr, *in_r = nullptr, *in_q = nullptr;
-    // the even-odd reduced inner solve (every extent even, params.eo): per lattice
-    // the parity with fewer rest sites carries the reduced system; mask_eo is 1 on
-    // coarse sites, 0 / 2 on the rest sites of that parity / the other one; coef
-    // holds per lattice [1, 0, d, 1 / d, -1 / d] (d = 4 + m0) as five arrays;
-    // in_w the intermediate H_qp r, in_t the inner right-hand side's other-parity part
+    // the even-odd reduced inner solve (every extent even, params.eo) on compact
+    // half-lattice fields (BatchHalf): per lattice the parity with fewer rest
+    // sites carries the reduced system; coef holds per lattice [1, 0, d, 1 / d,
+    // -1 / d] (d = 4 + m0) as five arrays; the compact fields (inner precision):
+    // the reduced iterate, residual, A r and the intermediate H_qp r, the inner
+    // right-hand side's other parity b_q and the reconstructed e_q
     bool eo = false;
-    uint8_t *mask_eo = nullptr;
+    int Vh = 0;  // compact entries (a multiple of 256)
+    int *tile_lat_h = nullptr, *off_h = nullptr, *par_h = nullptr;
+    uint8_t *mask_h = nullptr;
     double *coef = nullptr;
-    void *in_w = nullptr, *in_t = nullptr;
+    void *hx = nullptr, *hr = nullptr, *hq = nullptr, *hw = nullptr, *hbq = nullptr, *heq = nullptr;
     double *partials = nullptr;
     double2 *alpha = nullptr;
     double *thr2 = nullptr, *fr2 = nullptr, *rn2i = nullptr;
@@ -141,28 +144,48 @@ static grg_status dslash(grg_batch B, int prec, const void *in, void *out, int s
     return GRG_OK;
 }
 
-// The reduced mode of the batched stencil on the rows mask_eo == sel:
-// out = c[ka] in2 + c[kb] H in per lattice (see BatchDslashArgs).
-static grg_status dslash_red(grg_batch B, int prec, const void *in, const void *in2, void *out, int sel, int ka,
-                             int kb, bool dots, bool keep, const int *act)
+static BatchHalf half(grg_batch B)
 {
-    BatchDslashArgs a;
-    a.act = act;
+    BatchHalf h;
+    h.tile_lat = B->tile_lat_h;
+    h.off = B->off_h;
+    h.par = B->par_h;
+    h.mask = B->mask_h;
+    h.Vtot = B->Vh;
+    return h;
+}
+
+static int hgrid(grg_batch B) { return round8(std::min<long>(B->Vh / 256, kBatchMaxGrid)); }
+
+// vector kernels over the compact fields
+static BatchBlasArgs blas_h(grg_batch B)
+{
+    BatchBlasArgs a = blas(B);
+    a.bt.tile_lat = B->tile_lat_h;
+    a.bt.off = B->off_h;
+    a.Vtot = B->Vh;
+    a.grid = hgrid(B);
+    return a;
+}
+
+// out = c[ka] in2 + c[kb] H in on side po of every lattice (BatchEoArgs)
+static grg_status eo_half(grg_batch B, int prec, const void *in, const void *in2, void *out, int po, int ka,
+                          int kb, bool dots, const int *act)
+{
+    BatchEoArgs a;
     a.in = in;
     a.in2 = in2;
     a.out = out;
     a.U = B->U[prec];
-    a.mask = B->mask_eo;
-    a.sel = sel;
     a.bt = table(B);
-    a.Vtot = B->Vtot;
+    a.hf = half(B);
+    a.po = po;
     a.nrhs = B->nrhs;
-    a.RG = B->RG[prec];
-    a.partials = dots ? B->partials : nullptr;
     a.ca = B->coef + (size_t)ka * B->nlat;
     a.cb = B->coef + (size_t)kb * B->nlat;
-    a.keep = keep ? 1 : 0;
-    GRG_TRY_HIP(launch_dslash_batch(prec, a, dgrid(B, prec), B->SB[prec], B->st));
+    a.partials = dots ? B->partials : nullptr;
+    a.act = act;
+    GRG_TRY_HIP(launch_batch_eo(prec, a, hgrid(B), B->st));
     return GRG_OK;
 }
 
@@ -200,17 +223,21 @@ static grg_status ctl(grg_batch B, bool init)
 // set (a no-op launch sequence once none is)
 static grg_status inner_step(grg_batch B, int prec)
 {
-    BatchBlasArgs a = blas(B);
+    BatchBlasArgs a = B->eo ? blas_h(B) : blas(B);
     a.act = B->active;
     a.ctr = B->ctr;
     if (B->eo) {
         // q = (d - H_pq H_qp / d) r on the reduced parity, with <q, r>, |q|^2
-        // (the other parity's rows of w and q stay zero: not written)
-        GRG_TRY(dslash_red(B, prec, B->in_r, nullptr, B->in_w, 2, kC0, kC1, false, true, B->active));
-        GRG_TRY(dslash_red(B, prec, B->in_w, B->in_r, B->in_q, 0, kCd, kCminv, true, true, B->active));
-    } else {
-        GRG_TRY(dslash(B, prec, B->in_r, B->in_q, 0, true, B->active));
+        GRG_TRY(eo_half(B, prec, B->hr, nullptr, B->hw, 1, kC0, kC1, false, B->active));
+        GRG_TRY(eo_half(B, prec, B->hw, B->hr, B->hq, 0, kCd, kCminv, true, B->active));
+        GRG_TRY_HIP(launch_batch_reduce(kAlpha, B->partials, hgrid(B), B->nsys, B->alpha, nullptr, nullptr,
+                                        B->active, nullptr, B->st));
+        GRG_TRY_HIP(launch_batch_mr_update(prec, a, B->hx, B->hr, B->hq, B->st));
+        GRG_TRY_HIP(launch_batch_reduce(kNorm, B->partials, a.grid, B->nsys, nullptr, B->rn2i, B->thr2,
+                                        B->active, B->active, B->st));
+        return GRG_OK;
     }
+    GRG_TRY(dslash(B, prec, B->in_r, B->in_q, 0, true, B->active));
     GRG_TRY_HIP(launch_batch_reduce(kAlpha, B->partials, dgrid(B, prec), B->nsys, B->alpha, nullptr, nullptr,
                                     B->active, nullptr, B->st));
     GRG_TRY_HIP(launch_batch_mr_update(prec, a, B->in_x, B->in_r, B->in_q, B->st));
@@ -233,12 +260,15 @@ static grg_status outer_step(grg_batch B, int prec, const void *r_src, const voi
     GRG_TRY_HIP(launch_batch_reduce(kNorm, B->partials, a.grid, B->nsys, nullptr, B->rn2i, B->thr2, B->oact,
                                     B->active, B->st));
     if (B->eo) {
-        // the reduced right-hand side b_p - H_pq b_q / d in place (b_q kept in
-        // in_t for the reconstruction), its |.|^2 setting the inner flags
-        GRG_TRY_HIP(launch_batch_select(prec, a, B->mask_eo, 2, B->in_r, B->in_t, B->st));
-        GRG_TRY(dslash_red(B, prec, B->in_t, B->in_r, B->in_r, 0, kC1, kCminv, true, false, B->oact));
-        GRG_TRY_HIP(launch_batch_reduce(kNorm3, B->partials, dgrid(B, prec), B->nsys, nullptr, B->rn2i, B->thr2,
+        // the halves b_p (into hq for the moment) and b_q of the inner right-hand
+        // side, the reduced right-hand side b_p - H_pq b_q / d into hr with its
+        // |.|^2 setting the inner flags, and the reduced iterate from zero
+        GRG_TRY_HIP(launch_batch_eo_split(prec, table(B), half(B), B->nrhs, B->in_r, B->hq, B->hbq, 0, hgrid(B),
+                                          B->st));
+        GRG_TRY(eo_half(B, prec, B->hbq, B->hq, B->hr, 0, kC1, kCminv, true, B->oact));
+        GRG_TRY_HIP(launch_batch_reduce(kNorm3, B->partials, hgrid(B), B->nsys, nullptr, B->rn2i, B->thr2,
                                         B->oact, B->active, B->st));
+        GRG_TRY_HIP(launch_fill_zero(B->hx, (size_t)B->Vh * B->nrhs * 12 * prec_bytes(prec), B->st));
     }
     int it = 0;
     if (eager) {
@@ -258,9 +288,11 @@ static grg_status outer_step(grg_batch B, int prec, const void *r_src, const voi
         for (int k = 0; k < n_inner; ++k) GRG_TRY(inner_step(B, prec));
     }
     if (B->eo) {
-        // the other parity of the correction, e_q = (b_q - H_qp e_p) / d,
-        // into in_x beside e_p
-        GRG_TRY(dslash_red(B, prec, B->in_x, B->in_t, B->in_x, 2, kCinv, kCminv, false, true, B->oact));
+        // the other parity of the correction, e_q = (b_q - H_qp e_p) / d, and
+        // both halves into the full-layout correction in_x
+        GRG_TRY(eo_half(B, prec, B->hx, B->hbq, B->heq, 1, kCinv, kCminv, false, B->oact));
+        GRG_TRY_HIP(launch_batch_eo_split(prec, table(B), half(B), B->nrhs, B->in_x, B->hx, B->heq, 1, hgrid(B),
+                                          B->st));
     }
     BatchDcArgs d;
     d.e = B->in_x;
@@ -483,10 +515,12 @@ static void batch_free(grg_batch B)
     f(B->in_x);
     f(B->in_r);
     f(B->in_q);
-    f(B->mask_eo);
+    f(B->tile_lat_h);
+    f(B->off_h);
+    f(B->par_h);
+    f(B->mask_h);
     f(B->coef);
-    f(B->in_w);
-    f(B->in_t);
+    for (void *p : {B->hx, B->hr, B->hq, B->hw, B->hbq, B->heq}) f(p);
     f(B->partials);
     f(B->alpha);
     f(B->dsc);  // rn2, bn2, the counters and the inner flags
@@ -604,9 +638,18 @@ grg_status grg_batch_create(const grg_batch_member *m, int count, int nrhs,
     for (int i = 0; i < count && eo; ++i)
         for (int mu = 0; mu < 4; ++mu)
             if (mem[i].dims[mu] % 2) eo = false;
-    std::vector<uint8_t> mask_eo(eo ? Vtot : 0);
+    // compact halves: lattice i's block of V / 2 half-sites, padded to 256
+    std::vector<int> off_h(count), par_h(count), tile_lat_h;
+    std::vector<uint8_t> mask_h;
     std::vector<double> coef(eo ? 5 * (size_t)count : 0);
+    long Vh = 0;
     if (eo) {
+        for (int i = 0; i < count; ++i) {
+            off_h[i] = (int)Vh;
+            Vh += (mem[i].V / 2 + 255) / 256 * 256;
+        }
+        tile_lat_h.assign(Vh / 64, 0);
+        mask_h.assign(2 * (size_t)Vh, 1);  // padding masked
         for (int i = 0; i < count; ++i) {
             const BatchMember &b = mem[i];
             long rest[2] = {0, 0};
@@ -622,8 +665,16 @@ grg_status grg_batch_create(const grg_batch_member *m, int count, int nrhs,
             }
             // the reduced system on the parity with fewer rest sites (as one lattice)
             const int p = rest[0] < rest[1] ? 0 : 1;
-            for (int x = 0; x < b.V; ++x)
-                mask_eo[b.off + x] = mask[b.off + x] ? 1 : (par[x] == p ? 0 : 2);
+            par_h[i] = p;
+            const int nblk = (b.V / 2 + 255) / 256 * 256;
+            for (int t = 0; t < nblk / 64; ++t) tile_lat_h[off_h[i] / 64 + t] = i;
+            // side 0: the sites of parity p, side 1: the others (pair 2h, 2h + 1)
+            for (int h = 0; h < b.V / 2; ++h)
+                for (int k = 0; k < 2; ++k) {
+                    const int x = 2 * h + k;
+                    const int side = par[x] == p ? 0 : 1;
+                    mask_h[(size_t)side * Vh + off_h[i] + h] = mask[b.off + x];
+                }
             const double d = diag[i];
             coef[kC1 * (size_t)count + i] = 1.0;
             coef[kC0 * (size_t)count + i] = 0.0;
@@ -656,11 +707,15 @@ grg_status grg_batch_create(const grg_batch_member *m, int count, int nrhs,
     for (void **p : {&B->b64, &B->x64, &B->r64, &B->t64, &B->u64}) al(p, f64);
     for (void **p : {&B->in_b, &B->in_x, &B->in_r, &B->in_q}) al(p, fin);
     B->eo = eo;
+    B->Vh = (int)Vh;
+    const size_t fh = (size_t)Vh * nrhs * 12 * prec_bytes(prm.inner);
     if (eo) {
-        al((void **)&B->mask_eo, Vtot);
+        al((void **)&B->tile_lat_h, sizeof(int) * (Vh / 64));
+        al((void **)&B->off_h, sizeof(int) * count);
+        al((void **)&B->par_h, sizeof(int) * count);
+        al((void **)&B->mask_h, 2 * (size_t)Vh);
         al((void **)&B->coef, sizeof(double) * 5 * count);
-        al(&B->in_w, fin);
-        al(&B->in_t, fin);
+        for (void **p : {&B->hx, &B->hr, &B->hq, &B->hw, &B->hbq, &B->heq}) al(p, fh);
     }
     al((void **)&B->partials, sizeof(double) * kBatchMaxGrid * B->nsys * 3);
     al((void **)&B->alpha, sizeof(double2) * B->nsys);
@@ -704,14 +759,18 @@ grg_status grg_batch_create(const grg_batch_member *m, int count, int nrhs,
     UP(B->diag, diag.data(), sizeof(double) * count);
     UP(B->coff, coffs.data(), sizeof(long long) * count);
     if (eo) {
-        UP(B->mask_eo, mask_eo.data(), Vtot);
+        UP(B->tile_lat_h, tile_lat_h.data(), sizeof(int) * (Vh / 64));
+        UP(B->off_h, off_h.data(), sizeof(int) * count);
+        UP(B->par_h, par_h.data(), sizeof(int) * count);
+        UP(B->mask_h, mask_h.data(), 2 * (size_t)Vh);
         UP(B->coef, coef.data(), sizeof(double) * 5 * count);
     }
     GRG_TRY_HIP(hipStreamSynchronize(st));
 #undef UP
     for (void *p : {B->b64, B->x64, B->r64, B->t64, B->u64}) GRG_TRY_HIP(launch_fill_zero(p, f64, st));
-    for (void *p : {B->in_b, B->in_x, B->in_r, B->in_q, B->in_w, B->in_t})
-        if (p) GRG_TRY_HIP(launch_fill_zero(p, fin, st));
+    for (void *p : {B->in_b, B->in_x, B->in_r, B->in_q}) GRG_TRY_HIP(launch_fill_zero(p, fin, st));
+    for (void *p : {B->hx, B->hr, B->hq, B->hw, B->hbq, B->heq})
+        if (p) GRG_TRY_HIP(launch_fill_zero(p, fh, st));
     GRG_TRY_HIP(launch_fill_zero(B->dsc, B->dsc_bytes, st));
     GRG_TRY_HIP(launch_fill_zero(B->oact, sizeof(int) * B->nsys, st));
     // links, one member at a time through a staging buffer
@@ -871,13 +930,6 @@ grg_status grg_batch_tune(grg_batch B)
     if (B->graph) {
         (void)hipGraphExecDestroy(B->graph);  // launch shapes are baked into the graph
         B->graph = nullptr;
-    }
-    // the reduced inner solve writes only its own rows of q and w: the rows of
-    // the other parity must read zero, as at creation
-    if (B->eo) {
-        const size_t fin = spinor_elems(B->gtot, B->nrhs) * prec_bytes(B->prm.inner);
-        GRG_TRY_HIP(launch_fill_zero(B->in_q, fin, B->st));
-        GRG_TRY_HIP(launch_fill_zero(B->in_w, fin, B->st));
     }
     return GRG_OK;
 }

@@ -18,8 +18,7 @@ struct BatchDslashArgs {
     const void *in;
     void *out;
     const void *U;
-    const uint8_t *mask;  // 1 on coarse sites (the reduced mode: 0 / 2 on the rest sites of the
-                          // reduced parity / the other parity)
+    const uint8_t *mask;  // 1 on coarse sites
     int sel;              // rows kept: mask[s] == sel
     BatchTable bt;
     int Vtot;             // total sites (a multiple of 256)
@@ -28,13 +27,6 @@ struct BatchDslashArgs {
     double *partials;     // [grid][nlat * nrhs][3] or nullptr
     const int *act;       // per-system flags, or nullptr: with flags, systems whose flag is 0
                           // are skipped and a launch with no flag set returns at once
-    // the even-odd reduced mode (ca != nullptr): out = ca[l] in2 + cb[l] H in on the
-    // kept rows, H the hopping term of D (no diagonal), in2 == nullptr read as zero;
-    // the fused sums are taken with in2; with keep, rows not kept are left as they are
-    // (else written as zero)
-    const void *in2 = nullptr;
-    const double *ca = nullptr, *cb = nullptr;
-    int keep = 0;
 };
 
 struct BatchBlasArgs {
@@ -107,9 +99,44 @@ hipError_t launch_batch_reduce(int mode, const double *partials, int nparts, int
 hipError_t launch_batch_ctl(const BatchCtlArgs &c, hipStream_t st);
 // y = x - y (FP64, every site and RHS)
 hipError_t launch_batch_xmy(const BatchBlasArgs &a, const void *x, void *y, hipStream_t st);
-// y = x on the sites with mask[s] == sel, zero elsewhere (every RHS, precision prec)
-hipError_t launch_batch_select(int prec, const BatchBlasArgs &a, const uint8_t *mask, int sel, const void *x,
-                               void *y, hipStream_t st);
+
+// The even-odd reduced form of every lattice's D_rr on compact half-lattice
+// fields.  Each lattice's half-sites h (the site pair 2h, 2h + 1 of opposite
+// parities: Lx is even) form a block of its own, starting on a 256 boundary
+// (padded: entries past V / 2 are zero and stay zero); within a block the
+// field of one parity holds at h the site of that parity.  par[l] is the
+// parity of lattice l's reduced system (its rest sites there are the fewer).
+struct BatchHalf {
+    const int *tile_lat;  // lattice of every 64-entry compact tile
+    const int *off;       // first compact entry of every lattice
+    const int *par;       // the reduced parity per lattice
+    const uint8_t *mask;  // [2][Vtot]: 1 on coarse sites and padding, per output side (below)
+    int Vtot;             // compact entries of the whole batch (a multiple of 256)
+};
+
+// out = ca[l] in2 + cb[l] H in on the output side po (0: each lattice's reduced
+// parity, 1: the other), H the hopping term of D (no diagonal); in is a field
+// of the other side, in2 one of side po (nullptr: zero).  Rows on coarse
+// sites and padding are written as zero.  With partials, the fused sums
+// <out, in2>, |out|^2 per system; act as in BatchDslashArgs.
+struct BatchEoArgs {
+    const void *in, *in2;
+    void *out;
+    const void *U;        // full-layout links of the batch, in the stencil's precision
+    BatchTable bt;        // the full layout (extents, first sites, lattices of full tiles)
+    BatchHalf hf;
+    int po;
+    int nrhs;
+    const double *ca, *cb;  // per lattice
+    double *partials;       // [grid][nsys][3] or nullptr
+    const int *act;
+};
+hipError_t launch_batch_eo(int prec, const BatchEoArgs &a, int grid, hipStream_t st);
+// full-layout field x -> its two halves (xp on each lattice's reduced parity,
+// xq on the other), zero on padding; with to_full, the reverse (every site of
+// the full field written from the halves)
+hipError_t launch_batch_eo_split(int prec, const BatchTable &bt, const BatchHalf &hf, int nrhs, void *x,
+                                 void *xp, void *xq, int to_full, int grid, hipStream_t st);
 hipError_t launch_batch_coarse(const BatchTable &bt, const void *in, const void *U, double *yb,
                                const int32_t *qg, const int *clat, const int *nb, const int *nboff,
                                const long long *coff, int nbtot, int nrhs, hipStream_t st);

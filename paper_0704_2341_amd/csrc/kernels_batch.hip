@@ -83,9 +83,6 @@ __device__ bool any_set(const int *flags, int n)
 }
 
 // out = mask_sel D in over all lattices; fused dots per system when partials.
-// The reduced mode (a.ca set): out = ca in2 + cb H in per lattice on the kept
-// rows (the two half-steps of d - H_pq H_qp / d, the reduced right-hand side
-// and the reconstruction of the other parity), the sums taken with in2.
 template <int P>
 __global__ void __launch_bounds__(256) dslash_batch_kernel(BatchDslashArgs a)
 {
@@ -93,10 +90,8 @@ __global__ void __launch_bounds__(256) dslash_batch_kernel(BatchDslashArgs a)
     typedef typename Store<P>::R R;
     extern __shared__ double smem[];
     const S *__restrict__ in = (const S *)a.in;
-    const S *in2 = (const S *)a.in2;  // may alias out (read before the write of the same element)
-    S *out = (S *)a.out;
+    S *__restrict__ out = (S *)a.out;
     const S *__restrict__ U = (const S *)a.U;
-    const bool red = a.ca != nullptr;
     const int nsys = a.bt.nlat * a.nrhs;
     if (a.act && !any_set(a.act, nsys)) return;
     const bool dots = a.partials != nullptr;
@@ -111,8 +106,7 @@ __global__ void __launch_bounds__(256) dslash_batch_kernel(BatchDslashArgs a)
         const BSite b = bsite(a.bt, s);
         const bool on = a.mask[s] == a.sel;
         const SiteGeo q = site_geo(b.local, b.g);
-        const R diag = red ? (R)0 : (R)a.bt.diag[b.l];
-        const R ca = red ? (R)a.ca[b.l] : (R)0, cb = red ? (R)a.cb[b.l] : (R)0;
+        const R diag = (R)a.bt.diag[b.l];
         const int r0 = grp * a.RG, r1 = min(r0 + a.RG, a.nrhs);
         for (int r = r0; r < r1; ++r) {
             // (a workgroup lies inside one lattice: the skip is uniform)
@@ -120,28 +114,18 @@ __global__ void __launch_bounds__(256) dslash_batch_kernel(BatchDslashArgs a)
             cpx<R> acc[12];
             if (on) {
                 dslash_site<S, R, true>(acc, in, U, s, q, b.g, r, a.nrhs, diag);
-                if (red) {
-#pragma unroll
-                    for (int c = 0; c < 12; ++c) {
-                        const cpx<R> v2 = in2 ? ldc(in2, fidx(s, r, c, a.nrhs)) : cpx<R>{0, 0};
-                        acc[c] = {ca * v2.re + cb * acc[c].re, ca * v2.im + cb * acc[c].im};
-                    }
-                }
             } else {
 #pragma unroll
                 for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
             }
-            if (on || !(red && a.keep)) {
 #pragma unroll
-                for (int c = 0; c < 12; ++c) stc(out, fidx(s, r, c, a.nrhs), acc[c]);
-            }
+            for (int c = 0; c < 12; ++c) stc(out, fidx(s, r, c, a.nrhs), acc[c]);
             if (dots) {
                 R sre = 0, sim = 0, sqq = 0;
                 if (on) {
-                    const S *dv = red ? in2 : in;
 #pragma unroll
                     for (int c = 0; c < 12; ++c) {
-                        const cpx<R> v = dv ? ldc(dv, fidx(s, r, c, a.nrhs)) : cpx<R>{0, 0};
+                        const cpx<R> v = ldc(in, fidx(s, r, c, a.nrhs));
                         sre = fma(acc[c].re, v.re, fma(acc[c].im, v.im, sre));
                         sim = fma(acc[c].re, v.im, fma(-acc[c].im, v.re, sim));
                         sqq = fma(acc[c].re, acc[c].re, fma(acc[c].im, acc[c].im, sqq));
@@ -520,6 +504,173 @@ __global__ void __launch_bounds__(256) batch_xmy_kernel(BatchBlasArgs a, const d
 // ------------------------------------------------------------------ launchers
 static size_t lds_sys(int nsys, int K) { return (size_t)4 * nsys * K * sizeof(double); }
 
+// ------------------------------------------------------------------ even-odd reduced form
+// The site of side po (0: the lattice's reduced parity, 1: the other) at
+// half-site h: 2h and 2h + 1 differ in parity (Lx even), 2h having the
+// parity of y + z + t.
+__device__ __forceinline__ int half_site(int h, int4 d, int parity)
+{
+    const int t1 = (2 * h) / d.x;
+    const int y = t1 % d.y, t2 = t1 / d.y;
+    const int z = t2 % d.z, t = t2 / d.z;
+    return 2 * h + ((parity ^ (y + z + t)) & 1);
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) batch_eo_kernel(BatchEoArgs a)
+{
+    typedef typename Store<P>::S S;
+    typedef typename Store<P>::R R;
+    typedef Operand<S, R> OP;
+    typedef typename OP::T PT;
+    extern __shared__ double smem[];
+    const S *__restrict__ in = (const S *)a.in;
+    const S *__restrict__ in2 = (const S *)a.in2;
+    S *__restrict__ out = (S *)a.out;
+    const S *__restrict__ U = (const S *)a.U;
+    const int nsys = a.bt.nlat * a.nrhs;
+    if (a.act && !any_set(a.act, nsys)) return;
+    const bool dots = a.partials != nullptr;
+    SysPartial<3> part;
+    if (dots) part.init(smem, nsys);
+    const uint8_t *mk = a.hf.mask + (size_t)a.po * a.hf.Vtot;
+    const ItemRange it = xcd_items(a.hf.Vtot / 256);
+    for (int w = it.begin; w < it.end; w += it.step) {
+        const int H = w * 256 + (int)threadIdx.x;
+        const int l = a.hf.tile_lat[H >> 6];  // a block of 256 lies in one lattice
+        const int4 d = a.bt.dims[l];
+        Geom g;
+        g.L[0] = d.x;
+        g.L[1] = d.y;
+        g.L[2] = d.z;
+        g.L[3] = d.w;
+        g.V = g.Vs = d.x * d.y * d.z * d.w;
+        const bool on = mk[H] == 0;  // rest site (coarse sites and padding are masked)
+        const int par = a.po ? 1 - a.hf.par[l] : a.hf.par[l];
+        const int s = half_site(on ? H - a.hf.off[l] : 0, d, par);  // local full site
+        const SiteGeo q = site_geo(s, g);
+        const int fo = a.bt.off[l], co = a.hf.off[l];
+        const R ca = (R)a.ca[l], cb = (R)a.cb[l];
+        for (int r = 0; r < a.nrhs; ++r) {
+            if (a.act && !a.act[l * a.nrhs + r]) continue;  // uniform (one lattice)
+            cpx<R> acc[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
+            if (on) {
+#pragma unroll 1
+                for (int hp = 0; hp < 8; ++hp) {
+                    const int mu = hp >> 1;
+                    int sp, sm;
+                    nbr(s, mu, q, g, sp, sm);
+                    // the neighbour (other side) at its half-site index
+                    const int n = co + (((hp & 1) ? sm : sp) >> 1);
+                    PT p[12], u[9];
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) p[c] = OP::load(in, fidx(n, r, c, a.nrhs));
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) u[e] = OP::load(U, lidx(fo + ((hp & 1) ? sm : s), mu, e));
+                    switch (hp) {
+                    case 0: hop<0, true>(acc, p, u); break;
+                    case 1: hop<0, false>(acc, p, u); break;
+                    case 2: hop<1, true>(acc, p, u); break;
+                    case 3: hop<1, false>(acc, p, u); break;
+                    case 4: hop<2, true>(acc, p, u); break;
+                    case 5: hop<2, false>(acc, p, u); break;
+                    case 6: hop<3, true>(acc, p, u); break;
+                    default: hop<3, false>(acc, p, u); break;
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    const cpx<R> v2 = in2 ? ldc(in2, fidx(H, r, c, a.nrhs)) : cpx<R>{0, 0};
+                    acc[c] = {ca * v2.re + cb * acc[c].re, ca * v2.im + cb * acc[c].im};
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 12; ++c) stc(out, fidx(H, r, c, a.nrhs), acc[c]);
+            if (dots) {
+                R sre = 0, sim = 0, sqq = 0;
+                if (on) {
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) {
+                        const cpx<R> v = in2 ? ldc(in2, fidx(H, r, c, a.nrhs)) : cpx<R>{0, 0};
+                        sre = fma(acc[c].re, v.re, fma(acc[c].im, v.im, sre));
+                        sim = fma(acc[c].re, v.im, fma(-acc[c].im, v.re, sim));
+                        sqq = fma(acc[c].re, acc[c].re, fma(acc[c].im, acc[c].im, sqq));
+                    }
+                }
+                const double dd[3] = {(double)sre, (double)sim, (double)sqq};
+                part.add(l * a.nrhs + r, dd);
+            }
+        }
+    }
+    if (dots) part.flush(a.partials);
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) batch_eo_split_kernel(BatchTable bt, BatchHalf hf, int nrhs, void *x_,
+                                                             void *xp_, void *xq_, int to_full)
+{
+    typedef typename Store<P>::S S;
+    S *x = (S *)x_, *xp = (S *)xp_, *xq = (S *)xq_;
+    const size_t n = (size_t)hf.Vtot * nrhs * 12;
+    for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (size_t)gridDim.x * blockDim.x) {
+        // j = fidx(H, r, c): compact tile, RHS, component, lane
+        const size_t rest = j >> 6;
+        const int tile = (int)(rest / ((size_t)nrhs * 12)), rc = (int)(rest - (size_t)tile * nrhs * 12);
+        const int r = rc / 12, c = rc - r * 12;
+        const int H = tile * 64 + (int)(j & 63);
+        const int l = hf.tile_lat[tile];
+        const int4 d = bt.dims[l];
+        const int h = H - hf.off[l];
+        const bool valid = 2 * h < d.x * d.y * d.z * d.w;
+        const int sp = half_site(valid ? h : 0, d, hf.par[l]);
+        const int sq = sp ^ 1;  // the other site of the pair
+        const size_t gp = fidx(bt.off[l] + sp, r, c, nrhs), gq = fidx(bt.off[l] + sq, r, c, nrhs);
+        if (!to_full) {
+            const S zero = {};
+            xp[j] = valid ? x[gp] : zero;
+            xq[j] = valid ? x[gq] : zero;
+        } else if (valid) {
+            x[gp] = xp[j];
+            x[gq] = xq[j];
+        }
+    }
+}
+
+hipError_t launch_batch_eo(int prec, const BatchEoArgs &a, int grid, hipStream_t st)
+{
+    const size_t lds = a.partials ? lds_sys(a.bt.nlat * a.nrhs, 3) : 0;
+    switch (prec) {
+    case GRG_FP64: hipLaunchKernelGGL(batch_eo_kernel<GRG_FP64>, dim3(grid), dim3(256), lds, st, a); break;
+    case GRG_FP32: hipLaunchKernelGGL(batch_eo_kernel<GRG_FP32>, dim3(grid), dim3(256), lds, st, a); break;
+    case GRG_BF16: hipLaunchKernelGGL(batch_eo_kernel<GRG_BF16>, dim3(grid), dim3(256), lds, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_eo_split(int prec, const BatchTable &bt, const BatchHalf &hf, int nrhs, void *x,
+                                 void *xp, void *xq, int to_full, int grid, hipStream_t st)
+{
+    switch (prec) {
+    case GRG_FP64:
+        hipLaunchKernelGGL(batch_eo_split_kernel<GRG_FP64>, dim3(grid), dim3(256), 0, st, bt, hf, nrhs, x, xp, xq,
+                           to_full);
+        break;
+    case GRG_FP32:
+        hipLaunchKernelGGL(batch_eo_split_kernel<GRG_FP32>, dim3(grid), dim3(256), 0, st, bt, hf, nrhs, x, xp, xq,
+                           to_full);
+        break;
+    case GRG_BF16:
+        hipLaunchKernelGGL(batch_eo_split_kernel<GRG_BF16>, dim3(grid), dim3(256), 0, st, bt, hf, nrhs, x, xp, xq,
+                           to_full);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_dslash_batch(int prec, const BatchDslashArgs &a, int grid, int SB, hipStream_t st)
 {
     if (SB != 64 && SB != 128 && SB != 256) return hipErrorInvalidValue;
@@ -621,35 +772,6 @@ hipError_t launch_batch_ctl(const BatchCtlArgs &c, hipStream_t st)
 {
     if (c.nsys < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(batch_ctl_kernel, dim3((c.nsys + 255) / 256), dim3(256), 0, st, c);
-    return hipGetLastError();
-}
-
-template <int P>
-__global__ void __launch_bounds__(256) batch_select_kernel(BatchBlasArgs a, const uint8_t *mask, int sel,
-                                                           const void *x_, void *y_)
-{
-    typedef typename Store<P>::S S;
-    typedef typename Store<P>::R R;
-    const S *x = (const S *)x_;
-    S *y = (S *)y_;
-    const size_t n = (size_t)a.Vtot * a.nrhs * 12;
-    for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (size_t)gridDim.x * blockDim.x) {
-        // j = fidx order: tile, RHS, component, lane
-        const int s = (int)((j >> 6) / ((size_t)a.nrhs * 12)) * 64 + (int)(j & 63);
-        stc(y, j, mask[s] == sel ? ldc(x, j) : cpx<R>{0, 0});
-    }
-}
-
-hipError_t launch_batch_select(int prec, const BatchBlasArgs &a, const uint8_t *mask, int sel, const void *x,
-                               void *y, hipStream_t st)
-{
-    dim3 g(a.grid), b(256);
-    switch (prec) {
-    case GRG_FP64: hipLaunchKernelGGL(batch_select_kernel<GRG_FP64>, g, b, 0, st, a, mask, sel, x, y); break;
-    case GRG_FP32: hipLaunchKernelGGL(batch_select_kernel<GRG_FP32>, g, b, 0, st, a, mask, sel, x, y); break;
-    case GRG_BF16: hipLaunchKernelGGL(batch_select_kernel<GRG_BF16>, g, b, 0, st, a, mask, sel, x, y); break;
-    default: return hipErrorInvalidValue;
-    }
     return hipGetLastError();
 }
 
