@@ -514,8 +514,11 @@ grg_status grg_batch_graph_info(grg_batch b, int32_t counts[2]);
 /* The batched stencil launch in use for a precision, info = {sites per
  * workgroup, RHS per thread, workgroups}, and from the last grg_batch_tune
  * the time per launch (HIP events on the batch's stream, every system
- * active) of that stencil (ms[0]) and, for the inner precision, of the MR
- * update (ms[1]); -1 where not timed. */
+ * active) of the stencil the solve runs in that precision (ms[0]: for the
+ * inner precision with the even-odd reduced solve, one half-step of the
+ * reduced operator on the compact fields, the average of its two halves)
+ * and, for the inner precision, of the MR update (ms[1], on the compact
+ * fields with the reduced solve); -1 where not timed. */
 grg_status grg_batch_tune_info(grg_batch b, int precision, int32_t info[3], float ms[2]);
 
 /* Kernel timing: with profiling on, every dslash launch and every phase of

@@ -83,6 +83,7 @@ struct grg_batch_s {
     int SB[3] = {64, 64, 64}, RG[3] = {1, 1, 1}, grid[3] = {0, 0, 0};
     float tune_ms[3] = {-1, -1, -1};  // tuned stencil time per launch (every system), per precision
     float upd_ms = -1;                // the inner precision's MR update (every system)
+    float eo_ms = -1;                 // with the reduced solve: one half-step (average of the two)
     hipGraphExec_t graph = nullptr;
     int g_outer = 0, g_inner = 0;  // counts the graph was captured with
     int e_outer = 0, e_inner = 0;  // counts the last eager apply needed
@@ -854,8 +855,9 @@ grg_status grg_batch_tune_info(grg_batch B, int precision, int32_t info[3], floa
     info[0] = B->SB[precision];
     info[1] = B->RG[precision];
     info[2] = dgrid(B, precision);
-    ms[0] = B->tune_ms[precision];
-    ms[1] = precision == B->prm.inner ? B->upd_ms : -1.0f;
+    const bool inner = precision == B->prm.inner;
+    ms[0] = inner && B->eo ? B->eo_ms : B->tune_ms[precision];
+    ms[1] = inner ? B->upd_ms : -1.0f;
     return GRG_OK;
 }
 
@@ -910,14 +912,31 @@ grg_status grg_batch_tune(grg_batch B)
         B->grid[prec] = bgrid;
         B->tune_ms[prec] = best;
     }
-    {
-        // the inner precision's MR update over every system (x += alpha r,
-        // r -= alpha q with the step lengths in place; overwrites workspaces)
+    if (B->eo) {
+        // the reduced operator's two half-steps as the inner solve runs them
+        // (every system; overwrites workspaces)
         const int prec = B->prm.inner;
-        const BatchBlasArgs a = blas(B);
         for (int k = 0; k < 4; ++k) {
             if (k == 1) GRG_TRY_HIP(hipEventRecord(e0, B->st));
-            GRG_TRY_HIP(launch_batch_mr_update(prec, a, B->in_x, B->in_r, B->in_q, B->st));
+            GRG_TRY(eo_half(B, prec, B->hr, nullptr, B->hw, 1, kC0, kC1, false, nullptr));
+            GRG_TRY(eo_half(B, prec, B->hw, B->hr, B->hq, 0, kCd, kCminv, true, nullptr));
+        }
+        GRG_TRY_HIP(hipEventRecord(e1, B->st));
+        GRG_TRY_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        B->eo_ms = ms / 6;
+    }
+    {
+        // the inner precision's MR update over every system (x += alpha r,
+        // r -= alpha q with the step lengths in place; overwrites workspaces),
+        // on the compact fields with the reduced solve
+        const int prec = B->prm.inner;
+        const BatchBlasArgs a = B->eo ? blas_h(B) : blas(B);
+        void *ux = B->eo ? B->hx : B->in_x, *ur = B->eo ? B->hr : B->in_r, *uq = B->eo ? B->hq : B->in_q;
+        for (int k = 0; k < 4; ++k) {
+            if (k == 1) GRG_TRY_HIP(hipEventRecord(e0, B->st));
+            GRG_TRY_HIP(launch_batch_mr_update(prec, a, ux, ur, uq, B->st));
         }
         GRG_TRY_HIP(hipEventRecord(e1, B->st));
         GRG_TRY_HIP(hipEventSynchronize(e1));
