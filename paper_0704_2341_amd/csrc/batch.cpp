@@ -157,6 +157,8 @@ static BatchHalf half(grg_batch B)
 }
 
 static int hgrid(grg_batch B) { return round8(std::min<long>(B->Vh / 256, kBatchMaxGrid)); }
+// the half-step's grid (its items: a block of 256 half-sites with one RHS)
+static int egrid(grg_batch B) { return round8(std::min<long>((long)B->Vh / 256 * B->nrhs, kBatchMaxGrid)); }
 
 // vector kernels over the compact fields
 static BatchBlasArgs blas_h(grg_batch B)
@@ -186,7 +188,7 @@ static grg_status eo_half(grg_batch B, int prec, const void *in, const void *in2
     a.cb = B->coef + (size_t)kb * B->nlat;
     a.partials = dots ? B->partials : nullptr;
     a.act = act;
-    GRG_TRY_HIP(launch_batch_eo(prec, a, hgrid(B), B->st));
+    GRG_TRY_HIP(launch_batch_eo(prec, a, egrid(B), B->st));
     return GRG_OK;
 }
 
@@ -231,7 +233,7 @@ static grg_status inner_step(grg_batch B, int prec)
         // q = (d - H_pq H_qp / d) r on the reduced parity, with <q, r>, |q|^2
         GRG_TRY(eo_half(B, prec, B->hr, nullptr, B->hw, 1, kC0, kC1, false, B->active));
         GRG_TRY(eo_half(B, prec, B->hw, B->hr, B->hq, 0, kCd, kCminv, true, B->active));
-        GRG_TRY_HIP(launch_batch_reduce(kAlpha, B->partials, hgrid(B), B->nsys, B->alpha, nullptr, nullptr,
+        GRG_TRY_HIP(launch_batch_reduce(kAlpha, B->partials, egrid(B), B->nsys, B->alpha, nullptr, nullptr,
                                         B->active, nullptr, B->st));
         GRG_TRY_HIP(launch_batch_mr_update(prec, a, B->hx, B->hr, B->hq, B->st));
         GRG_TRY_HIP(launch_batch_reduce(kNorm, B->partials, a.grid, B->nsys, nullptr, B->rn2i, B->thr2,
@@ -267,7 +269,7 @@ static grg_status outer_step(grg_batch B, int prec, const void *r_src, const voi
         GRG_TRY_HIP(launch_batch_eo_split(prec, table(B), half(B), B->nrhs, B->in_r, B->hq, B->hbq, 0, hgrid(B),
                                           B->st));
         GRG_TRY(eo_half(B, prec, B->hbq, B->hq, B->hr, 0, kC1, kCminv, true, B->oact));
-        GRG_TRY_HIP(launch_batch_reduce(kNorm3, B->partials, hgrid(B), B->nsys, nullptr, B->rn2i, B->thr2,
+        GRG_TRY_HIP(launch_batch_reduce(kNorm3, B->partials, egrid(B), B->nsys, nullptr, B->rn2i, B->thr2,
                                         B->oact, B->active, B->st));
         GRG_TRY_HIP(launch_fill_zero(B->hx, (size_t)B->Vh * B->nrhs * 12 * prec_bytes(prec), B->st));
     }

@@ -534,9 +534,12 @@ __global__ void __launch_bounds__(256) batch_eo_kernel(BatchEoArgs a)
     SysPartial<3> part;
     if (dots) part.init(smem, nsys);
     const uint8_t *mk = a.hf.mask + (size_t)a.po * a.hf.Vtot;
-    const ItemRange it = xcd_items(a.hf.Vtot / 256);
+    // work items: a block of 256 half-sites with one RHS (the RHS of a block
+    // adjacent, so that they share its links in L2)
+    const ItemRange it = xcd_items(a.hf.Vtot / 256 * a.nrhs);
     for (int w = it.begin; w < it.end; w += it.step) {
-        const int H = w * 256 + (int)threadIdx.x;
+        const int blk = w / a.nrhs, r = w - blk * a.nrhs;
+        const int H = blk * 256 + (int)threadIdx.x;
         const int l = a.hf.tile_lat[H >> 6];  // a block of 256 lies in one lattice
         const int4 d = a.bt.dims[l];
         Geom g;
@@ -551,8 +554,8 @@ __global__ void __launch_bounds__(256) batch_eo_kernel(BatchEoArgs a)
         const SiteGeo q = site_geo(s, g);
         const int fo = a.bt.off[l], co = a.hf.off[l];
         const R ca = (R)a.ca[l], cb = (R)a.cb[l];
-        for (int r = 0; r < a.nrhs; ++r) {
-            if (a.act && !a.act[l * a.nrhs + r]) continue;  // uniform (one lattice)
+        {
+            if (a.act && !a.act[l * a.nrhs + r]) continue;  // uniform (one lattice, one RHS)
             cpx<R> acc[12];
 #pragma unroll
             for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
