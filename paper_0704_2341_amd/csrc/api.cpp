@@ -258,6 +258,7 @@ grg_status grg_gauge_set(grg_lattice L, const double *links, int on_device)
         L->tmp_links = nullptr;
     }
     L->gauge_set = true;
+    ++L->gauge_version;
     return GRG_OK;
 }
 

@@ -17,6 +17,7 @@ struct grg_lattice_s {
     int Vhs = 0;
     void *Ueo[3] = {nullptr, nullptr, nullptr};
     bool gauge_set = false;
+    int gauge_version = 0;  // incremented by every grg_gauge_set (caches derived from the links)
     // grow-only scratch of grg_dirac_apply
     void *tmp_in = nullptr, *tmp_out = nullptr;
     size_t tmp_bytes = 0;
@@ -108,8 +109,10 @@ struct grg_schur_s {
     int in_m[3] = {0, 0, 0};
     // coarse-space staging for assembly
     double *cb_in = nullptr, *cb_out = nullptr;
-    // row sums of D_rr (one FP64 field) for the section 3 approximation
+    // row sums of D_rr (one FP64 field) for the section 3 approximation, and
+    // the lattice's gauge_version they were computed from (-1: not yet)
     void *dt64 = nullptr;
+    int dt_version = -1;
     // even-odd reduced inner solve: mask per parity ([2][Vhs]), the parity of
     // the reduced system, and compact fields per inner precision: r, x, q
     // (reduced parity), w (other parity) and the preconditioned direction p

@@ -1535,8 +1535,12 @@ grg_status reusken_apply_internal(grg_schur S, const double *xb, double *yb, int
         set_error("row-sum field: hipMalloc failed");
         return GRG_ENOMEM;
     }
-    GRG_TRY_HIP(launch_rest_ones(g, S->d_mask, S->t64, st));
-    GRG_TRY(run_dslash(S, GRG_FP64, S->t64, S->dt64, 0, 1, nullptr));
+    if (S->dt_version != L->gauge_version) {
+        // d~ = D_rr 1 (the row sums), once per gauge field
+        GRG_TRY_HIP(launch_rest_ones(g, S->d_mask, S->t64, st));
+        GRG_TRY(run_dslash(S, GRG_FP64, S->t64, S->dt64, 0, 1, nullptr));
+        S->dt_version = L->gauge_version;
+    }
     GRG_TRY_HIP(launch_scatter_coarse(xb, S->u64, S->d_bidx, S->nb, g, nrhs, st));
     GRG_TRY_HIP(launch_rb_apply(g, xb, S->d_bidx, S->nb, L->U[GRG_FP64], S->b64, nrhs, st));
     GRG_TRY_HIP(launch_reusken_divide(sh, S->b64, S->dt64, S->d_mask, S->t64, st));

@@ -48,6 +48,8 @@ struct grg_vcycle_s {
 
 namespace grg {
 
+grg_status reusken_apply_internal(grg_schur S, const double *xb, double *yb, int nrhs);
+
 namespace {
 
 struct Dev {
@@ -102,10 +104,11 @@ grg_status dots(grg_vcycle_s *v, int k, int nrhs, const double *a, const double 
     return GRG_OK;
 }
 
-// out = A_k in
+// out = A_k in (the approximate top level enqueued without the API call's
+// synchronisation: the solve's next norm read waits for it)
 grg_status apply_level(grg_vcycle_s *v, int k, int nrhs, const double *in, double *out)
 {
-    if (k > 0 && v->approx_top) return grg_reusken_apply(v->schur[0], in, out, nrhs);
+    if (k > 0 && v->approx_top) return reusken_apply_internal(v->schur[0], in, out, nrhs);
     GRG_TRY(grg_dirac_apply(v->lat[k], v->m[k], GRG_FP64, in, out, nrhs));
     if (v->c[k] != 1.0) {
         double2 s[kMaxRhs];
@@ -176,10 +179,9 @@ grg_status bicgstab(grg_vcycle_s *v, int k, int set, bool pre, double tol, int n
             sin_ = sh;
         }
         GRG_TRY(apply_level(v, k, nrhs, sin_, t));
-        GRG_TRY(dots(v, k, nrhs, t, s, tmp, nullptr));  // <t, s>
-        GRG_TRY(dots(v, k, nrhs, t, t, nullptr, tt));   // |t|^2
+        GRG_TRY(dots(v, k, nrhs, s, t, tmp, tt));  // <s, t> and |t|^2 in one pass; <t, s> = conj <s, t>
         for (int i = 0; i < nrhs; ++i)
-            omega[i] = act[i] && tt[i] > 0 ? make_double2(tmp[i].x / tt[i], tmp[i].y / tt[i]) : make_double2(0, 0);
+            omega[i] = act[i] && tt[i] > 0 ? make_double2(tmp[i].x / tt[i], -tmp[i].y / tt[i]) : make_double2(0, 0);
         // x += alpha p^ + omega s^ ; r = s - omega t
         GRG_TRY(lincomb(v, k, nrhs, x, 3, x, one, pin, alpha, sin_, omega));
         for (int i = 0; i < nrhs; ++i) tmp[i] = make_double2(-omega[i].x, -omega[i].y);
