@@ -58,6 +58,33 @@ def test_matrix_free(dims, kind, inv, nrhs):
     lat.close()
 
 
+def test_new_gauge_field_recomputes_row_sums():
+    """The row sums d~ = D_rr 1 are kept between applies: a new gauge field
+    on the lattice must replace them (the apply after it matches the oracle
+    on the new links, not the old)."""
+    import torch
+
+    from grg_inputs import su3_links
+
+    dims, nrhs = (8, 8, 4, 8), 2
+    lat = Lattice(dims, 0.5, 5)
+    s = lat.schur(-0.2, "II", True, max_rhs=nrhs)
+    xb = gaussian_vectors(12 * s.nb, nrhs, 6)
+    x = to_dev(xb)
+    y = torch.empty_like(x)
+    lat.grg.grg_reusken_apply(s.h, x, y, nrhs)
+    first = to_host(y)
+    links2 = su3_links(dims, 0.5, 7)
+    lat.grg.grg_gauge_set(lat.h, links2)
+    lat.grg.grg_reusken_apply(s.h, x, y, nrhs)
+    got = to_host(y)
+    want = matfree.reusken_apply(links2, dims, -0.2, s.q, s.nb, xb)
+    assert rel_err(got, want) < 1e-12
+    assert rel_err(first, want) > 1e-3  # the field did change the operator
+    s.close()
+    lat.close()
+
+
 def test_zero_diagonal_rejected():
     import torch
 
