@@ -36,6 +36,9 @@
  * Errors: every call returns a grg_status and never aborts or throws across
  * the boundary.  Arguments are validated before anything is enqueued.  The
  * message of the last failure in the calling thread is grg_last_error().
+ * Every apply and solve call takes nrhs in 1..max_rhs of its handle (1..16
+ * for the lattice calls): an empty batch, nrhs = 0, is GRG_EINVAL and writes
+ * nothing.
  */
 #ifndef GRG_H
 #define GRG_H

@@ -410,7 +410,8 @@ grg_status ensure_inner(grg_schur S, int prec)
 
 // Inner GCR(m) on D_rr in precision prec: solves A x = b, with b already in
 // in_r (it becomes the residual) and x in xdst, until |r|^2 <= thr[k] per RHS
-// (thr: host copy of the device array thr2) or maxit iterations.
+// (thr: host copy of the device array thr2; HUGE_VAL for a RHS that takes no
+// part, whose correction stays zero) or maxit iterations.
 // Returns the iterations taken in *iters and the last |r|^2 read in rn2_out.
 static grg_status inner_gcr(grg_schur S, int prec, int nrhs, const double *thr, int maxit,
                             int *iters, double *rn2_out, void *xdst)
@@ -814,10 +815,12 @@ static grg_status inner_mr_eo(grg_schur S, int prec, int nrhs, const double *thr
     GRG_TRY_HIP(launch_reduce(kNorm3, S->partials, pgrid, nrhs, nullptr, S->rn2, S->thr2, S->active, st));
     double h[kMaxRhs];
     GRG_TRY(read_norms(S, nrhs, h));
-    // the RHS that take steps at all (the others keep a zero correction)
+    // the RHS that take part (thr finite; the others keep a zero correction).
+    // One whose reduced right-hand side already meets its threshold takes no
+    // step, x_P = 0, but its correction z_Q = b_Q / d is not zero.
     {
         int *flags = (int *)(S->h_buf + 8 * kMaxRhs);
-        for (int k = 0; k < nrhs; ++k) flags[k] = h[k] > thr[k] ? 1 : 0;
+        for (int k = 0; k < nrhs; ++k) flags[k] = thr[k] < HUGE_VAL ? 1 : 0;
         GRG_TRY_HIP(hipMemcpyAsync(S->act0, flags, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
     }
     auto all_done = [&](const double *n2) {
@@ -851,9 +854,8 @@ static grg_status inner_mr_eo(grg_schur S, int prec, int nrhs, const double *thr
     if (it == 0) GRG_TRY_HIP(launch_fill_zero(x, vbytes, st));
     *iters = it;
     memcpy(rn2_out, h, sizeof(double) * nrhs);
-    // z_Q = (b_Q - H_QP z_P) / d (zero for RHS that took no step: their
-    // x_P is zero and the correction must be too), written with z_P into
-    // the full layout
+    // z_Q = (b_Q - H_QP z_P) / d (zero for the RHS that take no part),
+    // written with z_P into the full layout
     GRG_TRY(eo_hop(S, prec, t, x, b, xdst, Q, 1.0 / d, -1.0 / d, nrhs, nullptr, nullptr, S->act0,
                    0, 1, x));
     if (done < 0) {
@@ -900,7 +902,7 @@ static grg_status inner_fgcr_eo(grg_schur S, int prec, int nrhs, const double *t
     GRG_TRY(read_norms(S, nrhs, h));
     {
         int *flags = (int *)(S->h_buf + 8 * kMaxRhs);
-        for (int k = 0; k < nrhs; ++k) flags[k] = h[k] > thr[k] ? 1 : 0;
+        for (int k = 0; k < nrhs; ++k) flags[k] = thr[k] < HUGE_VAL ? 1 : 0;  // taking part
         GRG_TRY_HIP(hipMemcpyAsync(S->act0, flags, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
     }
     auto all_done = [&](const double *n2) {
@@ -1021,7 +1023,7 @@ static grg_status inner_bicgstab(grg_schur S, int prec, int nrhs, const double *
     GRG_TRY(read_norms(S, nrhs, h));
     if (reduce) {
         int *flags = (int *)(S->h_buf + 8 * kMaxRhs);
-        for (int k = 0; k < nrhs; ++k) flags[k] = h[k] > thr[k] ? 1 : 0;
+        for (int k = 0; k < nrhs; ++k) flags[k] = thr[k] < HUGE_VAL ? 1 : 0;  // taking part
         GRG_TRY_HIP(hipMemcpyAsync(S->act0, flags, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
     }
     auto all_done = [&](const double *n2) {
@@ -1286,7 +1288,7 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
             const double rel = prec == GRG_FP64 ? need : std::max(p.inner_tol, 0.5 * need);
             const bool on = bn2[k] > 0 && sqrt(rn2[k] / bn2[k]) > p.tol;
             ih[k] = sc[k] * sc[k] * rn2[k];
-            thr[k] = on ? rel * rel * ih[k] : 2.0 * ih[k] + 1.0;  // above |s r|^2: inactive
+            thr[k] = on ? rel * rel * ih[k] : HUGE_VAL;  // converged: takes no part
             f[k] = 1.0 / sc[k];
         }
         GRG_TRY(upload(S->thr2, thr, 0));

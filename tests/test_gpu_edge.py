@@ -1,0 +1,162 @@
+"""Degenerate partitions and empty calls.
+
+Section 1's split of D holds for any set of coarse sites, not only the
+blocking sets of section 2, so the library takes any ordering q with
+1 <= N_b <= V - 1.  The extreme and structured cases are checked against the
+dense oracle at 4^4:
+* one coarse site, and one rest site (D_rr a single 12 x 12 block);
+* every even site coarse, or every odd site coarse: the rest sites then have
+  no rest neighbour, so D_rr = (4 + m0) 1, and the even-odd reduced solve has
+  an empty parity;
+* a whole time slice coarse (the rest sites a slab, open in t);
+* a random coarse set.
+Every inner precision and both forms of the D_rr solve (even-odd reduced or
+not) go through each.  An empty batch (nrhs = 0) is an invalid argument for
+every apply and solve call, rejected before anything runs."""
+import numpy as np
+import pytest
+
+from grg_inputs import gaussian_vectors
+from oracle import dense, matfree
+
+from gpu_support import Lattice, Schur, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+DIMS, M0 = (4, 4, 4, 4), -0.2
+
+
+@pytest.fixture(scope="module")
+def c4():
+    lat = Lattice(DIMS, 0.4, 61)
+    d = dense.wilson_dense(lat.links, DIMS, M0)
+    yield lat, d
+    lat.close()
+
+
+def ordering(case):
+    V = int(np.prod(DIMS))
+    rng = np.random.default_rng(62)
+    par = matfree.site_parity(DIMS)
+    if case == "one-coarse":
+        return rng.permutation(V), 1
+    if case == "one-rest":
+        return rng.permutation(V), V - 1
+    if case in ("even-coarse", "odd-coarse"):
+        p = 0 if case == "even-coarse" else 1
+        first = np.flatnonzero(par == p)
+        return np.concatenate([first, np.flatnonzero(par != p)]), len(first)
+    if case == "t-slice":
+        v3 = V // DIMS[3]
+        return np.arange(V), v3  # sites of t = 0 come first
+    assert case == "random"
+    return rng.permutation(V), V // 16
+
+
+CASES = ["one-coarse", "one-rest", "even-coarse", "odd-coarse", "t-slice", "random"]
+
+
+def make(lat, case, inner, eo):
+    q, nb = ordering(case)
+    grg = lat.grg
+    tol_in = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 1e-2}[inner]
+    p = grg.grg_solver_params_default(tol=1e-12, inner=inner, inner_tol=tol_in, max_rhs=2, eo=eo)
+    h = grg.grg_schur_create(lat.h, M0, q.astype(np.int32), nb, p)
+    return Schur(lat, h, q, nb, M0)
+
+
+@pytest.mark.parametrize("eo", [1, 0])
+@pytest.mark.parametrize("inner", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("case", CASES)
+def test_schur_apply_degenerate_partition(c4, case, inner, eo):
+    lat, d = c4
+    s = make(lat, case, inner, eo)
+    xb = gaussian_vectors(12 * s.nb, 2, 63)
+    print(f"S_bb apply, {case}, N_b {s.nb}, inner {inner}, eo {eo}", flush=True)
+    y, st = s.apply(xb)
+    assert st["converged"]
+    want = dense.schur_apply_dense(d, s.q, s.nb, xb)
+    assert rel_err(y, want) < 1e-10, (case, inner, eo)
+    s.close()
+
+
+@pytest.mark.parametrize("eo", [1, 0])
+@pytest.mark.parametrize("case", CASES)
+def test_drr_solve_degenerate_partition(c4, case, eo):
+    lat, d = c4
+    s = make(lat, case, "bf16", eo)
+    V = lat.V
+    b = gaussian_vectors(12 * V, 2, 64).reshape(2, V, 12)
+    b[:, np.asarray(s.q[: s.nb])] = 0
+    b = b.reshape(2, -1)
+    x, st = s.drr_solve(b)
+    assert st["converged"]
+    rr = matfree.drr_residual(lat.links, DIMS, M0, s.q, s.nb, b, x)
+    assert np.all(rr <= 1e-12 * (1 + 1e-6)), (case, rr)
+    assert not np.any(x.reshape(2, V, 12)[:, np.asarray(s.q[: s.nb])])
+    if case in ("even-coarse", "odd-coarse"):
+        # no rest site has a rest neighbour: D_rr = (4 + m0) 1
+        xr = b.reshape(2, V, 12) / (4.0 + M0)
+        assert rel_err(x, xr.reshape(2, -1)) < 1e-13
+    s.close()
+
+
+@pytest.mark.parametrize("case", ["one-coarse", "one-rest", "even-coarse", "t-slice"])
+def test_approximations_degenerate_partition(c4, case):
+    """Section 3's S~_bb and the approximation ignoring D_rr's couplings; on
+    the even-site set D_rr is diagonal, so both equal S_bb there."""
+    import torch
+
+    lat, d = c4
+    s = make(lat, case, "fp64", 1)
+    grg = lat.grg
+    xb = gaussian_vectors(12 * s.nb, 2, 65)
+    x = to_dev(xb)
+    y = torch.empty_like(x)
+    grg.grg_reusken_apply(s.h, x, y, 2)
+    want = (dense.reusken_dense(d, s.q, s.nb) @ xb.T).T
+    assert rel_err(to_host(y), want) < 1e-12
+    grg.grg_diag_schur_apply(s.h, x, y, 2)
+    want0 = (dense.diag_schur_dense(d, s.q, s.nb) @ xb.T).T
+    assert rel_err(to_host(y), want0) < 1e-12
+    if case == "even-coarse":
+        assert rel_err(want, dense.schur_apply_dense(d, s.q, s.nb, xb)) < 1e-12
+    s.close()
+
+
+def test_empty_batch_is_rejected(c4):
+    import torch
+
+    lat, _ = c4
+    grg = lat.grg
+    s = make(lat, "random", "bf16", 1)
+    xb = to_dev(np.zeros((1, 12 * s.nb)))
+    yb = torch.empty_like(xb)
+    xf = to_dev(np.zeros((1, 12 * lat.V)))
+    yf = torch.empty_like(xf)
+    calls = [
+        lambda: grg.grg_schur_apply(s.h, xb, yb, 0),
+        lambda: grg.grg_drr_solve(s.h, xf, yf, 0),
+        lambda: grg.grg_reusken_apply(s.h, xb, yb, 0),
+        lambda: grg.grg_diag_schur_apply(s.h, xb, yb, 0),
+        lambda: grg.grg_dirac_apply(lat.h, M0, "fp64", xf, yf, 0),
+    ]
+    for call in calls:
+        yb.fill_(7.0)
+        yf.fill_(7.0)
+        with pytest.raises(grg.GrgError) as e:
+            call()
+        assert e.value.status == grg.GRG_EINVAL
+        # nothing was written
+        assert torch.all(yb == 7.0) and torch.all(yf == 7.0)
+    s.close()
+
+
+def test_partition_bounds_are_checked(c4):
+    lat, _ = c4
+    grg = lat.grg
+    q = np.arange(lat.V, dtype=np.int32)
+    for nb in (0, lat.V, -1):
+        with pytest.raises(grg.GrgError) as e:
+            grg.grg_schur_create(lat.h, M0, q, nb, grg.grg_solver_params_default())
+        assert e.value.status == grg.GRG_EINVAL
