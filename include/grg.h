@@ -56,7 +56,7 @@ typedef enum {
     GRG_EODD_EXTENT = -2,  /* Type I/II blocking needs even extents */
     GRG_ENOMEM = -3,       /* device or host allocation failed */
     GRG_EHIP = -4,         /* HIP runtime error; text in grg_last_error() */
-    GRG_ENOCONV = -5,      /* solver hit its iteration cap; best iterate kept */
+    GRG_ENOCONV = -5,      /* solver hit its iteration cap; best iterate returned */
     GRG_ENONFINITE = -6,   /* NaN or Inf met in a residual */
     GRG_ETOO_LARGE = -7,   /* output would exceed the caller's capacity */
     GRG_EUNSUPPORTED = -8  /* valid request that this library does not support */
@@ -92,7 +92,8 @@ typedef struct {
                           and equals b - D_rr x up to FP64 rounding */
     int eo;            /* 1 (default): inner solves with restart 1 (minimal residual, its
                           flexible form with the learned preconditioner) and BiCGstab run on
-                          the even-odd reduced system of D_rr when every extent is even (the
+                          the even-odd reduced system of D_rr when every extent is even and
+                          d = 4 + m0 is not zero (the
                           hopping term couples opposite parities: solve
                           (d - H_pq H_qp / d) z_p = b_p - H_pq b_q / d on one parity, then
                           z_q = (b_q - H_qp z_p) / d); 0: on D_rr itself */
@@ -226,8 +227,12 @@ grg_status grg_schur_set_params(grg_schur s, const grg_solver_params *params);
  * the cost section 2 points at (computing S_bb requires inverting D_rr).
  * Solved to ||rhs - D_rr x|| <= params.tol ||rhs|| per RHS in FP64 (the
  * defect correction's FP64 residual, see grg_solver_params).  Entries of rhs
- * on coarse sites are ignored; x is zero there.  GRG_ENOCONV keeps the best
- * iterate; GRG_ENONFINITE on a NaN or Inf residual.  stats may be NULL. */
+ * on coarse sites are ignored; x is zero there.  GRG_ENOCONV (an iteration
+ * cap met): per RHS, x is the iterate of smallest FP64 residual among the
+ * defect-correction steps (x = 0 included) since the corrections were last
+ * summed into the iterate (every 16 steps, so normally the best overall),
+ * and stats->true_rel_resid is its residual.  GRG_ENONFINITE on a NaN or Inf
+ * residual.  stats may be NULL. */
 grg_status grg_drr_solve(grg_schur s, const double *rhs, double *x, int nrhs,
                          grg_solver_stats *stats);
 
@@ -342,7 +347,8 @@ grg_status grg_block_apply(grg_schur s, int precision, int rows, int cols, const
  * (device); in is read on the rest sites of parity p only and out is zero
  * elsewhere.  Computed in the given precision with the two half-lattice
  * stencils of the handle's launch (grg_schur_tune_info, precision 3..5).
- * GRG_EINVAL if an extent is odd (no even-odd form) or parity is not 0 or 1. */
+ * GRG_EINVAL if an extent is odd (no even-odd form), 4 + m0 = 0 (no reduced
+ * form) or parity is not 0 or 1. */
 grg_status grg_reduced_apply(grg_schur s, int precision, int parity, const double *in, double *out,
                              int nrhs);
 

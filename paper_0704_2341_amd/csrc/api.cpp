@@ -858,6 +858,7 @@ grg_status grg_reduced_apply(grg_schur S, int precision, int parity, const doubl
     if (precision < 0 || precision > 2) return set_error("bad precision"), GRG_EINVAL;
     if (parity != 0 && parity != 1) return set_error("parity must be 0 or 1"), GRG_EINVAL;
     if (!S->lat->eo_ok) return set_error("the lattice has no even-odd form (odd extent)"), GRG_EINVAL;
+    if (4.0 + S->m0 == 0.0) return set_error("4 + m0 = 0: the reduced operator divides by it"), GRG_EINVAL;
     DeviceGuard dg(S->lat->device);
     grg_status st = reduced_apply_internal(S, precision, parity, in, out, nrhs);
     hipError_t e = hipStreamSynchronize(S->lat->stream);

@@ -636,11 +636,14 @@ grg_status grg_batch_create(const grg_batch_member *m, int count, int nrhs,
         diag[i] = 4.0 + b.m0;
         coffs[i] = b.coff;
     }
-    // the even-odd reduced inner solve: every lattice with even extents
+    // the even-odd reduced inner solve: every lattice with even extents and a
+    // nonzero diagonal 4 + m0 (the reduced operator divides by it)
     bool eo = prm.eo != 0;
-    for (int i = 0; i < count && eo; ++i)
+    for (int i = 0; i < count && eo; ++i) {
+        if (4.0 + mem[i].m0 == 0.0) eo = false;
         for (int mu = 0; mu < 4; ++mu)
             if (mem[i].dims[mu] % 2) eo = false;
+    }
     // compact halves: lattice i's block of V / 2 half-sites, padded to 256
     std::vector<int> off_h(count), par_h(count), tile_lat_h;
     std::vector<uint8_t> mask_h;

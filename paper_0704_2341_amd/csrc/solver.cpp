@@ -1207,6 +1207,7 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
     };
     // the kept corrections and the part of x already summed into x64
     int npool = 0;
+    int ncorr = 0, nsummed = 0;  // corrections made, and summed into x64
     bool have_x = false;
     bool u_ready = xb == nullptr;
     if (fused) *fused = false;
@@ -1232,9 +1233,18 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
         }
         if (npool > 0) GRG_TRY_HIP(hipStreamSynchronize(st));  // h_fk is reused next
         npool = 0;
+        nsummed = ncorr;
         have_x = true;
         return GRG_OK;
     };
+    // per RHS the iterate of smallest FP64 residual so far (returned with
+    // GRG_ENOCONV): that residual and the corrections it sums (0: x = 0)
+    double best[kMaxRhs];
+    int best_n[kMaxRhs];
+    for (int k = 0; k < nrhs; ++k) {
+        best[k] = bn2[k];
+        best_n[k] = 0;
+    }
 
     const void *r_src = S->b64;  // the residual of the current iterate
     int r_prec = GRG_FP64;       // its storage (FP32 in the late steps, see dc_fp32_threshold)
@@ -1265,6 +1275,8 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
             GRG_TRY_HIP(launch_reduce(kNorm, S->partials, sh.grid, nrhs, nullptr, S->rn2, nullptr,
                                       nullptr, st));
             GRG_TRY(read_norms(S, nrhs, rn2));
+            for (int k = 0; k < nrhs; ++k)
+                if (best_n[k] == ncorr) best[k] = rn2[k];
             r_src = S->r64;
             r_prec = GRG_FP64;
             rhs_ready = false;
@@ -1274,8 +1286,6 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
         verified = false;
         if (outer >= p.max_outer || total >= p.max_iter) {
             status = GRG_ENOCONV;
-            set_error("D_rr solve: no convergence after %d outer / %d inner iterations "
-                      "(residual %.3e > %.3e)", outer, total, worst, p.tol);
             break;
         }
         if (npool == kCorrPool) GRG_TRY(combine(nullptr, 1.0));  // pool full: sum it into x64
@@ -1300,9 +1310,11 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
         int it = 0;
         grg_status is;
         double h[kMaxRhs];
-        const bool reduce = p.eo && L->eo_ok && std::max(1, p.restart) == 1;
+        // the reduced system divides by the diagonal d = 4 + m0: none at d = 0
+        const bool eo_form = p.eo && L->eo_ok && 4.0 + S->m0 != 0.0;
+        const bool reduce = eo_form && std::max(1, p.restart) == 1;
         if (p.method == 1) {
-            is = inner_bicgstab(S, prec, nrhs, thr, p.max_iter - total, &it, h, e, p.eo && L->eo_ok);
+            is = inner_bicgstab(S, prec, nrhs, thr, p.max_iter - total, &it, h, e, eo_form);
             total += it;
         } else if (S->precond) {
             // preconditioned inner solve, with the plain solve as the fallback
@@ -1380,11 +1392,31 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
         }
         for (int k = 0; k < kMaxRhs; ++k) S->h_fk[npool * kMaxRhs + k] = k < nrhs ? f[k] : 0.0;
         ++npool;
+        ++ncorr;
         GRG_TRY(read_norms(S, nrhs, rn2));
+        for (int k = 0; k < nrhs; ++k)
+            if (rn2[k] < best[k]) {
+                best[k] = rn2[k];
+                best_n[k] = ncorr;
+            }
         memcpy(sc, scn, sizeof(double) * nrhs);
         r_src = small ? S->r32 : S->r64;
         r_prec = small ? GRG_FP32 : GRG_FP64;
         rhs_ready = true;
+    }
+    if (status == GRG_ENOCONV) {
+        // return each RHS's best iterate: drop the corrections after it that
+        // are still kept (those summed into x64 already stay)
+        worst = 0;
+        for (int k = 0; k < nrhs; ++k) {
+            if (best_n[k] < ncorr && best_n[k] >= nsummed) {
+                for (int j = best_n[k] - nsummed; j < npool; ++j) S->h_fk[j * kMaxRhs + k] = 0.0;
+                rn2[k] = best[k];
+            }
+            worst = std::max(worst, bn2[k] > 0 ? sqrt(rn2[k] / bn2[k]) : 0.0);
+        }
+        set_error("D_rr solve: no convergence after %d outer / %d inner iterations "
+                  "(residual of the returned iterate %.3e > %.3e)", outer, total, worst, p.tol);
     }
     if (xb && yb && fused && u_minus && !have_x) {
         // y_b = [D (u - sum_j f_j e_j)]_b straight from the corrections

@@ -11,7 +11,9 @@ dense oracle at 4^4:
 * a whole time slice coarse (the rest sites a slab, open in t);
 * a random coarse set.
 Every inner precision and both forms of the D_rr solve (even-odd reduced or
-not) go through each.  An empty batch (nrhs = 0) is an invalid argument for
+not) go through each, and the many-lattice batch takes such members too.
+At m0 = -4 (a zero diagonal) the reduced form does not exist and the solve
+runs on D_rr itself.  An empty batch (nrhs = 0) is an invalid argument for
 every apply and solve call, rejected before anything runs."""
 import numpy as np
 import pytest
@@ -160,3 +162,75 @@ def test_partition_bounds_are_checked(c4):
         with pytest.raises(grg.GrgError) as e:
             grg.grg_schur_create(lat.h, M0, q, nb, grg.grg_solver_params_default())
         assert e.value.status == grg.GRG_EINVAL
+
+
+@pytest.mark.parametrize("method", ["gcr", "bicgstab"])
+def test_zero_diagonal(method):
+    """m0 = -4: D_rr is the hopping term alone (4 + m0 = 0).  The even-odd
+    reduction, which divides by the diagonal, does not exist: the reduced
+    apply is refused and the solve runs on D_rr itself whatever params.eo
+    says.  With every site of the slice t = 0 coarse, D_rr is invertible
+    (condition number about 2e3 on this field) but its spectrum is symmetric
+    about zero, where minimal residual stagnates and BiCGstab diverges (as
+    restarted GCR does in the oracle too): the call reports GRG_ENOCONV and
+    returns per RHS the iterate of smallest residual, never worse than
+    x = 0."""
+    import torch
+
+    lat = Lattice(DIMS, 0.4, 61)
+    m0 = -4.0
+    q, nb = ordering("t-slice")
+    grg = lat.grg
+    xb = gaussian_vectors(12 * nb, 2, 66)
+    ys = []
+    for eo in (1, 0):
+        p = grg.grg_solver_params_default(tol=1e-12, inner="fp64", max_rhs=2, eo=eo, method=method,
+                                          max_iter=300)
+        s = Schur(lat, grg.grg_schur_create(lat.h, m0, q.astype(np.int32), nb, p), q, nb, m0)
+        with pytest.raises(grg.GrgError) as e:
+            s.apply(xb)
+        assert e.value.status == grg.GRG_ENOCONV
+        y, st = s.apply(xb, allow_noconv=True)
+        assert st["status"] == grg.GRG_ENOCONV and np.isfinite(y).all()
+        assert st["true_rel_resid"] <= 1.0
+        ys.append(y)
+        x = to_dev(np.zeros((1, 12 * lat.V)))
+        with pytest.raises(grg.GrgError) as e:
+            grg.grg_reduced_apply(s.h, "fp64", 0, x, torch.empty_like(x), 1)
+        assert e.value.status == grg.GRG_EINVAL
+        s.close()
+    assert np.array_equal(ys[0], ys[1])  # the same unreduced solve
+    lat.close()
+
+
+@pytest.mark.parametrize("eo", [1, 0])
+def test_batch_degenerate_partitions(c4, eo):
+    """The many-lattice batch with members whose partitions are degenerate
+    (one rest site; every even site coarse: an empty reduced parity) beside
+    a Type I member, each against the dense oracle."""
+    import torch
+
+    lat, d = c4
+    grg = lat.grg
+    qI, nbI = grg.grg_permutation_block(DIMS, 1, False)
+    orders = [ordering("one-rest"), ordering("even-coarse"), (qI, nbI)]
+    ms = [dict(dims=DIMS, m0=M0, links=lat.links, q=np.asarray(q, np.int32), n_coarse=nb) for q, nb in orders]
+    nrhs = 2
+    p = grg.grg_solver_params_default(tol=1e-12, inner="fp32", inner_tol=1e-5, check_every=2, eo=eo)
+    b = grg.grg_batch_create(ms, nrhs, p)
+    total, _ = grg.grg_batch_layout(b, len(ms))
+    x = np.zeros(total, np.complex128)
+    for i, m in enumerate(ms):
+        off, nb = grg.grg_batch_layout(b, i)
+        x[off:off + 12 * nb * nrhs] = gaussian_vectors(12 * nb, nrhs, 67 + i).reshape(-1)
+    xd = to_dev(x)
+    yd = torch.empty_like(xd)
+    st = grg.grg_batch_apply(b, xd, yd, use_graph=False)
+    assert st["converged"] and st["true_rel_resid"] <= 1e-12
+    y = to_host(yd)
+    for i, m in enumerate(ms):
+        off, nb = grg.grg_batch_layout(b, i)
+        xi = x[off:off + 12 * nb * nrhs].reshape(nrhs, -1)
+        yi = y[off:off + 12 * nb * nrhs].reshape(nrhs, -1)
+        assert rel_err(yi, dense.schur_apply_dense(d, m["q"], nb, xi)) < 1e-10, i
+    grg.grg_batch_destroy(b)
