@@ -25,7 +25,8 @@ def gpu_apply(lat, m0, prec, x):
     return to_host(out)
 
 
-@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (4, 4, 4, 8), (6, 2, 10, 4), (3, 5, 7, 2), (8, 8, 8, 16)])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (4, 4, 4, 8), (6, 2, 10, 4), (3, 5, 7, 2), (8, 8, 8, 16),
+                                  (1, 4, 3, 2), (3, 2, 1, 1)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 def test_dirac_apply_vs_oracle(dims, prec):
     lat = Lattice(dims, 0.5, 21)

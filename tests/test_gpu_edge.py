@@ -234,3 +234,26 @@ def test_batch_degenerate_partitions(c4, eo):
         yi = y[off:off + 12 * nb * nrhs].reshape(nrhs, -1)
         assert rel_err(yi, dense.schur_apply_dense(d, m["q"], nb, xi)) < 1e-10, i
     grg.grg_batch_destroy(b)
+
+
+@pytest.mark.parametrize("dims", [(1, 4, 3, 2), (3, 2, 1, 1), (2, 2, 2, 2)])
+@pytest.mark.parametrize("inner", ["fp64", "bf16"])
+def test_tiny_lattices(dims, inner):
+    """Extents of one (a site is its own neighbour) and two (forward and
+    backward neighbours coincide), fewer sites than one 64-site tile, a
+    random coarse set: S_bb against the dense oracle (the even-odd form only
+    where every extent is even)."""
+    lat = Lattice(dims, 0.4, 68)
+    V = lat.V
+    q = np.random.default_rng(69).permutation(V).astype(np.int32)
+    nb = max(1, V // 6)
+    tol_in = {"fp64": 1e-12, "bf16": 1e-2}[inner]
+    p = lat.grg.grg_solver_params_default(tol=1e-12, inner=inner, inner_tol=tol_in, max_rhs=2)
+    s = Schur(lat, lat.grg.grg_schur_create(lat.h, M0, q, nb, p), q, nb, M0)
+    xb = gaussian_vectors(12 * nb, 2, 70)
+    y, st = s.apply(xb)
+    assert st["converged"]
+    d = dense.wilson_dense(lat.links, dims, M0)
+    assert rel_err(y, dense.schur_apply_dense(d, q, nb, xb)) < 1e-10
+    s.close()
+    lat.close()

@@ -204,6 +204,21 @@ def test_free_field_plane_wave(dfree):
     assert check_plane_wave(dfree, DIMS, M0) < 1e-12
 
 
+@pytest.mark.parametrize("dims", [(1, 4, 3, 2), (2, 1, 2, 3), (3, 2, 1, 1), (2, 2, 2, 2)])
+def test_free_field_plane_wave_small_extents(dims):
+    """Extents of one and two, where the forward and backward neighbours of
+    a site coincide (and with one, are the site itself): the plane-wave
+    symbol still holds, for the dense operator and the C stencil alike."""
+    from oracle import matfree
+
+    v = int(np.prod(dims))
+    free = np.broadcast_to(np.eye(3, dtype=np.complex128), (v, 4, 3, 3)).copy()
+    d = dense.wilson_dense(free, dims, M0)
+    assert check_plane_wave(d, dims, M0) < 1e-12
+    x = gaussian_vectors(12 * v, 2, 5)
+    assert np.abs(matfree.dirac_apply(free, dims, M0, x) - (d @ x.T).T).max() < 1e-13
+
+
 def test_gamma5_hermiticity(dmat):
     v = 256
     g5 = site_local(lambda s: np.kron(np.diag([1, 1, -1, -1]), np.eye(3)), v)
