@@ -139,8 +139,8 @@ class Level:
         return Level(apply, cd)
 
 
-def hierarchy(links, dims, m0, levels):
-    lv = [Level(lambda x: matfree.dirac_apply(links, dims, m0, x[None, :])[0], dims)]
+def hierarchy(links, dims, m0, levels, bc=(1, 1, 1, -1)):
+    lv = [Level(lambda x: matfree.dirac_apply(links, dims, m0, x[None, :], bc)[0], dims)]
     for _ in range(levels - 1):
         lv.append(lv[-1].next_level())
     return lv

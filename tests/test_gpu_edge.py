@@ -257,3 +257,64 @@ def test_tiny_lattices(dims, inner):
     assert rel_err(y, dense.schur_apply_dense(d, q, nb, xb)) < 1e-10
     s.close()
     lat.close()
+
+
+@pytest.mark.parametrize("bc", [(-1, -1, 1, 1), (1, 1, 1, 1)])
+def test_other_boundary_signs_tuned(bc):
+    """S_bb, S~_bb and the reduced BF16 solve in the tuned launch forms at
+    16^4 (where the plane form of the half-lattice stencil applies) with
+    other boundary signs, against the C oracle with the same signs."""
+    import torch
+
+    dims = (16, 16, 16, 16)
+    lat = Lattice(dims, 0.5, 71, bc=bc)
+    grg = lat.grg
+    q, nb = grg.grg_permutation_block(dims, 1, False)
+    p = grg.grg_solver_params_default(tol=1e-10, inner="bf16", inner_tol=1e-2, max_rhs=2)
+    s = Schur(lat, grg.grg_schur_create(lat.h, -0.3, q, nb, p), q, nb, -0.3)
+    grg.grg_schur_tune(s.h, 2)
+    xb = gaussian_vectors(12 * nb, 2, 72)
+    print(f"S_bb 16^4 bc {bc}, tuned", flush=True)
+    y, st = s.apply(xb)
+    assert st["converged"]
+    want, _, _ = matfree.schur_apply(lat.links, dims, -0.3, q, nb, xb[:1], tol=1e-12, bc=bc)
+    assert rel_err(y[:1], want) < 1e-8
+    x = to_dev(xb)
+    yr = torch.empty_like(x)
+    grg.grg_reusken_apply(s.h, x, yr, 2)
+    assert rel_err(to_host(yr), matfree.reusken_apply(lat.links, dims, -0.3, q, nb, xb, bc=bc)) < 1e-12
+    s.close()
+    lat.close()
+
+
+def test_batch_members_with_other_boundary_signs():
+    """Batch members keep their own boundary signs."""
+    import torch
+    from grg_inputs import su3_links
+
+    import paper_0704_2341_amd as grg
+
+    dims = (8, 8, 8, 8)
+    bcs = [(1, 1, 1, -1), (-1, 1, 1, 1), (1, -1, -1, -1)]
+    q, nb = grg.grg_permutation_block(dims, 1, False)
+    ms = [dict(dims=dims, bc=bc, m0=-0.2, links=su3_links(dims, 0.5, 73 + i), q=np.asarray(q), n_coarse=nb)
+          for i, bc in enumerate(bcs)]
+    nrhs = 2
+    p = grg.grg_solver_params_default(tol=1e-11, inner="bf16", inner_tol=1e-2, check_every=2)
+    b = grg.grg_batch_create(ms, nrhs, p)
+    total, _ = grg.grg_batch_layout(b, len(ms))
+    x = np.zeros(total, np.complex128)
+    for i in range(len(ms)):
+        off, n = grg.grg_batch_layout(b, i)
+        x[off:off + 12 * n * nrhs] = gaussian_vectors(12 * n, nrhs, 76 + i).reshape(-1)
+    xd = to_dev(x)
+    yd = torch.empty_like(xd)
+    st = grg.grg_batch_apply(b, xd, yd, use_graph=True)
+    assert st["converged"]
+    y = to_host(yd)
+    for i, m in enumerate(ms):
+        off, n = grg.grg_batch_layout(b, i)
+        xi = x[off:off + 12 * n * nrhs].reshape(nrhs, -1)
+        want, _, _ = matfree.schur_apply(m["links"], dims, m["m0"], q, nb, xi[:1], tol=1e-13, bc=m["bc"])
+        assert rel_err(y[off:off + 12 * n * nrhs].reshape(nrhs, -1)[:1], want) < 1e-9, i
+    grg.grg_batch_destroy(b)

@@ -41,6 +41,27 @@ def test_cycle_vs_oracle(lat, levels):
     grg.grg_vcycle_destroy(v)
 
 
+@pytest.mark.parametrize("levels", [2, 3])
+def test_cycle_other_boundary_signs(levels):
+    """Boundary signs other than antiperiodic t: every level keeps them."""
+    import torch
+
+    bc = (-1, 1, -1, 1)
+    lt = Lattice(DIMS, 0.5, 44, bc=bc)
+    grg = lt.grg
+    prm = grg.grg_vcycle_params_default(levels=levels, drr_tol=1e-12, top_tol=1e-13, max_rhs=1)
+    v = grg.grg_vcycle_create(lt.h, M0, prm)
+    f = gaussian_vectors(12 * lt.V, 1, 47)
+    fd = to_dev(f)
+    xd = torch.empty_like(fd)
+    print(f"V-cycle apply, {levels} levels, 8^4, bc {bc}", flush=True)
+    grg.grg_vcycle_apply(v, fd, xd, 1)
+    lv = vcycle.hierarchy(lt.links, DIMS, M0, levels, bc)
+    assert rel_err(to_host(xd)[0], vcycle.cycle(lv, 0, f[0], tol=1e-13)) < 1e-9
+    grg.grg_vcycle_destroy(v)
+    lt.close()
+
+
 def test_preconditioned_solve(lat):
     import torch
 

@@ -38,11 +38,12 @@ def golden_gammas():
 
 
 # ------------------------------------------------------------------ helpers
-def free_spectrum(dims, m0):
-    """Eigenvalues of the free Wilson operator (U = 1), periodic x, y, z and
-    antiperiodic t: (4 + m0 - sum cos p) +- i sqrt(sum sin^2 p), each six-fold."""
-    ax = [2 * np.pi * np.arange(L) / L for L in dims[:3]]
-    ax.append(2 * np.pi * (np.arange(dims[3]) + 0.5) / dims[3])
+def free_spectrum(dims, m0, bc=(1, 1, 1, -1)):
+    """Eigenvalues of the free Wilson operator (U = 1) with boundary signs bc
+    (the default: periodic x, y, z and antiperiodic t): (4 + m0 - sum cos p)
+    +- i sqrt(sum sin^2 p), each six-fold, with p_mu = 2 pi (n + theta_mu) /
+    L_mu, theta_mu = 0 for a periodic and 1/2 for an antiperiodic extent."""
+    ax = [2 * np.pi * (np.arange(L) + (0.5 if b < 0 else 0.0)) / L for L, b in zip(dims, bc)]
     ev = []
     for p in itertools.product(*ax):
         p = np.array(p)
@@ -202,6 +203,26 @@ def check_plane_wave(d, dims, m0):
 
 def test_free_field_plane_wave(dfree):
     assert check_plane_wave(dfree, DIMS, M0) < 1e-12
+
+
+@pytest.mark.parametrize("bc", [(-1, 1, -1, 1), (1, -1, -1, -1), (1, 1, 1, 1)])
+def test_free_field_spectrum_boundary_signs(bc):
+    """Other boundary signs: the momenta shift by half a unit exactly in the
+    antiperiodic directions, for the dense operator and the C stencil."""
+    from oracle import matfree
+
+    dims = (2, 4, 2, 4)
+    v = int(np.prod(dims))
+    free = np.broadcast_to(np.eye(3, dtype=np.complex128), (v, 4, 3, 3)).copy()
+    d = dense.wilson_dense(free, dims, M0, bc=bc)
+    ok, worst = same_multiset(np.linalg.eigvals(d), free_spectrum(dims, M0, bc), 1e-9)
+    assert ok, worst
+    # the same matrix from the C stencil, column by column
+    cols = matfree.dirac_apply(free, dims, M0, np.eye(12 * v, dtype=np.complex128), bc)
+    assert np.abs(cols.T - d).max() < 1e-14
+    # and the pin tells the boundary signs apart
+    other = tuple(-b if k == 0 else b for k, b in enumerate(bc))
+    assert not same_multiset(np.linalg.eigvals(d), free_spectrum(dims, M0, other), 1e-6)[0]
 
 
 @pytest.mark.parametrize("dims", [(1, 4, 3, 2), (2, 1, 2, 3), (3, 2, 1, 1), (2, 2, 2, 2)])

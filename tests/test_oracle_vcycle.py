@@ -39,6 +39,22 @@ def test_level_one_is_the_coarse_wilson_operator(links):
         assert np.linalg.norm(got - alt) <= 1e-12 * np.linalg.norm(alt)
 
 
+@pytest.mark.parametrize("bc", [(-1, 1, -1, 1), (1, -1, 1, 1)])
+def test_level_one_other_boundary_signs(bc):
+    """With other boundary signs the blocked operator is the coarse Wilson
+    form with the same signs (a coarse hop wraps exactly when a fine one
+    does)."""
+    dims = (4, 4, 8, 4)
+    lk = su3_links(dims, 0.5, 43)
+    lv = vcycle.hierarchy(lk, dims, M0, 2, bc)
+    x = gaussian_vectors(12 * lv[1].n, 1, 43)[0]
+    want = vcycle.coarse_wilson_apply(lk, dims, M0, x[None, :], bc)[0]
+    assert np.linalg.norm(lv[1].apply(x) - want) <= 1e-12 * np.linalg.norm(want)
+    # not the form with the default signs
+    dflt = vcycle.coarse_wilson_apply(lk, dims, M0, x[None, :])[0]
+    assert np.linalg.norm(lv[1].apply(x) - dflt) > 1e-3 * np.linalg.norm(want)
+
+
 def test_level_two_is_the_twice_blocked_wilson_operator(links):
     lv = vcycle.hierarchy(links, DIMS, M0, 3)
     d0 = 4 + M0
