@@ -318,3 +318,21 @@ def test_batch_members_with_other_boundary_signs():
         want, _, _ = matfree.schur_apply(m["links"], dims, m["m0"], q, nb, xi[:1], tol=1e-13, bc=m["bc"])
         assert rel_err(y[off:off + 12 * n * nrhs].reshape(nrhs, -1)[:1], want) < 1e-9, i
     grg.grg_batch_destroy(b)
+
+
+@pytest.mark.parametrize("case", ["even-coarse", "one-rest", "random"])
+def test_learned_preconditioner_degenerate_partition(c4, case):
+    """The flexible inner solve with the network (its initial weights) on
+    the reduced parity, where that parity may be empty."""
+    lat, d = c4
+    s = make(lat, case, "bf16", 1)
+    grg = lat.grg
+    p = grg.grg_precond_create(s.h)
+    grg.grg_schur_attach_precond(s.h, p)
+    xb = gaussian_vectors(12 * s.nb, 2, 78)
+    y, st = s.apply(xb)
+    assert st["converged"]
+    assert rel_err(y, dense.schur_apply_dense(d, s.q, s.nb, xb)) < 1e-10
+    grg.grg_schur_attach_precond(s.h, None)
+    grg.grg_precond_destroy(p)
+    s.close()
