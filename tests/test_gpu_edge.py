@@ -336,3 +336,28 @@ def test_learned_preconditioner_degenerate_partition(c4, case):
     grg.grg_schur_attach_precond(s.h, None)
     grg.grg_precond_destroy(p)
     s.close()
+
+
+@pytest.mark.parametrize("dims,inner,tune", [((8, 8, 8, 8), "fp32", False), ((16, 16, 16, 16), "bf16", True)])
+def test_sixteen_rhs(dims, inner, tune):
+    """The largest RHS count (16) through the solve, the per-RHS sums and, at
+    16^4, the tuned launch forms; every RHS against the C oracle."""
+    lat = Lattice(dims, 0.5, 79)
+    grg = lat.grg
+    q, nb = grg.grg_permutation_block(dims, 1, False)
+    tol_in = {"fp32": 1e-5, "bf16": 1e-2}[inner]
+    p = grg.grg_solver_params_default(tol=1e-10, inner=inner, inner_tol=tol_in, max_rhs=16)
+    s = Schur(lat, grg.grg_schur_create(lat.h, -0.2, q, nb, p), q, nb, -0.2)
+    if tune:
+        grg.grg_schur_tune(s.h, 16)
+    xb = gaussian_vectors(12 * nb, 16, 80)
+    xb[5] = 0.0  # a zero RHS among them
+    print(f"S_bb {dims}, 16 RHS, inner {inner}", flush=True)
+    y, st = s.apply(xb)
+    assert st["converged"] and st["true_rel_resid"] <= 1e-10
+    assert not np.any(y[5])
+    idx = [0, 7, 15] if tune else list(range(16))
+    want, _, _ = matfree.schur_apply(lat.links, dims, -0.2, q, nb, xb[idx], tol=1e-13)
+    assert rel_err(y[idx], want) < 1e-8
+    s.close()
+    lat.close()
