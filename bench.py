@@ -225,6 +225,38 @@ def stream_ceiling(torch, mib: int = 1024, reps: int = 10) -> dict:
             "frac_of_peak": gbs / PEAK_HBM_GBS}
 
 
+def host_rates(torch, matfree, links, dims, m0, volume):
+    """The oracle's FP64 stencil on one field (median of three; 960 B per site
+    algorithmic: in, out and links), a multi-threaded copy of 1 GiB on the
+    host (read plus written bytes), and the host's CPU model."""
+    from grg_inputs import gaussian_vectors
+
+    x = gaussian_vectors(12 * volume, 1, 9)
+    ts = []
+    for _ in range(3):
+        t = time.perf_counter()
+        matfree.dirac_apply(links, dims, m0, x)
+        ts.append(time.perf_counter() - t)
+    ds = sorted(ts)[1]
+    src = torch.ones(1 << 27, dtype=torch.float64)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    cs = []
+    for _ in range(3):
+        t = time.perf_counter()
+        dst.copy_(src)
+        cs.append(time.perf_counter() - t)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"dslash_ms": ds * 1e3, "dslash_gbs": 960.0 * volume / ds / 1e9,
+            "host_copy_gbs": 2.0 * src.numel() * 8 / sorted(cs)[1] / 1e9,
+            "host_copy_threads": torch.get_num_threads(), "cpu_model": model}
+
+
 def parse_stencil_launches(spec: str) -> dict:
     """'fp64_nrhs1=SB,RG,SPLIT,GRID,CHUNK,MARCH;...' -> {row: [6 ints]}."""
     out = {}
@@ -665,7 +697,10 @@ def main():
                "sample": f"one of the 12 point sources, full S_bb apply at {args.dims.replace(',', 'x')} "
                          f"(C oracle, GCR(8) to {tol:g}, {int(it_or[0])} iterations) in {dt_cpu:.1f} s",
                "gpu_vs_oracle_rel_diff": agree}
-        log(f"oracle: {dt_cpu:.1f} s per apply, GPU agreement {agree:.2e}")
+        cpu.update(host_rates(torch, matfree, links, dims, m0, volume))
+        log(f"oracle: {dt_cpu:.1f} s per apply, GPU agreement {agree:.2e}; "
+            f"its stencil {cpu['dslash_ms']:.1f} ms ({cpu['dslash_gbs']:.1f} GB/s algorithmic), "
+            f"host copy {cpu['host_copy_gbs']:.1f} GB/s")
 
     out = {
         "metric": METRIC,
