@@ -1496,7 +1496,6 @@ grg_status schur_apply_internal(grg_schur S, const double *xb, double *yb, int n
     grg_lattice L = S->lat;
     hipStream_t st = L->stream;
     const Geom &g = L->g;
-    const BlasShape sh = blas_shape(g, nrhs);
     // b = (D u)_r = D_rb x_b (u = x_b on the coarse sites), from the coarse
     // vector's hops only
     GRG_TRY_HIP(launch_rb_apply(g, xb, S->d_bidx, S->nb, L->U[GRG_FP64], S->b64, nrhs, st, S->partials));
@@ -1505,7 +1504,6 @@ grg_status schur_apply_internal(grg_schur S, const double *xb, double *yb, int n
     bool fused = false;
     grg_status s = drr_solve_internal(S, nrhs, stats, S->u64, xb, yb, &fused, rb_apply_grid(g));
     if (s != GRG_OK && s != GRG_ENOCONV) return s;
-    (void)sh;
     if (fused) return s;
     // y_b = [D (u - z)]_b
     CoarseArgs c;
