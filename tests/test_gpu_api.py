@@ -1,0 +1,104 @@
+"""Boundary behaviour that the parity tests do not reach: the gauge field
+handed over from device memory or from a torch host tensor, a lattice on a
+stream of its own, and the lattice's queries.  Results are compared bit for
+bit with the host-numpy path, and the stencil once with the oracle."""
+import numpy as np
+import pytest
+
+from grg_inputs import gaussian_vectors, su3_links
+from oracle import matfree
+
+from gpu_support import ensure_built, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+DIMS, M0 = (8, 4, 6, 8), -0.25
+
+
+def apply_all(grg, lat, x):
+    import torch
+
+    outs = []
+    for prec in ("fp64", "fp32", "bf16"):
+        y = torch.empty_like(x)
+        grg.grg_dirac_apply(lat, M0, prec, x, y, x.shape[0])
+        outs.append(to_host(y))
+    return outs
+
+
+def test_gauge_field_from_device_and_torch_host():
+    import torch
+    import paper_0704_2341_amd as grg
+
+    ensure_built()
+    links = su3_links(DIMS, 0.5, 81)
+    x = to_dev(gaussian_vectors(12 * int(np.prod(DIMS)), 2, 82))
+    ref = grg.grg_lattice_create(DIMS)
+    grg.grg_gauge_set(ref, links)
+    want = apply_all(grg, ref, x)
+    assert rel_err(want[0], matfree.dirac_apply(links, DIMS, M0, to_host(x))) < 1e-14
+    for src in (torch.from_numpy(links).to("cuda"), torch.from_numpy(links)):
+        lat = grg.grg_lattice_create(DIMS)
+        grg.grg_gauge_set(lat, src)
+        got = apply_all(grg, lat, x)
+        for a, b in zip(got, want):
+            assert np.array_equal(a, b)
+        grg.grg_lattice_destroy(lat)
+    grg.grg_lattice_destroy(ref)
+
+
+def test_lattice_on_its_own_stream():
+    """Work runs on the lattice's stream and the call returns once that
+    stream has drained: the output is complete when the call returns."""
+    import torch
+    import paper_0704_2341_amd as grg
+
+    ensure_built()
+    links = su3_links(DIMS, 0.5, 83)
+    V = int(np.prod(DIMS))
+    x = to_dev(gaussian_vectors(12 * V, 3, 84))
+    ref = grg.grg_lattice_create(DIMS)
+    grg.grg_gauge_set(ref, links)
+    want = apply_all(grg, ref, x)
+    s = torch.cuda.Stream()
+    lat = grg.grg_lattice_create(DIMS, stream=s.cuda_stream)
+    grg.grg_gauge_set(lat, links)
+    q, nb = grg.grg_permutation_block(DIMS, 1, False)
+    for a, b in zip(apply_all(grg, lat, x), want):
+        assert np.array_equal(a, b)
+    # the S_bb apply on that stream, against one on the default stream
+    p = grg.grg_solver_params_default(tol=1e-11, inner="bf16", inner_tol=1e-2, max_rhs=3)
+    xb = to_dev(gaussian_vectors(12 * nb, 3, 85))
+    ys = []
+    for lt in (ref, lat):
+        h = grg.grg_schur_create(lt, M0, q, nb, p)
+        y = torch.empty_like(xb)
+        st = grg.grg_schur_apply(h, xb, y, 3)
+        assert st["converged"]
+        ys.append(to_host(y))
+        grg.grg_schur_destroy(h)
+    assert np.array_equal(ys[0], ys[1])
+    grg.grg_lattice_destroy(lat)
+    grg.grg_lattice_destroy(ref)
+
+
+def test_lattice_queries_and_null_handles():
+    import paper_0704_2341_amd as grg
+
+    ensure_built()
+    lat = grg.grg_lattice_create(DIMS)
+    assert grg.grg_lattice_volume(lat) == int(np.prod(DIMS))
+    grg.grg_lattice_destroy(lat)
+    # destroying nothing is allowed; using nothing is an invalid argument
+    grg.grg_lattice_destroy(None)
+    grg.grg_schur_destroy(None)
+    with pytest.raises(grg.GrgError) as e:
+        grg.grg_lattice_volume(None)
+    assert e.value.status == grg.GRG_EINVAL
+    for bad in ((8, 4, 0, 8), (8, -2, 6, 8)):
+        with pytest.raises(grg.GrgError) as e:
+            grg.grg_lattice_create(bad)
+        assert e.value.status == grg.GRG_EINVAL
+    with pytest.raises(grg.GrgError) as e:
+        grg.grg_lattice_create(DIMS, bc=(1, 1, 0, -1))
+    assert e.value.status == grg.GRG_EINVAL
