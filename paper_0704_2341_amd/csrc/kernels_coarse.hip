@@ -48,49 +48,63 @@ __device__ __forceinline__ void rb_hops(cpx<double> (&acc)[12], int s, const Sit
     }
 }
 
+// Work items (block of 256 sites, RHS) with the RHS fastest, one contiguous
+// range per XCD: the RHS of a site block run side by side in one L2 and share
+// its links and neighbour lists.  partials[workgroup][r]: the workgroup's sum
+// of |out|^2 for RHS r.
 __global__ void __launch_bounds__(256) rb_apply_kernel(Geom g, const double2 *__restrict__ xb,
                                                        const int32_t *__restrict__ bidx, int nb,
                                                        const double2 *__restrict__ U, double2 *__restrict__ out,
                                                        int nrhs, double *partials)
 {
-    __shared__ double red[256];
-    const int r = blockIdx.y;
-    double n2 = 0;
-    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < g.V; s += gridDim.x * blockDim.x) {
-        cpx<double> acc[12];
+    __shared__ double red[4][kMaxRhs];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = lane; i < nrhs; i += 64) red[wave][i] = 0.0;
+    const int nsb = (g.V + 255) >> 8;
+    const ItemRange it = xcd_items(nsb * nrhs);
+    for (int w = it.begin; w < it.end; w += it.step) {
+        const int sb = w / nrhs, r = w - sb * nrhs;
+        const int s = sb * 256 + (int)threadIdx.x;
+        double n2 = 0;
+        if (s < g.V) {
+            cpx<double> acc[12];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
-        if (bidx[s] < 0) {
-            const SiteGeo q = site_geo(s, g);
-            rb_hops<0>(acc, s, q, g, xb, bidx, nb, r, U);
-            rb_hops<1>(acc, s, q, g, xb, bidx, nb, r, U);
-            rb_hops<2>(acc, s, q, g, xb, bidx, nb, r, U);
-            rb_hops<3>(acc, s, q, g, xb, bidx, nb, r, U);
-        }
+            for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
+            if (bidx[s] < 0) {
+                const SiteGeo q = site_geo(s, g);
+                rb_hops<0>(acc, s, q, g, xb, bidx, nb, r, U);
+                rb_hops<1>(acc, s, q, g, xb, bidx, nb, r, U);
+                rb_hops<2>(acc, s, q, g, xb, bidx, nb, r, U);
+                rb_hops<3>(acc, s, q, g, xb, bidx, nb, r, U);
+            }
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            out[fidx(s, r, c, nrhs)] = make_double2(acc[c].re, acc[c].im);
-            n2 += acc[c].re * acc[c].re + acc[c].im * acc[c].im;
+            for (int c = 0; c < 12; ++c) {
+                out[fidx(s, r, c, nrhs)] = make_double2(acc[c].re, acc[c].im);
+                n2 += acc[c].re * acc[c].re + acc[c].im * acc[c].im;
+            }
         }
+        n2 = wave_sum(n2);  // every lane of the wavefront takes part
+        if (lane == 0) red[wave][r] += n2;
     }
-    if (partials) {  // per-workgroup |out|^2 of RHS r: partials[blockIdx.x][r]
-        red[threadIdx.x] = n2;
+    if (partials) {
         __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) partials[(size_t)blockIdx.x * nrhs + r] = red[0];
+        for (int i = threadIdx.x; i < nrhs; i += blockDim.x)
+            partials[(size_t)blockIdx.x * nrhs + i] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
     }
 }
 
-int rb_apply_grid(const Geom &g) { return (int)std::min<long>(((long)g.V + 255) / 256, 2048); }
+int rb_apply_grid(const Geom &g)
+{
+    // whole XCD shares: a multiple of 8 workgroups, at least 8
+    const long n = std::min<long>(((long)g.V + 255) / 256 * 4, 2048);
+    return (int)std::max<long>(8, (n + 7) / 8 * 8);
+}
 
 hipError_t launch_rb_apply(const Geom &g, const double *xb, const int32_t *bidx, int nb, const void *U64,
                            void *out, int nrhs, hipStream_t st, double *partials)
 {
     if (nrhs < 1 || nrhs > kMaxRhs || nb < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(rb_apply_kernel, dim3(rb_apply_grid(g), nrhs), dim3(256), 0, st, g,
+    hipLaunchKernelGGL(rb_apply_kernel, dim3(rb_apply_grid(g)), dim3(256), 0, st, g,
                        (const double2 *)xb, bidx, nb, (const double2 *)U64, (double2 *)out, nrhs, partials);
     return hipGetLastError();
 }
