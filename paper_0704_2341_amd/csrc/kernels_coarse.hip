@@ -165,44 +165,50 @@ __global__ void __launch_bounds__(256) coarse_combine_apply_kernel(Geom g, const
                                                                    CombineArgs a, double2 *__restrict__ yb,
                                                                    int nrhs)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int r = blockIdx.y;
-    if (k >= nb) return;
-    const int s = qsites[k];
-    const SiteGeo q = site_geo(s, g);
-    cpx<double> acc[12];
-    const double2 *v = xb + ((size_t)r * nb + k) * 12;
+    // work items (block of 256 coarse sites, RHS), RHS fastest, one
+    // contiguous range per XCD: the RHS of a block share its links in L2
+    const int nkb = (nb + 255) >> 8;
+    const ItemRange it = xcd_items(nkb * nrhs);
+    for (int wi = it.begin; wi < it.end; wi += it.step) {
+        const int kb = wi / nrhs, r = wi - kb * nrhs;
+        const int k = kb * 256 + (int)threadIdx.x;
+        if (k >= nb) continue;
+        const int s = qsites[k];
+        const SiteGeo q = site_geo(s, g);
+        cpx<double> acc[12];
+        const double2 *v = xb + ((size_t)r * nb + k) * 12;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) acc[c] = {diag * v[c].x, diag * v[c].y};
-    // one hop per iteration (+x, -x, ..., -t): the FP64 operands of a hop
-    // are 84 registers, so the hops are not unrolled
+        for (int c = 0; c < 12; ++c) acc[c] = {diag * v[c].x, diag * v[c].y};
+        // one hop per iteration (+x, -x, ..., -t): the FP64 operands of a hop
+        // are 84 registers, so the hops are not unrolled
 #pragma unroll 1
-    for (int h = 0; h < 8; ++h) {
-        const int mu = h >> 1;
-        int sp, sm;
-        nbr(s, mu, q, g, sp, sm);
-        const int n = (h & 1) ? sm : sp;
-        cpx<double> w[12], u[9];
-        coarse_w<P>(w, n, xb, bidx, nb, r, nrhs, a);
+        for (int h = 0; h < 8; ++h) {
+            const int mu = h >> 1;
+            int sp, sm;
+            nbr(s, mu, q, g, sp, sm);
+            const int n = (h & 1) ? sm : sp;
+            cpx<double> w[12], u[9];
+            coarse_w<P>(w, n, xb, bidx, nb, r, nrhs, a);
 #pragma unroll
-        for (int e = 0; e < 9; ++e) {
-            const double2 x = U[lidx((h & 1) ? sm : s, mu, e)];
-            u[e] = {x.x, x.y};
+            for (int e = 0; e < 9; ++e) {
+                const double2 x = U[lidx((h & 1) ? sm : s, mu, e)];
+                u[e] = {x.x, x.y};
+            }
+            switch (h) {
+            case 0: hop_math<0, true>(acc, w, u); break;
+            case 1: hop_math<0, false>(acc, w, u); break;
+            case 2: hop_math<1, true>(acc, w, u); break;
+            case 3: hop_math<1, false>(acc, w, u); break;
+            case 4: hop_math<2, true>(acc, w, u); break;
+            case 5: hop_math<2, false>(acc, w, u); break;
+            case 6: hop_math<3, true>(acc, w, u); break;
+            default: hop_math<3, false>(acc, w, u); break;
+            }
         }
-        switch (h) {
-        case 0: hop_math<0, true>(acc, w, u); break;
-        case 1: hop_math<0, false>(acc, w, u); break;
-        case 2: hop_math<1, true>(acc, w, u); break;
-        case 3: hop_math<1, false>(acc, w, u); break;
-        case 4: hop_math<2, true>(acc, w, u); break;
-        case 5: hop_math<2, false>(acc, w, u); break;
-        case 6: hop_math<3, true>(acc, w, u); break;
-        default: hop_math<3, false>(acc, w, u); break;
-        }
+        double2 *o = yb + ((size_t)r * nb + k) * 12;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) o[c] = make_double2(acc[c].re, acc[c].im);
     }
-    double2 *o = yb + ((size_t)r * nb + k) * 12;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) o[c] = make_double2(acc[c].re, acc[c].im);
 }
 
 hipError_t launch_coarse_combine_apply(int prec, const Geom &g, const double *xb, const int32_t *qsites,
@@ -210,7 +216,8 @@ hipError_t launch_coarse_combine_apply(int prec, const Geom &g, const double *xb
                                        const CombineArgs &a, double *yb, int nrhs, hipStream_t st)
 {
     if (nrhs < 1 || nrhs > kMaxRhs || nb < 1 || a.n < 0 || a.n > kCorrPool) return hipErrorInvalidValue;
-    dim3 grd((nb + 255) / 256, nrhs), blk(256);
+    const long items = (long)(nb + 255) / 256 * nrhs;
+    dim3 grd((unsigned)std::max<long>(8, (std::min<long>(items, 2048) + 7) / 8 * 8)), blk(256);
 #define CCA(PP)                                                                                        \
     hipLaunchKernelGGL(coarse_combine_apply_kernel<PP>, grd, blk, 0, st, g, (const double2 *)xb, qsites, bidx, nb, \
                        (const double2 *)U64, diag, a, (double2 *)yb, nrhs)
