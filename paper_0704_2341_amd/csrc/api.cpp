@@ -424,6 +424,7 @@ static void schur_free(grg_schur S)
     S->h_fk = nullptr;
     for (int p = 0; p < 3; ++p) {
         for (int k = 0; k < 5; ++k) dfree(S->eo_f[p][k]);
+        dfree(S->eo_b[p]);
         for (int k = 0; k < 5; ++k) dfree(S->bicg_f[p][k]);
     }
     dfree((void *&)S->partials);

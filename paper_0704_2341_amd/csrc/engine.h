@@ -129,6 +129,11 @@ struct DcArgs {
                           // groups of one tile run together on one XCD and share its links
     int r_in32 = 0;       // r_in is stored in FP32 (float2 per complex), else FP64
     int r_out32 = 0;      // r_out is stored in FP32 (rounded from the FP64 result), else FP64
+    // r_next in the compact even-odd halves (the reduced solve's right-hand
+    // side) instead of the full layout: the half of parity next_par first, the
+    // other next_half elements on (0: full layout)
+    size_t next_half = 0;
+    int next_par = 0;
 };
 
 hipError_t launch_dslash(int prec, const DslashArgs &a, int grid, hipStream_t st);

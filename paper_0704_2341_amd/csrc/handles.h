@@ -126,6 +126,8 @@ struct grg_schur_s {
     double *d_fk = nullptr, *h_fk = nullptr;  // [kCorrPool][kMaxRhs]
     int eo_par = 1;
     void *eo_f[3][5] = {};
+    void *eo_b[3] = {};  // the reduced solve's right-hand side as written by the defect
+                         // correction: both compact halves, parity eo_par's first
     // BiCGstab: p, v, s, t and the shadow residual (inner precision, full
     // size, also used as compact halves), and rho, alpha, omega, beta per RHS
     void *bicg_f[3][5] = {};

@@ -173,6 +173,26 @@ __device__ __forceinline__ void dc_store_r(const DcArgs &a, double2 *r, size_t i
     else r[i] = v;
 }
 
+// Where r_next's element (r, c) of site s goes: the full layout (i), or the
+// compact half of the site's parity at its compact index s / 2.
+struct DcNext {
+    size_t base = 0;
+    int hs;
+    bool compact;
+    __device__ DcNext(const DcArgs &a, int s) : hs(s), compact(a.next_half != 0)
+    {
+        if (compact) {
+            const SiteGeo q = site_geo(s, a.g);
+            base = ((q.c[0] ^ q.c[1] ^ q.c[2] ^ q.c[3]) & 1) == a.next_par ? 0 : a.next_half;
+            hs = s >> 1;
+        }
+    }
+    __device__ size_t at(size_t i, int r, int c, int nrhs) const
+    {
+        return compact ? base + fidx(hs, r, c, nrhs) : i;
+    }
+};
+
 template <int P>
 struct DcEpi {
     typedef typename Store<P>::S SIN;
@@ -199,6 +219,7 @@ struct DcEpi {
         const SIN *e = (const SIN *)a.e;
         const double f = a.f[r];
         const double sn = r_next ? a.s_next[r] : 0.0;
+        const DcNext nx(a, s);
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
             // three components at a time: a compiler barrier keeps the
@@ -209,7 +230,7 @@ struct DcEpi {
                 const double2 rv = dc_load_r(a, r_in, i);
                 const double2 d = make_double2(rv.x - f * acc[c].re, rv.y - f * acc[c].im);
                 dc_store_r(a, r_out, i, d);
-                if (r_next) stc(r_next, i, cpx<RN>{(RN)(sn * d.x), (RN)(sn * d.y)});
+                if (r_next) stc(r_next, nx.at(i, r, c, a.nrhs), cpx<RN>{(RN)(sn * d.x), (RN)(sn * d.y)});
                 nrm[0] += d.x * d.x + d.y * d.y;
                 if (x_out) {
                     const cpx<double> ev = ldr<double>(e, i);
@@ -219,7 +240,7 @@ struct DcEpi {
             } else {
                 dc_store_r(a, r_out, i, make_double2(0.0, 0.0));
                 if (x_out) x_out[i] = make_double2(0.0, 0.0);
-                if (r_next) stc(r_next, i, cpx<RN>{0, 0});
+                if (r_next) stc(r_next, nx.at(i, r, c, a.nrhs), cpx<RN>{0, 0});
             }
         }
     }
@@ -580,13 +601,14 @@ __global__ void __launch_bounds__(256) dc_update_kernel(DcArgs a)
                 dslash_site<S, double, true, double2>(acc, e, U, s, q, a.g, r, a.nrhs, a.diag);
                 const double f = a.f[r];
                 const double sn = r_next ? a.s_next[r] : 0.0;
+                const DcNext nx(a, s);
 #pragma unroll
                 for (int c = 0; c < 12; ++c) {
                     const size_t i = fidx(s, r, c, a.nrhs);
                     const double2 rv = dc_load_r(a, r_in, i);
                     const double2 d = make_double2(rv.x - f * acc[c].re, rv.y - f * acc[c].im);
                     dc_store_r(a, r_out, i, d);
-                    if (r_next) stc(r_next, i, cpx<R>{(R)(sn * d.x), (R)(sn * d.y)});
+                    if (r_next) stc(r_next, nx.at(i, r, c, a.nrhs), cpx<R>{(R)(sn * d.x), (R)(sn * d.y)});
                     nrm += d.x * d.x + d.y * d.y;
                     if (x_out) {
                         const cpx<double> ev = ldr<double>(e, i);
@@ -595,12 +617,13 @@ __global__ void __launch_bounds__(256) dc_update_kernel(DcArgs a)
                     }
                 }
             } else if (valid) {
+                const DcNext nx(a, s);
 #pragma unroll
                 for (int c = 0; c < 12; ++c) {
                     const size_t i = fidx(s, r, c, a.nrhs);
                     dc_store_r(a, r_out, i, make_double2(0.0, 0.0));
                     if (x_out) x_out[i] = make_double2(0.0, 0.0);
-                    if (r_next) stc(r_next, i, cpx<R>{0, 0});
+                    if (r_next) stc(r_next, nx.at(i, r, c, a.nrhs), cpx<R>{0, 0});
                 }
             }
             nrm = wave_sum(nrm);

@@ -103,8 +103,9 @@ template <int P, class OP, int IO>
 __device__ __forceinline__ void eo_march(const EoArgs &a, double (*red)[3])
 {
     // IO as for eo_hop_kernel: 0 compact fields, 1 in and in2 in the full
-    // layout, 2 in2 and out in the full layout (with the partner copy)
-    constexpr bool in_full = IO == 1, in2_full = IO >= 1, out_full = IO == 2;
+    // layout, 2 in2 and out in the full layout (with the partner copy), 3
+    // out alone in the full layout
+    constexpr bool in_full = IO == 1, in2_full = IO == 1 || IO == 2, out_full = IO >= 2;
     typedef typename Store<P>::S S;
     typedef typename Store<P>::R R;
     typedef typename OP::T PT;
@@ -384,10 +385,10 @@ template <int P, int HOPS, int IO>
 __global__ void __launch_bounds__(256) eo_hop_kernel(EoArgs a)
 {
     // IO = 0: compact fields; 1: in and in2 in the full layout; 2: in2 and
-    // out in the full layout (the full-layout modes run once per reduced
-    // solve, the compact one every iteration: separate instances keep the
-    // latter free of their indexing)
-    constexpr bool in_full = IO == 1, in2_full = IO >= 1, out_full = IO == 2;
+    // out in the full layout; 3: out alone in the full layout (the
+    // full-layout modes run once per reduced solve, the compact one every
+    // iteration: separate instances keep the latter free of their indexing)
+    constexpr bool in_full = IO == 1, in2_full = IO == 1 || IO == 2, out_full = IO >= 2;
     typedef typename Store<P>::S S;
     typedef typename Store<P>::R R;
     typedef Operand<S, R> OP;
@@ -586,7 +587,7 @@ constexpr int kMaxPlane = 512;
 template <int IO, int EPI, int NPL>
 __global__ void __launch_bounds__(kMaxPlane * NPL, 4) eo_plane_kernel(EoArgs a)
 {
-    constexpr bool in_full = IO == 1, in2_full = IO >= 1, out_full = IO == 2;
+    constexpr bool in_full = IO == 1, in2_full = IO == 1 || IO == 2, out_full = IO >= 2;
     constexpr bool has_in2 = EPI == 1 || EPI == 2, dots = EPI == 2, scaled = EPI != 0;
     typedef bf16x2 S;
     typedef float R;
@@ -763,7 +764,7 @@ __global__ void __launch_bounds__(kMaxPlane * NPL, 4) eo_plane_kernel(EoArgs a)
             if constexpr (has_in2) {
 #pragma unroll
                 for (int c = 0; c < 12; ++c) {
-                    if constexpr (IO == 0)
+                    if constexpr (!in2_full)
                         // read once, whole lines: streamed past L2
                         w2[c] = __builtin_nontemporal_load(in2 + fidx(h, r, c, nr));
                     else
@@ -911,6 +912,7 @@ hipError_t launch_eo_hop(int prec, const EoArgs &a, int grid, hipStream_t st)
     int io = 0;
     if (a.in_full && a.in2_full && !a.out_full) io = 1;
     else if (!a.in_full && a.in2_full && a.out_full) io = 2;
+    else if (!a.in_full && !a.in2_full && a.out_full) io = 3;
     else if (a.in_full || a.in2_full || a.out_full) return hipErrorInvalidValue;
     if (a.hops == 7) {
         // plane form: packed BF16, one workgroup of P = Lx / 2 * Ly lanes
@@ -935,6 +937,8 @@ hipError_t launch_eo_hop(int prec, const EoArgs &a, int grid, hipStream_t st)
             if (epi == 2) PLANE(1, 2); else if (epi == 1) PLANE(1, 1); else return hipErrorInvalidValue;
         } else if (io == 2) {
             if (epi == 1) PLANE(2, 1); else return hipErrorInvalidValue;
+        } else if (io == 3) {
+            if (epi == 1) PLANE(3, 1); else return hipErrorInvalidValue;
         } else {
             if (epi == 2) PLANE(0, 2); else if (epi == 1) PLANE(0, 1); else if (epi == 3) PLANE(0, 3);
             else PLANE(0, 0);
@@ -952,6 +956,7 @@ hipError_t launch_eo_hop(int prec, const EoArgs &a, int grid, hipStream_t st)
             return hipErrorInvalidValue;
         if (io == 1) hipLaunchKernelGGL((eo_hop_kernel<GRG_BF16, 3, 1>), grd, blk, 0, st, a);
         else if (io == 2) hipLaunchKernelGGL((eo_hop_kernel<GRG_BF16, 3, 2>), grd, blk, 0, st, a);
+        else if (io == 3) hipLaunchKernelGGL((eo_hop_kernel<GRG_BF16, 3, 3>), grd, blk, 0, st, a);
         else hipLaunchKernelGGL((eo_hop_kernel<GRG_BF16, 3, 0>), grd, blk, 0, st, a);
         return hipGetLastError();
     }
@@ -969,9 +974,10 @@ hipError_t launch_eo_hop(int prec, const EoArgs &a, int grid, hipStream_t st)
         return hipGetLastError();
     }
 #define EOH(PP, H, IO) hipLaunchKernelGGL((eo_hop_kernel<PP, H, IO>), grd, blk, 0, st, a)
-#define EOIO(PP)                   \
-    if (io == 1) EOH(PP, 1, 1);    \
+#define EOIO(PP)                     \
+    if (io == 1) EOH(PP, 1, 1);      \
     else if (io == 2) EOH(PP, 1, 2); \
+    else if (io == 3) EOH(PP, 1, 3); \
     else EOH(PP, 1, 0);
     switch (prec) {
     case GRG_FP64: EOIO(GRG_FP64) break;

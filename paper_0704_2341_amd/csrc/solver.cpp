@@ -521,6 +521,28 @@ DslashTune default_eo_tune(const Geom &gh, int prec, int nrhs)
     return t;
 }
 
+// Bytes of one compact half-lattice field at the handle's largest RHS count
+// (the offset of the second half of a compact pair).
+static size_t eo_half_bytes(grg_schur S, int prec)
+{
+    return spinor_elems(half_geom(S->lat), S->prm.max_rhs) * prec_bytes(prec);
+}
+
+// The compact pair the defect correction writes the next reduced solve's
+// right-hand side into (parity eo_par's half first).
+static grg_status ensure_eo_rhs(grg_schur S, int prec)
+{
+    if (S->eo_b[prec]) return GRG_OK;
+    const size_t bytes = 2 * eo_half_bytes(S, prec);
+    if (hipMalloc(&S->eo_b[prec], bytes) != hipSuccess) {
+        S->eo_b[prec] = nullptr;
+        set_error("even-odd workspace: hipMalloc of %zu bytes failed", bytes);
+        return GRG_ENOMEM;
+    }
+    GRG_TRY_HIP(launch_fill_zero(S->eo_b[prec], bytes, S->lat->stream));
+    return GRG_OK;
+}
+
 static grg_status ensure_eo(grg_schur S, int prec)
 {
     grg_lattice L = S->lat;
@@ -544,7 +566,8 @@ static grg_status ensure_eo(grg_schur S, int prec)
 static grg_status eo_hop(grg_schur S, int prec, const DslashTune &t, const void *in, const void *in2,
                          void *out, int po, double alpha, double beta, int nrhs, double *partials,
                          const void *dot_with, const int *active = nullptr, int in_full = 0,
-                         int in2_full = 0, const void *partner = nullptr, int *grid_out = nullptr)
+                         int in2_full = 0, const void *partner = nullptr, int *grid_out = nullptr,
+                         bool timed = true)
 {
     grg_lattice L = S->lat;
     // the full-layout steps: with the t-marching form tuned, in the one-hop
@@ -580,7 +603,7 @@ static grg_status eo_hop(grg_schur S, int prec, const DslashTune &t, const void 
     // profiled: the compact half-stencils of the reduced operator (the
     // per-iteration launches), not the full-layout first and last steps
     ProfilePool &P = S->prof;
-    const bool ev = !io && P.on && P.used < (int)P.start.size();
+    const bool ev = timed && !io && P.on && P.used < (int)P.start.size();
     if (ev) GRG_TRY_HIP(hipEventRecord(P.start[P.used], L->stream));
     GRG_TRY_HIP(launch_eo_hop(prec, a, tu.grid, L->stream));
     if (grid_out) *grid_out = tu.grid;
@@ -786,11 +809,12 @@ grg_status tune_eo(grg_schur S, int prec, int nrhs, int reps)
 }
 
 // Minimal residual on the even-odd reduced system.  The inner right-hand
-// side b is in in_r (full layout); the solution is written to xdst (full
-// layout, zero on the coarse sites and for RHS that were already converged),
-// as inner_gcr does.
+// side b is in in_r (full layout), or with bc in the compact pair the defect
+// correction wrote (b_P at bc, b_Q one half on); the solution is written to
+// xdst (full layout, zero on the coarse sites and for RHS that were already
+// converged), as inner_gcr does.
 static grg_status inner_mr_eo(grg_schur S, int prec, int nrhs, const double *thr, int maxit,
-                              int *iters, double *rn2_out, void *xdst)
+                              int *iters, double *rn2_out, void *xdst, const void *bc = nullptr)
 {
     grg_lattice L = S->lat;
     hipStream_t st = L->stream;
@@ -805,13 +829,18 @@ static grg_status inner_mr_eo(grg_schur S, int prec, int nrhs, const double *thr
     void **f = S->eo_f[prec];
     void *r = f[0], *x = f[1], *q = f[2], *w = f[3];
     const void *b = S->in_r[prec];  // the unreduced right-hand side (full layout)
+    const void *bQ = bc ? (const char *)bc + eo_half_bytes(S, prec) : nullptr;
     const double d = 4.0 + S->m0;
     const int check = std::max(1, S->prm.check_every);
     // the reduced right-hand side b_P - H_PQ b_Q / d, read from the full field
-    // (with |r|^2 summed by the same launch)
+    // or the compact pair (with |r|^2 summed by the same launch)
     int pgrid = 0;
-    GRG_TRY(eo_hop(S, prec, t, b, b, r, P, 1.0, -1.0 / d, nrhs, S->partials, nullptr, nullptr, 1, 1, nullptr,
-                   &pgrid));
+    if (bc)
+        GRG_TRY(eo_hop(S, prec, t, bQ, bc, r, P, 1.0, -1.0 / d, nrhs, S->partials, nullptr, nullptr, 0, 0,
+                       nullptr, &pgrid, false));
+    else
+        GRG_TRY(eo_hop(S, prec, t, b, b, r, P, 1.0, -1.0 / d, nrhs, S->partials, nullptr, nullptr, 1, 1,
+                       nullptr, &pgrid));
     GRG_TRY_HIP(launch_reduce(kNorm3, S->partials, pgrid, nrhs, nullptr, S->rn2, S->thr2, S->active, st));
     double h[kMaxRhs];
     GRG_TRY(read_norms(S, nrhs, h));
@@ -856,8 +885,8 @@ static grg_status inner_mr_eo(grg_schur S, int prec, int nrhs, const double *thr
     memcpy(rn2_out, h, sizeof(double) * nrhs);
     // z_Q = (b_Q - H_QP z_P) / d (zero for the RHS that take no part),
     // written with z_P into the full layout
-    GRG_TRY(eo_hop(S, prec, t, x, b, xdst, Q, 1.0 / d, -1.0 / d, nrhs, nullptr, nullptr, S->act0,
-                   0, 1, x));
+    GRG_TRY(eo_hop(S, prec, t, x, bc ? bQ : b, xdst, Q, 1.0 / d, -1.0 / d, nrhs, nullptr, nullptr, S->act0,
+                   0, bc ? 0 : 1, x));
     if (done < 0) {
         set_error("non-finite residual in the inner solve");
         return GRG_ENONFINITE;
@@ -1249,6 +1278,7 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
     const void *r_src = S->b64;  // the residual of the current iterate
     int r_prec = GRG_FP64;       // its storage (FP32 in the late steps, see dc_fp32_threshold)
     bool rhs_ready = false;      // in_r holds s r_src in the inner precision
+    bool rhs_compact = false;    // ... in the compact pair eo_b instead (the reduced solve's)
     int total = 0, outer = 0;
     bool verified = false;
     grg_status status = GRG_OK;
@@ -1306,6 +1336,7 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
         if (!rhs_ready) {
             GRG_TRY(upload(d_s, sc, 2));
             GRG_TRY(convert_rhs(S, prec, sh, r_src, d_s, r_prec));
+            rhs_compact = false;
         }
         int it = 0;
         grg_status is;
@@ -1334,7 +1365,8 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
                 total += it;
             }
         } else if (reduce) {
-            is = inner_mr_eo(S, prec, nrhs, thr, p.max_iter - total, &it, h, e);
+            is = inner_mr_eo(S, prec, nrhs, thr, p.max_iter - total, &it, h, e,
+                             rhs_compact ? S->eo_b[prec] : nullptr);
             total += it;
         } else {
             is = inner_gcr(S, prec, nrhs, thr, p.max_iter - total, &it, h, e);
@@ -1376,7 +1408,13 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
         d.r_out32 = small;
         d.x_out = nullptr;
         d.f = d_f;
-        d.r_next = S->in_r[prec];
+        // the next inner right-hand side: straight into the compact pair of
+        // the reduced solve when the next inner solve is that one
+        const bool next_compact = reduce && !S->precond && p.method == 0;
+        if (next_compact) GRG_TRY(ensure_eo_rhs(S, prec));
+        d.r_next = next_compact ? S->eo_b[prec] : S->in_r[prec];
+        d.next_half = next_compact ? eo_half_bytes(S, prec) / prec_bytes(prec) : 0;
+        d.next_par = S->eo_par;
         d.s_next = d_sn;
         d.mask = S->d_mask;
         d.diag = 4.0 + S->m0;
@@ -1403,6 +1441,7 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
         r_src = small ? S->r32 : S->r64;
         r_prec = small ? GRG_FP32 : GRG_FP64;
         rhs_ready = true;
+        rhs_compact = next_compact;
     }
     if (status == GRG_ENOCONV) {
         // return each RHS's best iterate: drop the corrections after it that
