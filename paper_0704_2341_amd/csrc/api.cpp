@@ -432,7 +432,7 @@ static void schur_free(grg_schur S)
     dfree((void *&)S->bicg_sc);
     dfree((void *&)S->beta);
     dfree((void *&)S->rn2);
-    dfree((void *&)S->thr2);
+    S->thr2 = nullptr;  // inside bn2
     dfree((void *&)S->qn2);
     dfree((void *&)S->bn2);
     dfree((void *&)S->active);
@@ -497,9 +497,12 @@ grg_status grg_schur_create(grg_lattice L, double m0, const int32_t *q, int32_t 
     ALLOC(S->bicg_sc, sizeof(double2) * 4 * kMaxRhs);
     ALLOC(S->beta, sizeof(double2) * kMaxRhs * kMaxRhs);
     ALLOC(S->rn2, sizeof(double) * kMaxRhs);
-    ALLOC(S->thr2, sizeof(double) * kMaxRhs);
     ALLOC(S->qn2, sizeof(double) * kMaxRhs * kMaxRhs);
-    ALLOC(S->bn2, sizeof(double) * 4 * kMaxRhs);  // |b|^2, then per-RHS scales
+    // |b|^2, then the per-RHS scales f = 1/s, s and the next s, then the
+    // inner thresholds (thr2): one block, so the host uploads a step's
+    // scalars with one copy
+    ALLOC(S->bn2, sizeof(double) * 5 * kMaxRhs);
+    if (S->bn2) S->thr2 = S->bn2 + 4 * kMaxRhs;
     ALLOC(S->active, sizeof(int) * kMaxRhs);
     ALLOC(S->act0, sizeof(int) * kMaxRhs);
     if (L->eo_ok) ALLOC(S->d_mask_eo, (size_t)2 * L->Vhs);

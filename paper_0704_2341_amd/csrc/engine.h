@@ -183,9 +183,12 @@ struct BlasShape {
 //               active[r], else 0.  Also stores |q|^2 in aux[r].
 //  mode kNorm : in k = 1; out2[r] = sum; active[r] = sum > thr2[r].
 //  mode kNorm3: as kNorm from the third of k = 3 sums (a stencil's fused |out|^2).
+//  part (kNorm, kNorm3; optional): part[r] = thr2[r] finite (the RHS takes
+//  part in the solve; an infinite threshold marks one that does not).
 enum { kAlpha = 0, kNorm = 1, kNorm3 = 2 };
 hipError_t launch_reduce(int mode, const double *partials, int nparts, int nrhs, double2 *alpha,
-                         double *out2, const double *thr2, int *active, hipStream_t st);
+                         double *out2, const double *thr2, int *active, hipStream_t st,
+                         int *part = nullptr);
 
 // x += alpha r ; r -= alpha q ; partial |r|^2     (one MR/GCR step; x_zero:
 // x is taken as zero and not read, the first step from x = 0)

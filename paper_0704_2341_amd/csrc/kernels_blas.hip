@@ -708,7 +708,7 @@ __global__ void __launch_bounds__(256) orthogonalise_kernel(BlasShape sh, const 
 // ------------------------------------------------------------------ reductions
 __global__ void __launch_bounds__(256) reduce_kernel(int mode, const double *partials, int nparts,
                                                      int nrhs, double2 *alpha, double *out2,
-                                                     const double *thr2, int *active)
+                                                     const double *thr2, int *active, int *part)
 {
     __shared__ double sm[3][256];
     const int r = blockIdx.x;
@@ -733,6 +733,7 @@ __global__ void __launch_bounds__(256) reduce_kernel(int mode, const double *par
             const double n2 = sm[mode == kNorm3 ? 2 : 0][0];
             out2[r] = n2;
             if (active) active[r] = n2 > thr2[r] ? 1 : 0;
+            if (part) part[r] = isinf(thr2[r]) ? 0 : 1;
         }
     }
 }
@@ -782,10 +783,10 @@ static bool shape_ok(const BlasShape &sh)
 }
 
 hipError_t launch_reduce(int mode, const double *partials, int nparts, int nrhs, double2 *alpha,
-                         double *out2, const double *thr2, int *active, hipStream_t st)
+                         double *out2, const double *thr2, int *active, hipStream_t st, int *part)
 {
     hipLaunchKernelGGL(reduce_kernel, dim3(nrhs), dim3(256), 0, st, mode, partials, nparts, nrhs,
-                       alpha, out2, thr2, active);
+                       alpha, out2, thr2, active, part);
     return hipGetLastError();
 }
 

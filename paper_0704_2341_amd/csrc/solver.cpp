@@ -841,17 +841,13 @@ static grg_status inner_mr_eo(grg_schur S, int prec, int nrhs, const double *thr
     else
         GRG_TRY(eo_hop(S, prec, t, b, b, r, P, 1.0, -1.0 / d, nrhs, S->partials, nullptr, nullptr, 1, 1,
                        nullptr, &pgrid));
-    GRG_TRY_HIP(launch_reduce(kNorm3, S->partials, pgrid, nrhs, nullptr, S->rn2, S->thr2, S->active, st));
+    // |r|^2, the device's active flags, and act0: the RHS that take part
+    // (finite threshold; the others keep a zero correction).  One whose
+    // reduced right-hand side already meets its threshold takes no step,
+    // x_P = 0, but its correction z_Q = b_Q / d is not zero.
+    GRG_TRY_HIP(launch_reduce(kNorm3, S->partials, pgrid, nrhs, nullptr, S->rn2, S->thr2, S->active, st,
+                              S->act0));
     double h[kMaxRhs];
-    GRG_TRY(read_norms(S, nrhs, h));
-    // the RHS that take part (thr finite; the others keep a zero correction).
-    // One whose reduced right-hand side already meets its threshold takes no
-    // step, x_P = 0, but its correction z_Q = b_Q / d is not zero.
-    {
-        int *flags = (int *)(S->h_buf + 8 * kMaxRhs);
-        for (int k = 0; k < nrhs; ++k) flags[k] = thr[k] < HUGE_VAL ? 1 : 0;
-        GRG_TRY_HIP(hipMemcpyAsync(S->act0, flags, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
-    }
     auto all_done = [&](const double *n2) {
         for (int k = 0; k < nrhs; ++k) {
             if (!isfinite(n2[k])) return -1;
@@ -860,7 +856,13 @@ static grg_status inner_mr_eo(grg_schur S, int prec, int nrhs, const double *thr
         return 1;
     };
     int it = 0;
-    int done = all_done(h);
+    // the norms are first read after `check` iterations (inactive RHS leave
+    // them unchanged), not before the first: one wait for the host fewer
+    int done = 0;
+    if (maxit <= 0) {
+        GRG_TRY(read_norms(S, nrhs, h));
+        done = all_done(h);
+    }
     while (done == 0 && it < maxit) {
         // q = (d - H_PQ H_QP / d) r, with the sums for alpha
         GRG_TRY(eo_hop(S, prec, t, r, nullptr, w, Q, 0.0, 1.0, nrhs, nullptr, nullptr));
@@ -1227,11 +1229,15 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
     memcpy(bn2, S->h_buf, sizeof(double) * nrhs);
     memcpy(rn2, bn2, sizeof(double) * nrhs);
     for (int k = 0; k < nrhs; ++k) sc[k] = bn2[k] > 0 && isfinite(bn2[k]) ? 1.0 / sqrt(bn2[k]) : 1.0;
-    double *hb = S->h_buf + 4 * kMaxRhs;  // upload staging; reads use the front
-    auto upload = [&](double *dst, const double *src, int slot) -> grg_status {
-        memcpy(hb + slot * kMaxRhs, src, sizeof(double) * nrhs);
-        GRG_TRY_HIP(hipMemcpyAsync(dst, hb + slot * kMaxRhs, sizeof(double) * nrhs,
-                                   hipMemcpyHostToDevice, st));
+    // the per-RHS scalar block bn2: row 0 |b|^2, rows 1..4 f = 1/s, s, the
+    // next s and the inner thresholds (thr2), staged on the host at hb (row k
+    // at hb + (k - 1) kMaxRhs; reads use the front of h_buf), rows k0..k1
+    // uploaded by one copy
+    double *hb = S->h_buf + 4 * kMaxRhs;
+    auto stage = [&](int row, const double *src) { memcpy(hb + (row - 1) * kMaxRhs, src, sizeof(double) * nrhs); };
+    auto upload_rows = [&](int k0, int k1) -> grg_status {
+        GRG_TRY_HIP(hipMemcpyAsync(S->bn2 + k0 * kMaxRhs, hb + (k0 - 1) * kMaxRhs,
+                                   sizeof(double) * kMaxRhs * (k1 - k0 + 1), hipMemcpyHostToDevice, st));
         return GRG_OK;
     };
     // the kept corrections and the part of x already summed into x64
@@ -1331,10 +1337,11 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
             thr[k] = on ? rel * rel * ih[k] : HUGE_VAL;  // converged: takes no part
             f[k] = 1.0 / sc[k];
         }
-        GRG_TRY(upload(S->thr2, thr, 0));
-        GRG_TRY(upload(d_f, f, 1));
+        stage(4, thr);
+        stage(1, f);
+        if (!rhs_ready) stage(2, sc);
+        GRG_TRY(upload_rows(1, 4));  // f, s (when it changes), thresholds
         if (!rhs_ready) {
-            GRG_TRY(upload(d_s, sc, 2));
             GRG_TRY(convert_rhs(S, prec, sh, r_src, d_s, r_prec));
             rhs_compact = false;
         }
@@ -1357,7 +1364,8 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
                 grg_precond keep = S->precond;
                 S->precond = nullptr;
                 ++S->fallbacks;
-                GRG_TRY(upload(d_s, sc, 2));
+                stage(2, sc);
+                GRG_TRY(upload_rows(2, 2));
                 GRG_TRY(convert_rhs(S, prec, sh, r_src, d_s, r_prec));
                 is = reduce ? inner_mr_eo(S, prec, nrhs, thr, p.max_iter - total, &it, h, e)
                             : inner_gcr(S, prec, nrhs, thr, p.max_iter - total, &it, h, e);
@@ -1380,7 +1388,8 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
             const double est = sqrt(h[k] > 0 ? h[k] : 0.0) / sc[k];
             scn[k] = est > 0 && isfinite(est) && isfinite(1.0 / est) ? 1.0 / est : sc[k];
         }
-        GRG_TRY(upload(d_sn, scn, 3));
+        stage(3, scn);
+        GRG_TRY(upload_rows(3, 3));
         // r -= A e / s ; next inner rhs s' r   (FP64, fused; x is summed at the end)
         // the residual's storage from here on: FP32 once it is small for
         // every RHS (r_src is that of the step's input)
