@@ -319,9 +319,10 @@ grg_status grg_schur_set_launch(grg_schur s, int precision, int nrhs, const int3
  * (info[0] threads per workgroup: 64, 128 or 256) and info[5] = T > 0 the
  * t-marching kernel (64 * info[1] <= 512 threads, time chunks of T);
  * info[2] = 1 selects the LDS-ring form of the t-marching kernel (BF16 inner
- * precision, Lx dividing 64 and a multiple of 64 sites per x-y-z slice;
- * the column's e at t - 1 and t kept in LDS, each site finished within its
- * slice), 3 the same with the work items ordered RHS group first (the groups
+ * precision, Lx dividing 64, a multiple of 64 sites per x-y-z slice and at
+ * most 4 RHS per workgroup; the column's e at t - 1 and t and its U_t at
+ * t - 1 kept in LDS, each site finished within its slice), 3 the same with
+ * the work items ordered RHS group first (the groups
  * of a tile run together on one XCD and share its links), else 0.
  * *ms = tuned time per step, or -1 if untuned. */
 grg_status grg_schur_dc_launch_info(grg_schur s, int precision, int nrhs, int32_t info[6],

@@ -406,8 +406,9 @@ __global__ void __launch_bounds__(E::kThreads) march_kernel(typename E::Args a)
 // x-row, lanes of the same wavefront) read LDS, and no second FP64
 // accumulator is carried from one slice to the next.  The hops of a site are
 // summed in march_kernel's order (backward t, diagonal, x, y, z, forward t).
+constexpr int kRingWaves = 4;  // wavefronts (RHS) per workgroup of the LDS-ring form
 template <class E>
-__global__ void __launch_bounds__(512) ring_march_kernel(typename E::Args a)
+__global__ void __launch_bounds__(64 * kRingWaves) ring_march_kernel(typename E::Args a)
 {
     typedef typename E::SIN S;
     typedef typename E::SU SU;
@@ -418,7 +419,10 @@ __global__ void __launch_bounds__(512) ring_march_kernel(typename E::Args a)
     typedef typename OU::T UT;
     static_assert(sizeof(PT) == 4, "the LDS ring holds packed BF16 words");
     constexpr int K = E::K;
-    __shared__ PT ring[8][2][12][64];
+    __shared__ PT ring[kRingWaves][2][12][64];
+    // per wavefront, U_t of its column at the previous slice: the backward t
+    // link of this slice (the forward one of the last), kept from there
+    __shared__ double2 utl[kRingWaves][9][64];
     __shared__ double red[kMaxRhs][K];
     const S *__restrict__ in = E::input(a);
     const SU *__restrict__ U = E::links(a);
@@ -440,6 +444,7 @@ __global__ void __launch_bounds__(512) ring_march_kernel(typename E::Args a)
     const int xh = lane % Lx, rs = lane - xh;
     const int lp = rs + (xh + 1 == Lx ? 0 : xh + 1), lm = rs + (xh == 0 ? Lx - 1 : xh - 1);
     PT (*q)[12][64] = ring[wv];
+    double2 (*ut)[64] = utl[wv];
     double dot[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) dot[k] = 0.0;
@@ -476,6 +481,9 @@ __global__ void __launch_bounds__(512) ring_march_kernel(typename E::Args a)
                 q[(t0 - 1) & 1][c][lane] = OP::load(in, fidx(s3 + V3 * tm, r, c, a.nrhs));
                 q[t0 & 1][c][lane] = OP::load(in, fidx(s3 + V3 * t0, r, c, a.nrhs));
             }
+            // U_t one slice below t0 (each lane reads back only its own entries)
+#pragma unroll
+            for (int e = 0; e < 9; ++e) ut[e][lane] = ((const double2 *)U)[lidx(s3 + V3 * tm, 3, e)];
         }
 #pragma unroll 1
         for (int t = t0; t < t1; ++t) {
@@ -494,7 +502,10 @@ __global__ void __launch_bounds__(512) ring_march_kernel(typename E::Args a)
                 PT p[12];
                 UT u[9];
 #pragma unroll
-                for (int e = 0; e < 9; ++e) u[e] = OU::load(U, lidx(s3 + V3 * tb, 3, e));
+                for (int e = 0; e < 9; ++e) {
+                    const double2 w = ut[e][lane];
+                    u[e] = {w.x, w.y};
+                }
 #pragma unroll
                 for (int c = 0; c < 12; ++c) p[c] = q[(t - 1) & 1][c][lane];
                 hop<3, false>(acc, p, u);
@@ -537,6 +548,9 @@ __global__ void __launch_bounds__(512) ring_march_kernel(typename E::Args a)
 #pragma unroll
                 for (int e = 0; e < 9; ++e) u[e] = OU::load(U, lidx(s, 3, e));
                 hop<3, true>(acc, qc, u);
+                // the backward t link of the next slice
+#pragma unroll
+                for (int e = 0; e < 9; ++e) ut[e][lane] = make_double2(u[e].re, u[e].im);
             }
             // slice t + 1 into the slot of slice t - 1 (read above by this
             // lane only)
@@ -787,7 +801,7 @@ hipError_t launch_dc_update(int prec, const DcArgs &a, int grid, int SB, hipStre
     if (a.nrhs < 1 || a.nrhs > kMaxRhs || grid < 8 || grid % 8) return hipErrorInvalidValue;
     if (a.march > 0 && a.ring) {
         const int V3 = a.g.L[0] * a.g.L[1] * a.g.L[2];
-        if (prec != GRG_BF16 || a.RG < 1 || 64 * a.RG > 512 || V3 % 64 || 64 % a.g.L[0])
+        if (prec != GRG_BF16 || a.RG < 1 || a.RG > kRingWaves || V3 % 64 || 64 % a.g.L[0])
             return hipErrorInvalidValue;
         hipLaunchKernelGGL(ring_march_kernel<DcEpi<GRG_BF16>>, dim3(grid), dim3(64 * a.RG), 0, st, a);
         return hipGetLastError();

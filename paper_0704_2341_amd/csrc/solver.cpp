@@ -251,7 +251,7 @@ bool dc_launch_ok(const Geom &g, int prec, int nrhs, const DslashTune &t)
     // the RHS groups of a tile adjacent in the item order
     if (t.split != 0 && t.split != 1 && t.split != 3) return false;
     const int V3 = g.L[0] * g.L[1] * g.L[2];
-    if ((t.split & 1) && (t.march < 1 || prec != GRG_BF16 || V3 % 64 || 64 % g.L[0])) return false;
+    if ((t.split & 1) && (t.march < 1 || prec != GRG_BF16 || V3 % 64 || 64 % g.L[0] || t.RG > 4)) return false;
     if (t.march > 0) return t.march <= g.L[3] && t.RG >= 1 && t.RG <= nrhs && 64 * t.RG <= 512;
     return t.SB == 64 || t.SB == 128 || t.SB == 256;
 }
