@@ -202,10 +202,12 @@ hipError_t launch_norm2(int prec, const BlasShape &sh, const void *v, double *pa
 hipError_t launch_sub_norm(const BlasShape &sh, const void *b, const void *ax, void *r,
                            double *partials, hipStream_t st);
 // y (prec_out) = beta*y + scale[r] * x (prec_in); scale from a device array
-// of per-RHS reals, multiplied by 1/sqrt(scale) when inv_sqrt != 0.
+// of per-RHS reals, multiplied by 1/sqrt(scale) when inv_sqrt != 0.  With
+// y_half > 0, y is a compact even-odd pair (parity y_first's half first, the
+// other y_half elements on; beta 0).
 hipError_t launch_axpy_convert(int prec_in, int prec_out, const BlasShape &sh, const void *x,
                                void *y, const double *scale, int inv_sqrt, int beta,
-                               const int *active, hipStream_t st);
+                               const int *active, hipStream_t st, size_t y_half = 0, int y_first = 0);
 // y = x - y (FP64), used for u - z
 hipError_t launch_xmy(const BlasShape &sh, const void *x, void *y, hipStream_t st);
 // Second-order Schur complement approximation (kernels_blas.hip): the

@@ -390,10 +390,14 @@ __global__ void __launch_bounds__(256) sub_norm_kernel(BlasShape sh, const doubl
 }
 
 // y = beta*y + f(scale[k]) * x, f = identity / 1/sqrt / sqrt
+// With y_half > 0, y is written as a compact even-odd pair instead (a site
+// of parity y_first at compact index s / 2, the other parity y_half
+// elements on; beta must be 0).
 template <int PI, int PO>
 __global__ void __launch_bounds__(256) axpy_convert_kernel(BlasShape sh, const void *x_, void *y_,
                                                            const double *scale, int mode,
-                                                           int beta, const int *active)
+                                                           int beta, const int *active,
+                                                           size_t y_half, int y_first)
 {
     typedef typename Store<PI>::S SI;
     typedef typename Store<PI>::R RI;
@@ -403,6 +407,13 @@ __global__ void __launch_bounds__(256) axpy_convert_kernel(BlasShape sh, const v
     SO *y = (SO *)y_;
     SITE_LOOP_BEGIN(sh)
     if (valid) {
+        size_t ybase = 0;
+        if (y_half) {
+            const int x0 = s % sh.g.L[0], s1 = s / sh.g.L[0];
+            const int x1 = s1 % sh.g.L[1], s2 = s1 / sh.g.L[1];
+            const int par = (x0 + x1 + s2 % sh.g.L[2] + s2 / sh.g.L[2]) & 1;
+            ybase = par == y_first ? 0 : y_half;
+        }
         for (int k = 0; k < sh.nrhs; ++k) {
             double f = scale ? scale[k] : 1.0;
             if (mode == 1) f = f > 0 ? 1.0 / sqrt(f) : 0.0;
@@ -419,7 +430,7 @@ __global__ void __launch_bounds__(256) axpy_convert_kernel(BlasShape sh, const v
                     o.re += yo.re;
                     o.im += yo.im;
                 }
-                stc(y, i, o);
+                stc(y, y_half ? ybase + fidx(s >> 1, k, c, sh.nrhs) : i, o);
             }
         }
     }
@@ -859,14 +870,14 @@ hipError_t launch_sub_norm(const BlasShape &sh, const void *b, const void *ax, v
 
 hipError_t launch_axpy_convert(int prec_in, int prec_out, const BlasShape &sh, const void *x,
                                void *y, const double *scale, int mode, int beta,
-                               const int *active, hipStream_t st)
+                               const int *active, hipStream_t st, size_t y_half, int y_first)
 {
-    if (!shape_ok(sh)) return hipErrorInvalidValue;
+    if (!shape_ok(sh) || (y_half && beta)) return hipErrorInvalidValue;
     dim3 g(sh.grid), b(kBlasSB);
 #define AXC(PI, PO)                                                                                \
     if (prec_in == PI && prec_out == PO) {                                                         \
         hipLaunchKernelGGL((axpy_convert_kernel<PI, PO>), g, b, 0, st, sh, x, y, scale, mode, beta, \
-                           active);                                                                \
+                           active, y_half, y_first);                                               \
         return hipGetLastError();                                                                  \
     }
     AXC(GRG_FP64, GRG_FP64) AXC(GRG_FP64, GRG_FP32) AXC(GRG_FP64, GRG_BF16)

@@ -1151,9 +1151,17 @@ constexpr int kPrecondInnerCap = 100;
 // The inner right-hand side s_k r_k in the inner precision, from the FP64
 // residual r (scale: device array of s_k).
 static grg_status convert_rhs(grg_schur S, int prec, const BlasShape &sh, const void *r_src,
-                              const double *scale, int r_prec = GRG_FP64)
+                              const double *scale, int r_prec = GRG_FP64, bool pair = false)
 {
     PhaseTimer pt(S->prof, S->lat->stream, kProfBlas);
+    if (pair) {
+        // into the compact pair the reduced solve reads (parity eo_par first)
+        GRG_TRY(ensure_eo_rhs(S, prec));
+        GRG_TRY_HIP(launch_axpy_convert(r_prec, prec, sh, r_src, S->eo_b[prec], scale, 0, 0, nullptr,
+                                        S->lat->stream, eo_half_bytes(S, prec) / prec_bytes(prec),
+                                        S->eo_par));
+        return GRG_OK;
+    }
     GRG_TRY_HIP(launch_axpy_convert(r_prec, prec, sh, r_src, S->in_r[prec], scale, 0, 0, nullptr,
                                     S->lat->stream));
     return GRG_OK;
@@ -1341,16 +1349,20 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
         stage(1, f);
         if (!rhs_ready) stage(2, sc);
         GRG_TRY(upload_rows(1, 4));  // f, s (when it changes), thresholds
+        // the reduced system divides by the diagonal d = 4 + m0: none at d = 0
+        const bool eo_form = p.eo && L->eo_ok && 4.0 + S->m0 != 0.0;
+        const bool reduce = eo_form && std::max(1, p.restart) == 1;
+        // the inner right-hand side as the compact pair of the reduced solve
+        // when that is the inner solve (converted here, or written so by the
+        // previous defect-correction step)
+        const bool pair_rhs = reduce && !S->precond && p.method == 0;
         if (!rhs_ready) {
-            GRG_TRY(convert_rhs(S, prec, sh, r_src, d_s, r_prec));
-            rhs_compact = false;
+            GRG_TRY(convert_rhs(S, prec, sh, r_src, d_s, r_prec, pair_rhs));
+            rhs_compact = pair_rhs;
         }
         int it = 0;
         grg_status is;
         double h[kMaxRhs];
-        // the reduced system divides by the diagonal d = 4 + m0: none at d = 0
-        const bool eo_form = p.eo && L->eo_ok && 4.0 + S->m0 != 0.0;
-        const bool reduce = eo_form && std::max(1, p.restart) == 1;
         if (p.method == 1) {
             is = inner_bicgstab(S, prec, nrhs, thr, p.max_iter - total, &it, h, e, eo_form);
             total += it;
@@ -1419,7 +1431,7 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
         d.f = d_f;
         // the next inner right-hand side: straight into the compact pair of
         // the reduced solve when the next inner solve is that one
-        const bool next_compact = reduce && !S->precond && p.method == 0;
+        const bool next_compact = pair_rhs;
         if (next_compact) GRG_TRY(ensure_eo_rhs(S, prec));
         d.r_next = next_compact ? S->eo_b[prec] : S->in_r[prec];
         d.next_half = next_compact ? eo_half_bytes(S, prec) / prec_bytes(prec) : 0;
