@@ -28,7 +28,7 @@ void set_error(const char *fmt, ...)
 
 grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats,
                               const void *u_minus = nullptr, const double *xb = nullptr, double *yb = nullptr,
-                              bool *fused = nullptr, int bn2_parts = 0);
+                              bool *fused = nullptr, int bn2_parts = 0, bool rhs_pair = false);
 grg_status schur_apply_internal(grg_schur S, const double *xb, double *yb, int nrhs,
                                 grg_solver_stats *stats);
 grg_status run_dslash(grg_schur S, int prec, const void *in, void *out, int sel, int nrhs,

@@ -145,8 +145,11 @@ hipError_t launch_dslash_coarse(const CoarseArgs &a, hipStream_t st);
 // b = D_rb x_b from the canonical coarse vector (kernels_coarse.hip): internal
 // FP64 field, zero on the coarse sites
 // With partials set, also the per-workgroup |b|^2 per RHS ([rb_apply_grid(g)][nrhs]).
+// With pair set, b also in precision pair_prec as a compact even-odd pair
+// (parity `first` at compact index s / 2, the other parity `half` elements on).
 hipError_t launch_rb_apply(const Geom &g, const double *xb, const int32_t *bidx, int nb, const void *U64,
-                           void *out, int nrhs, hipStream_t st, double *partials = nullptr);
+                           void *out, int nrhs, hipStream_t st, double *partials = nullptr,
+                           int pair_prec = -1, void *pair = nullptr, size_t half = 0, int first = 0);
 int rb_apply_grid(const Geom &g);
 // y_b = [D (u + sigma sum_j f_j e_j)]_b, u = x_b on the coarse sites, from the
 // kept corrections (inner precision prec) at the coarse sites' neighbours

@@ -51,11 +51,15 @@ __device__ __forceinline__ void rb_hops(cpx<double> (&acc)[12], int s, const Sit
 // Work items (block of 256 sites, RHS) with the RHS fastest, one contiguous
 // range per XCD: the RHS of a site block run side by side in one L2 and share
 // its links and neighbour lists.  partials[workgroup][r]: the workgroup's sum
-// of |out|^2 for RHS r.
+// of |out|^2 for RHS r.  PP >= 0: b also written, in precision PP, into the
+// compact even-odd pair `pair` (parity `first` at compact index s / 2, the
+// other parity `half` elements on), the reduced solve's right-hand side.
+template <int PP>
 __global__ void __launch_bounds__(256) rb_apply_kernel(Geom g, const double2 *__restrict__ xb,
                                                        const int32_t *__restrict__ bidx, int nb,
                                                        const double2 *__restrict__ U, double2 *__restrict__ out,
-                                                       int nrhs, double *partials)
+                                                       int nrhs, double *partials, void *pair, size_t half,
+                                                       int first)
 {
     __shared__ double red[4][kMaxRhs];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -82,6 +86,15 @@ __global__ void __launch_bounds__(256) rb_apply_kernel(Geom g, const double2 *__
                 out[fidx(s, r, c, nrhs)] = make_double2(acc[c].re, acc[c].im);
                 n2 += acc[c].re * acc[c].re + acc[c].im * acc[c].im;
             }
+            if constexpr (PP >= 0) {
+                typedef typename Store<PP>::S SP;
+                typedef typename Store<PP>::R RP;
+                const SiteGeo q = site_geo(s, g);
+                const size_t base =
+                    (((q.c[0] + q.c[1] + q.c[2] + q.c[3]) & 1) == first ? 0 : half) + fidx(s >> 1, r, 0, nrhs);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) stc((SP *)pair, base + 64 * c, cpx<RP>{(RP)acc[c].re, (RP)acc[c].im});
+            }
         }
         n2 = wave_sum(n2);  // every lane of the wavefront takes part
         if (lane == 0) red[wave][r] += n2;
@@ -101,11 +114,21 @@ int rb_apply_grid(const Geom &g)
 }
 
 hipError_t launch_rb_apply(const Geom &g, const double *xb, const int32_t *bidx, int nb, const void *U64,
-                           void *out, int nrhs, hipStream_t st, double *partials)
+                           void *out, int nrhs, hipStream_t st, double *partials, int pair_prec, void *pair,
+                           size_t half, int first)
 {
     if (nrhs < 1 || nrhs > kMaxRhs || nb < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(rb_apply_kernel, dim3(rb_apply_grid(g)), dim3(256), 0, st, g,
-                       (const double2 *)xb, bidx, nb, (const double2 *)U64, (double2 *)out, nrhs, partials);
+#define RBA(PP)                                                                                        \
+    hipLaunchKernelGGL(rb_apply_kernel<PP>, dim3(rb_apply_grid(g)), dim3(256), 0, st, g, (const double2 *)xb, \
+                       bidx, nb, (const double2 *)U64, (double2 *)out, nrhs, partials, pair, half, first)
+    switch (pair ? pair_prec : -1) {
+    case -1: RBA(-1); break;
+    case GRG_FP64: RBA(GRG_FP64); break;
+    case GRG_FP32: RBA(GRG_FP32); break;
+    case GRG_BF16: RBA(GRG_BF16); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef RBA
     return hipGetLastError();
 }
 

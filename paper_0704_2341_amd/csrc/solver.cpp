@@ -1215,7 +1215,7 @@ static grg_status pool_slot(grg_schur S, int prec, int k, void **out)
 // when it is not (no pool overflow, no verification) the final step writes
 // y_b = [D (u - z)]_b from the corrections directly and sets *fused.
 grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, const void *u_minus,
-                              const double *xb, double *yb, bool *fused, int bn2_parts)
+                              const double *xb, double *yb, bool *fused, int bn2_parts, bool rhs_pair)
 {
     grg_lattice L = S->lat;
     hipStream_t st = L->stream;
@@ -1237,6 +1237,17 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
     memcpy(bn2, S->h_buf, sizeof(double) * nrhs);
     memcpy(rn2, bn2, sizeof(double) * nrhs);
     for (int k = 0; k < nrhs; ++k) sc[k] = bn2[k] > 0 && isfinite(bn2[k]) ? 1.0 / sqrt(bn2[k]) : 1.0;
+    // rhs_pair: the producer of b also wrote it unscaled (s = 1) into the
+    // compact pair of the reduced solve; used when that is the first inner
+    // solve and every |b| is within [1e-10, 1e10] (the inner precision's
+    // sums then stay far inside FP32's range), else converted as usual
+    const bool pair_inner = p.eo && L->eo_ok && 4.0 + S->m0 != 0.0 && std::max(1, p.restart) == 1 &&
+                            !S->precond && p.method == 0;
+    bool pair_ok = rhs_pair && pair_inner;
+    for (int k = 0; k < nrhs && pair_ok; ++k)
+        if (!(bn2[k] == 0.0 || (bn2[k] >= 1e-20 && bn2[k] <= 1e20))) pair_ok = false;
+    if (pair_ok)
+        for (int k = 0; k < nrhs; ++k) sc[k] = 1.0;
     // the per-RHS scalar block bn2: row 0 |b|^2, rows 1..4 f = 1/s, s, the
     // next s and the inner thresholds (thr2), staged on the host at hb (row k
     // at hb + (k - 1) kMaxRhs; reads use the front of h_buf), rows k0..k1
@@ -1291,8 +1302,8 @@ grg_status drr_solve_internal(grg_schur S, int nrhs, grg_solver_stats *stats, co
 
     const void *r_src = S->b64;  // the residual of the current iterate
     int r_prec = GRG_FP64;       // its storage (FP32 in the late steps, see dc_fp32_threshold)
-    bool rhs_ready = false;      // in_r holds s r_src in the inner precision
-    bool rhs_compact = false;    // ... in the compact pair eo_b instead (the reduced solve's)
+    bool rhs_ready = pair_ok;    // in_r holds s r_src in the inner precision
+    bool rhs_compact = pair_ok;  // ... in the compact pair eo_b instead (the reduced solve's)
     int total = 0, outer = 0;
     bool verified = false;
     grg_status status = GRG_OK;
@@ -1557,12 +1568,22 @@ grg_status schur_apply_internal(grg_schur S, const double *xb, double *yb, int n
     hipStream_t st = L->stream;
     const Geom &g = L->g;
     // b = (D u)_r = D_rb x_b (u = x_b on the coarse sites), from the coarse
-    // vector's hops only
-    GRG_TRY_HIP(launch_rb_apply(g, xb, S->d_bidx, S->nb, L->U[GRG_FP64], S->b64, nrhs, st, S->partials));
+    // vector's hops only; for a mixed-precision reduced solve also straight
+    // into its compact right-hand side
+    const grg_solver_params &p = S->prm;
+    const bool pair = p.inner != GRG_FP64 && p.eo && L->eo_ok && 4.0 + S->m0 != 0.0 &&
+                      std::max(1, p.restart) == 1 && !S->precond && p.method == 0;
+    if (pair) {
+        GRG_TRY(ensure_inner(S, p.inner));
+        GRG_TRY(ensure_eo_rhs(S, p.inner));
+    }
+    GRG_TRY_HIP(launch_rb_apply(g, xb, S->d_bidx, S->nb, L->U[GRG_FP64], S->b64, nrhs, st, S->partials,
+                                pair ? p.inner : -1, pair ? S->eo_b[p.inner] : nullptr,
+                                pair ? eo_half_bytes(S, p.inner) / prec_bytes(p.inner) : 0, S->eo_par));
     // z = D_rr^{-1} b (|b|^2 from rb_apply's sums), and y_b = [D (u - z)]_b
     // fused into its last step, or x64 = u - z (u scattered into u64 when needed)
     bool fused = false;
-    grg_status s = drr_solve_internal(S, nrhs, stats, S->u64, xb, yb, &fused, rb_apply_grid(g));
+    grg_status s = drr_solve_internal(S, nrhs, stats, S->u64, xb, yb, &fused, rb_apply_grid(g), pair);
     if (s != GRG_OK && s != GRG_ENOCONV) return s;
     if (fused) return s;
     // y_b = [D (u - z)]_b
