@@ -361,3 +361,26 @@ def test_sixteen_rhs(dims, inner, tune):
     assert rel_err(y[idx], want) < 1e-8
     s.close()
     lat.close()
+
+
+@pytest.mark.parametrize("inner", ["bf16", "fp32"])
+def test_extreme_magnitudes(c4, inner):
+    """S_bb is linear: inputs scaled by 1e-15 or 1e15 (beyond the range in
+    which the inner solve starts from the unscaled right-hand side, so it is
+    rescaled first) give the scaled result of the unit-size input."""
+    lat, d = c4
+    grg = lat.grg
+    q, nb = grg.grg_permutation_block(DIMS, 1, False)
+    tol_in = {"fp32": 1e-5, "bf16": 1e-2}[inner]
+    p = grg.grg_solver_params_default(tol=1e-12, inner=inner, inner_tol=tol_in, max_rhs=3)
+    s = Schur(lat, grg.grg_schur_create(lat.h, M0, q, nb, p), q, nb, M0)
+    xb = gaussian_vectors(12 * nb, 1, 86)
+    want = dense.schur_apply_dense(d, q, nb, xb)
+    y1, st = s.apply(xb)
+    assert st["converged"] and rel_err(y1, want) < 1e-10
+    x3 = np.concatenate([xb * 1e-15, xb, xb * 1e15])
+    y3, st = s.apply(x3)
+    assert st["converged"]
+    for k, f in enumerate((1e-15, 1.0, 1e15)):
+        assert rel_err(y3[k:k + 1] / f, want) < 1e-10, f
+    s.close()
