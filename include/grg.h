@@ -164,7 +164,12 @@ grg_status grg_lattice_destroy(grg_lattice lat);
 grg_status grg_lattice_volume(grg_lattice lat, int64_t *volume);
 
 /* Set the gauge field from canonical links (host pointer if on_device == 0,
- * device pointer otherwise).  Copies are made in every precision. */
+ * device pointer otherwise).  Copies are made in every precision.  Schur
+ * handles and learned preconditioners on lat read the links at every call,
+ * so they follow a new field from their next call; a V-cycle hierarchy
+ * blocks the links into its coarse lattices when it is created and must be
+ * created again after the field changes.  Must not overlap a call that uses
+ * lat. */
 grg_status grg_gauge_set(grg_lattice lat, const double *links, int on_device);
 
 /* The site permutation of section 2 (Permutation_block): q[k] is the site

@@ -102,3 +102,35 @@ def test_lattice_queries_and_null_handles():
     with pytest.raises(grg.GrgError) as e:
         grg.grg_lattice_create(DIMS, bc=(1, 1, 0, -1))
     assert e.value.status == grg.GRG_EINVAL
+
+
+def test_new_gauge_field_on_existing_handles():
+    """A Schur handle reads the lattice's links at every call: after
+    grg_gauge_set its S_bb apply (BF16 inner solve on the even-odd reduced
+    D_rr, whose links are repacked) and its section 3 approximation (whose
+    row sums of D_rr are cached per gauge field) follow the new field."""
+    import torch
+    import paper_0704_2341_amd as grg
+
+    ensure_built()
+    dims, m0 = (8, 8, 8, 8), -0.2
+    fields = [su3_links(dims, 0.5, 86), su3_links(dims, 0.3, 87)]
+    lat = grg.grg_lattice_create(dims)
+    grg.grg_gauge_set(lat, fields[0])
+    q, nb = grg.grg_permutation_block(dims, 1, False)
+    p = grg.grg_solver_params_default(tol=1e-12, inner="bf16", inner_tol=1e-2, max_rhs=2)
+    h = grg.grg_schur_create(lat, m0, q, nb, p)
+    xb = gaussian_vectors(12 * nb, 2, 88)
+    x = to_dev(xb)
+    for k, links in enumerate(fields):
+        if k:
+            grg.grg_gauge_set(lat, links)
+        y = torch.empty_like(x)
+        st = grg.grg_schur_apply(h, x, y, 2)
+        assert st["converged"]
+        want, _, _ = matfree.schur_apply(links, dims, m0, q, nb, xb, restart=8, tol=1e-13)
+        assert rel_err(to_host(y), want) < 1e-10, k
+        grg.grg_reusken_apply(h, x, y, 2)
+        assert rel_err(to_host(y), matfree.reusken_apply(links, dims, m0, q, nb, xb)) < 1e-12, k
+    grg.grg_schur_destroy(h)
+    grg.grg_lattice_destroy(lat)
