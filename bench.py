@@ -104,11 +104,15 @@ def copy_calibration(torch, mib: int) -> int:
 
 
 def time_applies(grg, s, xb, yb, nrhs, steps, warmup, profile):
+    """Time `steps` applies after `warmup` untimed ones.  With profile set,
+    HIP events bracket every stencil launch of the timed applies (the
+    library's launch-only profiling: no per-phase events, and the events are
+    read once, after the timed region)."""
     import torch
 
     for _ in range(warmup):
         grg.grg_schur_apply(s, xb, yb, nrhs)
-    grg.grg_profile_enable(s, profile)
+    grg.grg_profile_enable(s, profile, launches_only=True)
     grg.grg_profile_reset(s)
     stats = []
     torch.cuda.synchronize()

@@ -112,7 +112,9 @@ typedef struct {
     double true_rel_resid; /* max over RHS of the FP64 ||b - D_rr x|| / ||b|| */
     double t_total_ms;     /* wall time of the call on the stream */
     double t_dslash_ms;    /* summed stencil time: D_rr, D_rb and the reduced operator's
-                              half-lattice stencils (only with profiling on) */
+                              half-lattice stencils (only with profiling on; this and
+                              the other phase times are -1 with launch-only
+                              profiling) */
     int fallbacks;         /* inner solves redone without the preconditioner */
     double t_dc_ms;        /* summed time of the FP64 defect-correction steps (stencil and
                               residual update fused; profiling on) */
@@ -536,13 +538,21 @@ grg_status grg_batch_graph_info(grg_batch b, int32_t counts[2]);
  * fields with the reduced solve); -1 where not timed. */
 grg_status grg_batch_tune_info(grg_batch b, int precision, int32_t info[3], float ms[2]);
 
-/* Kernel timing: with profiling on, every dslash launch and every phase of
- * the solve is bracketed by HIP events on the lattice stream;
- * grg_profile_read returns the count and the summed milliseconds since the
- * last reset, per slot: 0..2 full-lattice stencil launches in that
- * grg_precision, 3..5 the half-lattice stencils of the even-odd reduced solve
- * in precision - 3, 6 the FP64 defect-correction steps, 7 the Krylov vector
- * kernels, 8 the learned preconditioner's applications. */
+/* Kernel timing: with profiling on (on = 1), every dslash launch and every
+ * phase of the solve is bracketed by HIP events on the lattice stream, and
+ * the events are read at the end of each call (the phase times of
+ * grg_solver_stats); with on = 2 only the stencil launches (slots 0..5) are
+ * bracketed and their events are read by grg_profile_read and
+ * grg_profile_reset (which first wait for the lattice stream), or at the end
+ * of a call once half of the 16384 event pairs are in use, so that a timed
+ * sequence of calls carries fewer events and no per-call readback; the
+ * stats' phase times are then -1.  on = 0 turns profiling off; other values
+ * are GRG_EINVAL.  grg_profile_read returns the count and the summed
+ * milliseconds since the last reset, per slot: 0..2 full-lattice stencil
+ * launches in that grg_precision, 3..5 the half-lattice stencils of the
+ * even-odd reduced solve in precision - 3, 6 the FP64 defect-correction
+ * steps, 7 the Krylov vector kernels, 8 the learned preconditioner's
+ * applications. */
 grg_status grg_profile_enable(grg_schur s, int on);
 grg_status grg_profile_read(grg_schur s, int precision, int64_t *count, double *total_ms);
 grg_status grg_profile_reset(grg_schur s);

@@ -533,8 +533,8 @@ def grg_batch_graph_info(b):
     return int(c[0]), int(c[1])
 
 
-def grg_profile_enable(s, on=True):
-    _check(load().grg_profile_enable(s, int(bool(on))))
+def grg_profile_enable(s, on=True, launches_only=False):
+    _check(load().grg_profile_enable(s, 0 if not on else 2 if launches_only else 1))
 
 
 PROFILE_PHASES = {"dc": 6, "blas": 7, "precond": 8}

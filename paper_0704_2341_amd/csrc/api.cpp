@@ -611,7 +611,7 @@ static grg_status finish_call(grg_schur S, grg_status st, clk::time_point t0, gr
         set_error("stream synchronise failed: %s", hipGetErrorString(e));
         st = GRG_EHIP;
     }
-    collect_profile(S);
+    if (S->prof.per_call || 2 * S->prof.used > (int)S->prof.start.size()) collect_profile(S);
     if (stats) {
         stats->t_total_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
         stats->n_dslash = S->n_dslash;
@@ -624,6 +624,8 @@ static grg_status finish_call(grg_schur S, grg_status st, clk::time_point t0, gr
         stats->t_dc_ms = S->prof.total_ms[kProfDc] - before.ms[kProfDc];
         stats->t_blas_ms = S->prof.total_ms[kProfBlas] - before.ms[kProfBlas];
         stats->t_prec_ms = S->prof.total_ms[kProfPrec] - before.ms[kProfPrec];
+        if (S->prof.on && !S->prof.per_call)
+            stats->t_dslash_ms = stats->t_dc_ms = stats->t_blas_ms = stats->t_prec_ms = -1.0;
     }
     return st;
 }
@@ -895,6 +897,7 @@ grg_status grg_block_apply(grg_schur S, int precision, int rows, int cols, const
 grg_status grg_profile_enable(grg_schur S, int on)
 {
     if (!S) return set_error("null argument"), GRG_EINVAL;
+    if (on < 0 || on > 2) return set_error("profiling mode %d outside 0..2", on), GRG_EINVAL;
     ProfilePool &P = S->prof;
     if (on && P.start.empty()) {
         const int n = 16384;
@@ -907,6 +910,17 @@ grg_status grg_profile_enable(grg_schur S, int on)
         }
     }
     P.on = on != 0;
+    P.phases = P.per_call = on != 2;
+    return GRG_OK;
+}
+
+// Event pairs not yet read (launch-only profiling reads them here): the
+// lattice stream is drained first so that every pair has completed.
+static grg_status collect_pending(grg_schur S)
+{
+    if (S->prof.used == 0) return GRG_OK;
+    GRG_TRY_HIP(hipStreamSynchronize(S->lat->stream));
+    collect_profile(S);
     return GRG_OK;
 }
 
@@ -914,6 +928,7 @@ grg_status grg_profile_read(grg_schur S, int precision, int64_t *count, double *
 {
     if (!S || !count || !total_ms) return set_error("null argument"), GRG_EINVAL;
     if (precision < 0 || precision >= kProfSlots) return set_error("bad profile slot"), GRG_EINVAL;
+    GRG_TRY(collect_pending(S));
     *count = S->prof.count[precision];
     *total_ms = S->prof.total_ms[precision];
     return GRG_OK;
@@ -922,6 +937,7 @@ grg_status grg_profile_read(grg_schur S, int precision, int64_t *count, double *
 grg_status grg_profile_reset(grg_schur S)
 {
     if (!S) return set_error("null argument"), GRG_EINVAL;
+    GRG_TRY(collect_pending(S));
     for (int p = 0; p < kProfSlots; ++p) {
         S->prof.count[p] = 0;
         S->prof.total_ms[p] = 0;

@@ -33,6 +33,10 @@ constexpr int kProfStencilSlots = 6;
 
 struct ProfilePool {
     bool on = false;
+    // phases: the solve's phases are timed too; per_call: the event pairs are
+    // read back at the end of every call (for the call's stats) rather than
+    // when the totals are read
+    bool phases = true, per_call = true;
     std::vector<hipEvent_t> start, stop;
     std::vector<int> prec;
     int used = 0;
@@ -49,7 +53,7 @@ struct PhaseTimer {
     int idx = -1;
     PhaseTimer(ProfilePool &pool, hipStream_t stream, int slot) : P(&pool), st(stream)
     {
-        if (!pool.on || pool.used >= (int)pool.start.size()) return;
+        if (!pool.on || !pool.phases || pool.used >= (int)pool.start.size()) return;
         idx = pool.used++;
         pool.prec[idx] = slot;
         (void)hipEventRecord(pool.start[idx], st);

@@ -134,3 +134,46 @@ def test_new_gauge_field_on_existing_handles():
         assert rel_err(to_host(y), matfree.reusken_apply(links, dims, m0, q, nb, xb)) < 1e-12, k
     grg.grg_schur_destroy(h)
     grg.grg_lattice_destroy(lat)
+
+
+def test_profiling_modes():
+    """Full profiling times every stencil launch and the solve's phases and
+    reads them per call; launch-only profiling times the same stencil
+    launches, no phases, reads them when asked, and reports the per-call
+    phase times as -1.  Modes outside 0..2 are rejected."""
+    import torch
+    import paper_0704_2341_amd as grg
+    from paper_0704_2341_amd.binding import load
+
+    ensure_built()
+    dims = (8, 8, 8, 8)
+    lat = grg.grg_lattice_create(dims)
+    grg.grg_gauge_set(lat, su3_links(dims, 0.5, 89))
+    q, nb = grg.grg_permutation_block(dims, 1, False)
+    p = grg.grg_solver_params_default(tol=1e-10, inner="bf16", inner_tol=1e-2, max_rhs=2)
+    h = grg.grg_schur_create(lat, M0, q, nb, p)
+    x = to_dev(gaussian_vectors(12 * nb, 2, 90))
+    y = torch.empty_like(x)
+    grg.grg_schur_apply(h, x, y, 2)
+    seen = {}
+    for only in (False, True):
+        grg.grg_profile_enable(h, True, launches_only=only)
+        grg.grg_profile_reset(h)
+        sts = [grg.grg_schur_apply(h, x, y, 2) for _ in range(2)]
+        seen[only] = {k: grg.grg_profile_read(h, k) for k in ("dc", "blas")}
+        seen[only]["eo"] = grg.grg_profile_read(h, "bf16", eo=True)
+        seen[only]["stats"] = sts
+        grg.grg_profile_enable(h, False)
+    full, light = seen[False], seen[True]
+    assert full["eo"][0] > 0 and full["eo"][1] > 0
+    assert full["dc"][0] > 0 and full["blas"][0] > 0
+    assert all(st["t_dc_ms"] > 0 and st["t_dslash_ms"] > 0 for st in full["stats"])
+    # the same solves: as many stencil launches timed, no phases
+    assert light["eo"][0] == full["eo"][0] and light["eo"][1] > 0
+    assert light["dc"] == (0, 0.0) and light["blas"] == (0, 0.0)
+    for st in light["stats"]:
+        assert st["t_dslash_ms"] == st["t_dc_ms"] == st["t_blas_ms"] == st["t_prec_ms"] == -1.0
+    for bad in (-1, 3):
+        assert load().grg_profile_enable(h, bad) == grg.GRG_EINVAL
+    grg.grg_schur_destroy(h)
+    grg.grg_lattice_destroy(lat)
