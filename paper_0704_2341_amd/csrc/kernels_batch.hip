@@ -8,6 +8,7 @@
 #include "batch.h"
 #include "common.h"
 #include "engine.h"
+#include "reduce.h"
 #include "stencil.h"
 
 namespace grg {
@@ -443,8 +444,8 @@ __global__ void __launch_bounds__(256) batch_reduce_kernel(int mode, const doubl
     }
     const int K = mode == kNorm ? 1 : 3;
     double acc[3] = {0, 0, 0};
-    for (int i = threadIdx.x; i < nparts; i += 256)
-        for (int k = 0; k < K; ++k) acc[k] += partials[((size_t)i * nsys + r) * K + k];
+    if (K == 1) strided_sum<1>(partials, nparts, nsys, r, acc);
+    else strided_sum<3>(partials, nparts, nsys, r, acc);
     for (int k = 0; k < K; ++k) sm[k][threadIdx.x] = acc[k];
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {

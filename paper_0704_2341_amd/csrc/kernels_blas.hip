@@ -8,6 +8,7 @@
 // point atomics anywhere, so every reduction is bitwise reproducible.
 #include "common.h"
 #include "engine.h"
+#include "reduce.h"
 
 namespace grg {
 
@@ -296,8 +297,8 @@ __global__ void __launch_bounds__(256) bicg_reduce_kernel(int mode, const double
     const int r = blockIdx.x;
     const int K = mode == kBicgInit ? 1 : 3;
     double acc[3] = {0, 0, 0};
-    for (int i = threadIdx.x; i < nparts; i += 256)
-        for (int k = 0; k < K; ++k) acc[k] += partials[((size_t)i * nrhs + r) * K + k];
+    if (K == 1) strided_sum<1>(partials, nparts, nrhs, r, acc);
+    else strided_sum<3>(partials, nparts, nrhs, r, acc);
     for (int k = 0; k < K; ++k) sm[k][threadIdx.x] = acc[k];
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
@@ -725,8 +726,8 @@ __global__ void __launch_bounds__(256) reduce_kernel(int mode, const double *par
     const int r = blockIdx.x;
     const int K = mode == kNorm ? 1 : 3;
     double acc[3] = {0, 0, 0};
-    for (int i = threadIdx.x; i < nparts; i += 256)
-        for (int k = 0; k < K; ++k) acc[k] += partials[((size_t)i * nrhs + r) * K + k];
+    if (K == 1) strided_sum<1>(partials, nparts, nrhs, r, acc);
+    else strided_sum<3>(partials, nparts, nrhs, r, acc);
     for (int k = 0; k < K; ++k) sm[k][threadIdx.x] = acc[k];
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
