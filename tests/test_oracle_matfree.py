@@ -128,3 +128,27 @@ def test_drr_residual_vs_dense(setup4, kind, inv):
     # zero right-hand side: the absolute residual
     z = matfree.drr_residual(u, dims, 0.1, q, nb, np.zeros_like(b[:1]), x[:1])
     assert np.isclose(z[0], np.linalg.norm((drr @ x[0, o])), rtol=1e-13)
+
+
+@pytest.mark.parametrize("kind,inv", [("I", False), ("II", True)])
+def test_drr_residual_vs_dense(setup4, kind, inv):
+    """The oracle's residual ||b - D_rr x|| / ||b|| for an arbitrary x (not a
+    solver's output) against the dense D_rr block: values on the coarse
+    sites of x are not columns of D_rr and change nothing, and b = 0 gives
+    the absolute norm ||D_rr x||."""
+    dims, u, d = setup4
+    q, nb = dense.permutation_block(dims, kind, inv)
+    _, _, _, drr = dense.blocks(d, q, nb)
+    o = dense.dof_order(q)[12 * nb:]
+    ob = dense.dof_order(q)[: 12 * nb]
+    b = np.zeros((3, 12 * 256), np.complex128)
+    b[:2, o] = gaussian_vectors(len(o), 2, 21)
+    x = np.zeros((3, 12 * 256), np.complex128)
+    x[:, o] = gaussian_vectors(len(o), 3, 22)
+    want = np.linalg.norm(b[:, o] - (drr @ x[:, o].T).T, axis=1)
+    want[:2] /= np.linalg.norm(b[:2, o], axis=1)
+    got = matfree.drr_residual(u, dims, 0.1, q, nb, b, x)
+    assert np.allclose(got, want, rtol=1e-13, atol=0), (got, want)
+    assert got.min() > 0.1  # not a solution: the comparison is of O(1) values
+    x[:, ob] = gaussian_vectors(len(ob), 3, 23)
+    assert np.allclose(matfree.drr_residual(u, dims, 0.1, q, nb, b, x), want, rtol=1e-13, atol=0)
